@@ -1,0 +1,293 @@
+"""CPU oracle of the device heap allocator -- TEST INFRASTRUCTURE ONLY.
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this package.  The product path (the HIP library and
+its binding) never does, and this package imports nothing from it.
+
+The C sources (``hbheap_oracle.c``, ``hbheap_model.c``) hold the oracle:
+
+* a sequential allocator with the same size classes as the device heap
+  (Introduction; Results, "Page allocator" and "Chunk allocator"), with two
+  tie-break policies: LOWEST (canonical outcome) and FIFO (what a single
+  device thread sees);
+* an invariant checker for block lists and heap snapshots;
+* the seeded payload pattern (MurmurHash3's 32-bit finaliser);
+* a step-level model of the concurrent algorithm, explored exhaustively.
+
+This module compiles them with gcc into ``liboracle.so`` and wraps them with
+ctypes over numpy arrays.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liboracle.so")
+SOURCES = ["hbheap_oracle.c", "hbheap_model.c"]
+
+VARIANT_CHUNK, VARIANT_PAGE = 0, 1
+POLICY_LOWEST, POLICY_FIFO = 0, 1
+FREE_OK, FREE_DOUBLE, FREE_INVALID, FREE_NULL = 0, 1, 2, 3
+MAX_CLASSES = 16
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle's C sources into ``liboracle.so`` (gcc, -O2)."""
+    srcs = [os.path.join(HERE, s) for s in SOURCES if os.path.exists(os.path.join(HERE, s))]
+    if not force and os.path.exists(LIB_PATH):
+        newest = max(os.path.getmtime(s) for s in srcs + [os.path.join(HERE, "hbheap_oracle.h")])
+        if os.path.getmtime(LIB_PATH) >= newest:
+            return LIB_PATH
+    tmp = LIB_PATH + ".tmp"
+    cmd = ["gcc", "-std=c11", "-O2", "-g", "-Wall", "-Wextra", "-shared", "-fPIC", "-o", tmp] + srcs
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, LIB_PATH)
+    return LIB_PATH
+
+
+class Acct(C.Structure):
+    _fields_ = [
+        ("n_classes", C.c_uint32), ("pad", C.c_uint32),
+        ("n_chunks", C.c_uint64), ("free_chunks", C.c_uint64),
+        ("live", C.c_uint64 * MAX_CLASSES), ("chunks", C.c_uint64 * MAX_CLASSES),
+        ("free_pages", C.c_uint64 * MAX_CLASSES),
+        ("n_alloc_ok", C.c_uint64), ("n_alloc_null", C.c_uint64), ("n_free_ok", C.c_uint64),
+        ("n_free_double", C.c_uint64), ("n_free_invalid", C.c_uint64),
+    ]
+
+
+class BlocksReport(C.Structure):
+    _fields_ = [
+        ("n", C.c_uint64), ("n_null", C.c_uint64), ("n_nonnull", C.c_uint64),
+        ("n_null_valid", C.c_uint64), ("n_bad_size_nonnull", C.c_uint64),
+        ("n_oob", C.c_uint64), ("n_misaligned", C.c_uint64), ("n_straddle", C.c_uint64),
+        ("n_overlap", C.c_uint64), ("live", C.c_uint64 * MAX_CLASSES),
+    ]
+
+
+class SnapReport(C.Structure):
+    _fields_ = [
+        ("ok_header", C.c_int32), ("n_classes", C.c_uint32),
+        ("bad_class_byte", C.c_uint64), ("bad_free_chunk", C.c_uint64), ("bad_stray_bits", C.c_uint64),
+        ("bad_count", C.c_uint64), ("bad_pool", C.c_uint64), ("bad_ring_ctl", C.c_uint64),
+        ("bad_ring_entry", C.c_uint64), ("bad_ring_missing", C.c_uint64), ("bad_ring_dup", C.c_uint64),
+        ("bad_conservation", C.c_uint64), ("bad_owned", C.c_uint64), ("free_chunks", C.c_uint64),
+        ("live", C.c_uint64 * MAX_CLASSES), ("chunks", C.c_uint64 * MAX_CLASSES),
+        ("free_pages", C.c_uint64 * MAX_CLASSES),
+    ]
+
+    def violations(self) -> dict:
+        names = [f for f, _ in self._fields_ if f.startswith("bad_")]
+        return {n: int(getattr(self, n)) for n in names if getattr(self, n)}
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        build(force=False)
+        L = C.CDLL(LIB_PATH)
+        u64, i64, u32, i32, vp = C.c_uint64, C.c_int64, C.c_uint32, C.c_int32, C.c_void_p
+        sig = {
+            "orc_class_of": (C.c_int, [u64, u64]),
+            "orc_num_classes": (u32, [u64]),
+            "orc_page_bytes": (u64, [u32]),
+            "orc_pages_per_chunk": (u64, [u64, u32]),
+            "orc_page_ring_entries": (u64, [u64, u64]),
+            "orc_page_max_chunks": (u64, [u64, u64, u32]),
+            "orc_geometry_ok": (C.c_int, [u64, u64]),
+            "orc_create": (vp, [u64, u64, C.c_int, C.c_int]),
+            "orc_destroy": (None, [vp]),
+            "orc_alloc": (i64, [vp, u64]),
+            "orc_free": (C.c_int, [vp, i64]),
+            "orc_trim": (None, [vp]),
+            "orc_alloc_batch": (None, [vp, vp, vp, u64]),
+            "orc_free_batch": (None, [vp, vp, u64, vp]),
+            "orc_accounting": (None, [vp, C.POINTER(Acct)]),
+            "orc_replay": (None, [vp, vp, u64, vp]),
+            "orc_fmix32": (u32, [u32]),
+            "orc_pattern_word": (u32, [u32, u32, u32]),
+            "orc_pattern_fill": (None, [u32, u32, vp, u64]),
+            "orc_check_blocks": (C.c_int, [u64, u64, vp, vp, u64, C.POINTER(BlocksReport)]),
+            "orc_check_snapshot": (C.c_int, [vp, u64, C.POINTER(SnapReport)]),
+            "orc_check_blocks_in_snapshot": (u64, [vp, u64, vp, vp, u64]),
+        }
+        for name, (res, args) in sig.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _model_sigs(L)
+        _lib = L
+    return _lib
+
+
+def _model_sigs(L):
+    if not hasattr(L, "orc_model_run"):
+        return
+    L.orc_model_run.restype = C.c_int
+    L.orc_model_run.argtypes = [C.POINTER(ModelParams), C.POINTER(ModelResult)]
+
+
+class ModelParams(C.Structure):
+    _fields_ = [
+        ("variant", C.c_int32), ("n_chunks", C.c_int32), ("ppc", C.c_int32), ("n_classes", C.c_int32),
+        ("n_leaders", C.c_int32), ("ops", (C.c_int32 * 4) * 4), ("n_ops", C.c_int32 * 4),
+        ("prefill", C.c_int32 * 8), ("n_prefill", C.c_int32),
+        ("freeze", C.c_int32), ("mutation", C.c_int32), ("max_states", C.c_int64),
+    ]
+
+
+class ModelResult(C.Structure):
+    _fields_ = [
+        ("states", C.c_int64), ("terminals", C.c_int64), ("violations", C.c_int64),
+        ("linearizability_failures", C.c_int64), ("deadlocks", C.c_int64), ("blocked_freezes", C.c_int64),
+        ("truncated", C.c_int32), ("first_violation", C.c_int32), ("outcomes", C.c_int64),
+        ("null_outcomes", C.c_int64),
+    ]
+
+
+def _ptr(a: np.ndarray):
+    return C.c_void_p(a.ctypes.data) if a.size else C.c_void_p(0)
+
+
+# --------------------------------------------------------------------------
+# closed forms
+# --------------------------------------------------------------------------
+
+def class_of(n: int, chunk_bytes: int) -> int:
+    return int(lib().orc_class_of(n, chunk_bytes))
+
+
+def num_classes(chunk_bytes: int) -> int:
+    return int(lib().orc_num_classes(chunk_bytes))
+
+
+def page_bytes(k: int) -> int:
+    return int(lib().orc_page_bytes(k))
+
+
+def pages_per_chunk(chunk_bytes: int, k: int) -> int:
+    return int(lib().orc_pages_per_chunk(chunk_bytes, k))
+
+
+def page_ring_entries(nbytes: int, chunk_bytes: int) -> int:
+    return int(lib().orc_page_ring_entries(nbytes, chunk_bytes))
+
+
+def page_max_chunks(nbytes: int, chunk_bytes: int, k: int) -> int:
+    return int(lib().orc_page_max_chunks(nbytes, chunk_bytes, k))
+
+
+# --------------------------------------------------------------------------
+# sequential allocator
+# --------------------------------------------------------------------------
+
+class OracleHeap:
+    """Sequential allocator; offsets from the data base, -1 for NULL."""
+
+    def __init__(self, nbytes: int, chunk_bytes: int, variant: int = VARIANT_CHUNK, policy: int = POLICY_LOWEST):
+        self.h = lib().orc_create(nbytes, chunk_bytes, variant, policy)
+        if not self.h:
+            raise ValueError("invalid oracle geometry")
+        self.nbytes, self.chunk_bytes = nbytes, chunk_bytes
+        self.n_chunks = nbytes // chunk_bytes
+        self.variant, self.policy = variant, policy
+
+    def close(self):
+        if self.h:
+            lib().orc_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def alloc(self, n: int) -> int:
+        return int(lib().orc_alloc(self.h, n))
+
+    def free(self, off: int) -> int:
+        return int(lib().orc_free(self.h, off))
+
+    def trim(self):
+        lib().orc_trim(self.h)
+
+    def alloc_batch(self, sizes: np.ndarray) -> np.ndarray:
+        sizes = np.ascontiguousarray(sizes, dtype=np.uint64)
+        out = np.empty(sizes.shape[0], dtype=np.int64)
+        lib().orc_alloc_batch(self.h, _ptr(sizes), _ptr(out), sizes.shape[0])
+        return out
+
+    def free_batch(self, offs: np.ndarray) -> np.ndarray:
+        offs = np.ascontiguousarray(offs, dtype=np.int64)
+        st = np.empty(offs.shape[0], dtype=np.int32)
+        lib().orc_free_batch(self.h, _ptr(offs), offs.shape[0], _ptr(st))
+        return st
+
+    def replay(self, ops: np.ndarray) -> np.ndarray:
+        ops = np.ascontiguousarray(ops, dtype=np.int64)
+        out = np.empty(ops.shape[0], dtype=np.int64)
+        lib().orc_replay(self.h, _ptr(ops), ops.shape[0], _ptr(out))
+        return out
+
+    def accounting(self) -> dict:
+        a = Acct()
+        lib().orc_accounting(self.h, C.byref(a))
+        K = a.n_classes
+        return {
+            "n_chunks": a.n_chunks, "free_chunks": a.free_chunks,
+            "live": list(a.live)[:K], "chunks": list(a.chunks)[:K], "free_pages": list(a.free_pages)[:K],
+            "n_alloc_ok": a.n_alloc_ok, "n_alloc_null": a.n_alloc_null, "n_free_ok": a.n_free_ok,
+            "n_free_double": a.n_free_double, "n_free_invalid": a.n_free_invalid,
+        }
+
+
+# --------------------------------------------------------------------------
+# pattern
+# --------------------------------------------------------------------------
+
+def fmix32(x: int) -> int:
+    return int(lib().orc_fmix32(x & 0xFFFFFFFF))
+
+
+def pattern_word(seed: int, req: int, i: int) -> int:
+    return int(lib().orc_pattern_word(seed & 0xFFFFFFFF, req & 0xFFFFFFFF, i & 0xFFFFFFFF))
+
+
+def pattern_bytes(seed: int, req: int, nbytes: int) -> bytes:
+    buf = np.empty(nbytes, dtype=np.uint8)
+    lib().orc_pattern_fill(seed & 0xFFFFFFFF, req & 0xFFFFFFFF, _ptr(buf), nbytes)
+    return buf.tobytes()
+
+
+# --------------------------------------------------------------------------
+# checker
+# --------------------------------------------------------------------------
+
+def check_blocks(data_bytes: int, chunk_bytes: int, sizes: np.ndarray, offs: np.ndarray) -> BlocksReport:
+    sizes = np.ascontiguousarray(sizes, dtype=np.uint64)
+    offs = np.ascontiguousarray(offs, dtype=np.int64)
+    rep = BlocksReport()
+    lib().orc_check_blocks(data_bytes, chunk_bytes, _ptr(sizes), _ptr(offs), sizes.shape[0], C.byref(rep))
+    return rep
+
+
+def check_snapshot(snap: bytes | np.ndarray) -> SnapReport:
+    a = np.frombuffer(bytes(snap), dtype=np.uint8) if not isinstance(snap, np.ndarray) else np.ascontiguousarray(snap, dtype=np.uint8)
+    rep = SnapReport()
+    lib().orc_check_snapshot(_ptr(a), a.shape[0], C.byref(rep))
+    return rep
+
+
+def check_blocks_in_snapshot(snap, sizes: np.ndarray, offs: np.ndarray) -> int:
+    a = np.frombuffer(bytes(snap), dtype=np.uint8) if not isinstance(snap, np.ndarray) else np.ascontiguousarray(snap, dtype=np.uint8)
+    sizes = np.ascontiguousarray(sizes, dtype=np.uint64)
+    offs = np.ascontiguousarray(offs, dtype=np.int64)
+    return int(lib().orc_check_blocks_in_snapshot(_ptr(a), a.shape[0], _ptr(sizes), _ptr(offs), sizes.shape[0]))

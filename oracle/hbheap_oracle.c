@@ -1,0 +1,663 @@
+/*
+ * hbheap_oracle.c -- plain sequential CPU oracle of the device heap allocator.
+ *
+ * TEST INFRASTRUCTURE ONLY: used by tests/, the smoke check and the
+ * benchmark's CPU-baseline leg; never by the product path.  Written from the
+ * paper and the documented snapshot format; it shares no code with the HIP
+ * library.
+ *
+ * The method (Introduction; Results, "Page allocator" and "Chunk
+ * allocator"): a heap preallocated by the host is cut into chunks of one
+ * fixed size C; a chunk, once handed to a size, is split into pages of that
+ * size; sizes are powers of two and each size has its own queue.  In the
+ * chunk variant the queue lists chunks that still have free pages and an
+ * allocation takes a chunk from it, then a free page inside that chunk; in
+ * the page variant the queue lists free pages directly.
+ *
+ * Readings (paper silent): smallest page 16 B; classes k = 0..K-1 with page
+ * 16*2^k and K = log2(C) - 3; a request n maps to the smallest page >= n;
+ * n == 0 or n > C is a NULL request; a chunk is returned to the pool of
+ * unowned chunks only by trim() at quiescence; the page variant's queues
+ * share a budget of bytes/8 of metadata, which caps the chunks one class
+ * may own.
+ *
+ * Two tie-break policies produce legal outcomes:
+ *   LOWEST -- the lowest chunk with a free page, then its lowest free page,
+ *             else the lowest unowned chunk (the canonical outcome);
+ *   FIFO   -- queue order as one device thread alone sees it: class queues
+ *             and the pool are first-in first-out, a chunk that keeps free
+ *             pages after an allocation goes to the back of its queue, a
+ *             fresh chunk serves its page 0 and publishes the rest, the pool
+ *             hands out its ids in stored order.
+ */
+#include "hbheap_oracle.h"
+
+#include <stdlib.h>
+#include <string.h>
+
+/* ------------------------------------------------------------------ */
+/* geometry                                                            */
+/* ------------------------------------------------------------------ */
+
+static int ilog2_u64(uint64_t x) { int r = -1; while (x) { x >>= 1; ++r; } return r; }
+static int is_pow2(uint64_t x) { return x && !(x & (x - 1)); }
+
+int orc_geometry_ok(uint64_t bytes, uint64_t chunk_bytes)
+{
+    if (!is_pow2(chunk_bytes) || chunk_bytes < 4096 || chunk_bytes > 65536) return 0;
+    if (bytes < chunk_bytes) return 0;
+    return 1;
+}
+
+uint32_t orc_num_classes(uint64_t chunk_bytes) { return (uint32_t)(ilog2_u64(chunk_bytes) - 3); }
+
+uint64_t orc_page_bytes(uint32_t k) { return (uint64_t)16 << k; }
+
+uint64_t orc_pages_per_chunk(uint64_t chunk_bytes, uint32_t k) { return chunk_bytes / orc_page_bytes(k); }
+
+/* Smallest class whose page holds n bytes: walk the page sizes upward. */
+int orc_class_of(uint64_t n, uint64_t chunk_bytes)
+{
+    if (n == 0 || n > chunk_bytes) return -1;
+    uint32_t k = 0;
+    while (orc_page_bytes(k) < n) ++k;
+    return (int)k;
+}
+
+/* Page-variant queue budget: bytes/8 of 4-byte entries split evenly over the
+ * K classes, rounded down to a power of two. */
+uint64_t orc_page_ring_entries(uint64_t bytes, uint64_t chunk_bytes)
+{
+    uint64_t per = bytes / 8 / orc_num_classes(chunk_bytes) / 4;
+    uint64_t p = 1;
+    while (p * 2 <= per) p *= 2;
+    return p;
+}
+
+uint64_t orc_page_max_chunks(uint64_t bytes, uint64_t chunk_bytes, uint32_t k)
+{
+    return orc_page_ring_entries(bytes, chunk_bytes) / orc_pages_per_chunk(chunk_bytes, k);
+}
+
+/* ------------------------------------------------------------------ */
+/* small containers                                                    */
+/* ------------------------------------------------------------------ */
+
+/* hierarchical bitset: lowest set index in O(levels) */
+typedef struct {
+    int levels;
+    uint64_t n;
+    uint64_t* lv[8];
+    uint64_t words[8];
+} hset;
+
+static void hset_init(hset* s, uint64_t n)
+{
+    memset(s, 0, sizeof(*s));
+    s->n = n;
+    uint64_t m = n;
+    do {
+        uint64_t w = (m + 63) / 64;
+        s->words[s->levels] = w;
+        s->lv[s->levels] = (uint64_t*)calloc(w ? w : 1, 8);
+        s->levels++;
+        m = w;
+    } while (m > 1);
+}
+static void hset_free(hset* s) { for (int i = 0; i < s->levels; ++i) free(s->lv[i]); }
+static void hset_set(hset* s, uint64_t i)
+{
+    for (int l = 0; l < s->levels; ++l) {
+        uint64_t w = i >> 6, b = i & 63;
+        int was = s->lv[l][w] != 0;
+        s->lv[l][w] |= 1ull << b;
+        if (was) break;
+        i = w;
+    }
+}
+static void hset_clear(hset* s, uint64_t i)
+{
+    for (int l = 0; l < s->levels; ++l) {
+        uint64_t w = i >> 6, b = i & 63;
+        s->lv[l][w] &= ~(1ull << b);
+        if (s->lv[l][w]) break;
+        i = w;
+    }
+}
+static int64_t hset_lowest(const hset* s)
+{
+    int top = s->levels - 1;
+    if (!s->lv[top][0]) return -1;
+    uint64_t i = 0;
+    for (int l = top; l >= 0; --l) {
+        uint64_t w = s->lv[l][i];
+        i = i * 64 + (uint64_t)__builtin_ctzll(w);
+    }
+    return (int64_t)i;
+}
+
+/* growable FIFO of u64 */
+typedef struct { uint64_t* a; uint64_t cap, head, len; } fifo;
+static void fifo_init(fifo* q) { q->cap = 16; q->a = (uint64_t*)malloc(16 * 8); q->head = q->len = 0; }
+static void fifo_free(fifo* q) { free(q->a); }
+static void fifo_push(fifo* q, uint64_t v)
+{
+    if (q->len == q->cap) {
+        uint64_t* b = (uint64_t*)malloc(q->cap * 2 * 8);
+        for (uint64_t i = 0; i < q->len; ++i) b[i] = q->a[(q->head + i) % q->cap];
+        free(q->a);
+        q->a = b; q->head = 0; q->cap *= 2;
+    }
+    q->a[(q->head + q->len) % q->cap] = v;
+    q->len++;
+}
+static uint64_t fifo_pop(fifo* q)
+{
+    uint64_t v = q->a[q->head];
+    q->head = (q->head + 1) % q->cap;
+    q->len--;
+    return v;
+}
+static void fifo_clear(fifo* q) { q->head = q->len = 0; }
+
+/* ------------------------------------------------------------------ */
+/* heap state                                                          */
+/* ------------------------------------------------------------------ */
+
+#define FREE_CLASS 0xFF
+
+struct orc_heap {
+    uint64_t bytes, C, N;
+    uint32_t log2C, K, W;
+    int variant, policy;
+    uint8_t*  cls;        /* class of each chunk, FREE_CLASS if unowned     */
+    uint32_t* cnt;        /* free pages in each owned chunk                  */
+    uint64_t* bits;       /* N*W words, bit set = page free                  */
+    uint64_t  maxc[ORC_MAX_CLASSES];
+    uint64_t  owned[ORC_MAX_CLASSES];
+    orc_acct  acct;
+    /* LOWEST policy */
+    hset free_set;                    /* unowned chunks                      */
+    hset avail[ORC_MAX_CLASSES];      /* owned chunks with a free page       */
+    /* FIFO policy */
+    uint32_t* pool; uint64_t pool_size, pool_next;
+    fifo q[ORC_MAX_CLASSES];          /* chunk ids (chunk variant) or page offsets (page variant) */
+};
+
+static uint64_t ppc_of(const orc_heap* h, uint32_t k) { return h->C >> (4 + k); }
+
+orc_heap* orc_create(uint64_t bytes, uint64_t chunk_bytes, int variant, int policy)
+{
+    if (!orc_geometry_ok(bytes, chunk_bytes)) return NULL;
+    if (variant != ORC_VARIANT_CHUNK && variant != ORC_VARIANT_PAGE) return NULL;
+    if (policy != ORC_POLICY_LOWEST && policy != ORC_POLICY_FIFO) return NULL;
+    orc_heap* h = (orc_heap*)calloc(1, sizeof(orc_heap));
+    h->bytes = bytes; h->C = chunk_bytes; h->N = bytes / chunk_bytes;
+    h->log2C = (uint32_t)ilog2_u64(chunk_bytes);
+    h->K = orc_num_classes(chunk_bytes);
+    h->W = (uint32_t)(chunk_bytes / 16 / 64);
+    h->variant = variant; h->policy = policy;
+    h->cls = (uint8_t*)malloc(h->N);
+    memset(h->cls, FREE_CLASS, h->N);
+    h->cnt = (uint32_t*)calloc(h->N, 4);
+    h->bits = (uint64_t*)calloc(h->N * h->W, 8);
+    for (uint32_t k = 0; k < h->K; ++k)
+        h->maxc[k] = variant == ORC_VARIANT_PAGE ? orc_page_max_chunks(bytes, chunk_bytes, k) : h->N;
+    h->acct.n_classes = h->K;
+    h->acct.n_chunks = h->N;
+    h->acct.free_chunks = h->N;
+    if (policy == ORC_POLICY_LOWEST) {
+        hset_init(&h->free_set, h->N);
+        for (uint64_t c = 0; c < h->N; ++c) hset_set(&h->free_set, c);
+        for (uint32_t k = 0; k < h->K; ++k) hset_init(&h->avail[k], h->N);
+    } else {
+        h->pool = (uint32_t*)malloc(h->N * 4);
+        for (uint64_t c = 0; c < h->N; ++c) h->pool[c] = (uint32_t)c;
+        h->pool_size = h->N; h->pool_next = 0;
+        for (uint32_t k = 0; k < h->K; ++k) fifo_init(&h->q[k]);
+    }
+    return h;
+}
+
+void orc_destroy(orc_heap* h)
+{
+    if (!h) return;
+    if (h->policy == ORC_POLICY_LOWEST) {
+        hset_free(&h->free_set);
+        for (uint32_t k = 0; k < h->K; ++k) hset_free(&h->avail[k]);
+    } else {
+        free(h->pool);
+        for (uint32_t k = 0; k < h->K; ++k) fifo_free(&h->q[k]);
+    }
+    free(h->cls); free(h->cnt); free(h->bits); free(h);
+}
+
+static int bit_get(const orc_heap* h, uint64_t c, uint64_t p) { return (int)((h->bits[c * h->W + (p >> 6)] >> (p & 63)) & 1); }
+static void bit_set(orc_heap* h, uint64_t c, uint64_t p) { h->bits[c * h->W + (p >> 6)] |= 1ull << (p & 63); }
+static void bit_clr(orc_heap* h, uint64_t c, uint64_t p) { h->bits[c * h->W + (p >> 6)] &= ~(1ull << (p & 63)); }
+
+static int64_t lowest_free_page(const orc_heap* h, uint64_t c)
+{
+    for (uint32_t w = 0; w < h->W; ++w) {
+        uint64_t x = h->bits[c * h->W + w];
+        if (x) return (int64_t)(w * 64 + (uint64_t)__builtin_ctzll(x));
+    }
+    return -1;
+}
+
+static int64_t offset_of(const orc_heap* h, uint64_t c, uint32_t k, uint64_t p)
+{
+    return (int64_t)((c << h->log2C) + p * orc_page_bytes(k));
+}
+
+/* Hand a fresh chunk to class k: page 0 is served, the rest become free. */
+static void claim_fresh(orc_heap* h, uint64_t c, uint32_t k)
+{
+    uint64_t ppc = ppc_of(h, k);
+    h->cls[c] = (uint8_t)k;
+    for (uint64_t p = 1; p < ppc; ++p) bit_set(h, c, p);
+    h->cnt[c] = (uint32_t)(ppc - 1);
+    h->owned[k]++;
+    h->acct.free_chunks--;
+    h->acct.chunks[k]++;
+    h->acct.free_pages[k] += ppc - 1;
+    h->acct.live[k]++;
+}
+
+static int64_t alloc_lowest(orc_heap* h, uint32_t k)
+{
+    int64_t c = hset_lowest(&h->avail[k]);
+    if (c >= 0) {
+        int64_t p = lowest_free_page(h, (uint64_t)c);
+        bit_clr(h, (uint64_t)c, (uint64_t)p);
+        if (--h->cnt[c] == 0) hset_clear(&h->avail[k], (uint64_t)c);
+        h->acct.free_pages[k]--; h->acct.live[k]++;
+        return offset_of(h, (uint64_t)c, k, (uint64_t)p);
+    }
+    if (h->owned[k] >= h->maxc[k]) return -1;
+    c = hset_lowest(&h->free_set);
+    if (c < 0) return -1;
+    hset_clear(&h->free_set, (uint64_t)c);
+    claim_fresh(h, (uint64_t)c, k);
+    if (h->cnt[c] > 0) hset_set(&h->avail[k], (uint64_t)c);
+    return offset_of(h, (uint64_t)c, k, 0);
+}
+
+static int64_t alloc_fifo(orc_heap* h, uint32_t k)
+{
+    fifo* q = &h->q[k];
+    if (q->len) {
+        if (h->variant == ORC_VARIANT_CHUNK) {
+            uint64_t c = fifo_pop(q);
+            int64_t p = lowest_free_page(h, c);
+            bit_clr(h, c, (uint64_t)p);
+            if (--h->cnt[c] > 0) fifo_push(q, c);
+            h->acct.free_pages[k]--; h->acct.live[k]++;
+            return offset_of(h, c, k, (uint64_t)p);
+        } else {
+            uint64_t off = fifo_pop(q);
+            uint64_t c = off >> h->log2C, p = (off & (h->C - 1)) / orc_page_bytes(k);
+            bit_clr(h, c, p);
+            h->cnt[c]--;
+            h->acct.free_pages[k]--; h->acct.live[k]++;
+            return (int64_t)off;
+        }
+    }
+    if (h->owned[k] >= h->maxc[k]) return -1;
+    if (h->pool_next >= h->pool_size) return -1;
+    uint64_t c = h->pool[h->pool_next++];
+    claim_fresh(h, c, k);
+    if (h->variant == ORC_VARIANT_CHUNK) {
+        if (h->cnt[c] > 0) fifo_push(q, c);
+    } else {
+        for (uint64_t p = 1; p < ppc_of(h, k); ++p) fifo_push(q, (uint64_t)offset_of(h, c, k, p));
+    }
+    return offset_of(h, c, k, 0);
+}
+
+int64_t orc_alloc(orc_heap* h, uint64_t n)
+{
+    int k = orc_class_of(n, h->C);
+    int64_t r = -1;
+    if (k >= 0) r = h->policy == ORC_POLICY_LOWEST ? alloc_lowest(h, (uint32_t)k) : alloc_fifo(h, (uint32_t)k);
+    if (r < 0) h->acct.n_alloc_null++; else h->acct.n_alloc_ok++;
+    return r;
+}
+
+int orc_free(orc_heap* h, int64_t off)
+{
+    if (off < 0) return ORC_FREE_NULL;
+    uint64_t o = (uint64_t)off;
+    if (o >= h->N * h->C) { h->acct.n_free_invalid++; return ORC_FREE_INVALID; }
+    uint64_t c = o >> h->log2C;
+    if (h->cls[c] == FREE_CLASS) { h->acct.n_free_invalid++; return ORC_FREE_INVALID; }
+    uint32_t k = h->cls[c];
+    uint64_t in = o & (h->C - 1);
+    if (in % orc_page_bytes(k)) { h->acct.n_free_invalid++; return ORC_FREE_INVALID; }
+    uint64_t p = in / orc_page_bytes(k);
+    if (bit_get(h, c, p)) { h->acct.n_free_double++; return ORC_FREE_DOUBLE; }
+    bit_set(h, c, p);
+    uint32_t was = h->cnt[c]++;
+    h->acct.free_pages[k]++; h->acct.live[k]--; h->acct.n_free_ok++;
+    if (h->policy == ORC_POLICY_LOWEST) {
+        if (was == 0) hset_set(&h->avail[k], c);
+    } else if (h->variant == ORC_VARIANT_CHUNK) {
+        if (was == 0) fifo_push(&h->q[k], c);
+    } else {
+        fifo_push(&h->q[k], o);
+    }
+    return ORC_FREE_OK;
+}
+
+/* Quiescent trim: chunks whose pages are all free go back to the pool; the
+ * pool and the class queues are rebuilt in ascending order. */
+void orc_trim(orc_heap* h)
+{
+    for (uint64_t c = 0; c < h->N; ++c) {
+        if (h->cls[c] == FREE_CLASS) continue;
+        uint32_t k = h->cls[c];
+        if (h->cnt[c] != ppc_of(h, k)) continue;
+        for (uint32_t w = 0; w < h->W; ++w) h->bits[c * h->W + w] = 0;
+        h->cnt[c] = 0;
+        h->cls[c] = FREE_CLASS;
+        h->owned[k]--;
+        h->acct.chunks[k]--;
+        h->acct.free_pages[k] -= ppc_of(h, k);
+        h->acct.free_chunks++;
+        if (h->policy == ORC_POLICY_LOWEST) {
+            hset_clear(&h->avail[k], c);
+            hset_set(&h->free_set, c);
+        }
+    }
+    if (h->policy == ORC_POLICY_FIFO) {
+        h->pool_size = 0; h->pool_next = 0;
+        for (uint64_t c = 0; c < h->N; ++c)
+            if (h->cls[c] == FREE_CLASS) h->pool[h->pool_size++] = (uint32_t)c;
+        for (uint32_t k = 0; k < h->K; ++k) fifo_clear(&h->q[k]);
+        for (uint64_t c = 0; c < h->N; ++c) {
+            if (h->cls[c] == FREE_CLASS || h->cnt[c] == 0) continue;
+            uint32_t k = h->cls[c];
+            if (h->variant == ORC_VARIANT_CHUNK) {
+                fifo_push(&h->q[k], c);
+            } else {
+                for (uint64_t p = 0; p < ppc_of(h, k); ++p)
+                    if (bit_get(h, c, p)) fifo_push(&h->q[k], (uint64_t)offset_of(h, c, k, p));
+            }
+        }
+    }
+}
+
+void orc_alloc_batch(orc_heap* h, const uint64_t* sizes, int64_t* offs, uint64_t n)
+{
+    for (uint64_t i = 0; i < n; ++i) offs[i] = orc_alloc(h, sizes[i]);
+}
+
+void orc_free_batch(orc_heap* h, const int64_t* offs, uint64_t n, int32_t* status)
+{
+    for (uint64_t i = 0; i < n; ++i) {
+        int s = orc_free(h, offs[i]);
+        if (status) status[i] = s;
+    }
+}
+
+void orc_replay(orc_heap* h, const int64_t* op, uint64_t n, int64_t* out)
+{
+    for (uint64_t i = 0; i < n; ++i) {
+        if (op[i] >= 0) out[i] = orc_alloc(h, (uint64_t)op[i]);
+        else out[i] = orc_free(h, out[(uint64_t)(-op[i] - 1)]);
+    }
+}
+
+void orc_accounting(const orc_heap* h, orc_acct* out) { *out = h->acct; }
+
+/* ------------------------------------------------------------------ */
+/* pattern: the 32-bit finaliser of MurmurHash3 (public domain)        */
+/* ------------------------------------------------------------------ */
+
+uint32_t orc_fmix32(uint32_t x)
+{
+    x ^= x >> 16;
+    x *= 0x85ebca6bu;
+    x ^= x >> 13;
+    x *= 0xc2b2ae35u;
+    x ^= x >> 16;
+    return x;
+}
+
+uint32_t orc_pattern_word(uint32_t seed, uint32_t req, uint32_t i)
+{
+    return orc_fmix32(seed ^ orc_fmix32(req) ^ (i * 0x9E3779B9u));
+}
+
+void orc_pattern_fill(uint32_t seed, uint32_t req, uint8_t* dst, uint64_t nbytes)
+{
+    for (uint64_t b = 0; b < nbytes; ++b) {
+        uint32_t w = orc_pattern_word(seed, req, (uint32_t)(b / 4));
+        dst[b] = (uint8_t)(w >> (8 * (b % 4)));
+    }
+}
+
+/* ------------------------------------------------------------------ */
+/* invariant checker: blocks                                           */
+/* ------------------------------------------------------------------ */
+
+typedef struct { uint64_t lo, hi; } ival;
+static int ival_cmp(const void* a, const void* b)
+{
+    const ival* x = (const ival*)a; const ival* y = (const ival*)b;
+    return x->lo < y->lo ? -1 : x->lo > y->lo ? 1 : 0;
+}
+
+int orc_check_blocks(uint64_t data_bytes, uint64_t chunk_bytes, const uint64_t* sizes,
+                     const int64_t* offs, uint64_t n, orc_blocks_report* rep)
+{
+    memset(rep, 0, sizeof(*rep));
+    rep->n = n;
+    ival* iv = (ival*)malloc((n ? n : 1) * sizeof(ival));
+    uint64_t m = 0;
+    for (uint64_t i = 0; i < n; ++i) {
+        int k = orc_class_of(sizes[i], chunk_bytes);
+        if (offs[i] < 0) {
+            rep->n_null++;
+            if (k >= 0) rep->n_null_valid++;
+            continue;
+        }
+        rep->n_nonnull++;
+        if (k < 0) { rep->n_bad_size_nonnull++; continue; }
+        uint64_t s = orc_page_bytes((uint32_t)k), o = (uint64_t)offs[i];
+        if (o + s > data_bytes || o >= data_bytes) { rep->n_oob++; continue; }
+        if (o % s) rep->n_misaligned++;
+        if (o / chunk_bytes != (o + s - 1) / chunk_bytes) rep->n_straddle++;
+        rep->live[k]++;
+        iv[m].lo = o; iv[m].hi = o + s; m++;
+    }
+    qsort(iv, m, sizeof(ival), ival_cmp);
+    for (uint64_t i = 1; i < m; ++i)
+        if (iv[i].lo < iv[i - 1].hi) rep->n_overlap++;
+    free(iv);
+    return (rep->n_bad_size_nonnull || rep->n_oob || rep->n_misaligned || rep->n_straddle || rep->n_overlap) ? 1 : 0;
+}
+
+/* ------------------------------------------------------------------ */
+/* invariant checker: snapshot (layout version 1)                      */
+/*                                                                     */
+/* header (256 B, little-endian):                                      */
+/*   0 u32 magic 0x48424850   4 u32 version 1     8 u64 data_bytes     */
+/*  16 u32 n_chunks          20 u32 log2_chunk   24 u32 n_classes      */
+/*  28 u32 variant           32 u32 words/chunk  36 u32 log2 ring cap  */
+/*  40 u64 max chunks/class  48 u64 off pool     56 u64 off classes    */
+/*  64 u64 off chunk_class   72 u64 off chunk_cnt 80 u64 off bits      */
+/*  88 u64 off pool_ids      96 u64 off slots    104 u64 total bytes   */
+/* pool block (128 B): u64 bump, u32 size                              */
+/* class block k (384 B): u64 state (H<<32 | C+2^31), u64 owned,       */
+/*   u32 head at +128, u32 tail at +256                                */
+/* chunk_class u8[N] (0xFF unowned), chunk_cnt u32[N], bits u64[N*W],  */
+/* pool_ids u32[N], slots u32[K << log2 ring cap] (0xFFFFFFFF empty);  */
+/* page-variant slots hold the page's byte offset / 16.                */
+/* ------------------------------------------------------------------ */
+
+#define SNAP_MAGIC 0x48424850u
+#define SLOT_EMPTY 0xFFFFFFFFu
+
+static uint32_t rd32(const uint8_t* p) { uint32_t v; memcpy(&v, p, 4); return v; }
+static uint64_t rd64(const uint8_t* p) { uint64_t v; memcpy(&v, p, 8); return v; }
+
+typedef struct {
+    uint64_t data_bytes, N, maxc;
+    uint32_t log2C, K, variant, W, log2q;
+    const uint8_t *pool, *classes, *cls, *cnt, *bits, *pool_ids, *slots;
+} snapview;
+
+static int snap_open(const uint8_t* s, uint64_t len, snapview* v)
+{
+    if (len < 256 || rd32(s) != SNAP_MAGIC || rd32(s + 4) != 1) return 0;
+    v->data_bytes = rd64(s + 8);
+    v->N = rd32(s + 16); v->log2C = rd32(s + 20); v->K = rd32(s + 24);
+    v->variant = rd32(s + 28); v->W = rd32(s + 32); v->log2q = rd32(s + 36);
+    v->maxc = rd64(s + 40);
+    uint64_t o_pool = rd64(s + 48), o_cl = rd64(s + 56), o_cls = rd64(s + 64), o_cnt = rd64(s + 72);
+    uint64_t o_bits = rd64(s + 80), o_pid = rd64(s + 88), o_sl = rd64(s + 96), total = rd64(s + 104);
+    if (total > len || v->K == 0 || v->K > ORC_MAX_CLASSES || v->log2C < 12 || v->log2C > 16) return 0;
+    if (v->W != (1u << v->log2C) / 1024 || v->data_bytes != (v->N << v->log2C)) return 0;
+    if (o_sl + ((uint64_t)v->K << v->log2q) * 4 > total) return 0;
+    v->pool = s + o_pool; v->classes = s + o_cl; v->cls = s + o_cls; v->cnt = s + o_cnt;
+    v->bits = s + o_bits; v->pool_ids = s + o_pid; v->slots = s + o_sl;
+    return 1;
+}
+
+static uint64_t sv_word(const snapview* v, uint64_t c, uint32_t w) { return rd64(v->bits + (c * v->W + w) * 8); }
+
+static uint64_t popc_chunk(const snapview* v, uint64_t c)
+{
+    uint64_t t = 0;
+    for (uint32_t w = 0; w < v->W; ++w) t += (uint64_t)__builtin_popcountll(sv_word(v, c, w));
+    return t;
+}
+
+int orc_check_snapshot(const uint8_t* snap, uint64_t len, orc_snap_report* rep)
+{
+    memset(rep, 0, sizeof(*rep));
+    snapview v;
+    if (!snap_open(snap, len, &v)) { rep->ok_header = 0; return 1; }
+    rep->ok_header = 1;
+    rep->n_classes = v.K;
+    const uint64_t C = 1ull << v.log2C;
+    uint64_t Q = 1ull << v.log2q;
+
+    /* per chunk: class byte, stray bits beyond the class's pages, counts */
+    for (uint64_t c = 0; c < v.N; ++c) {
+        uint8_t k = v.cls[c];
+        uint32_t cn = rd32(v.cnt + c * 4);
+        if (k == 0xFF) {
+            rep->free_chunks++;
+            if (cn != 0 || popc_chunk(&v, c) != 0) rep->bad_free_chunk++;
+            continue;
+        }
+        if (k >= v.K) { rep->bad_class_byte++; continue; }
+        uint64_t ppc = C >> (4 + k);
+        for (uint32_t w = 0; w < v.W; ++w) {
+            uint64_t x = sv_word(&v, c, w);
+            uint64_t lo = (uint64_t)w * 64;
+            uint64_t valid = lo >= ppc ? 0 : (ppc - lo >= 64 ? ~0ull : ((1ull << (ppc - lo)) - 1));
+            if (x & ~valid) rep->bad_stray_bits++;
+        }
+        uint64_t f = popc_chunk(&v, c);
+        if (v.variant == 0 && cn != f) rep->bad_count++;
+        rep->chunks[k]++;
+        rep->free_pages[k] += f;
+        rep->live[k] += ppc - f;
+    }
+
+    /* pool: ids[bump..size) are exactly the unowned chunks */
+    uint64_t bump = rd64(v.pool), psize = rd32(v.pool + 8);
+    uint64_t start = bump < psize ? bump : psize;
+    uint8_t* seen = (uint8_t*)calloc(v.N ? v.N : 1, 1);
+    if (psize > v.N) rep->bad_pool++;
+    else {
+        for (uint64_t i = start; i < psize; ++i) {
+            uint32_t c = rd32(v.pool_ids + i * 4);
+            if (c >= v.N || v.cls[c] != 0xFF || seen[c]) { rep->bad_pool++; continue; }
+            seen[c] = 1;
+        }
+        if (psize - start != rep->free_chunks) rep->bad_pool++;
+    }
+    uint64_t sum = rep->free_chunks;
+    for (uint32_t k = 0; k < v.K; ++k) sum += rep->chunks[k];
+    if (sum != v.N) rep->bad_conservation++;
+
+    /* class rings */
+    for (uint32_t k = 0; k < v.K; ++k) {
+        const uint8_t* cb = v.classes + (uint64_t)k * 384;
+        uint64_t state = rd64(cb), owned = rd64(cb + 8);
+        uint32_t head = rd32(cb + 128), tail = rd32(cb + 256);
+        uint32_t H = (uint32_t)(state >> 32);
+        int64_t Cnt = (int64_t)(uint32_t)state - (int64_t)0x80000000u;
+        uint32_t used = tail - head;
+        if (H != 0 || Cnt != (int64_t)used || used > Q) { rep->bad_ring_ctl++; continue; }
+        if (v.variant == 1 && owned != rep->chunks[k]) rep->bad_owned++;
+        if (v.variant == 1 && rep->chunks[k] > v.maxc) rep->bad_owned++;
+        const uint8_t* sl = v.slots + ((uint64_t)k << v.log2q) * 4;
+        /* slots outside [head, tail) must be empty */
+        for (uint64_t i = used; i < Q; ++i) {
+            uint32_t e = rd32(sl + ((uint64_t)((head + (uint32_t)i) & (uint32_t)(Q - 1))) * 4);
+            if (e != SLOT_EMPTY) rep->bad_ring_entry++;
+        }
+        if (v.variant == 0) {
+            memset(seen, 0, v.N);
+            for (uint32_t i = 0; i < used; ++i) {
+                uint32_t c = rd32(sl + ((uint64_t)((head + i) & (uint32_t)(Q - 1))) * 4);
+                if (c >= v.N || v.cls[c] != k || rd32(v.cnt + (uint64_t)c * 4) == 0) { rep->bad_ring_entry++; continue; }
+                if (seen[c]) { rep->bad_ring_dup++; continue; }
+                seen[c] = 1;
+            }
+            for (uint64_t c = 0; c < v.N; ++c)
+                if (v.cls[c] == k && rd32(v.cnt + c * 4) > 0 && !seen[c]) rep->bad_ring_missing++;
+        } else {
+            /* page variant: entries are exactly the free pages of class k */
+            uint64_t s = 16ull << k, ppc = C >> (4 + k);
+            uint64_t npages = v.N * ppc;
+            uint8_t* pseen = (uint8_t*)calloc(npages ? npages : 1, 1);
+            for (uint32_t i = 0; i < used; ++i) {
+                uint64_t off = (uint64_t)rd32(sl + ((uint64_t)((head + i) & (uint32_t)(Q - 1))) * 4) * 16;
+                uint64_t c = off >> v.log2C;
+                uint64_t in = off & (C - 1);
+                if (off >= v.data_bytes || v.cls[c] != k || in % s) { rep->bad_ring_entry++; continue; }
+                uint64_t p = in / s;
+                if (!((sv_word(&v, c, (uint32_t)(p >> 6)) >> (p & 63)) & 1)) { rep->bad_ring_entry++; continue; }
+                uint64_t gi = c * ppc + p;
+                if (pseen[gi]) { rep->bad_ring_dup++; continue; }
+                pseen[gi] = 1;
+            }
+            for (uint64_t c = 0; c < v.N; ++c) {
+                if (v.cls[c] != k) continue;
+                for (uint64_t p = 0; p < ppc; ++p)
+                    if (((sv_word(&v, c, (uint32_t)(p >> 6)) >> (p & 63)) & 1) && !pseen[c * ppc + p]) rep->bad_ring_missing++;
+            }
+            free(pseen);
+        }
+    }
+    free(seen);
+    uint64_t bad = rep->bad_class_byte + rep->bad_free_chunk + rep->bad_stray_bits + rep->bad_count + rep->bad_pool +
+                   rep->bad_ring_ctl + rep->bad_ring_entry + rep->bad_ring_missing + rep->bad_ring_dup +
+                   rep->bad_conservation + rep->bad_owned;
+    return bad ? 1 : 0;
+}
+
+uint64_t orc_check_blocks_in_snapshot(const uint8_t* snap, uint64_t len, const uint64_t* sizes,
+                                      const int64_t* offs, uint64_t n)
+{
+    snapview v;
+    if (!snap_open(snap, len, &v)) return n ? n : 1;
+    const uint64_t C = 1ull << v.log2C;
+    uint64_t bad = 0;
+    for (uint64_t i = 0; i < n; ++i) {
+        if (offs[i] < 0) continue;
+        int k = orc_class_of(sizes[i], C);
+        uint64_t o = (uint64_t)offs[i];
+        if (k < 0 || o >= v.data_bytes) { bad++; continue; }
+        uint64_t c = o >> v.log2C, p = (o & (C - 1)) >> (4 + k);
+        if (v.cls[c] != (uint8_t)k) { bad++; continue; }
+        if ((sv_word(&v, c, (uint32_t)(p >> 6)) >> (p & 63)) & 1) bad++;
+    }
+    return bad;
+}

@@ -1,0 +1,121 @@
+/*
+ * hbheap_oracle.h -- CPU oracle for the device heap allocator.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product path (the HIP library,
+ * its Python binding, the timed part of the benchmark) may include, link or
+ * call this code; only the tests, the smoke check and the benchmark's CPU
+ * baseline leg do.  It shares no code, header, table or constant generator
+ * with the HIP path: every definition below is written out again here from
+ * the paper and from the documented snapshot format.
+ *
+ * What the paper fixes (Standish, "Dynamic Memory Management on GPUs with
+ * SYCL"):
+ *   - Introduction: the host preallocates a block that acts as the heap and
+ *     a heap algorithm runs on the device; the block is divided into chunks,
+ *     each served through a lock-free queue dedicated to one size.
+ *   - Results, "Page allocator": pages of one fixed size per queue; the heap
+ *     is divided among the queues.
+ *   - Results, "Chunk allocator": queues hold chunks that have free pages;
+ *     an allocation first obtains a chunk index, then scans the chunk for a
+ *     free page.  Queues are per power-of-two size.
+ * Readings where the paper is silent (smallest page 16 B, fixed chunk size,
+ * ceil-to-power-of-two rounding, NULL for 0 or > chunk, metadata outside the
+ * heap bytes, page-variant queue budget) are listed in the design doc.
+ *
+ * Offsets, not pointers: a block is reported as its byte offset from the
+ * start of the heap's data region; -1 stands for NULL.
+ */
+#ifndef HBHEAP_ORACLE_H
+#define HBHEAP_ORACLE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define ORC_MAX_CLASSES 16
+
+enum { ORC_VARIANT_CHUNK = 0, ORC_VARIANT_PAGE = 1 };
+/* LOWEST: canonical legal outcome (lowest chunk id, then lowest page).
+ * FIFO:   the order a single device thread observes (queue order). */
+enum { ORC_POLICY_LOWEST = 0, ORC_POLICY_FIFO = 1 };
+enum { ORC_FREE_OK = 0, ORC_FREE_DOUBLE = 1, ORC_FREE_INVALID = 2, ORC_FREE_NULL = 3 };
+
+/* ---- closed forms of the geometry (Results: page and chunk allocators) ---- */
+int      orc_class_of(uint64_t n, uint64_t chunk_bytes);   /* -1: NULL request */
+uint32_t orc_num_classes(uint64_t chunk_bytes);
+uint64_t orc_page_bytes(uint32_t k);
+uint64_t orc_pages_per_chunk(uint64_t chunk_bytes, uint32_t k);
+uint64_t orc_page_ring_entries(uint64_t bytes, uint64_t chunk_bytes);
+uint64_t orc_page_max_chunks(uint64_t bytes, uint64_t chunk_bytes, uint32_t k);
+int      orc_geometry_ok(uint64_t bytes, uint64_t chunk_bytes);
+
+/* ---- sequential allocator ---- */
+typedef struct orc_heap orc_heap;
+
+typedef struct {
+    uint32_t n_classes;
+    uint32_t pad;
+    uint64_t n_chunks;
+    uint64_t free_chunks;                      /* chunks owned by no class */
+    uint64_t live[ORC_MAX_CLASSES];            /* allocated pages per class */
+    uint64_t chunks[ORC_MAX_CLASSES];          /* chunks owned per class    */
+    uint64_t free_pages[ORC_MAX_CLASSES];      /* free pages inside owned chunks */
+    uint64_t n_alloc_ok, n_alloc_null, n_free_ok, n_free_double, n_free_invalid;
+} orc_acct;
+
+orc_heap* orc_create(uint64_t bytes, uint64_t chunk_bytes, int variant, int policy);
+void      orc_destroy(orc_heap* h);
+int64_t   orc_alloc(orc_heap* h, uint64_t n);
+int       orc_free(orc_heap* h, int64_t off);
+void      orc_trim(orc_heap* h);
+void      orc_alloc_batch(orc_heap* h, const uint64_t* sizes, int64_t* offs, uint64_t n);
+void      orc_free_batch(orc_heap* h, const int64_t* offs, uint64_t n, int32_t* status);
+void      orc_accounting(const orc_heap* h, orc_acct* out);
+/* replay of a mixed op list: op[i] >= 0 is an allocation of op[i] bytes whose
+ * offset goes to out[i]; op[i] < 0 frees the block allocated by op index
+ * (-op[i] - 1), and out[i] receives the free status. */
+void      orc_replay(orc_heap* h, const int64_t* op, uint64_t n, int64_t* out);
+
+/* ---- pattern written into every block (harness) ---- */
+uint32_t orc_fmix32(uint32_t x);
+uint32_t orc_pattern_word(uint32_t seed, uint32_t req, uint32_t i);
+void     orc_pattern_fill(uint32_t seed, uint32_t req, uint8_t* dst, uint64_t nbytes);
+
+/* ---- invariant checker ---- */
+typedef struct {
+    uint64_t n, n_null, n_nonnull;
+    uint64_t n_null_valid;        /* NULL for a request that had a valid size */
+    uint64_t n_bad_size_nonnull;  /* non-NULL for size 0 or size > chunk      */
+    uint64_t n_oob, n_misaligned, n_straddle;
+    uint64_t n_overlap;           /* overlapping neighbour pairs after sorting */
+    uint64_t live[ORC_MAX_CLASSES];
+} orc_blocks_report;
+
+int orc_check_blocks(uint64_t data_bytes, uint64_t chunk_bytes, const uint64_t* sizes,
+                     const int64_t* offs, uint64_t n, orc_blocks_report* rep);
+
+typedef struct {
+    int32_t  ok_header;
+    uint32_t n_classes;
+    uint64_t bad_class_byte, bad_free_chunk, bad_stray_bits, bad_count;
+    uint64_t bad_pool, bad_ring_ctl, bad_ring_entry, bad_ring_missing, bad_ring_dup;
+    uint64_t bad_conservation, bad_owned;
+    uint64_t free_chunks;
+    uint64_t live[ORC_MAX_CLASSES], chunks[ORC_MAX_CLASSES], free_pages[ORC_MAX_CLASSES];
+} orc_snap_report;
+
+/* Quiescent-state consistency of a snapshot (documented layout, version 1). */
+int orc_check_snapshot(const uint8_t* snap, uint64_t len, orc_snap_report* rep);
+
+/* Blocks against a snapshot: each live block must lie in a chunk of its
+ * request's class with its page bit clear (allocated).  Returns the number
+ * of blocks that fail. */
+uint64_t orc_check_blocks_in_snapshot(const uint8_t* snap, uint64_t len, const uint64_t* sizes,
+                                      const int64_t* offs, uint64_t n);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,120 @@
+"""Seeded synthetic workloads shared by the device path's tests, the oracle's
+tests and the benchmark.
+
+This module only draws numbers: request sizes, which blocks to free, growth
+schedules, arrival processes.  It holds none of the allocator's arithmetic
+(no size classes, no geometry), so both sides of a parity test can be fed
+from it without sharing the method's code.
+
+The shapes follow the paper's driver (Methods: many threads allocate in
+parallel, write data, read it back and free, ten times over) and the
+workloads this library is measured on:
+
+* ``tiny``   -- 8 MiB heap, 8 KiB chunks, 1024 threads x 64 B, one round;
+* ``sweep``  -- 4 GiB heap, 2^20 threads, one fixed size per launch swept over
+  powers of two 16 B .. 8 KiB, 10 iterations per size;
+* ``churn``  -- 8 GiB heap, 2^21 threads, log-uniform sizes in [4 B, 8 KiB],
+  50 % freed and reallocated per round, 20 rounds;
+* ``growth`` -- 2^18 agents doubling an int32 list 16 B -> 4 KiB over 9 steps
+  with geometric per-agent growth;
+* ``serve``  -- Poisson batches (mean 4096 requests, 64..65536) of mixed
+  allocations and frees, sizes log-uniform in [16 B, 8 KiB], 16 GiB heap.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass
+
+import numpy as np
+
+KiB = 1 << 10
+MiB = 1 << 20
+GiB = 1 << 30
+
+SEED_TINY = 0xC0F1
+SEED_SWEEP = 0xC0F2
+SEED_CHURN = 0xC0F3
+SEED_GROWTH = 0xC0F4
+SEED_SERVE = 0xC0F5
+
+SWEEP_SIZES = [16 << i for i in range(10)]  # 16 B .. 8 KiB
+
+
+@dataclass(frozen=True)
+class Workload:
+    name: str
+    heap_bytes: int
+    chunk_bytes: int
+    threads: int
+    seed: int
+    rounds: int
+
+
+TINY = Workload("tiny", 8 * MiB, 8 * KiB, 1024, SEED_TINY, 1)
+SWEEP = Workload("sweep", 4 * GiB, 8 * KiB, 1 << 20, SEED_SWEEP, 10)
+CHURN = Workload("churn", 8 * GiB, 8 * KiB, 1 << 21, SEED_CHURN, 20)
+GROWTH = Workload("growth", 4 * GiB, 8 * KiB, 1 << 18, SEED_GROWTH, 9)
+SERVE = Workload("serve", 16 * GiB, 8 * KiB, 4096, SEED_SERVE, 0)
+
+
+def rng(seed: int) -> np.random.Generator:
+    return np.random.Generator(np.random.PCG64(seed))
+
+
+def sizes_fixed(n: int, size: int) -> np.ndarray:
+    return np.full(n, size, dtype=np.uint64)
+
+
+def sizes_log_uniform(n: int, lo: int, hi: int, seed: int) -> np.ndarray:
+    """u ~ U[ln lo, ln(hi+1)), size = min(hi, floor(e^u))."""
+    u = rng(seed).uniform(math.log(lo), math.log(hi + 1), size=n)
+    s = np.floor(np.exp(u)).astype(np.uint64)
+    return np.minimum(s, np.uint64(hi))
+
+
+def churn_round(n: int, round_idx: int, seed: int, lo: int = 4, hi: int = 8 * KiB):
+    """Indices freed in round ``round_idx`` (a random half) and their new sizes."""
+    g = rng(seed + 1 + round_idx)
+    idx = np.sort(g.permutation(n)[: n // 2]).astype(np.int64)
+    new_sizes = sizes_log_uniform(idx.shape[0], lo, hi, seed + 1000 + round_idx)
+    return idx, new_sizes
+
+
+def growth_doublings(agents: int, seed: int, p: float = 0.3, cap: int = 8) -> np.ndarray:
+    """Per-agent number of doublings: min(cap, G) with G ~ Geometric(p) on {0,1,...}."""
+    g = rng(seed).geometric(p, size=agents) - 1
+    return np.minimum(g, cap).astype(np.int32)
+
+
+def serve_batches(n_batches: int, seed: int, mean: int = 4096, lo: int = 64, hi: int = 65536) -> np.ndarray:
+    """Batch sizes ceil(Exponential(mean)) clamped to [lo, hi]."""
+    b = np.ceil(rng(seed).exponential(mean, size=n_batches)).astype(np.int64)
+    return np.clip(b, lo, hi)
+
+
+def serve_arrivals(n_batches: int, rate_per_s: float, seed: int) -> np.ndarray:
+    """Poisson arrival times (seconds from start) at ``rate_per_s`` batches/s."""
+    gaps = rng(seed + 7).exponential(1.0 / rate_per_s, size=n_batches)
+    return np.cumsum(gaps)
+
+
+def op_script(n_ops: int, seed: int, lo: int = 1, hi: int = 8 * KiB, p_free: float = 0.4,
+              p_invalid_size: float = 0.0) -> np.ndarray:
+    """A mixed op list for single-thread replays: op >= 0 allocates op bytes;
+    op < 0 frees the block allocated by op index (-op - 1).  Each live block
+    is freed at most once."""
+    g = rng(seed)
+    ops = np.empty(n_ops, dtype=np.int64)
+    live: list[int] = []
+    for i in range(n_ops):
+        if live and g.random() < p_free:
+            j = live.pop(int(g.integers(len(live))))
+            ops[i] = -j - 1
+        else:
+            if p_invalid_size and g.random() < p_invalid_size:
+                ops[i] = 0 if g.random() < 0.5 else hi * 2
+            else:
+                ops[i] = int(math.floor(math.exp(g.uniform(math.log(lo), math.log(hi + 1)))))
+                ops[i] = min(ops[i], hi)
+            live.append(i)
+    return ops

@@ -1,0 +1,417 @@
+"""Pins of the CPU oracle against what the paper and plain mathematics fix.
+
+The paper prints no worked example, so the oracle is pinned by closed forms
+(class map minimality, capacity N * C / s), textbook special cases (a single
+class with no frees is a bump allocator; the page variant alone is a FIFO
+free list), brute force on small inputs (an occupancy map over every byte),
+exact accounting, and the published MurmurHash3 vectors for the payload
+pattern.  Each test names the mistake it would catch.
+"""
+import os
+import struct
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2504_18211_amd import inputs
+
+KiB = 1024
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _build():
+    O.build(force=False)
+
+
+# ---------------------------------------------------------------------------
+# class map: smallest power-of-two page >= n, 16 B minimum (Results: queues
+# are per power-of-two size; reading: 16 B smallest page)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("C", [4 * KiB, 8 * KiB, 16 * KiB, 32 * KiB, 64 * KiB])
+def test_class_map_is_minimal_cover(C):
+    K = O.num_classes(C)
+    assert O.page_bytes(K - 1) == C, "largest class must be the whole chunk"
+    assert O.class_of(0, C) == -1 and O.class_of(C + 1, C) == -1
+    for n in range(1, C + 1):
+        k = O.class_of(n, C)
+        s = O.page_bytes(k)
+        assert s >= n and s >= 16
+        assert k == 0 or O.page_bytes(k - 1) < n, (n, k)
+        assert s & (s - 1) == 0
+
+
+def test_pages_per_chunk_closed_form():
+    for C in [4 * KiB, 8 * KiB, 64 * KiB]:
+        for k in range(O.num_classes(C)):
+            assert O.pages_per_chunk(C, k) * O.page_bytes(k) == C
+
+
+# ---------------------------------------------------------------------------
+# capacity: a heap of N chunks serves exactly N * C / s pages of one class
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("variant", [O.VARIANT_CHUNK, O.VARIANT_PAGE])
+@pytest.mark.parametrize("policy", [O.POLICY_LOWEST, O.POLICY_FIFO])
+def test_single_class_capacity_exact(variant, policy):
+    C, nbytes = 8 * KiB, 40 * 8 * KiB + 123  # ragged tail of heap bytes is unused
+    N = nbytes // C
+    for k in [0, 3, 6, 9]:
+        h = O.OracleHeap(nbytes, C, variant, policy)
+        s = O.page_bytes(k)
+        cap_chunks = N if variant == O.VARIANT_CHUNK else min(N, O.page_max_chunks(nbytes, C, k))
+        expect = cap_chunks * (C // s)
+        offs = h.alloc_batch(np.full(expect + 5, s, dtype=np.uint64))
+        assert (offs[:expect] >= 0).all()
+        assert (offs[expect:] < 0).all()
+        a = h.accounting()
+        assert a["live"][k] == expect and a["free_pages"][k] == 0
+        h.close()
+
+
+def test_lowest_single_class_is_bump_allocator():
+    """No frees, one class, LOWEST policy: block i sits at i * s."""
+    C, nbytes = 8 * KiB, 16 * 8 * KiB
+    for s in [16, 48, 1000, 4096, 8192]:
+        h = O.OracleHeap(nbytes, C)
+        k = O.class_of(s, C)
+        ps = O.page_bytes(k)
+        n = nbytes // ps
+        offs = h.alloc_batch(np.full(n, s, dtype=np.uint64))
+        assert np.array_equal(offs, np.arange(n, dtype=np.int64) * ps)
+        h.close()
+
+
+def test_page_variant_fifo_is_a_fifo_free_list():
+    """Page variant, FIFO policy, one class: after the fresh pages run out,
+    allocations return freed pages in the order they were freed."""
+    C, nbytes = 8 * KiB, 4 * 8 * KiB
+    h = O.OracleHeap(nbytes, C, O.VARIANT_PAGE, O.POLICY_FIFO)
+    ps = 1024
+    n = nbytes // ps
+    offs = h.alloc_batch(np.full(n, ps, dtype=np.uint64))
+    assert np.array_equal(offs, np.arange(n) * ps)
+    order = np.random.default_rng(5).permutation(n)
+    for i in order:
+        assert h.free(int(offs[i])) == O.FREE_OK
+    again = h.alloc_batch(np.full(n, ps, dtype=np.uint64))
+    assert np.array_equal(again, offs[order])
+    h.close()
+
+
+def test_chunk_variant_fifo_single_chunk_is_lowest_free_bit():
+    """One chunk, chunk variant, FIFO policy: each allocation takes the lowest
+    free page of that chunk (the scan inside a chunk)."""
+    C = 8 * KiB
+    h = O.OracleHeap(C, C, O.VARIANT_CHUNK, O.POLICY_FIFO)
+    ps = 64
+    n = C // ps
+    offs = h.alloc_batch(np.full(n, ps, dtype=np.uint64))
+    freed = sorted(np.random.default_rng(1).choice(n, 37, replace=False).tolist(), reverse=True)
+    for i in freed:
+        assert h.free(int(offs[i])) == O.FREE_OK
+    again = h.alloc_batch(np.full(len(freed), ps, dtype=np.uint64))
+    assert again.tolist() == sorted(int(offs[i]) for i in freed)
+    h.close()
+
+
+def test_chunk_variant_fifo_rotates_partial_chunks():
+    """Two partially used chunks: a chunk that keeps free pages after serving
+    goes to the back of its queue, so consecutive allocations alternate."""
+    C = 8 * KiB
+    h = O.OracleHeap(2 * C, C, O.VARIANT_CHUNK, O.POLICY_FIFO)
+    ps = 1024  # 8 pages per chunk
+    offs = h.alloc_batch(np.full(16, ps, dtype=np.uint64))
+    # free pages 1,2 of chunk 0 then pages 3,4 of chunk 1
+    for i in [1, 2, 8 + 3, 8 + 4]:
+        h.free(int(offs[i]))
+    again = h.alloc_batch(np.full(4, ps, dtype=np.uint64))
+    assert again.tolist() == [1 * ps, C + 3 * ps, 2 * ps, C + 4 * ps]
+    h.close()
+
+
+# ---------------------------------------------------------------------------
+# brute force: random mixed streams on a small heap against a byte map
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("variant", [O.VARIANT_CHUNK, O.VARIANT_PAGE])
+@pytest.mark.parametrize("policy", [O.POLICY_LOWEST, O.POLICY_FIFO])
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_random_stream_against_byte_map(variant, policy, seed):
+    C, nbytes = 4 * KiB, 24 * 4 * KiB
+    h = O.OracleHeap(nbytes, C, variant, policy)
+    occ = np.zeros(nbytes, dtype=np.int32)  # owner id + 1
+    live = {}
+    g = np.random.default_rng(seed)
+    for step in range(4000):
+        if live and g.random() < 0.45:
+            rid = list(live)[int(g.integers(len(live)))]
+            off, s = live.pop(rid)
+            assert h.free(off) == O.FREE_OK
+            assert (occ[off:off + s] == rid + 1).all()
+            occ[off:off + s] = 0
+        else:
+            n = int(g.integers(1, C + 1)) if g.random() < 0.3 else int(g.integers(1, 200))
+            off = h.alloc(n)
+            k = O.class_of(n, C)
+            if off < 0:
+                # NULL only when neither a free page of the class nor a usable
+                # unowned chunk exists (exact out-of-memory)
+                a = h.accounting()
+                assert a["free_pages"][k] == 0
+                cap_hit = variant == O.VARIANT_PAGE and a["chunks"][k] >= O.page_max_chunks(nbytes, C, k)
+                assert a["free_chunks"] == 0 or cap_hit
+                continue
+            s = O.page_bytes(k)
+            assert off % s == 0 and off // C == (off + s - 1) // C and off + s <= (nbytes // C) * C
+            assert (occ[off:off + s] == 0).all(), "overlap"
+            occ[off:off + s] = step + 1
+            live[step] = (off, s)
+    # accounting matches the byte map
+    a = h.accounting()
+    for k in range(O.num_classes(C)):
+        assert a["live"][k] == sum(1 for (o, s) in live.values() if s == O.page_bytes(k))
+    h.close()
+
+
+def test_free_semantics():
+    C = 8 * KiB
+    h = O.OracleHeap(4 * C, C)
+    a = h.alloc(100)  # 128 B class
+    assert a == 0
+    assert h.free(-1) == O.FREE_NULL
+    assert h.free(a + 16) == O.FREE_INVALID  # misaligned for 128 B pages
+    assert h.free(3 * C) == O.FREE_INVALID   # unowned chunk
+    assert h.free(4 * C) == O.FREE_INVALID   # out of range
+    before = h.accounting()
+    assert h.free(a) == O.FREE_OK
+    assert h.free(a) == O.FREE_DOUBLE        # double free changes nothing
+    assert h.free(a + 128) == O.FREE_DOUBLE  # never-allocated page of an owned chunk is free
+    after = h.accounting()
+    assert after["live"][3] == before["live"][3] - 1
+    assert after["n_free_double"] == 2 and after["n_free_invalid"] == 3
+    h.close()
+
+
+@pytest.mark.parametrize("variant", [O.VARIANT_CHUNK, O.VARIANT_PAGE])
+@pytest.mark.parametrize("policy", [O.POLICY_LOWEST, O.POLICY_FIFO])
+def test_trim_returns_to_fresh(variant, policy):
+    C, nbytes = 8 * KiB, 64 * 8 * KiB
+    sizes = inputs.sizes_log_uniform(3000, 4, 8 * KiB, 11)
+    fresh = O.OracleHeap(nbytes, C, variant, policy)
+    ref = fresh.alloc_batch(sizes)
+    fresh.close()
+    h = O.OracleHeap(nbytes, C, variant, policy)
+    offs = h.alloc_batch(sizes)
+    assert np.array_equal(offs, ref)
+    st = h.free_batch(offs[::-1].copy())
+    assert ((st == O.FREE_OK) | (st == O.FREE_NULL)).all()
+    h.trim()
+    a = h.accounting()
+    assert a["free_chunks"] == nbytes // C and sum(a["chunks"]) == 0 and sum(a["live"]) == 0
+    # a trimmed empty heap behaves exactly like a fresh one
+    assert np.array_equal(h.alloc_batch(sizes), ref)
+    h.close()
+
+
+def test_replay_matches_stepwise_calls():
+    ops = inputs.op_script(2000, 3, p_invalid_size=0.05)
+    C, nbytes = 8 * KiB, 32 * 8 * KiB
+    h1 = O.OracleHeap(nbytes, C, O.VARIANT_CHUNK, O.POLICY_FIFO)
+    out = h1.replay(ops)
+    h2 = O.OracleHeap(nbytes, C, O.VARIANT_CHUNK, O.POLICY_FIFO)
+    ref = []
+    for i, op in enumerate(ops):
+        ref.append(h2.alloc(int(op)) if op >= 0 else h2.free(int(ref[-op - 1])))
+    assert out.tolist() == ref
+
+
+# ---------------------------------------------------------------------------
+# checker: planted mistakes must be caught
+# ---------------------------------------------------------------------------
+
+def test_check_blocks_catches_planted_faults():
+    C, data = 8 * KiB, 8 * 8 * KiB
+    sizes = np.array([16, 16, 100, 8192, 0, 17], dtype=np.uint64)
+    good = np.array([0, 16, 128, C, -1, 32], dtype=np.int64)
+    r = O.check_blocks(data, C, sizes, good)
+    assert r.n_overlap == 0 and r.n_misaligned == 0 and r.n_oob == 0 and r.n_null_valid == 0
+    assert list(r.live)[:3] == [2, 1, 0] and r.live[3] == 1 and r.live[9] == 1
+    bad = good.copy(); bad[1] = 8            # overlaps block 0, misaligned
+    r = O.check_blocks(data, C, sizes, bad)
+    assert r.n_overlap == 1 and r.n_misaligned == 1
+    bad = good.copy(); bad[3] = 7 * C + 4096  # 8 KiB page straddles the heap end
+    assert O.check_blocks(data, C, sizes, bad).n_oob == 1
+    bad = good.copy(); bad[4] = 0             # non-NULL for a size-0 request
+    assert O.check_blocks(data, C, sizes, bad).n_bad_size_nonnull == 1
+    bad = good.copy(); bad[0] = -1            # NULL for a valid request
+    assert O.check_blocks(data, C, sizes, bad).n_null_valid == 1
+    bad = good.copy(); bad[2] = C - 64        # 128 B page at C-64 crosses into the next chunk
+    r = O.check_blocks(data, C, sizes, bad)
+    assert r.n_straddle == 1 and r.n_misaligned == 1
+
+
+# ---------------------------------------------------------------------------
+# snapshot checker on hand-built snapshots of the documented layout
+# ---------------------------------------------------------------------------
+
+def build_snapshot(N, log2C, variant, log2q, cls, cnt, bits, pool_bump, pool_ids, rings, owned=None, maxc=None):
+    """Write a version-1 snapshot from plain arrays.  rings[k] = (H, head, entries)."""
+    K = log2C - 3
+    W = (1 << log2C) // 1024
+    Q = 1 << log2q
+    def al(x):
+        return (x + 255) & ~255
+    off_pool = 256
+    off_cl = off_pool + 128
+    off_cls = al(off_cl + 384 * K)
+    off_cnt = al(off_cls + N)
+    off_bits = al(off_cnt + 4 * N)
+    off_pid = al(off_bits + 8 * N * W)
+    off_sl = al(off_pid + 4 * N)
+    total = al(off_sl + 4 * K * Q)
+    b = bytearray(total)
+    struct.pack_into("<IIQIIIIIIQQQQQQQQQ", b, 0, 0x48424850, 1, N << log2C, N, log2C, K, variant, W, log2q,
+                     maxc if maxc is not None else N, off_pool, off_cl, off_cls, off_cnt, off_bits, off_pid, off_sl, total)
+    struct.pack_into("<QI", b, off_pool, pool_bump, len(pool_ids))
+    for i, c in enumerate(pool_ids):
+        struct.pack_into("<I", b, off_pid + 4 * i, c)
+    b[off_cls:off_cls + N] = bytes(cls)
+    for c in range(N):
+        struct.pack_into("<I", b, off_cnt + 4 * c, cnt[c])
+        for w in range(W):
+            struct.pack_into("<Q", b, off_bits + 8 * (c * W + w), bits[c][w])
+    for k in range(K):
+        H, head, ents = rings[k] if k in rings else (0, 0, [])
+        struct.pack_into("<QQ", b, off_cl + 384 * k, (H << 32) | ((len(ents) + 0x80000000) & 0xFFFFFFFF),
+                         (owned or {}).get(k, 0))
+        struct.pack_into("<I", b, off_cl + 384 * k + 128, head & 0xFFFFFFFF)
+        struct.pack_into("<I", b, off_cl + 384 * k + 256, (head + len(ents)) & 0xFFFFFFFF)
+        for j in range(Q):
+            struct.pack_into("<I", b, off_sl + 4 * (k * Q + j), 0xFFFFFFFF)
+        for j, e in enumerate(ents):
+            struct.pack_into("<I", b, off_sl + 4 * (k * Q + ((head + j) % Q)), e)
+    return bytes(b)
+
+
+def _tiny_state():
+    # 4 chunks of 4 KiB (W = 4 words, K = 9); chunk 0 class 6 (1 KiB, 4 pages)
+    # with pages 1,3 free; chunk 2 class 0 (16 B, 256 pages) with page 5 free;
+    # chunks 1 and 3 unowned and still in the pool.
+    N, log2C = 4, 12
+    cls = [6, 0xFF, 0, 0xFF]
+    cnt = [2, 0, 1, 0]
+    bits = [[0b1010, 0, 0, 0], [0, 0, 0, 0], [1 << 5, 0, 0, 0], [0, 0, 0, 0]]
+    pool_ids = [2, 0, 1, 3]
+    return N, log2C, cls, cnt, bits, pool_ids
+
+
+def test_snapshot_checker_accepts_consistent_state():
+    N, log2C, cls, cnt, bits, pool_ids = _tiny_state()
+    snap = build_snapshot(N, log2C, 0, 2, cls, cnt, bits, 2, pool_ids, {6: (0, 5, [0]), 0: (0, 0, [2])})
+    r = O.check_snapshot(snap)
+    assert r.ok_header and not r.violations(), r.violations()
+    assert r.free_chunks == 2 and r.live[6] == 2 and r.live[0] == 255 and r.free_pages[6] == 2
+
+
+@pytest.mark.parametrize("plant,field", [
+    ("count", "bad_count"), ("stray", "bad_stray_bits"), ("dup", "bad_ring_dup"),
+    ("missing", "bad_ring_missing"), ("held", "bad_ring_ctl"), ("pool", "bad_pool"),
+    ("freebits", "bad_free_chunk"), ("badclass", "bad_class_byte"),
+])
+def test_snapshot_checker_catches_planted_faults(plant, field):
+    N, log2C, cls, cnt, bits, pool_ids = _tiny_state()
+    rings = {6: (0, 5, [0]), 0: (0, 0, [2])}
+    bump = 2
+    if plant == "count":
+        cnt[0] = 3
+    elif plant == "stray":
+        bits[0][0] |= 1 << 4           # class 6 has 4 pages per 4 KiB chunk
+    elif plant == "dup":
+        rings[6] = (0, 5, [0, 0])
+    elif plant == "missing":
+        rings[0] = (0, 0, [])
+    elif plant == "held":
+        rings[6] = (1, 5, [0])
+    elif plant == "pool":
+        pool_ids = [2, 0, 1, 1]
+    elif plant == "freebits":
+        bits[1][2] = 1
+    elif plant == "badclass":
+        cls[1] = 12
+    snap = build_snapshot(N, log2C, 0, 2, cls, cnt, bits, bump, pool_ids, rings)
+    v = O.check_snapshot(snap).violations()
+    assert v.get(field, 0) > 0, (plant, v)
+
+
+def test_snapshot_checker_page_variant():
+    N, log2C, cls, cnt, bits, pool_ids = _tiny_state()
+    # page variant: entries are byte offsets / 16 of the free pages
+    e6 = [(0 * 4096 + 1 * 1024) // 16, (0 * 4096 + 3 * 1024) // 16]
+    e0 = [(2 * 4096 + 5 * 16) // 16]
+    snap = build_snapshot(N, log2C, 1, 2, cls, [0] * 4, bits, 2, pool_ids, {6: (0, 3, e6), 0: (0, 0, e0)},
+                          owned={6: 1, 0: 1})
+    assert not O.check_snapshot(snap).violations()
+    bad = build_snapshot(N, log2C, 1, 2, cls, [0] * 4, bits, 2, pool_ids, {6: (0, 3, e6[:1]), 0: (0, 0, e0)},
+                         owned={6: 1, 0: 1})
+    assert O.check_snapshot(bad).violations().get("bad_ring_missing", 0) == 1
+    bad = build_snapshot(N, log2C, 1, 2, cls, [0] * 4, bits, 2, pool_ids, {6: (0, 3, e6), 0: (0, 0, e0)},
+                         owned={6: 2, 0: 1})
+    assert O.check_snapshot(bad).violations().get("bad_owned", 0) == 1
+
+
+def test_blocks_in_snapshot():
+    N, log2C, cls, cnt, bits, pool_ids = _tiny_state()
+    snap = build_snapshot(N, log2C, 0, 2, cls, cnt, bits, 2, pool_ids, {6: (0, 5, [0]), 0: (0, 0, [2])})
+    sizes = np.array([1000, 1000, 16, 16, 16], dtype=np.uint64)
+    assert O.check_blocks_in_snapshot(snap, sizes, np.array([0, 2048, 2 * 4096, -1, 2 * 4096 + 16], dtype=np.int64)) == 0
+    # page 1 of chunk 0 is free -> not a live block; 16 B block in a 1 KiB chunk
+    assert O.check_blocks_in_snapshot(snap, sizes, np.array([1024, 0, 16, -1, -1], dtype=np.int64)) == 2
+
+
+# ---------------------------------------------------------------------------
+# payload pattern: MurmurHash3 x86_32 published vectors pin fmix32
+# ---------------------------------------------------------------------------
+
+def _rotl(x, r):
+    return ((x << r) | (x >> (32 - r))) & 0xFFFFFFFF
+
+
+def _murmur3_x86_32(key: bytes, seed: int) -> int:
+    h, c1, c2 = seed, 0xCC9E2D51, 0x1B873593
+    nb = len(key) // 4
+    for i in range(nb):
+        k = int.from_bytes(key[4 * i:4 * i + 4], "little")
+        k = _rotl((k * c1) & 0xFFFFFFFF, 15) * c2 & 0xFFFFFFFF
+        h = (_rotl(h ^ k, 13) * 5 + 0xE6546B64) & 0xFFFFFFFF
+    t = key[4 * nb:]
+    k = 0
+    for j in range(len(t) - 1, -1, -1):
+        k ^= t[j] << (8 * j)
+    if t:
+        h ^= _rotl((k * c1) & 0xFFFFFFFF, 15) * c2 & 0xFFFFFFFF
+    return O.fmix32(h ^ len(key))
+
+
+def test_fmix32_published_vectors():
+    n = 0
+    with open(os.path.join(GOLD, "murmur3_x86_32_vectors.txt")) as f:
+        for line in f:
+            if line.startswith("#") or not line.strip():
+                continue
+            key, seed, want = line.split()
+            kb = b"" if key == "-" else bytes.fromhex(key)
+            assert _murmur3_x86_32(kb, int(seed, 16)) == int(want, 16), line
+            n += 1
+    assert n >= 10
+
+
+def test_pattern_bytes_little_endian_truncated():
+    seed, req = 0xC0F2 ^ 77, 77
+    w0, w1 = O.pattern_word(seed, req, 0), O.pattern_word(seed, req, 1)
+    assert O.pattern_word(seed, req, 0) == O.fmix32(seed ^ O.fmix32(req) ^ 0)
+    assert O.pattern_word(seed, req, 1) == O.fmix32(seed ^ O.fmix32(req) ^ 0x9E3779B9)
+    b = O.pattern_bytes(seed, req, 6)
+    assert b == w0.to_bytes(4, "little") + w1.to_bytes(4, "little")[:2]
