@@ -1,0 +1,181 @@
+/*
+ * hbheap.h -- C ABI of the device heap allocator (host side).
+ *
+ * The paper's problem statement (Introduction): dynamic allocation inside
+ * running device kernels, served by a heap that the host preallocates once
+ * and that a heap algorithm on the device manages; the block is cut into
+ * chunks, each size served through its own lock-free queue.  The paper's
+ * driver (Methods) allocates many blocks in parallel, writes data into them,
+ * checks it on read-back and frees them, timing allocation and free.
+ *
+ * Conventions for every entry point:
+ *   - Return 0 (HBHEAP_OK) or a negative HBHEAP_E_* code; nothing aborts the
+ *     process.  Arguments are validated on the host before any launch.
+ *   - "device buffer" = memory from hipMalloc (or a torch CUDA tensor)
+ *     that the caller owns and keeps alive until the work on `stream` ends.
+ *   - Calls that take a stream are asynchronous and stream-ordered unless
+ *     said otherwise.  A NULL stream is the null stream.
+ *   - The library owns every byte of the heap; `heap_t` is opaque.
+ */
+#ifndef HBHEAP_H
+#define HBHEAP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#include "hbheap_types.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct hbheap_heap* heap_t;
+
+/* Tunables of heap_create_ex.  Zero fields take the defaults. */
+typedef struct heap_config {
+    uint32_t variant;      /* HBHEAP_VARIANT_CHUNK (default) or _PAGE          */
+    uint32_t width;        /* lanes aggregated per queue operation: power of
+                              two in [1, 64], default 64                     */
+    uint32_t spin_cap;     /* bounded-wait iterations, default 1 << 18        */
+    uint32_t backoff_max;  /* longest backoff in s_sleep(1) units, default 64 */
+    uint32_t flags;        /* HBHEAP_FLAG_*                                   */
+} heap_config_t;
+
+/* Geometry and placement of a heap (heap_info). */
+typedef struct heap_info {
+    void*    data;            /* device address of the data region           */
+    uint64_t data_bytes;      /* n_chunks * chunk_bytes                      */
+    uint64_t chunk_bytes;
+    uint64_t n_chunks;
+    uint32_t n_classes;       /* pages 16 B * 2^k, k < n_classes             */
+    uint32_t variant;
+    uint64_t ring_entries;    /* capacity of each class queue                */
+    uint64_t state_bytes;     /* size of the state region (= snapshot size)  */
+    uint64_t metadata_bytes;  /* all device memory besides the data region   */
+} heap_info_t;
+
+/*
+ * Create a heap of floor(bytes / chunk_bytes) chunks (Introduction: the host
+ * preallocates the heap).  Metadata is allocated separately and is not
+ * counted in `bytes`.  chunk_bytes: power of two in [4 KiB, 64 KiB]; bytes
+ * >= chunk_bytes; page variant: data region at most 64 GiB.  Blocking: the
+ * heap is initialised when the call returns.  *out is untouched on error.
+ * Errors: HBHEAP_E_INVAL (geometry, config, out == NULL), HBHEAP_E_NOMEM
+ * (hipMalloc failed), HBHEAP_E_HIP.
+ */
+int heap_create(size_t bytes, size_t chunk_bytes, heap_t* out);
+int heap_create_ex(size_t bytes, size_t chunk_bytes, const heap_config_t* cfg, heap_t* out);
+
+/* Free all device memory of the heap.  The caller guarantees no work on the
+ * heap is in flight; every block becomes invalid.  NULL is a no-op. */
+int heap_destroy(heap_t h);
+
+/*
+ * Batch allocation: thread i of one launch sets ptrs[i] to a block of at
+ * least sizes[i] bytes, or NULL when sizes[i] is 0, exceeds chunk_bytes, or
+ * neither a page of its class nor an unowned chunk is left.  sizes (u64) and
+ * ptrs are device buffers of n entries.  256-thread blocks; the lanes of each
+ * wave are aggregated by size class (Porting section: warp votes let several
+ * allocations of one warp proceed together).
+ * Errors: HBHEAP_E_INVAL (h NULL, or a NULL buffer with n > 0), HBHEAP_E_HIP.
+ */
+int heap_alloc_batch(heap_t h, const size_t* sizes, void** ptrs, size_t n, hipStream_t stream);
+
+/*
+ * Batch free of ptrs[0..n) (device buffer).  NULL entries are skipped.
+ * sizes may be NULL; if given, each must be the size the block was
+ * requested with (same class), else the free is invalid.  Invalid pointers
+ * and double frees are ignored and set bits of the sticky error word.
+ */
+int heap_free_batch(heap_t h, const size_t* sizes, void* const* ptrs, size_t n, hipStream_t stream);
+
+/* As heap_free_batch; status (device buffer of n int32, may be NULL)
+ * receives 0 ok, 1 double free, 2 invalid, 3 NULL pointer per entry. */
+int heap_free_batch_ex(heap_t h, const size_t* sizes, void* const* ptrs, size_t n, int32_t* status,
+                       hipStream_t stream);
+
+/* Device handle for user kernels calling dev_malloc/dev_free
+ * (hbheap_device.h).  Valid until heap_destroy. */
+int heap_device_handle(heap_t h, hbheap_dev_t* out);
+
+/* Geometry, placement and metadata size. */
+int heap_info(heap_t h, heap_info_t* out);
+
+/*
+ * Quiescent trim (stream-ordered; no other work on the heap may overlap):
+ * chunks whose pages are all free return to the pool, and the pool and the
+ * class queues are rewritten in ascending order with head = 0.  After every
+ * block is freed, trim makes the state region byte-identical to a fresh
+ * heap's.
+ */
+int heap_trim(heap_t h, hipStream_t stream);
+
+/*
+ * Copy the state region (layout version 1, documented in the design doc and in
+ * the header of the snapshot itself) into host memory `dst` of `cap` bytes.
+ * Synchronises `stream`.  *len receives the size (also when cap is too
+ * small, which returns HBHEAP_E_RANGE).  dst may be NULL to query the size.
+ */
+int heap_snapshot(heap_t h, void* dst, size_t cap, size_t* len, hipStream_t stream);
+
+/* Sticky device error word (HBHEAP_ERR_* bits); synchronises the device
+ * copy with a blocking read.  heap_clear_error resets it to 0. */
+int heap_get_error(heap_t h, uint32_t* err);
+int heap_clear_error(heap_t h);
+
+/* Device statistics counters (HBHEAP_STAT_*), blocking read. */
+int heap_stats(heap_t h, uint64_t* out, size_t count);
+
+/*
+ * Single-thread replay of an op list on one device lane, in order (the
+ * deterministic case that a sequential pool allocator reproduces exactly).
+ * ops/out: device buffers of n int64.  ops[i] >= 0 allocates ops[i] bytes and
+ * out[i] gets the block's byte offset in the data region or -1; ops[i] < 0
+ * frees the block of op index -ops[i]-1 (a previous allocation) and out[i]
+ * gets the free status (0 ok, 1 double, 2 invalid, 3 NULL).
+ */
+int heap_replay(heap_t h, const int64_t* ops, int64_t* out, size_t n, hipStream_t stream);
+
+/* ---------------- harness: payload written into blocks (Methods) ---------
+ * Block i holds exactly sizes[i] bytes of the little-endian words
+ * w_j = fmix32(seed ^ fmix32(i) ^ j * 0x9E3779B9), fmix32 being the 32-bit
+ * finaliser of MurmurHash3; the last word is truncated.  NULL blocks are
+ * skipped, and so is any block not wholly inside h's data region (the check
+ * counts it as one mismatch).  heap_pattern_check adds the number of
+ * mismatching words to *mismatches (a device u64). */
+int heap_pattern_write(heap_t h, void* const* ptrs, const size_t* sizes, size_t n, uint32_t seed,
+                       hipStream_t stream);
+int heap_pattern_check(heap_t h, void* const* ptrs, const size_t* sizes, size_t n, uint32_t seed,
+                       unsigned long long* mismatches, hipStream_t stream);
+
+/* ---------------- measurement kernels ----------------------------------- */
+
+/* Device atomic-throughput probes over `buf` (device, >= buf_bytes):
+ *   pattern 0: one 64-bit atomic add per wave, all on one address;
+ *   pattern 1: one per wave on `lines` addresses 128 B apart (wave % lines);
+ *   pattern 2: one 32-bit atomic add per lane on pseudo-random words of buf;
+ *   pattern 3: one 64-bit compare-and-swap per wave on one address;
+ *   pattern 4: one 64-bit atomic add per lane on one address.
+ * `threads` lanes each repeat `iters` times.  Atomics issued: pattern 2 and
+ * 4: threads * iters; others: threads / 64 * iters. */
+int hb_atomic_probe(int pattern, void* buf, size_t buf_bytes, size_t threads, uint32_t lines, uint32_t iters,
+                    hipStream_t stream);
+
+/* HBM stream copy of `bytes` (multiple of 16) from src to dst. */
+int hb_stream_copy(void* dst, const void* src, size_t bytes, hipStream_t stream);
+
+/* Baseline: the runtime's own per-thread device malloc / free.
+ * hb_plain_set_heap sets the device malloc heap limit (call before use). */
+int hb_plain_set_heap(size_t bytes);
+int hb_plain_alloc(const size_t* sizes, void** ptrs, size_t n, hipStream_t stream);
+int hb_plain_free(void* const* ptrs, size_t n, hipStream_t stream);
+
+/* Library version string. */
+const char* hbheap_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,91 @@
+/*
+ * hbheap_types.h -- plain-C types shared by the host C ABI (hbheap.h) and
+ * the device API (hbheap_device.h).
+ *
+ * The heap follows the paper's statement of the problem (Introduction): the
+ * host preallocates one block of device memory that acts as the heap, and a
+ * heap algorithm running on the device serves allocation requests from
+ * threads of running kernels.  The block is cut into chunks of one fixed
+ * size C, and a chunk handed to a size class is split into pages of that
+ * class (Results, "Page allocator" and "Chunk allocator").
+ */
+#ifndef HBHEAP_TYPES_H
+#define HBHEAP_TYPES_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Queue variants (Results): "chunk" queues list chunks that have free
+ * pages; "page" queues list free pages. */
+#define HBHEAP_VARIANT_CHUNK 0u
+#define HBHEAP_VARIANT_PAGE  1u
+
+/* Return codes of every host entry point. */
+#define HBHEAP_OK          0
+#define HBHEAP_E_INVAL    -1   /* bad argument                              */
+#define HBHEAP_E_NOMEM    -2   /* device memory for the heap not available  */
+#define HBHEAP_E_HIP      -3   /* a HIP runtime call failed                 */
+#define HBHEAP_E_RANGE    -4   /* buffer too small for the requested data   */
+#define HBHEAP_E_UNSUP    -5   /* feature not available on this device      */
+
+/* Bits of the sticky device error word (heap_get_error). */
+#define HBHEAP_ERR_DOUBLE_FREE  0x1u  /* a page freed while already free     */
+#define HBHEAP_ERR_INVALID_FREE 0x2u  /* pointer outside the heap, misaligned
+                                         for its class, in an unowned chunk,
+                                         or with a size of another class     */
+#define HBHEAP_ERR_TIMEOUT      0x4u  /* a bounded wait gave up: the heap is
+                                         inconsistent and must be destroyed  */
+#define HBHEAP_ERR_CORRUPT      0x8u  /* a queue entry contradicted the
+                                         bitmasks: the heap is inconsistent  */
+
+/* Indices of the device statistics counters (heap_stats). */
+#define HBHEAP_STAT_CHUNK_GRABS   0   /* chunks taken from the pool (FLAG_STATS) */
+#define HBHEAP_STAT_REFILLS       1   /* refills of a class queue (FLAG_STATS)   */
+#define HBHEAP_STAT_OOM           2   /* requests that returned NULL on OOM  */
+#define HBHEAP_STAT_OOM_WAITS     3   /* OOM checks that had to wait         */
+#define HBHEAP_STAT_DOUBLE_FREE   4
+#define HBHEAP_STAT_INVALID_FREE  5
+#define HBHEAP_STAT_TIMEOUTS      6
+#define HBHEAP_STAT_COUNT         8
+
+/*
+ * Device handle: plain data passed by value as a kernel argument.  All
+ * pointers are device pointers into memory the library owns.  Obtain it with
+ * heap_device_handle(); it stays valid until heap_destroy().
+ */
+typedef struct hbheap_dev {
+    uint8_t*  data;            /* data region: n_chunks * 2^log2_chunk bytes  */
+    uint8_t*  state;           /* state region (snapshot layout, version 1)  */
+    uint64_t* pool;            /* [0] bump (u64); [1] low 32 bits: size      */
+    uint8_t*  classes;         /* n_classes control blocks of 384 bytes      */
+    uint8_t*  chunk_class;     /* class of each chunk, 0xFF when unowned     */
+    int32_t*  chunk_cnt;       /* free pages per chunk (chunk variant)       */
+    uint64_t* bits;            /* words_per_chunk words per chunk, 1 = free  */
+    uint32_t* pool_ids;        /* ids of unowned chunks, consumed by bump    */
+    uint32_t* slots;           /* n_classes rings of 2^log2q u32 entries     */
+    uint32_t* err;             /* sticky error word                          */
+    uint64_t* stats;           /* HBHEAP_STAT_COUNT counters                 */
+    uint64_t  data_bytes;
+    uint32_t  n_chunks;
+    uint32_t  log2_chunk;
+    uint32_t  n_classes;       /* log2_chunk - 3: pages 16 B .. chunk        */
+    uint32_t  variant;
+    uint32_t  words_per_chunk; /* chunk / 1024                               */
+    uint32_t  log2q;           /* ring capacity per class, log2              */
+    uint32_t  width;           /* aggregation width: 1, 16, 32 or 64 lanes   */
+    uint32_t  spin_cap;        /* bounded-wait iterations before TIMEOUT     */
+    uint32_t  backoff_max;     /* largest s_sleep backoff, in s_sleep(1)s    */
+    uint32_t  flags;           /* HBHEAP_FLAG_* bits                         */
+} hbheap_dev_t;
+
+/* Count refills and chunk grabs in the statistics counters (one extra
+ * atomic per refill; errors and out-of-memory are always counted). */
+#define HBHEAP_FLAG_STATS 0x1u
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -485,7 +485,7 @@ int orc_check_blocks(uint64_t data_bytes, uint64_t chunk_bytes, const uint64_t* 
 /*   0 u32 magic 0x48424850   4 u32 version 1     8 u64 data_bytes     */
 /*  16 u32 n_chunks          20 u32 log2_chunk   24 u32 n_classes      */
 /*  28 u32 variant           32 u32 words/chunk  36 u32 log2 ring cap  */
-/*  40 u64 max chunks/class  48 u64 off pool     56 u64 off classes    */
+/*  40 u64 reserved (0)      48 u64 off pool     56 u64 off classes    */
 /*  64 u64 off chunk_class   72 u64 off chunk_cnt 80 u64 off bits      */
 /*  88 u64 off pool_ids      96 u64 off slots    104 u64 total bytes   */
 /* pool block (128 B): u64 bump, u32 size                              */
@@ -493,7 +493,8 @@ int orc_check_blocks(uint64_t data_bytes, uint64_t chunk_bytes, const uint64_t* 
 /*   u32 head at +128, u32 tail at +256                                */
 /* chunk_class u8[N] (0xFF unowned), chunk_cnt u32[N], bits u64[N*W],  */
 /* pool_ids u32[N], slots u32[K << log2 ring cap] (0xFFFFFFFF empty);  */
-/* page-variant slots hold the page's byte offset / 16.                */
+/* page-variant slots hold the page's byte offset / 16; a page-variant */
+/* class may own at most (ring entries / pages per chunk) chunks.       */
 /* ------------------------------------------------------------------ */
 
 #define SNAP_MAGIC 0x48424850u
@@ -503,7 +504,7 @@ static uint32_t rd32(const uint8_t* p) { uint32_t v; memcpy(&v, p, 4); return v;
 static uint64_t rd64(const uint8_t* p) { uint64_t v; memcpy(&v, p, 8); return v; }
 
 typedef struct {
-    uint64_t data_bytes, N, maxc;
+    uint64_t data_bytes, N;
     uint32_t log2C, K, variant, W, log2q;
     const uint8_t *pool, *classes, *cls, *cnt, *bits, *pool_ids, *slots;
 } snapview;
@@ -514,7 +515,6 @@ static int snap_open(const uint8_t* s, uint64_t len, snapview* v)
     v->data_bytes = rd64(s + 8);
     v->N = rd32(s + 16); v->log2C = rd32(s + 20); v->K = rd32(s + 24);
     v->variant = rd32(s + 28); v->W = rd32(s + 32); v->log2q = rd32(s + 36);
-    v->maxc = rd64(s + 40);
     uint64_t o_pool = rd64(s + 48), o_cl = rd64(s + 56), o_cls = rd64(s + 64), o_cnt = rd64(s + 72);
     uint64_t o_bits = rd64(s + 80), o_pid = rd64(s + 88), o_sl = rd64(s + 96), total = rd64(s + 104);
     if (total > len || v->K == 0 || v->K > ORC_MAX_CLASSES || v->log2C < 12 || v->log2C > 16) return 0;
@@ -595,7 +595,7 @@ int orc_check_snapshot(const uint8_t* snap, uint64_t len, orc_snap_report* rep)
         uint32_t used = tail - head;
         if (H != 0 || Cnt != (int64_t)used || used > Q) { rep->bad_ring_ctl++; continue; }
         if (v.variant == 1 && owned != rep->chunks[k]) rep->bad_owned++;
-        if (v.variant == 1 && rep->chunks[k] > v.maxc) rep->bad_owned++;
+        if (v.variant == 1 && rep->chunks[k] > (Q >> (v.log2C - 4 - k))) rep->bad_owned++;
         const uint8_t* sl = v.slots + ((uint64_t)k << v.log2q) * 4;
         /* slots outside [head, tail) must be empty */
         for (uint64_t i = used; i < Q; ++i) {

@@ -1,0 +1,799 @@
+/*
+ * hbheap.hip -- host library and kernels of the device heap allocator
+ * (C ABI in include/hbheap.h, device API in include/hbheap_device.h).
+ *
+ * Contents:
+ *   - heap creation: state-region layout (snapshot version 1) and init;
+ *   - batch alloc / free kernels (one lane per request, 256-lane blocks);
+ *   - single-lane replay kernel;
+ *   - quiescent trim: retire fully free chunks, rebuild pool and queues in
+ *     ascending order (a counting pass, a scan, a writing pass);
+ *   - payload pattern write/check (the paper's driver writes data into each
+ *     block and checks it on read-back, Methods);
+ *   - measurement kernels: device atomic probes and an HBM copy.
+ * The plain baseline (the runtime's own device malloc/free) is in
+ * plain_baseline.hip.
+ */
+#include <hip/hip_runtime.h>
+
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <new>
+
+#include "hbheap.h"
+#include "hbheap_device.h"
+
+using namespace hbheap::detail;
+
+namespace {
+
+constexpr uint32_t kMagic = 0x48424850u;
+constexpr uint32_t kVersion = 1;
+constexpr uint32_t kBatchBlock = 256;
+constexpr uint32_t kTrimBlock = 1024;
+constexpr uint32_t kMaxKeys = 17; /* up to 13 classes + pool + none */
+
+struct Layout {
+    uint64_t off_pool, off_cl, off_cls, off_cnt, off_bits, off_pid, off_sl, total;
+    uint32_t log2q;
+};
+
+uint64_t al256(uint64_t x) { return (x + 255) & ~255ull; }
+uint32_t ilog2(uint64_t x) { uint32_t r = 0; while (x >>= 1) ++r; return r; }
+uint32_t ceil_log2(uint64_t x) { uint32_t r = 0; while ((1ull << r) < x) ++r; return r; }
+
+}  // namespace
+
+struct hbheap_heap {
+    hbheap_dev_t dev;
+    Layout lay;
+    void* data = nullptr;
+    void* state = nullptr;
+    void* aux = nullptr;      /* err word, stats, trim workspace */
+    uint32_t* trim_counts = nullptr;
+    uint32_t* trim_offsets = nullptr;
+    uint32_t* trim_totals = nullptr;
+    uint32_t* trim_owned = nullptr;
+    uint32_t trim_blocks = 0;
+    uint64_t aux_bytes = 0;
+    uint64_t chunk_bytes = 0;
+};
+
+#define HB_TRY(expr)                                \
+    do {                                            \
+        if ((expr) != hipSuccess) return HBHEAP_E_HIP; \
+    } while (0)
+
+/* ======================================================================= */
+/* kernels                                                                 */
+/* ======================================================================= */
+
+__global__ void k_fill_u32(uint32_t* p, uint64_t n, uint32_t v)
+{
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+__global__ void k_fill_u8(uint8_t* p, uint64_t n, uint8_t v)
+{
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+__global__ void k_iota_u32(uint32_t* p, uint64_t n)
+{
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+        p[i] = (uint32_t)i;
+}
+
+__global__ void __launch_bounds__(kBatchBlock) k_alloc_batch(hbheap_dev_t h, const uint64_t* __restrict__ sizes,
+                                                             void** __restrict__ ptrs, uint64_t n)
+{
+    const uint64_t i = (uint64_t)blockIdx.x * kBatchBlock + threadIdx.x;
+    if (i >= n) return;
+    ptrs[i] = malloc_wave(h, sizes[i]);
+}
+
+__global__ void __launch_bounds__(kBatchBlock) k_free_batch(hbheap_dev_t h, const uint64_t* __restrict__ sizes,
+                                                            void* const* __restrict__ ptrs, uint64_t n,
+                                                            int32_t* __restrict__ status)
+{
+    const uint64_t i = (uint64_t)blockIdx.x * kBatchBlock + threadIdx.x;
+    if (i >= n) return;
+    const uint32_t st = free_wave(h, ptrs[i], sizes ? sizes[i] : 0, sizes != nullptr);
+    if (status) status[i] = (int32_t)st;
+}
+
+/* One lane runs the op list in order. */
+__global__ void k_replay(hbheap_dev_t h, const int64_t* ops, int64_t* out, uint64_t n)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    for (uint64_t i = 0; i < n; ++i) {
+        const int64_t op = ops[i];
+        if (op >= 0) {
+            void* p = malloc_wave(h, (uint64_t)op);
+            out[i] = p ? (int64_t)((uint8_t*)p - h.data) : -1;
+        } else {
+            const uint64_t j = (uint64_t)(-op - 1);
+            const int64_t o = j < i ? out[j] : -1;
+            void* p = o >= 0 ? (void*)(h.data + o) : nullptr;
+            out[i] = (int64_t)free_wave(h, p, 0, false);
+        }
+    }
+}
+
+/* ---------------- trim ---------------- */
+
+struct TrimKey {
+    uint32_t key, weight;
+};
+
+/* Key of a chunk after retirement: class k ring (0..K-1), pool (K), or none
+ * (K+1); weight = entries it contributes. */
+__device__ __forceinline__ TrimKey trim_key(const hbheap_dev_t& h, uint64_t c)
+{
+    TrimKey t;
+    const uint32_t k = h.chunk_class[c];
+    if (k == kFreeClass) { t.key = h.n_classes; t.weight = 1; return t; }
+    if (h.variant == HBHEAP_VARIANT_CHUNK) {
+        const bool listed = h.chunk_cnt[c] > 0;
+        t.key = listed ? k : h.n_classes + 1;
+        t.weight = listed ? 1u : 0u;
+    } else {
+        uint32_t f = 0;
+        const uint32_t ppc = 1u << (h.log2_chunk - 4u - k);
+        const uint32_t nw = ppc >= 64u ? ppc >> 6 : 1u;
+        for (uint32_t w = 0; w < nw; ++w) f += (uint32_t)__popcll(h.bits[c * h.words_per_chunk + w]);
+        t.key = k;
+        t.weight = f;
+    }
+    return t;
+}
+
+/* Pass 1: retire fully free chunks, count entries per key per block. */
+__global__ void __launch_bounds__(kTrimBlock) k_trim_count(hbheap_dev_t h, uint32_t* counts, uint32_t nblocks,
+                                                           uint32_t* owned)
+{
+    __shared__ uint32_t cnt[kMaxKeys], own[kMaxKeys];
+    const uint32_t nkeys = h.n_classes + 2;
+    if (threadIdx.x < kMaxKeys) { cnt[threadIdx.x] = 0; own[threadIdx.x] = 0; }
+    __syncthreads();
+    const uint64_t c = (uint64_t)blockIdx.x * kTrimBlock + threadIdx.x;
+    if (c < h.n_chunks) {
+        const uint32_t k = h.chunk_class[c];
+        if (k != kFreeClass) {
+            const uint32_t ppc = 1u << (h.log2_chunk - 4u - k);
+            const uint32_t nw = ppc >= 64u ? ppc >> 6 : 1u;
+            uint32_t f = 0;
+            for (uint32_t w = 0; w < nw; ++w) f += (uint32_t)__popcll(h.bits[c * h.words_per_chunk + w]);
+            if (f == ppc) {
+                for (uint32_t w = 0; w < h.words_per_chunk; ++w) h.bits[c * h.words_per_chunk + w] = 0;
+                h.chunk_cnt[c] = 0;
+                h.chunk_class[c] = (uint8_t)kFreeClass;
+            } else {
+                atomicAdd(&own[k], 1u);
+            }
+        }
+        const TrimKey t = trim_key(h, c);
+        if (t.weight) atomicAdd(&cnt[t.key], t.weight);
+    }
+    __syncthreads();
+    if (threadIdx.x < nkeys) counts[(uint64_t)threadIdx.x * nblocks + blockIdx.x] = cnt[threadIdx.x];
+    if (threadIdx.x < h.n_classes && own[threadIdx.x]) atomicAdd(&owned[threadIdx.x], own[threadIdx.x]);
+}
+
+/* Pass 2: per key, exclusive scan of the block counts. */
+__global__ void k_trim_scan(const uint32_t* counts, uint32_t* offsets, uint32_t* totals, uint32_t nblocks, uint32_t nkeys)
+{
+    const uint32_t key = threadIdx.x;
+    if (key >= nkeys) return;
+    uint32_t run = 0;
+    for (uint32_t b = 0; b < nblocks; ++b) {
+        offsets[(uint64_t)key * nblocks + b] = run;
+        run += counts[(uint64_t)key * nblocks + b];
+    }
+    totals[key] = run;
+}
+
+/* Block-wide exclusive scan of v over the 1024 threads (all active). */
+__device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t* wsum)
+{
+    const uint32_t me = lane(), wave = threadIdx.x >> 6;
+    uint32_t x = v;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t y = __shfl_up(x, d, 64);
+        if (me >= (uint32_t)d) x += y;
+    }
+    if (me == 63) wsum[wave] = x;
+    __syncthreads();
+    if (threadIdx.x < 64) {
+        uint32_t s = threadIdx.x < kTrimBlock / 64 ? wsum[threadIdx.x] : 0;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const uint32_t y = __shfl_up(s, d, 64);
+            if (me >= (uint32_t)d) s += y;
+        }
+        if (threadIdx.x < kTrimBlock / 64) wsum[threadIdx.x] = s;
+    }
+    __syncthreads();
+    const uint32_t before = wave ? wsum[wave - 1] : 0u;
+    const uint32_t r = before + x - v;
+    __syncthreads();
+    return r;
+}
+
+/* Pass 3: write pool ids and ring entries in ascending chunk (page) order. */
+__global__ void __launch_bounds__(kTrimBlock) k_trim_write(hbheap_dev_t h, const uint32_t* offsets, uint32_t nblocks)
+{
+    __shared__ uint32_t wsum[kTrimBlock / 64];
+    const uint64_t c = (uint64_t)blockIdx.x * kTrimBlock + threadIdx.x;
+    TrimKey t;
+    t.key = h.n_classes + 1;
+    t.weight = 0;
+    if (c < h.n_chunks) t = trim_key(h, c);
+    const uint64_t Q = 1ull << h.log2q;
+    for (uint32_t key = 0; key <= h.n_classes; ++key) {
+        const uint32_t w = t.key == key ? t.weight : 0u;
+        const uint32_t pos = offsets[(uint64_t)key * nblocks + blockIdx.x] + block_excl_scan(w, wsum);
+        if (!w) continue;
+        if (key == h.n_classes) {
+            if (pos < h.n_chunks) h.pool_ids[pos] = (uint32_t)c;
+        } else if (h.variant == HBHEAP_VARIANT_CHUNK) {
+            if (pos < Q) h.slots[(uint64_t)key * Q + pos] = (uint32_t)c;
+        } else {
+            const uint32_t shift = 4u + key;
+            const uint32_t ppc = 1u << (h.log2_chunk - shift);
+            const uint32_t nw = ppc >= 64u ? ppc >> 6 : 1u;
+            uint32_t j = pos;
+            for (uint32_t wd = 0; wd < nw; ++wd) {
+                uint64_t x = h.bits[c * h.words_per_chunk + wd];
+                while (x) {
+                    const uint32_t b = ctz64(x);
+                    x &= x - 1ull;
+                    const uint64_t off = (c << h.log2_chunk) + ((uint64_t)(wd * 64u + b) << shift);
+                    if (j < Q) h.slots[(uint64_t)key * Q + j] = (uint32_t)(off >> 4);
+                    ++j;
+                }
+            }
+        }
+    }
+}
+
+/* Pass 4: queue control words and pool counters. */
+__global__ void k_trim_ctl(hbheap_dev_t h, const uint32_t* totals, const uint32_t* owned)
+{
+    const uint32_t k = threadIdx.x;
+    if (k < h.n_classes) {
+        uint8_t* cb = h.classes + (uint64_t)k * kClassBlock;
+        *(uint64_t*)cb = (uint64_t)(totals[k] + kBias);
+        *(uint64_t*)(cb + 8) = h.variant == HBHEAP_VARIANT_PAGE ? (uint64_t)owned[k] : 0ull;
+        *(uint32_t*)(cb + 128) = 0;
+        *(uint32_t*)(cb + 256) = totals[k];
+    }
+    if (k == 0) {
+        h.pool[0] = 0;
+        h.pool[1] = totals[h.n_classes];
+    }
+}
+
+/* ---------------- payload pattern ---------------- */
+
+__device__ __forceinline__ uint32_t fmix32(uint32_t x)
+{
+    x ^= x >> 16;
+    x *= 0x85ebca6bu;
+    x ^= x >> 13;
+    x *= 0xc2b2ae35u;
+    x ^= x >> 16;
+    return x;
+}
+__device__ __forceinline__ uint32_t pat_word(uint32_t sr, uint32_t j) { return fmix32(sr ^ (j * 0x9E3779B9u)); }
+
+/* Bytes [b0, b1) of the block, b0 a multiple of 16; `step` 16-byte units
+ * apart per iteration starting at unit `first`. */
+__device__ __forceinline__ void pat_write_range(uint8_t* p, uint64_t size, uint32_t sr, uint64_t first, uint64_t step)
+{
+    const uint64_t nq = size >> 4;
+    uint4* q = (uint4*)p;
+    for (uint64_t u = first; u < nq; u += step) {
+        const uint32_t j = (uint32_t)(u * 4);
+        q[u] = make_uint4(pat_word(sr, j), pat_word(sr, j + 1), pat_word(sr, j + 2), pat_word(sr, j + 3));
+    }
+    if (first == 0) {
+        for (uint64_t b = nq << 4; b < size; ++b) {
+            const uint32_t w = pat_word(sr, (uint32_t)(b >> 2));
+            p[b] = (uint8_t)(w >> (8 * (b & 3)));
+        }
+    }
+}
+
+__device__ __forceinline__ uint32_t pat_check_range(const uint8_t* p, uint64_t size, uint32_t sr, uint64_t first, uint64_t step)
+{
+    const uint64_t nq = size >> 4;
+    const uint4* q = (const uint4*)p;
+    uint32_t bad = 0;
+    for (uint64_t u = first; u < nq; u += step) {
+        const uint32_t j = (uint32_t)(u * 4);
+        const uint4 v = q[u];
+        bad += (v.x != pat_word(sr, j)) + (v.y != pat_word(sr, j + 1)) + (v.z != pat_word(sr, j + 2)) +
+               (v.w != pat_word(sr, j + 3));
+    }
+    if (first == 0) {
+        /* tail bytes, counted per (partial) word */
+        for (uint64_t b = nq << 4; b < size; b += 4) {
+            const uint32_t w = pat_word(sr, (uint32_t)(b >> 2));
+            bool ok = true;
+            for (uint64_t e = b; e < size && e < b + 4; ++e) ok &= p[e] == (uint8_t)(w >> (8 * (e & 3)));
+            bad += ok ? 0u : 1u;
+        }
+    }
+    return bad;
+}
+
+constexpr uint64_t kCoopBytes = 1024;
+
+__global__ void __launch_bounds__(kBatchBlock) k_pattern(void* const* ptrs, const uint64_t* sizes, uint64_t n,
+                                                         uint32_t seed, unsigned long long* mismatches, int check,
+                                                         const uint8_t* lo, uint64_t span)
+{
+    const uint64_t i = (uint64_t)blockIdx.x * kBatchBlock + threadIdx.x;
+    if (i >= n) return;
+    uint8_t* p = (uint8_t*)ptrs[i];
+    uint64_t size = p ? sizes[i] : 0;
+    const uint32_t sr = seed ^ fmix32((uint32_t)i);
+    uint32_t bad = 0;
+    /* only blocks that lie inside the heap's data region are touched */
+    if (size && (p < lo || (uint64_t)(p - lo) >= span || span - (uint64_t)(p - lo) < size)) {
+        size = 0;
+        bad = 1;
+    }
+    const bool coop = size >= kCoopBytes;
+    if (!coop && size) {
+        if (check) bad += pat_check_range(p, size, sr, 0, 1);
+        else pat_write_range(p, size, sr, 0, 1);
+    }
+    /* large blocks: the whole wave writes one block at a time, 16 B per lane */
+    uint64_t big = __ballot(coop);
+    const uint32_t me = lane();
+    while (big) {
+        const uint32_t l = ctz64(big);
+        big &= big - 1ull;
+        uint8_t* bp = (uint8_t*)bcast64((uint64_t)p, l);
+        const uint64_t bs = bcast64(size, l);
+        const uint32_t bsr = bcast(sr, l);
+        const uint64_t nq = bs >> 4;
+        if (check) {
+            const uint4* q = (const uint4*)bp;
+            for (uint64_t u = me; u < nq; u += 64) {
+                const uint32_t j = (uint32_t)(u * 4);
+                const uint4 v = q[u];
+                bad += (v.x != pat_word(bsr, j)) + (v.y != pat_word(bsr, j + 1)) + (v.z != pat_word(bsr, j + 2)) +
+                       (v.w != pat_word(bsr, j + 3));
+            }
+        } else {
+            uint4* q = (uint4*)bp;
+            for (uint64_t u = me; u < nq; u += 64) {
+                const uint32_t j = (uint32_t)(u * 4);
+                q[u] = make_uint4(pat_word(bsr, j), pat_word(bsr, j + 1), pat_word(bsr, j + 2), pat_word(bsr, j + 3));
+            }
+        }
+        if (me == l && (bs & 15)) {
+            /* tail bytes of the owner's block */
+            if (check) {
+                for (uint64_t b = nq << 4; b < bs; b += 4) {
+                    const uint32_t w = pat_word(bsr, (uint32_t)(b >> 2));
+                    bool ok = true;
+                    for (uint64_t e = b; e < bs && e < b + 4; ++e) ok &= bp[e] == (uint8_t)(w >> (8 * (e & 3)));
+                    bad += ok ? 0u : 1u;
+                }
+            } else {
+                for (uint64_t b = nq << 4; b < bs; ++b) {
+                    const uint32_t w = pat_word(bsr, (uint32_t)(b >> 2));
+                    bp[b] = (uint8_t)(w >> (8 * (b & 3)));
+                }
+            }
+        }
+    }
+    if (check) {
+        const uint64_t any = __ballot(bad != 0);
+        if (any) atomicAdd(mismatches, (unsigned long long)bad);
+    }
+}
+
+/* ---------------- measurement ---------------- */
+
+__device__ __forceinline__ uint32_t hash32(uint64_t x)
+{
+    return fmix32((uint32_t)x ^ fmix32((uint32_t)(x >> 32) + 0x9E3779B9u));
+}
+
+__global__ void __launch_bounds__(kBatchBlock) k_atomic_probe(int pattern, uint64_t* buf, uint64_t words64, uint32_t lines,
+                                                              uint32_t iters, uint64_t threads)
+{
+    const uint64_t tid = (uint64_t)blockIdx.x * kBatchBlock + threadIdx.x;
+    if (tid >= threads) return;
+    const uint64_t wave = tid >> 6;
+    const uint32_t me = lane();
+    uint64_t acc = 0;
+    switch (pattern) {
+    case 0:
+        if (me == 0)
+            for (uint32_t it = 0; it < iters; ++it) acc += a_add64(buf, 1);
+        break;
+    case 1:
+        if (me == 0)
+            for (uint32_t it = 0; it < iters; ++it) acc += a_add64(buf + (wave % lines) * 16, 1);
+        break;
+    case 2: {
+        uint32_t* w32 = (uint32_t*)buf;
+        const uint64_t words32 = words64 * 2;
+        for (uint32_t it = 0; it < iters; ++it) acc += a_add32(w32 + hash32(tid * 131u + it) % words32, 1u);
+        break;
+    }
+    case 3:
+        if (me == 0)
+            for (uint32_t it = 0; it < iters; ++it) {
+                uint64_t expect = a_load64(buf);
+                const bool ok = __hip_atomic_compare_exchange_strong(buf, &expect, expect + 1, __ATOMIC_RELAXED,
+                                                                     __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                acc += ok ? 1 : expect;
+            }
+        break;
+    case 4:
+        for (uint32_t it = 0; it < iters; ++it) acc += a_add64(buf + 16, 1);
+        break;
+    default:
+        break;
+    }
+    /* keep the returned values live so the atomics stay returning ones */
+    if (acc == 0x5EED5EED5EED5EEDull) buf[32] = acc;
+}
+
+__global__ void k_copy(uint4* __restrict__ dst, const uint4* __restrict__ src, uint64_t n)
+{
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+        dst[i] = src[i];
+}
+
+/* ======================================================================= */
+/* host side                                                               */
+/* ======================================================================= */
+
+namespace {
+
+uint32_t grid_for(uint64_t n, uint32_t block)
+{
+    const uint64_t g = (n + block - 1) / block;
+    return (uint32_t)(g > 0x7FFFFFFFull ? 0x7FFFFFFFull : (g ? g : 1));
+}
+
+uint32_t grid_stride(uint64_t n) { uint64_t g = (n + 255) / 256; return (uint32_t)(g > 65536 ? 65536 : (g ? g : 1)); }
+
+int fill_u32(uint32_t* p, uint64_t n, uint32_t v, hipStream_t s)
+{
+    if (!n) return HBHEAP_OK;
+    hipLaunchKernelGGL(k_fill_u32, dim3(grid_stride(n)), dim3(256), 0, s, p, n, v);
+    return hipGetLastError() == hipSuccess ? HBHEAP_OK : HBHEAP_E_HIP;
+}
+
+int fill_u8(uint8_t* p, uint64_t n, uint8_t v, hipStream_t s)
+{
+    if (!n) return HBHEAP_OK;
+    hipLaunchKernelGGL(k_fill_u8, dim3(grid_stride(n)), dim3(256), 0, s, p, n, v);
+    return hipGetLastError() == hipSuccess ? HBHEAP_OK : HBHEAP_E_HIP;
+}
+
+Layout make_layout(uint64_t N, uint32_t log2C, uint32_t K, uint32_t variant, uint64_t bytes)
+{
+    Layout L;
+    const uint64_t W = (1ull << log2C) / 1024;
+    if (variant == HBHEAP_VARIANT_CHUNK) {
+        L.log2q = ceil_log2(N);
+    } else {
+        const uint64_t per = bytes / 8 / K / 4;
+        L.log2q = per ? ilog2(per) : 0;
+    }
+    L.off_pool = 256;
+    L.off_cl = L.off_pool + 128;
+    L.off_cls = al256(L.off_cl + (uint64_t)kClassBlock * K);
+    L.off_cnt = al256(L.off_cls + N);
+    L.off_bits = al256(L.off_cnt + 4 * N);
+    L.off_pid = al256(L.off_bits + 8 * N * W);
+    L.off_sl = al256(L.off_pid + 4 * N);
+    L.total = al256(L.off_sl + 4ull * K * (1ull << L.log2q));
+    return L;
+}
+
+void put32(uint8_t* b, uint64_t o, uint32_t v) { memcpy(b + o, &v, 4); }
+void put64(uint8_t* b, uint64_t o, uint64_t v) { memcpy(b + o, &v, 8); }
+
+void release(hbheap_heap* h)
+{
+    if (h->data) (void)hipFree(h->data);
+    if (h->state) (void)hipFree(h->state);
+    if (h->aux) (void)hipFree(h->aux);
+    delete h;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* hbheap_version(void) { return "hbheap 0.1 (gfx950)"; }
+
+int heap_create_ex(size_t bytes, size_t chunk_bytes, const heap_config_t* cfg, heap_t* out)
+{
+    if (!out) return HBHEAP_E_INVAL;
+    if (chunk_bytes < 4096 || chunk_bytes > 65536 || (chunk_bytes & (chunk_bytes - 1))) return HBHEAP_E_INVAL;
+    if (bytes < chunk_bytes) return HBHEAP_E_INVAL;
+    heap_config_t c = {};
+    if (cfg) c = *cfg;
+    if (c.variant > HBHEAP_VARIANT_PAGE) return HBHEAP_E_INVAL;
+    if (!c.width) c.width = 64;
+    if (c.width > 64 || (c.width & (c.width - 1))) return HBHEAP_E_INVAL;
+    if (!c.spin_cap) c.spin_cap = 1u << 18;
+    if (!c.backoff_max) c.backoff_max = 64;
+    const uint64_t N = bytes / chunk_bytes;
+    if (N >= 0x80000000ull) return HBHEAP_E_INVAL;
+    const uint32_t log2C = ilog2(chunk_bytes);
+    const uint32_t K = log2C - 3;
+    if (c.variant == HBHEAP_VARIANT_PAGE && N * chunk_bytes > (64ull << 30)) return HBHEAP_E_INVAL;
+
+    hbheap_heap* h = new (std::nothrow) hbheap_heap();
+    if (!h) return HBHEAP_E_NOMEM;
+    h->chunk_bytes = chunk_bytes;
+    h->lay = make_layout(N, log2C, K, c.variant, bytes);
+    const Layout& L = h->lay;
+    h->trim_blocks = (uint32_t)((N + kTrimBlock - 1) / kTrimBlock);
+    const uint32_t nkeys = K + 2;
+    /* aux: err (256 B line) | stats (256 B) | trim counts | offsets | totals | owned */
+    const uint64_t tb = (uint64_t)h->trim_blocks * nkeys * 4;
+    h->aux_bytes = 512 + al256(tb) * 2 + 256 + 256;
+    if (hipMalloc(&h->data, N * chunk_bytes) != hipSuccess) { h->data = nullptr; release(h); return HBHEAP_E_NOMEM; }
+    if (hipMalloc(&h->state, L.total) != hipSuccess) { h->state = nullptr; release(h); return HBHEAP_E_NOMEM; }
+    if (hipMalloc(&h->aux, h->aux_bytes) != hipSuccess) { h->aux = nullptr; release(h); return HBHEAP_E_NOMEM; }
+
+    uint8_t* st = (uint8_t*)h->state;
+    uint8_t* ax = (uint8_t*)h->aux;
+    hbheap_dev_t& d = h->dev;
+    d.data = (uint8_t*)h->data;
+    d.state = st;
+    d.pool = (uint64_t*)(st + L.off_pool);
+    d.classes = st + L.off_cl;
+    d.chunk_class = st + L.off_cls;
+    d.chunk_cnt = (int32_t*)(st + L.off_cnt);
+    d.bits = (uint64_t*)(st + L.off_bits);
+    d.pool_ids = (uint32_t*)(st + L.off_pid);
+    d.slots = (uint32_t*)(st + L.off_sl);
+    d.err = (uint32_t*)ax;
+    d.stats = (uint64_t*)(ax + 256);
+    d.data_bytes = N * chunk_bytes;
+    d.n_chunks = (uint32_t)N;
+    d.log2_chunk = log2C;
+    d.n_classes = K;
+    d.variant = c.variant;
+    d.words_per_chunk = (uint32_t)(chunk_bytes / 1024);
+    d.log2q = L.log2q;
+    d.width = c.width;
+    d.spin_cap = c.spin_cap;
+    d.backoff_max = c.backoff_max;
+    d.flags = c.flags;
+    h->trim_counts = (uint32_t*)(ax + 512);
+    h->trim_offsets = (uint32_t*)(ax + 512 + al256(tb));
+    h->trim_totals = (uint32_t*)(ax + 512 + 2 * al256(tb));
+    h->trim_owned = (uint32_t*)(ax + 512 + 2 * al256(tb) + 256);
+
+    /* header, pool block and class blocks are built on the host */
+    const uint64_t head_bytes = L.off_cls;
+    uint8_t* hb = (uint8_t*)calloc(1, head_bytes);
+    if (!hb) { release(h); return HBHEAP_E_NOMEM; }
+    put32(hb, 0, kMagic);
+    put32(hb, 4, kVersion);
+    put64(hb, 8, d.data_bytes);
+    put32(hb, 16, (uint32_t)N);
+    put32(hb, 20, log2C);
+    put32(hb, 24, K);
+    put32(hb, 28, c.variant);
+    put32(hb, 32, d.words_per_chunk);
+    put32(hb, 36, L.log2q);
+    put64(hb, 40, 0);
+    put64(hb, 48, L.off_pool);
+    put64(hb, 56, L.off_cl);
+    put64(hb, 64, L.off_cls);
+    put64(hb, 72, L.off_cnt);
+    put64(hb, 80, L.off_bits);
+    put64(hb, 88, L.off_pid);
+    put64(hb, 96, L.off_sl);
+    put64(hb, 104, L.total);
+    put64(hb, L.off_pool, 0);
+    put32(hb, L.off_pool + 8, (uint32_t)N);
+    for (uint32_t k = 0; k < K; ++k) put64(hb, L.off_cl + (uint64_t)k * kClassBlock, kBias);
+
+    int rc = HBHEAP_OK;
+    hipStream_t s = nullptr;
+    if (fill_u32((uint32_t*)st, L.total / 4, 0u, s) || fill_u8(st + L.off_cls, N, (uint8_t)kFreeClass, s) ||
+        fill_u32(d.slots, (uint64_t)K << L.log2q, kEmpty, s) || fill_u32((uint32_t*)ax, h->aux_bytes / 4, 0u, s))
+        rc = HBHEAP_E_HIP;
+    if (rc == HBHEAP_OK) {
+        hipLaunchKernelGGL(k_iota_u32, dim3(grid_stride(N)), dim3(256), 0, s, d.pool_ids, N);
+        if (hipGetLastError() != hipSuccess) rc = HBHEAP_E_HIP;
+    }
+    if (rc == HBHEAP_OK && hipMemcpyAsync(st, hb, head_bytes, hipMemcpyHostToDevice, s) != hipSuccess) rc = HBHEAP_E_HIP;
+    if (rc == HBHEAP_OK && hipStreamSynchronize(s) != hipSuccess) rc = HBHEAP_E_HIP;
+    free(hb);
+    if (rc != HBHEAP_OK) { release(h); return rc; }
+    *out = h;
+    return HBHEAP_OK;
+}
+
+int heap_create(size_t bytes, size_t chunk_bytes, heap_t* out) { return heap_create_ex(bytes, chunk_bytes, nullptr, out); }
+
+int heap_destroy(heap_t h)
+{
+    if (!h) return HBHEAP_OK;
+    int rc = HBHEAP_OK;
+    if (h->data && hipFree(h->data) != hipSuccess) rc = HBHEAP_E_HIP;
+    if (h->state && hipFree(h->state) != hipSuccess) rc = HBHEAP_E_HIP;
+    if (h->aux && hipFree(h->aux) != hipSuccess) rc = HBHEAP_E_HIP;
+    delete h;
+    return rc;
+}
+
+int heap_alloc_batch(heap_t h, const size_t* sizes, void** ptrs, size_t n, hipStream_t stream)
+{
+    if (!h || (n && (!sizes || !ptrs))) return HBHEAP_E_INVAL;
+    if (!n) return HBHEAP_OK;
+    hipLaunchKernelGGL(k_alloc_batch, dim3(grid_for(n, kBatchBlock)), dim3(kBatchBlock), 0, stream, h->dev,
+                       (const uint64_t*)sizes, ptrs, (uint64_t)n);
+    return hipGetLastError() == hipSuccess ? HBHEAP_OK : HBHEAP_E_HIP;
+}
+
+int heap_free_batch_ex(heap_t h, const size_t* sizes, void* const* ptrs, size_t n, int32_t* status, hipStream_t stream)
+{
+    if (!h || (n && !ptrs)) return HBHEAP_E_INVAL;
+    if (!n) return HBHEAP_OK;
+    hipLaunchKernelGGL(k_free_batch, dim3(grid_for(n, kBatchBlock)), dim3(kBatchBlock), 0, stream, h->dev,
+                       (const uint64_t*)sizes, ptrs, (uint64_t)n, status);
+    return hipGetLastError() == hipSuccess ? HBHEAP_OK : HBHEAP_E_HIP;
+}
+
+int heap_free_batch(heap_t h, const size_t* sizes, void* const* ptrs, size_t n, hipStream_t stream)
+{
+    return heap_free_batch_ex(h, sizes, ptrs, n, nullptr, stream);
+}
+
+int heap_device_handle(heap_t h, hbheap_dev_t* out)
+{
+    if (!h || !out) return HBHEAP_E_INVAL;
+    *out = h->dev;
+    return HBHEAP_OK;
+}
+
+int heap_info(heap_t h, heap_info_t* out)
+{
+    if (!h || !out) return HBHEAP_E_INVAL;
+    out->data = h->data;
+    out->data_bytes = h->dev.data_bytes;
+    out->chunk_bytes = h->chunk_bytes;
+    out->n_chunks = h->dev.n_chunks;
+    out->n_classes = h->dev.n_classes;
+    out->variant = h->dev.variant;
+    out->ring_entries = 1ull << h->lay.log2q;
+    out->state_bytes = h->lay.total;
+    out->metadata_bytes = h->lay.total + h->aux_bytes;
+    return HBHEAP_OK;
+}
+
+int heap_trim(heap_t h, hipStream_t stream)
+{
+    if (!h) return HBHEAP_E_INVAL;
+    const hbheap_dev_t& d = h->dev;
+    const uint32_t nkeys = d.n_classes + 2;
+    const uint32_t nb = h->trim_blocks;
+    int rc = fill_u32(h->trim_owned, 64, 0u, stream);
+    if (rc) return rc;
+    hipLaunchKernelGGL(k_trim_count, dim3(nb), dim3(kTrimBlock), 0, stream, d, h->trim_counts, nb, h->trim_owned);
+    HB_TRY(hipGetLastError());
+    hipLaunchKernelGGL(k_trim_scan, dim3(1), dim3(64), 0, stream, h->trim_counts, h->trim_offsets, h->trim_totals, nb,
+                       nkeys);
+    HB_TRY(hipGetLastError());
+    rc = fill_u32(d.slots, (uint64_t)d.n_classes << d.log2q, kEmpty, stream);
+    if (!rc) rc = fill_u32(d.pool_ids, d.n_chunks, kEmpty, stream);
+    if (rc) return rc;
+    hipLaunchKernelGGL(k_trim_write, dim3(nb), dim3(kTrimBlock), 0, stream, d, h->trim_offsets, nb);
+    HB_TRY(hipGetLastError());
+    hipLaunchKernelGGL(k_trim_ctl, dim3(1), dim3(64), 0, stream, d, h->trim_totals, h->trim_owned);
+    HB_TRY(hipGetLastError());
+    return HBHEAP_OK;
+}
+
+int heap_snapshot(heap_t h, void* dst, size_t cap, size_t* len, hipStream_t stream)
+{
+    if (!h) return HBHEAP_E_INVAL;
+    if (len) *len = h->lay.total;
+    if (!dst) return len ? HBHEAP_OK : HBHEAP_E_INVAL;
+    if (cap < h->lay.total) return HBHEAP_E_RANGE;
+    HB_TRY(hipStreamSynchronize(stream));
+    HB_TRY(hipMemcpy(dst, h->state, h->lay.total, hipMemcpyDeviceToHost));
+    return HBHEAP_OK;
+}
+
+int heap_get_error(heap_t h, uint32_t* err)
+{
+    if (!h || !err) return HBHEAP_E_INVAL;
+    HB_TRY(hipDeviceSynchronize());
+    HB_TRY(hipMemcpy(err, h->dev.err, 4, hipMemcpyDeviceToHost));
+    return HBHEAP_OK;
+}
+
+int heap_clear_error(heap_t h)
+{
+    if (!h) return HBHEAP_E_INVAL;
+    HB_TRY(hipDeviceSynchronize());
+    const uint32_t z = 0;
+    HB_TRY(hipMemcpy(h->dev.err, &z, 4, hipMemcpyHostToDevice));
+    return HBHEAP_OK;
+}
+
+int heap_stats(heap_t h, uint64_t* out, size_t count)
+{
+    if (!h || !out) return HBHEAP_E_INVAL;
+    if (count > HBHEAP_STAT_COUNT) count = HBHEAP_STAT_COUNT;
+    HB_TRY(hipDeviceSynchronize());
+    HB_TRY(hipMemcpy(out, h->dev.stats, count * 8, hipMemcpyDeviceToHost));
+    return HBHEAP_OK;
+}
+
+int heap_replay(heap_t h, const int64_t* ops, int64_t* out, size_t n, hipStream_t stream)
+{
+    if (!h || (n && (!ops || !out))) return HBHEAP_E_INVAL;
+    if (!n) return HBHEAP_OK;
+    hipLaunchKernelGGL(k_replay, dim3(1), dim3(64), 0, stream, h->dev, ops, out, (uint64_t)n);
+    return hipGetLastError() == hipSuccess ? HBHEAP_OK : HBHEAP_E_HIP;
+}
+
+int heap_pattern_write(heap_t h, void* const* ptrs, const size_t* sizes, size_t n, uint32_t seed, hipStream_t stream)
+{
+    if (!h || (n && (!ptrs || !sizes))) return HBHEAP_E_INVAL;
+    if (!n) return HBHEAP_OK;
+    hipLaunchKernelGGL(k_pattern, dim3(grid_for(n, kBatchBlock)), dim3(kBatchBlock), 0, stream, ptrs,
+                       (const uint64_t*)sizes, (uint64_t)n, seed, (unsigned long long*)nullptr, 0,
+                       (const uint8_t*)h->data, h->dev.data_bytes);
+    return hipGetLastError() == hipSuccess ? HBHEAP_OK : HBHEAP_E_HIP;
+}
+
+int heap_pattern_check(heap_t h, void* const* ptrs, const size_t* sizes, size_t n, uint32_t seed,
+                       unsigned long long* mismatches, hipStream_t stream)
+{
+    if (!h || (n && (!ptrs || !sizes || !mismatches))) return HBHEAP_E_INVAL;
+    if (!n) return HBHEAP_OK;
+    hipLaunchKernelGGL(k_pattern, dim3(grid_for(n, kBatchBlock)), dim3(kBatchBlock), 0, stream, ptrs,
+                       (const uint64_t*)sizes, (uint64_t)n, seed, mismatches, 1, (const uint8_t*)h->data,
+                       h->dev.data_bytes);
+    return hipGetLastError() == hipSuccess ? HBHEAP_OK : HBHEAP_E_HIP;
+}
+
+int hb_atomic_probe(int pattern, void* buf, size_t buf_bytes, size_t threads, uint32_t lines, uint32_t iters,
+                    hipStream_t stream)
+{
+    if (!buf || buf_bytes < 4096 || pattern < 0 || pattern > 4 || !threads || !iters) return HBHEAP_E_INVAL;
+    if (pattern == 1 && (!lines || (uint64_t)lines * 128 > buf_bytes)) return HBHEAP_E_INVAL;
+    hipLaunchKernelGGL(k_atomic_probe, dim3(grid_for(threads, kBatchBlock)), dim3(kBatchBlock), 0, stream, pattern,
+                       (uint64_t*)buf, (uint64_t)(buf_bytes / 8), lines, iters, (uint64_t)threads);
+    return hipGetLastError() == hipSuccess ? HBHEAP_OK : HBHEAP_E_HIP;
+}
+
+int hb_stream_copy(void* dst, const void* src, size_t bytes, hipStream_t stream)
+{
+    if (!dst || !src || (bytes & 15)) return HBHEAP_E_INVAL;
+    const uint64_t n = bytes / 16;
+    if (!n) return HBHEAP_OK;
+    const uint32_t blocks = 256 * 8;
+    hipLaunchKernelGGL(k_copy, dim3(blocks), dim3(256), 0, stream, (uint4*)dst, (const uint4*)src, n);
+    return hipGetLastError() == hipSuccess ? HBHEAP_OK : HBHEAP_E_HIP;
+}
+
+}  // extern "C"

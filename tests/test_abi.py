@@ -1,0 +1,79 @@
+"""CPU checks of the C-ABI library: it loads, exports every function that
+include/*.h declares, and rejects bad arguments on the host before any GPU
+call.  No compute call is made here."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+from paper_2504_18211_amd import hbheap as hb
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_functions():
+    names = set()
+    for fn in os.listdir(os.path.join(ROOT, "include")):
+        if not fn.endswith(".h") or fn == "hbheap_device.h":
+            continue
+        text = open(os.path.join(ROOT, "include", fn)).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        for m in re.finditer(r"^\s*(?:const\s+)?[A-Za-z_][\w\s\*]*?\b([a-z_][a-z0-9_]*)\s*\([^;{]*\)\s*;", text, re.M):
+            if m.group(1) not in ("if", "while", "for", "return"):
+                names.add(m.group(1))
+    return names
+
+
+@pytest.fixture(scope="module")
+def L():
+    if not os.path.exists(hb.LIB_PATH):
+        from paper_2504_18211_amd import build
+        build.build()
+    return hb.lib()
+
+
+def test_exports_every_declared_symbol(L):
+    declared = _declared_functions()
+    assert {"heap_create", "heap_destroy", "heap_alloc_batch", "heap_free_batch"} <= declared
+    for name in sorted(declared):
+        assert hasattr(L, name), f"{name} declared in include/ but not exported"
+    assert set(hb.EXPORTS) <= declared
+
+
+def test_version(L):
+    assert "gfx950" in hb.hbheap_version()
+
+
+@pytest.mark.parametrize("nbytes,chunk", [(1 << 20, 3000), (1 << 20, 2048), (1 << 20, 1 << 17), (4096, 8192)])
+def test_create_rejects_bad_geometry(L, nbytes, chunk):
+    out = C.c_void_p(0)
+    assert L.heap_create(nbytes, chunk, C.byref(out)) == hb.E_INVAL
+    assert out.value is None
+
+
+def test_create_rejects_bad_config(L):
+    out = C.c_void_p(0)
+    for cfg in [hb.HeapConfig(2, 64, 0, 0, 0), hb.HeapConfig(0, 48, 0, 0, 0), hb.HeapConfig(0, 128, 0, 0, 0)]:
+        assert L.heap_create_ex(1 << 20, 8192, C.byref(cfg), C.byref(out)) == hb.E_INVAL
+    # page variant data region above 64 GiB
+    assert L.heap_create_ex(65 << 30, 8192, C.byref(hb.HeapConfig(1, 64, 0, 0, 0)), C.byref(out)) == hb.E_INVAL
+    assert L.heap_create(1 << 20, 8192, None) == hb.E_INVAL
+
+
+def test_null_handle_and_buffers_rejected(L):
+    assert L.heap_alloc_batch(None, None, None, 5, None) == hb.E_INVAL
+    assert L.heap_free_batch(None, None, None, 5, None) == hb.E_INVAL
+    assert L.heap_trim(None, None) == hb.E_INVAL
+    assert L.heap_destroy(None) == hb.OK
+    assert L.heap_replay(None, None, None, 1, None) == hb.E_INVAL
+    assert L.heap_pattern_write(None, None, None, 3, 0, None) == hb.E_INVAL
+    assert L.hb_atomic_probe(9, None, 0, 1, 1, 1, None) == hb.E_INVAL
+    assert L.hb_stream_copy(None, None, 16, None) == hb.E_INVAL
+    d = hb.DevHandle()
+    assert L.heap_device_handle(None, C.byref(d)) == hb.E_INVAL
+
+
+def test_dev_handle_layout_matches_header():
+    # 11 pointers, one u64, ten u32
+    assert C.sizeof(hb.DevHandle) == 11 * 8 + 8 + 10 * 4

@@ -1,0 +1,284 @@
+"""GPU parity: the HIP allocator (through the C ABI) against the CPU oracle.
+
+Results of a concurrent allocator are not unique, so each GPU result is
+checked against what the oracle fixes exactly: every block in bounds,
+aligned to its class and inside one chunk; no two blocks overlap; every
+block reads back its seeded pattern; per-class live counts equal the
+oracle's for the same request stream; NULL only at the oracle's exact
+capacity; the heap state is consistent at quiescence and byte-identical to a
+fresh heap after everything is freed and trimmed.  A single device lane is
+deterministic, and there the GPU must return the oracle's FIFO-policy
+offsets one for one.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2504_18211_amd import inputs
+from tests.hbtest import (check_blocks, check_snapshot, dev_i64, dev_u64, live_of, offsets, say,
+                          zeros_i64)
+
+pytestmark = pytest.mark.gpu
+
+KiB, MiB, GiB = 1 << 10, 1 << 20, 1 << 30
+VARIANTS = [0, 1]
+
+
+@pytest.fixture(scope="module")
+def hb():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2504_18211_amd import hbheap
+    hbheap.lib()
+    O.build(force=False)
+    return hbheap
+
+
+def _oracle_cap(nbytes, C, variant, k):
+    N = nbytes // C
+    chunks = N if variant == 0 else min(N, O.page_max_chunks(nbytes, C, k))
+    return chunks * O.pages_per_chunk(C, k)
+
+
+# ---------------------------------------------------------------------------
+# tiny workload: 8 MiB heap, 8 KiB chunks, 1024 threads x 64 B, one round trip
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("variant", VARIANTS)
+def test_tiny_round_trip(hb, variant):
+    w = inputs.TINY
+    say(f"case tiny variant={variant}")
+    sizes = inputs.sizes_fixed(w.threads, 64)
+    with hb.Heap(w.heap_bytes, w.chunk_bytes, variant=variant) as heap:
+        fresh = heap.snapshot()
+        assert not O.check_snapshot(fresh).violations()
+        sd, ptrs = dev_u64(sizes), zeros_i64(w.threads)
+        heap.alloc(sd, ptrs)
+        heap.pattern_write(ptrs, sd, w.seed)
+        assert heap.pattern_check(ptrs, sd, w.seed) == 0
+        offs = offsets(ptrs, heap.base)
+        check_blocks(heap, sizes, offs)
+        snap, rep = check_snapshot(heap)
+        ref = O.OracleHeap(w.heap_bytes, w.chunk_bytes, variant)
+        ref.alloc_batch(sizes)
+        assert live_of(rep) == ref.accounting()["live"]
+        assert O.check_blocks_in_snapshot(snap, sizes, offs) == 0
+        # 1024 x 64 B = 8 chunks of 128 pages at least; bounded by one partial chunk per wave
+        assert 8 <= sum(rep.chunks) <= 8 + 16
+        st = zeros_i64(w.threads).to(dtype=__import__("torch").int32)
+        heap.free(ptrs, status=st)
+        assert (st.cpu().numpy() == 0).all()
+        _, rep2 = check_snapshot(heap)
+        assert sum(live_of(rep2)) == 0
+        heap.trim()
+        assert heap.snapshot() == fresh
+        assert heap.error() == 0
+
+
+# ---------------------------------------------------------------------------
+# single device lane: address-for-address parity with the FIFO oracle
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("variant", VARIANTS)
+@pytest.mark.parametrize("seed", [1, 2])
+def test_single_lane_replay_matches_fifo_oracle(hb, variant, seed):
+    say(f"case replay variant={variant} seed={seed}")
+    nbytes, C = 32 * 8 * KiB, 8 * KiB
+    ops = inputs.op_script(3000, seed, lo=1, hi=8 * KiB, p_free=0.4, p_invalid_size=0.05)
+    ref = O.OracleHeap(nbytes, C, variant, O.POLICY_FIFO).replay(ops)
+    with hb.Heap(nbytes, C, variant=variant) as heap:
+        od, out = dev_i64(ops), zeros_i64(len(ops))
+        heap.replay(od, out)
+        got = out.cpu().numpy()
+        bad = np.nonzero(got != ref)[0]
+        assert bad.size == 0, f"first mismatch at op {bad[:5]}: gpu {got[bad[:5]]} oracle {ref[bad[:5]]}"
+        _, rep = check_snapshot(heap)
+        acc_oracle = O.OracleHeap(nbytes, C, variant, O.POLICY_FIFO)
+        acc_oracle.replay(ops)
+        a = acc_oracle.accounting()
+        assert live_of(rep) == a["live"]
+        assert [int(x) for x in list(rep.chunks)[: rep.n_classes]] == a["chunks"]
+        assert heap.error() == 0
+
+
+# ---------------------------------------------------------------------------
+# fixed-size sweep, reduced: 64 MiB heap (8192 chunks), 2^16 threads,
+# 16 B .. 8 KiB; from 2 KiB up the heap runs out and exactly the oracle's
+# capacity succeeds
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("variant", VARIANTS)
+def test_sweep_small_exact_capacity(hb, variant):
+    nbytes, C, n = 64 * MiB, 8 * KiB, 1 << 16
+    with hb.Heap(nbytes, C, variant=variant) as heap:
+        fresh = heap.snapshot()
+        ptrs = zeros_i64(n)
+        for size in inputs.SWEEP_SIZES:
+            k = O.class_of(size, C)
+            cap = _oracle_cap(nbytes, C, variant, k)
+            for it in range(2):
+                say(f"case sweep-small variant={variant} size={size} iter={it}")
+                sizes = inputs.sizes_fixed(n, size)
+                sd = dev_u64(sizes)
+                heap.alloc(sd, ptrs)
+                heap.pattern_write(ptrs, sd, inputs.SEED_SWEEP)
+                assert heap.pattern_check(ptrs, sd, inputs.SEED_SWEEP) == 0
+                offs = offsets(ptrs, heap.base)
+                rep = check_blocks(heap, sizes, offs, allow_null=True)
+                assert rep.n_nonnull == min(n, cap), (rep.n_nonnull, cap)
+                snap, srep = check_snapshot(heap)
+                assert live_of(srep)[k] == min(n, cap)
+                if n >= cap:
+                    assert srep.free_pages[k] == 0 and srep.free_chunks == 0 or variant == 1
+                assert O.check_blocks_in_snapshot(snap, sizes, offs) == 0
+                heap.free(ptrs)
+                _, srep = check_snapshot(heap)
+                assert sum(live_of(srep)) == 0
+            heap.trim()
+            assert heap.snapshot() == fresh, f"not fresh after trim (size {size})"
+        assert heap.error() == 0
+
+
+# ---------------------------------------------------------------------------
+# mixed-size churn, reduced: 2^16 threads, log-uniform 4 B .. 8 KiB, half
+# freed and reallocated per round
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("variant", VARIANTS)
+def test_churn_small(hb, variant):
+    import torch
+    nbytes, C, n, rounds = 256 * MiB, 8 * KiB, 1 << 16, 4
+    seed = inputs.SEED_CHURN
+    sizes = inputs.sizes_log_uniform(n, 4, 8 * KiB, seed)
+    ref = O.OracleHeap(nbytes, C, variant)
+    ref_offs = ref.alloc_batch(sizes)
+    with hb.Heap(nbytes, C, variant=variant) as heap:
+        fresh = heap.snapshot()
+        ptrs = zeros_i64(n)
+        heap.alloc(dev_u64(sizes), ptrs)
+        for r in range(rounds + 1):
+            say(f"case churn-small variant={variant} round={r}")
+            if r:
+                idx, new_sizes = inputs.churn_round(n, r, seed)
+                idx_d = torch.from_numpy(idx).to("cuda")
+                victims = ptrs[idx_d].contiguous()
+                heap.free(victims)
+                ref.free_batch(ref_offs[idx])
+                sizes[idx] = new_sizes
+                fresh_ptrs = zeros_i64(len(idx))
+                heap.alloc(dev_u64(new_sizes), fresh_ptrs)
+                ptrs[idx_d] = fresh_ptrs
+                ref_offs[idx] = ref.alloc_batch(new_sizes)
+            sd = dev_u64(sizes)
+            heap.pattern_write(ptrs, sd, seed)
+            assert heap.pattern_check(ptrs, sd, seed) == 0
+            offs = offsets(ptrs, heap.base)
+            check_blocks(heap, sizes, offs)
+            snap, srep = check_snapshot(heap)
+            assert live_of(srep) == ref.accounting()["live"]
+            assert O.check_blocks_in_snapshot(snap, sizes, offs) == 0
+        heap.free(ptrs)
+        heap.trim()
+        assert heap.snapshot() == fresh
+        assert heap.error() == 0
+
+
+# ---------------------------------------------------------------------------
+# free errors: double, invalid, NULL -- detected, ignored, state unharmed
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("variant", VARIANTS)
+def test_free_errors(hb, variant):
+    import torch
+    say(f"case free-errors variant={variant}")
+    nbytes, C = 1 * MiB, 8 * KiB
+    with hb.Heap(nbytes, C, variant=variant) as heap:
+        sizes = inputs.sizes_fixed(100, 64)
+        ptrs = zeros_i64(100)
+        heap.alloc(dev_u64(sizes), ptrs)
+        p = ptrs.cpu().numpy()
+        base = heap.base
+        bad = np.array([p[0], p[0], p[1] + 16, base + nbytes + 64, 0, base + 100 * C, p[2], base - 64],
+                       dtype=np.int64)
+        st = torch.zeros(len(bad), dtype=torch.int32, device="cuda")
+        heap.free(dev_i64(bad), status=st)
+        s = st.cpu().numpy().tolist()
+        assert sorted(s[:2]) == [0, 1]       # same page twice in one batch: one ok, one double
+        assert s[2] == 2 and s[3] == 2 and s[4] == 3 and s[5] == 2 and s[6] == 0 and s[7] == 2
+        err = heap.error()
+        assert err & hb.ERR_DOUBLE_FREE and err & hb.ERR_INVALID_FREE and not err & hb.ERR_TIMEOUT
+        _, srep = check_snapshot(heap)
+        assert live_of(srep)[2] == 98
+        st2 = torch.zeros(1, dtype=torch.int32, device="cuda")
+        heap.free(dev_i64(np.array([p[0]])), status=st2)
+        assert st2.item() == 1
+        # sizes of the wrong class make a free invalid
+        st3 = torch.zeros(1, dtype=torch.int32, device="cuda")
+        heap.free(dev_i64(np.array([p[3]])), sizes=dev_u64(np.array([1000])), status=st3)
+        assert st3.item() == 2
+        stats = heap.stats()
+        assert stats["double_free"] == 2 and stats["invalid_free"] == 5
+
+
+# ---------------------------------------------------------------------------
+# aggregation width: 1, 16, 64 lanes per queue operation
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("variant", VARIANTS)
+@pytest.mark.parametrize("width", [1, 16, 64])
+def test_width_mixed_batch(hb, variant, width):
+    say(f"case width variant={variant} width={width}")
+    nbytes, C, n = 64 * MiB, 16 * KiB, 20000  # ragged last wave
+    sizes = inputs.sizes_log_uniform(n, 1, 16 * KiB, 77)
+    sizes[::97] = 0
+    sizes[5::101] = 16 * KiB + 1
+    with hb.Heap(nbytes, C, variant=variant, width=width) as heap:
+        fresh = heap.snapshot()
+        sd, ptrs = dev_u64(sizes), zeros_i64(n)
+        heap.alloc(sd, ptrs)
+        offs = offsets(ptrs, heap.base)
+        rep = check_blocks(heap, sizes, offs)
+        assert rep.n_null == int((sizes == 0).sum() + (sizes > C).sum())
+        heap.pattern_write(ptrs, sd, 5)
+        assert heap.pattern_check(ptrs, sd, 5) == 0
+        _, srep = check_snapshot(heap)
+        ref = O.OracleHeap(nbytes, C, variant)
+        ref.alloc_batch(sizes)
+        assert live_of(srep) == ref.accounting()["live"]
+        heap.free(ptrs)
+        heap.trim()
+        assert heap.snapshot() == fresh
+
+
+# ---------------------------------------------------------------------------
+# headline workload at full size: 4 GiB heap, 2^20 threads, 16 B .. 8 KiB
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("variant", VARIANTS)
+def test_sweep_full_size(hb, variant):
+    w = inputs.SWEEP
+    n = w.threads
+    with hb.Heap(w.heap_bytes, w.chunk_bytes, variant=variant) as heap:
+        fresh = heap.snapshot()
+        ptrs = zeros_i64(n)
+        for size in inputs.SWEEP_SIZES:
+            say(f"case sweep-full variant={variant} size={size}")
+            k = O.class_of(size, w.chunk_bytes)
+            cap = _oracle_cap(w.heap_bytes, w.chunk_bytes, variant, k)
+            sizes = inputs.sizes_fixed(n, size)
+            sd = dev_u64(sizes)
+            for it in range(2):
+                heap.alloc(sd, ptrs)
+                heap.pattern_write(ptrs, sd, w.seed)
+                assert heap.pattern_check(ptrs, sd, w.seed) == 0
+                offs = offsets(ptrs, heap.base)
+                rep = check_blocks(heap, sizes, offs, allow_null=True)
+                assert rep.n_nonnull == min(n, cap), (size, rep.n_nonnull, cap)
+                if it == 0:
+                    snap, srep = check_snapshot(heap)
+                    assert live_of(srep)[k] == min(n, cap)
+                heap.free(ptrs)
+            heap.trim()
+            assert heap.snapshot() == fresh
+        assert heap.error() == 0

@@ -257,7 +257,7 @@ def test_check_blocks_catches_planted_faults():
 # snapshot checker on hand-built snapshots of the documented layout
 # ---------------------------------------------------------------------------
 
-def build_snapshot(N, log2C, variant, log2q, cls, cnt, bits, pool_bump, pool_ids, rings, owned=None, maxc=None):
+def build_snapshot(N, log2C, variant, log2q, cls, cnt, bits, pool_bump, pool_ids, rings, owned=None):
     """Write a version-1 snapshot from plain arrays.  rings[k] = (H, head, entries)."""
     K = log2C - 3
     W = (1 << log2C) // 1024
@@ -274,7 +274,7 @@ def build_snapshot(N, log2C, variant, log2q, cls, cnt, bits, pool_bump, pool_ids
     total = al(off_sl + 4 * K * Q)
     b = bytearray(total)
     struct.pack_into("<IIQIIIIIIQQQQQQQQQ", b, 0, 0x48424850, 1, N << log2C, N, log2C, K, variant, W, log2q,
-                     maxc if maxc is not None else N, off_pool, off_cl, off_cls, off_cnt, off_bits, off_pid, off_sl, total)
+                     0, off_pool, off_cl, off_cls, off_cnt, off_bits, off_pid, off_sl, total)
     struct.pack_into("<QI", b, off_pool, pool_bump, len(pool_ids))
     for i, c in enumerate(pool_ids):
         struct.pack_into("<I", b, off_pid + 4 * i, c)
@@ -348,16 +348,17 @@ def test_snapshot_checker_catches_planted_faults(plant, field):
 
 def test_snapshot_checker_page_variant():
     N, log2C, cls, cnt, bits, pool_ids = _tiny_state()
-    # page variant: entries are byte offsets / 16 of the free pages
+    # page variant: entries are byte offsets / 16 of the free pages; a ring of
+    # 2^8 entries lets class 0 (256 pages per 4 KiB chunk) own one chunk
     e6 = [(0 * 4096 + 1 * 1024) // 16, (0 * 4096 + 3 * 1024) // 16]
     e0 = [(2 * 4096 + 5 * 16) // 16]
-    snap = build_snapshot(N, log2C, 1, 2, cls, [0] * 4, bits, 2, pool_ids, {6: (0, 3, e6), 0: (0, 0, e0)},
+    snap = build_snapshot(N, log2C, 1, 8, cls, [0] * 4, bits, 2, pool_ids, {6: (0, 3, e6), 0: (0, 0, e0)},
                           owned={6: 1, 0: 1})
     assert not O.check_snapshot(snap).violations()
-    bad = build_snapshot(N, log2C, 1, 2, cls, [0] * 4, bits, 2, pool_ids, {6: (0, 3, e6[:1]), 0: (0, 0, e0)},
+    bad = build_snapshot(N, log2C, 1, 8, cls, [0] * 4, bits, 2, pool_ids, {6: (0, 3, e6[:1]), 0: (0, 0, e0)},
                          owned={6: 1, 0: 1})
     assert O.check_snapshot(bad).violations().get("bad_ring_missing", 0) == 1
-    bad = build_snapshot(N, log2C, 1, 2, cls, [0] * 4, bits, 2, pool_ids, {6: (0, 3, e6), 0: (0, 0, e0)},
+    bad = build_snapshot(N, log2C, 1, 8, cls, [0] * 4, bits, 2, pool_ids, {6: (0, 3, e6), 0: (0, 0, e0)},
                          owned={6: 2, 0: 1})
     assert O.check_snapshot(bad).violations().get("bad_owned", 0) == 1
 
