@@ -1,0 +1,351 @@
+#!/usr/bin/env python3
+"""Benchmark of the device heap allocator on one MI355X.
+
+Workload (the headline): a 4 GiB heap of 8 KiB chunks; 2^20 threads, one
+fixed request size per launch, swept over powers of two 16 B .. 8 KiB.  One
+step = for every size: ten iterations of an allocation launch, a payload
+write, a read-back check and a free launch (the paper's driver loop,
+Methods), then a quiescent trim before the next size.  As in the paper, the
+allocator's figure is the time of the allocations and frees averaged over
+the iterations after the first ("subsequent iterations", Methods): value =
+successful (alloc + free) ops / alloc+free launch time over iterations
+2..10 (HIP events on the launch stream); iterations 1..10 are reported too.
+The whole step's wall time (payload write/check and trims included) is
+ms_per_step, and all ops over it is wall_ops_per_s.
+
+Also measured in the same process:
+  * the device atomic ceilings (same-address, 1024 lines, per-lane random);
+  * a counting pass with the heap's statistics flag, giving the exact
+    atomics issued per launch by target (class state word, head/tail, pool,
+    per-lane); the roofline compares the busiest word's atomics per launch
+    over the launch time against the measured same-address ceiling;
+  * the plain baseline: the runtime's own per-thread device malloc/free;
+  * the CPU baseline: the sequential oracle on a bounded sample, one core.
+
+Prints one JSON line.  Only --gpus 1 is supported.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--iters", type=int, default=10, help="alloc-write-check-free iterations per size")
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--variant", choices=["chunk", "page"], default="chunk")
+    ap.add_argument("--width", type=int, default=64)
+    ap.add_argument("--no-plain", action="store_true", help="skip the plain device-malloc baseline")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--sizes", type=str, default="", help="comma list overriding the 16..8192 sweep")
+    return ap.parse_args()
+
+
+def pct(a, q):
+    import numpy as np
+    return float(np.percentile(np.asarray(a, dtype=float), q)) if len(a) else None
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}): the heap lives in one GPU's HBM and "
+              "every allocation is served on that GPU; there is no multi-GPU path to measure.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2504_18211_amd import hbheap as hb
+    from paper_2504_18211_amd import inputs
+
+    hb.lib()  # fails loudly without the built library
+    if not torch.cuda.is_available():
+        log("no GPU visible")
+        sys.exit(3)
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    w = inputs.SWEEP
+    n = w.threads
+    sizes_list = [int(x) for x in args.sizes.split(",")] if args.sizes else list(inputs.SWEEP_SIZES)
+    variant = hb.VARIANT_CHUNK if args.variant == "chunk" else hb.VARIANT_PAGE
+
+    def ev():
+        return torch.cuda.Event(enable_timing=True)
+
+    # ---------------- atomic ceilings and HBM copy ----------------
+    def probe(pattern, lines, threads, iters):
+        buf = torch.zeros(64 << 20, dtype=torch.uint8, device=dev)
+        best = None
+        for _ in range(3):
+            e0, e1 = ev(), ev()
+            e0.record()
+            hb.hb_atomic_probe(pattern, buf, buf.numel(), threads, lines, iters)
+            e1.record()
+            torch.cuda.synchronize()
+            t = e0.elapsed_time(e1) / 1e3
+            best = t if best is None else min(best, t)
+        n_at = threads * iters if pattern in (2, 4) else threads // 64 * iters
+        return n_at / best
+
+    ceil_same = probe(0, 1, 1 << 20, 4)
+    ceil_lines = probe(1, 1024, 1 << 20, 4)
+    ceil_spread = probe(2, 1, 1 << 20, 4)
+    log(f"atomic ceilings: same-address {ceil_same/1e9:.3f} G/s, 1024 lines {ceil_lines/1e9:.2f} G/s, "
+        f"per-lane random {ceil_spread/1e9:.2f} G/s")
+
+    # ---------------- allocator sweep ----------------
+    heap = hb.Heap(w.heap_bytes, w.chunk_bytes, variant=variant, width=args.width)
+    ptrs = torch.zeros(n, dtype=torch.int64, device=dev)
+    mism = torch.zeros(1, dtype=torch.int64, device=dev)
+    size_dev = {s: torch.from_numpy(inputs.sizes_fixed(n, s).view(np.int64)).to(dev) for s in sizes_list}
+
+    iters = args.iters
+
+    def one_size(s, rec):
+        sd = size_dev[s]
+        for it in range(iters):
+            e = [ev() for _ in range(4)]
+            e[0].record()
+            heap.alloc(sd, ptrs)
+            e[1].record()
+            hb.heap_pattern_write(heap.h, ptrs, sd, w.seed)
+            hb.heap_pattern_check(heap.h, ptrs, sd, w.seed, mism)
+            ok = (ptrs != 0).sum()
+            e[2].record()
+            heap.free(ptrs)
+            e[3].record()
+            rec.append((s, it, e, ok))
+        heap.trim()
+
+    def run_step(rec):
+        for s in sizes_list:
+            one_size(s, rec)
+
+    # counting pass: exact atomics per launch by target, for the first
+    # iteration after a trim and for a subsequent one
+    keys = ("state_ops", "headtail_ops", "pool_ops", "spread_ops")
+    counts = {}
+    heap.set_flags(hb.FLAG_STATS)
+    for s in sizes_list:
+        sd = size_dev[s]
+        counts[s] = {}
+        for phase in ("first", "subsequent"):
+            before = heap.stats()
+            heap.alloc(sd, ptrs)
+            torch.cuda.synchronize()
+            mid = heap.stats()
+            heap.free(ptrs)
+            torch.cuda.synchronize()
+            after = heap.stats()
+            counts[s][phase] = {"alloc": {k: mid[k] - before[k] for k in keys},
+                                "free": {k: after[k] - mid[k] for k in keys}}
+        heap.trim()
+    heap.set_flags(0)
+    assert heap.error() == 0, "heap error during counting pass"
+
+    warm = []
+    for _ in range(args.warmup):
+        run_step(warm)
+    torch.cuda.synchronize()
+
+    recs = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        run_step(recs)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+
+    if int(mism.item()) != 0:
+        log(f"PAYLOAD MISMATCHES: {int(mism.item())}")
+        sys.exit(4)
+    err = heap.error()
+    if err:
+        log(f"HEAP ERROR WORD {err:#x}")
+        sys.exit(5)
+
+    per_size = {s: {"alloc_us": [], "free_us": [], "ok": 0} for s in sizes_list}
+    sub_ops = sub_t = all_ops = all_t = 0.0
+    t_alloc_sub, t_free_sub = [], []
+    for s, it, e, ok in recs:
+        ta = e[0].elapsed_time(e[1]) / 1e3
+        tf = e[2].elapsed_time(e[3]) / 1e3
+        okv = int(ok.item())
+        all_ops += 2 * okv
+        all_t += ta + tf
+        if it > 0:
+            sub_ops += 2 * okv
+            sub_t += ta + tf
+            t_alloc_sub.append(ta)
+            t_free_sub.append(tf)
+            per_size[s]["alloc_us"].append(ta * 1e6)
+            per_size[s]["free_us"].append(tf * 1e6)
+        per_size[s]["ok"] = okv
+    value = sub_ops / sub_t
+    ms_per_step = wall / args.steps * 1e3
+
+    # roofline of the dominant kernel, k_alloc_batch: counted atomics on the
+    # class state word per launch over the average launch time of every
+    # non-counting allocation launch of this process (warmup + timed), the
+    # same population a kernel trace of this command averages over
+    alloc_launch_t, state_atomics = [], 0
+    for s, it, e, ok in warm + recs:
+        alloc_launch_t.append(e[0].elapsed_time(e[1]) / 1e3)
+        state_atomics += counts[s]["first" if it == 0 else "subsequent"]["alloc"]["state_ops"]
+    achieved = state_atomics / sum(alloc_launch_t)
+    roofline = {
+        "bound": "atomic",
+        "kernel": "k_alloc_batch<false>",
+        "achieved": achieved / 1e9,
+        "peak": ceil_same / 1e9,
+        "unit": "Gatomic/s (returning 64-bit device-scope atomics on one address)",
+        "frac": achieved / ceil_same,
+        "traffic": None,
+        "avg_launch_us": float(np.mean(alloc_launch_t)) * 1e6,
+        "launches": len(alloc_launch_t),
+        "state_word_atomics_per_launch": state_atomics / len(alloc_launch_t),
+        "alloc_share_of_alloc_free_time": sum(t_alloc_sub) / (sum(t_alloc_sub) + sum(t_free_sub)),
+    }
+
+    sizes_summary = {
+        str(s): {
+            "ok": v["ok"],
+            "alloc_us": round(float(np.mean(v["alloc_us"])), 1),
+            "free_us": round(float(np.mean(v["free_us"])), 1),
+            "ops_per_s": round(2 * v["ok"] / ((np.mean(v["alloc_us"]) + np.mean(v["free_us"])) * 1e-6), 0),
+            "atomics_per_op_subsequent": {
+                ph: {k: round(c / max(1, v["ok"]), 4) for k, c in counts[s]["subsequent"][ph].items()}
+                for ph in ("alloc", "free")
+            },
+        }
+        for s, v in per_size.items()
+    }
+    heap.close()
+
+    # ---------------- plain baseline: runtime device malloc/free ----------------
+    plain = None
+    if not args.no_plain:
+        plain = {"sizes": {}}
+        rc = hb.hb_plain_set_heap(6 << 30)
+        plain["heap_limit_rc"] = rc
+        p_ptrs = torch.zeros(n, dtype=torch.int64, device=dev)
+        tot_ops, tot_t = 0, 0.0
+        for s in sizes_list:
+            nn = n if s <= 1024 else (1 << 16)
+            sd = size_dev[s][:nn]
+            pp = p_ptrs[:nn]
+            e = [ev() for _ in range(4)]
+            e[0].record()
+            hb.hb_plain_alloc(sd, pp)
+            e[1].record()
+            ok = int((pp != 0).sum().item())
+            e[2].record()
+            hb.hb_plain_free(pp)
+            e[3].record()
+            torch.cuda.synchronize()
+            t = (e[0].elapsed_time(e[1]) + e[2].elapsed_time(e[3])) / 1e3
+            plain["sizes"][str(s)] = {"threads": nn, "ok": ok, "ops_per_s": round(2 * ok / t, 0),
+                                      "alloc_us": round(e[0].elapsed_time(e[1]) * 1e3, 1),
+                                      "free_us": round(e[2].elapsed_time(e[3]) * 1e3, 1)}
+            if nn == n:
+                tot_ops += 2 * ok
+                tot_t += t
+            log(f"plain size={s} threads={nn} ok={ok} {2*ok/t/1e6:.2f} M ops/s")
+        plain["value_full_size_sizes"] = tot_ops / tot_t if tot_t else None
+        # ours over the same sizes (those the plain kernel ran at 2^20 threads)
+        o_ops = sum(2 * per_size[s]["ok"] for s in sizes_list if s <= 1024)
+        o_t = sum((np.mean(per_size[s]["alloc_us"]) + np.mean(per_size[s]["free_us"])) * 1e-6
+                  for s in sizes_list if s <= 1024)
+        plain["ours_same_sizes"] = o_ops / o_t if o_t else None
+
+    # ---------------- CPU baseline: the oracle on a bounded sample ----------------
+    cpu = None
+    if not args.no_cpu:
+        import oracle as O
+        O.build(force=False)
+        t_cpu, cpu_ops, passes = 0.0, 0, 0
+        sample_sizes = sizes_list
+        while t_cpu < args.cpu_seconds and passes < 50:
+            h = O.OracleHeap(w.heap_bytes, w.chunk_bytes, variant)
+            for s in sample_sizes:
+                sz = inputs.sizes_fixed(n, s)
+                c0 = time.perf_counter()
+                offs = h.alloc_batch(sz)
+                h.free_batch(offs)
+                h.trim()
+                t_cpu += time.perf_counter() - c0
+                cpu_ops += 2 * int((offs >= 0).sum())
+            h.close()
+            passes += 1
+        cpu = {"value": cpu_ops / t_cpu, "unit": "ops/s", "cores": 1, "kind": "oracle",
+               "sample": f"{passes} pass(es) of the sweep ({len(sample_sizes)} sizes x 2^20 alloc+free, trim "
+                         f"between sizes) through the sequential oracle, {t_cpu:.1f} s",
+               "cpu_model": _cpu_model(), "host_cores_available": os.cpu_count()}
+
+    out = {
+        "metric": "device malloc+free ops/sec (2^20 threads, 16B-8KiB) vs plain; p99 batch latency",
+        "value": value,
+        "unit": "ops/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u64",
+        "data": "synthetic",
+        "config": {
+            "workload": "fixed-size sweep: 4 GiB heap, 8 KiB chunks, 2^20 threads per launch, one size per launch "
+                        "16 B..8 KiB, 10 x (alloc -> write -> check -> free) per size, trim between sizes; value over "
+                        "iterations 2..10",
+            "variant": args.variant,
+            "aggregation_width": args.width,
+            "iterations_per_size": iters,
+            "sizes": sizes_list,
+        },
+        "value_all_iterations": all_ops / all_t,
+        "wall_ops_per_s": all_ops / wall,
+        "batch_latency_us": {
+            "alloc_p50": pct(t_alloc_sub, 50) * 1e6, "alloc_p99": pct(t_alloc_sub, 99) * 1e6,
+            "free_p50": pct(t_free_sub, 50) * 1e6, "free_p99": pct(t_free_sub, 99) * 1e6,
+        },
+        "roofline": roofline,
+        "atomic_ceilings_gps": {"same_address": ceil_same / 1e9, "lines_1024": ceil_lines / 1e9,
+                                "per_lane_random": ceil_spread / 1e9},
+        "per_size": sizes_summary,
+        "plain": plain,
+        "vs_plain": (plain["ours_same_sizes"] / plain["value_full_size_sizes"])
+        if plain and plain["value_full_size_sizes"] and plain["ours_same_sizes"] else None,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+if __name__ == "__main__":
+    main()

@@ -96,6 +96,10 @@ int heap_free_batch(heap_t h, const size_t* sizes, void* const* ptrs, size_t n, 
 int heap_free_batch_ex(heap_t h, const size_t* sizes, void* const* ptrs, size_t n, int32_t* status,
                        hipStream_t stream);
 
+/* Replace the HBHEAP_FLAG_* bits used by launches issued after this call
+ * (and by handles obtained after it). */
+int heap_set_flags(heap_t h, uint32_t flags);
+
 /* Device handle for user kernels calling dev_malloc/dev_free
  * (hbheap_device.h).  Valid until heap_destroy. */
 int heap_device_handle(heap_t h, hbheap_dev_t* out);

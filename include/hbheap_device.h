@@ -61,7 +61,7 @@ constexpr uint64_t kHold = 1ull << 32;
 constexpr uint32_t kBias = 0x80000000u;
 constexpr uint64_t kNoPage = ~0ull;
 constexpr uint32_t kFreeClass = 0xFFu;
-constexpr uint32_t kClassBlock = 384;    /* state line, head line, tail line */
+constexpr uint32_t kClassBlock = 512;    /* state, head, tail, owned: one 128 B line each */
 constexpr uint32_t kMaxWavesPerBlock = 16;
 
 enum : uint32_t { kFreeOk = 0, kFreeDouble = 1, kFreeInvalid = 2, kFreeNull = 3 };
@@ -144,6 +144,29 @@ struct Backoff {
     }
 };
 
+/* Atomics issued, by target, when HBHEAP_FLAG_STATS is set: class state
+ * words, class head/tail words, the pool counter, and per-lane atomics on
+ * slots, bitmasks and chunk counts. */
+struct Tally {
+    uint32_t state = 0, headtail = 0, pool = 0, spread = 0;
+};
+
+__device__ __forceinline__ void tally_flush(const hbheap_dev_t& h, const Tally& t)
+{
+    if (!(h.flags & HBHEAP_FLAG_STATS)) return;
+    uint32_t s, ht, pl, sp;
+    (void)excl_scan<20>(t.state, &s);
+    (void)excl_scan<20>(t.headtail, &ht);
+    (void)excl_scan<20>(t.pool, &pl);
+    (void)excl_scan<20>(t.spread, &sp);
+    if (lane() == ctz64(exec_mask())) {
+        if (s) a_add64(h.stats + HBHEAP_STAT_STATE_OPS, s);
+        if (ht) a_add64(h.stats + HBHEAP_STAT_HEADTAIL_OPS, ht);
+        if (pl) a_add64(h.stats + HBHEAP_STAT_POOL_OPS, pl);
+        if (sp) a_add64(h.stats + HBHEAP_STAT_SPREAD_OPS, sp);
+    }
+}
+
 /* ---------------- geometry ---------------- */
 
 __device__ __forceinline__ int class_of(const hbheap_dev_t& h, uint64_t n)
@@ -176,35 +199,41 @@ __device__ __forceinline__ Ring ring_of(const hbheap_dev_t& h, uint32_t k)
 }
 __device__ __forceinline__ uint64_t* owned_of(const hbheap_dev_t& h, uint32_t k)
 {
-    return (uint64_t*)(h.classes + (uint64_t)k * kClassBlock + 8);
+    return (uint64_t*)(h.classes + (uint64_t)k * kClassBlock + 384);
 }
 __device__ __forceinline__ int32_t state_count(uint64_t s) { return (int32_t)((uint32_t)s - kBias); }
 
 /* Leader only.  Takes a hold (H += 1) and reserves up to n published
  * entries; returns how many were reserved.  The hold is dropped by
  * ring_release(), which also publishes entries written meanwhile. */
-__device__ __forceinline__ uint32_t ring_reserve(const Ring& r, uint32_t n)
+__device__ __forceinline__ uint32_t ring_reserve(const Ring& r, uint32_t n, Tally& t)
 {
     const uint64_t old = a_add64(r.state, kHold - n);
     const int32_t c = state_count(old);
     const uint32_t got = c <= 0 ? 0u : ((uint32_t)c < n ? (uint32_t)c : n);
-    if (got < n) a_add64(r.state, (uint64_t)(n - got));
+    t.state += 1;
+    if (got < n) {
+        a_add64(r.state, (uint64_t)(n - got));
+        t.state += 1;
+    }
     return got;
 }
-__device__ __forceinline__ void ring_release(const Ring& r, uint32_t publish)
+__device__ __forceinline__ void ring_release(const Ring& r, uint32_t publish, Tally& t)
 {
     a_add64(r.state, (uint64_t)publish - kHold);
+    t.state += 1;
 }
 
 /* Per lane: take the entry of ring position pos (wait while its producer is
  * late).  kEmpty on timeout. */
-__device__ __forceinline__ uint32_t slot_take(const hbheap_dev_t& h, const Ring& r, uint32_t pos)
+__device__ __forceinline__ uint32_t slot_take(const hbheap_dev_t& h, const Ring& r, uint32_t pos, Tally& t)
 {
     uint32_t* s = r.slots + (pos & r.mask);
     Backoff b;
     for (;;) {
         if (a_load32(s) != kEmpty) {
             const uint32_t v = a_xchg32(s, kEmpty);
+            t.spread += 1;
             if (v != kEmpty) return v;
         }
         if (!b.wait(h)) {
@@ -216,12 +245,15 @@ __device__ __forceinline__ uint32_t slot_take(const hbheap_dev_t& h, const Ring&
 
 /* Per lane: fill ring position pos with v (wait while the slot still holds
  * the entry of the previous lap). */
-__device__ __forceinline__ bool slot_put(const hbheap_dev_t& h, const Ring& r, uint32_t pos, uint32_t v)
+__device__ __forceinline__ bool slot_put(const hbheap_dev_t& h, const Ring& r, uint32_t pos, uint32_t v, Tally& t)
 {
     uint32_t* s = r.slots + (pos & r.mask);
     Backoff b;
     for (;;) {
-        if (a_load32(s) == kEmpty && a_cas32(s, kEmpty, v)) return true;
+        if (a_load32(s) == kEmpty) {
+            t.spread += 1;
+            if (a_cas32(s, kEmpty, v)) return true;
+        }
         if (!b.wait(h)) {
             raise_err(h, HBHEAP_ERR_TIMEOUT, HBHEAP_STAT_TIMEOUTS);
             return false;
@@ -233,10 +265,11 @@ __device__ __forceinline__ bool slot_put(const hbheap_dev_t& h, const Ring& r, u
 
 /* Leader only: take up to m unowned chunks; returns the first pool index in
  * *first and the number granted. */
-__device__ __forceinline__ uint32_t pool_take(const hbheap_dev_t& h, uint32_t m, uint64_t* first)
+__device__ __forceinline__ uint32_t pool_take(const hbheap_dev_t& h, uint32_t m, uint64_t* first, Tally& t)
 {
     const uint64_t size = (uint32_t)h.pool[1];
     const uint64_t b = a_add64(h.pool, m);
+    t.pool += 1;
     *first = b;
     if (b >= size) return 0;
     return (uint32_t)((size - b) < m ? (size - b) : m);
@@ -286,7 +319,8 @@ __device__ __forceinline__ uint64_t lowest_bits(uint64_t x, uint32_t n)
  * lowest first, writing the pages' byte offsets to out[0..t).  The caller
  * already took t from the chunk's count, so t set bits exist; bits lost to a
  * concurrent claimer are looked for again. */
-__device__ __forceinline__ uint32_t claim_pages(const hbheap_dev_t& h, uint32_t c, uint32_t k, uint32_t t, uint64_t* out)
+__device__ __forceinline__ uint32_t claim_pages(const hbheap_dev_t& h, uint32_t c, uint32_t k, uint32_t t, uint64_t* out,
+                                                Tally& tl)
 {
     const uint32_t shift = 4u + k;
     const uint32_t ppc = 1u << (h.log2_chunk - shift);
@@ -301,6 +335,7 @@ __device__ __forceinline__ uint32_t claim_pages(const hbheap_dev_t& h, uint32_t 
             while (x && got < t) {
                 const uint64_t pick = lowest_bits(x, t - got);
                 const uint64_t old = a_and64(&words[w], ~pick);
+                tl.spread += 1;
                 uint64_t won = old & pick;
                 while (won) {
                     const uint32_t bit = ctz64(won);
@@ -356,7 +391,8 @@ __device__ __forceinline__ bool oom_should_retry(const hbheap_dev_t& h, const Ri
 
 /* ---------------- chunk variant: serve one class group ---------------- */
 
-__device__ __forceinline__ uint64_t alloc_group_chunk(const hbheap_dev_t& h, uint32_t k, uint64_t grp, uint64_t* stage)
+__device__ __forceinline__ uint64_t alloc_group_chunk(const hbheap_dev_t& h, uint32_t k, uint64_t grp, uint64_t* stage,
+                                                      Tally& tl)
 {
     const uint64_t act = exec_mask();
     const uint32_t me = lane();
@@ -380,8 +416,11 @@ __device__ __forceinline__ uint64_t alloc_group_chunk(const hbheap_dev_t& h, uin
         const uint32_t want = want0 < nact ? want0 : nact;
         uint32_t got = 0, h0 = 0;
         if (me == leader) {
-            got = ring_reserve(R, want);
-            if (got) h0 = a_add32(R.head, got);
+            got = ring_reserve(R, want, tl);
+            if (got) {
+                h0 = a_add32(R.head, got);
+                tl.headtail += 1;
+            }
         }
         got = bcast(got, leader);
         h0 = bcast(h0, leader);
@@ -391,7 +430,7 @@ __device__ __forceinline__ uint64_t alloc_group_chunk(const hbheap_dev_t& h, uin
         uint32_t c = kEmpty;
         int32_t v = 0;
         if (helper) {
-            c = slot_take(h, R, h0 + arank);
+            c = slot_take(h, R, h0 + arank, tl);
             if (c != kEmpty && c >= h.n_chunks) {
                 raise_err(h, HBHEAP_ERR_CORRUPT, HBHEAP_STAT_TIMEOUTS);
                 c = kEmpty;
@@ -408,20 +447,26 @@ __device__ __forceinline__ uint64_t alloc_group_chunk(const hbheap_dev_t& h, uin
 
         bool keep = false;
         if (vc > 0) {
-            if (t) keep = a_addi(h.chunk_cnt + c, -(int32_t)t) - (int32_t)t > 0;
+            if (t) {
+                keep = a_addi(h.chunk_cnt + c, -(int32_t)t) - (int32_t)t > 0;
+                tl.spread += 1;
+            }
             else keep = true;
         }
         uint32_t took;
         const uint32_t tpre = excl_scan<7>(t, &took);
-        if (t) claim_pages(h, c, k, t, stage + served + tpre);
+        if (t) claim_pages(h, c, k, t, stage + served + tpre, tl);
 
         /* chunks that still hold free pages go back to the tail */
         const uint64_t rq = __ballot(keep);
         const uint32_t nrq = (uint32_t)__popcll(rq);
         uint32_t t0 = 0;
-        if (nrq && me == leader) t0 = a_add32(R.tail, nrq);
+        if (nrq && me == leader) {
+            t0 = a_add32(R.tail, nrq);
+            tl.headtail += 1;
+        }
         t0 = bcast(t0, leader);
-        if (keep) slot_put(h, R, t0 + rank_in(rq), c);
+        if (keep) slot_put(h, R, t0 + rank_in(rq), c, tl);
         need -= took;
         served += took;
 
@@ -433,7 +478,7 @@ __device__ __forceinline__ uint64_t alloc_group_chunk(const hbheap_dev_t& h, uin
             uint64_t first = 0;
             uint32_t gm = 0;
             if (me == leader) {
-                gm = pool_take(h, m, &first);
+                gm = pool_take(h, m, &first, tl);
                 count_refill(h, gm);
             }
             gm = bcast(gm, leader);
@@ -458,14 +503,15 @@ __device__ __forceinline__ uint64_t alloc_group_chunk(const hbheap_dev_t& h, uin
                 fence_release();
                 if (me == leader) {
                     const uint32_t pos = a_add32(R.tail, 1u);
-                    slot_put(h, R, pos, cl);
+                    tl.headtail += 1;
+                    slot_put(h, R, pos, cl, tl);
                 }
                 publish += 1u;
             }
             need -= r;
             served += r;
         }
-        if (me == leader) ring_release(R, publish);
+        if (me == leader) ring_release(R, publish, tl);
         if (need > 0 && exhausted) {
             bool retry = false;
             if (me == leader) retry = oom_should_retry(h, R, k, oom);
@@ -481,7 +527,7 @@ __device__ __forceinline__ uint64_t alloc_group_chunk(const hbheap_dev_t& h, uin
 
 /* ---------------- page variant: serve one class group ---------------- */
 
-__device__ __forceinline__ uint64_t alloc_group_page(const hbheap_dev_t& h, uint32_t k, uint64_t grp)
+__device__ __forceinline__ uint64_t alloc_group_page(const hbheap_dev_t& h, uint32_t k, uint64_t grp, Tally& tl)
 {
     const uint64_t act = exec_mask();
     const uint32_t me = lane();
@@ -501,13 +547,16 @@ __device__ __forceinline__ uint64_t alloc_group_page(const hbheap_dev_t& h, uint
     while (need > 0) {
         uint32_t got = 0, h0 = 0;
         if (me == leader) {
-            got = ring_reserve(R, need);
-            if (got) h0 = a_add32(R.head, got);
+            got = ring_reserve(R, need, tl);
+            if (got) {
+                h0 = a_add32(R.head, got);
+                tl.headtail += 1;
+            }
         }
         got = bcast(got, leader);
         h0 = bcast(h0, leader);
         if (req && qrank >= served && qrank < served + got) {
-            const uint32_t v = slot_take(h, R, h0 + (qrank - served));
+            const uint32_t v = slot_take(h, R, h0 + (qrank - served), tl);
             if (v != kEmpty && ((uint64_t)v << 4) >= h.data_bytes) raise_err(h, HBHEAP_ERR_CORRUPT, HBHEAP_STAT_TIMEOUTS);
             else if (v != kEmpty) {
                 const uint64_t o = (uint64_t)v << 4;
@@ -515,6 +564,7 @@ __device__ __forceinline__ uint64_t alloc_group_page(const hbheap_dev_t& h, uint
                 const uint32_t p = (uint32_t)((o & ((1ull << h.log2_chunk) - 1ull)) >> shift);
                 const uint64_t bit = 1ull << (p & 63u);
                 const uint64_t old = a_and64(h.bits + c * h.words_per_chunk + (p >> 6), ~bit);
+                tl.spread += 1;
                 if (old & bit) off = o;
                 else raise_err(h, HBHEAP_ERR_CORRUPT, HBHEAP_STAT_TIMEOUTS);
             }
@@ -533,8 +583,12 @@ __device__ __forceinline__ uint64_t alloc_group_page(const hbheap_dev_t& h, uint
                 const uint64_t maxc = page_max_chunks(h, lppc);
                 const uint64_t o = a_add64(owned, m);
                 const uint32_t allow = o >= maxc ? 0u : (uint32_t)((maxc - o) < m ? (maxc - o) : m);
-                gm = allow ? pool_take(h, allow, &first) : 0u;
-                if (gm < m) a_add64(owned, (uint64_t)0 - (uint64_t)(m - gm));
+                gm = allow ? pool_take(h, allow, &first, tl) : 0u;
+                tl.pool += 1;
+                if (gm < m) {
+                    a_add64(owned, (uint64_t)0 - (uint64_t)(m - gm));
+                    tl.pool += 1;
+                }
                 count_refill(h, gm);
             }
             gm = bcast(gm, leader);
@@ -558,17 +612,20 @@ __device__ __forceinline__ uint64_t alloc_group_page(const hbheap_dev_t& h, uint
                 fence_release();
                 const uint32_t L = ppc - u;
                 uint32_t t0 = 0;
-                if (me == leader) t0 = a_add32(R.tail, L);
+                if (me == leader) {
+                    t0 = a_add32(R.tail, L);
+                    tl.headtail += 1;
+                }
                 t0 = bcast(t0, leader);
                 const uint64_t cbase = (uint64_t)cl << h.log2_chunk;
                 for (uint32_t j = arank; j < L; j += nact)
-                    slot_put(h, R, t0 + j, (uint32_t)((cbase + ((uint64_t)(u + j) << shift)) >> 4));
+                    slot_put(h, R, t0 + j, (uint32_t)((cbase + ((uint64_t)(u + j) << shift)) >> 4), tl);
                 publish = L;
             }
             need -= r;
             served += r;
         }
-        if (me == leader) ring_release(R, publish);
+        if (me == leader) ring_release(R, publish, tl);
         if (need > 0 && exhausted) {
             bool retry = false;
             if (me == leader) retry = oom_should_retry(h, R, k, oom);
@@ -591,6 +648,7 @@ __device__ __forceinline__ void* malloc_wave(const hbheap_dev_t& h, uint64_t n)
     uint64_t pending = __ballot(k >= 0);
     uint64_t* stage = stage_for_wave();
     uint64_t off = kNoPage;
+    Tally tl;
     while (pending) {
         const uint32_t leader = ctz64(pending);
         const uint32_t kk = bcast((uint32_t)k, leader);
@@ -599,11 +657,12 @@ __device__ __forceinline__ void* malloc_wave(const hbheap_dev_t& h, uint64_t n)
             const uint32_t seg = leader & ~(h.width - 1u);
             grp &= ((1ull << h.width) - 1ull) << seg;
         }
-        const uint64_t o = h.variant == HBHEAP_VARIANT_CHUNK ? alloc_group_chunk(h, kk, grp, stage)
-                                                              : alloc_group_page(h, kk, grp);
+        const uint64_t o = h.variant == HBHEAP_VARIANT_CHUNK ? alloc_group_chunk(h, kk, grp, stage, tl)
+                                                              : alloc_group_page(h, kk, grp, tl);
         if ((grp >> me) & 1ull) off = o;
         pending &= ~grp;
     }
+    tally_flush(h, tl);
     return off == kNoPage ? nullptr : (void*)(h.data + off);
 }
 
@@ -615,6 +674,7 @@ __device__ __forceinline__ uint32_t free_wave(const hbheap_dev_t& h, void* p, ui
     const uint32_t me = lane();
     uint32_t status = kFreeNull;
     bool enq = false;
+    Tally tl;
     uint32_t val = 0, k = 0;
     if (p != nullptr) {
         status = kFreeInvalid;
@@ -629,12 +689,14 @@ __device__ __forceinline__ uint32_t free_wave(const hbheap_dev_t& h, void* p, ui
                 const uint32_t pg = (uint32_t)((o & ((1ull << h.log2_chunk) - 1ull)) >> shift);
                 const uint64_t bit = 1ull << (pg & 63u);
                 const uint64_t old = a_or64(h.bits + c * h.words_per_chunk + (pg >> 6), bit);
+                tl.spread += 1;
                 if (old & bit) {
                     status = kFreeDouble;
                 } else {
                     status = kFreeOk;
                     if (h.variant == HBHEAP_VARIANT_CHUNK) {
                         enq = a_addi(h.chunk_cnt + c, 1) == 0;
+                        tl.spread += 1;
                         val = (uint32_t)c;
                     } else {
                         enq = true;
@@ -663,12 +725,19 @@ __device__ __forceinline__ uint32_t free_wave(const hbheap_dev_t& h, void* p, ui
         const uint32_t n = (uint32_t)__popcll(grp);
         const Ring R = ring_of(h, kk);
         uint32_t t0 = 0;
-        if (me == leader) t0 = a_add32(R.tail, n);
+        if (me == leader) {
+            t0 = a_add32(R.tail, n);
+            tl.headtail += 1;
+        }
         t0 = bcast(t0, leader);
-        if ((grp >> me) & 1ull) slot_put(h, R, t0 + rank_in(grp), val);
-        if (me == leader) a_add64(R.state, (uint64_t)n);
+        if ((grp >> me) & 1ull) slot_put(h, R, t0 + rank_in(grp), val, tl);
+        if (me == leader) {
+            a_add64(R.state, (uint64_t)n);
+            tl.state += 1;
+        }
         pend &= ~grp;
     }
+    tally_flush(h, tl);
     return status;
 }
 

@@ -49,7 +49,13 @@ extern "C" {
 #define HBHEAP_STAT_DOUBLE_FREE   4
 #define HBHEAP_STAT_INVALID_FREE  5
 #define HBHEAP_STAT_TIMEOUTS      6
-#define HBHEAP_STAT_COUNT         8
+/* atomics issued, by target (FLAG_STATS): class state words, class head and
+ * tail words, the pool counters, per-lane slot/bitmask/count atomics */
+#define HBHEAP_STAT_STATE_OPS     8
+#define HBHEAP_STAT_HEADTAIL_OPS  9
+#define HBHEAP_STAT_POOL_OPS      10
+#define HBHEAP_STAT_SPREAD_OPS    11
+#define HBHEAP_STAT_COUNT         16
 
 /*
  * Device handle: plain data passed by value as a kernel argument.  All
@@ -81,8 +87,9 @@ typedef struct hbheap_dev {
     uint32_t  flags;           /* HBHEAP_FLAG_* bits                         */
 } hbheap_dev_t;
 
-/* Count refills and chunk grabs in the statistics counters (one extra
- * atomic per refill; errors and out-of-memory are always counted). */
+/* Count refills, chunk grabs and atomics by target in the statistics
+ * counters (extra atomics: for measurement runs only; errors and
+ * out-of-memory are always counted). */
 #define HBHEAP_FLAG_STATS 0x1u
 
 #ifdef __cplusplus

@@ -489,8 +489,8 @@ int orc_check_blocks(uint64_t data_bytes, uint64_t chunk_bytes, const uint64_t* 
 /*  64 u64 off chunk_class   72 u64 off chunk_cnt 80 u64 off bits      */
 /*  88 u64 off pool_ids      96 u64 off slots    104 u64 total bytes   */
 /* pool block (128 B): u64 bump, u32 size                              */
-/* class block k (384 B): u64 state (H<<32 | C+2^31), u64 owned,       */
-/*   u32 head at +128, u32 tail at +256                                */
+/* class block k (512 B): u64 state (H<<32 | C+2^31), u32 head at     */
+/*   +128, u32 tail at +256, u64 owned at +384                         */
 /* chunk_class u8[N] (0xFF unowned), chunk_cnt u32[N], bits u64[N*W],  */
 /* pool_ids u32[N], slots u32[K << log2 ring cap] (0xFFFFFFFF empty);  */
 /* page-variant slots hold the page's byte offset / 16; a page-variant */
@@ -587,8 +587,8 @@ int orc_check_snapshot(const uint8_t* snap, uint64_t len, orc_snap_report* rep)
 
     /* class rings */
     for (uint32_t k = 0; k < v.K; ++k) {
-        const uint8_t* cb = v.classes + (uint64_t)k * 384;
-        uint64_t state = rd64(cb), owned = rd64(cb + 8);
+        const uint8_t* cb = v.classes + (uint64_t)k * 512;
+        uint64_t state = rd64(cb), owned = rd64(cb + 384);
         uint32_t head = rd32(cb + 128), tail = rd32(cb + 256);
         uint32_t H = (uint32_t)(state >> 32);
         int64_t Cnt = (int64_t)(uint32_t)state - (int64_t)0x80000000u;

@@ -88,20 +88,29 @@ __global__ void k_iota_u32(uint32_t* p, uint64_t n)
         p[i] = (uint32_t)i;
 }
 
+/* Batch kernels.  The Counted instances run when HBHEAP_FLAG_STATS is set
+ * (measurement passes) and carry their own symbol, so profiles of the
+ * plain instances are not mixed with counting launches. */
+template <bool Counted>
 __global__ void __launch_bounds__(kBatchBlock) k_alloc_batch(hbheap_dev_t h, const uint64_t* __restrict__ sizes,
                                                              void** __restrict__ ptrs, uint64_t n)
 {
     const uint64_t i = (uint64_t)blockIdx.x * kBatchBlock + threadIdx.x;
     if (i >= n) return;
+    if (Counted) h.flags |= HBHEAP_FLAG_STATS;
+    else h.flags &= ~HBHEAP_FLAG_STATS;
     ptrs[i] = malloc_wave(h, sizes[i]);
 }
 
+template <bool Counted>
 __global__ void __launch_bounds__(kBatchBlock) k_free_batch(hbheap_dev_t h, const uint64_t* __restrict__ sizes,
                                                             void* const* __restrict__ ptrs, uint64_t n,
                                                             int32_t* __restrict__ status)
 {
     const uint64_t i = (uint64_t)blockIdx.x * kBatchBlock + threadIdx.x;
     if (i >= n) return;
+    if (Counted) h.flags |= HBHEAP_FLAG_STATS;
+    else h.flags &= ~HBHEAP_FLAG_STATS;
     const uint32_t st = free_wave(h, ptrs[i], sizes ? sizes[i] : 0, sizes != nullptr);
     if (status) status[i] = (int32_t)st;
 }
@@ -269,7 +278,7 @@ __global__ void k_trim_ctl(hbheap_dev_t h, const uint32_t* totals, const uint32_
     if (k < h.n_classes) {
         uint8_t* cb = h.classes + (uint64_t)k * kClassBlock;
         *(uint64_t*)cb = (uint64_t)(totals[k] + kBias);
-        *(uint64_t*)(cb + 8) = h.variant == HBHEAP_VARIANT_PAGE ? (uint64_t)owned[k] : 0ull;
+        *(uint64_t*)(cb + 384) = h.variant == HBHEAP_VARIANT_PAGE ? (uint64_t)owned[k] : 0ull;
         *(uint32_t*)(cb + 128) = 0;
         *(uint32_t*)(cb + 256) = totals[k];
     }
@@ -646,8 +655,12 @@ int heap_alloc_batch(heap_t h, const size_t* sizes, void** ptrs, size_t n, hipSt
 {
     if (!h || (n && (!sizes || !ptrs))) return HBHEAP_E_INVAL;
     if (!n) return HBHEAP_OK;
-    hipLaunchKernelGGL(k_alloc_batch, dim3(grid_for(n, kBatchBlock)), dim3(kBatchBlock), 0, stream, h->dev,
-                       (const uint64_t*)sizes, ptrs, (uint64_t)n);
+    if (h->dev.flags & HBHEAP_FLAG_STATS)
+        hipLaunchKernelGGL(k_alloc_batch<true>, dim3(grid_for(n, kBatchBlock)), dim3(kBatchBlock), 0, stream, h->dev,
+                           (const uint64_t*)sizes, ptrs, (uint64_t)n);
+    else
+        hipLaunchKernelGGL(k_alloc_batch<false>, dim3(grid_for(n, kBatchBlock)), dim3(kBatchBlock), 0, stream, h->dev,
+                           (const uint64_t*)sizes, ptrs, (uint64_t)n);
     return hipGetLastError() == hipSuccess ? HBHEAP_OK : HBHEAP_E_HIP;
 }
 
@@ -655,14 +668,25 @@ int heap_free_batch_ex(heap_t h, const size_t* sizes, void* const* ptrs, size_t 
 {
     if (!h || (n && !ptrs)) return HBHEAP_E_INVAL;
     if (!n) return HBHEAP_OK;
-    hipLaunchKernelGGL(k_free_batch, dim3(grid_for(n, kBatchBlock)), dim3(kBatchBlock), 0, stream, h->dev,
-                       (const uint64_t*)sizes, ptrs, (uint64_t)n, status);
+    if (h->dev.flags & HBHEAP_FLAG_STATS)
+        hipLaunchKernelGGL(k_free_batch<true>, dim3(grid_for(n, kBatchBlock)), dim3(kBatchBlock), 0, stream, h->dev,
+                           (const uint64_t*)sizes, ptrs, (uint64_t)n, status);
+    else
+        hipLaunchKernelGGL(k_free_batch<false>, dim3(grid_for(n, kBatchBlock)), dim3(kBatchBlock), 0, stream, h->dev,
+                           (const uint64_t*)sizes, ptrs, (uint64_t)n, status);
     return hipGetLastError() == hipSuccess ? HBHEAP_OK : HBHEAP_E_HIP;
 }
 
 int heap_free_batch(heap_t h, const size_t* sizes, void* const* ptrs, size_t n, hipStream_t stream)
 {
     return heap_free_batch_ex(h, sizes, ptrs, n, nullptr, stream);
+}
+
+int heap_set_flags(heap_t h, uint32_t flags)
+{
+    if (!h) return HBHEAP_E_INVAL;
+    h->dev.flags = flags;
+    return HBHEAP_OK;
 }
 
 int heap_device_handle(heap_t h, hbheap_dev_t* out)

@@ -18,12 +18,14 @@ VARIANT_CHUNK, VARIANT_PAGE = 0, 1
 OK, E_INVAL, E_NOMEM, E_HIP, E_RANGE, E_UNSUP = 0, -1, -2, -3, -4, -5
 ERR_DOUBLE_FREE, ERR_INVALID_FREE, ERR_TIMEOUT, ERR_CORRUPT = 0x1, 0x2, 0x4, 0x8
 FLAG_STATS = 0x1
-STAT_NAMES = ["chunk_grabs", "refills", "oom", "oom_waits", "double_free", "invalid_free", "timeouts", "reserved"]
+STAT_NAMES = ["chunk_grabs", "refills", "oom", "oom_waits", "double_free", "invalid_free", "timeouts", "reserved7",
+              "state_ops", "headtail_ops", "pool_ops", "spread_ops", "reserved12", "reserved13", "reserved14",
+              "reserved15"]
 FREE_OK, FREE_DOUBLE, FREE_INVALID, FREE_NULL = 0, 1, 2, 3
 
 EXPORTS = [
     "heap_create", "heap_create_ex", "heap_destroy", "heap_alloc_batch", "heap_free_batch", "heap_free_batch_ex",
-    "heap_device_handle", "heap_info", "heap_trim", "heap_snapshot", "heap_get_error", "heap_clear_error",
+    "heap_device_handle", "heap_set_flags", "heap_info", "heap_trim", "heap_snapshot", "heap_get_error", "heap_clear_error",
     "heap_stats", "heap_replay", "heap_pattern_write", "heap_pattern_check", "hb_atomic_probe", "hb_stream_copy",
     "hb_plain_set_heap", "hb_plain_alloc", "hb_plain_free", "hbheap_version",
 ]
@@ -76,6 +78,7 @@ def lib():
         "heap_free_batch": [vp, vp, vp, sz, vp],
         "heap_free_batch_ex": [vp, vp, vp, sz, vp, vp],
         "heap_device_handle": [vp, C.POINTER(DevHandle)],
+        "heap_set_flags": [vp, u32],
         "heap_info": [vp, C.POINTER(HeapInfo)],
         "heap_trim": [vp, vp],
         "heap_snapshot": [vp, vp, sz, C.POINTER(sz), vp],
@@ -153,6 +156,10 @@ def heap_free_batch(h: int, sizes, ptrs, n: int | None = None, stream=None, stat
            lib().heap_free_batch_ex(h, _addr(sizes), _addr(ptrs), n, _addr(status), _stream(stream)))
 
 
+def heap_set_flags(h: int, flags: int):
+    _check("heap_set_flags", lib().heap_set_flags(h, flags))
+
+
 def heap_device_handle(h: int) -> DevHandle:
     d = DevHandle()
     _check("heap_device_handle", lib().heap_device_handle(h, C.byref(d)))
@@ -188,8 +195,8 @@ def heap_clear_error(h: int):
 
 
 def heap_stats(h: int) -> dict:
-    a = (C.c_uint64 * 8)()
-    _check("heap_stats", lib().heap_stats(h, a, 8))
+    a = (C.c_uint64 * 16)()
+    _check("heap_stats", lib().heap_stats(h, a, 16))
     return {name: int(a[i]) for i, name in enumerate(STAT_NAMES)}
 
 
@@ -278,6 +285,9 @@ class Heap:
 
     def stats(self) -> dict:
         return heap_stats(self.h)
+
+    def set_flags(self, flags: int):
+        heap_set_flags(self.h, flags)
 
     def replay(self, ops, out, stream=None):
         heap_replay(self.h, ops, out, stream=stream)

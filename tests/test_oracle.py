@@ -266,7 +266,7 @@ def build_snapshot(N, log2C, variant, log2q, cls, cnt, bits, pool_bump, pool_ids
         return (x + 255) & ~255
     off_pool = 256
     off_cl = off_pool + 128
-    off_cls = al(off_cl + 384 * K)
+    off_cls = al(off_cl + 512 * K)
     off_cnt = al(off_cls + N)
     off_bits = al(off_cnt + 4 * N)
     off_pid = al(off_bits + 8 * N * W)
@@ -285,10 +285,10 @@ def build_snapshot(N, log2C, variant, log2q, cls, cnt, bits, pool_bump, pool_ids
             struct.pack_into("<Q", b, off_bits + 8 * (c * W + w), bits[c][w])
     for k in range(K):
         H, head, ents = rings[k] if k in rings else (0, 0, [])
-        struct.pack_into("<QQ", b, off_cl + 384 * k, (H << 32) | ((len(ents) + 0x80000000) & 0xFFFFFFFF),
-                         (owned or {}).get(k, 0))
-        struct.pack_into("<I", b, off_cl + 384 * k + 128, head & 0xFFFFFFFF)
-        struct.pack_into("<I", b, off_cl + 384 * k + 256, (head + len(ents)) & 0xFFFFFFFF)
+        struct.pack_into("<Q", b, off_cl + 512 * k, (H << 32) | ((len(ents) + 0x80000000) & 0xFFFFFFFF))
+        struct.pack_into("<I", b, off_cl + 512 * k + 128, head & 0xFFFFFFFF)
+        struct.pack_into("<I", b, off_cl + 512 * k + 256, (head + len(ents)) & 0xFFFFFFFF)
+        struct.pack_into("<Q", b, off_cl + 512 * k + 384, (owned or {}).get(k, 0))
         for j in range(Q):
             struct.pack_into("<I", b, off_sl + 4 * (k * Q + j), 0xFFFFFFFF)
         for j, e in enumerate(ents):
