@@ -99,10 +99,13 @@ def lib():
             "orc_num_classes": (u32, [u64]),
             "orc_page_bytes": (u64, [u32]),
             "orc_pages_per_chunk": (u64, [u64, u32]),
-            "orc_page_ring_entries": (u64, [u64, u64]),
-            "orc_page_max_chunks": (u64, [u64, u64, u32]),
+            "orc_shard_geometry": (None, [u64, u32, C.POINTER(u32), C.POINTER(u32)]),
+            "orc_page_ring_entries": (u64, [u64, u64, u32]),
+            "orc_page_max_chunks": (u64, [u64, u64, u32, u32]),
             "orc_geometry_ok": (C.c_int, [u64, u64]),
             "orc_create": (vp, [u64, u64, C.c_int, C.c_int]),
+            "orc_create_ex": (vp, [u64, u64, C.c_int, C.c_int, u32]),
+            "orc_shards": (u32, [vp]),
             "orc_destroy": (None, [vp]),
             "orc_alloc": (i64, [vp, u64]),
             "orc_free": (C.c_int, [vp, i64]),
@@ -134,22 +137,55 @@ def _model_sigs(L):
     L.orc_model_run.argtypes = [C.POINTER(ModelParams), C.POINTER(ModelResult)]
 
 
+class ModelOp(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("a", C.c_int32), ("b", C.c_int32)]
+
+
 class ModelParams(C.Structure):
     _fields_ = [
-        ("variant", C.c_int32), ("n_chunks", C.c_int32), ("ppc", C.c_int32), ("n_classes", C.c_int32),
-        ("n_leaders", C.c_int32), ("ops", (C.c_int32 * 4) * 4), ("n_ops", C.c_int32 * 4),
-        ("prefill", C.c_int32 * 8), ("n_prefill", C.c_int32),
-        ("freeze", C.c_int32), ("mutation", C.c_int32), ("max_states", C.c_int64),
+        ("variant", C.c_int32), ("n_chunks", C.c_int32), ("ppc", C.c_int32), ("maxc", C.c_int32),
+        ("n_leaders", C.c_int32), ("n_ops", C.c_int32 * 3), ("ops", (ModelOp * 3) * 3),
+        ("prefill", C.c_int32), ("freeze", C.c_int32), ("mutation", C.c_int32), ("max_states", C.c_int64),
     ]
 
 
 class ModelResult(C.Structure):
     _fields_ = [
-        ("states", C.c_int64), ("terminals", C.c_int64), ("violations", C.c_int64),
-        ("linearizability_failures", C.c_int64), ("deadlocks", C.c_int64), ("blocked_freezes", C.c_int64),
-        ("truncated", C.c_int32), ("first_violation", C.c_int32), ("outcomes", C.c_int64),
-        ("null_outcomes", C.c_int64),
+        ("states", C.c_int64), ("terminals", C.c_int64), ("violations", C.c_int64), ("deadlocks", C.c_int64),
+        ("token_violations", C.c_int64), ("oom_violations", C.c_int64), ("final_violations", C.c_int64),
+        ("grant_violations", C.c_int64), ("blocked_freezes", C.c_int64), ("null_outcomes", C.c_int64),
+        ("truncated", C.c_int32), ("first_violation", C.c_int32), ("blocking_pcs", C.c_uint32),
+        ("pad", C.c_uint32),
     ]
+
+    def as_dict(self) -> dict:
+        return {f: int(getattr(self, f)) for f, _ in self._fields_ if f != "pad"}
+
+
+OP_ALLOC, OP_FREE_OWN, OP_FREE_GIVEN = 1, 2, 3
+MUTATIONS = {"no_hold": 1, "requeue_always": 2, "free_enqueue_always": 3, "no_refund": 4,
+             "release_no_publish": 5, "publish_early": 6}
+
+
+def model_run(variant: int, n_chunks: int, ppc: int, leaders: list, prefill: int = 0, maxc: int | None = None,
+              freeze: bool = False, mutation: int = 0, max_states: int = 2_000_000) -> dict:
+    """Explore every interleaving of `leaders` (each a list of (kind, a, b)
+    ops) on a heap of n_chunks chunks of ppc pages.  Returns the counters."""
+    p = ModelParams()
+    p.variant, p.n_chunks, p.ppc = variant, n_chunks, ppc
+    p.maxc = n_chunks if maxc is None else maxc
+    p.n_leaders = len(leaders)
+    for l, ops in enumerate(leaders):
+        p.n_ops[l] = len(ops)
+        for i, op in enumerate(ops):
+            kind, a, b = (tuple(op) + (0, 0))[:3]
+            p.ops[l][i] = ModelOp(kind, a, b)
+    p.prefill, p.freeze, p.mutation, p.max_states = prefill, int(freeze), mutation, max_states
+    r = ModelResult()
+    rc = lib().orc_model_run(C.byref(p), C.byref(r))
+    if rc != 0:
+        raise ValueError(f"bad model parameters ({rc})")
+    return r.as_dict()
 
 
 def _ptr(a: np.ndarray):
@@ -176,12 +212,20 @@ def pages_per_chunk(chunk_bytes: int, k: int) -> int:
     return int(lib().orc_pages_per_chunk(chunk_bytes, k))
 
 
-def page_ring_entries(nbytes: int, chunk_bytes: int) -> int:
-    return int(lib().orc_page_ring_entries(nbytes, chunk_bytes))
+def shard_geometry(n_chunks: int, requested: int = 0) -> tuple[int, int]:
+    """(shards, log2 span) for a heap of n_chunks chunks."""
+    S, L = C.c_uint32(), C.c_uint32()
+    lib().orc_shard_geometry(n_chunks, requested, C.byref(S), C.byref(L))
+    return int(S.value), int(L.value)
 
 
-def page_max_chunks(nbytes: int, chunk_bytes: int, k: int) -> int:
-    return int(lib().orc_page_max_chunks(nbytes, chunk_bytes, k))
+def page_ring_entries(nbytes: int, chunk_bytes: int, shards: int = 1) -> int:
+    return int(lib().orc_page_ring_entries(nbytes, chunk_bytes, shards))
+
+
+def page_max_chunks(nbytes: int, chunk_bytes: int, k: int, shards: int = 1) -> int:
+    """Chunks one class may own in one shard (page variant)."""
+    return int(lib().orc_page_max_chunks(nbytes, chunk_bytes, k, shards))
 
 
 # --------------------------------------------------------------------------
@@ -191,13 +235,15 @@ def page_max_chunks(nbytes: int, chunk_bytes: int, k: int) -> int:
 class OracleHeap:
     """Sequential allocator; offsets from the data base, -1 for NULL."""
 
-    def __init__(self, nbytes: int, chunk_bytes: int, variant: int = VARIANT_CHUNK, policy: int = POLICY_LOWEST):
-        self.h = lib().orc_create(nbytes, chunk_bytes, variant, policy)
+    def __init__(self, nbytes: int, chunk_bytes: int, variant: int = VARIANT_CHUNK, policy: int = POLICY_LOWEST,
+                 shards: int = 1):
+        self.h = lib().orc_create_ex(nbytes, chunk_bytes, variant, policy, shards)
         if not self.h:
             raise ValueError("invalid oracle geometry")
         self.nbytes, self.chunk_bytes = nbytes, chunk_bytes
         self.n_chunks = nbytes // chunk_bytes
         self.variant, self.policy = variant, policy
+        self.shards = int(lib().orc_shards(self.h))
 
     def close(self):
         if self.h:

@@ -18,9 +18,11 @@
  *   - Results, "Chunk allocator": queues hold chunks that have free pages;
  *     an allocation first obtains a chunk index, then scans the chunk for a
  *     free page.  Queues are per power-of-two size.
- * Readings where the paper is silent (smallest page 16 B, fixed chunk size,
- * ceil-to-power-of-two rounding, NULL for 0 or > chunk, metadata outside the
- * heap bytes, page-variant queue budget) are listed in the design doc.
+ * Where the paper is silent this file takes these readings: smallest page
+ * 16 B, one fixed chunk size, ceil-to-power-of-two rounding, NULL for 0 or
+ * > chunk, metadata outside the heap bytes, a page-variant queue budget of
+ * bytes/8, and a heap split into shards (runs of chunks with their own pool
+ * and queues) where a request is served from any shard that can.
  *
  * Offsets, not pointers: a block is reported as its byte offset from the
  * start of the heap's data region; -1 stands for NULL.
@@ -47,8 +49,9 @@ int      orc_class_of(uint64_t n, uint64_t chunk_bytes);   /* -1: NULL request *
 uint32_t orc_num_classes(uint64_t chunk_bytes);
 uint64_t orc_page_bytes(uint32_t k);
 uint64_t orc_pages_per_chunk(uint64_t chunk_bytes, uint32_t k);
-uint64_t orc_page_ring_entries(uint64_t bytes, uint64_t chunk_bytes);
-uint64_t orc_page_max_chunks(uint64_t bytes, uint64_t chunk_bytes, uint32_t k);
+void     orc_shard_geometry(uint64_t n_chunks, uint32_t requested, uint32_t* shards, uint32_t* log2_span);
+uint64_t orc_page_ring_entries(uint64_t bytes, uint64_t chunk_bytes, uint32_t shards);
+uint64_t orc_page_max_chunks(uint64_t bytes, uint64_t chunk_bytes, uint32_t k, uint32_t shards);
 int      orc_geometry_ok(uint64_t bytes, uint64_t chunk_bytes);
 
 /* ---- sequential allocator ---- */
@@ -65,7 +68,10 @@ typedef struct {
     uint64_t n_alloc_ok, n_alloc_null, n_free_ok, n_free_double, n_free_invalid;
 } orc_acct;
 
-orc_heap* orc_create(uint64_t bytes, uint64_t chunk_bytes, int variant, int policy);
+/* shards: power of two <= 64, 0 for one per 256 chunks (up to 64) */
+orc_heap* orc_create_ex(uint64_t bytes, uint64_t chunk_bytes, int variant, int policy, uint32_t shards);
+orc_heap* orc_create(uint64_t bytes, uint64_t chunk_bytes, int variant, int policy); /* one shard */
+uint32_t  orc_shards(const orc_heap* h);
 void      orc_destroy(orc_heap* h);
 int64_t   orc_alloc(orc_heap* h, uint64_t n);
 int       orc_free(orc_heap* h, int64_t off);
@@ -106,7 +112,7 @@ typedef struct {
     uint64_t live[ORC_MAX_CLASSES], chunks[ORC_MAX_CLASSES], free_pages[ORC_MAX_CLASSES];
 } orc_snap_report;
 
-/* Quiescent-state consistency of a snapshot (documented layout, version 1). */
+/* Quiescent-state consistency of a snapshot (documented layout, version 2). */
 int orc_check_snapshot(const uint8_t* snap, uint64_t len, orc_snap_report* rep);
 
 /* Blocks against a snapshot: each live block must lie in a chunk of its
@@ -114,6 +120,44 @@ int orc_check_snapshot(const uint8_t* snap, uint64_t len, orc_snap_report* rep);
  * of blocks that fail. */
 uint64_t orc_check_blocks_in_snapshot(const uint8_t* snap, uint64_t len, const uint64_t* sizes,
                                       const int64_t* offs, uint64_t n);
+
+/* ---- step-level model of the concurrent algorithm (hbheap_model.c) ---- */
+#define ORC_MODEL_MAXL 3
+#define ORC_MODEL_MAXOPS 3
+enum { ORC_OP_NONE = 0, ORC_OP_ALLOC = 1, ORC_OP_FREE_OWN = 2, ORC_OP_FREE_GIVEN = 3 };
+
+/* ALLOC: a = pages wanted (group size <= 4); FREE_OWN: a = index of an
+ * earlier ALLOC op of the same leader whose pages are freed; FREE_GIVEN:
+ * free prefill pages [a, a+b). */
+typedef struct { int32_t kind, a, b; } orc_model_op;
+
+typedef struct {
+    int32_t variant;           /* 0 chunk, 1 page                         */
+    int32_t n_chunks;          /* <= 4                                    */
+    int32_t ppc;               /* pages per chunk, <= 8                   */
+    int32_t maxc;              /* page variant: chunks the class may own  */
+    int32_t n_leaders;         /* <= 3                                    */
+    int32_t n_ops[ORC_MODEL_MAXL];
+    orc_model_op ops[ORC_MODEL_MAXL][ORC_MODEL_MAXOPS];
+    int32_t prefill;           /* pages allocated before exploration      */
+    int32_t freeze;            /* also run the freeze analysis            */
+    int32_t mutation;          /* planted mistake, 0 for none             */
+    int64_t max_states;
+} orc_model_params;
+
+typedef struct {
+    int64_t states, terminals, violations, deadlocks;
+    int64_t token_violations, oom_violations, final_violations, grant_violations;
+    int64_t blocked_freezes;   /* freeze points where others cannot finish */
+    int64_t null_outcomes;     /* final states where some request got NULL */
+    int32_t truncated;
+    int32_t first_violation;
+    uint32_t blocking_pcs;     /* bit mask of the frozen leader's pcs      */
+    uint32_t pad;
+} orc_model_result;
+
+/* 0 on success, negative for bad parameters. */
+int orc_model_run(const orc_model_params* p, orc_model_result* r);
 
 #ifdef __cplusplus
 }

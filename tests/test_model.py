@@ -1,0 +1,85 @@
+"""Brute-force enumeration of interleavings on tiny heaps (CPU).
+
+The step-level model (oracle/hbheap_model.c) restates the queue protocol of
+the device allocator one atomic step at a time and explores every schedule
+of two or three wave leaders.  It must find no violation of the token,
+exact-out-of-memory and final-state checks and no deadlock on the clean
+algorithm, and it must find violations for each planted mistake -- which
+shows that the checks can fail.  The freeze analysis must locate blocking
+only where a stopped leader holds the queue (H) or a reserved slot.
+"""
+import pytest
+
+import oracle as O
+
+A, FO, FG = O.OP_ALLOC, O.OP_FREE_OWN, O.OP_FREE_GIVEN
+
+CONFIGS = {
+    "two_allocs": dict(n_chunks=2, ppc=4, leaders=[[(A, 2)], [(A, 2)]]),
+    "three_allocs": dict(n_chunks=2, ppc=4, leaders=[[(A, 1)], [(A, 2)], [(A, 1)]]),
+    "oom_one_chunk": dict(n_chunks=1, ppc=2, leaders=[[(A, 2)], [(A, 2)]]),
+    "oom_refill_race": dict(n_chunks=1, ppc=4, leaders=[[(A, 1)], [(A, 4)]]),
+    "oom_three": dict(n_chunks=2, ppc=2, leaders=[[(A, 2)], [(A, 2)], [(A, 1)]]),
+    "alloc_free_own": dict(n_chunks=2, ppc=2, leaders=[[(A, 2), (FO, 0)], [(A, 2), (FO, 0)]]),
+    "free_vs_alloc": dict(n_chunks=1, ppc=4, prefill=4, leaders=[[(FG, 0, 2)], [(A, 1)], [(A, 1)]]),
+    "free_vs_alloc_2c": dict(n_chunks=2, ppc=2, prefill=4, leaders=[[(FG, 0, 2)], [(A, 2)], [(FG, 2, 1)]]),
+    "churn": dict(n_chunks=2, ppc=2, leaders=[[(A, 1), (FO, 0), (A, 1)], [(A, 2), (FO, 0)]]),
+    "churn3": dict(n_chunks=2, ppc=2, leaders=[[(A, 1), (FO, 0), (A, 1)], [(A, 2), (FO, 0)], [(A, 1)]]),
+    "wide_pages": dict(n_chunks=2, ppc=8, leaders=[[(A, 4)], [(A, 4), (FO, 0)], [(A, 3)]]),
+}
+
+# pcs between a leader's reservation and its release (it holds H), and the
+# slot puts of frees (a tail position reserved but not yet written)
+HOLDING = {0: set(range(2, 16)) | {43}, 1: set(range(22, 33)) | {43}}
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _build():
+    O.build(force=False)
+
+
+@pytest.mark.parametrize("variant", [0, 1])
+@pytest.mark.parametrize("name", sorted(CONFIGS))
+def test_clean_algorithm_has_no_violation(variant, name):
+    r = O.model_run(variant, **CONFIGS[name])
+    assert not r["truncated"], r
+    assert r["terminals"] > 0 and r["states"] > r["terminals"]
+    assert r["violations"] == 0 and r["deadlocks"] == 0, r
+
+
+def test_exact_oom_outcomes_are_reached():
+    """Configurations that over-ask the heap do produce NULLs (so the exact
+    out-of-memory check is exercised), and the ones within capacity never do."""
+    for v in (0, 1):
+        assert O.model_run(v, **CONFIGS["oom_one_chunk"])["null_outcomes"] > 0
+        assert O.model_run(v, **CONFIGS["oom_three"])["null_outcomes"] > 0
+        assert O.model_run(v, **CONFIGS["two_allocs"])["null_outcomes"] == 0
+        assert O.model_run(v, **CONFIGS["three_allocs"])["null_outcomes"] == 0
+
+
+# each mistake must be caught by at least one configuration; the chunk-count
+# mistakes only exist in the chunk variant
+MUTANT_CASES = [
+    (0, "no_hold"), (0, "requeue_always"), (0, "free_enqueue_always"), (0, "no_refund"),
+    (0, "release_no_publish"), (0, "publish_early"),
+    (1, "no_hold"), (1, "no_refund"), (1, "release_no_publish"),
+]
+
+
+@pytest.mark.parametrize("variant,mutant", MUTANT_CASES)
+def test_planted_mistakes_are_caught(variant, mutant):
+    hits = 0
+    for name in ("oom_refill_race", "oom_three", "three_allocs", "churn", "free_vs_alloc"):
+        r = O.model_run(variant, mutation=O.MUTATIONS[mutant], **CONFIGS[name])
+        hits += r["violations"] + r["deadlocks"]
+    assert hits > 0, f"{mutant} not detected"
+
+
+@pytest.mark.parametrize("variant", [0, 1])
+@pytest.mark.parametrize("name", ["three_allocs", "churn", "oom_three", "free_vs_alloc"])
+def test_blocking_points_are_holds_or_reserved_slots(variant, name):
+    r = O.model_run(variant, freeze=True, **CONFIGS[name])
+    assert r["violations"] == 0
+    pcs = {b for b in range(32) if (r["blocking_pcs"] >> b) & 1}  # pcs modulo 32
+    allowed = {pc % 32 for pc in HOLDING[variant]}
+    assert pcs <= allowed, (sorted(pcs), sorted(allowed))
