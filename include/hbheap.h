@@ -41,6 +41,8 @@ typedef struct heap_config {
     uint32_t spin_cap;     /* bounded-wait iterations, default 1 << 18        */
     uint32_t backoff_max;  /* longest backoff in s_sleep(1) units, default 64 */
     uint32_t flags;        /* HBHEAP_FLAG_*                                   */
+    uint32_t shards;       /* queue shards: power of two <= 64; 0 = about one
+                              per 256 chunks, at most 64                     */
 } heap_config_t;
 
 /* Geometry and placement of a heap (heap_info). */
@@ -51,9 +53,12 @@ typedef struct heap_info {
     uint64_t n_chunks;
     uint32_t n_classes;       /* pages 16 B * 2^k, k < n_classes             */
     uint32_t variant;
-    uint64_t ring_entries;    /* capacity of each class queue                */
+    uint64_t ring_entries;    /* capacity of each (shard, class) queue       */
     uint64_t state_bytes;     /* size of the state region (= snapshot size)  */
     uint64_t metadata_bytes;  /* all device memory besides the data region   */
+    uint32_t n_shards;        /* shards actually used (chunk runs of a power
+                                 of two, the last one possibly shorter)      */
+    uint32_t reserved;
 } heap_info_t;
 
 /*

@@ -23,8 +23,8 @@
  *   - Each class queue is a ring of u32 slots with monotone head/tail and a
  *     64-bit state word (H << 32 | count + 2^31), each on its own 128-byte
  *     line.  H counts operations in flight that may still publish entries;
- *     a request returns NULL only after it saw the pool exhausted, then the
- *     state with H == 0 and count <= 0 (exact out-of-memory).
+ *     a shard counts as empty for a class only once its pool is exhausted
+ *     and its state shows H == 0 and count <= 0 (exact out-of-memory).
  *   - Slots are taken with an atomic exchange against EMPTY and filled with
  *     compare-and-swap from EMPTY, so a slot whose producer is late is waited
  *     for instead of being read twice.
@@ -36,6 +36,14 @@
  *   - Unowned chunks sit in a pool array consumed by a 64-bit bump counter,
  *     so "pool empty" is exact and never undone during a kernel; chunks come
  *     back to the pool only through heap_trim() at quiescence.
+ *   - The heap is split into shards, each owning a run of consecutive chunks
+ *     with its own pool and its own class queues; a wave starts at its home
+ *     shard (spread by wave index); when it runs dry the wave looks at every
+ *     shard at once (one lane per shard) and steals from one that has
+ *     something, so the queue words of one class are hit by 1/S of the
+ *     waves.  A request returns NULL only when one such look finds every
+ *     shard with no entry, no hold in flight and no chunk left for the
+ *     class.
  *   - Every wait is bounded: past spin_cap iterations the wait gives up,
  *     sets HBHEAP_ERR_TIMEOUT and the request returns NULL.
  *   - Metadata atomics are agent-scope and relaxed; ordering comes from
@@ -176,6 +184,25 @@ __device__ __forceinline__ int class_of(const hbheap_dev_t& h, uint64_t n)
     return 64 - __builtin_clzll(n - 1) - 4; /* ceil(log2 n) - 4 */
 }
 
+/* Shard owning chunk c: shards own consecutive runs of 2^log2_span chunks. */
+__device__ __forceinline__ uint32_t shard_of_chunk(const hbheap_dev_t& h, uint64_t c)
+{
+    return (uint32_t)(c >> h.log2_span);
+}
+
+/* Home shard of the calling wave: waves are spread round-robin over the
+ * shards by their linear wave index in the grid (block-major), so the
+ * waves of one launch load every shard's queues evenly. */
+__device__ __forceinline__ uint32_t home_shard(const hbheap_dev_t& h)
+{
+    if (h.n_shards == 1) return 0;
+    const uint32_t blk = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
+    const uint32_t nthr = blockDim.x * blockDim.y * blockDim.z;
+    const uint32_t lin = threadIdx.x + blockDim.x * (threadIdx.y + blockDim.y * threadIdx.z);
+    const uint32_t wave = blk * ((nthr + 63u) >> 6) + (lin >> 6);
+    return wave % h.n_shards;
+}
+
 /* ---------------- class ring ---------------- */
 
 struct Ring {
@@ -186,20 +213,25 @@ struct Ring {
     uint32_t mask;
 };
 
-__device__ __forceinline__ Ring ring_of(const hbheap_dev_t& h, uint32_t k)
+__device__ __forceinline__ uint8_t* class_block(const hbheap_dev_t& h, uint32_t j, uint32_t k)
 {
-    uint8_t* cb = h.classes + (uint64_t)k * kClassBlock;
+    return h.classes + ((uint64_t)j * h.n_classes + k) * kClassBlock;
+}
+
+__device__ __forceinline__ Ring ring_of(const hbheap_dev_t& h, uint32_t j, uint32_t k)
+{
+    uint8_t* cb = class_block(h, j, k);
     Ring r;
     r.state = (uint64_t*)cb;
     r.head = (uint32_t*)(cb + 128);
     r.tail = (uint32_t*)(cb + 256);
-    r.slots = h.slots + ((uint64_t)k << h.log2q);
+    r.slots = h.slots + (((uint64_t)j * h.n_classes + k) << h.log2q);
     r.mask = (1u << h.log2q) - 1u;
     return r;
 }
-__device__ __forceinline__ uint64_t* owned_of(const hbheap_dev_t& h, uint32_t k)
+__device__ __forceinline__ uint64_t* owned_of(const hbheap_dev_t& h, uint32_t j, uint32_t k)
 {
-    return (uint64_t*)(h.classes + (uint64_t)k * kClassBlock + 384);
+    return (uint64_t*)(class_block(h, j, k) + 384);
 }
 __device__ __forceinline__ int32_t state_count(uint64_t s) { return (int32_t)((uint32_t)s - kBias); }
 
@@ -261,26 +293,33 @@ __device__ __forceinline__ bool slot_put(const hbheap_dev_t& h, const Ring& r, u
     }
 }
 
-/* ---------------- pool ---------------- */
+/* ---------------- pool (per shard) ---------------- */
 
-/* Leader only: take up to m unowned chunks; returns the first pool index in
- * *first and the number granted. */
-__device__ __forceinline__ uint32_t pool_take(const hbheap_dev_t& h, uint32_t m, uint64_t* first, Tally& t)
+/* Pool block of shard j (128 B): u64 bump, u32 size, u32 first pool index. */
+__device__ __forceinline__ uint64_t* pool_block(const hbheap_dev_t& h, uint32_t j) { return h.pool + 16ull * j; }
+
+/* Leader only: take up to m unowned chunks of shard j; *first receives the
+ * index in pool_ids of the first one, the return value how many. */
+__device__ __forceinline__ uint32_t pool_take(const hbheap_dev_t& h, uint32_t j, uint32_t m, uint64_t* first, Tally& t)
 {
-    const uint64_t size = (uint32_t)h.pool[1];
-    const uint64_t b = a_add64(h.pool, m);
+    uint64_t* pb = pool_block(h, j);
+    const uint32_t size = ((const uint32_t*)pb)[2];
+    const uint32_t start = ((const uint32_t*)pb)[3];
+    if (a_load64(pb) >= size) return 0; /* exhausted: no need to move the bump */
+    const uint64_t b = a_add64(pb, m);
     t.pool += 1;
-    *first = b;
+    *first = start + b;
     if (b >= size) return 0;
     return (uint32_t)((size - b) < m ? (size - b) : m);
 }
-__device__ __forceinline__ bool pool_empty(const hbheap_dev_t& h)
+__device__ __forceinline__ bool pool_empty(const hbheap_dev_t& h, uint32_t j)
 {
-    return a_load64(h.pool) >= (uint32_t)h.pool[1];
+    uint64_t* pb = pool_block(h, j);
+    return a_load64(pb) >= ((const uint32_t*)pb)[2];
 }
 
 /* Page variant: a class may own at most (ring capacity / pages per chunk)
- * chunks, so its ring can always hold every free page it owns. */
+ * chunks of a shard, so its ring can always hold every free page it owns. */
 __device__ __forceinline__ uint64_t page_max_chunks(const hbheap_dev_t& h, uint32_t lppc)
 {
     return (1ull << h.log2q) >> lppc;
@@ -362,76 +401,131 @@ __device__ __forceinline__ uint64_t* stage_for_wave()
     return hbheap_stage_lds + (lin >> 6) * 64u;
 }
 
-/* Out-of-memory decision, leader only, after this group saw the pool (or
- * the class cap) exhausted: wait until no operation holds the class queue,
- * then retry if entries were published, else report out of memory.  For the
- * page variant the cap and pool are read again once nothing is in flight. */
-__device__ __forceinline__ bool oom_should_retry(const hbheap_dev_t& h, const Ring& R, uint32_t k, Backoff& b)
+/* ---------------- one class group of one wave ---------------- */
+
+/* Wave-uniform facts about the lanes requesting one class.  The leader is
+ * the lowest active lane; helpers are the active lanes by rank. */
+struct Group {
+    uint64_t act;
+    uint32_t me, leader, nact, arank, qrank;
+    bool req;
+    uint32_t k, shift, lppc, ppc;
+};
+
+__device__ __forceinline__ Group make_group(const hbheap_dev_t& h, uint32_t k, uint64_t grp)
 {
-    a_add64(h.stats + HBHEAP_STAT_OOM_WAITS, 1);
-    /* every decision spends from the same budget, so retries are bounded */
-    if (!b.wait(h)) {
-        raise_err(h, HBHEAP_ERR_TIMEOUT, HBHEAP_STAT_TIMEOUTS);
-        return false;
-    }
+    Group g;
+    g.act = exec_mask();
+    g.me = lane();
+    g.leader = ctz64(g.act);
+    g.nact = (uint32_t)__popcll(g.act);
+    g.arank = rank_in(g.act);
+    g.req = (grp >> g.me) & 1ull;
+    g.qrank = rank_in(grp);
+    g.k = k;
+    g.shift = 4u + k;
+    g.lppc = h.log2_chunk - g.shift;
+    g.ppc = 1u << g.lppc;
+    return g;
+}
+
+/* Page variant: reserve room for up to m more chunks of class k in shard j
+ * under the cap, with compare-and-swap so the counter never passes the cap.
+ * Returns the number reserved; unused reservations are returned by the
+ * caller only when the pool ran dry. */
+__device__ __forceinline__ uint32_t owned_reserve(const hbheap_dev_t& h, uint32_t j, uint32_t k, uint32_t lppc, uint32_t m,
+                                                  Tally& tl)
+{
+    uint64_t* owned = owned_of(h, j, k);
+    const uint64_t maxc = page_max_chunks(h, lppc);
+    uint64_t o = a_load64(owned);
     for (;;) {
-        const uint64_t s = a_load64(R.state);
-        if (state_count(s) > 0) return true;
-        if ((s >> 32) == 0) {
-            if (h.variant == HBHEAP_VARIANT_PAGE)
-                return !pool_empty(h) && a_load64(owned_of(h, k)) < page_max_chunks(h, h.log2_chunk - 4u - k);
-            return false;
-        }
-        if (!b.wait(h)) {
-            raise_err(h, HBHEAP_ERR_TIMEOUT, HBHEAP_STAT_TIMEOUTS);
-            return false;
-        }
+        if (o >= maxc) return 0;
+        const uint32_t allow = (maxc - o) < m ? (uint32_t)(maxc - o) : m;
+        tl.pool += 1;
+        if (__hip_atomic_compare_exchange_strong(owned, &o, o + allow, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                                 __HIP_MEMORY_SCOPE_AGENT))
+            return allow;
     }
 }
 
-/* ---------------- chunk variant: serve one class group ---------------- */
-
-__device__ __forceinline__ uint64_t alloc_group_chunk(const hbheap_dev_t& h, uint32_t k, uint64_t grp, uint64_t* stage,
-                                                      Tally& tl)
+/* Does shard j show entries or room to grow for class k?  (Pool and owned
+ * counter read before the state word.)  A wave skips a shard that shows
+ * neither instead of taking a hold on it, so waves that find nothing do not
+ * keep the shard's hold count busy. */
+__device__ __forceinline__ bool shard_has_something(const hbheap_dev_t& h, uint32_t j, uint32_t k, uint32_t lppc)
 {
-    const uint64_t act = exec_mask();
-    const uint32_t me = lane();
-    const uint32_t leader = ctz64(act);
-    const uint32_t nact = (uint32_t)__popcll(act);
-    const uint32_t arank = rank_in(act);
-    const bool req = (grp >> me) & 1ull;
-    const uint32_t qrank = rank_in(grp);
-    const uint32_t shift = 4u + k;
-    const uint32_t lppc = h.log2_chunk - shift;
-    const uint32_t ppc = 1u << lppc;
-    const Ring R = ring_of(h, k);
+    bool grow = !pool_empty(h, j);
+    if (grow && h.variant == HBHEAP_VARIANT_PAGE) grow = a_load64(owned_of(h, j, k)) < page_max_chunks(h, lppc);
+    return grow || state_count(a_load64(ring_of(h, j, k).state)) > 0;
+}
 
-    stage[arank] = kNoPage;
-    wave_sync_lds();
+/* One look at every shard's queue for the group's class, spread over the
+ * active lanes (rank r looks at shards home+r, home+r+nact, ...).  Per
+ * shard the pool (and the page-variant owned counter) is read before the
+ * state word: a pool once empty stays empty until the next trim, so "pool
+ * empty, then no hold and no entry" means the shard had nothing at the
+ * moment its state was read.  Returns the rotated rank (from home) of the
+ * first shard with published entries or room to grow, or S; *busy tells
+ * whether any shard had a hold in flight. */
+__device__ __forceinline__ uint32_t scan_shards(const hbheap_dev_t& h, const Group& g, uint32_t home, bool* busy)
+{
+    const uint32_t S = h.n_shards;
+    bool anybusy = false;
+    for (uint32_t base = 0; base < S; base += g.nact) {
+        const uint32_t r = base + g.arank;
+        bool avail = false, hold = false;
+        if (r < S) {
+            const uint32_t j = home + r < S ? home + r : home + r - S;
+            bool grow = !pool_empty(h, j);
+            if (grow && h.variant == HBHEAP_VARIANT_PAGE)
+                grow = a_load64(owned_of(h, j, g.k)) < page_max_chunks(h, g.lppc);
+            const uint64_t st = a_load64(ring_of(h, j, g.k).state);
+            hold = (st >> 32) != 0;
+            avail = state_count(st) > 0 || grow;
+        }
+        const uint64_t av = __ballot(avail);
+        anybusy = anybusy || __ballot(hold) != 0;
+        if (av) {
+            *busy = anybusy;
+            return bcast(r, ctz64(av));
+        }
+    }
+    *busy = anybusy;
+    return S;
+}
 
-    uint32_t need = (uint32_t)__popcll(grp), served = 0;
-    Backoff oom;
+/* Chunk variant, shard j: serve up to `need` pages of the group's class,
+ * writing their byte offsets to stage[served..).  Returns when need is met
+ * or when shard j's queue and pool could not supply more. */
+__device__ __forceinline__ void chunk_serve_shard(const hbheap_dev_t& h, const Group& g, uint32_t j, uint32_t& need,
+                                                  uint32_t& served, uint64_t* stage, Tally& tl)
+{
+    const Ring R = ring_of(h, j, g.k);
     while (need > 0) {
-        const uint32_t want0 = (need + ppc - 1u) >> lppc;
-        const uint32_t want = want0 < nact ? want0 : nact;
+        uint32_t some = 0;
+        if (g.me == g.leader) some = shard_has_something(h, j, g.k, g.lppc);
+        if (!bcast(some, g.leader)) return;
+        const uint32_t want0 = (need + g.ppc - 1u) >> g.lppc;
+        const uint32_t want = want0 < g.nact ? want0 : g.nact;
         uint32_t got = 0, h0 = 0;
-        if (me == leader) {
+        if (g.me == g.leader) {
             got = ring_reserve(R, want, tl);
             if (got) {
                 h0 = a_add32(R.head, got);
                 tl.headtail += 1;
             }
         }
-        got = bcast(got, leader);
-        h0 = bcast(h0, leader);
+        got = bcast(got, g.leader);
+        h0 = bcast(h0, g.leader);
 
         /* helpers take one chunk each and read its free count */
-        const bool helper = arank < got;
+        const bool helper = g.arank < got;
         uint32_t c = kEmpty;
         int32_t v = 0;
         if (helper) {
-            c = slot_take(h, R, h0 + arank, tl);
-            if (c != kEmpty && c >= h.n_chunks) {
+            c = slot_take(h, R, h0 + g.arank, tl);
+            if (c != kEmpty && (c >= h.n_chunks || shard_of_chunk(h, c) != j)) {
                 raise_err(h, HBHEAP_ERR_CORRUPT, HBHEAP_STAT_TIMEOUTS);
                 c = kEmpty;
             }
@@ -450,22 +544,23 @@ __device__ __forceinline__ uint64_t alloc_group_chunk(const hbheap_dev_t& h, uin
             if (t) {
                 keep = a_addi(h.chunk_cnt + c, -(int32_t)t) - (int32_t)t > 0;
                 tl.spread += 1;
+            } else {
+                keep = true;
             }
-            else keep = true;
         }
         uint32_t took;
         const uint32_t tpre = excl_scan<7>(t, &took);
-        if (t) claim_pages(h, c, k, t, stage + served + tpre, tl);
+        if (t) claim_pages(h, c, g.k, t, stage + served + tpre, tl);
 
         /* chunks that still hold free pages go back to the tail */
         const uint64_t rq = __ballot(keep);
         const uint32_t nrq = (uint32_t)__popcll(rq);
         uint32_t t0 = 0;
-        if (nrq && me == leader) {
+        if (nrq && g.me == g.leader) {
             t0 = a_add32(R.tail, nrq);
             tl.headtail += 1;
         }
-        t0 = bcast(t0, leader);
+        t0 = bcast(t0, g.leader);
         if (keep) slot_put(h, R, t0 + rank_in(rq), c, tl);
         need -= took;
         served += took;
@@ -473,35 +568,35 @@ __device__ __forceinline__ uint64_t alloc_group_chunk(const hbheap_dev_t& h, uin
         uint32_t publish = nrq;
         bool exhausted = false;
         if (got < want && need > 0) {
-            /* refill from the pool while still holding the queue */
-            const uint32_t m = (need + ppc - 1u) >> lppc;
+            /* refill from the shard's pool while still holding the queue */
+            const uint32_t m = (need + g.ppc - 1u) >> g.lppc;
             uint64_t first = 0;
             uint32_t gm = 0;
-            if (me == leader) {
-                gm = pool_take(h, m, &first, tl);
+            if (g.me == g.leader) {
+                gm = pool_take(h, j, m, &first, tl);
                 count_refill(h, gm);
             }
-            gm = bcast(gm, leader);
-            first = bcast64(first, leader);
+            gm = bcast(gm, g.leader);
+            first = bcast64(first, g.leader);
             exhausted = gm < m;
-            if (arank < gm) h.chunk_class[h.pool_ids[first + arank]] = (uint8_t)k;
-            const uint32_t cap = gm << lppc;
+            if (g.arank < gm) h.chunk_class[h.pool_ids[first + g.arank]] = (uint8_t)g.k;
+            const uint32_t cap = gm << g.lppc;
             const uint32_t r = cap < need ? cap : need;
-            if (arank < r) {
-                const uint32_t ci = h.pool_ids[first + (arank >> lppc)];
-                stage[served + arank] = ((uint64_t)ci << h.log2_chunk) + ((uint64_t)(arank & (ppc - 1u)) << shift);
+            if (g.arank < r) {
+                const uint32_t ci = h.pool_ids[first + (g.arank >> g.lppc)];
+                stage[served + g.arank] = ((uint64_t)ci << h.log2_chunk) + ((uint64_t)(g.arank & (g.ppc - 1u)) << g.shift);
             }
             if (cap > need) {
                 /* last chunk keeps pages [u, ppc): set their bits, publish it */
                 const uint32_t last = gm - 1u;
-                const uint32_t u = need - (last << lppc);
+                const uint32_t u = need - (last << g.lppc);
                 const uint32_t cl = h.pool_ids[first + last];
-                const uint32_t nw = ppc >= 64u ? ppc >> 6 : 1u;
-                for (uint32_t w = arank; w < nw; w += nact)
-                    h.bits[(uint64_t)cl * h.words_per_chunk + w] = free_mask_word(w, u, ppc);
-                if (me == leader) h.chunk_cnt[cl] = (int32_t)(ppc - u);
+                const uint32_t nw = g.ppc >= 64u ? g.ppc >> 6 : 1u;
+                for (uint32_t w = g.arank; w < nw; w += g.nact)
+                    h.bits[(uint64_t)cl * h.words_per_chunk + w] = free_mask_word(w, u, g.ppc);
+                if (g.me == g.leader) h.chunk_cnt[cl] = (int32_t)(g.ppc - u);
                 fence_release();
-                if (me == leader) {
+                if (g.me == g.leader) {
                     const uint32_t pos = a_add32(R.tail, 1u);
                     tl.headtail += 1;
                     slot_put(h, R, pos, cl, tl);
@@ -511,129 +606,205 @@ __device__ __forceinline__ uint64_t alloc_group_chunk(const hbheap_dev_t& h, uin
             need -= r;
             served += r;
         }
-        if (me == leader) ring_release(R, publish, tl);
-        if (need > 0 && exhausted) {
-            bool retry = false;
-            if (me == leader) retry = oom_should_retry(h, R, k, oom);
-            if (!bcast((uint32_t)retry, leader)) break;
-        }
+        if (g.me == g.leader) ring_release(R, publish, tl);
+        if (need > 0 && got < want && exhausted) return;
         /* entries reserved but nothing served: a wait gave up (error raised) */
-        if (got > 0 && took == 0) break;
+        if (got > 0 && took == 0) return;
     }
-    if (need > 0 && me == leader) a_add64(h.stats + HBHEAP_STAT_OOM, need);
-    wave_sync_lds();
-    return req ? stage[qrank] : kNoPage;
 }
 
-/* ---------------- page variant: serve one class group ---------------- */
-
-__device__ __forceinline__ uint64_t alloc_group_page(const hbheap_dev_t& h, uint32_t k, uint64_t grp, Tally& tl)
+/* Page variant: lanes with `have` clear `bit` of bitmask word `widx`
+ * (their page must have been free); lanes sharing a word are combined into
+ * one atomicAnd by their lowest lane until a group of fewer than 4 lanes
+ * shows up, then the rest clear their bits one lane at a time.  On success
+ * a lane's `off` becomes its page offset `o`. */
+__device__ __forceinline__ void clear_bits_grouped(const hbheap_dev_t& h, bool have, uint64_t widx, uint64_t bit,
+                                                   uint64_t o, uint64_t& off, Tally& tl)
 {
-    const uint64_t act = exec_mask();
     const uint32_t me = lane();
-    const uint32_t leader = ctz64(act);
-    const uint32_t nact = (uint32_t)__popcll(act);
-    const uint32_t arank = rank_in(act);
-    const bool req = (grp >> me) & 1ull;
-    const uint32_t qrank = rank_in(grp);
-    const uint32_t shift = 4u + k;
-    const uint32_t lppc = h.log2_chunk - shift;
-    const uint32_t ppc = 1u << lppc;
-    const Ring R = ring_of(h, k);
-
-    uint64_t off = kNoPage;
-    uint32_t need = (uint32_t)__popcll(grp), served = 0;
-    Backoff oom;
-    while (need > 0) {
-        uint32_t got = 0, h0 = 0;
+    uint64_t todo = __ballot(have);
+    uint64_t* acc = stage_for_wave();
+    bool first_round = true;
+    while (todo) {
+        const uint32_t leader = ctz64(todo);
+        const uint64_t wkey = bcast64(widx, leader);
+        const uint64_t grp = __ballot(have && widx == wkey) & todo;
+        if (!first_round && __popcll(grp) < 4) break;
+        first_round = false;
+        if (me == leader) *acc = 0;
+        wave_sync_lds();
+        if ((grp >> me) & 1ull) __hip_atomic_fetch_or(acc, bit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        wave_sync_lds();
+        uint64_t old = 0;
         if (me == leader) {
+            old = a_and64(h.bits + widx, ~*acc);
+            tl.spread += 1;
+        }
+        wave_sync_lds();
+        old = bcast64(old, leader);
+        if ((grp >> me) & 1ull) {
+            if (old & bit) off = o;
+            else raise_err(h, HBHEAP_ERR_CORRUPT, HBHEAP_STAT_TIMEOUTS);
+        }
+        todo &= ~grp;
+    }
+    if ((todo >> me) & 1ull) {
+        /* scattered pages: one lane at a time */
+        const uint64_t old = a_and64(h.bits + widx, ~bit);
+        tl.spread += 1;
+        if (old & bit) off = o;
+        else raise_err(h, HBHEAP_ERR_CORRUPT, HBHEAP_STAT_TIMEOUTS);
+    }
+}
+
+/* Page variant, shard j: requesting lanes of ranks [served, served+need)
+ * receive pages; *off is this lane's page. */
+__device__ __forceinline__ void page_serve_shard(const hbheap_dev_t& h, const Group& g, uint32_t j, uint32_t& need,
+                                                 uint32_t& served, uint64_t& off, Tally& tl)
+{
+    const Ring R = ring_of(h, j, g.k);
+    while (need > 0) {
+        uint32_t some = 0;
+        if (g.me == g.leader) some = shard_has_something(h, j, g.k, g.lppc);
+        if (!bcast(some, g.leader)) return;
+        uint32_t got = 0, h0 = 0;
+        if (g.me == g.leader) {
             got = ring_reserve(R, need, tl);
             if (got) {
                 h0 = a_add32(R.head, got);
                 tl.headtail += 1;
             }
         }
-        got = bcast(got, leader);
-        h0 = bcast(h0, leader);
-        if (req && qrank >= served && qrank < served + got) {
-            const uint32_t v = slot_take(h, R, h0 + (qrank - served), tl);
-            if (v != kEmpty && ((uint64_t)v << 4) >= h.data_bytes) raise_err(h, HBHEAP_ERR_CORRUPT, HBHEAP_STAT_TIMEOUTS);
-            else if (v != kEmpty) {
-                const uint64_t o = (uint64_t)v << 4;
+        got = bcast(got, g.leader);
+        h0 = bcast(h0, g.leader);
+        /* takers read their slots; then the bits of taken pages are cleared,
+         * one atomicAnd per bitmask word shared by the takers */
+        bool took_page = false;
+        uint64_t widx = 0, bit = 0, o = 0;
+        if (g.req && g.qrank >= served && g.qrank < served + got) {
+            const uint32_t v = slot_take(h, R, h0 + (g.qrank - served), tl);
+            o = (uint64_t)v << 4;
+            if (v != kEmpty && (o >= h.data_bytes || shard_of_chunk(h, o >> h.log2_chunk) != j)) {
+                raise_err(h, HBHEAP_ERR_CORRUPT, HBHEAP_STAT_TIMEOUTS);
+            } else if (v != kEmpty) {
                 const uint64_t c = o >> h.log2_chunk;
-                const uint32_t p = (uint32_t)((o & ((1ull << h.log2_chunk) - 1ull)) >> shift);
-                const uint64_t bit = 1ull << (p & 63u);
-                const uint64_t old = a_and64(h.bits + c * h.words_per_chunk + (p >> 6), ~bit);
-                tl.spread += 1;
-                if (old & bit) off = o;
-                else raise_err(h, HBHEAP_ERR_CORRUPT, HBHEAP_STAT_TIMEOUTS);
+                const uint32_t p = (uint32_t)((o & ((1ull << h.log2_chunk) - 1ull)) >> g.shift);
+                widx = c * h.words_per_chunk + (p >> 6);
+                bit = 1ull << (p & 63u);
+                took_page = true;
             }
         }
+        clear_bits_grouped(h, took_page, widx, bit, o, off, tl);
         need -= got;
         served += got;
 
         uint32_t publish = 0;
         bool exhausted = false;
         if (need > 0) {
-            const uint32_t m = (need + ppc - 1u) >> lppc;
+            const uint32_t m = (need + g.ppc - 1u) >> g.lppc;
             uint64_t first = 0;
             uint32_t gm = 0;
-            if (me == leader) {
-                uint64_t* owned = owned_of(h, k);
-                const uint64_t maxc = page_max_chunks(h, lppc);
-                const uint64_t o = a_add64(owned, m);
-                const uint32_t allow = o >= maxc ? 0u : (uint32_t)((maxc - o) < m ? (maxc - o) : m);
-                gm = allow ? pool_take(h, allow, &first, tl) : 0u;
-                tl.pool += 1;
-                if (gm < m) {
-                    a_add64(owned, (uint64_t)0 - (uint64_t)(m - gm));
-                    tl.pool += 1;
+            if (g.me == g.leader) {
+                if (!pool_empty(h, j)) {
+                    const uint32_t allow = owned_reserve(h, j, g.k, g.lppc, m, tl);
+                    gm = allow ? pool_take(h, j, allow, &first, tl) : 0u;
+                    if (gm < allow) {
+                        /* the pool ran dry: give back what was not taken */
+                        a_add64(owned_of(h, j, g.k), (uint64_t)0 - (uint64_t)(allow - gm));
+                        tl.pool += 1;
+                    }
                 }
                 count_refill(h, gm);
             }
-            gm = bcast(gm, leader);
-            first = bcast64(first, leader);
+            gm = bcast(gm, g.leader);
+            first = bcast64(first, g.leader);
             exhausted = gm < m;
-            if (arank < gm) h.chunk_class[h.pool_ids[first + arank]] = (uint8_t)k;
-            const uint32_t cap = gm << lppc;
+            if (g.arank < gm) h.chunk_class[h.pool_ids[first + g.arank]] = (uint8_t)g.k;
+            const uint32_t cap = gm << g.lppc;
             const uint32_t r = cap < need ? cap : need;
-            if (req && qrank >= served && qrank < served + r) {
-                const uint32_t q = qrank - served;
-                const uint32_t ci = h.pool_ids[first + (q >> lppc)];
-                off = ((uint64_t)ci << h.log2_chunk) + ((uint64_t)(q & (ppc - 1u)) << shift);
+            if (g.req && g.qrank >= served && g.qrank < served + r) {
+                const uint32_t q = g.qrank - served;
+                const uint32_t ci = h.pool_ids[first + (q >> g.lppc)];
+                off = ((uint64_t)ci << h.log2_chunk) + ((uint64_t)(q & (g.ppc - 1u)) << g.shift);
             }
             if (cap > need) {
                 const uint32_t last = gm - 1u;
-                const uint32_t u = need - (last << lppc);
+                const uint32_t u = need - (last << g.lppc);
                 const uint32_t cl = h.pool_ids[first + last];
-                const uint32_t nw = ppc >= 64u ? ppc >> 6 : 1u;
-                for (uint32_t w = arank; w < nw; w += nact)
-                    h.bits[(uint64_t)cl * h.words_per_chunk + w] = free_mask_word(w, u, ppc);
+                const uint32_t nw = g.ppc >= 64u ? g.ppc >> 6 : 1u;
+                for (uint32_t w = g.arank; w < nw; w += g.nact)
+                    h.bits[(uint64_t)cl * h.words_per_chunk + w] = free_mask_word(w, u, g.ppc);
                 fence_release();
-                const uint32_t L = ppc - u;
+                const uint32_t L = g.ppc - u;
                 uint32_t t0 = 0;
-                if (me == leader) {
+                if (g.me == g.leader) {
                     t0 = a_add32(R.tail, L);
                     tl.headtail += 1;
                 }
-                t0 = bcast(t0, leader);
+                t0 = bcast(t0, g.leader);
                 const uint64_t cbase = (uint64_t)cl << h.log2_chunk;
-                for (uint32_t j = arank; j < L; j += nact)
-                    slot_put(h, R, t0 + j, (uint32_t)((cbase + ((uint64_t)(u + j) << shift)) >> 4), tl);
+                for (uint32_t i = g.arank; i < L; i += g.nact)
+                    slot_put(h, R, t0 + i, (uint32_t)((cbase + ((uint64_t)(u + i) << g.shift)) >> 4), tl);
                 publish = L;
             }
             need -= r;
             served += r;
         }
-        if (me == leader) ring_release(R, publish, tl);
-        if (need > 0 && exhausted) {
-            bool retry = false;
-            if (me == leader) retry = oom_should_retry(h, R, k, oom);
-            if (!bcast((uint32_t)retry, leader)) break;
+        if (g.me == g.leader) ring_release(R, publish, tl);
+        if (need > 0 && exhausted) return;
+    }
+}
+
+/* Serve one class group: the home shard first; then, while requests remain,
+ * scan every shard at once and serve from the first one (after home) that
+ * has entries or room to grow; give up only when a scan finds every shard
+ * without entries, without room and without holds in flight.  Returns this
+ * lane's page offset or kNoPage. */
+__device__ __forceinline__ uint64_t alloc_group(const hbheap_dev_t& h, uint32_t k, uint64_t grp, uint64_t* stage,
+                                                Tally& tl)
+{
+    const Group g = make_group(h, k, grp);
+    const bool chunk = h.variant == HBHEAP_VARIANT_CHUNK;
+    if (chunk) {
+        stage[g.arank] = kNoPage;
+        wave_sync_lds();
+    }
+    uint64_t off = kNoPage;
+    uint32_t need = (uint32_t)__popcll(grp), served = 0;
+    const uint32_t S = h.n_shards;
+    const uint32_t home = home_shard(h);
+    if (chunk) chunk_serve_shard(h, g, home, need, served, stage, tl);
+    else page_serve_shard(h, g, home, need, served, off, tl);
+    Backoff wb;
+    bool timed_out = false;
+    while (need > 0) {
+        bool busy = false;
+        const uint32_t r = scan_shards(h, g, home, &busy);
+        if (r == S && !busy) break; /* every shard empty for this class: out of memory */
+        if (r < S) {
+            const uint32_t j = home + r < S ? home + r : home + r - S;
+            const uint32_t before = need;
+            if (chunk) chunk_serve_shard(h, g, j, need, served, stage, tl);
+            else page_serve_shard(h, g, j, need, served, off, tl);
+            if (need < before) continue;
+        }
+        /* holds in flight, or the shard was drained under us: wait, bounded */
+        if (g.me == g.leader) a_add64(h.stats + HBHEAP_STAT_OOM_WAITS, 1);
+        if (!wb.wait(h)) {
+            timed_out = true;
+            break;
         }
     }
-    if (need > 0 && me == leader) a_add64(h.stats + HBHEAP_STAT_OOM, need);
-    return req ? off : kNoPage;
+    if (need > 0 && g.me == g.leader) {
+        if (timed_out) raise_err(h, HBHEAP_ERR_TIMEOUT, HBHEAP_STAT_TIMEOUTS);
+        a_add64(h.stats + HBHEAP_STAT_OOM, need);
+    }
+    if (chunk) {
+        wave_sync_lds();
+        off = g.req ? stage[g.qrank] : kNoPage;
+        wave_sync_lds();
+    }
+    return g.req ? off : kNoPage;
 }
 
 /* ---------------- wave entry points ---------------- */
@@ -657,8 +828,7 @@ __device__ __forceinline__ void* malloc_wave(const hbheap_dev_t& h, uint64_t n)
             const uint32_t seg = leader & ~(h.width - 1u);
             grp &= ((1ull << h.width) - 1ull) << seg;
         }
-        const uint64_t o = h.variant == HBHEAP_VARIANT_CHUNK ? alloc_group_chunk(h, kk, grp, stage, tl)
-                                                              : alloc_group_page(h, kk, grp, tl);
+        const uint64_t o = alloc_group(h, kk, grp, stage, tl);
         if ((grp >> me) & 1ull) off = o;
         pending &= ~grp;
     }
@@ -673,36 +843,96 @@ __device__ __forceinline__ uint32_t free_wave(const hbheap_dev_t& h, void* p, ui
 {
     const uint32_t me = lane();
     uint32_t status = kFreeNull;
-    bool enq = false;
+    bool enq = false, cand = false;
     Tally tl;
-    uint32_t val = 0, k = 0;
+    uint32_t val = 0, key = 0, k = 0;
+    uint64_t c = 0, widx = 0, bit = 0, o = 0;
     if (p != nullptr) {
         status = kFreeInvalid;
-        const uint64_t o = (uint64_t)((uint8_t*)p - h.data);
+        o = (uint64_t)((uint8_t*)p - h.data);
         if ((uint8_t*)p >= h.data && o < h.data_bytes) {
-            const uint64_t c = o >> h.log2_chunk;
+            c = o >> h.log2_chunk;
             k = h.chunk_class[c];
             const uint32_t shift = 4u + k;
             bool ok = k < h.n_classes && (o & ((1ull << shift) - 1ull)) == 0;
             if (ok && check_size) ok = class_of(h, size_hint) == (int)k;
             if (ok) {
                 const uint32_t pg = (uint32_t)((o & ((1ull << h.log2_chunk) - 1ull)) >> shift);
-                const uint64_t bit = 1ull << (pg & 63u);
-                const uint64_t old = a_or64(h.bits + c * h.words_per_chunk + (pg >> 6), bit);
+                widx = c * h.words_per_chunk + (pg >> 6);
+                bit = 1ull << (pg & 63u);
+                key = shard_of_chunk(h, c) * h.n_classes + k;
+                cand = true;
+            }
+        }
+    }
+    /* Set the free bits.  Lanes freeing pages of the same bitmask word are
+     * combined: their bits are OR-ed in LDS (which also finds the same page
+     * twice in one call), the group's leader sets them with one atomicOr and,
+     * in the chunk variant, raises the chunk's count once by the number of
+     * newly set bits.  Once a group of fewer than 4 lanes shows up, the rest
+     * set their bits one lane at a time. */
+    uint64_t todo = __ballot(cand);
+    uint64_t* acc = stage_for_wave();
+    bool first_round = true;
+    while (todo) {
+        const uint32_t leader = ctz64(todo);
+        const uint64_t wkey = bcast64(widx, leader);
+        uint64_t grp = __ballot(cand && widx == wkey) & todo;
+        if (h.width < 64u) {
+            const uint32_t seg = leader & ~(h.width - 1u);
+            grp &= ((1ull << h.width) - 1ull) << seg;
+        }
+        if (!first_round && __popcll(grp) < 4) break;
+        first_round = false;
+        if (me == leader) *acc = 0;
+        wave_sync_lds();
+        bool dup = false;
+        if ((grp >> me) & 1ull)
+            dup = (__hip_atomic_fetch_or(acc, bit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) & bit) != 0;
+        wave_sync_lds();
+        uint64_t old = 0;
+        uint32_t cold = 1, nnew = 0;
+        if (me == leader) {
+            const uint64_t m = *acc;
+            old = a_or64(h.bits + widx, m);
+            nnew = (uint32_t)__popcll(m & ~old);
+            tl.spread += 1;
+            if (h.variant == HBHEAP_VARIANT_CHUNK && nnew) {
+                cold = (uint32_t)a_addi(h.chunk_cnt + c, (int32_t)nnew);
                 tl.spread += 1;
-                if (old & bit) {
-                    status = kFreeDouble;
-                } else {
-                    status = kFreeOk;
-                    if (h.variant == HBHEAP_VARIANT_CHUNK) {
-                        enq = a_addi(h.chunk_cnt + c, 1) == 0;
-                        tl.spread += 1;
-                        val = (uint32_t)c;
-                    } else {
-                        enq = true;
-                        val = (uint32_t)(o >> 4);
-                    }
-                }
+            }
+        }
+        wave_sync_lds();
+        old = bcast64(old, leader);
+        cold = bcast(cold, leader);
+        nnew = bcast(nnew, leader);
+        if ((grp >> me) & 1ull) {
+            status = (dup || (old & bit)) ? kFreeDouble : kFreeOk;
+            if (h.variant == HBHEAP_VARIANT_CHUNK) {
+                /* the chunk's count left zero: the group enqueues it once */
+                enq = me == leader && nnew > 0 && cold == 0;
+                val = (uint32_t)c;
+            } else {
+                enq = status == kFreeOk;
+                val = (uint32_t)(o >> 4);
+            }
+        }
+        todo &= ~grp;
+    }
+    if ((todo >> me) & 1ull) {
+        const uint64_t old = a_or64(h.bits + widx, bit);
+        tl.spread += 1;
+        if (old & bit) {
+            status = kFreeDouble;
+        } else {
+            status = kFreeOk;
+            if (h.variant == HBHEAP_VARIANT_CHUNK) {
+                enq = a_addi(h.chunk_cnt + c, 1) == 0;
+                tl.spread += 1;
+                val = (uint32_t)c;
+            } else {
+                enq = true;
+                val = (uint32_t)(o >> 4);
             }
         }
     }
@@ -712,18 +942,18 @@ __device__ __forceinline__ uint32_t free_wave(const hbheap_dev_t& h, void* p, ui
         if (dbl) { a_or32(h.err, HBHEAP_ERR_DOUBLE_FREE); a_add64(h.stats + HBHEAP_STAT_DOUBLE_FREE, (uint64_t)__popcll(dbl)); }
         if (inv) { a_or32(h.err, HBHEAP_ERR_INVALID_FREE); a_add64(h.stats + HBHEAP_STAT_INVALID_FREE, (uint64_t)__popcll(inv)); }
     }
-    /* aggregated enqueue by class */
+    /* aggregated enqueue by (shard, class) */
     uint64_t pend = __ballot(enq);
     while (pend) {
         const uint32_t leader = ctz64(pend);
-        const uint32_t kk = bcast(k, leader);
-        uint64_t grp = __ballot(enq && k == kk) & pend;
+        const uint32_t kk = bcast(key, leader);
+        uint64_t grp = __ballot(enq && key == kk) & pend;
         if (h.width < 64u) {
             const uint32_t seg = leader & ~(h.width - 1u);
             grp &= ((1ull << h.width) - 1ull) << seg;
         }
         const uint32_t n = (uint32_t)__popcll(grp);
-        const Ring R = ring_of(h, kk);
+        const Ring R = ring_of(h, kk / h.n_classes, kk % h.n_classes);
         uint32_t t0 = 0;
         if (me == leader) {
             t0 = a_add32(R.tail, n);
@@ -745,7 +975,7 @@ __device__ __forceinline__ uint32_t free_wave(const hbheap_dev_t& h, void* p, ui
 }  // namespace hbheap
 
 /* Allocate n bytes from the heap; NULL when n == 0, n exceeds the chunk
- * size, or no page of the class and no chunk is left. */
+ * size, or no page of the class and no chunk is left in any shard. */
 __device__ __forceinline__ void* dev_malloc(hbheap_dev_t h, size_t n)
 {
     return hbheap::detail::malloc_wave(h, (uint64_t)n);

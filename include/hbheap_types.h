@@ -65,13 +65,14 @@ extern "C" {
 typedef struct hbheap_dev {
     uint8_t*  data;            /* data region: n_chunks * 2^log2_chunk bytes  */
     uint8_t*  state;           /* state region (snapshot layout, version 1)  */
-    uint64_t* pool;            /* [0] bump (u64); [1] low 32 bits: size      */
-    uint8_t*  classes;         /* n_classes control blocks of 384 bytes      */
+    uint64_t* pool;            /* n_shards pool blocks of 128 bytes: u64 bump,
+                                  u32 size, u32 first index into pool_ids    */
+    uint8_t*  classes;         /* n_shards * n_classes blocks of 512 bytes   */
     uint8_t*  chunk_class;     /* class of each chunk, 0xFF when unowned     */
     int32_t*  chunk_cnt;       /* free pages per chunk (chunk variant)       */
     uint64_t* bits;            /* words_per_chunk words per chunk, 1 = free  */
     uint32_t* pool_ids;        /* ids of unowned chunks, consumed by bump    */
-    uint32_t* slots;           /* n_classes rings of 2^log2q u32 entries     */
+    uint32_t* slots;           /* n_shards * n_classes rings of 2^log2q u32  */
     uint32_t* err;             /* sticky error word                          */
     uint64_t* stats;           /* HBHEAP_STAT_COUNT counters                 */
     uint64_t  data_bytes;
@@ -80,11 +81,14 @@ typedef struct hbheap_dev {
     uint32_t  n_classes;       /* log2_chunk - 3: pages 16 B .. chunk        */
     uint32_t  variant;
     uint32_t  words_per_chunk; /* chunk / 1024                               */
-    uint32_t  log2q;           /* ring capacity per class, log2              */
+    uint32_t  log2q;           /* capacity of each (shard, class) ring, log2 */
     uint32_t  width;           /* aggregation width: 1, 16, 32 or 64 lanes   */
     uint32_t  spin_cap;        /* bounded-wait iterations before TIMEOUT     */
     uint32_t  backoff_max;     /* largest s_sleep backoff, in s_sleep(1)s    */
     uint32_t  flags;           /* HBHEAP_FLAG_* bits                         */
+    uint32_t  n_shards;        /* shards; shard j owns chunks
+                                  [j << log2_span, (j+1) << log2_span)       */
+    uint32_t  log2_span;
 } hbheap_dev_t;
 
 /* Count refills, chunk grabs and atomics by target in the statistics

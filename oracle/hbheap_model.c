@@ -286,7 +286,7 @@ static void check_final(ctx* x, const mstate* s)
  *  12 refill init  13 refill tail  14 refill put  15 release  16 oom decide
  *  alloc, page variant:
  *  21 reserve  22 refund  23 head  24 take slot(i)  25 clear bit(i)
- *  26 owned add  27 pool  28 owned refund  29 refill init  30 refill tail
+ *  26 owned reserve (CAS)  27 pool  28 owned give-back  29 refill init  30 refill tail
  *  31 refill put(i)  32 release  33 oom decide
  *  free (both):
  *  40 set bit(i)  41 count add(i)  42 tail add  43 put slot(i)  44 publish
@@ -595,9 +595,10 @@ static int step(ctx* x, mstate* s, int l)
         L->m = (uint8_t)((L->need + P - 1) / P);
         if (s->bump >= N) { L->gm = 0; L->exhausted = 1; L->pc = 32; return 1; }
         {
+            /* reserve room under the cap with compare-and-swap: never above it */
             int o = s->owned;
-            s->owned = (uint8_t)(s->owned + L->m);
             int allow = o >= x->p->maxc ? 0 : (x->p->maxc - o < L->m ? x->p->maxc - o : L->m);
+            s->owned = (uint8_t)(s->owned + allow);
             L->t0 = (uint8_t)allow;
         }
         L->pc = 27;
@@ -612,11 +613,12 @@ static int step(ctx* x, mstate* s, int l)
         }
         L->gm = (uint8_t)gm;
         L->exhausted = (uint8_t)(gm < L->m);
-        L->pc = gm < L->m ? 28 : 29;
+        L->pc = gm < allow ? 28 : 29;
         return 1;
     }
     case 28:
-        s->owned = (uint8_t)(s->owned - (L->m - L->gm));
+        /* the pool ran dry: give back the room not used */
+        s->owned = (uint8_t)(s->owned - (L->t0 - L->gm));
         L->pc = 29;
         return 1;
     case 29: {

@@ -64,19 +64,39 @@ int orc_class_of(uint64_t n, uint64_t chunk_bytes)
     return (int)k;
 }
 
-/* Page-variant queue budget: bytes/8 of 4-byte entries split evenly over the
- * K classes, rounded down to a power of two. */
-uint64_t orc_page_ring_entries(uint64_t bytes, uint64_t chunk_bytes)
+/* Shards: runs of 2^log2_span consecutive chunks, as many as needed to
+ * cover N; the span is the smallest power of two >= ceil(N / requested).
+ * requested == 0: one shard per 256 chunks, doubling up to 64. */
+void orc_shard_geometry(uint64_t n_chunks, uint32_t requested, uint32_t* shards, uint32_t* log2_span)
 {
-    uint64_t per = bytes / 8 / orc_num_classes(chunk_bytes) / 4;
+    uint64_t want = requested;
+    if (want == 0) {
+        want = 1;
+        while (want < 64 && want * 2 * 256 <= n_chunks) want *= 2;
+    }
+    if (want > n_chunks) want = n_chunks;
+    uint64_t per = (n_chunks + want - 1) / want;
+    uint32_t l = 0;
+    while ((1ull << l) < per) ++l;
+    *log2_span = l;
+    *shards = (uint32_t)((n_chunks + (1ull << l) - 1) >> l);
+}
+
+/* Page-variant queue budget: bytes/8 of 4-byte entries split evenly over the
+ * K classes of each of the S shards, rounded down to a power of two (at
+ * least one entry). */
+uint64_t orc_page_ring_entries(uint64_t bytes, uint64_t chunk_bytes, uint32_t shards)
+{
+    uint64_t per = bytes / 8 / orc_num_classes(chunk_bytes) / 4 / shards;
     uint64_t p = 1;
     while (p * 2 <= per) p *= 2;
     return p;
 }
 
-uint64_t orc_page_max_chunks(uint64_t bytes, uint64_t chunk_bytes, uint32_t k)
+/* Chunks one class may own in one shard (page variant). */
+uint64_t orc_page_max_chunks(uint64_t bytes, uint64_t chunk_bytes, uint32_t k, uint32_t shards)
 {
-    return orc_page_ring_entries(bytes, chunk_bytes) / orc_pages_per_chunk(chunk_bytes, k);
+    return orc_page_ring_entries(bytes, chunk_bytes, shards) / orc_pages_per_chunk(chunk_bytes, k);
 }
 
 /* ------------------------------------------------------------------ */
@@ -136,6 +156,20 @@ static int64_t hset_lowest(const hset* s)
     return (int64_t)i;
 }
 
+/* lowest set index >= from at level l (level 0 = the bits themselves) */
+static int64_t hset_next_at(const hset* s, int l, uint64_t from)
+{
+    uint64_t nbits = l == 0 ? s->n : s->words[l - 1];
+    if (from >= nbits) return -1;
+    uint64_t w = from >> 6;
+    uint64_t x = s->lv[l][w] & (~0ull << (from & 63));
+    if (x) return (int64_t)(w * 64 + (uint64_t)__builtin_ctzll(x));
+    if (l + 1 >= s->levels) return -1;
+    int64_t nw = hset_next_at(s, l + 1, w + 1);
+    if (nw < 0) return -1;
+    return (int64_t)((uint64_t)nw * 64 + (uint64_t)__builtin_ctzll(s->lv[l][nw]));
+}
+
 /* growable FIFO of u64 */
 typedef struct { uint64_t* a; uint64_t cap, head, len; } fifo;
 static void fifo_init(fifo* q) { q->cap = 16; q->a = (uint64_t*)malloc(16 * 8); q->head = q->len = 0; }
@@ -168,41 +202,54 @@ static void fifo_clear(fifo* q) { q->head = q->len = 0; }
 
 struct orc_heap {
     uint64_t bytes, C, N;
-    uint32_t log2C, K, W;
+    uint32_t log2C, K, W, S, log2_span;
     int variant, policy;
     uint8_t*  cls;        /* class of each chunk, FREE_CLASS if unowned     */
     uint32_t* cnt;        /* free pages in each owned chunk                  */
     uint64_t* bits;       /* N*W words, bit set = page free                  */
-    uint64_t  maxc[ORC_MAX_CLASSES];
-    uint64_t  owned[ORC_MAX_CLASSES];
+    uint64_t  maxc[ORC_MAX_CLASSES];  /* chunks a class may own per shard    */
+    uint64_t* owned;      /* S*K: chunks owned per (shard, class)            */
     orc_acct  acct;
     /* LOWEST policy */
     hset free_set;                    /* unowned chunks                      */
     hset avail[ORC_MAX_CLASSES];      /* owned chunks with a free page       */
-    /* FIFO policy */
-    uint32_t* pool; uint64_t pool_size, pool_next;
-    fifo q[ORC_MAX_CLASSES];          /* chunk ids (chunk variant) or page offsets (page variant) */
+    /* FIFO policy: per shard a pool segment consumed in order, per (shard,
+     * class) a queue of chunk ids (chunk variant) or page offsets (page) */
+    uint32_t* pool;
+    uint64_t* pool_size;
+    uint64_t* pool_next;
+    fifo* q;
 };
 
 static uint64_t ppc_of(const orc_heap* h, uint32_t k) { return h->C >> (4 + k); }
+static uint32_t shard_of(const orc_heap* h, uint64_t c) { return (uint32_t)(c >> h->log2_span); }
+static uint64_t shard_first(const orc_heap* h, uint32_t j) { return (uint64_t)j << h->log2_span; }
+static uint64_t shard_end(const orc_heap* h, uint32_t j)
+{
+    uint64_t e = ((uint64_t)j + 1) << h->log2_span;
+    return e < h->N ? e : h->N;
+}
 
-orc_heap* orc_create(uint64_t bytes, uint64_t chunk_bytes, int variant, int policy)
+orc_heap* orc_create_ex(uint64_t bytes, uint64_t chunk_bytes, int variant, int policy, uint32_t shards)
 {
     if (!orc_geometry_ok(bytes, chunk_bytes)) return NULL;
     if (variant != ORC_VARIANT_CHUNK && variant != ORC_VARIANT_PAGE) return NULL;
     if (policy != ORC_POLICY_LOWEST && policy != ORC_POLICY_FIFO) return NULL;
+    if (shards > 64 || (shards & (shards - 1))) return NULL;
     orc_heap* h = (orc_heap*)calloc(1, sizeof(orc_heap));
     h->bytes = bytes; h->C = chunk_bytes; h->N = bytes / chunk_bytes;
     h->log2C = (uint32_t)ilog2_u64(chunk_bytes);
     h->K = orc_num_classes(chunk_bytes);
     h->W = (uint32_t)(chunk_bytes / 16 / 64);
     h->variant = variant; h->policy = policy;
+    orc_shard_geometry(h->N, shards, &h->S, &h->log2_span);
     h->cls = (uint8_t*)malloc(h->N);
     memset(h->cls, FREE_CLASS, h->N);
     h->cnt = (uint32_t*)calloc(h->N, 4);
     h->bits = (uint64_t*)calloc(h->N * h->W, 8);
+    h->owned = (uint64_t*)calloc((uint64_t)h->S * h->K, 8);
     for (uint32_t k = 0; k < h->K; ++k)
-        h->maxc[k] = variant == ORC_VARIANT_PAGE ? orc_page_max_chunks(bytes, chunk_bytes, k) : h->N;
+        h->maxc[k] = variant == ORC_VARIANT_PAGE ? orc_page_max_chunks(bytes, chunk_bytes, k, h->S) : h->N;
     h->acct.n_classes = h->K;
     h->acct.n_chunks = h->N;
     h->acct.free_chunks = h->N;
@@ -213,11 +260,21 @@ orc_heap* orc_create(uint64_t bytes, uint64_t chunk_bytes, int variant, int poli
     } else {
         h->pool = (uint32_t*)malloc(h->N * 4);
         for (uint64_t c = 0; c < h->N; ++c) h->pool[c] = (uint32_t)c;
-        h->pool_size = h->N; h->pool_next = 0;
-        for (uint32_t k = 0; k < h->K; ++k) fifo_init(&h->q[k]);
+        h->pool_size = (uint64_t*)calloc(h->S, 8);
+        h->pool_next = (uint64_t*)calloc(h->S, 8);
+        for (uint32_t j = 0; j < h->S; ++j) h->pool_size[j] = shard_end(h, j) - shard_first(h, j);
+        h->q = (fifo*)calloc((uint64_t)h->S * h->K, sizeof(fifo));
+        for (uint64_t i = 0; i < (uint64_t)h->S * h->K; ++i) fifo_init(&h->q[i]);
     }
     return h;
 }
+
+orc_heap* orc_create(uint64_t bytes, uint64_t chunk_bytes, int variant, int policy)
+{
+    return orc_create_ex(bytes, chunk_bytes, variant, policy, 1);
+}
+
+uint32_t orc_shards(const orc_heap* h) { return h->S; }
 
 void orc_destroy(orc_heap* h)
 {
@@ -226,10 +283,11 @@ void orc_destroy(orc_heap* h)
         hset_free(&h->free_set);
         for (uint32_t k = 0; k < h->K; ++k) hset_free(&h->avail[k]);
     } else {
-        free(h->pool);
-        for (uint32_t k = 0; k < h->K; ++k) fifo_free(&h->q[k]);
+        free(h->pool); free(h->pool_size); free(h->pool_next);
+        for (uint64_t i = 0; i < (uint64_t)h->S * h->K; ++i) fifo_free(&h->q[i]);
+        free(h->q);
     }
-    free(h->cls); free(h->cnt); free(h->bits); free(h);
+    free(h->cls); free(h->cnt); free(h->bits); free(h->owned); free(h);
 }
 
 static int bit_get(const orc_heap* h, uint64_t c, uint64_t p) { return (int)((h->bits[c * h->W + (p >> 6)] >> (p & 63)) & 1); }
@@ -257,12 +315,14 @@ static void claim_fresh(orc_heap* h, uint64_t c, uint32_t k)
     h->cls[c] = (uint8_t)k;
     for (uint64_t p = 1; p < ppc; ++p) bit_set(h, c, p);
     h->cnt[c] = (uint32_t)(ppc - 1);
-    h->owned[k]++;
+    h->owned[(uint64_t)shard_of(h, c) * h->K + k]++;
     h->acct.free_chunks--;
     h->acct.chunks[k]++;
     h->acct.free_pages[k] += ppc - 1;
     h->acct.live[k]++;
 }
+
+static int can_grow(const orc_heap* h, uint32_t j, uint32_t k) { return h->owned[(uint64_t)j * h->K + k] < h->maxc[k]; }
 
 static int64_t alloc_lowest(orc_heap* h, uint32_t k)
 {
@@ -274,45 +334,54 @@ static int64_t alloc_lowest(orc_heap* h, uint32_t k)
         h->acct.free_pages[k]--; h->acct.live[k]++;
         return offset_of(h, (uint64_t)c, k, (uint64_t)p);
     }
-    if (h->owned[k] >= h->maxc[k]) return -1;
-    c = hset_lowest(&h->free_set);
-    if (c < 0) return -1;
-    hset_clear(&h->free_set, (uint64_t)c);
-    claim_fresh(h, (uint64_t)c, k);
-    if (h->cnt[c] > 0) hset_set(&h->avail[k], (uint64_t)c);
-    return offset_of(h, (uint64_t)c, k, 0);
+    /* lowest unowned chunk in a shard where the class may still grow */
+    for (uint32_t j = 0; j < h->S; ++j) {
+        if (!can_grow(h, j, k)) continue;
+        c = hset_next_at(&h->free_set, 0, shard_first(h, j));
+        if (c < 0) return -1;
+        if ((uint64_t)c >= shard_end(h, j)) { j = shard_of(h, (uint64_t)c) - 1; continue; }
+        hset_clear(&h->free_set, (uint64_t)c);
+        claim_fresh(h, (uint64_t)c, k);
+        if (h->cnt[c] > 0) hset_set(&h->avail[k], (uint64_t)c);
+        return offset_of(h, (uint64_t)c, k, 0);
+    }
+    return -1;
 }
 
+/* One device lane alone: its home shard is shard 0; each shard is tried in
+ * order, its queue first, then its pool. */
 static int64_t alloc_fifo(orc_heap* h, uint32_t k)
 {
-    fifo* q = &h->q[k];
-    if (q->len) {
-        if (h->variant == ORC_VARIANT_CHUNK) {
-            uint64_t c = fifo_pop(q);
-            int64_t p = lowest_free_page(h, c);
-            bit_clr(h, c, (uint64_t)p);
-            if (--h->cnt[c] > 0) fifo_push(q, c);
-            h->acct.free_pages[k]--; h->acct.live[k]++;
-            return offset_of(h, c, k, (uint64_t)p);
-        } else {
-            uint64_t off = fifo_pop(q);
-            uint64_t c = off >> h->log2C, p = (off & (h->C - 1)) / orc_page_bytes(k);
-            bit_clr(h, c, p);
-            h->cnt[c]--;
-            h->acct.free_pages[k]--; h->acct.live[k]++;
-            return (int64_t)off;
+    for (uint32_t j = 0; j < h->S; ++j) {
+        fifo* q = &h->q[(uint64_t)j * h->K + k];
+        if (q->len) {
+            if (h->variant == ORC_VARIANT_CHUNK) {
+                uint64_t c = fifo_pop(q);
+                int64_t p = lowest_free_page(h, c);
+                bit_clr(h, c, (uint64_t)p);
+                if (--h->cnt[c] > 0) fifo_push(q, c);
+                h->acct.free_pages[k]--; h->acct.live[k]++;
+                return offset_of(h, c, k, (uint64_t)p);
+            } else {
+                uint64_t off = fifo_pop(q);
+                uint64_t c = off >> h->log2C, p = (off & (h->C - 1)) / orc_page_bytes(k);
+                bit_clr(h, c, p);
+                h->cnt[c]--;
+                h->acct.free_pages[k]--; h->acct.live[k]++;
+                return (int64_t)off;
+            }
         }
+        if (!can_grow(h, j, k) || h->pool_next[j] >= h->pool_size[j]) continue;
+        uint64_t c = h->pool[shard_first(h, j) + h->pool_next[j]++];
+        claim_fresh(h, c, k);
+        if (h->variant == ORC_VARIANT_CHUNK) {
+            if (h->cnt[c] > 0) fifo_push(q, c);
+        } else {
+            for (uint64_t p = 1; p < ppc_of(h, k); ++p) fifo_push(q, (uint64_t)offset_of(h, c, k, p));
+        }
+        return offset_of(h, c, k, 0);
     }
-    if (h->owned[k] >= h->maxc[k]) return -1;
-    if (h->pool_next >= h->pool_size) return -1;
-    uint64_t c = h->pool[h->pool_next++];
-    claim_fresh(h, c, k);
-    if (h->variant == ORC_VARIANT_CHUNK) {
-        if (h->cnt[c] > 0) fifo_push(q, c);
-    } else {
-        for (uint64_t p = 1; p < ppc_of(h, k); ++p) fifo_push(q, (uint64_t)offset_of(h, c, k, p));
-    }
-    return offset_of(h, c, k, 0);
+    return -1;
 }
 
 int64_t orc_alloc(orc_heap* h, uint64_t n)
@@ -341,16 +410,19 @@ int orc_free(orc_heap* h, int64_t off)
     h->acct.free_pages[k]++; h->acct.live[k]--; h->acct.n_free_ok++;
     if (h->policy == ORC_POLICY_LOWEST) {
         if (was == 0) hset_set(&h->avail[k], c);
-    } else if (h->variant == ORC_VARIANT_CHUNK) {
-        if (was == 0) fifo_push(&h->q[k], c);
     } else {
-        fifo_push(&h->q[k], o);
+        fifo* q = &h->q[(uint64_t)shard_of(h, c) * h->K + k];
+        if (h->variant == ORC_VARIANT_CHUNK) {
+            if (was == 0) fifo_push(q, c);
+        } else {
+            fifo_push(q, o);
+        }
     }
     return ORC_FREE_OK;
 }
 
 /* Quiescent trim: chunks whose pages are all free go back to the pool; the
- * pool and the class queues are rebuilt in ascending order. */
+ * pool segments and the queues are rebuilt in ascending order. */
 void orc_trim(orc_heap* h)
 {
     for (uint64_t c = 0; c < h->N; ++c) {
@@ -360,7 +432,7 @@ void orc_trim(orc_heap* h)
         for (uint32_t w = 0; w < h->W; ++w) h->bits[c * h->W + w] = 0;
         h->cnt[c] = 0;
         h->cls[c] = FREE_CLASS;
-        h->owned[k]--;
+        h->owned[(uint64_t)shard_of(h, c) * h->K + k]--;
         h->acct.chunks[k]--;
         h->acct.free_pages[k] -= ppc_of(h, k);
         h->acct.free_chunks++;
@@ -370,18 +442,21 @@ void orc_trim(orc_heap* h)
         }
     }
     if (h->policy == ORC_POLICY_FIFO) {
-        h->pool_size = 0; h->pool_next = 0;
-        for (uint64_t c = 0; c < h->N; ++c)
-            if (h->cls[c] == FREE_CLASS) h->pool[h->pool_size++] = (uint32_t)c;
-        for (uint32_t k = 0; k < h->K; ++k) fifo_clear(&h->q[k]);
+        for (uint32_t j = 0; j < h->S; ++j) {
+            h->pool_size[j] = 0; h->pool_next[j] = 0;
+            for (uint64_t c = shard_first(h, j); c < shard_end(h, j); ++c)
+                if (h->cls[c] == FREE_CLASS) h->pool[shard_first(h, j) + h->pool_size[j]++] = (uint32_t)c;
+        }
+        for (uint64_t i = 0; i < (uint64_t)h->S * h->K; ++i) fifo_clear(&h->q[i]);
         for (uint64_t c = 0; c < h->N; ++c) {
             if (h->cls[c] == FREE_CLASS || h->cnt[c] == 0) continue;
             uint32_t k = h->cls[c];
+            fifo* q = &h->q[(uint64_t)shard_of(h, c) * h->K + k];
             if (h->variant == ORC_VARIANT_CHUNK) {
-                fifo_push(&h->q[k], c);
+                fifo_push(q, c);
             } else {
                 for (uint64_t p = 0; p < ppc_of(h, k); ++p)
-                    if (bit_get(h, c, p)) fifo_push(&h->q[k], (uint64_t)offset_of(h, c, k, p));
+                    if (bit_get(h, c, p)) fifo_push(q, (uint64_t)offset_of(h, c, k, p));
             }
         }
     }
@@ -479,22 +554,26 @@ int orc_check_blocks(uint64_t data_bytes, uint64_t chunk_bytes, const uint64_t* 
 }
 
 /* ------------------------------------------------------------------ */
-/* invariant checker: snapshot (layout version 1)                      */
+/* invariant checker: snapshot (layout version 2)                      */
 /*                                                                     */
 /* header (256 B, little-endian):                                      */
-/*   0 u32 magic 0x48424850   4 u32 version 1     8 u64 data_bytes     */
+/*   0 u32 magic 0x48424850   4 u32 version 2     8 u64 data_bytes     */
 /*  16 u32 n_chunks          20 u32 log2_chunk   24 u32 n_classes      */
 /*  28 u32 variant           32 u32 words/chunk  36 u32 log2 ring cap  */
-/*  40 u64 reserved (0)      48 u64 off pool     56 u64 off classes    */
-/*  64 u64 off chunk_class   72 u64 off chunk_cnt 80 u64 off bits      */
-/*  88 u64 off pool_ids      96 u64 off slots    104 u64 total bytes   */
-/* pool block (128 B): u64 bump, u32 size                              */
-/* class block k (512 B): u64 state (H<<32 | C+2^31), u32 head at     */
-/*   +128, u32 tail at +256, u64 owned at +384                         */
+/*  40 u32 shards S          44 u32 log2 span    48 u64 off pools      */
+/*  56 u64 off classes       64 u64 off chunk_class                    */
+/*  72 u64 off chunk_cnt     80 u64 off bits     88 u64 off pool_ids   */
+/*  96 u64 off slots        104 u64 total bytes                        */
+/* shard j owns chunks [j << span, (j+1) << span) (last one shorter)   */
+/* pool block j (128 B): u64 bump, u32 size, u32 first pool index      */
+/* class block (j, k) at index j*K + k (512 B): u64 state              */
+/*   (H<<32 | C+2^31), u32 head at +128, u32 tail at +256, u64 owned   */
+/*   at +384                                                           */
 /* chunk_class u8[N] (0xFF unowned), chunk_cnt u32[N], bits u64[N*W],  */
-/* pool_ids u32[N], slots u32[K << log2 ring cap] (0xFFFFFFFF empty);  */
-/* page-variant slots hold the page's byte offset / 16; a page-variant */
-/* class may own at most (ring entries / pages per chunk) chunks.       */
+/* pool_ids u32[N], slots u32[S*K << log2 ring cap] (0xFFFFFFFF empty) */
+/* ring (j, k) at slot index (j*K + k) << log2 ring cap; page-variant  */
+/* slots hold the page's byte offset / 16; a page-variant class may    */
+/* own at most (ring entries / pages per chunk) chunks of one shard.   */
 /* ------------------------------------------------------------------ */
 
 #define SNAP_MAGIC 0x48424850u
@@ -505,21 +584,24 @@ static uint64_t rd64(const uint8_t* p) { uint64_t v; memcpy(&v, p, 8); return v;
 
 typedef struct {
     uint64_t data_bytes, N;
-    uint32_t log2C, K, variant, W, log2q;
+    uint32_t log2C, K, variant, W, log2q, S, log2_span;
     const uint8_t *pool, *classes, *cls, *cnt, *bits, *pool_ids, *slots;
 } snapview;
 
 static int snap_open(const uint8_t* s, uint64_t len, snapview* v)
 {
-    if (len < 256 || rd32(s) != SNAP_MAGIC || rd32(s + 4) != 1) return 0;
+    if (len < 256 || rd32(s) != SNAP_MAGIC || rd32(s + 4) != 2) return 0;
     v->data_bytes = rd64(s + 8);
     v->N = rd32(s + 16); v->log2C = rd32(s + 20); v->K = rd32(s + 24);
     v->variant = rd32(s + 28); v->W = rd32(s + 32); v->log2q = rd32(s + 36);
+    v->S = rd32(s + 40); v->log2_span = rd32(s + 44);
     uint64_t o_pool = rd64(s + 48), o_cl = rd64(s + 56), o_cls = rd64(s + 64), o_cnt = rd64(s + 72);
     uint64_t o_bits = rd64(s + 80), o_pid = rd64(s + 88), o_sl = rd64(s + 96), total = rd64(s + 104);
     if (total > len || v->K == 0 || v->K > ORC_MAX_CLASSES || v->log2C < 12 || v->log2C > 16) return 0;
     if (v->W != (1u << v->log2C) / 1024 || v->data_bytes != (v->N << v->log2C)) return 0;
-    if (o_sl + ((uint64_t)v->K << v->log2q) * 4 > total) return 0;
+    if (v->S == 0 || v->log2_span > 31 || ((uint64_t)v->S << v->log2_span) < v->N ||
+        ((uint64_t)(v->S - 1) << v->log2_span) >= v->N) return 0;
+    if (o_sl + (((uint64_t)v->S * v->K) << v->log2q) * 4 > total) return 0;
     v->pool = s + o_pool; v->classes = s + o_cl; v->cls = s + o_cls; v->cnt = s + o_cnt;
     v->bits = s + o_bits; v->pool_ids = s + o_pid; v->slots = s + o_sl;
     return 1;
@@ -542,14 +624,18 @@ int orc_check_snapshot(const uint8_t* snap, uint64_t len, orc_snap_report* rep)
     rep->ok_header = 1;
     rep->n_classes = v.K;
     const uint64_t C = 1ull << v.log2C;
-    uint64_t Q = 1ull << v.log2q;
+    const uint64_t Q = 1ull << v.log2q;
+    uint64_t* chunks_sk = (uint64_t*)calloc((uint64_t)v.S * v.K, 8);
+    uint64_t* free_s = (uint64_t*)calloc(v.S, 8);
 
     /* per chunk: class byte, stray bits beyond the class's pages, counts */
     for (uint64_t c = 0; c < v.N; ++c) {
         uint8_t k = v.cls[c];
         uint32_t cn = rd32(v.cnt + c * 4);
+        uint32_t j = (uint32_t)(c >> v.log2_span);
         if (k == 0xFF) {
             rep->free_chunks++;
+            free_s[j]++;
             if (cn != 0 || popc_chunk(&v, c) != 0) rep->bad_free_chunk++;
             continue;
         }
@@ -564,79 +650,90 @@ int orc_check_snapshot(const uint8_t* snap, uint64_t len, orc_snap_report* rep)
         uint64_t f = popc_chunk(&v, c);
         if (v.variant == 0 && cn != f) rep->bad_count++;
         rep->chunks[k]++;
+        chunks_sk[(uint64_t)j * v.K + k]++;
         rep->free_pages[k] += f;
         rep->live[k] += ppc - f;
     }
 
-    /* pool: ids[bump..size) are exactly the unowned chunks */
-    uint64_t bump = rd64(v.pool), psize = rd32(v.pool + 8);
-    uint64_t start = bump < psize ? bump : psize;
+    /* pools: shard j's ids[first+bump .. first+size) are exactly its unowned chunks */
     uint8_t* seen = (uint8_t*)calloc(v.N ? v.N : 1, 1);
-    if (psize > v.N) rep->bad_pool++;
-    else {
+    for (uint32_t j = 0; j < v.S; ++j) {
+        const uint8_t* pb = v.pool + 128ull * j;
+        uint64_t bump = rd64(pb), psize = rd32(pb + 8), first = rd32(pb + 12);
+        uint64_t lo = (uint64_t)j << v.log2_span, hi = lo + (1ull << v.log2_span);
+        if (hi > v.N) hi = v.N;
+        if (first != lo || psize > hi - lo) { rep->bad_pool++; continue; }
+        uint64_t start = bump < psize ? bump : psize;
         for (uint64_t i = start; i < psize; ++i) {
-            uint32_t c = rd32(v.pool_ids + i * 4);
-            if (c >= v.N || v.cls[c] != 0xFF || seen[c]) { rep->bad_pool++; continue; }
+            uint32_t c = rd32(v.pool_ids + (first + i) * 4);
+            if (c < lo || c >= hi || v.cls[c] != 0xFF || seen[c]) { rep->bad_pool++; continue; }
             seen[c] = 1;
         }
-        if (psize - start != rep->free_chunks) rep->bad_pool++;
+        if (psize - start != free_s[j]) rep->bad_pool++;
     }
     uint64_t sum = rep->free_chunks;
     for (uint32_t k = 0; k < v.K; ++k) sum += rep->chunks[k];
     if (sum != v.N) rep->bad_conservation++;
 
-    /* class rings */
-    for (uint32_t k = 0; k < v.K; ++k) {
-        const uint8_t* cb = v.classes + (uint64_t)k * 512;
-        uint64_t state = rd64(cb), owned = rd64(cb + 384);
-        uint32_t head = rd32(cb + 128), tail = rd32(cb + 256);
-        uint32_t H = (uint32_t)(state >> 32);
-        int64_t Cnt = (int64_t)(uint32_t)state - (int64_t)0x80000000u;
-        uint32_t used = tail - head;
-        if (H != 0 || Cnt != (int64_t)used || used > Q) { rep->bad_ring_ctl++; continue; }
-        if (v.variant == 1 && owned != rep->chunks[k]) rep->bad_owned++;
-        if (v.variant == 1 && rep->chunks[k] > (Q >> (v.log2C - 4 - k))) rep->bad_owned++;
-        const uint8_t* sl = v.slots + ((uint64_t)k << v.log2q) * 4;
-        /* slots outside [head, tail) must be empty */
-        for (uint64_t i = used; i < Q; ++i) {
-            uint32_t e = rd32(sl + ((uint64_t)((head + (uint32_t)i) & (uint32_t)(Q - 1))) * 4);
-            if (e != SLOT_EMPTY) rep->bad_ring_entry++;
-        }
-        if (v.variant == 0) {
-            memset(seen, 0, v.N);
-            for (uint32_t i = 0; i < used; ++i) {
-                uint32_t c = rd32(sl + ((uint64_t)((head + i) & (uint32_t)(Q - 1))) * 4);
-                if (c >= v.N || v.cls[c] != k || rd32(v.cnt + (uint64_t)c * 4) == 0) { rep->bad_ring_entry++; continue; }
-                if (seen[c]) { rep->bad_ring_dup++; continue; }
-                seen[c] = 1;
+    /* rings */
+    for (uint32_t j = 0; j < v.S; ++j) {
+        uint64_t lo = (uint64_t)j << v.log2_span, hi = lo + (1ull << v.log2_span);
+        if (hi > v.N) hi = v.N;
+        for (uint32_t k = 0; k < v.K; ++k) {
+            const uint64_t ring = (uint64_t)j * v.K + k;
+            const uint8_t* cb = v.classes + ring * 512;
+            uint64_t state = rd64(cb), owned = rd64(cb + 384);
+            uint32_t head = rd32(cb + 128), tail = rd32(cb + 256);
+            uint32_t H = (uint32_t)(state >> 32);
+            int64_t Cnt = (int64_t)(uint32_t)state - (int64_t)0x80000000u;
+            uint32_t used = tail - head;
+            if (H != 0 || Cnt != (int64_t)used || used > Q) { rep->bad_ring_ctl++; continue; }
+            if (v.variant == 1 && owned != chunks_sk[ring]) rep->bad_owned++;
+            if (v.variant == 1 && chunks_sk[ring] > (Q >> (v.log2C - 4 - k))) rep->bad_owned++;
+            const uint8_t* sl = v.slots + (ring << v.log2q) * 4;
+            for (uint64_t i = used; i < Q; ++i) {
+                uint32_t e = rd32(sl + ((uint64_t)((head + (uint32_t)i) & (uint32_t)(Q - 1))) * 4);
+                if (e != SLOT_EMPTY) rep->bad_ring_entry++;
             }
-            for (uint64_t c = 0; c < v.N; ++c)
-                if (v.cls[c] == k && rd32(v.cnt + c * 4) > 0 && !seen[c]) rep->bad_ring_missing++;
-        } else {
-            /* page variant: entries are exactly the free pages of class k */
-            uint64_t s = 16ull << k, ppc = C >> (4 + k);
-            uint64_t npages = v.N * ppc;
-            uint8_t* pseen = (uint8_t*)calloc(npages ? npages : 1, 1);
-            for (uint32_t i = 0; i < used; ++i) {
-                uint64_t off = (uint64_t)rd32(sl + ((uint64_t)((head + i) & (uint32_t)(Q - 1))) * 4) * 16;
-                uint64_t c = off >> v.log2C;
-                uint64_t in = off & (C - 1);
-                if (off >= v.data_bytes || v.cls[c] != k || in % s) { rep->bad_ring_entry++; continue; }
-                uint64_t p = in / s;
-                if (!((sv_word(&v, c, (uint32_t)(p >> 6)) >> (p & 63)) & 1)) { rep->bad_ring_entry++; continue; }
-                uint64_t gi = c * ppc + p;
-                if (pseen[gi]) { rep->bad_ring_dup++; continue; }
-                pseen[gi] = 1;
+            if (v.variant == 0) {
+                for (uint64_t c = lo; c < hi; ++c) seen[c] = 0;
+                for (uint32_t i = 0; i < used; ++i) {
+                    uint32_t c = rd32(sl + ((uint64_t)((head + i) & (uint32_t)(Q - 1))) * 4);
+                    if (c < lo || c >= hi || v.cls[c] != k || rd32(v.cnt + (uint64_t)c * 4) == 0) { rep->bad_ring_entry++; continue; }
+                    if (seen[c]) { rep->bad_ring_dup++; continue; }
+                    seen[c] = 1;
+                }
+                for (uint64_t c = lo; c < hi; ++c)
+                    if (v.cls[c] == k && rd32(v.cnt + c * 4) > 0 && !seen[c]) rep->bad_ring_missing++;
+            } else {
+                /* page variant: entries are exactly the free pages of class k in shard j */
+                uint64_t s = 16ull << k, ppc = C >> (4 + k);
+                uint64_t npages = (hi - lo) * ppc;
+                uint8_t* pseen = (uint8_t*)calloc(npages ? npages : 1, 1);
+                for (uint32_t i = 0; i < used; ++i) {
+                    uint64_t off = (uint64_t)rd32(sl + ((uint64_t)((head + i) & (uint32_t)(Q - 1))) * 4) * 16;
+                    uint64_t c = off >> v.log2C;
+                    uint64_t in = off & (C - 1);
+                    if (off >= v.data_bytes || c < lo || c >= hi || v.cls[c] != k || in % s) { rep->bad_ring_entry++; continue; }
+                    uint64_t p = in / s;
+                    if (!((sv_word(&v, c, (uint32_t)(p >> 6)) >> (p & 63)) & 1)) { rep->bad_ring_entry++; continue; }
+                    uint64_t gi = (c - lo) * ppc + p;
+                    if (pseen[gi]) { rep->bad_ring_dup++; continue; }
+                    pseen[gi] = 1;
+                }
+                for (uint64_t c = lo; c < hi; ++c) {
+                    if (v.cls[c] != k) continue;
+                    for (uint64_t p = 0; p < ppc; ++p)
+                        if (((sv_word(&v, c, (uint32_t)(p >> 6)) >> (p & 63)) & 1) && !pseen[(c - lo) * ppc + p])
+                            rep->bad_ring_missing++;
+                }
+                free(pseen);
             }
-            for (uint64_t c = 0; c < v.N; ++c) {
-                if (v.cls[c] != k) continue;
-                for (uint64_t p = 0; p < ppc; ++p)
-                    if (((sv_word(&v, c, (uint32_t)(p >> 6)) >> (p & 63)) & 1) && !pseen[c * ppc + p]) rep->bad_ring_missing++;
-            }
-            free(pseen);
         }
     }
     free(seen);
+    free(chunks_sk);
+    free(free_s);
     uint64_t bad = rep->bad_class_byte + rep->bad_free_chunk + rep->bad_stray_bits + rep->bad_count + rep->bad_pool +
                    rep->bad_ring_ctl + rep->bad_ring_entry + rep->bad_ring_missing + rep->bad_ring_dup +
                    rep->bad_conservation + rep->bad_owned;

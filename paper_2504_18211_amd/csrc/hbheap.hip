@@ -30,10 +30,11 @@ using namespace hbheap::detail;
 namespace {
 
 constexpr uint32_t kMagic = 0x48424850u;
-constexpr uint32_t kVersion = 1;
+constexpr uint32_t kVersion = 2;
 constexpr uint32_t kBatchBlock = 256;
 constexpr uint32_t kTrimBlock = 1024;
-constexpr uint32_t kMaxKeys = 17; /* up to 13 classes + pool + none */
+constexpr uint32_t kMaxKeys = 1024; /* trim keys: 64 shards x (13 classes + pool) + none */
+constexpr uint32_t kMaxShards = 64;
 
 struct Layout {
     uint64_t off_pool, off_cl, off_cls, off_cnt, off_bits, off_pid, off_sl, total;
@@ -57,6 +58,7 @@ struct hbheap_heap {
     uint32_t* trim_totals = nullptr;
     uint32_t* trim_owned = nullptr;
     uint32_t trim_blocks = 0;
+    uint32_t owned_words = 0;
     uint64_t aux_bytes = 0;
     uint64_t chunk_bytes = 0;
 };
@@ -135,39 +137,52 @@ __global__ void k_replay(hbheap_dev_t h, const int64_t* ops, int64_t* out, uint6
 
 /* ---------------- trim ---------------- */
 
+/* Keys of the trim compaction: ring (shard j, class k) = j*K + k; pool of
+ * shard j = S*K + j; nothing = S*(K+1).  A chunk contributes `weight`
+ * entries under its key: an unowned chunk one pool id, a chunk-variant chunk
+ * with free pages its id, a page-variant chunk its free pages. */
 struct TrimKey {
     uint32_t key, weight;
 };
 
-/* Key of a chunk after retirement: class k ring (0..K-1), pool (K), or none
- * (K+1); weight = entries it contributes. */
+__device__ __forceinline__ uint32_t trim_nkeys(const hbheap_dev_t& h) { return h.n_shards * (h.n_classes + 1) + 1; }
+
 __device__ __forceinline__ TrimKey trim_key(const hbheap_dev_t& h, uint64_t c)
 {
     TrimKey t;
+    const uint32_t j = shard_of_chunk(h, c);
     const uint32_t k = h.chunk_class[c];
-    if (k == kFreeClass) { t.key = h.n_classes; t.weight = 1; return t; }
+    if (k == kFreeClass) {
+        t.key = h.n_shards * h.n_classes + j;
+        t.weight = 1;
+        return t;
+    }
     if (h.variant == HBHEAP_VARIANT_CHUNK) {
         const bool listed = h.chunk_cnt[c] > 0;
-        t.key = listed ? k : h.n_classes + 1;
+        t.key = listed ? j * h.n_classes + k : h.n_shards * (h.n_classes + 1);
         t.weight = listed ? 1u : 0u;
     } else {
         uint32_t f = 0;
         const uint32_t ppc = 1u << (h.log2_chunk - 4u - k);
         const uint32_t nw = ppc >= 64u ? ppc >> 6 : 1u;
         for (uint32_t w = 0; w < nw; ++w) f += (uint32_t)__popcll(h.bits[c * h.words_per_chunk + w]);
-        t.key = k;
+        t.key = j * h.n_classes + k;
         t.weight = f;
     }
     return t;
 }
 
-/* Pass 1: retire fully free chunks, count entries per key per block. */
+/* Pass 1: retire fully free chunks, count entries per key per block, and
+ * count the chunks each (shard, class) keeps. */
 __global__ void __launch_bounds__(kTrimBlock) k_trim_count(hbheap_dev_t h, uint32_t* counts, uint32_t nblocks,
                                                            uint32_t* owned)
 {
     __shared__ uint32_t cnt[kMaxKeys], own[kMaxKeys];
-    const uint32_t nkeys = h.n_classes + 2;
-    if (threadIdx.x < kMaxKeys) { cnt[threadIdx.x] = 0; own[threadIdx.x] = 0; }
+    const uint32_t nkeys = trim_nkeys(h);
+    for (uint32_t i = threadIdx.x; i < kMaxKeys; i += kTrimBlock) {
+        cnt[i] = 0;
+        own[i] = 0;
+    }
     __syncthreads();
     const uint64_t c = (uint64_t)blockIdx.x * kTrimBlock + threadIdx.x;
     if (c < h.n_chunks) {
@@ -182,28 +197,30 @@ __global__ void __launch_bounds__(kTrimBlock) k_trim_count(hbheap_dev_t h, uint3
                 h.chunk_cnt[c] = 0;
                 h.chunk_class[c] = (uint8_t)kFreeClass;
             } else {
-                atomicAdd(&own[k], 1u);
+                atomicAdd(&own[shard_of_chunk(h, c) * h.n_classes + k], 1u);
             }
         }
         const TrimKey t = trim_key(h, c);
         if (t.weight) atomicAdd(&cnt[t.key], t.weight);
     }
     __syncthreads();
-    if (threadIdx.x < nkeys) counts[(uint64_t)threadIdx.x * nblocks + blockIdx.x] = cnt[threadIdx.x];
-    if (threadIdx.x < h.n_classes && own[threadIdx.x]) atomicAdd(&owned[threadIdx.x], own[threadIdx.x]);
+    for (uint32_t i = threadIdx.x; i < nkeys; i += kTrimBlock) {
+        counts[(uint64_t)i * nblocks + blockIdx.x] = cnt[i];
+        if (i < h.n_shards * h.n_classes && own[i]) atomicAdd(&owned[i], own[i]);
+    }
 }
 
 /* Pass 2: per key, exclusive scan of the block counts. */
 __global__ void k_trim_scan(const uint32_t* counts, uint32_t* offsets, uint32_t* totals, uint32_t nblocks, uint32_t nkeys)
 {
-    const uint32_t key = threadIdx.x;
-    if (key >= nkeys) return;
-    uint32_t run = 0;
-    for (uint32_t b = 0; b < nblocks; ++b) {
-        offsets[(uint64_t)key * nblocks + b] = run;
-        run += counts[(uint64_t)key * nblocks + b];
+    for (uint32_t key = threadIdx.x; key < nkeys; key += blockDim.x) {
+        uint32_t run = 0;
+        for (uint32_t b = 0; b < nblocks; ++b) {
+            offsets[(uint64_t)key * nblocks + b] = run;
+            run += counts[(uint64_t)key * nblocks + b];
+        }
+        totals[key] = run;
     }
-    totals[key] = run;
 }
 
 /* Block-wide exclusive scan of v over the 1024 threads (all active). */
@@ -234,37 +251,46 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t* wsum)
     return r;
 }
 
-/* Pass 3: write pool ids and ring entries in ascending chunk (page) order. */
+/* Pass 3: write pool ids and ring entries in ascending chunk (page) order,
+ * for the keys of the shards this block's chunks belong to. */
 __global__ void __launch_bounds__(kTrimBlock) k_trim_write(hbheap_dev_t h, const uint32_t* offsets, uint32_t nblocks)
 {
     __shared__ uint32_t wsum[kTrimBlock / 64];
-    const uint64_t c = (uint64_t)blockIdx.x * kTrimBlock + threadIdx.x;
+    const uint64_t c0 = (uint64_t)blockIdx.x * kTrimBlock;
+    const uint64_t c = c0 + threadIdx.x;
+    const uint64_t c_last = (c0 + kTrimBlock <= h.n_chunks ? c0 + kTrimBlock : h.n_chunks) - 1;
     TrimKey t;
-    t.key = h.n_classes + 1;
+    t.key = h.n_shards * (h.n_classes + 1);
     t.weight = 0;
     if (c < h.n_chunks) t = trim_key(h, c);
     const uint64_t Q = 1ull << h.log2q;
-    for (uint32_t key = 0; key <= h.n_classes; ++key) {
-        const uint32_t w = t.key == key ? t.weight : 0u;
-        const uint32_t pos = offsets[(uint64_t)key * nblocks + blockIdx.x] + block_excl_scan(w, wsum);
-        if (!w) continue;
-        if (key == h.n_classes) {
-            if (pos < h.n_chunks) h.pool_ids[pos] = (uint32_t)c;
-        } else if (h.variant == HBHEAP_VARIANT_CHUNK) {
-            if (pos < Q) h.slots[(uint64_t)key * Q + pos] = (uint32_t)c;
-        } else {
-            const uint32_t shift = 4u + key;
-            const uint32_t ppc = 1u << (h.log2_chunk - shift);
-            const uint32_t nw = ppc >= 64u ? ppc >> 6 : 1u;
-            uint32_t j = pos;
-            for (uint32_t wd = 0; wd < nw; ++wd) {
-                uint64_t x = h.bits[c * h.words_per_chunk + wd];
-                while (x) {
-                    const uint32_t b = ctz64(x);
-                    x &= x - 1ull;
-                    const uint64_t off = (c << h.log2_chunk) + ((uint64_t)(wd * 64u + b) << shift);
-                    if (j < Q) h.slots[(uint64_t)key * Q + j] = (uint32_t)(off >> 4);
-                    ++j;
+    const uint32_t K = h.n_classes, S = h.n_shards;
+    const uint32_t j0 = shard_of_chunk(h, c0), j1 = shard_of_chunk(h, c_last);
+    for (uint32_t j = j0; j <= j1; ++j) {
+        for (uint32_t kk = 0; kk <= K; ++kk) {
+            const uint32_t key = kk < K ? j * K + kk : S * K + j;
+            const uint32_t w = t.key == key ? t.weight : 0u;
+            const uint32_t pos = offsets[(uint64_t)key * nblocks + blockIdx.x] + block_excl_scan(w, wsum);
+            if (!w) continue;
+            if (kk == K) {
+                const uint64_t idx = ((uint64_t)j << h.log2_span) + pos;
+                if (idx < h.n_chunks) h.pool_ids[idx] = (uint32_t)c;
+            } else if (h.variant == HBHEAP_VARIANT_CHUNK) {
+                if (pos < Q) h.slots[(uint64_t)key * Q + pos] = (uint32_t)c;
+            } else {
+                const uint32_t shift = 4u + kk;
+                const uint32_t ppc = 1u << (h.log2_chunk - shift);
+                const uint32_t nw = ppc >= 64u ? ppc >> 6 : 1u;
+                uint32_t q = pos;
+                for (uint32_t wd = 0; wd < nw; ++wd) {
+                    uint64_t x = h.bits[c * h.words_per_chunk + wd];
+                    while (x) {
+                        const uint32_t b = ctz64(x);
+                        x &= x - 1ull;
+                        const uint64_t off = (c << h.log2_chunk) + ((uint64_t)(wd * 64u + b) << shift);
+                        if (q < Q) h.slots[(uint64_t)key * Q + q] = (uint32_t)(off >> 4);
+                        ++q;
+                    }
                 }
             }
         }
@@ -274,17 +300,18 @@ __global__ void __launch_bounds__(kTrimBlock) k_trim_write(hbheap_dev_t h, const
 /* Pass 4: queue control words and pool counters. */
 __global__ void k_trim_ctl(hbheap_dev_t h, const uint32_t* totals, const uint32_t* owned)
 {
-    const uint32_t k = threadIdx.x;
-    if (k < h.n_classes) {
-        uint8_t* cb = h.classes + (uint64_t)k * kClassBlock;
-        *(uint64_t*)cb = (uint64_t)(totals[k] + kBias);
-        *(uint64_t*)(cb + 384) = h.variant == HBHEAP_VARIANT_PAGE ? (uint64_t)owned[k] : 0ull;
+    const uint32_t K = h.n_classes, S = h.n_shards;
+    for (uint32_t i = threadIdx.x; i < S * K; i += blockDim.x) {
+        uint8_t* cb = h.classes + (uint64_t)i * kClassBlock;
+        *(uint64_t*)cb = (uint64_t)(totals[i] + kBias);
         *(uint32_t*)(cb + 128) = 0;
-        *(uint32_t*)(cb + 256) = totals[k];
+        *(uint32_t*)(cb + 256) = totals[i];
+        *(uint64_t*)(cb + 384) = h.variant == HBHEAP_VARIANT_PAGE ? (uint64_t)owned[i] : 0ull;
     }
-    if (k == 0) {
-        h.pool[0] = 0;
-        h.pool[1] = totals[h.n_classes];
+    for (uint32_t j = threadIdx.x; j < S; j += blockDim.x) {
+        uint64_t* pb = h.pool + 16ull * j;
+        pb[0] = 0;
+        ((uint32_t*)pb)[2] = totals[S * K + j];
     }
 }
 
@@ -495,24 +522,41 @@ int fill_u8(uint8_t* p, uint64_t n, uint8_t v, hipStream_t s)
     return hipGetLastError() == hipSuccess ? HBHEAP_OK : HBHEAP_E_HIP;
 }
 
-Layout make_layout(uint64_t N, uint32_t log2C, uint32_t K, uint32_t variant, uint64_t bytes)
+/* Shards: span = smallest power of two >= ceil(N / requested); as many
+ * shards as spans needed to cover N.  Auto (0): about N/256 chunks per
+ * shard, between 1 and 64 shards. */
+void shard_geometry(uint64_t N, uint32_t requested, uint32_t* S, uint32_t* log2_span)
+{
+    uint32_t want = requested;
+    if (!want) {
+        want = 1;
+        while (want < kMaxShards && (uint64_t)want * 2 * 256 <= N) want *= 2;
+    }
+    if (want > N) want = (uint32_t)N;
+    const uint64_t per = (N + want - 1) / want;
+    *log2_span = ceil_log2(per);
+    *S = (uint32_t)((N + (1ull << *log2_span) - 1) >> *log2_span);
+}
+
+Layout make_layout(uint64_t N, uint32_t log2C, uint32_t K, uint32_t variant, uint64_t bytes, uint32_t S,
+                   uint32_t log2_span)
 {
     Layout L;
     const uint64_t W = (1ull << log2C) / 1024;
     if (variant == HBHEAP_VARIANT_CHUNK) {
-        L.log2q = ceil_log2(N);
+        L.log2q = log2_span;
     } else {
-        const uint64_t per = bytes / 8 / K / 4;
+        const uint64_t per = bytes / 8 / K / 4 / S;
         L.log2q = per ? ilog2(per) : 0;
     }
     L.off_pool = 256;
-    L.off_cl = L.off_pool + 128;
-    L.off_cls = al256(L.off_cl + (uint64_t)kClassBlock * K);
+    L.off_cl = al256(L.off_pool + 128ull * S);
+    L.off_cls = al256(L.off_cl + (uint64_t)kClassBlock * S * K);
     L.off_cnt = al256(L.off_cls + N);
     L.off_bits = al256(L.off_cnt + 4 * N);
     L.off_pid = al256(L.off_bits + 8 * N * W);
     L.off_sl = al256(L.off_pid + 4 * N);
-    L.total = al256(L.off_sl + 4ull * K * (1ull << L.log2q));
+    L.total = al256(L.off_sl + 4ull * S * K * (1ull << L.log2q));
     return L;
 }
 
@@ -550,17 +594,21 @@ int heap_create_ex(size_t bytes, size_t chunk_bytes, const heap_config_t* cfg, h
     const uint32_t log2C = ilog2(chunk_bytes);
     const uint32_t K = log2C - 3;
     if (c.variant == HBHEAP_VARIANT_PAGE && N * chunk_bytes > (64ull << 30)) return HBHEAP_E_INVAL;
+    if (c.shards > kMaxShards || (c.shards & (c.shards - 1))) return HBHEAP_E_INVAL;
+    uint32_t S = 1, log2_span = 0;
+    shard_geometry(N, c.shards, &S, &log2_span);
 
     hbheap_heap* h = new (std::nothrow) hbheap_heap();
     if (!h) return HBHEAP_E_NOMEM;
     h->chunk_bytes = chunk_bytes;
-    h->lay = make_layout(N, log2C, K, c.variant, bytes);
+    h->lay = make_layout(N, log2C, K, c.variant, bytes, S, log2_span);
     const Layout& L = h->lay;
     h->trim_blocks = (uint32_t)((N + kTrimBlock - 1) / kTrimBlock);
-    const uint32_t nkeys = K + 2;
-    /* aux: err (256 B line) | stats (256 B) | trim counts | offsets | totals | owned */
-    const uint64_t tb = (uint64_t)h->trim_blocks * nkeys * 4;
-    h->aux_bytes = 512 + al256(tb) * 2 + 256 + 256;
+    const uint32_t nkeys = S * (K + 1) + 1;
+    /* aux: err (256 B) | stats (256 B) | trim counts | offsets | totals | owned */
+    const uint64_t tb = al256((uint64_t)h->trim_blocks * nkeys * 4);
+    const uint64_t kb = al256((uint64_t)nkeys * 4);
+    h->aux_bytes = 512 + 2 * tb + 2 * kb;
     if (hipMalloc(&h->data, N * chunk_bytes) != hipSuccess) { h->data = nullptr; release(h); return HBHEAP_E_NOMEM; }
     if (hipMalloc(&h->state, L.total) != hipSuccess) { h->state = nullptr; release(h); return HBHEAP_E_NOMEM; }
     if (hipMalloc(&h->aux, h->aux_bytes) != hipSuccess) { h->aux = nullptr; release(h); return HBHEAP_E_NOMEM; }
@@ -590,12 +638,15 @@ int heap_create_ex(size_t bytes, size_t chunk_bytes, const heap_config_t* cfg, h
     d.spin_cap = c.spin_cap;
     d.backoff_max = c.backoff_max;
     d.flags = c.flags;
+    d.n_shards = S;
+    d.log2_span = log2_span;
     h->trim_counts = (uint32_t*)(ax + 512);
-    h->trim_offsets = (uint32_t*)(ax + 512 + al256(tb));
-    h->trim_totals = (uint32_t*)(ax + 512 + 2 * al256(tb));
-    h->trim_owned = (uint32_t*)(ax + 512 + 2 * al256(tb) + 256);
+    h->trim_offsets = (uint32_t*)(ax + 512 + tb);
+    h->trim_totals = (uint32_t*)(ax + 512 + 2 * tb);
+    h->trim_owned = (uint32_t*)(ax + 512 + 2 * tb + kb);
+    h->owned_words = S * K;
 
-    /* header, pool block and class blocks are built on the host */
+    /* header, pool blocks and class blocks are built on the host */
     const uint64_t head_bytes = L.off_cls;
     uint8_t* hb = (uint8_t*)calloc(1, head_bytes);
     if (!hb) { release(h); return HBHEAP_E_NOMEM; }
@@ -608,7 +659,8 @@ int heap_create_ex(size_t bytes, size_t chunk_bytes, const heap_config_t* cfg, h
     put32(hb, 28, c.variant);
     put32(hb, 32, d.words_per_chunk);
     put32(hb, 36, L.log2q);
-    put64(hb, 40, 0);
+    put32(hb, 40, S);
+    put32(hb, 44, log2_span);
     put64(hb, 48, L.off_pool);
     put64(hb, 56, L.off_cl);
     put64(hb, 64, L.off_cls);
@@ -617,14 +669,19 @@ int heap_create_ex(size_t bytes, size_t chunk_bytes, const heap_config_t* cfg, h
     put64(hb, 88, L.off_pid);
     put64(hb, 96, L.off_sl);
     put64(hb, 104, L.total);
-    put64(hb, L.off_pool, 0);
-    put32(hb, L.off_pool + 8, (uint32_t)N);
-    for (uint32_t k = 0; k < K; ++k) put64(hb, L.off_cl + (uint64_t)k * kClassBlock, kBias);
+    for (uint32_t j = 0; j < S; ++j) {
+        const uint64_t first = (uint64_t)j << log2_span;
+        const uint64_t size = first + (1ull << log2_span) <= N ? (1ull << log2_span) : N - first;
+        put64(hb, L.off_pool + 128ull * j, 0);
+        put32(hb, L.off_pool + 128ull * j + 8, (uint32_t)size);
+        put32(hb, L.off_pool + 128ull * j + 12, (uint32_t)first);
+    }
+    for (uint64_t i = 0; i < (uint64_t)S * K; ++i) put64(hb, L.off_cl + i * kClassBlock, kBias);
 
     int rc = HBHEAP_OK;
     hipStream_t s = nullptr;
     if (fill_u32((uint32_t*)st, L.total / 4, 0u, s) || fill_u8(st + L.off_cls, N, (uint8_t)kFreeClass, s) ||
-        fill_u32(d.slots, (uint64_t)K << L.log2q, kEmpty, s) || fill_u32((uint32_t*)ax, h->aux_bytes / 4, 0u, s))
+        fill_u32(d.slots, ((uint64_t)S * K) << L.log2q, kEmpty, s) || fill_u32((uint32_t*)ax, h->aux_bytes / 4, 0u, s))
         rc = HBHEAP_E_HIP;
     if (rc == HBHEAP_OK) {
         hipLaunchKernelGGL(k_iota_u32, dim3(grid_stride(N)), dim3(256), 0, s, d.pool_ids, N);
@@ -706,6 +763,7 @@ int heap_info(heap_t h, heap_info_t* out)
     out->n_classes = h->dev.n_classes;
     out->variant = h->dev.variant;
     out->ring_entries = 1ull << h->lay.log2q;
+    out->n_shards = h->dev.n_shards;
     out->state_bytes = h->lay.total;
     out->metadata_bytes = h->lay.total + h->aux_bytes;
     return HBHEAP_OK;
@@ -715,21 +773,21 @@ int heap_trim(heap_t h, hipStream_t stream)
 {
     if (!h) return HBHEAP_E_INVAL;
     const hbheap_dev_t& d = h->dev;
-    const uint32_t nkeys = d.n_classes + 2;
+    const uint32_t nkeys = d.n_shards * (d.n_classes + 1) + 1;
     const uint32_t nb = h->trim_blocks;
-    int rc = fill_u32(h->trim_owned, 64, 0u, stream);
+    int rc = fill_u32(h->trim_owned, h->owned_words, 0u, stream);
     if (rc) return rc;
     hipLaunchKernelGGL(k_trim_count, dim3(nb), dim3(kTrimBlock), 0, stream, d, h->trim_counts, nb, h->trim_owned);
     HB_TRY(hipGetLastError());
-    hipLaunchKernelGGL(k_trim_scan, dim3(1), dim3(64), 0, stream, h->trim_counts, h->trim_offsets, h->trim_totals, nb,
+    hipLaunchKernelGGL(k_trim_scan, dim3(1), dim3(1024), 0, stream, h->trim_counts, h->trim_offsets, h->trim_totals, nb,
                        nkeys);
     HB_TRY(hipGetLastError());
-    rc = fill_u32(d.slots, (uint64_t)d.n_classes << d.log2q, kEmpty, stream);
+    rc = fill_u32(d.slots, ((uint64_t)d.n_shards * d.n_classes) << d.log2q, kEmpty, stream);
     if (!rc) rc = fill_u32(d.pool_ids, d.n_chunks, kEmpty, stream);
     if (rc) return rc;
     hipLaunchKernelGGL(k_trim_write, dim3(nb), dim3(kTrimBlock), 0, stream, d, h->trim_offsets, nb);
     HB_TRY(hipGetLastError());
-    hipLaunchKernelGGL(k_trim_ctl, dim3(1), dim3(64), 0, stream, d, h->trim_totals, h->trim_owned);
+    hipLaunchKernelGGL(k_trim_ctl, dim3(1), dim3(1024), 0, stream, d, h->trim_totals, h->trim_owned);
     HB_TRY(hipGetLastError());
     return HBHEAP_OK;
 }

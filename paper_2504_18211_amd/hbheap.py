@@ -39,13 +39,14 @@ class HbHeapError(RuntimeError):
 
 class HeapConfig(C.Structure):
     _fields_ = [("variant", C.c_uint32), ("width", C.c_uint32), ("spin_cap", C.c_uint32),
-                ("backoff_max", C.c_uint32), ("flags", C.c_uint32)]
+                ("backoff_max", C.c_uint32), ("flags", C.c_uint32), ("shards", C.c_uint32)]
 
 
 class HeapInfo(C.Structure):
     _fields_ = [("data", C.c_void_p), ("data_bytes", C.c_uint64), ("chunk_bytes", C.c_uint64),
                 ("n_chunks", C.c_uint64), ("n_classes", C.c_uint32), ("variant", C.c_uint32),
-                ("ring_entries", C.c_uint64), ("state_bytes", C.c_uint64), ("metadata_bytes", C.c_uint64)]
+                ("ring_entries", C.c_uint64), ("state_bytes", C.c_uint64), ("metadata_bytes", C.c_uint64),
+                ("n_shards", C.c_uint32), ("reserved", C.c_uint32)]
 
 
 class DevHandle(C.Structure):
@@ -54,7 +55,8 @@ class DevHandle(C.Structure):
                                           "pool_ids", "slots", "err", "stats")] + \
                [("data_bytes", C.c_uint64)] + \
                [(n, C.c_uint32) for n in ("n_chunks", "log2_chunk", "n_classes", "variant", "words_per_chunk",
-                                          "log2q", "width", "spin_cap", "backoff_max", "flags")]
+                                          "log2q", "width", "spin_cap", "backoff_max", "flags", "n_shards",
+                                          "log2_span")]
 
 
 _lib = None
@@ -134,8 +136,8 @@ def _stream(stream) -> int | None:
 # ---------------------------------------------------------------------------
 
 def heap_create(nbytes: int, chunk_bytes: int, variant: int = VARIANT_CHUNK, width: int = 64,
-                spin_cap: int = 0, backoff_max: int = 0, flags: int = 0) -> int:
-    cfg = HeapConfig(variant, width, spin_cap, backoff_max, flags)
+                spin_cap: int = 0, backoff_max: int = 0, flags: int = 0, shards: int = 0) -> int:
+    cfg = HeapConfig(variant, width, spin_cap, backoff_max, flags, shards)
     out = C.c_void_p()
     _check("heap_create_ex", lib().heap_create_ex(nbytes, chunk_bytes, C.byref(cfg), C.byref(out)))
     return out.value
@@ -252,8 +254,8 @@ class Heap:
     """Owns one heap; methods forward to the C ABI above."""
 
     def __init__(self, nbytes: int, chunk_bytes: int = 8192, variant: int = VARIANT_CHUNK, width: int = 64,
-                 spin_cap: int = 0, backoff_max: int = 0, flags: int = 0):
-        self.h = heap_create(nbytes, chunk_bytes, variant, width, spin_cap, backoff_max, flags)
+                 spin_cap: int = 0, backoff_max: int = 0, flags: int = 0, shards: int = 0):
+        self.h = heap_create(nbytes, chunk_bytes, variant, width, spin_cap, backoff_max, flags, shards)
         self.info = heap_info(self.h)
         self.base = int(self.info.data)
 

@@ -75,5 +75,5 @@ def test_null_handle_and_buffers_rejected(L):
 
 
 def test_dev_handle_layout_matches_header():
-    # 11 pointers, one u64, ten u32
-    assert C.sizeof(hb.DevHandle) == 11 * 8 + 8 + 10 * 4
+    # 11 pointers, one u64, twelve u32
+    assert C.sizeof(hb.DevHandle) == 11 * 8 + 8 + 12 * 4

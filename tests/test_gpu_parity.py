@@ -35,10 +35,22 @@ def hb():
     return hbheap
 
 
-def _oracle_cap(nbytes, C, variant, k):
+def _oracle_cap(nbytes, C, variant, k, shards):
+    """Pages of class k the heap holds: per shard min(chunks, cap) * ppc."""
     N = nbytes // C
-    chunks = N if variant == 0 else min(N, O.page_max_chunks(nbytes, C, k))
-    return chunks * O.pages_per_chunk(C, k)
+    S, L = O.shard_geometry(N, shards)
+    tot = 0
+    for j in range(S):
+        nj = min(N, (j + 1) << L) - (j << L)
+        cj = nj if variant == 0 else min(nj, O.page_max_chunks(nbytes, C, k, S))
+        tot += cj * O.pages_per_chunk(C, k)
+    return tot
+
+
+def _same_shards(heap, nbytes, C, requested):
+    S, _ = O.shard_geometry(nbytes // C, requested)
+    assert heap.info.n_shards == S, (heap.info.n_shards, S)
+    return S
 
 
 # ---------------------------------------------------------------------------
@@ -81,20 +93,21 @@ def test_tiny_round_trip(hb, variant):
 # ---------------------------------------------------------------------------
 
 @pytest.mark.parametrize("variant", VARIANTS)
-@pytest.mark.parametrize("seed", [1, 2])
-def test_single_lane_replay_matches_fifo_oracle(hb, variant, seed):
-    say(f"case replay variant={variant} seed={seed}")
+@pytest.mark.parametrize("seed,shards", [(1, 1), (2, 1), (3, 4), (4, 8)])
+def test_single_lane_replay_matches_fifo_oracle(hb, variant, seed, shards):
+    say(f"case replay variant={variant} seed={seed} shards={shards}")
     nbytes, C = 32 * 8 * KiB, 8 * KiB
     ops = inputs.op_script(3000, seed, lo=1, hi=8 * KiB, p_free=0.4, p_invalid_size=0.05)
-    ref = O.OracleHeap(nbytes, C, variant, O.POLICY_FIFO).replay(ops)
-    with hb.Heap(nbytes, C, variant=variant) as heap:
+    ref = O.OracleHeap(nbytes, C, variant, O.POLICY_FIFO, shards).replay(ops)
+    with hb.Heap(nbytes, C, variant=variant, shards=shards) as heap:
+        _same_shards(heap, nbytes, C, shards)
         od, out = dev_i64(ops), zeros_i64(len(ops))
         heap.replay(od, out)
         got = out.cpu().numpy()
         bad = np.nonzero(got != ref)[0]
         assert bad.size == 0, f"first mismatch at op {bad[:5]}: gpu {got[bad[:5]]} oracle {ref[bad[:5]]}"
         _, rep = check_snapshot(heap)
-        acc_oracle = O.OracleHeap(nbytes, C, variant, O.POLICY_FIFO)
+        acc_oracle = O.OracleHeap(nbytes, C, variant, O.POLICY_FIFO, shards)
         acc_oracle.replay(ops)
         a = acc_oracle.accounting()
         assert live_of(rep) == a["live"]
@@ -109,16 +122,18 @@ def test_single_lane_replay_matches_fifo_oracle(hb, variant, seed):
 # ---------------------------------------------------------------------------
 
 @pytest.mark.parametrize("variant", VARIANTS)
-def test_sweep_small_exact_capacity(hb, variant):
+@pytest.mark.parametrize("shards", [1, 0])
+def test_sweep_small_exact_capacity(hb, variant, shards):
     nbytes, C, n = 64 * MiB, 8 * KiB, 1 << 16
-    with hb.Heap(nbytes, C, variant=variant) as heap:
+    with hb.Heap(nbytes, C, variant=variant, shards=shards) as heap:
+        _same_shards(heap, nbytes, C, shards)
         fresh = heap.snapshot()
         ptrs = zeros_i64(n)
         for size in inputs.SWEEP_SIZES:
             k = O.class_of(size, C)
-            cap = _oracle_cap(nbytes, C, variant, k)
+            cap = _oracle_cap(nbytes, C, variant, k, shards)
             for it in range(2):
-                say(f"case sweep-small variant={variant} size={size} iter={it}")
+                say(f"case sweep-small variant={variant} shards={shards} size={size} iter={it}")
                 sizes = inputs.sizes_fixed(n, size)
                 sd = dev_u64(sizes)
                 heap.alloc(sd, ptrs)
@@ -130,7 +145,8 @@ def test_sweep_small_exact_capacity(hb, variant):
                 snap, srep = check_snapshot(heap)
                 assert live_of(srep)[k] == min(n, cap)
                 if n >= cap:
-                    assert srep.free_pages[k] == 0 and srep.free_chunks == 0 or variant == 1
+                    assert srep.free_pages[k] == 0
+                    assert srep.free_chunks == 0 or variant == 1
                 assert O.check_blocks_in_snapshot(snap, sizes, offs) == 0
                 heap.free(ptrs)
                 _, srep = check_snapshot(heap)
@@ -141,24 +157,58 @@ def test_sweep_small_exact_capacity(hb, variant):
 
 
 # ---------------------------------------------------------------------------
+# stealing: 64 shards of one chunk each, far more requests than pages; every
+# wave ends up taking from other shards and exactly the capacity succeeds
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("variant", VARIANTS)
+def test_steal_exact_capacity(hb, variant):
+    nbytes, C, n = 64 * 8 * KiB, 8 * KiB, 1 << 14
+    with hb.Heap(nbytes, C, variant=variant, shards=64) as heap:
+        _same_shards(heap, nbytes, C, 64)
+        fresh = heap.snapshot()
+        ptrs = zeros_i64(n)
+        for size in [16, 200, 1024, 8192]:
+            say(f"case steal variant={variant} size={size}")
+            k = O.class_of(size, C)
+            cap = _oracle_cap(nbytes, C, variant, k, 64)
+            sizes = inputs.sizes_fixed(n, size)
+            sd = dev_u64(sizes)
+            heap.alloc(sd, ptrs)
+            offs = offsets(ptrs, heap.base)
+            rep = check_blocks(heap, sizes, offs, allow_null=True)
+            assert rep.n_nonnull == min(n, cap), (size, rep.n_nonnull, cap)
+            heap.pattern_write(ptrs, sd, 9)
+            assert heap.pattern_check(ptrs, sd, 9) == 0
+            _, srep = check_snapshot(heap)
+            if n >= cap:
+                assert srep.free_pages[k] == 0
+            heap.free(ptrs)
+            heap.trim()
+            assert heap.snapshot() == fresh
+        assert heap.error() == 0
+
+
+# ---------------------------------------------------------------------------
 # mixed-size churn, reduced: 2^16 threads, log-uniform 4 B .. 8 KiB, half
 # freed and reallocated per round
 # ---------------------------------------------------------------------------
 
 @pytest.mark.parametrize("variant", VARIANTS)
-def test_churn_small(hb, variant):
+@pytest.mark.parametrize("shards", [1, 0])
+def test_churn_small(hb, variant, shards):
     import torch
     nbytes, C, n, rounds = 256 * MiB, 8 * KiB, 1 << 16, 4
     seed = inputs.SEED_CHURN
     sizes = inputs.sizes_log_uniform(n, 4, 8 * KiB, seed)
     ref = O.OracleHeap(nbytes, C, variant)
     ref_offs = ref.alloc_batch(sizes)
-    with hb.Heap(nbytes, C, variant=variant) as heap:
+    with hb.Heap(nbytes, C, variant=variant, shards=shards) as heap:
         fresh = heap.snapshot()
         ptrs = zeros_i64(n)
         heap.alloc(dev_u64(sizes), ptrs)
         for r in range(rounds + 1):
-            say(f"case churn-small variant={variant} round={r}")
+            say(f"case churn-small variant={variant} shards={shards} round={r}")
             if r:
                 idx, new_sizes = inputs.churn_round(n, r, seed)
                 idx_d = torch.from_numpy(idx).to("cuda")
@@ -260,12 +310,13 @@ def test_sweep_full_size(hb, variant):
     w = inputs.SWEEP
     n = w.threads
     with hb.Heap(w.heap_bytes, w.chunk_bytes, variant=variant) as heap:
+        _same_shards(heap, w.heap_bytes, w.chunk_bytes, 0)
         fresh = heap.snapshot()
         ptrs = zeros_i64(n)
         for size in inputs.SWEEP_SIZES:
             say(f"case sweep-full variant={variant} size={size}")
             k = O.class_of(size, w.chunk_bytes)
-            cap = _oracle_cap(w.heap_bytes, w.chunk_bytes, variant, k)
+            cap = _oracle_cap(w.heap_bytes, w.chunk_bytes, variant, k, 0)
             sizes = inputs.sizes_fixed(n, size)
             sd = dev_u64(sizes)
             for it in range(2):

@@ -53,22 +53,60 @@ def test_pages_per_chunk_closed_form():
 # capacity: a heap of N chunks serves exactly N * C / s pages of one class
 # ---------------------------------------------------------------------------
 
+def shard_caps(nbytes, C, variant, k, shards):
+    """Pages of class k a heap can hold: per shard min(chunks, cap) * ppc."""
+    N = nbytes // C
+    S, L = O.shard_geometry(N, shards)
+    tot = 0
+    for j in range(S):
+        nj = min(N, (j + 1) << L) - (j << L)
+        cj = nj if variant == O.VARIANT_CHUNK else min(nj, O.page_max_chunks(nbytes, C, k, S))
+        tot += cj * O.pages_per_chunk(C, k)
+    return tot
+
+
 @pytest.mark.parametrize("variant", [O.VARIANT_CHUNK, O.VARIANT_PAGE])
 @pytest.mark.parametrize("policy", [O.POLICY_LOWEST, O.POLICY_FIFO])
-def test_single_class_capacity_exact(variant, policy):
+@pytest.mark.parametrize("shards", [1, 4])
+def test_single_class_capacity_exact(variant, policy, shards):
     C, nbytes = 8 * KiB, 40 * 8 * KiB + 123  # ragged tail of heap bytes is unused
     N = nbytes // C
     for k in [0, 3, 6, 9]:
-        h = O.OracleHeap(nbytes, C, variant, policy)
+        h = O.OracleHeap(nbytes, C, variant, policy, shards)
         s = O.page_bytes(k)
-        cap_chunks = N if variant == O.VARIANT_CHUNK else min(N, O.page_max_chunks(nbytes, C, k))
-        expect = cap_chunks * (C // s)
+        expect = shard_caps(nbytes, C, variant, k, shards)
+        if variant == O.VARIANT_CHUNK:
+            assert expect == N * (C // s)
         offs = h.alloc_batch(np.full(expect + 5, s, dtype=np.uint64))
         assert (offs[:expect] >= 0).all()
         assert (offs[expect:] < 0).all()
         a = h.accounting()
         assert a["live"][k] == expect and a["free_pages"][k] == 0
         h.close()
+
+
+def test_shard_geometry_closed_form():
+    for N in [1, 7, 32, 1000, 1024, 8192, 1 << 19, 1 << 21]:
+        for req in [0, 1, 2, 8, 64]:
+            S, L = O.shard_geometry(N, req)
+            assert (S - 1) << L < N <= S << L, (N, req, S, L)
+            want = req or min(64, max(1, 1 << ((N // 256).bit_length() - 1))) if N >= 256 else (req or 1)
+            want = min(want, N)
+            assert (1 << L) >= -(-N // want) and (L == 0 or (1 << (L - 1)) < -(-N // want))
+
+
+def test_fifo_home_shard_then_steal():
+    """One lane, two shards of two 8 KiB chunks: shard 0's queue, then its
+    pool, then shard 1; a page freed in shard 0 is reused before shard 1."""
+    C = 8 * KiB
+    h = O.OracleHeap(4 * C, C, O.VARIANT_CHUNK, O.POLICY_FIFO, 2)
+    assert h.shards == 2
+    offs = [h.alloc(4096) for _ in range(5)]
+    assert offs == [0, 4096, C, C + 4096, 2 * C]
+    h.free(4096)
+    assert h.alloc(4096) == 4096
+    assert h.alloc(4096) == 2 * C + 4096
+    h.close()
 
 
 def test_lowest_single_class_is_bump_allocator():
@@ -138,11 +176,13 @@ def test_chunk_variant_fifo_rotates_partial_chunks():
 
 @pytest.mark.parametrize("variant", [O.VARIANT_CHUNK, O.VARIANT_PAGE])
 @pytest.mark.parametrize("policy", [O.POLICY_LOWEST, O.POLICY_FIFO])
-@pytest.mark.parametrize("seed", [1, 2, 3])
-def test_random_stream_against_byte_map(variant, policy, seed):
+@pytest.mark.parametrize("seed,shards", [(1, 1), (2, 1), (3, 4), (4, 8)])
+def test_random_stream_against_byte_map(variant, policy, seed, shards):
     C, nbytes = 4 * KiB, 24 * 4 * KiB
-    h = O.OracleHeap(nbytes, C, variant, policy)
+    h = O.OracleHeap(nbytes, C, variant, policy, shards)
+    S, L = O.shard_geometry(nbytes // C, shards)
     occ = np.zeros(nbytes, dtype=np.int32)  # owner id + 1
+    owner = {}                               # chunk -> class (no trim: owned for good)
     live = {}
     g = np.random.default_rng(seed)
     for step in range(4000):
@@ -157,19 +197,23 @@ def test_random_stream_against_byte_map(variant, policy, seed):
             off = h.alloc(n)
             k = O.class_of(n, C)
             if off < 0:
-                # NULL only when neither a free page of the class nor a usable
-                # unowned chunk exists (exact out-of-memory)
+                # NULL only when no free page of the class exists and no shard
+                # has an unowned chunk the class may still take (exact OOM)
                 a = h.accounting()
                 assert a["free_pages"][k] == 0
-                cap_hit = variant == O.VARIANT_PAGE and a["chunks"][k] >= O.page_max_chunks(nbytes, C, k)
-                assert a["free_chunks"] == 0 or cap_hit
+                for j in range(S):
+                    chunks = range(j << L, min(nbytes // C, (j + 1) << L))
+                    unowned = sum(1 for c in chunks if c not in owner)
+                    mine = sum(1 for c in chunks if owner.get(c) == k)
+                    capped = variant == O.VARIANT_PAGE and mine >= O.page_max_chunks(nbytes, C, k, S)
+                    assert unowned == 0 or capped, (j, unowned, mine)
                 continue
             s = O.page_bytes(k)
             assert off % s == 0 and off // C == (off + s - 1) // C and off + s <= (nbytes // C) * C
             assert (occ[off:off + s] == 0).all(), "overlap"
+            assert owner.setdefault(off // C, k) == k, "chunk serves two classes"
             occ[off:off + s] = step + 1
             live[step] = (off, s)
-    # accounting matches the byte map
     a = h.accounting()
     for k in range(O.num_classes(C)):
         assert a["live"][k] == sum(1 for (o, s) in live.values() if s == O.page_bytes(k))
@@ -257,25 +301,36 @@ def test_check_blocks_catches_planted_faults():
 # snapshot checker on hand-built snapshots of the documented layout
 # ---------------------------------------------------------------------------
 
-def build_snapshot(N, log2C, variant, log2q, cls, cnt, bits, pool_bump, pool_ids, rings, owned=None):
-    """Write a version-1 snapshot from plain arrays.  rings[k] = (H, head, entries)."""
+def build_snapshot(N, log2C, variant, log2q, cls, cnt, bits, pool_bumps, pool_ids, rings, owned=None, S=1,
+                   log2_span=None):
+    """Write a version-2 snapshot from plain arrays.  rings[(j, k)] or
+    rings[k] (shard 0) = (H, head, entries); pool_bumps: one per shard;
+    pool_ids: the whole id array."""
     K = log2C - 3
     W = (1 << log2C) // 1024
     Q = 1 << log2q
+    if log2_span is None:
+        log2_span = max(0, (N - 1).bit_length())
+    if isinstance(pool_bumps, int):
+        pool_bumps = [pool_bumps]
+
     def al(x):
         return (x + 255) & ~255
     off_pool = 256
-    off_cl = off_pool + 128
-    off_cls = al(off_cl + 512 * K)
+    off_cl = al(off_pool + 128 * S)
+    off_cls = al(off_cl + 512 * S * K)
     off_cnt = al(off_cls + N)
     off_bits = al(off_cnt + 4 * N)
     off_pid = al(off_bits + 8 * N * W)
     off_sl = al(off_pid + 4 * N)
-    total = al(off_sl + 4 * K * Q)
+    total = al(off_sl + 4 * S * K * Q)
     b = bytearray(total)
-    struct.pack_into("<IIQIIIIIIQQQQQQQQQ", b, 0, 0x48424850, 1, N << log2C, N, log2C, K, variant, W, log2q,
-                     0, off_pool, off_cl, off_cls, off_cnt, off_bits, off_pid, off_sl, total)
-    struct.pack_into("<QI", b, off_pool, pool_bump, len(pool_ids))
+    struct.pack_into("<IIQIIIIIIIIQQQQQQQQ", b, 0, 0x48424850, 2, N << log2C, N, log2C, K, variant, W, log2q,
+                     S, log2_span, off_pool, off_cl, off_cls, off_cnt, off_bits, off_pid, off_sl, total)
+    for j in range(S):
+        first = j << log2_span
+        size = min(N, (j + 1) << log2_span) - first
+        struct.pack_into("<QII", b, off_pool + 128 * j, pool_bumps[j], size, first)
     for i, c in enumerate(pool_ids):
         struct.pack_into("<I", b, off_pid + 4 * i, c)
     b[off_cls:off_cls + N] = bytes(cls)
@@ -283,16 +338,20 @@ def build_snapshot(N, log2C, variant, log2q, cls, cnt, bits, pool_bump, pool_ids
         struct.pack_into("<I", b, off_cnt + 4 * c, cnt[c])
         for w in range(W):
             struct.pack_into("<Q", b, off_bits + 8 * (c * W + w), bits[c][w])
-    for k in range(K):
-        H, head, ents = rings[k] if k in rings else (0, 0, [])
-        struct.pack_into("<Q", b, off_cl + 512 * k, (H << 32) | ((len(ents) + 0x80000000) & 0xFFFFFFFF))
-        struct.pack_into("<I", b, off_cl + 512 * k + 128, head & 0xFFFFFFFF)
-        struct.pack_into("<I", b, off_cl + 512 * k + 256, (head + len(ents)) & 0xFFFFFFFF)
-        struct.pack_into("<Q", b, off_cl + 512 * k + 384, (owned or {}).get(k, 0))
-        for j in range(Q):
-            struct.pack_into("<I", b, off_sl + 4 * (k * Q + j), 0xFFFFFFFF)
-        for j, e in enumerate(ents):
-            struct.pack_into("<I", b, off_sl + 4 * (k * Q + ((head + j) % Q)), e)
+    rings = {(key if isinstance(key, tuple) else (0, key)): v for key, v in rings.items()}
+    owned = {(key if isinstance(key, tuple) else (0, key)): v for key, v in (owned or {}).items()}
+    for j in range(S):
+        for k in range(K):
+            r = j * K + k
+            H, head, ents = rings.get((j, k), (0, 0, []))
+            struct.pack_into("<Q", b, off_cl + 512 * r, (H << 32) | ((len(ents) + 0x80000000) & 0xFFFFFFFF))
+            struct.pack_into("<I", b, off_cl + 512 * r + 128, head & 0xFFFFFFFF)
+            struct.pack_into("<I", b, off_cl + 512 * r + 256, (head + len(ents)) & 0xFFFFFFFF)
+            struct.pack_into("<Q", b, off_cl + 512 * r + 384, owned.get((j, k), 0))
+            for q in range(Q):
+                struct.pack_into("<I", b, off_sl + 4 * (r * Q + q), 0xFFFFFFFF)
+            for q, e in enumerate(ents):
+                struct.pack_into("<I", b, off_sl + 4 * (r * Q + ((head + q) % Q)), e)
     return bytes(b)
 
 
@@ -304,7 +363,7 @@ def _tiny_state():
     cls = [6, 0xFF, 0, 0xFF]
     cnt = [2, 0, 1, 0]
     bits = [[0b1010, 0, 0, 0], [0, 0, 0, 0], [1 << 5, 0, 0, 0], [0, 0, 0, 0]]
-    pool_ids = [2, 0, 1, 3]
+    pool_ids = [0, 2, 1, 3]     # consumed: 0, 2; left: 1, 3
     return N, log2C, cls, cnt, bits, pool_ids
 
 
@@ -336,7 +395,7 @@ def test_snapshot_checker_catches_planted_faults(plant, field):
     elif plant == "held":
         rings[6] = (1, 5, [0])
     elif plant == "pool":
-        pool_ids = [2, 0, 1, 1]
+        pool_ids = [0, 1, 3, 3]
     elif plant == "freebits":
         bits[1][2] = 1
     elif plant == "badclass":
@@ -361,6 +420,23 @@ def test_snapshot_checker_page_variant():
     bad = build_snapshot(N, log2C, 1, 8, cls, [0] * 4, bits, 2, pool_ids, {6: (0, 3, e6), 0: (0, 0, e0)},
                          owned={6: 2, 0: 1})
     assert O.check_snapshot(bad).violations().get("bad_owned", 0) == 1
+
+
+def test_snapshot_checker_shards():
+    """Two shards of two chunks: entries must stay inside their shard."""
+    N, log2C, cls, cnt, bits, _ = _tiny_state()
+    # shard 0 = chunks 0,1 (chunk 0 class 6, chunk 1 unowned); shard 1 = chunks 2,3
+    pool_ids = [0, 1, 2, 3]
+    good = build_snapshot(N, log2C, 0, 1, cls, cnt, bits, [1, 1], pool_ids, {(0, 6): (0, 0, [0]), (1, 0): (0, 0, [2])},
+                          S=2, log2_span=1)
+    assert not O.check_snapshot(good).violations(), O.check_snapshot(good).violations()
+    bad = build_snapshot(N, log2C, 0, 1, cls, cnt, bits, [1, 1], pool_ids, {(0, 6): (0, 0, [0]), (0, 0): (0, 0, [2])},
+                         S=2, log2_span=1)
+    v = O.check_snapshot(bad).violations()
+    assert v.get("bad_ring_entry", 0) == 1 and v.get("bad_ring_missing", 0) == 1
+    bad = build_snapshot(N, log2C, 0, 1, cls, cnt, bits, [1, 0], [0, 1, 3, 2], {(0, 6): (0, 0, [0]), (1, 0): (0, 0, [2])},
+                         S=2, log2_span=1)
+    assert O.check_snapshot(bad).violations().get("bad_pool", 0) > 0
 
 
 def test_blocks_in_snapshot():
