@@ -13,16 +13,21 @@ successful (alloc + free) ops / alloc+free launch time over iterations
 The whole step's wall time (payload write/check and trims included) is
 ms_per_step, and all ops over it is wall_ops_per_s.
 
+The headline runs the page-queue variant (the faster one on this workload);
+the chunk-queue variant runs the same sweep for one step beside it.
+
 Also measured in the same process:
-  * the device atomic ceilings (same-address, 1024 lines, per-lane random);
+  * the device atomic ceilings (same address, 64 and 1024 lines, per-lane
+    random addresses);
   * a counting pass with the heap's statistics flag, giving the exact
-    atomics issued per launch by target (class state word, head/tail, pool,
-    per-lane); the roofline compares the busiest word's atomics per launch
-    over the launch time against the measured same-address ceiling;
+    atomics issued per launch by target; the roofline compares all atomics
+    of the allocation launch per second with the measured device atomic
+    throughput, and the busiest queue word with the same-address ceiling;
   * the plain baseline: the runtime's own per-thread device malloc/free;
   * the CPU baseline: the sequential oracle on a bounded sample, one core.
 
-Prints one JSON line.  Only --gpus 1 is supported.
+Prints one JSON line.  Only --gpus 1 is supported.  `--copy-probe BYTES`
+only runs the HBM copy kernel (to calibrate traffic counters).
 """
 from __future__ import annotations
 
@@ -44,15 +49,17 @@ def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--iters", type=int, default=10, help="alloc-write-check-free iterations per size")
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--variant", choices=["chunk", "page"], default="chunk")
+    ap.add_argument("--iters", type=int, default=10, help="alloc-write-check-free iterations per size")
+    ap.add_argument("--variant", choices=["chunk", "page"], default="page")
     ap.add_argument("--width", type=int, default=64)
     ap.add_argument("--shards", type=int, default=0, help="queue shards (0: one per 256 chunks, up to 64)")
+    ap.add_argument("--no-other", action="store_true", help="skip the other queue variant")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain device-malloc baseline")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--sizes", type=str, default="", help="comma list overriding the 16..8192 sweep")
+    ap.add_argument("--copy-probe", type=int, default=0, help="only run an HBM copy of this many bytes")
     return ap.parse_args()
 
 
@@ -79,16 +86,31 @@ def main():
         log("no GPU visible")
         sys.exit(3)
     dev = torch.device("cuda:0")
-    stream = torch.cuda.current_stream()
-    w = inputs.SWEEP
-    n = w.threads
-    sizes_list = [int(x) for x in args.sizes.split(",")] if args.sizes else list(inputs.SWEEP_SIZES)
-    variant = hb.VARIANT_CHUNK if args.variant == "chunk" else hb.VARIANT_PAGE
 
     def ev():
         return torch.cuda.Event(enable_timing=True)
 
-    # ---------------- atomic ceilings and HBM copy ----------------
+    if args.copy_probe:
+        nbytes = args.copy_probe // 16 * 16
+        a = torch.ones(nbytes, dtype=torch.uint8, device=dev)
+        b = torch.empty_like(a)
+        ts = []
+        for _ in range(2):
+            e0, e1 = ev(), ev()
+            e0.record()
+            hb.hb_stream_copy(b, a, nbytes)
+            e1.record()
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1) / 1e3)
+        print(json.dumps({"copy_bytes_read": nbytes, "copy_bytes_written": nbytes, "launches": 2,
+                          "gb_per_s": 2 * nbytes / min(ts) / 1e9}), flush=True)
+        return
+
+    w = inputs.SWEEP
+    n = w.threads
+    sizes_list = [int(x) for x in args.sizes.split(",")] if args.sizes else list(inputs.SWEEP_SIZES)
+
+    # ---------------- atomic ceilings ----------------
     def probe(pattern, lines, threads, iters):
         buf = torch.zeros(64 << 20, dtype=torch.uint8, device=dev)
         best = None
@@ -110,144 +132,161 @@ def main():
     log(f"atomic ceilings: same-address {ceil_same/1e9:.3f} G/s, 64 lines {ceil_64/1e9:.2f} G/s, "
         f"1024 lines {ceil_lines/1e9:.2f} G/s, per-lane random {ceil_spread/1e9:.2f} G/s")
 
-    # ---------------- allocator sweep ----------------
-    heap = hb.Heap(w.heap_bytes, w.chunk_bytes, variant=variant, width=args.width, shards=args.shards)
-    heap_shards = int(heap.info.n_shards)
+    size_dev = {s: torch.from_numpy(inputs.sizes_fixed(n, s).view(np.int64)).to(dev) for s in sizes_list}
     ptrs = torch.zeros(n, dtype=torch.int64, device=dev)
     mism = torch.zeros(1, dtype=torch.int64, device=dev)
-    size_dev = {s: torch.from_numpy(inputs.sizes_fixed(n, s).view(np.int64)).to(dev) for s in sizes_list}
-
-    iters = args.iters
-
-    def one_size(s, rec):
-        sd = size_dev[s]
-        for it in range(iters):
-            e = [ev() for _ in range(4)]
-            e[0].record()
-            heap.alloc(sd, ptrs)
-            e[1].record()
-            hb.heap_pattern_write(heap.h, ptrs, sd, w.seed)
-            hb.heap_pattern_check(heap.h, ptrs, sd, w.seed, mism)
-            ok = (ptrs != 0).sum()
-            e[2].record()
-            heap.free(ptrs)
-            e[3].record()
-            rec.append((s, it, e, ok))
-        heap.trim()
-
-    def run_step(rec):
-        for s in sizes_list:
-            one_size(s, rec)
-
-    # counting pass: exact atomics per launch by target, for the first
-    # iteration after a trim and for a subsequent one
     keys = ("state_ops", "headtail_ops", "pool_ops", "spread_ops")
-    counts = {}
-    heap.set_flags(hb.FLAG_STATS)
-    for s in sizes_list:
-        sd = size_dev[s]
-        counts[s] = {}
-        for phase in ("first", "subsequent"):
-            before = heap.stats()
-            heap.alloc(sd, ptrs)
-            torch.cuda.synchronize()
-            mid = heap.stats()
-            heap.free(ptrs)
-            torch.cuda.synchronize()
-            after = heap.stats()
-            counts[s][phase] = {"alloc": {k: mid[k] - before[k] for k in keys},
-                                "free": {k: after[k] - mid[k] for k in keys}}
-        heap.trim()
-    heap.set_flags(0)
-    assert heap.error() == 0, "heap error during counting pass"
 
-    warm = []
-    for _ in range(args.warmup):
-        run_step(warm)
-    torch.cuda.synchronize()
+    def run_sweep(variant_name: str, steps: int, warmup: int, count: bool) -> dict:
+        variant = hb.VARIANT_CHUNK if variant_name == "chunk" else hb.VARIANT_PAGE
+        heap = hb.Heap(w.heap_bytes, w.chunk_bytes, variant=variant, width=args.width, shards=args.shards)
+        shards = int(heap.info.n_shards)
 
-    recs = []
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        run_step(recs)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
+        def one_size(s, rec):
+            sd = size_dev[s]
+            for it in range(args.iters):
+                e = [ev() for _ in range(4)]
+                e[0].record()
+                heap.alloc(sd, ptrs)
+                e[1].record()
+                hb.heap_pattern_write(heap.h, ptrs, sd, w.seed)
+                hb.heap_pattern_check(heap.h, ptrs, sd, w.seed, mism)
+                ok = (ptrs != 0).sum()
+                e[2].record()
+                heap.free(ptrs)
+                e[3].record()
+                rec.append((s, it, e, ok))
+            heap.trim()
 
-    if int(mism.item()) != 0:
-        log(f"PAYLOAD MISMATCHES: {int(mism.item())}")
-        sys.exit(4)
-    err = heap.error()
-    if err:
-        log(f"HEAP ERROR WORD {err:#x}")
-        sys.exit(5)
+        def run_step(rec):
+            for s in sizes_list:
+                one_size(s, rec)
 
-    per_size = {s: {"alloc_us": [], "free_us": [], "ok": 0} for s in sizes_list}
-    sub_ops = sub_t = all_ops = all_t = 0.0
-    t_alloc_sub, t_free_sub = [], []
-    for s, it, e, ok in recs:
-        ta = e[0].elapsed_time(e[1]) / 1e3
-        tf = e[2].elapsed_time(e[3]) / 1e3
-        okv = int(ok.item())
-        all_ops += 2 * okv
-        all_t += ta + tf
-        if it > 0:
-            sub_ops += 2 * okv
-            sub_t += ta + tf
-            t_alloc_sub.append(ta)
-            t_free_sub.append(tf)
-            per_size[s]["alloc_us"].append(ta * 1e6)
-            per_size[s]["free_us"].append(tf * 1e6)
-        per_size[s]["ok"] = okv
-    value = sub_ops / sub_t
-    ms_per_step = wall / args.steps * 1e3
+        # counting pass: exact atomics per launch by target, for the first
+        # iteration after a trim and for a subsequent one
+        counts = {}
+        if count:
+            heap.set_flags(hb.FLAG_STATS)
+            for s in sizes_list:
+                sd = size_dev[s]
+                counts[s] = {}
+                for phase in ("first", "subsequent"):
+                    before = heap.stats()
+                    heap.alloc(sd, ptrs)
+                    torch.cuda.synchronize()
+                    mid = heap.stats()
+                    heap.free(ptrs)
+                    torch.cuda.synchronize()
+                    after = heap.stats()
+                    counts[s][phase] = {"alloc": {k: mid[k] - before[k] for k in keys},
+                                        "free": {k: after[k] - mid[k] for k in keys}}
+                heap.trim()
+            heap.set_flags(0)
+            assert heap.error() == 0, "heap error during counting pass"
 
-    # roofline of the dominant kernel, k_alloc_batch: all atomics it issues
-    # (counted exactly in the counting pass, by target) per launch over the
-    # average launch time of every non-counting allocation launch of this
-    # process (warmup + timed: the population a kernel trace of this command
-    # averages over), against the measured device atomic throughput; the
-    # busiest queue word (a class state word, spread over the shards) is
-    # compared with the same-address ceiling
-    alloc_launch_t, atomics, state_atomics = [], 0, 0
-    for s, it, e, ok in warm + recs:
-        alloc_launch_t.append(e[0].elapsed_time(e[1]) / 1e3)
-        cnt = counts[s]["first" if it == 0 else "subsequent"]["alloc"]
-        atomics += sum(cnt.values())
-        state_atomics += cnt["state_ops"]
-    t_sum = sum(alloc_launch_t)
-    achieved = atomics / t_sum
-    shards = heap_shards
-    busiest = state_atomics / shards / t_sum
-    roofline = {
-        "bound": "atomic",
-        "kernel": "k_alloc_batch<false>",
-        "achieved": achieved / 1e9,
-        "peak": ceil_spread / 1e9,
-        "unit": "Gatomic/s (device-scope atomics issued; peak = measured per-lane random atomic throughput)",
-        "frac": achieved / ceil_spread,
-        "traffic": None,
-        "avg_launch_us": float(np.mean(alloc_launch_t)) * 1e6,
-        "launches": len(alloc_launch_t),
-        "atomics_per_launch": atomics / len(alloc_launch_t),
-        "busiest_word": {"achieved": busiest / 1e9, "peak": ceil_same / 1e9, "frac": busiest / ceil_same,
-                         "state_word_atomics_per_launch": state_atomics / len(alloc_launch_t), "shards": shards},
-        "alloc_share_of_alloc_free_time": sum(t_alloc_sub) / (sum(t_alloc_sub) + sum(t_free_sub)),
-    }
+        warm = []
+        for _ in range(warmup):
+            run_step(warm)
+        torch.cuda.synchronize()
+        recs = []
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            run_step(recs)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
 
-    sizes_summary = {
-        str(s): {
-            "ok": v["ok"],
-            "alloc_us": round(float(np.mean(v["alloc_us"])), 1),
-            "free_us": round(float(np.mean(v["free_us"])), 1),
-            "ops_per_s": round(2 * v["ok"] / ((np.mean(v["alloc_us"]) + np.mean(v["free_us"])) * 1e-6), 0),
-            "atomics_per_op_subsequent": {
-                ph: {k: round(c / max(1, v["ok"]), 4) for k, c in counts[s]["subsequent"][ph].items()}
-                for ph in ("alloc", "free")
+        if int(mism.item()) != 0:
+            log(f"PAYLOAD MISMATCHES: {int(mism.item())}")
+            sys.exit(4)
+        err = heap.error()
+        heap.close()
+        if err:
+            log(f"HEAP ERROR WORD {err:#x}")
+            sys.exit(5)
+
+        per_size = {s: {"alloc_us": [], "free_us": [], "ok": 0} for s in sizes_list}
+        sub_ops = sub_t = all_ops = all_t = 0.0
+        t_alloc_sub, t_free_sub = [], []
+        for s, it, e, ok in recs:
+            ta = e[0].elapsed_time(e[1]) / 1e3
+            tf = e[2].elapsed_time(e[3]) / 1e3
+            okv = int(ok.item())
+            all_ops += 2 * okv
+            all_t += ta + tf
+            if it > 0:
+                sub_ops += 2 * okv
+                sub_t += ta + tf
+                t_alloc_sub.append(ta)
+                t_free_sub.append(tf)
+                per_size[s]["alloc_us"].append(ta * 1e6)
+                per_size[s]["free_us"].append(tf * 1e6)
+            per_size[s]["ok"] = okv
+        out = {
+            "variant": variant_name,
+            "shards": shards,
+            "value": sub_ops / sub_t,
+            "value_all_iterations": all_ops / all_t,
+            "ms_per_step": wall / steps * 1e3,
+            "wall_ops_per_s": all_ops / wall,
+            "batch_latency_us": {
+                "alloc_p50": pct(t_alloc_sub, 50) * 1e6, "alloc_p99": pct(t_alloc_sub, 99) * 1e6,
+                "free_p50": pct(t_free_sub, 50) * 1e6, "free_p99": pct(t_free_sub, 99) * 1e6,
+            },
+            "per_size": {
+                str(s): {
+                    "ok": v["ok"],
+                    "alloc_us": round(float(np.mean(v["alloc_us"])), 1),
+                    "free_us": round(float(np.mean(v["free_us"])), 1),
+                    "ops_per_s": round(2 * v["ok"] / ((np.mean(v["alloc_us"]) + np.mean(v["free_us"])) * 1e-6), 0),
+                }
+                for s, v in per_size.items()
             },
         }
-        for s, v in per_size.items()
-    }
-    heap.close()
+        if count:
+            for s in sizes_list:
+                out["per_size"][str(s)]["atomics_per_op_subsequent"] = {
+                    ph: {k: round(c / max(1, per_size[s]["ok"]), 4) for k, c in counts[s]["subsequent"][ph].items()}
+                    for ph in ("alloc", "free")}
+            # roofline of the dominant kernel, k_alloc_batch: all atomics it
+            # issues (counted in the counting pass) per launch over the average
+            # time of every non-counting allocation launch of this sweep
+            # (warmup + timed: the population a kernel trace averages over),
+            # against the measured device atomic throughput; the busiest queue
+            # word (a class state word, spread over the shards) against the
+            # same-address ceiling
+            alloc_t, atomics, state_atomics = [], 0, 0
+            for s, it, e, ok in warm + recs:
+                alloc_t.append(e[0].elapsed_time(e[1]) / 1e3)
+                cnt = counts[s]["first" if it == 0 else "subsequent"]["alloc"]
+                atomics += sum(cnt.values())
+                state_atomics += cnt["state_ops"]
+            t_sum = sum(alloc_t)
+            achieved = atomics / t_sum
+            busiest = state_atomics / shards / t_sum
+            out["roofline"] = {
+                "bound": "atomic",
+                "kernel": "k_alloc_batch<false>",
+                "achieved": achieved / 1e9,
+                "peak": ceil_spread / 1e9,
+                "unit": "Gatomic/s (device-scope atomics issued; peak = measured per-lane random atomic throughput)",
+                "frac": achieved / ceil_spread,
+                "traffic": None,
+                "avg_launch_us": float(np.mean(alloc_t)) * 1e6,
+                "launches": len(alloc_t),
+                "atomics_per_launch": atomics / len(alloc_t),
+                "busiest_word": {"achieved": busiest / 1e9, "peak": ceil_same / 1e9, "frac": busiest / ceil_same,
+                                 "state_word_atomics_per_launch": state_atomics / len(alloc_t), "shards": shards},
+                "alloc_share_of_alloc_free_time": sum(t_alloc_sub) / (sum(t_alloc_sub) + sum(t_free_sub)),
+            }
+        return out
+
+    head = run_sweep(args.variant, args.steps, args.warmup, count=True)
+    log(f"{args.variant}: {head['value']/1e9:.2f} G ops/s (iterations 2..10)")
+    other = None
+    if not args.no_other:
+        other_name = "chunk" if args.variant == "page" else "page"
+        other = run_sweep(other_name, 1, 1, count=False)
+        log(f"{other_name}: {other['value']/1e9:.2f} G ops/s (iterations 2..10)")
 
     # ---------------- plain baseline: runtime device malloc/free ----------------
     plain = None
@@ -280,9 +319,12 @@ def main():
             log(f"plain size={s} threads={nn} ok={ok} {2*ok/t/1e6:.2f} M ops/s")
         plain["value_full_size_sizes"] = tot_ops / tot_t if tot_t else None
         # ours over the same sizes (those the plain kernel ran at 2^20 threads)
-        o_ops = sum(2 * per_size[s]["ok"] for s in sizes_list if s <= 1024)
-        o_t = sum((np.mean(per_size[s]["alloc_us"]) + np.mean(per_size[s]["free_us"])) * 1e-6
-                  for s in sizes_list if s <= 1024)
+        o_ops = o_t = 0.0
+        for s in sizes_list:
+            if s <= 1024:
+                v = head["per_size"][str(s)]
+                o_ops += 2 * v["ok"]
+                o_t += (v["alloc_us"] + v["free_us"]) * 1e-6
         plain["ours_same_sizes"] = o_ops / o_t if o_t else None
 
     # ---------------- CPU baseline: the oracle on a bounded sample ----------------
@@ -290,11 +332,11 @@ def main():
     if not args.no_cpu:
         import oracle as O
         O.build(force=False)
+        variant = hb.VARIANT_CHUNK if args.variant == "chunk" else hb.VARIANT_PAGE
         t_cpu, cpu_ops, passes = 0.0, 0, 0
-        sample_sizes = sizes_list
         while t_cpu < args.cpu_seconds and passes < 50:
             h = O.OracleHeap(w.heap_bytes, w.chunk_bytes, variant)
-            for s in sample_sizes:
+            for s in sizes_list:
                 sz = inputs.sizes_fixed(n, s)
                 c0 = time.perf_counter()
                 offs = h.alloc_batch(sz)
@@ -305,18 +347,18 @@ def main():
             h.close()
             passes += 1
         cpu = {"value": cpu_ops / t_cpu, "unit": "ops/s", "cores": 1, "kind": "oracle",
-               "sample": f"{passes} pass(es) of the sweep ({len(sample_sizes)} sizes x 2^20 alloc+free, trim "
+               "sample": f"{passes} pass(es) of the sweep ({len(sizes_list)} sizes x 2^20 alloc+free, trim "
                          f"between sizes) through the sequential oracle, {t_cpu:.1f} s",
                "cpu_model": _cpu_model(), "host_cores_available": os.cpu_count()}
 
     out = {
         "metric": "device malloc+free ops/sec (2^20 threads, 16B-8KiB) vs plain; p99 batch latency",
-        "value": value,
+        "value": head["value"],
         "unit": "ops/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
+        "ms_per_step": head["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -328,20 +370,18 @@ def main():
                         "iterations 2..10",
             "variant": args.variant,
             "aggregation_width": args.width,
-            "shards": heap_shards,
-            "iterations_per_size": iters,
+            "shards": head["shards"],
+            "iterations_per_size": args.iters,
             "sizes": sizes_list,
         },
-        "value_all_iterations": all_ops / all_t,
-        "wall_ops_per_s": all_ops / wall,
-        "batch_latency_us": {
-            "alloc_p50": pct(t_alloc_sub, 50) * 1e6, "alloc_p99": pct(t_alloc_sub, 99) * 1e6,
-            "free_p50": pct(t_free_sub, 50) * 1e6, "free_p99": pct(t_free_sub, 99) * 1e6,
-        },
-        "roofline": roofline,
+        "value_all_iterations": head["value_all_iterations"],
+        "wall_ops_per_s": head["wall_ops_per_s"],
+        "batch_latency_us": head["batch_latency_us"],
+        "roofline": head["roofline"],
         "atomic_ceilings_gps": {"same_address": ceil_same / 1e9, "lines_64": ceil_64 / 1e9,
                                 "lines_1024": ceil_lines / 1e9, "per_lane_random": ceil_spread / 1e9},
-        "per_size": sizes_summary,
+        "per_size": head["per_size"],
+        "other_variant": other,
         "plain": plain,
         "vs_plain": (plain["ours_same_sizes"] / plain["value_full_size_sizes"])
         if plain and plain["value_full_size_sizes"] and plain["ours_same_sizes"] else None,

@@ -567,22 +567,27 @@ static int step(ctx* x, mstate* s, int l)
         else { L->pc = 26; }
         return 1;
     case 24: {
+        /* takers read their slots; the bits are cleared afterwards */
         uint8_t* sl = &s->slot[(uint8_t)(L->h0 + L->i) % Q];
         if (*sl == M_EMPTY) return 0;
         L->c[L->i] = *sl;
         *sl = M_EMPTY;
         L->tok[L->i] = 1;
+        if (++L->i < L->got) return 1;
+        L->i = 0;
         L->pc = 25;
         return 1;
     }
     case 25: {
+        /* clear the bits of the taken pages, one lane per step (the device
+         * combines lanes of one word into a single atomicAnd) */
         uint8_t pg = L->c[L->i];
         uint8_t bit = (uint8_t)(1u << (pg % P));
         if (!(s->bits[pg / P] & bit)) violation(x, 80, &x->r->token_violations);
         s->bits[pg / P] = (uint8_t)(s->bits[pg / P] & ~bit);
         L->tok[L->i] = 0;
         L->granted[L->op][L->served + L->i] = pg;
-        if (++L->i < L->got) { L->pc = 24; return 1; }
+        if (++L->i < L->got) return 1;
         L->need = (uint8_t)(L->need - L->got);
         L->served = (uint8_t)(L->served + L->got);
         L->pc = 26;
