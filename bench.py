@@ -26,6 +26,11 @@ Also measured in the same process:
   * the plain baseline: the runtime's own per-thread device malloc/free;
   * the CPU baseline: the sequential oracle on a bounded sample, one core.
 
+roofline.traffic is the HBM bytes per allocation launch (FETCH_SIZE and
+WRITE_SIZE counters, scaled by the same counters' reading for a copy of known
+size) recorded in the counter summary under profiles/; it is null once the
+kernel sources differ from the digest stored there.
+
 Prints one JSON line.  Only --gpus 1 is supported.  `--copy-probe BYTES`
 only runs the HBM copy kernel (to calibrate traffic counters).
 """
@@ -61,6 +66,38 @@ def parse():
     ap.add_argument("--sizes", type=str, default="", help="comma list overriding the 16..8192 sweep")
     ap.add_argument("--copy-probe", type=int, default=0, help="only run an HBM copy of this many bytes")
     return ap.parse_args()
+
+
+# sources that make up the allocation kernel; the traffic recorded with the
+# hardware counters is only reported while their digest is unchanged
+KERNEL_SOURCES = ("paper_2504_18211_amd/csrc/hbheap.hip", "include/hbheap_device.h", "include/hbheap_types.h")
+TRAFFIC_RECORD = "profiles/k_alloc_batch_sweep_4GiB_page_traffic.md"
+
+
+def kernel_digest() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def recorded_traffic():
+    """HBM bytes per allocation launch from the counter summary, or None when
+    there is none or the kernel sources changed since it was taken."""
+    try:
+        text = open(os.path.join(ROOT, TRAFFIC_RECORD)).read()
+    except OSError:
+        return None
+    kv = {}
+    for line in text.splitlines():
+        if ":" in line and line.strip().startswith(("traffic_bytes_per_launch", "kernel_source_sha256")):
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.strip()
+    if kv.get("kernel_source_sha256") != kernel_digest() or "traffic_bytes_per_launch" not in kv:
+        return None
+    return float(kv["traffic_bytes_per_launch"])
 
 
 def pct(a, q):
@@ -270,7 +307,7 @@ def main():
                 "peak": ceil_spread / 1e9,
                 "unit": "Gatomic/s (device-scope atomics issued; peak = measured per-lane random atomic throughput)",
                 "frac": achieved / ceil_spread,
-                "traffic": None,
+                "traffic": recorded_traffic(),
                 "avg_launch_us": float(np.mean(alloc_t)) * 1e6,
                 "launches": len(alloc_t),
                 "atomics_per_launch": atomics / len(alloc_t),

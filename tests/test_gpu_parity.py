@@ -333,3 +333,53 @@ def test_sweep_full_size(hb, variant):
             heap.trim()
             assert heap.snapshot() == fresh
         assert heap.error() == 0
+
+
+# ---------------------------------------------------------------------------
+# mixed-size churn at full size: 8 GiB heap, 2^21 threads, log-uniform sizes
+# in [4 B, 8 KiB], a random half freed and reallocated per round, 20 rounds
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("variant", VARIANTS)
+def test_churn_full_size(hb, variant):
+    import torch
+    w = inputs.CHURN
+    n, seed = w.threads, w.seed
+    sizes = inputs.sizes_log_uniform(n, 4, 8 * KiB, seed)
+    ref = O.OracleHeap(w.heap_bytes, w.chunk_bytes, variant)
+    ref_offs = ref.alloc_batch(sizes)
+    with hb.Heap(w.heap_bytes, w.chunk_bytes, variant=variant) as heap:
+        _same_shards(heap, w.heap_bytes, w.chunk_bytes, 0)
+        fresh = heap.snapshot()
+        ptrs = zeros_i64(n)
+        heap.alloc(dev_u64(sizes), ptrs)
+        for r in range(w.rounds + 1):
+            say(f"case churn-full variant={variant} round={r}")
+            if r:
+                idx, new_sizes = inputs.churn_round(n, r, seed)
+                idx_d = torch.from_numpy(idx).to("cuda")
+                victims = ptrs[idx_d].contiguous()
+                st = torch.zeros(len(idx), dtype=torch.int32, device="cuda")
+                heap.free(victims, status=st)
+                assert int((st != 0).sum()) == 0
+                ref.free_batch(ref_offs[idx])
+                sizes[idx] = new_sizes
+                fresh_ptrs = zeros_i64(len(idx))
+                heap.alloc(dev_u64(new_sizes), fresh_ptrs)
+                ptrs[idx_d] = fresh_ptrs
+                ref_offs[idx] = ref.alloc_batch(new_sizes)
+            sd = dev_u64(sizes)
+            # blocks that survived earlier rounds are re-checked with the new ones
+            heap.pattern_write(ptrs, sd, seed + r)
+            assert heap.pattern_check(ptrs, sd, seed + r) == 0
+            offs = offsets(ptrs, heap.base)
+            check_blocks(heap, sizes, offs)
+            if r % 10 == 0:
+                snap, srep = check_snapshot(heap)
+                assert live_of(srep) == ref.accounting()["live"]
+                assert O.check_blocks_in_snapshot(snap, sizes, offs) == 0
+                say(f"  chunks in use {heap.info.n_chunks - srep.free_chunks} of {heap.info.n_chunks}")
+        heap.free(ptrs)
+        heap.trim()
+        assert heap.snapshot() == fresh
+        assert heap.error() == 0
