@@ -117,6 +117,9 @@ def lib():
             "orc_fmix32": (u32, [u32]),
             "orc_pattern_word": (u32, [u32, u32, u32]),
             "orc_pattern_fill": (None, [u32, u32, vp, u64]),
+            "orc_pattern_sum": (u32, [u32, u32, u64]),
+            "orc_classes": (None, [vp, u64, u64, vp]),
+            "orc_pattern_sums": (None, [u32, vp, vp, u64, vp]),
             "orc_check_blocks": (C.c_int, [u64, u64, vp, vp, u64, C.POINTER(BlocksReport)]),
             "orc_check_snapshot": (C.c_int, [vp, u64, C.POINTER(SnapReport)]),
             "orc_check_blocks_in_snapshot": (u64, [vp, u64, vp, vp, u64]),
@@ -198,6 +201,13 @@ def _ptr(a: np.ndarray):
 
 def class_of(n: int, chunk_bytes: int) -> int:
     return int(lib().orc_class_of(n, chunk_bytes))
+
+
+def classes(sizes: np.ndarray, chunk_bytes: int) -> np.ndarray:
+    sizes = np.ascontiguousarray(sizes, dtype=np.uint64)
+    out = np.empty(len(sizes), dtype=np.int8)
+    lib().orc_classes(_ptr(sizes), len(sizes), chunk_bytes, _ptr(out))
+    return out
 
 
 def num_classes(chunk_bytes: int) -> int:
@@ -311,6 +321,18 @@ def pattern_bytes(seed: int, req: int, nbytes: int) -> bytes:
     buf = np.empty(nbytes, dtype=np.uint8)
     lib().orc_pattern_fill(seed & 0xFFFFFFFF, req & 0xFFFFFFFF, _ptr(buf), nbytes)
     return buf.tobytes()
+
+
+def pattern_sum(seed: int, req: int, nbytes: int) -> int:
+    return int(lib().orc_pattern_sum(seed & 0xFFFFFFFF, req & 0xFFFFFFFF, nbytes))
+
+
+def pattern_sums(seed: int, reqs: np.ndarray, sizes: np.ndarray) -> np.ndarray:
+    reqs = np.ascontiguousarray(reqs, dtype=np.uint64)
+    sizes = np.ascontiguousarray(sizes, dtype=np.uint64)
+    out = np.empty(len(reqs), dtype=np.uint32)
+    lib().orc_pattern_sums(seed & 0xFFFFFFFF, _ptr(reqs), _ptr(sizes), len(reqs), _ptr(out))
+    return out
 
 
 # --------------------------------------------------------------------------

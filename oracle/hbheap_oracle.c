@@ -64,6 +64,11 @@ int orc_class_of(uint64_t n, uint64_t chunk_bytes)
     return (int)k;
 }
 
+void orc_classes(const uint64_t* sizes, uint64_t n, uint64_t chunk_bytes, int8_t* out)
+{
+    for (uint64_t i = 0; i < n; ++i) out[i] = (int8_t)orc_class_of(sizes[i], chunk_bytes);
+}
+
 /* Shards: runs of 2^log2_span consecutive chunks, as many as needed to
  * cover N; the span is the smallest power of two >= ceil(N / requested).
  * requested == 0: one shard per 256 chunks, doubling up to 64. */
@@ -510,6 +515,26 @@ void orc_pattern_fill(uint32_t seed, uint32_t req, uint8_t* dst, uint64_t nbytes
         uint32_t w = orc_pattern_word(seed, req, (uint32_t)(b / 4));
         dst[b] = (uint8_t)(w >> (8 * (b % 4)));
     }
+}
+
+/* Checksum of a block holding the pattern: the 32-bit wrap-around sum of
+ * its little-endian words, a partial last word taken with its missing high
+ * bytes as zero. */
+uint32_t orc_pattern_sum(uint32_t seed, uint32_t req, uint64_t nbytes)
+{
+    uint32_t s = 0;
+    for (uint64_t j = 0; j * 4 < nbytes; ++j) {
+        uint32_t w = orc_pattern_word(seed, req, (uint32_t)j);
+        const uint64_t have = nbytes - j * 4;
+        if (have < 4) w &= (1u << (8 * have)) - 1u;
+        s += w;
+    }
+    return s;
+}
+
+void orc_pattern_sums(uint32_t seed, const uint64_t* reqs, const uint64_t* sizes, uint64_t n, uint32_t* out)
+{
+    for (uint64_t i = 0; i < n; ++i) out[i] = orc_pattern_sum(seed, (uint32_t)reqs[i], sizes[i]);
 }
 
 /* ------------------------------------------------------------------ */

@@ -46,6 +46,7 @@ enum { ORC_FREE_OK = 0, ORC_FREE_DOUBLE = 1, ORC_FREE_INVALID = 2, ORC_FREE_NULL
 
 /* ---- closed forms of the geometry (Results: page and chunk allocators) ---- */
 int      orc_class_of(uint64_t n, uint64_t chunk_bytes);   /* -1: NULL request */
+void     orc_classes(const uint64_t* sizes, uint64_t n, uint64_t chunk_bytes, int8_t* out);
 uint32_t orc_num_classes(uint64_t chunk_bytes);
 uint64_t orc_page_bytes(uint32_t k);
 uint64_t orc_pages_per_chunk(uint64_t chunk_bytes, uint32_t k);
@@ -88,6 +89,10 @@ void      orc_replay(orc_heap* h, const int64_t* op, uint64_t n, int64_t* out);
 uint32_t orc_fmix32(uint32_t x);
 uint32_t orc_pattern_word(uint32_t seed, uint32_t req, uint32_t i);
 void     orc_pattern_fill(uint32_t seed, uint32_t req, uint8_t* dst, uint64_t nbytes);
+/* 32-bit wrap-around sum of the little-endian words of the first nbytes of
+ * the pattern (a partial last word zero-extended); batch form per request */
+uint32_t orc_pattern_sum(uint32_t seed, uint32_t req, uint64_t nbytes);
+void     orc_pattern_sums(uint32_t seed, const uint64_t* reqs, const uint64_t* sizes, uint64_t n, uint32_t* out);
 
 /* ---- invariant checker ---- */
 typedef struct {

@@ -9,7 +9,7 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libhbheap.so")
-SOURCES = ["csrc/hbheap.hip", "csrc/plain_baseline.hip"]
+SOURCES = ["csrc/hbheap.hip", "csrc/growth.hip", "csrc/serve.hip", "csrc/plain_baseline.hip"]
 ARCH = "gfx950"
 
 

@@ -3,7 +3,7 @@
  * (C ABI in include/hbheap.h, device API in include/hbheap_device.h).
  *
  * Contents:
- *   - heap creation: state-region layout (snapshot version 1) and init;
+ *   - heap creation: state-region layout (snapshot version 2) and init;
  *   - batch alloc / free kernels (one lane per request, 256-lane blocks);
  *   - single-lane replay kernel;
  *   - quiescent trim: retire fully free chunks, rebuild pool and queues in
@@ -24,6 +24,7 @@
 
 #include "hbheap.h"
 #include "hbheap_device.h"
+#include "pattern.h"
 
 using namespace hbheap::detail;
 
@@ -315,59 +316,7 @@ __global__ void k_trim_ctl(hbheap_dev_t h, const uint32_t* totals, const uint32_
     }
 }
 
-/* ---------------- payload pattern ---------------- */
-
-__device__ __forceinline__ uint32_t fmix32(uint32_t x)
-{
-    x ^= x >> 16;
-    x *= 0x85ebca6bu;
-    x ^= x >> 13;
-    x *= 0xc2b2ae35u;
-    x ^= x >> 16;
-    return x;
-}
-__device__ __forceinline__ uint32_t pat_word(uint32_t sr, uint32_t j) { return fmix32(sr ^ (j * 0x9E3779B9u)); }
-
-/* Bytes [b0, b1) of the block, b0 a multiple of 16; `step` 16-byte units
- * apart per iteration starting at unit `first`. */
-__device__ __forceinline__ void pat_write_range(uint8_t* p, uint64_t size, uint32_t sr, uint64_t first, uint64_t step)
-{
-    const uint64_t nq = size >> 4;
-    uint4* q = (uint4*)p;
-    for (uint64_t u = first; u < nq; u += step) {
-        const uint32_t j = (uint32_t)(u * 4);
-        q[u] = make_uint4(pat_word(sr, j), pat_word(sr, j + 1), pat_word(sr, j + 2), pat_word(sr, j + 3));
-    }
-    if (first == 0) {
-        for (uint64_t b = nq << 4; b < size; ++b) {
-            const uint32_t w = pat_word(sr, (uint32_t)(b >> 2));
-            p[b] = (uint8_t)(w >> (8 * (b & 3)));
-        }
-    }
-}
-
-__device__ __forceinline__ uint32_t pat_check_range(const uint8_t* p, uint64_t size, uint32_t sr, uint64_t first, uint64_t step)
-{
-    const uint64_t nq = size >> 4;
-    const uint4* q = (const uint4*)p;
-    uint32_t bad = 0;
-    for (uint64_t u = first; u < nq; u += step) {
-        const uint32_t j = (uint32_t)(u * 4);
-        const uint4 v = q[u];
-        bad += (v.x != pat_word(sr, j)) + (v.y != pat_word(sr, j + 1)) + (v.z != pat_word(sr, j + 2)) +
-               (v.w != pat_word(sr, j + 3));
-    }
-    if (first == 0) {
-        /* tail bytes, counted per (partial) word */
-        for (uint64_t b = nq << 4; b < size; b += 4) {
-            const uint32_t w = pat_word(sr, (uint32_t)(b >> 2));
-            bool ok = true;
-            for (uint64_t e = b; e < size && e < b + 4; ++e) ok &= p[e] == (uint8_t)(w >> (8 * (e & 3)));
-            bad += ok ? 0u : 1u;
-        }
-    }
-    return bad;
-}
+/* ---------------- payload pattern (pattern.h) ---------------- */
 
 constexpr uint64_t kCoopBytes = 1024;
 
@@ -391,9 +340,12 @@ __global__ void __launch_bounds__(kBatchBlock) k_pattern(void* const* ptrs, cons
         if (check) bad += pat_check_range(p, size, sr, 0, 1);
         else pat_write_range(p, size, sr, 0, 1);
     }
-    /* large blocks: the whole wave writes one block at a time, 16 B per lane */
+    /* large blocks: the active lanes of the wave write one block at a time,
+     * 16 B per lane (the last wave of the grid may be partial) */
     uint64_t big = __ballot(coop);
     const uint32_t me = lane();
+    const uint64_t act = exec_mask();
+    const uint32_t nact = (uint32_t)__popcll(act), r = rank_in(act);
     while (big) {
         const uint32_t l = ctz64(big);
         big &= big - 1ull;
@@ -403,7 +355,7 @@ __global__ void __launch_bounds__(kBatchBlock) k_pattern(void* const* ptrs, cons
         const uint64_t nq = bs >> 4;
         if (check) {
             const uint4* q = (const uint4*)bp;
-            for (uint64_t u = me; u < nq; u += 64) {
+            for (uint64_t u = r; u < nq; u += nact) {
                 const uint32_t j = (uint32_t)(u * 4);
                 const uint4 v = q[u];
                 bad += (v.x != pat_word(bsr, j)) + (v.y != pat_word(bsr, j + 1)) + (v.z != pat_word(bsr, j + 2)) +
@@ -411,7 +363,7 @@ __global__ void __launch_bounds__(kBatchBlock) k_pattern(void* const* ptrs, cons
             }
         } else {
             uint4* q = (uint4*)bp;
-            for (uint64_t u = me; u < nq; u += 64) {
+            for (uint64_t u = r; u < nq; u += nact) {
                 const uint32_t j = (uint32_t)(u * 4);
                 q[u] = make_uint4(pat_word(bsr, j), pat_word(bsr, j + 1), pat_word(bsr, j + 2), pat_word(bsr, j + 3));
             }

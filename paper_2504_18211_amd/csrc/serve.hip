@@ -1,0 +1,590 @@
+/*
+ * serve.hip -- the serving line (C ABI in include/hbheap_serve.h).
+ *
+ * A host loop over arriving batches of allocation and free requests, K
+ * batches in flight on their own streams, admission against the chunks in
+ * use, and one kernel per batch in which every lane serves one request with
+ * dev_malloc / dev_free on the resident heap (Introduction: allocation from
+ * running kernels on a heap the host preallocated).
+ *
+ * Host side, per batch: stage the requests in the slot's pinned buffers,
+ * copy them in, launch, copy the packed results out, record an event; the
+ * loop polls the events, so several batches overlap on the device while
+ * the host admits the next ones.
+ */
+#include <hip/hip_runtime.h>
+
+#include <stdint.h>
+#include <string.h>
+
+#include <algorithm>
+#include <chrono>
+#include <new>
+#include <thread>
+#include <vector>
+
+#include "hbheap_device.h"
+#include "hbheap_serve.h"
+#include "pattern.h"
+
+using namespace hbheap::detail;
+
+namespace {
+
+constexpr uint32_t kServeBlock = 256;
+constexpr uint64_t kServeCoop = 1024;
+constexpr uint32_t kMaxSlots = 16;
+constexpr uint32_t kMaxBatch = 65536;
+constexpr uint32_t kMaxClasses = 16;
+constexpr uint64_t kUsageBytes = 8 * (1 + kMaxClasses);
+
+struct Slot {
+    hipStream_t st = nullptr;
+    hipEvent_t done = nullptr;
+    int64_t* ops_d = nullptr;
+    uint64_t* aux_d = nullptr;
+    uint64_t* res_d = nullptr;
+    int64_t* ops_h = nullptr;   /* pinned */
+    uint64_t* aux_h = nullptr;  /* pinned */
+    uint64_t* res_h = nullptr;  /* pinned */
+    int64_t batch = -1;
+};
+
+}  // namespace
+
+struct hbheap_server {
+    heap_t heap = nullptr;
+    hbheap_dev_t dev;
+    heap_info_t info;
+    serve_config_t cfg;
+    uint64_t* handles = nullptr; /* device, max_requests */
+    std::vector<Slot> slots;
+    hipStream_t mon = nullptr;
+    hipEvent_t mon_done = nullptr;
+    uint64_t* usage_d = nullptr;  /* 1 + kMaxClasses u64 */
+    uint64_t* usage_h = nullptr;  /* pinned, same size */
+    std::vector<uint64_t> class_cap; /* page variant: chunks class k may own */
+};
+
+namespace {
+
+/* ---------------- device ---------------- */
+
+/* out[0]: chunks taken from the pools (per shard, its chunks minus the
+ * pool's remaining ones, size - min(bump, size)); out[1 + k], page variant:
+ * chunks owned by class k over all shards (0 in the chunk variant).  One
+ * wave. */
+__global__ void k_usage(hbheap_dev_t h, uint64_t* out)
+{
+    const uint32_t j = threadIdx.x;
+    uint64_t used = 0;
+    for (uint32_t s = j; s < h.n_shards; s += 64) {
+        const uint64_t* pb = h.pool + 16ull * s;
+        const uint64_t bump = __hip_atomic_load(pb, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const uint32_t size = ((const uint32_t*)pb)[2];
+        const uint64_t lo = (uint64_t)s << h.log2_span;
+        const uint64_t hi = std::min<uint64_t>((uint64_t)h.n_chunks, ((uint64_t)s + 1) << h.log2_span);
+        const uint64_t left = size - std::min<uint64_t>(bump, size);
+        used += (hi - lo) - left;
+    }
+    for (uint32_t o = 32; o; o >>= 1) used += __shfl_xor(used, o);
+    if (j == 0) out[0] = used;
+    for (uint32_t k = j; k < h.n_classes; k += 64) {
+        uint64_t own = 0;
+        if (h.variant == HBHEAP_VARIANT_PAGE)
+            for (uint32_t s = 0; s < h.n_shards; ++s) own += a_load64(owned_of(h, s, k));
+        out[1 + k] = own;
+    }
+}
+
+/* 32-bit sum of the words of [0, size) read back, per lane (units u of 16 B
+ * with u = first, first + step, ...), tail bytes by the lane with first 0. */
+__device__ __forceinline__ uint32_t sum_range(const uint8_t* p, uint64_t size, uint64_t first, uint64_t step)
+{
+    const uint64_t nq = size >> 4;
+    const uint4* q = (const uint4*)p;
+    uint32_t s = 0;
+    for (uint64_t u = first; u < nq; u += step) {
+        const uint4 v = q[u];
+        s += v.x + v.y + v.z + v.w;
+    }
+    if (first == 0) {
+        for (uint64_t b = nq << 4; b < size; ++b) s += (uint32_t)p[b] << (8 * (b & 3));
+    }
+    return s;
+}
+
+/* Sum of v over the active lanes of the wave (any subset), through the
+ * wave's LDS stage word. */
+__device__ __forceinline__ uint32_t wave_sum(uint32_t v, uint32_t leader)
+{
+    uint32_t* acc = (uint32_t*)stage_for_wave();
+    if (lane() == leader) *acc = 0;
+    wave_sync_lds();
+    __hip_atomic_fetch_add(acc, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    wave_sync_lds();
+    const uint32_t t = *acc;
+    wave_sync_lds();
+    return t;
+}
+
+/* One lane per request.  ops[i] >= 0: allocate, write the words, read them
+ * back; ops[i] < 0: read the target block back, then free it.  Blocks of
+ * kServeCoop bytes and more are written and read by all active lanes of the
+ * wave, each lane on the same 16-byte units in both passes (so every lane
+ * reads back what it wrote itself). */
+__global__ void __launch_bounds__(kServeBlock) k_serve_batch(hbheap_dev_t h, const int64_t* ops, const uint64_t* aux,
+                                                             uint32_t n, uint64_t first_req, uint64_t* handles,
+                                                             uint64_t* res, uint32_t seed)
+{
+    const uint64_t i = (uint64_t)blockIdx.x * kServeBlock + threadIdx.x;
+    if (i >= n) return;
+    const uint32_t me = lane();
+    const int64_t op = ops[i];
+    const bool is_alloc = op >= 0;
+    const uint64_t req = first_req + i;
+    uint8_t* p = nullptr;
+    uint64_t size = 0;
+    uint32_t sr = 0;
+    if (is_alloc) {
+        size = (uint64_t)op;
+        sr = seed ^ fmix32((uint32_t)req);
+        p = (uint8_t*)dev_malloc(h, size);
+        handles[req] = (uint64_t)p;
+        if (!p) size = 0;
+    } else {
+        const uint64_t t = (uint64_t)(-(op + 1));
+        p = (uint8_t*)handles[t];
+        size = p ? aux[i] : 0;
+        sr = seed ^ fmix32((uint32_t)t);
+    }
+    int32_t cls = -1;
+    if (p) cls = h.chunk_class[(uint64_t)(p - h.data) >> h.log2_chunk];
+    const bool coop = size >= kServeCoop;
+    const uint64_t act = exec_mask();
+    const uint32_t nact = (uint32_t)__popcll(act), r = rank_in(act);
+    /* write (allocations) */
+    if (is_alloc && size && !coop) pat_write_range(p, size, sr, 0, 1);
+    uint64_t big = __ballot(is_alloc && coop);
+    while (big) {
+        const uint32_t l = ctz64(big);
+        big &= big - 1ull;
+        pat_write_range((uint8_t*)bcast64((uint64_t)p, l), bcast64(size, l), bcast(sr, l), r, nact);
+    }
+    /* read back (both kinds) */
+    uint32_t sum = 0;
+    if (size && !coop) sum = sum_range(p, size, 0, 1);
+    big = __ballot(coop);
+    while (big) {
+        const uint32_t l = ctz64(big);
+        big &= big - 1ull;
+        const uint32_t part = sum_range((const uint8_t*)bcast64((uint64_t)p, l), bcast64(size, l), r, nact);
+        const uint32_t tot = wave_sum(part, l);
+        if (me == l) sum = tot;
+    }
+    uint32_t status = is_alloc ? (p ? SERVE_OK : SERVE_ALLOC_NULL) : SERVE_FREE_NULL;
+    if (!is_alloc) {
+        /* the reads above complete before the block can be handed out again */
+        fence_release();
+        const uint32_t st = free_wave(h, p, 0, false);
+        status = st == kFreeOk ? SERVE_OK : st == kFreeDouble ? SERVE_FREE_DOUBLE
+                                          : st == kFreeInvalid ? SERVE_FREE_INVAL : SERVE_FREE_NULL;
+    }
+    res[i] = (uint64_t)sum | ((uint64_t)status << 32) | ((uint64_t)(uint8_t)(int8_t)cls << 40);
+}
+
+__global__ void k_serve_export(const uint64_t* handles, uint64_t first, uint64_t n, uint64_t* dst)
+{
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) dst[i] = handles[first + i];
+}
+
+/* ---------------- host ---------------- */
+
+using Clock = std::chrono::steady_clock;
+
+uint64_t ns_since(Clock::time_point t0)
+{
+    return (uint64_t)std::chrono::duration_cast<std::chrono::nanoseconds>(Clock::now() - t0).count();
+}
+
+int host_class(uint64_t n, uint64_t chunk)
+{
+    if (n == 0 || n > chunk) return -1;
+    if (n <= 16) return 0;
+    uint32_t r = 0;
+    while ((1ull << r) < n) ++r;
+    return (int)r - 4;
+}
+
+void free_slot(Slot& s)
+{
+    if (s.done) (void)hipEventDestroy(s.done);
+    if (s.st) (void)hipStreamDestroy(s.st);
+    if (s.ops_d) (void)hipFree(s.ops_d);
+    if (s.aux_d) (void)hipFree(s.aux_d);
+    if (s.res_d) (void)hipFree(s.res_d);
+    if (s.ops_h) (void)hipHostFree(s.ops_h);
+    if (s.aux_h) (void)hipHostFree(s.aux_h);
+    if (s.res_h) (void)hipHostFree(s.res_h);
+    s = Slot();
+}
+
+void release(hbheap_server* s)
+{
+    for (Slot& sl : s->slots) free_slot(sl);
+    if (s->mon_done) (void)hipEventDestroy(s->mon_done);
+    if (s->mon) (void)hipStreamDestroy(s->mon);
+    if (s->usage_d) (void)hipFree(s->usage_d);
+    if (s->usage_h) (void)hipHostFree(s->usage_h);
+    if (s->handles) (void)hipFree(s->handles);
+    delete s;
+}
+
+int usage_issue(hbheap_server* s)
+{
+    hipLaunchKernelGGL(k_usage, dim3(1), dim3(64), 0, s->mon, s->dev, s->usage_d);
+    if (hipGetLastError() != hipSuccess) return HBHEAP_E_HIP;
+    return hipMemcpyAsync(s->usage_h, s->usage_d, kUsageBytes, hipMemcpyDeviceToHost, s->mon) == hipSuccess
+               ? HBHEAP_OK : HBHEAP_E_HIP;
+}
+
+int usage_sync(hbheap_server* s)
+{
+    if (usage_issue(s) != HBHEAP_OK) return HBHEAP_E_HIP;
+    return hipStreamSynchronize(s->mon) == hipSuccess ? HBHEAP_OK : HBHEAP_E_HIP;
+}
+
+}  // namespace
+
+extern "C" {
+
+int heap_chunks_in_use(heap_t h, uint64_t* out, hipStream_t stream)
+{
+    if (!h || !out) return HBHEAP_E_INVAL;
+    hbheap_dev_t d;
+    if (heap_device_handle(h, &d) != HBHEAP_OK) return HBHEAP_E_INVAL;
+    uint64_t* dv = nullptr;
+    if (hipMalloc(&dv, kUsageBytes) != hipSuccess) return HBHEAP_E_NOMEM;
+    hipLaunchKernelGGL(k_usage, dim3(1), dim3(64), 0, stream, d, dv);
+    int rc = HBHEAP_OK;
+    if (hipGetLastError() != hipSuccess || hipMemcpyAsync(out, dv, 8, hipMemcpyDeviceToHost, stream) != hipSuccess ||
+        hipStreamSynchronize(stream) != hipSuccess)
+        rc = HBHEAP_E_HIP;
+    (void)hipFree(dv);
+    return rc;
+}
+
+int serve_create(heap_t h, const serve_config_t* cfg, server_t* out)
+{
+    if (!h || !cfg || !out) return HBHEAP_E_INVAL;
+    const serve_config_t c = *cfg;
+    if (c.slots == 0 || c.slots > kMaxSlots || c.max_batch == 0 || c.max_batch > kMaxBatch || c.max_requests == 0 ||
+        c.max_requests > (1ull << 32) || !(c.admit > 0.0 && c.admit <= 1.0) || c.free_lag == 0)
+        return HBHEAP_E_INVAL;
+    hbheap_server* s = new (std::nothrow) hbheap_server();
+    if (!s) return HBHEAP_E_NOMEM;
+    s->heap = h;
+    s->cfg = c;
+    if (heap_device_handle(h, &s->dev) != HBHEAP_OK || heap_info(h, &s->info) != HBHEAP_OK) {
+        delete s;
+        return HBHEAP_E_INVAL;
+    }
+    if (hipMalloc(&s->handles, 8ull * c.max_requests) != hipSuccess) { s->handles = nullptr; release(s); return HBHEAP_E_NOMEM; }
+    if (hipStreamCreate(&s->mon) != hipSuccess || hipEventCreateWithFlags(&s->mon_done, hipEventDisableTiming) != hipSuccess ||
+        hipMalloc(&s->usage_d, kUsageBytes) != hipSuccess ||
+        hipHostMalloc(&s->usage_h, kUsageBytes, hipHostMallocDefault) != hipSuccess) {
+        release(s);
+        return HBHEAP_E_HIP;
+    }
+    /* page variant: class k owns at most min(shard chunks, queue entries /
+     * pages per chunk) chunks of each shard (a request is served from any
+     * shard, so this sum is the class's capacity) */
+    s->class_cap.assign(s->info.n_classes, UINT64_MAX);
+    if (s->info.variant == HBHEAP_VARIANT_PAGE) {
+        const uint64_t N = s->info.n_chunks, span = 1ull << s->dev.log2_span;
+        for (uint32_t k = 0; k < s->info.n_classes; ++k) {
+            const uint64_t per = s->info.ring_entries / (s->info.chunk_bytes >> (4 + k));
+            uint64_t cap = 0;
+            for (uint64_t lo = 0; lo < N; lo += span) cap += std::min(std::min(N, lo + span) - lo, per);
+            s->class_cap[k] = cap;
+        }
+    }
+    s->slots.resize(c.slots);
+    const uint64_t mb = c.max_batch;
+    for (Slot& sl : s->slots) {
+        if (hipStreamCreate(&sl.st) != hipSuccess || hipEventCreateWithFlags(&sl.done, hipEventDisableTiming) != hipSuccess ||
+            hipMalloc(&sl.ops_d, 8 * mb) != hipSuccess || hipMalloc(&sl.aux_d, 8 * mb) != hipSuccess ||
+            hipMalloc(&sl.res_d, 8 * mb) != hipSuccess ||
+            hipHostMalloc(&sl.ops_h, 8 * mb, hipHostMallocDefault) != hipSuccess ||
+            hipHostMalloc(&sl.aux_h, 8 * mb, hipHostMallocDefault) != hipSuccess ||
+            hipHostMalloc(&sl.res_h, 8 * mb, hipHostMallocDefault) != hipSuccess) {
+            release(s);
+            return HBHEAP_E_NOMEM;
+        }
+    }
+    *out = s;
+    return HBHEAP_OK;
+}
+
+int serve_destroy(server_t s)
+{
+    if (!s) return HBHEAP_OK;
+    int rc = HBHEAP_OK;
+    for (Slot& sl : s->slots)
+        if (sl.st && hipStreamSynchronize(sl.st) != hipSuccess) rc = HBHEAP_E_HIP;
+    if (s->mon && hipStreamSynchronize(s->mon) != hipSuccess) rc = HBHEAP_E_HIP;
+    release(s);
+    return rc;
+}
+
+int serve_export(server_t s, uint64_t first, uint64_t n, uint64_t* dst, hipStream_t stream)
+{
+    if (!s || (n && !dst) || first > s->cfg.max_requests || n > s->cfg.max_requests - first) return HBHEAP_E_INVAL;
+    if (!n) return HBHEAP_OK;
+    hipLaunchKernelGGL(k_serve_export, dim3((uint32_t)((n + 255) / 256)), dim3(256), 0, stream, s->handles, first, n,
+                       dst);
+    return hipGetLastError() == hipSuccess ? HBHEAP_OK : HBHEAP_E_HIP;
+}
+
+int serve_run(server_t s, uint32_t nb, const uint64_t* first, const int64_t* ops, const uint64_t* arrival_ns,
+              int alone, uint8_t* status, int8_t* cls, uint32_t* sum, uint64_t* latency_ns, uint64_t* wait_ns,
+              serve_stats_t* stats)
+{
+    if (!s || !first || (nb && !ops) || (!alone && nb && !arrival_ns)) return HBHEAP_E_INVAL;
+    const serve_config_t& c = s->cfg;
+    const uint64_t C = s->info.chunk_bytes;
+    const uint64_t R = nb ? first[nb] : 0;
+    if (first[0] != 0 || R > c.max_requests) return HBHEAP_E_INVAL;
+    const uint32_t K = s->info.n_classes;
+    const bool per_class = s->info.variant == HBHEAP_VARIANT_PAGE;
+
+    /* ---- validate the request list, size the frees, price the batches ---- */
+    std::vector<uint64_t> aux(R, 0);
+    std::vector<uint32_t> worst_k((size_t)nb * K, 0); /* fresh chunks a batch may take, per class */
+    std::vector<uint64_t> worst(nb, 0);
+    std::vector<uint32_t> batch_of(R);
+    std::vector<uint8_t> freed(R, 0);
+    const uint32_t width = s->dev.width ? s->dev.width : 64;
+    for (uint32_t b = 0; b < nb; ++b) {
+        if (first[b + 1] < first[b] || first[b + 1] - first[b] > c.max_batch) return HBHEAP_E_INVAL;
+        if (!alone && b && arrival_ns[b] < arrival_ns[b - 1]) return HBHEAP_E_INVAL;
+        for (uint64_t g0 = first[b]; g0 < first[b + 1]; g0 += width) {
+            /* one aggregation group per (segment of `width` lanes, class):
+             * a group never takes more than ceil(g / pages per chunk) chunks */
+            uint32_t cnt[kMaxClasses] = {0};
+            const uint64_t g1 = std::min<uint64_t>(first[b + 1], g0 + width);
+            for (uint64_t i = g0; i < g1; ++i) {
+                batch_of[i] = b;
+                const int64_t op = ops[i];
+                if (op >= 0) {
+                    const int k = host_class((uint64_t)op, C);
+                    if (k >= 0) ++cnt[k];
+                    continue;
+                }
+                const uint64_t t = (uint64_t)(-(op + 1));
+                if (t >= first[b] || ops[t] < 0 || freed[t] || batch_of[t] + c.free_lag > b) return HBHEAP_E_INVAL;
+                freed[t] = 1;
+                aux[i] = (uint64_t)ops[t];
+            }
+            for (uint32_t k = 0; k < K; ++k) {
+                const uint64_t ppc = C >> (4 + k);
+                const uint32_t w = (uint32_t)((cnt[k] + ppc - 1) / ppc);
+                worst_k[(size_t)b * K + k] += w;
+                worst[b] += w;
+            }
+        }
+    }
+
+    /* ---- the chunk budget ----
+     * bound(now) = base + L, L = worst cases of every batch launched in this
+     * run; a usage read resets base so that the bound is the read value plus
+     * the worst cases of the batches not seen complete when it was issued.
+     * The same per class (page variant), against the class capacities. */
+    const uint64_t cap = (uint64_t)((double)s->info.n_chunks * c.admit);
+    int64_t base = 0;
+    uint64_t L = 0;
+    std::vector<int64_t> base_k(K, 0);
+    std::vector<uint64_t> L_k(K, 0);
+    auto set_exact = [&]() {
+        base = (int64_t)s->usage_h[0] - (int64_t)L;
+        for (uint32_t k = 0; k < K; ++k) base_k[k] = (int64_t)s->usage_h[1 + k] - (int64_t)L_k[k];
+    };
+    auto admissible = [&](uint32_t b) {
+        if (base + (int64_t)(L + worst[b]) > (int64_t)cap) return false;
+        if (per_class)
+            for (uint32_t k = 0; k < K; ++k) {
+                const uint32_t w = worst_k[(size_t)b * K + k];
+                if (w && base_k[k] + (int64_t)(L_k[k] + w) > (int64_t)s->class_cap[k]) return false;
+            }
+        return true;
+    };
+
+    serve_stats_t st;
+    memset(&st, 0, sizeof(st));
+    st.batches = nb;
+    st.requests = R;
+    for (uint64_t i = 0; i < R; ++i) (ops[i] >= 0 ? st.allocs : st.frees) += 1;
+
+    for (Slot& sl : s->slots)
+        if (hipStreamSynchronize(sl.st) != hipSuccess) return HBHEAP_E_HIP;
+    if (usage_sync(s) != HBHEAP_OK) return HBHEAP_E_HIP;
+    set_exact();
+
+    bool mon_busy = false;
+    uint64_t mon_L = 0, mon_out = 0;
+    std::vector<uint64_t> mon_L_k(K, 0), mon_out_k(K, 0);
+    std::vector<uint8_t> done(nb, 0);
+    uint32_t prefix = 0; /* batches [0, prefix) are complete */
+    uint32_t next = 0, inflight = 0;
+    std::vector<uint64_t> launch_ns(nb, 0);
+    bool stalled = false;
+
+    auto finish = [&](Slot& sl, uint64_t now) {
+        const uint32_t b = (uint32_t)sl.batch;
+        const uint64_t f = first[b], n = first[b + 1] - f;
+        for (uint64_t i = 0; i < n; ++i) {
+            const uint64_t r = sl.res_h[i];
+            if (sum) sum[f + i] = (uint32_t)r;
+            if (status) status[f + i] = (uint8_t)(r >> 32);
+            if (cls) cls[f + i] = (int8_t)(uint8_t)(r >> 40);
+        }
+        if (latency_ns) latency_ns[b] = now - (alone ? launch_ns[b] : arrival_ns[b]);
+        done[b] = 1;
+        while (prefix < nb && done[prefix]) ++prefix;
+        sl.batch = -1;
+        --inflight;
+    };
+    auto launch = [&](Slot& sl, uint32_t b, uint64_t now) -> int {
+        const uint64_t f = first[b], n = first[b + 1] - f;
+        sl.batch = b;
+        launch_ns[b] = now;
+        if (wait_ns) wait_ns[b] = alone ? 0 : now - arrival_ns[b];
+        L += worst[b];
+        for (uint32_t k = 0; k < K; ++k) L_k[k] += worst_k[(size_t)b * K + k];
+        st.peak_bound = std::max<uint64_t>(st.peak_bound, (uint64_t)(base + (int64_t)L));
+        ++inflight;
+        if (!n) return hipEventRecord(sl.done, sl.st) == hipSuccess ? HBHEAP_OK : HBHEAP_E_HIP;
+        memcpy(sl.ops_h, ops + f, 8 * n);
+        memcpy(sl.aux_h, aux.data() + f, 8 * n);
+        if (hipMemcpyAsync(sl.ops_d, sl.ops_h, 8 * n, hipMemcpyHostToDevice, sl.st) != hipSuccess ||
+            hipMemcpyAsync(sl.aux_d, sl.aux_h, 8 * n, hipMemcpyHostToDevice, sl.st) != hipSuccess)
+            return HBHEAP_E_HIP;
+        hipLaunchKernelGGL(k_serve_batch, dim3((uint32_t)((n + kServeBlock - 1) / kServeBlock)), dim3(kServeBlock), 0,
+                           sl.st, s->dev, sl.ops_d, sl.aux_d, (uint32_t)n, f, s->handles, sl.res_d, c.seed);
+        if (hipGetLastError() != hipSuccess) return HBHEAP_E_HIP;
+        if (hipMemcpyAsync(sl.res_h, sl.res_d, 8 * n, hipMemcpyDeviceToHost, sl.st) != hipSuccess) return HBHEAP_E_HIP;
+        return hipEventRecord(sl.done, sl.st) == hipSuccess ? HBHEAP_OK : HBHEAP_E_HIP;
+    };
+    /* quiescent trim and exact recount; the caller made sure nothing runs */
+    auto trim_recount = [&]() -> int {
+        if (heap_trim(s->heap, s->mon) != HBHEAP_OK) return HBHEAP_E_HIP;
+        if (usage_sync(s) != HBHEAP_OK) return HBHEAP_E_HIP;
+        set_exact();
+        ++st.trims;
+        return HBHEAP_OK;
+    };
+
+    const Clock::time_point t0 = Clock::now();
+    if (alone) {
+        Slot& sl = s->slots[0];
+        for (uint32_t b = 0; b < nb; ++b) {
+            if (!admissible(b)) {
+                ++st.admission_stalls;
+                if (trim_recount() != HBHEAP_OK) return HBHEAP_E_HIP;
+                if (!admissible(b)) return HBHEAP_E_NOMEM;
+            }
+            if (launch(sl, b, ns_since(t0)) != HBHEAP_OK) return HBHEAP_E_HIP;
+            if (hipEventSynchronize(sl.done) != hipSuccess) return HBHEAP_E_HIP;
+            finish(sl, ns_since(t0));
+            /* nothing in flight: the count is exact after every batch */
+            if (usage_sync(s) != HBHEAP_OK) return HBHEAP_E_HIP;
+            set_exact();
+        }
+    } else {
+        while (next < nb || inflight) {
+            const uint64_t now = ns_since(t0);
+            bool progress = false;
+            for (Slot& sl : s->slots) {
+                if (sl.batch < 0) continue;
+                const hipError_t q = hipEventQuery(sl.done);
+                if (q == hipSuccess) {
+                    finish(sl, ns_since(t0));
+                    progress = true;
+                } else if (q != hipErrorNotReady) {
+                    return HBHEAP_E_HIP;
+                }
+            }
+            if (mon_busy) {
+                const hipError_t q = hipEventQuery(s->mon_done);
+                if (q == hipSuccess) {
+                    /* exact for every batch seen complete before the read was
+                     * issued; the others keep their worst case */
+                    base = (int64_t)s->usage_h[0] + (int64_t)mon_out - (int64_t)mon_L;
+                    for (uint32_t k = 0; k < K; ++k)
+                        base_k[k] = (int64_t)s->usage_h[1 + k] + (int64_t)mon_out_k[k] - (int64_t)mon_L_k[k];
+                    mon_busy = false;
+                    ++st.monitor_reads;
+                } else if (q != hipErrorNotReady) {
+                    return HBHEAP_E_HIP;
+                }
+            }
+            if (!mon_busy && inflight) {
+                /* worst cases of the batches not yet seen complete */
+                mon_out = 0;
+                std::fill(mon_out_k.begin(), mon_out_k.end(), 0);
+                for (const Slot& sl : s->slots)
+                    if (sl.batch >= 0) {
+                        mon_out += worst[sl.batch];
+                        for (uint32_t k = 0; k < K; ++k) mon_out_k[k] += worst_k[(size_t)sl.batch * K + k];
+                    }
+                if (usage_issue(s) != HBHEAP_OK || hipEventRecord(s->mon_done, s->mon) != hipSuccess)
+                    return HBHEAP_E_HIP;
+                mon_busy = true;
+                mon_L = L;
+                mon_L_k = L_k;
+            }
+            if (next < nb && now >= arrival_ns[next] && prefix + c.free_lag > next) {
+                const uint32_t b = next;
+                Slot* free_sl = nullptr;
+                for (Slot& sl : s->slots)
+                    if (sl.batch < 0) { free_sl = &sl; break; }
+                if (free_sl) {
+                    if (admissible(b)) {
+                        if (launch(*free_sl, b, ns_since(t0)) != HBHEAP_OK) return HBHEAP_E_HIP;
+                        ++next;
+                        stalled = false;
+                        progress = true;
+                    } else {
+                        if (!stalled) ++st.admission_stalls;
+                        stalled = true;
+                        if (!inflight) {
+                            /* quiescent: first an exact count, then, if that
+                             * is not enough, a trim */
+                            if (mon_busy) {
+                                if (hipStreamSynchronize(s->mon) != hipSuccess) return HBHEAP_E_HIP;
+                                mon_busy = false;
+                            }
+                            if (usage_sync(s) != HBHEAP_OK) return HBHEAP_E_HIP;
+                            set_exact();
+                            if (!admissible(b)) {
+                                if (trim_recount() != HBHEAP_OK) return HBHEAP_E_HIP;
+                                if (!admissible(b)) return HBHEAP_E_NOMEM;
+                            }
+                            progress = true;
+                        }
+                    }
+                }
+            }
+            if (!progress) std::this_thread::yield();
+        }
+        if (mon_busy && hipStreamSynchronize(s->mon) != hipSuccess) return HBHEAP_E_HIP;
+    }
+    st.wall_s = (double)ns_since(t0) * 1e-9;
+    if (usage_sync(s) != HBHEAP_OK) return HBHEAP_E_HIP;
+    st.final_chunks = s->usage_h[0];
+    if (stats) *stats = st;
+    return HBHEAP_OK;
+}
+
+}  // extern "C"

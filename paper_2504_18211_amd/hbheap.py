@@ -28,7 +28,11 @@ EXPORTS = [
     "heap_device_handle", "heap_set_flags", "heap_info", "heap_trim", "heap_snapshot", "heap_get_error", "heap_clear_error",
     "heap_stats", "heap_replay", "heap_pattern_write", "heap_pattern_check", "hb_atomic_probe", "hb_stream_copy",
     "hb_plain_set_heap", "hb_plain_alloc", "hb_plain_free", "hbheap_version",
+    "growth_create", "growth_destroy", "growth_step", "growth_graph_launch", "growth_release", "growth_export",
+    "growth_launch_shape", "growth_autotune",
+    "serve_create", "serve_destroy", "serve_run", "serve_export", "heap_chunks_in_use",
 ]
+SERVE_OK, SERVE_FREE_DOUBLE, SERVE_FREE_INVAL, SERVE_FREE_NULL, SERVE_ALLOC_NULL = 0, 1, 2, 3, 4
 
 
 class HbHeapError(RuntimeError):
@@ -47,6 +51,23 @@ class HeapInfo(C.Structure):
                 ("n_chunks", C.c_uint64), ("n_classes", C.c_uint32), ("variant", C.c_uint32),
                 ("ring_entries", C.c_uint64), ("state_bytes", C.c_uint64), ("metadata_bytes", C.c_uint64),
                 ("n_shards", C.c_uint32), ("reserved", C.c_uint32)]
+
+
+class GrowthCandidate(C.Structure):
+    _fields_ = [("chunk_bytes", C.c_uint64), ("variant", C.c_uint32), ("width", C.c_uint32)]
+
+
+class ServeConfig(C.Structure):
+    _fields_ = [("slots", C.c_uint32), ("max_batch", C.c_uint32), ("max_requests", C.c_uint64),
+                ("admit", C.c_double), ("seed", C.c_uint32), ("free_lag", C.c_uint32)]
+
+
+class ServeStats(C.Structure):
+    _fields_ = [(n, C.c_uint64) for n in ("batches", "requests", "allocs", "frees", "trims", "admission_stalls",
+                                          "monitor_reads", "peak_bound", "final_chunks")] + [("wall_s", C.c_double)]
+
+    def as_dict(self) -> dict:
+        return {n: getattr(self, n) for n, _ in self._fields_}
 
 
 class DevHandle(C.Structure):
@@ -95,6 +116,20 @@ def lib():
         "hb_plain_set_heap": [sz],
         "hb_plain_alloc": [vp, vp, sz, vp],
         "hb_plain_free": [vp, sz, vp],
+        "growth_create": [vp, u32, vp, u32, u32, C.POINTER(vp)],
+        "growth_destroy": [vp],
+        "growth_step": [vp, u32, vp],
+        "growth_graph_launch": [vp, vp],
+        "growth_release": [vp, vp],
+        "growth_export": [vp, vp, vp, vp, vp],
+        "growth_launch_shape": [vp, C.POINTER(u32), C.POINTER(u32)],
+        "growth_autotune": [sz, u32, vp, u32, u32, C.POINTER(GrowthCandidate), u32, u32, C.POINTER(C.c_float),
+                            C.POINTER(C.c_int32)],
+        "serve_create": [vp, C.POINTER(ServeConfig), C.POINTER(vp)],
+        "serve_destroy": [vp],
+        "serve_run": [vp, u32, vp, vp, vp, i32, vp, vp, vp, vp, vp, C.POINTER(ServeStats)],
+        "serve_export": [vp, C.c_uint64, C.c_uint64, vp, vp],
+        "heap_chunks_in_use": [vp, C.POINTER(C.c_uint64), vp],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -246,6 +281,105 @@ def hbheap_version() -> str:
     return lib().hbheap_version().decode()
 
 
+# ---- serving line (include/hbheap_serve.h) ----
+
+def serve_create(h: int, slots: int, max_batch: int, max_requests: int, admit: float, seed: int,
+                 free_lag: int) -> int:
+    cfg = ServeConfig(slots, max_batch, max_requests, admit, seed & 0xFFFFFFFF, free_lag)
+    out = C.c_void_p()
+    _check("serve_create", lib().serve_create(h, C.byref(cfg), C.byref(out)))
+    return out.value
+
+
+def serve_destroy(s: int):
+    _check("serve_destroy", lib().serve_destroy(s))
+
+
+def _host(a, dtype):
+    import numpy as np
+    a = np.ascontiguousarray(a, dtype=dtype)
+    return a, a.ctypes.data
+
+
+def serve_run(s: int, first, ops, arrival_ns=None, alone: bool = False):
+    """Host arrays in (numpy); returns dict of per-request status, cls, sum
+    and per-batch latency_ns, wait_ns, plus the run's stats."""
+    import numpy as np
+    nb = len(first) - 1
+    first, pf = _host(first, np.uint64)
+    ops, po = _host(ops, np.int64)
+    if arrival_ns is not None:
+        arrival_ns, pa = _host(arrival_ns, np.uint64)
+    else:
+        pa = None
+    R = int(first[-1]) if nb else 0
+    status = np.zeros(R, dtype=np.uint8)
+    cls = np.zeros(R, dtype=np.int8)
+    sums = np.zeros(R, dtype=np.uint32)
+    lat = np.zeros(nb, dtype=np.uint64)
+    wait = np.zeros(nb, dtype=np.uint64)
+    st = ServeStats()
+    _check("serve_run", lib().serve_run(s, nb, pf, po, pa, 1 if alone else 0, status.ctypes.data, cls.ctypes.data,
+                                        sums.ctypes.data, lat.ctypes.data, wait.ctypes.data, C.byref(st)))
+    return {"status": status, "cls": cls, "sum": sums, "latency_ns": lat, "wait_ns": wait, "stats": st.as_dict()}
+
+
+def serve_export(s: int, first: int, n: int, dst, stream=None):
+    _check("serve_export", lib().serve_export(s, first, n, _addr(dst), _stream(stream)))
+
+
+def heap_chunks_in_use(h: int, stream=None) -> int:
+    v = C.c_uint64()
+    _check("heap_chunks_in_use", lib().heap_chunks_in_use(h, C.byref(v), _stream(stream)))
+    return v.value
+
+
+# ---- growth line (include/hbheap_growth.h) ----
+
+def growth_create(h: int, agents: int, doublings, steps: int, seed: int) -> int:
+    out = C.c_void_p()
+    _check("growth_create", lib().growth_create(h, agents, _addr(doublings), steps, seed & 0xFFFFFFFF, C.byref(out)))
+    return out.value
+
+
+def growth_destroy(g: int):
+    _check("growth_destroy", lib().growth_destroy(g))
+
+
+def growth_step(g: int, step: int, stream=None):
+    _check("growth_step", lib().growth_step(g, step, _stream(stream)))
+
+
+def growth_graph_launch(g: int, stream=None):
+    _check("growth_graph_launch", lib().growth_graph_launch(g, _stream(stream)))
+
+
+def growth_release(g: int, stream=None):
+    _check("growth_release", lib().growth_release(g, _stream(stream)))
+
+
+def growth_export(g: int, ptrs=None, nbytes=None, failures=None, stream=None):
+    _check("growth_export", lib().growth_export(g, _addr(ptrs), _addr(nbytes), _addr(failures), _stream(stream)))
+
+
+def growth_launch_shape(g: int) -> tuple[int, int]:
+    b, t = C.c_uint32(), C.c_uint32()
+    _check("growth_launch_shape", lib().growth_launch_shape(g, C.byref(b), C.byref(t)))
+    return b.value, t.value
+
+
+def growth_autotune(heap_bytes: int, agents: int, doublings, steps: int, seed: int, candidates, reps: int):
+    """candidates: list of (chunk_bytes, variant, width).  Returns (median ms
+    per candidate, negative where it could not run; index of the best)."""
+    n = len(candidates)
+    arr = (GrowthCandidate * n)(*[GrowthCandidate(c, v, w) for c, v, w in candidates])
+    ms = (C.c_float * n)()
+    best = C.c_int32()
+    _check("growth_autotune", lib().growth_autotune(heap_bytes, agents, _addr(doublings), steps, seed & 0xFFFFFFFF,
+                                                    arr, n, reps, ms, C.byref(best)))
+    return [float(x) for x in ms], best.value
+
+
 # ---------------------------------------------------------------------------
 # convenience owner of a heap handle
 # ---------------------------------------------------------------------------
@@ -302,3 +436,45 @@ class Heap:
         m = torch.zeros(1, dtype=torch.int64, device=ptrs.device)
         heap_pattern_check(self.h, ptrs, sizes, seed, m, stream=stream)
         return int(m.item())
+
+
+class Growth:
+    """Owns one growth run over a Heap; methods forward to the C ABI."""
+
+    def __init__(self, heap: Heap, doublings, steps: int = 9, seed: int = 0):
+        self.heap = heap
+        self.agents = int(doublings.numel())
+        self.g = growth_create(heap.h, self.agents, doublings, steps, seed)
+        self.steps, self.seed = steps, seed
+
+    def close(self):
+        if self.g:
+            growth_destroy(self.g)
+            self.g = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def step(self, s: int, stream=None):
+        growth_step(self.g, s, stream)
+
+    def run_graph(self, stream=None):
+        growth_graph_launch(self.g, stream)
+
+    def release(self, stream=None):
+        growth_release(self.g, stream)
+
+    def export(self, stream=None):
+        """(ptrs int64 tensor, bytes int64 tensor, failures int)."""
+        import torch
+        ptrs = torch.zeros(self.agents, dtype=torch.int64, device="cuda")
+        nbytes = torch.zeros(self.agents, dtype=torch.int64, device="cuda")
+        fails = torch.zeros(1, dtype=torch.int64, device="cuda")
+        growth_export(self.g, ptrs, nbytes, fails, stream)
+        return ptrs, nbytes, int(fails.item())
+
+    def shape(self) -> tuple[int, int]:
+        return growth_launch_shape(self.g)

@@ -118,3 +118,72 @@ def op_script(n_ops: int, seed: int, lo: int = 1, hi: int = 8 * KiB, p_free: flo
                 ops[i] = min(ops[i], hi)
             live.append(i)
     return ops
+
+
+@dataclass
+class ServePlan:
+    """Batches of requests for the serving loop.  Requests are numbered in
+    batch order; ops[i] >= 0 asks for that many bytes, ops[i] < 0 frees the
+    block of request -ops[i]-1.  Batch b is requests [first[b], first[b+1])."""
+    first: np.ndarray       # uint64, n_batches + 1
+    ops: np.ndarray         # int64
+    warm_batches: int       # leading batches that only allocate
+    free_lag: int
+
+
+def serve_plan(n_batches: int, seed: int, warm_requests: int, mean: int = 4096, lo: int = 64, hi: int = 65536,
+               size_lo: int = 16, size_hi: int = 8 * KiB, p_free: float = 0.5, free_lag: int = 4) -> ServePlan:
+    """Warm-up batches allocate until ``warm_requests`` allocations; after
+    that each request is a free with probability ``p_free`` (while blocks are
+    eligible), else an allocation.  A free picks uniformly among the live
+    blocks allocated at least ``free_lag`` batches earlier; each block is
+    freed at most once.  Batch sizes ceil(Exp(mean)) clamped to [lo, hi];
+    allocation sizes log-uniform in [size_lo, size_hi]."""
+    g = rng(seed + 11)
+    bsz = serve_batches(n_batches, seed, mean, lo, hi)
+    first = np.zeros(n_batches + 1, dtype=np.uint64)
+    first[1:] = np.cumsum(bsz)
+    total = int(first[-1])
+    ops = np.empty(total, dtype=np.int64)
+    pool = np.empty(total, dtype=np.int64)     # live ids eligible to be freed
+    npool = 0
+    allocs_of = []                               # alloc ids per batch
+    n_alloc = 0
+    warm = 0
+    for b in range(n_batches):
+        if b >= free_lag:
+            add = allocs_of[b - free_lag]
+            pool[npool:npool + len(add)] = add
+            npool += len(add)
+        f0, n = int(first[b]), int(bsz[b])
+        warm_phase = n_alloc < warm_requests
+        k = 0 if warm_phase else min(int(g.binomial(n, p_free)), npool)
+        if warm_phase:
+            warm += 1
+        is_free = np.zeros(n, dtype=bool)
+        if k:
+            is_free[g.choice(n, k, replace=False)] = True
+            pos = g.choice(npool, k, replace=False)
+            targets = pool[pos].copy()
+            # swap-remove the taken entries: holes outside the tail are
+            # refilled with the tail entries that were not taken
+            tail = npool - k
+            in_tail = pos >= tail
+            keep = np.ones(k, dtype=bool)
+            keep[pos[in_tail] - tail] = False
+            pool[pos[~in_tail]] = pool[tail:npool][keep]
+            npool = tail
+            ops[f0:f0 + n][is_free] = -targets - 1
+        na = n - k
+        ops[f0:f0 + n][~is_free] = sizes_log_uniform(na, size_lo, size_hi, seed + 100000 + b).astype(np.int64)
+        ids = np.nonzero(~is_free)[0].astype(np.int64) + f0
+        allocs_of.append(ids)
+        n_alloc += na
+    return ServePlan(first, ops, warm, free_lag)
+
+
+def arrivals_ns(n_batches: int, rate_per_s: float, seed: int) -> np.ndarray:
+    """Poisson arrival times in nanoseconds from the start (first at 0)."""
+    t = serve_arrivals(n_batches, rate_per_s, seed)
+    t = t - t[0]
+    return np.round(t * 1e9).astype(np.uint64)

@@ -77,3 +77,32 @@ def test_null_handle_and_buffers_rejected(L):
 def test_dev_handle_layout_matches_header():
     # 11 pointers, one u64, twelve u32
     assert C.sizeof(hb.DevHandle) == 11 * 8 + 8 + 12 * 4
+
+
+def test_growth_rejects_bad_arguments(L):
+    out = C.c_void_p(0)
+    assert L.growth_create(None, 10, None, 9, 0, C.byref(out)) == hb.E_INVAL
+    assert out.value is None
+    assert L.growth_destroy(None) == hb.OK
+    assert L.growth_step(None, 0, None) == hb.E_INVAL
+    assert L.growth_graph_launch(None, None) == hb.E_INVAL
+    assert L.growth_release(None, None) == hb.E_INVAL
+    assert L.growth_export(None, None, None, None, None) == hb.E_INVAL
+    b, t = C.c_uint32(), C.c_uint32()
+    assert L.growth_launch_shape(None, C.byref(b), C.byref(t)) == hb.E_INVAL
+    ms = (C.c_float * 1)()
+    best = C.c_int32()
+    assert L.growth_autotune(1 << 20, 10, None, 9, 0, None, 0, 1, ms, C.byref(best)) == hb.E_INVAL
+
+
+def test_serve_rejects_bad_arguments(L):
+    out = C.c_void_p(0)
+    cfg = hb.ServeConfig(4, 4096, 1000, 0.95, 1, 1)
+    assert L.serve_create(None, C.byref(cfg), C.byref(out)) == hb.E_INVAL
+    assert out.value is None
+    assert L.serve_destroy(None) == hb.OK
+    st = hb.ServeStats()
+    assert L.serve_run(None, 0, None, None, None, 1, None, None, None, None, None, C.byref(st)) == hb.E_INVAL
+    assert L.serve_export(None, 0, 1, None, None) == hb.E_INVAL
+    v = C.c_uint64()
+    assert L.heap_chunks_in_use(None, C.byref(v), None) == hb.E_INVAL

@@ -272,6 +272,29 @@ def test_free_errors(hb, variant):
 
 
 # ---------------------------------------------------------------------------
+# payload harness on a partial last wave: large blocks are written and
+# checked by the active lanes only, and must still be covered completely
+# ---------------------------------------------------------------------------
+
+def test_pattern_partial_wave_large_blocks(hb):
+    import torch
+    say("case pattern-partial-wave")
+    n, size, seed = 64 + 6, 4 * KiB, 0x1234
+    sizes = inputs.sizes_fixed(n, size)
+    with hb.Heap(4 * MiB, 8 * KiB) as heap:
+        sd, ptrs = dev_u64(sizes), zeros_i64(n)
+        heap.alloc(sd, ptrs)
+        heap.pattern_write(ptrs, sd, seed)
+        assert heap.pattern_check(ptrs, sd, seed) == 0
+        p = ptrs.cpu().numpy().view(np.uint64)
+        for i in range(60, n):
+            buf = torch.empty(size, dtype=torch.uint8, device="cuda")
+            hb.hb_stream_copy(buf, int(p[i]), size)
+            assert buf.cpu().numpy().tobytes() == O.pattern_bytes(seed, i, size), i
+        heap.free(ptrs)
+
+
+# ---------------------------------------------------------------------------
 # aggregation width: 1, 16, 64 lanes per queue operation
 # ---------------------------------------------------------------------------
 

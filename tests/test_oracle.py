@@ -492,3 +492,25 @@ def test_pattern_bytes_little_endian_truncated():
     assert O.pattern_word(seed, req, 1) == O.fmix32(seed ^ O.fmix32(req) ^ 0x9E3779B9)
     b = O.pattern_bytes(seed, req, 6)
     assert b == w0.to_bytes(4, "little") + w1.to_bytes(4, "little")[:2]
+
+
+def test_pattern_sum_against_bytes():
+    """The block checksum is the wrap-around sum of the block's little-endian
+    words, a partial last word zero-extended: closed forms at 0 and 4 bytes,
+    and brute force from the pattern bytes for ragged sizes."""
+    assert O.pattern_sum(7, 9, 0) == 0
+    for seed, req in [(0, 0), (0xC0F5, 12345), (0xFFFFFFFF, 1 << 31)]:
+        assert O.pattern_sum(seed, req, 4) == O.pattern_word(seed, req, 0)
+        for n in [1, 2, 3, 5, 15, 16, 17, 63, 1000, 1021, 8192]:
+            b = O.pattern_bytes(seed, req, n) + b"\0" * (-n % 4)
+            expect = int(np.frombuffer(b, dtype="<u4").astype(np.uint64).sum() & 0xFFFFFFFF)
+            assert O.pattern_sum(seed, req, n) == expect, (seed, req, n)
+    reqs = np.array([1, 2, 3, 4], dtype=np.uint64)
+    sizes = np.array([16, 5, 0, 4096], dtype=np.uint64)
+    got = O.pattern_sums(99, reqs, sizes)
+    assert got.tolist() == [O.pattern_sum(99, int(r), int(s)) for r, s in zip(reqs, sizes)]
+
+
+def test_classes_batch_matches_scalar():
+    sizes = np.array([0, 1, 15, 16, 17, 32, 33, 4096, 4097, 8192, 8193, 1 << 40], dtype=np.uint64)
+    assert O.classes(sizes, 8192).tolist() == [O.class_of(int(s), 8192) for s in sizes]
