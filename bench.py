@@ -60,11 +60,18 @@ def parse():
     ap.add_argument("--width", type=int, default=64)
     ap.add_argument("--shards", type=int, default=0, help="queue shards (0: one per 256 chunks, up to 64)")
     ap.add_argument("--no-other", action="store_true", help="skip the other queue variant")
+    ap.add_argument("--no-ablation", action="store_true", help="skip the width-1 (no aggregation) ablation")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain device-malloc baseline")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--sizes", type=str, default="", help="comma list overriding the 16..8192 sweep")
     ap.add_argument("--copy-probe", type=int, default=0, help="only run an HBM copy of this many bytes")
+    ap.add_argument("--no-growth", action="store_true", help="skip the growth line (graph replay, autotuner)")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving line")
+    ap.add_argument("--no-paper-sweeps", action="store_true", help="skip the paper's size and thread sweeps")
+    ap.add_argument("--growth-reps", type=int, default=20)
+    ap.add_argument("--serve-batches", type=int, default=10000, help="mixed batches per load point")
+    ap.add_argument("--serve-slots", type=int, default=4)
     return ap.parse_args()
 
 
@@ -174,9 +181,10 @@ def main():
     mism = torch.zeros(1, dtype=torch.int64, device=dev)
     keys = ("state_ops", "headtail_ops", "pool_ops", "spread_ops")
 
-    def run_sweep(variant_name: str, steps: int, warmup: int, count: bool) -> dict:
+    def run_sweep(variant_name: str, steps: int, warmup: int, count: bool, width: int | None = None) -> dict:
         variant = hb.VARIANT_CHUNK if variant_name == "chunk" else hb.VARIANT_PAGE
-        heap = hb.Heap(w.heap_bytes, w.chunk_bytes, variant=variant, width=args.width, shards=args.shards)
+        heap = hb.Heap(w.heap_bytes, w.chunk_bytes, variant=variant, width=args.width if width is None else width,
+                       shards=args.shards)
         shards = int(heap.info.n_shards)
 
         def one_size(s, rec):
@@ -325,6 +333,17 @@ def main():
         other = run_sweep(other_name, 1, 1, count=False)
         log(f"{other_name}: {other['value']/1e9:.2f} G ops/s (iterations 2..10)")
 
+    # ablation: the same sweep without wave aggregation (one queue operation
+    # per lane), one step
+    ablation = None
+    if not args.no_ablation:
+        a = run_sweep(args.variant, 1, 1, count=False, width=1)
+        ablation = {"width": 1, "variant": args.variant, "value": a["value"],
+                    "value_all_iterations": a["value_all_iterations"],
+                    "per_size_ops_per_s": {k: v["ops_per_s"] for k, v in a["per_size"].items()},
+                    "aggregation_speedup": head["value"] / a["value"]}
+        log(f"width 1 ablation: {a['value']/1e9:.2f} G ops/s")
+
     # ---------------- plain baseline: runtime device malloc/free ----------------
     plain = None
     if not args.no_plain:
@@ -388,6 +407,10 @@ def main():
                          f"between sizes) through the sequential oracle, {t_cpu:.1f} s",
                "cpu_model": _cpu_model(), "host_cores_available": os.cpu_count()}
 
+    paper = None if args.no_paper_sweeps else bench_paper_sweeps(hb, inputs, torch, args, ev, log)
+    growth = None if args.no_growth else bench_growth(hb, inputs, torch, args, ev, log)
+    serve = None if args.no_serve else bench_serve(hb, inputs, torch, args, log)
+
     out = {
         "metric": "device malloc+free ops/sec (2^20 threads, 16B-8KiB) vs plain; p99 batch latency",
         "value": head["value"],
@@ -419,12 +442,220 @@ def main():
                                 "lines_1024": ceil_lines / 1e9, "per_lane_random": ceil_spread / 1e9},
         "per_size": head["per_size"],
         "other_variant": other,
+        "ablation_width1": ablation,
         "plain": plain,
         "vs_plain": (plain["ours_same_sizes"] / plain["value_full_size_sizes"])
         if plain and plain["value_full_size_sizes"] and plain["ours_same_sizes"] else None,
         "cpu_baseline": cpu,
+        "paper_sweeps": paper,
+        "growth": growth,
+        "serving": serve,
     }
     print(json.dumps(out), flush=True)
+
+
+def bench_paper_sweeps(hb, inputs, torch, args, ev, log):
+    """The paper's driver loop (Methods) on its two sweeps (Results): 1024
+    allocations at each size 16 B .. 8 KiB, and 1 .. 2^20 threads allocating
+    1000 B.  Ten iterations of allocate -> write -> check -> free on a 4 GiB
+    heap of 8 KiB chunks; reported: the mean allocation and free launch time
+    over all iterations and over iterations 2..10 (the paper's "subsequent
+    iterations")."""
+    import numpy as np
+    w = inputs.SWEEP
+
+    def point(heap, n, size):
+        sd = torch.from_numpy(inputs.sizes_fixed(n, size).view(np.int64)).to("cuda")
+        ptrs = torch.zeros(n, dtype=torch.int64, device="cuda")
+        mism = torch.zeros(1, dtype=torch.int64, device="cuda")
+        ta, tf = [], []
+        for it in range(10):
+            e = [ev() for _ in range(4)]
+            e[0].record()
+            heap.alloc(sd, ptrs)
+            e[1].record()
+            hb.heap_pattern_write(heap.h, ptrs, sd, w.seed)
+            hb.heap_pattern_check(heap.h, ptrs, sd, w.seed, mism)
+            e[2].record()
+            heap.free(ptrs)
+            e[3].record()
+            torch.cuda.synchronize()
+            ta.append(e[0].elapsed_time(e[1]) * 1e3)
+            tf.append(e[2].elapsed_time(e[3]) * 1e3)
+        heap.trim()
+        assert int(mism.item()) == 0
+        return {"alloc_us_all": float(np.mean(ta)), "alloc_us_subsequent": float(np.mean(ta[1:])),
+                "free_us_all": float(np.mean(tf)), "free_us_subsequent": float(np.mean(tf[1:]))}
+
+    res = {"workload": "4 GiB heap, 8 KiB chunks; 10 x (alloc -> write -> check -> free) per point",
+           "size_sweep_1024_allocs": {}, "thread_sweep_1000B": {}}
+    for vname, variant in (("chunk", hb.VARIANT_CHUNK), ("page", hb.VARIANT_PAGE)):
+        with hb.Heap(w.heap_bytes, w.chunk_bytes, variant=variant) as heap:
+            res["size_sweep_1024_allocs"][vname] = {
+                str(s_): point(heap, inputs.PAPER_ALLOCS, s_) for s_ in inputs.SWEEP_SIZES}
+            res["thread_sweep_1000B"][vname] = {
+                str(t): point(heap, t, inputs.PAPER_SIZE) for t in inputs.PAPER_THREADS}
+            assert heap.error() == 0
+    ts = res["thread_sweep_1000B"]["page"]
+    log("paper sweeps: page, 1000 B: " + ", ".join(f"{t}: {v['alloc_us_subsequent']:.1f} us"
+                                                    for t, v in ts.items()))
+    return res
+
+
+def bench_growth(hb, inputs, torch, args, ev, log):
+    """Growth line: 2^18 agents on a 4 GiB heap grow int32 lists 16 B ->
+    4 KiB over nine steps (dev_malloc / copy / dev_free per doubling).  The
+    autotuner picks (chunk size, variant, width) on one seeded schedule; the
+    pick and the default are then timed on another (graph replays, median)."""
+    import numpy as np
+    w = inputs.GROWTH
+    agents, steps = w.threads, w.rounds
+    KiB = 1024
+    d_cal = inputs.growth_doublings(agents, w.seed * 16 + 0xA)   # 0xC0F4A
+    d_eval = inputs.growth_doublings(agents, w.seed * 16 + 0xB)  # 0xC0F4B
+    cands = [(c * KiB, v, wd) for c in (8, 16, 32, 64) for v in (0, 1) for wd in (16, 32, 64)]
+    t0 = time.perf_counter()
+    ms, best = hb.growth_autotune(w.heap_bytes, agents, torch.from_numpy(d_cal).to("cuda"), steps, w.seed, cands,
+                                  reps=5)
+    tune_s = time.perf_counter() - t0
+    if best < 0:
+        log("growth autotuner: no candidate ran")
+        return {"error": "no candidate ran"}
+    default = (8 * KiB, 1, 64)
+
+    def measure(cfg, d):
+        chunk, variant, width = cfg
+        with hb.Heap(w.heap_bytes, chunk, variant=variant, width=width) as heap:
+            with hb.Growth(heap, torch.from_numpy(d).to("cuda"), steps, w.seed) as gr:
+                gr.run_graph()
+                gr.release()
+                graph_t, eager_t = [], []
+                for _ in range(args.growth_reps):
+                    e0, e1 = ev(), ev()
+                    e0.record()
+                    gr.run_graph()
+                    e1.record()
+                    _, nbytes, fails = gr.export()
+                    gr.release()
+                    torch.cuda.synchronize()
+                    assert fails == 0
+                    graph_t.append(e0.elapsed_time(e1))
+                for _ in range(5):
+                    e0, e1 = ev(), ev()
+                    e0.record()
+                    for s_ in range(steps):
+                        gr.step(s_)
+                    e1.record()
+                    gr.release()
+                    torch.cuda.synchronize()
+                    eager_t.append(e0.elapsed_time(e1))
+                final_bytes = int(nbytes.sum().item())
+                blocks, threads = gr.shape()
+            assert heap.error() == 0
+        return float(np.median(graph_t)), float(np.median(eager_t)), final_bytes, blocks * threads
+
+    # per replay: step 0 allocates for every agent; each doubling allocates,
+    # copies the old list and frees it
+    doublings = int(d_eval.sum())
+    reallocs = agents + doublings
+    copied = int(sum((16 << s_) // 2 * int((d_eval >= s_).sum()) for s_ in range(1, steps)))
+    written = int(sum((16 << s_) * int((d_eval >= s_).sum()) for s_ in range(1, steps))) + 16 * agents
+    g_best, e_best, fb, lanes = measure(cands[best], d_eval)
+    g_def, e_def, _, _ = measure(default, d_eval)
+    res = {
+        "workload": f"{agents} agents, 4 GiB heap, {steps} steps (16 B -> 4 KiB doubling reallocs), "
+                    "doublings min(8, Geom(0.3)), calibration and evaluation schedules seeded apart",
+        "graph_ms": g_best,
+        "eager_ms": e_best,
+        "realloc_ops": reallocs,
+        "alloc_free_ops_per_s": (reallocs + doublings) / (g_best * 1e-3),
+        "payload_gb_per_s": (copied + written) / (g_best * 1e-3) / 1e9,
+        "final_live_bytes": fb,
+        "persistent_lanes": lanes,
+        "autotune": {
+            "best": {"chunk_bytes": cands[best][0], "variant": "chunk" if cands[best][1] == 0 else "page",
+                     "width": cands[best][2]},
+            "calibration_ms": {f"{c // KiB}K/{'page' if v else 'chunk'}/w{wd}": round(t, 4)
+                               for (c, v, wd), t in zip(cands, ms)},
+            "default": {"chunk_bytes": default[0], "variant": "page", "width": default[2]},
+            "default_graph_ms": g_def,
+            "margin_vs_default": g_def / g_best,
+            "seconds": tune_s,
+        },
+    }
+    log(f"growth: graph {g_best:.3f} ms (eager {e_best:.3f} ms), {res['alloc_free_ops_per_s']/1e9:.2f} G ops/s, "
+        f"autotune best {res['autotune']['best']} margin {g_def / g_best:.3f}")
+    return res
+
+
+def bench_serve(hb, inputs, torch, args, log):
+    """Serving line: 16 GiB heap (page variant), K slot streams, batches of
+    mean 4096 requests (64..65536) with sizes log-uniform in [16 B, 8 KiB];
+    warm-up to about half the heap, then mixed allocations and frees.  The
+    capacity run offers every batch at once; then Poisson arrivals at 0.25,
+    0.5 and 0.9 of that capacity."""
+    import numpy as np
+    w = inputs.SERVE
+    mean_block = 1817  # mean class size of log-uniform [16, 8192]
+    warm_req = int(0.5 * w.heap_bytes / mean_block)
+    t0 = time.perf_counter()
+    # enough batches for the warm-up plus the mixed phase
+    est_warm = int(warm_req / 4096 * 1.1) + 16
+    plan = inputs.serve_plan(est_warm + args.serve_batches, w.seed, warm_requests=warm_req)
+    gen_s = time.perf_counter() - t0
+    nb = len(plan.first) - 1
+    wb = plan.warm_batches
+    mixed = slice(wb, nb)
+    mixed_req = int(plan.first[nb] - plan.first[wb])
+
+    def run(arr):
+        with hb.Heap(w.heap_bytes, w.chunk_bytes, variant=hb.VARIANT_PAGE) as heap:
+            s = hb.serve_create(heap.h, args.serve_slots, int(np.diff(plan.first).max()), len(plan.ops), 0.95,
+                                w.seed, plan.free_lag)
+            try:
+                r = hb.serve_run(s, plan.first, plan.ops, arr, alone=False)
+            finally:
+                hb.serve_destroy(s)
+            assert heap.error() == 0
+        bad = int((r["status"] != 0).sum())
+        lat = r["latency_ns"][mixed] / 1e3
+        wait = r["wait_ns"][mixed] / 1e3
+        # mixed phase: from the later of its first arrival and the end of the
+        # warm-up, to its last completion
+        done_ns = arr + r["latency_ns"]
+        warm_done = float(np.max(done_ns[:wb])) * 1e-9 if wb else 0.0
+        t_end = float(np.max(done_ns[mixed])) * 1e-9
+        t_beg = max(float(arr[wb]) * 1e-9, warm_done)
+        span = max(t_end - t_beg, 1e-9)
+        return {"served_ops_per_s": mixed_req / span, "batches_per_s": (nb - wb) / span, "warm_done_s": warm_done,
+                "latency_us": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
+                "admission_wait_us": {"p50": float(np.percentile(wait, 50)), "p99": float(np.percentile(wait, 99))},
+                "failed_requests": bad, "trims": r["stats"]["trims"],
+                "admission_stalls": r["stats"]["admission_stalls"], "peak_chunk_bound": r["stats"]["peak_bound"]}
+
+    # capacity: warm-up and mixed batches all offered at time 0
+    cap = run(np.zeros(nb, dtype=np.uint64))
+    rate_cap = cap["batches_per_s"]
+    points = {"capacity": cap}
+    # load points: the warm-up is offered at time 0, the mixed batches arrive
+    # (Poisson) from a little after the capacity run's warm-up ended
+    start_ns = int(cap["warm_done_s"] * 1.25e9)
+    for f in (0.25, 0.5, 0.9):
+        arr = np.zeros(nb, dtype=np.uint64)
+        arr[wb:] = inputs.arrivals_ns(nb - wb, f * rate_cap, w.seed + int(f * 100)) + np.uint64(start_ns)
+        points[f"load_{f}"] = run(arr)
+        log(f"serving load {f}: p50 {points[f'load_{f}']['latency_us']['p50']:.1f} us, "
+            f"p99 {points[f'load_{f}']['latency_us']['p99']:.1f} us")
+    res = {
+        "workload": f"16 GiB heap, page variant, {args.serve_slots} slot streams, admission at 95% of chunks; "
+                    f"{wb} warm-up batches ({int(plan.first[wb])} allocations), then {nb - wb} mixed batches "
+                    f"({mixed_req} requests, half frees) per load point",
+        "capacity_batches_per_s": rate_cap,
+        "points": points,
+        "plan_seconds": gen_s,
+    }
+    log(f"serving: capacity {rate_cap:.0f} batches/s, {cap['served_ops_per_s']/1e9:.3f} G ops/s")
+    return res
 
 
 def _cpu_model():

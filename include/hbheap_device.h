@@ -108,6 +108,54 @@ __device__ __forceinline__ uint32_t excl_scan(uint32_t x, uint32_t* total)
     return pre;
 }
 
+/* Value of v held by lane `src` (ds_bpermute; src must be active for the
+ * result to be used). */
+__device__ __forceinline__ uint32_t perm32(uint32_t v, uint32_t src)
+{
+    return (uint32_t)__builtin_amdgcn_ds_bpermute((int)(src << 2), (int)v);
+}
+__device__ __forceinline__ uint64_t perm64(uint64_t v, uint32_t src)
+{
+    return ((uint64_t)perm32((uint32_t)(v >> 32), src) << 32) | perm32((uint32_t)v, src);
+}
+
+/* Runs of adjacent active lanes (inside aligned segments of `seg` lanes)
+ * that apply bits to the same bitmask word `key`.  The bits of a run are
+ * OR-ed by a segmented inclusive scan over the lanes (six permute steps,
+ * whatever the number of runs); the run's last lane then issues the run's
+ * single atomic.  incl: bits of the run's lanes up to this one (the whole
+ * run at the tail); prior: bits of the run's lower lanes; tail: the run's
+ * last lane. */
+struct Run {
+    uint64_t incl;
+    uint64_t prior;
+    uint32_t tail;
+};
+__device__ __forceinline__ Run run_combine(bool have, uint64_t key, uint64_t bit, uint32_t seg)
+{
+    const uint32_t me = lane();
+    const uint64_t todo = __ballot(have);
+    const uint64_t pkey = perm64(key, me ? me - 1u : 0u);
+    const bool same = have && (me & (seg - 1u)) != 0u && ((todo >> (me - 1u)) & 1ull) && pkey == key;
+    const uint64_t same_m = __ballot(same);
+    const uint64_t heads = todo & ~same_m;
+    const uint64_t tails = todo & ~(same_m >> 1);
+    const uint64_t upto = me == 63u ? ~0ull : ((2ull << me) - 1ull);
+    const uint32_t start = have ? 63u - (uint32_t)__builtin_clzll(heads & upto) : me;
+    uint64_t acc = have ? bit : 0ull;
+#pragma unroll
+    for (uint32_t d = 1; d < 64u; d <<= 1) {
+        const uint64_t v = perm64(acc, me >= d ? me - d : me);
+        if (have && me >= start + d) acc |= v;
+    }
+    Run r;
+    r.incl = acc;
+    const uint64_t pa = perm64(acc, me ? me - 1u : 0u);
+    r.prior = same ? pa : 0ull;
+    r.tail = have ? ctz64(tails & ~((1ull << me) - 1ull)) : me;
+    return r;
+}
+
 /* ---------------- scoped atomics ---------------- */
 
 #define HBH_A(order) order, __HIP_MEMORY_SCOPE_AGENT
@@ -613,45 +661,32 @@ __device__ __forceinline__ void chunk_serve_shard(const hbheap_dev_t& h, const G
     }
 }
 
-/* Page variant: lanes with `have` clear `bit` of bitmask word `widx`
- * (their page must have been free); lanes sharing a word are combined into
- * one atomicAnd by their lowest lane until a group of fewer than 4 lanes
- * shows up, then the rest clear their bits one lane at a time.  On success
- * a lane's `off` becomes its page offset `o`. */
+/* Page variant: lanes with `have` clear `bit` of bitmask word `widx` (the
+ * page is theirs: they took it from the queue); each run of adjacent lanes
+ * on one word clears its bits with one atomicAnd, and `off` becomes the
+ * lane's page offset `o`.  With HBHEAP_FLAG_VERIFY the old word is waited
+ * for and a page whose bit was already clear (a heap fault) is not handed
+ * out; without it the clearing atomic returns nothing, so the allocation
+ * does not wait for it. */
 __device__ __forceinline__ void clear_bits_grouped(const hbheap_dev_t& h, bool have, uint64_t widx, uint64_t bit,
                                                    uint64_t o, uint64_t& off, Tally& tl)
 {
-    const uint32_t me = lane();
-    uint64_t todo = __ballot(have);
-    uint64_t* acc = stage_for_wave();
-    bool first_round = true;
-    while (todo) {
-        const uint32_t leader = ctz64(todo);
-        const uint64_t wkey = bcast64(widx, leader);
-        const uint64_t grp = __ballot(have && widx == wkey) & todo;
-        if (!first_round && __popcll(grp) < 4) break;
-        first_round = false;
-        if (me == leader) *acc = 0;
-        wave_sync_lds();
-        if ((grp >> me) & 1ull) __hip_atomic_fetch_or(acc, bit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-        wave_sync_lds();
-        uint64_t old = 0;
-        if (me == leader) {
-            old = a_and64(h.bits + widx, ~*acc);
+    const Run r = run_combine(have, widx, bit, 64u);
+    if (!(h.flags & HBHEAP_FLAG_VERIFY)) {
+        if (have && lane() == r.tail) {
+            __hip_atomic_fetch_and(h.bits + widx, ~r.incl, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             tl.spread += 1;
         }
-        wave_sync_lds();
-        old = bcast64(old, leader);
-        if ((grp >> me) & 1ull) {
-            if (old & bit) off = o;
-            else raise_err(h, HBHEAP_ERR_CORRUPT, HBHEAP_STAT_TIMEOUTS);
-        }
-        todo &= ~grp;
+        if (have) off = o;
+        return;
     }
-    if ((todo >> me) & 1ull) {
-        /* scattered pages: one lane at a time */
-        const uint64_t old = a_and64(h.bits + widx, ~bit);
+    uint64_t old = 0;
+    if (have && lane() == r.tail) {
+        old = a_and64(h.bits + widx, ~r.incl);
         tl.spread += 1;
+    }
+    old = perm64(old, r.tail);
+    if (have) {
         if (old & bit) off = o;
         else raise_err(h, HBHEAP_ERR_CORRUPT, HBHEAP_STAT_TIMEOUTS);
     }
@@ -865,75 +900,38 @@ __device__ __forceinline__ uint32_t free_wave(const hbheap_dev_t& h, void* p, ui
             }
         }
     }
-    /* Set the free bits.  Lanes freeing pages of the same bitmask word are
-     * combined: their bits are OR-ed in LDS (which also finds the same page
-     * twice in one call), the group's leader sets them with one atomicOr and,
-     * in the chunk variant, raises the chunk's count once by the number of
-     * newly set bits.  Once a group of fewer than 4 lanes shows up, the rest
-     * set their bits one lane at a time. */
-    uint64_t todo = __ballot(cand);
-    uint64_t* acc = stage_for_wave();
-    bool first_round = true;
-    while (todo) {
-        const uint32_t leader = ctz64(todo);
-        const uint64_t wkey = bcast64(widx, leader);
-        uint64_t grp = __ballot(cand && widx == wkey) & todo;
-        if (h.width < 64u) {
-            const uint32_t seg = leader & ~(h.width - 1u);
-            grp &= ((1ull << h.width) - 1ull) << seg;
-        }
-        if (!first_round && __popcll(grp) < 4) break;
-        first_round = false;
-        if (me == leader) *acc = 0;
-        wave_sync_lds();
-        bool dup = false;
-        if ((grp >> me) & 1ull)
-            dup = (__hip_atomic_fetch_or(acc, bit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) & bit) != 0;
-        wave_sync_lds();
-        uint64_t old = 0;
-        uint32_t cold = 1, nnew = 0;
-        if (me == leader) {
-            const uint64_t m = *acc;
-            old = a_or64(h.bits + widx, m);
-            nnew = (uint32_t)__popcll(m & ~old);
-            tl.spread += 1;
-            if (h.variant == HBHEAP_VARIANT_CHUNK && nnew) {
-                cold = (uint32_t)a_addi(h.chunk_cnt + c, (int32_t)nnew);
-                tl.spread += 1;
-            }
-        }
-        wave_sync_lds();
-        old = bcast64(old, leader);
-        cold = bcast(cold, leader);
-        nnew = bcast(nnew, leader);
-        if ((grp >> me) & 1ull) {
-            status = (dup || (old & bit)) ? kFreeDouble : kFreeOk;
-            if (h.variant == HBHEAP_VARIANT_CHUNK) {
-                /* the chunk's count left zero: the group enqueues it once */
-                enq = me == leader && nnew > 0 && cold == 0;
-                val = (uint32_t)c;
-            } else {
-                enq = status == kFreeOk;
-                val = (uint32_t)(o >> 4);
-            }
-        }
-        todo &= ~grp;
-    }
-    if ((todo >> me) & 1ull) {
-        const uint64_t old = a_or64(h.bits + widx, bit);
+    /* Set the free bits.  Each run of adjacent lanes freeing pages of one
+     * bitmask word sets its bits with one atomicOr by its last lane (the
+     * run's bits are combined first, which also finds the same page twice in
+     * one run); in the chunk variant that lane also raises the chunk's count
+     * once by the number of newly set bits, and the run enqueues the chunk
+     * once if the count left zero.  Pages of one word in separate runs are
+     * set by separate atomics: the returned old word tells each run which of
+     * its bits were already set. */
+    const Run run = run_combine(cand, widx, bit, h.width < 64u ? h.width : 64u);
+    uint64_t old = 0;
+    uint32_t cold = 1, nnew = 0;
+    if (cand && me == run.tail) {
+        old = a_or64(h.bits + widx, run.incl);
+        nnew = (uint32_t)__popcll(run.incl & ~old);
         tl.spread += 1;
-        if (old & bit) {
-            status = kFreeDouble;
+        if (h.variant == HBHEAP_VARIANT_CHUNK && nnew) {
+            cold = (uint32_t)a_addi(h.chunk_cnt + c, (int32_t)nnew);
+            tl.spread += 1;
+        }
+    }
+    old = perm64(old, run.tail);
+    cold = perm32(cold, run.tail);
+    nnew = perm32(nnew, run.tail);
+    if (cand) {
+        status = ((run.prior & bit) || (old & bit)) ? kFreeDouble : kFreeOk;
+        if (h.variant == HBHEAP_VARIANT_CHUNK) {
+            /* the chunk's count left zero: the run enqueues it once */
+            enq = me == run.tail && nnew > 0 && cold == 0;
+            val = (uint32_t)c;
         } else {
-            status = kFreeOk;
-            if (h.variant == HBHEAP_VARIANT_CHUNK) {
-                enq = a_addi(h.chunk_cnt + c, 1) == 0;
-                tl.spread += 1;
-                val = (uint32_t)c;
-            } else {
-                enq = true;
-                val = (uint32_t)(o >> 4);
-            }
+            enq = status == kFreeOk;
+            val = (uint32_t)(o >> 4);
         }
     }
     /* rare paths: one report per wave */

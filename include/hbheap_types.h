@@ -95,6 +95,11 @@ typedef struct hbheap_dev {
  * counters (extra atomics: for measurement runs only; errors and
  * out-of-memory are always counted). */
 #define HBHEAP_FLAG_STATS 0x1u
+/* Page variant: check that every page taken from a queue still had its
+ * free bit set, raising HBHEAP_ERR_CORRUPT otherwise (the allocation then
+ * waits for the bit-clearing atomic to return; without the flag it does
+ * not). */
+#define HBHEAP_FLAG_VERIFY 0x2u
 
 #ifdef __cplusplus
 }

@@ -39,6 +39,12 @@ SEED_SERVE = 0xC0F5
 
 SWEEP_SIZES = [16 << i for i in range(10)]  # 16 B .. 8 KiB
 
+# the paper's own driver sweeps (Results): 1024 allocations over a range of
+# sizes, and a range of thread counts allocating 1000 B each
+PAPER_ALLOCS = 1024
+PAPER_SIZE = 1000
+PAPER_THREADS = [1 << (2 * i) for i in range(11)]  # 1 .. 2^20
+
 
 @dataclass(frozen=True)
 class Workload:

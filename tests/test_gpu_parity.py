@@ -194,21 +194,21 @@ def test_steal_exact_capacity(hb, variant):
 # freed and reallocated per round
 # ---------------------------------------------------------------------------
 
-@pytest.mark.parametrize("variant", VARIANTS)
-@pytest.mark.parametrize("shards", [1, 0])
-def test_churn_small(hb, variant, shards):
+@pytest.mark.parametrize("variant,shards,flags", [(0, 1, 0), (0, 0, 0), (1, 1, 0), (1, 0, 0), (1, 0, 2)])
+def test_churn_small(hb, variant, shards, flags):
+    """flags 2: the page variant verifies every page it takes from a queue."""
     import torch
     nbytes, C, n, rounds = 256 * MiB, 8 * KiB, 1 << 16, 4
     seed = inputs.SEED_CHURN
     sizes = inputs.sizes_log_uniform(n, 4, 8 * KiB, seed)
     ref = O.OracleHeap(nbytes, C, variant)
     ref_offs = ref.alloc_batch(sizes)
-    with hb.Heap(nbytes, C, variant=variant, shards=shards) as heap:
+    with hb.Heap(nbytes, C, variant=variant, shards=shards, flags=flags) as heap:
         fresh = heap.snapshot()
         ptrs = zeros_i64(n)
         heap.alloc(dev_u64(sizes), ptrs)
         for r in range(rounds + 1):
-            say(f"case churn-small variant={variant} shards={shards} round={r}")
+            say(f"case churn-small variant={variant} shards={shards} flags={flags} round={r}")
             if r:
                 idx, new_sizes = inputs.churn_round(n, r, seed)
                 idx_d = torch.from_numpy(idx).to("cuda")
@@ -405,4 +405,37 @@ def test_churn_full_size(hb, variant):
         heap.free(ptrs)
         heap.trim()
         assert heap.snapshot() == fresh
+        assert heap.error() == 0
+
+
+# ---------------------------------------------------------------------------
+# the paper's own sweeps: 1024 allocations over the sizes, and 1 .. 2^20
+# threads allocating 1000 B (4 GiB heap, 8 KiB chunks, two iterations each)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("variant", VARIANTS)
+def test_paper_sweeps(hb, variant):
+    w = inputs.SWEEP
+    points = [(inputs.PAPER_ALLOCS, s) for s in inputs.SWEEP_SIZES] + \
+             [(t, inputs.PAPER_SIZE) for t in inputs.PAPER_THREADS]
+    with hb.Heap(w.heap_bytes, w.chunk_bytes, variant=variant) as heap:
+        fresh = heap.snapshot()
+        for n, size in points:
+            say(f"case paper-sweep variant={variant} n={n} size={size}")
+            sizes = inputs.sizes_fixed(n, size)
+            sd, ptrs = dev_u64(sizes), zeros_i64(n)
+            ref = O.OracleHeap(w.heap_bytes, w.chunk_bytes, variant)
+            ref.alloc_batch(sizes)
+            for it in range(2):
+                heap.alloc(sd, ptrs)
+                heap.pattern_write(ptrs, sd, it)
+                assert heap.pattern_check(ptrs, sd, it) == 0
+                offs = offsets(ptrs, heap.base)
+                check_blocks(heap, sizes, offs)
+                if it == 0 and n <= 4096:
+                    _, srep = check_snapshot(heap)
+                    assert live_of(srep) == ref.accounting()["live"]
+                heap.free(ptrs)
+            heap.trim()
+            assert heap.snapshot() == fresh
         assert heap.error() == 0
