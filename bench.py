@@ -166,7 +166,7 @@ def main():
             torch.cuda.synchronize()
             t = e0.elapsed_time(e1) / 1e3
             best = t if best is None else min(best, t)
-        n_at = threads * iters if pattern in (2, 4) else threads // 64 * iters
+        n_at = threads * iters if pattern in (2, 4, 5, 6, 7) else threads // 64 * iters
         return n_at / best
 
     ceil_same = probe(0, 1, 1 << 20, 4)

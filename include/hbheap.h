@@ -166,9 +166,13 @@ int heap_pattern_check(heap_t h, void* const* ptrs, const size_t* sizes, size_t 
  *   pattern 1: one per wave on `lines` addresses 128 B apart (wave % lines);
  *   pattern 2: one 32-bit atomic add per lane on pseudo-random words of buf;
  *   pattern 3: one 64-bit compare-and-swap per wave on one address;
- *   pattern 4: one 64-bit atomic add per lane on one address.
- * `threads` lanes each repeat `iters` times.  Atomics issued: pattern 2 and
- * 4: threads * iters; others: threads / 64 * iters. */
+ *   pattern 4: one 64-bit atomic add per lane on one address;
+ *   pattern 5: one 32-bit exchange per lane, lanes on consecutive words;
+ *   pattern 6: one coherent (device-scope) 32-bit load and store per lane,
+ *              lanes on consecutive words;
+ *   pattern 7: the same with 64-bit words.
+ * `threads` lanes each repeat `iters` times.  Operations issued: patterns 2
+ * and 4..7: threads * iters; others: threads / 64 * iters. */
 int hb_atomic_probe(int pattern, void* buf, size_t buf_bytes, size_t threads, uint32_t lines, uint32_t iters,
                     hipStream_t stream);
 

@@ -238,17 +238,29 @@ __device__ __forceinline__ uint32_t shard_of_chunk(const hbheap_dev_t& h, uint64
     return (uint32_t)(c >> h.log2_span);
 }
 
-/* Home shard of the calling wave: waves are spread round-robin over the
- * shards by their linear wave index in the grid (block-major), so the
- * waves of one launch load every shard's queues evenly. */
+/* The shard a wave of a user kernel (dev_malloc) tries first.  Chosen from
+ * where the wave runs, read from hardware registers (no memory access, any
+ * launch shape): the XCD (XCC_ID) picks one of eight equal runs of shards,
+ * and the wave's place inside the XCD (CU, SIMD, wave slot: HW_ID) one shard
+ * of that run, so a shard's queues are worked by waves of one XCD.  The
+ * library's batch kernels pass their linear wave index instead, which
+ * spreads a launch over the shards exactly evenly (and, blocks being
+ * dispatched to the XCDs in turn, keeps each shard on one XCD).  With
+ * HBHEAP_FLAG_HOME0 every wave starts at shard 0 (the deterministic
+ * single-lane replay).  Any value in [0, S) is correct: the choice only
+ * spreads the load. */
 __device__ __forceinline__ uint32_t home_shard(const hbheap_dev_t& h)
 {
-    if (h.n_shards == 1) return 0;
-    const uint32_t blk = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
-    const uint32_t nthr = blockDim.x * blockDim.y * blockDim.z;
-    const uint32_t lin = threadIdx.x + blockDim.x * (threadIdx.y + blockDim.y * threadIdx.z);
-    const uint32_t wave = blk * ((nthr + 63u) >> 6) + (lin >> 6);
-    return wave % h.n_shards;
+    const uint32_t S = h.n_shards;
+    if (S == 1 || (h.flags & HBHEAP_FLAG_HOME0)) return 0;
+    const uint32_t xcc = __builtin_amdgcn_s_getreg((3 << 11) | (0 << 6) | 20) & 7u; /* XCC_ID[3:0] */
+    const uint32_t hw = __builtin_amdgcn_s_getreg((31 << 11) | (0 << 6) | 4);       /* HW_ID       */
+    /* wave slot [3:0], SIMD [5:4], CU [11:8], SH [12], SE [15:13] */
+    const uint32_t local = (hw & 0x3Fu) | ((hw >> 2) & 0x3FC0u);
+    const uint32_t mix = (local * 0x9E3779B1u) >> 16;
+    if (S < 8u) return (xcc + mix) % S;
+    const uint32_t lo = xcc * S / 8u, hi = (xcc + 1u) * S / 8u;
+    return lo + mix % (hi - lo);
 }
 
 /* ---------------- class ring ---------------- */
@@ -289,6 +301,21 @@ __device__ __forceinline__ int32_t state_count(uint64_t s) { return (int32_t)((u
 __device__ __forceinline__ uint32_t ring_reserve(const Ring& r, uint32_t n, Tally& t)
 {
     const uint64_t old = a_add64(r.state, kHold - n);
+    const int32_t c = state_count(old);
+    const uint32_t got = c <= 0 ? 0u : ((uint32_t)c < n ? (uint32_t)c : n);
+    t.state += 1;
+    if (got < n) {
+        a_add64(r.state, (uint64_t)(n - got));
+        t.state += 1;
+    }
+    return got;
+}
+/* Leader only: take up to n published entries without a hold, for an
+ * operation that will publish nothing (the caller knows it cannot refill);
+ * a deficit is given back at once. */
+__device__ __forceinline__ uint32_t ring_take_published(const Ring& r, uint32_t n, Tally& t)
+{
+    const uint64_t old = a_add64(r.state, (uint64_t)0 - (uint64_t)n);
     const int32_t c = state_count(old);
     const uint32_t got = c <= 0 ? 0u : ((uint32_t)c < n ? (uint32_t)c : n);
     t.state += 1;
@@ -547,13 +574,21 @@ __device__ __forceinline__ uint32_t scan_shards(const hbheap_dev_t& h, const Gro
  * writing their byte offsets to stage[served..).  Returns when need is met
  * or when shard j's queue and pool could not supply more. */
 __device__ __forceinline__ void chunk_serve_shard(const hbheap_dev_t& h, const Group& g, uint32_t j, uint32_t& need,
-                                                  uint32_t& served, uint64_t* stage, Tally& tl)
+                                                  uint32_t& served, uint64_t* stage, bool look_first, Tally& tl)
 {
     const Ring R = ring_of(h, j, g.k);
+    /* look before reserving, except on a first pass the caller vouches for
+     * (a home shard whose pool still had chunks, or a shard a scan just found
+     * something in): there an empty queue costs only a hold taken and given
+     * back, while on a dry shard such holds would keep scanning waves waiting */
+    bool first_pass = !look_first;
     while (need > 0) {
-        uint32_t some = 0;
-        if (g.me == g.leader) some = shard_has_something(h, j, g.k, g.lppc);
-        if (!bcast(some, g.leader)) return;
+        if (!first_pass) {
+            uint32_t some = 0;
+            if (g.me == g.leader) some = shard_has_something(h, j, g.k, g.lppc);
+            if (!bcast(some, g.leader)) return;
+        }
+        first_pass = false;
         const uint32_t want0 = (need + g.ppc - 1u) >> g.lppc;
         const uint32_t want = want0 < g.nact ? want0 : g.nact;
         uint32_t got = 0, h0 = 0;
@@ -695,16 +730,26 @@ __device__ __forceinline__ void clear_bits_grouped(const hbheap_dev_t& h, bool h
 /* Page variant, shard j: requesting lanes of ranks [served, served+need)
  * receive pages; *off is this lane's page. */
 __device__ __forceinline__ void page_serve_shard(const hbheap_dev_t& h, const Group& g, uint32_t j, uint32_t& need,
-                                                 uint32_t& served, uint64_t& off, Tally& tl)
+                                                 uint32_t& served, uint64_t& off, bool dry, Tally& tl)
 {
     const Ring R = ring_of(h, j, g.k);
+    /* The first pass reserves without looking first.  On a shard the caller
+     * saw with a dry pool (dry stays dry until a trim) this pass cannot
+     * refill, so it publishes nothing and needs no hold: it only takes
+     * published entries, which keeps waves that scan for out-of-memory from
+     * waiting on it.  Later passes look first and hold the queue. */
+    bool first_pass = true;
     while (need > 0) {
-        uint32_t some = 0;
-        if (g.me == g.leader) some = shard_has_something(h, j, g.k, g.lppc);
-        if (!bcast(some, g.leader)) return;
+        const bool held = !(first_pass && dry);
+        if (!first_pass) {
+            uint32_t some = 0;
+            if (g.me == g.leader) some = shard_has_something(h, j, g.k, g.lppc);
+            if (!bcast(some, g.leader)) return;
+        }
+        first_pass = false;
         uint32_t got = 0, h0 = 0;
         if (g.me == g.leader) {
-            got = ring_reserve(R, need, tl);
+            got = held ? ring_reserve(R, need, tl) : ring_take_published(R, need, tl);
             if (got) {
                 h0 = a_add32(R.head, got);
                 tl.headtail += 1;
@@ -734,8 +779,8 @@ __device__ __forceinline__ void page_serve_shard(const hbheap_dev_t& h, const Gr
         served += got;
 
         uint32_t publish = 0;
-        bool exhausted = false;
-        if (need > 0) {
+        bool exhausted = !held;
+        if (need > 0 && held) {
             const uint32_t m = (need + g.ppc - 1u) >> g.lppc;
             uint64_t first = 0;
             uint32_t gm = 0;
@@ -785,7 +830,7 @@ __device__ __forceinline__ void page_serve_shard(const hbheap_dev_t& h, const Gr
             need -= r;
             served += r;
         }
-        if (g.me == g.leader) ring_release(R, publish, tl);
+        if (held && g.me == g.leader) ring_release(R, publish, tl);
         if (need > 0 && exhausted) return;
     }
 }
@@ -796,7 +841,7 @@ __device__ __forceinline__ void page_serve_shard(const hbheap_dev_t& h, const Gr
  * without entries, without room and without holds in flight.  Returns this
  * lane's page offset or kNoPage. */
 __device__ __forceinline__ uint64_t alloc_group(const hbheap_dev_t& h, uint32_t k, uint64_t grp, uint64_t* stage,
-                                                Tally& tl)
+                                                uint32_t home, bool home_dry, Tally& tl)
 {
     const Group g = make_group(h, k, grp);
     const bool chunk = h.variant == HBHEAP_VARIANT_CHUNK;
@@ -807,9 +852,8 @@ __device__ __forceinline__ uint64_t alloc_group(const hbheap_dev_t& h, uint32_t 
     uint64_t off = kNoPage;
     uint32_t need = (uint32_t)__popcll(grp), served = 0;
     const uint32_t S = h.n_shards;
-    const uint32_t home = home_shard(h);
-    if (chunk) chunk_serve_shard(h, g, home, need, served, stage, tl);
-    else page_serve_shard(h, g, home, need, served, off, tl);
+    if (chunk) chunk_serve_shard(h, g, home, need, served, stage, home_dry, tl);
+    else page_serve_shard(h, g, home, need, served, off, home_dry, tl);
     Backoff wb;
     bool timed_out = false;
     while (need > 0) {
@@ -819,8 +863,8 @@ __device__ __forceinline__ uint64_t alloc_group(const hbheap_dev_t& h, uint32_t 
         if (r < S) {
             const uint32_t j = home + r < S ? home + r : home + r - S;
             const uint32_t before = need;
-            if (chunk) chunk_serve_shard(h, g, j, need, served, stage, tl);
-            else page_serve_shard(h, g, j, need, served, off, tl);
+            if (chunk) chunk_serve_shard(h, g, j, need, served, stage, false, tl);
+            else page_serve_shard(h, g, j, need, served, off, false, tl);
             if (need < before) continue;
         }
         /* holds in flight, or the shard was drained under us: wait, bounded */
@@ -847,7 +891,17 @@ __device__ __forceinline__ uint64_t alloc_group(const hbheap_dev_t& h, uint32_t 
 /* Every active lane calls this; lanes are grouped by class (restricted to
  * aligned segments of `width` lanes) and each group is served by one queue
  * operation of its leader. */
-__device__ __forceinline__ void* malloc_wave(const hbheap_dev_t& h, uint64_t n)
+/* Whether the home shard's pool has run dry.  A plain load: the bump only
+ * grows until a (quiescent) trim, so a stale value can only make the pool
+ * look less consumed, never dry when it is not.  Callers that load their
+ * request sizes issue this first, so that both loads are in flight together. */
+__device__ __forceinline__ bool home_pool_dry(const hbheap_dev_t& h, uint32_t home)
+{
+    const uint64_t* hp = pool_block(h, home);
+    return hp[0] >= ((const uint32_t*)hp)[2];
+}
+
+__device__ __forceinline__ void* malloc_wave(const hbheap_dev_t& h, uint64_t n, uint32_t home, bool home_dry)
 {
     const int k = class_of(h, n);
     const uint32_t me = lane();
@@ -863,7 +917,7 @@ __device__ __forceinline__ void* malloc_wave(const hbheap_dev_t& h, uint64_t n)
             const uint32_t seg = leader & ~(h.width - 1u);
             grp &= ((1ull << h.width) - 1ull) << seg;
         }
-        const uint64_t o = alloc_group(h, kk, grp, stage, tl);
+        const uint64_t o = alloc_group(h, kk, grp, stage, home, home_dry, tl);
         if ((grp >> me) & 1ull) off = o;
         pending &= ~grp;
     }
@@ -976,7 +1030,8 @@ __device__ __forceinline__ uint32_t free_wave(const hbheap_dev_t& h, void* p, ui
  * size, or no page of the class and no chunk is left in any shard. */
 __device__ __forceinline__ void* dev_malloc(hbheap_dev_t h, size_t n)
 {
-    return hbheap::detail::malloc_wave(h, (uint64_t)n);
+    const uint32_t home = hbheap::detail::home_shard(h);
+    return hbheap::detail::malloc_wave(h, (uint64_t)n, home, hbheap::detail::home_pool_dry(h, home));
 }
 
 /* Return a block to the heap.  NULL is ignored; an invalid pointer or a

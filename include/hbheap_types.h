@@ -100,6 +100,9 @@ typedef struct hbheap_dev {
  * waits for the bit-clearing atomic to return; without the flag it does
  * not). */
 #define HBHEAP_FLAG_VERIFY 0x2u
+/* Every wave starts at shard 0 instead of a shard of its XCD (used by the
+ * single-lane replay, whose outcome is then deterministic). */
+#define HBHEAP_FLAG_HOME0 0x4u
 
 #ifdef __cplusplus
 }

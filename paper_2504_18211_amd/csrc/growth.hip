@@ -73,8 +73,11 @@ __global__ void __launch_bounds__(kGrowBlock) k_growth_step(hbheap_dev_t h, Grow
     const uint64_t stride = (uint64_t)gridDim.x * kGrowBlock;
     for (uint64_t a = (uint64_t)blockIdx.x * kGrowBlock + threadIdx.x; a < g.agents; a += stride) {
         const uint32_t sr = g.seed ^ fmix32((uint32_t)a);
+        /* home shard: the agent's linear wave index */
+        const uint32_t home = (uint32_t)((a >> 6) % h.n_shards);
+        const bool dry = home_pool_dry(h, home);
         if (step == 0) {
-            void* p = dev_malloc(h, 16);
+            void* p = malloc_wave(h, 16, home, dry);
             if (p) *(uint4*)p = make_uint4(pat_word(sr, 0), pat_word(sr, 1), pat_word(sr, 2), pat_word(sr, 3));
             else atomicAdd(g.fails, 1ull);
             g.lists[a] = (uint64_t)p;
@@ -85,7 +88,7 @@ __global__ void __launch_bounds__(kGrowBlock) k_growth_step(hbheap_dev_t h, Grow
         const uint32_t e = g.elems[a];
         const bool active = old != 0 && g.doublings[a] >= (int32_t)step;
         void* q = nullptr;
-        if (active) q = dev_malloc(h, (size_t)e * 8u);
+        if (active) q = malloc_wave(h, (size_t)e * 8u, home, dry);
         const bool ok = active && q != nullptr;
         if (active && !ok) atomicAdd(g.fails, 1ull);
         const uint32_t nu = e / 4u; /* 16-byte units of the old list */

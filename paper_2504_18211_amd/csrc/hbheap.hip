@@ -94,15 +94,32 @@ __global__ void k_iota_u32(uint32_t* p, uint64_t n)
 /* Batch kernels.  The Counted instances run when HBHEAP_FLAG_STATS is set
  * (measurement passes) and carry their own symbol, so profiles of the
  * plain instances are not mixed with counting launches. */
+/* Occupancy target of the allocation kernel (waves per SIMD); 0 leaves the
+ * choice to the compiler. */
+#ifndef HBHEAP_ALLOC_WAVES
+#define HBHEAP_ALLOC_WAVES 0
+#endif
+#if HBHEAP_ALLOC_WAVES > 0
+#define HBHEAP_ALLOC_ATTR __attribute__((amdgpu_waves_per_eu(HBHEAP_ALLOC_WAVES, 8)))
+#else
+#define HBHEAP_ALLOC_ATTR
+#endif
+
 template <bool Counted>
-__global__ void __launch_bounds__(kBatchBlock) k_alloc_batch(hbheap_dev_t h, const uint64_t* __restrict__ sizes,
+__global__ void __launch_bounds__(kBatchBlock) HBHEAP_ALLOC_ATTR k_alloc_batch(hbheap_dev_t h, const uint64_t* __restrict__ sizes,
                                                              void** __restrict__ ptrs, uint64_t n)
 {
     const uint64_t i = (uint64_t)blockIdx.x * kBatchBlock + threadIdx.x;
     if (i >= n) return;
     if (Counted) h.flags |= HBHEAP_FLAG_STATS;
     else h.flags &= ~HBHEAP_FLAG_STATS;
-    ptrs[i] = malloc_wave(h, sizes[i]);
+    /* home shard: the linear wave index, spread evenly over the shards; its
+     * pool hint is loaded before the size so that both loads are in flight
+     * together (the empty asm keeps the compiler from sinking it) */
+    const uint32_t home = (uint32_t)((i >> 6) % h.n_shards);
+    const bool dry = home_pool_dry(h, home);
+    __asm__ volatile("" ::: "memory");
+    ptrs[i] = malloc_wave(h, sizes[i], home, dry);
 }
 
 template <bool Counted>
@@ -122,10 +139,11 @@ __global__ void __launch_bounds__(kBatchBlock) k_free_batch(hbheap_dev_t h, cons
 __global__ void k_replay(hbheap_dev_t h, const int64_t* ops, int64_t* out, uint64_t n)
 {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    h.flags |= HBHEAP_FLAG_HOME0;
     for (uint64_t i = 0; i < n; ++i) {
         const int64_t op = ops[i];
         if (op >= 0) {
-            void* p = malloc_wave(h, (uint64_t)op);
+            void* p = malloc_wave(h, (uint64_t)op, 0, home_pool_dry(h, 0));
             out[i] = p ? (int64_t)((uint8_t*)p - h.data) : -1;
         } else {
             const uint64_t j = (uint64_t)(-op - 1);
@@ -433,6 +451,35 @@ __global__ void __launch_bounds__(kBatchBlock) k_atomic_probe(int pattern, uint6
     case 4:
         for (uint32_t it = 0; it < iters; ++it) acc += a_add64(buf + 16, 1);
         break;
+    case 5: {
+        /* lane-contiguous 32-bit exchanges: a wave covers 256 consecutive bytes */
+        uint32_t* w32 = (uint32_t*)buf;
+        const uint64_t words32 = words64 * 2;
+        for (uint32_t it = 0; it < iters; ++it) acc += a_xchg32(w32 + (tid + (uint64_t)it * threads) % words32, 7u);
+        break;
+    }
+    case 6: {
+        /* lane-contiguous coherent 32-bit load then store (no read-modify-write) */
+        uint32_t* w32 = (uint32_t*)buf;
+        const uint64_t words32 = words64 * 2;
+        for (uint32_t it = 0; it < iters; ++it) {
+            uint32_t* q = w32 + (tid + (uint64_t)it * threads) % words32;
+            const uint32_t v = a_load32(q);
+            __hip_atomic_store(q, v + 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            acc += v;
+        }
+        break;
+    }
+    case 7: {
+        /* lane-contiguous coherent 64-bit load then store */
+        for (uint32_t it = 0; it < iters; ++it) {
+            uint64_t* q = buf + (tid + (uint64_t)it * threads) % words64;
+            const uint64_t v = a_load64(q);
+            __hip_atomic_store(q, v + 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            acc += v;
+        }
+        break;
+    }
     default:
         break;
     }
@@ -813,7 +860,7 @@ int heap_pattern_check(heap_t h, void* const* ptrs, const size_t* sizes, size_t 
 int hb_atomic_probe(int pattern, void* buf, size_t buf_bytes, size_t threads, uint32_t lines, uint32_t iters,
                     hipStream_t stream)
 {
-    if (!buf || buf_bytes < 4096 || pattern < 0 || pattern > 4 || !threads || !iters) return HBHEAP_E_INVAL;
+    if (!buf || buf_bytes < 4096 || pattern < 0 || pattern > 7 || !threads || !iters) return HBHEAP_E_INVAL;
     if (pattern == 1 && (!lines || (uint64_t)lines * 128 > buf_bytes)) return HBHEAP_E_INVAL;
     hipLaunchKernelGGL(k_atomic_probe, dim3(grid_for(threads, kBatchBlock)), dim3(kBatchBlock), 0, stream, pattern,
                        (uint64_t*)buf, (uint64_t)(buf_bytes / 8), lines, iters, (uint64_t)threads);

@@ -140,16 +140,21 @@ __global__ void __launch_bounds__(kServeBlock) k_serve_batch(hbheap_dev_t h, con
     const uint64_t i = (uint64_t)blockIdx.x * kServeBlock + threadIdx.x;
     if (i >= n) return;
     const uint32_t me = lane();
+    /* home shard: the request's linear wave index (batches rotate over the
+     * shards); its pool hint is loaded together with the request */
+    const uint64_t req = first_req + i;
+    const uint32_t home = (uint32_t)((req >> 6) % h.n_shards);
+    const bool dry = home_pool_dry(h, home);
+    __asm__ volatile("" ::: "memory");
     const int64_t op = ops[i];
     const bool is_alloc = op >= 0;
-    const uint64_t req = first_req + i;
     uint8_t* p = nullptr;
     uint64_t size = 0;
     uint32_t sr = 0;
     if (is_alloc) {
         size = (uint64_t)op;
         sr = seed ^ fmix32((uint32_t)req);
-        p = (uint8_t*)dev_malloc(h, size);
+        p = (uint8_t*)malloc_wave(h, size, home, dry);
         handles[req] = (uint64_t)p;
         if (!p) size = 0;
     } else {

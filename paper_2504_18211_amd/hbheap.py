@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(HERE, "libhbheap.so")
 VARIANT_CHUNK, VARIANT_PAGE = 0, 1
 OK, E_INVAL, E_NOMEM, E_HIP, E_RANGE, E_UNSUP = 0, -1, -2, -3, -4, -5
 ERR_DOUBLE_FREE, ERR_INVALID_FREE, ERR_TIMEOUT, ERR_CORRUPT = 0x1, 0x2, 0x4, 0x8
-FLAG_STATS, FLAG_VERIFY = 0x1, 0x2
+FLAG_STATS, FLAG_VERIFY, FLAG_HOME0 = 0x1, 0x2, 0x4
 STAT_NAMES = ["chunk_grabs", "refills", "oom", "oom_waits", "double_free", "invalid_free", "timeouts", "reserved7",
               "state_ops", "headtail_ops", "pool_ops", "spread_ops", "reserved12", "reserved13", "reserved14",
               "reserved15"]
