@@ -148,7 +148,8 @@ class ModelParams(C.Structure):
     _fields_ = [
         ("variant", C.c_int32), ("n_chunks", C.c_int32), ("ppc", C.c_int32), ("maxc", C.c_int32),
         ("n_leaders", C.c_int32), ("n_ops", C.c_int32 * 3), ("ops", (ModelOp * 3) * 3),
-        ("prefill", C.c_int32), ("freeze", C.c_int32), ("mutation", C.c_int32), ("max_states", C.c_int64),
+        ("prefill", C.c_int32), ("freeze", C.c_int32), ("mutation", C.c_int32), ("dry_hint", C.c_int32),
+        ("max_states", C.c_int64),
     ]
 
 
@@ -158,7 +159,7 @@ class ModelResult(C.Structure):
         ("token_violations", C.c_int64), ("oom_violations", C.c_int64), ("final_violations", C.c_int64),
         ("grant_violations", C.c_int64), ("blocked_freezes", C.c_int64), ("null_outcomes", C.c_int64),
         ("truncated", C.c_int32), ("first_violation", C.c_int32), ("blocking_pcs", C.c_uint32),
-        ("pad", C.c_uint32),
+        ("dry_starts", C.c_uint32),
     ]
 
     def as_dict(self) -> dict:
@@ -167,11 +168,11 @@ class ModelResult(C.Structure):
 
 OP_ALLOC, OP_FREE_OWN, OP_FREE_GIVEN = 1, 2, 3
 MUTATIONS = {"no_hold": 1, "requeue_always": 2, "free_enqueue_always": 3, "no_refund": 4,
-             "release_no_publish": 5, "publish_early": 6}
+             "release_no_publish": 5, "publish_early": 6, "dry_always": 7}
 
 
 def model_run(variant: int, n_chunks: int, ppc: int, leaders: list, prefill: int = 0, maxc: int | None = None,
-              freeze: bool = False, mutation: int = 0, max_states: int = 2_000_000) -> dict:
+              freeze: bool = False, mutation: int = 0, max_states: int = 2_000_000, dry_hint: bool = True) -> dict:
     """Explore every interleaving of `leaders` (each a list of (kind, a, b)
     ops) on a heap of n_chunks chunks of ppc pages.  Returns the counters."""
     p = ModelParams()
@@ -184,6 +185,7 @@ def model_run(variant: int, n_chunks: int, ppc: int, leaders: list, prefill: int
             kind, a, b = (tuple(op) + (0, 0))[:3]
             p.ops[l][i] = ModelOp(kind, a, b)
     p.prefill, p.freeze, p.mutation, p.max_states = prefill, int(freeze), mutation, max_states
+    p.dry_hint = int(dry_hint)
     r = ModelResult()
     rc = lib().orc_model_run(C.byref(p), C.byref(r))
     if rc != 0:

@@ -56,7 +56,8 @@ typedef orc_model_result model_result;
 enum { OP_NONE = ORC_OP_NONE, OP_ALLOC = ORC_OP_ALLOC, OP_FREE_OWN = ORC_OP_FREE_OWN, OP_FREE_GIVEN = ORC_OP_FREE_GIVEN };
 enum {
     MUT_NONE = 0, MUT_NO_HOLD = 1, MUT_REQUEUE_ALWAYS = 2, MUT_FREE_ENQ_ALWAYS = 3,
-    MUT_NO_REFUND = 4, MUT_RELEASE_NO_PUB = 5, MUT_PUBLISH_EARLY = 6
+    MUT_NO_REFUND = 4, MUT_RELEASE_NO_PUB = 5, MUT_PUBLISH_EARLY = 6,
+    MUT_DRY_ALWAYS = 7 /* page alloc: first pass without a hold even when it refills */
 };
 
 /* ---------------- state ---------------- */
@@ -64,6 +65,8 @@ enum {
 typedef struct {
     uint8_t op, pc, need, served, got, want, h0, i, t0, nrq, took, publish, exhausted, m, gm, bump0;
     uint8_t lastgot;
+    uint8_t dry;               /* page alloc: the pool looked dry at start */
+    uint8_t held;              /* page alloc: this pass holds the queue   */
     uint8_t c[M_MAXG];         /* chunk (chunk var.) or page (page var.) per lane */
     int8_t v[M_MAXG];          /* free count read per helper              */
     uint8_t t[M_MAXG];         /* pages this helper serves                */
@@ -313,7 +316,7 @@ static void start_op(ctx* x, mstate* s, int l)
         L->served = 0;
         L->ngranted[L->op] = (uint8_t)o->a;
         memset(L->granted[L->op], M_EMPTY, M_MAXG);
-        L->pc = x->p->variant == 0 ? 1 : 21;
+        L->pc = x->p->variant == 0 ? 1 : 20;
     } else {
         /* the pages to free, one per lane */
         int n = 0;
@@ -548,11 +551,20 @@ static int step(ctx* x, mstate* s, int l)
         return 1;
     }
     /* ---------------- page variant alloc ---------------- */
+    case 20:
+        /* read the pool before the request (the device loads it beside the
+         * request size): a dry pool lets the first pass take published
+         * entries without holding the queue, since it cannot refill */
+        L->dry = (uint8_t)((x->p->dry_hint && s->bump >= N) || mut == MUT_DRY_ALWAYS);
+        if (L->dry && x->r->dry_starts < 0xFFFFFFFFu) x->r->dry_starts++;
+        L->held = (uint8_t)!L->dry;
+        L->pc = 21;
+        return 1;
     case 21: {
         L->want = L->need;
         int c_old = s->cnt_pub;
         s->cnt_pub -= L->want;
-        if (mut != MUT_NO_HOLD) s->H++;
+        if (mut != MUT_NO_HOLD && L->held) s->H++;
         int got = c_old <= 0 ? 0 : (c_old < L->want ? c_old : L->want);
         L->got = (uint8_t)got;
         L->pc = (got < L->want && mut != MUT_NO_REFUND) ? 22 : 23;
@@ -597,6 +609,7 @@ static int step(ctx* x, mstate* s, int l)
         L->publish = 0;
         L->exhausted = 0;
         if (L->need == 0) { L->pc = 32; return 1; }
+        if (!L->held && mut != MUT_DRY_ALWAYS) { L->exhausted = 1; L->pc = 32; return 1; }
         L->m = (uint8_t)((L->need + P - 1) / P);
         if (s->bump >= N) { L->gm = 0; L->exhausted = 1; L->pc = 32; return 1; }
         {
@@ -671,7 +684,8 @@ static int step(ctx* x, mstate* s, int l)
     }
     case 32:
         s->cnt_pub += (mut == MUT_RELEASE_NO_PUB) ? 0 : L->publish;
-        if (mut != MUT_NO_HOLD) s->H--;
+        if (mut != MUT_NO_HOLD && L->held) s->H--;
+        L->held = 1; /* later passes hold the queue */
         L->lo_chunk = M_EMPTY;
         if (L->need > 0 && L->exhausted) { L->pc = 33; return 1; }
         if (L->need > 0) { L->pc = 21; return 1; }

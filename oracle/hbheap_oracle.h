@@ -147,6 +147,8 @@ typedef struct {
     int32_t prefill;           /* pages allocated before exploration      */
     int32_t freeze;            /* also run the freeze analysis            */
     int32_t mutation;          /* planted mistake, 0 for none             */
+    int32_t dry_hint;          /* page alloc reads the pool first and skips
+                                  the hold on a dry pool                  */
     int64_t max_states;
 } orc_model_params;
 
@@ -158,7 +160,7 @@ typedef struct {
     int32_t truncated;
     int32_t first_violation;
     uint32_t blocking_pcs;     /* bit mask of the frozen leader's pcs      */
-    uint32_t pad;
+    uint32_t dry_starts;       /* page allocs that started on a dry pool   */
 } orc_model_result;
 
 /* 0 on success, negative for bad parameters. */

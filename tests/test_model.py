@@ -83,3 +83,26 @@ def test_blocking_points_are_holds_or_reserved_slots(variant, name):
     pcs = {b for b in range(32) if (r["blocking_pcs"] >> b) & 1}  # pcs modulo 32
     allowed = {pc % 32 for pc in HOLDING[variant]}
     assert pcs <= allowed, (sorted(pcs), sorted(allowed))
+
+
+@pytest.mark.parametrize("name", ["oom_one_chunk", "oom_three", "churn", "churn3", "oom_refill_race"])
+def test_dry_pool_first_pass_without_hold(name):
+    """Page variant: an allocation that reads a dry pool first takes published
+    entries without holding the queue.  Those starts happen in these
+    configurations, and the checks still hold on every interleaving."""
+    r = O.model_run(1, **CONFIGS[name])
+    assert not r["truncated"]
+    assert r["violations"] == 0 and r["deadlocks"] == 0, r
+    if name in ("oom_one_chunk", "oom_three", "churn3"):
+        assert r["dry_starts"] > 0, r
+
+
+def test_hold_skipped_while_refilling_is_caught():
+    """Planted mistake: skip the hold on every first pass, refilling included;
+    a waiting leader can then see no entry and no hold while leftovers of a
+    refill are still unpublished, and report out-of-memory wrongly."""
+    hits = 0
+    for name in ("oom_refill_race", "oom_three", "three_allocs", "oom_one_chunk"):
+        r = O.model_run(1, mutation=O.MUTATIONS["dry_always"], **CONFIGS[name])
+        hits += r["violations"] + r["deadlocks"]
+    assert hits > 0
