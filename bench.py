@@ -169,6 +169,21 @@ def main():
         n_at = threads * iters if pattern in (2, 4, 5, 6, 7) else threads // 64 * iters
         return n_at / best
 
+    # what an event pair adds around a launch: median over a one-wave kernel
+    # doing a single atomic
+    def event_overhead_us():
+        buf = torch.zeros(1 << 16, dtype=torch.uint8, device=dev)
+        ts = []
+        for _ in range(50):
+            e0, e1 = ev(), ev()
+            e0.record()
+            hb.hb_atomic_probe(1, buf, buf.numel(), 64, 1, 1)
+            e1.record()
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1) * 1e3)
+        return float(np.median(ts))
+
+    ev_overhead = event_overhead_us()
     ceil_same = probe(0, 1, 1 << 20, 4)
     ceil_64 = probe(1, 64, 1 << 20, 4)
     ceil_lines = probe(1, 1024, 1 << 20, 4)
@@ -317,6 +332,7 @@ def main():
                 "frac": achieved / ceil_spread,
                 "traffic": recorded_traffic(),
                 "avg_launch_us": float(np.mean(alloc_t)) * 1e6,
+                "event_overhead_us": ev_overhead,
                 "launches": len(alloc_t),
                 "atomics_per_launch": atomics / len(alloc_t),
                 "busiest_word": {"achieved": busiest / 1e9, "peak": ceil_same / 1e9, "frac": busiest / ceil_same,
@@ -603,6 +619,7 @@ def bench_serve(hb, inputs, torch, args, log):
     est_warm = int(warm_req / 4096 * 1.1) + 16
     plan = inputs.serve_plan(est_warm + args.serve_batches, w.seed, warm_requests=warm_req)
     gen_s = time.perf_counter() - t0
+    log(f"serving: plan of {len(plan.first) - 1} batches ({len(plan.ops)} requests) in {gen_s:.1f} s")
     nb = len(plan.first) - 1
     wb = plan.warm_batches
     mixed = slice(wb, nb)
@@ -636,6 +653,7 @@ def bench_serve(hb, inputs, torch, args, log):
     # capacity: warm-up and mixed batches all offered at time 0
     cap = run(np.zeros(nb, dtype=np.uint64))
     rate_cap = cap["batches_per_s"]
+    log(f"serving: capacity {rate_cap:.0f} batches/s")
     points = {"capacity": cap}
     # load points: the warm-up is offered at time 0, the mixed batches arrive
     # (Poisson) from a little after the capacity run's warm-up ended

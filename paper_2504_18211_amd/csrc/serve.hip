@@ -36,6 +36,9 @@ constexpr uint64_t kServeCoop = 1024;
 constexpr uint32_t kMaxSlots = 16;
 constexpr uint32_t kMaxBatch = 65536;
 constexpr uint32_t kMaxClasses = 16;
+/* the monitor re-reads the chunk counters at most this often while batches
+ * run (each read is one small kernel and an 8-byte copy per class) */
+constexpr uint64_t kMonitorGapNs = 20000;
 constexpr uint64_t kUsageBytes = 8 * (1 + kMaxClasses);
 
 struct Slot {
@@ -437,7 +440,7 @@ int serve_run(server_t s, uint32_t nb, const uint64_t* first, const int64_t* ops
     set_exact();
 
     bool mon_busy = false;
-    uint64_t mon_L = 0, mon_out = 0;
+    uint64_t mon_L = 0, mon_out = 0, mon_next_ns = 0;
     std::vector<uint64_t> mon_L_k(K, 0), mon_out_k(K, 0);
     std::vector<uint8_t> done(nb, 0);
     uint32_t prefix = 0; /* batches [0, prefix) are complete */
@@ -534,7 +537,7 @@ int serve_run(server_t s, uint32_t nb, const uint64_t* first, const int64_t* ops
                     return HBHEAP_E_HIP;
                 }
             }
-            if (!mon_busy && inflight) {
+            if (!mon_busy && inflight && now >= mon_next_ns) {
                 /* worst cases of the batches not yet seen complete */
                 mon_out = 0;
                 std::fill(mon_out_k.begin(), mon_out_k.end(), 0);
@@ -546,6 +549,7 @@ int serve_run(server_t s, uint32_t nb, const uint64_t* first, const int64_t* ops
                 if (usage_issue(s) != HBHEAP_OK || hipEventRecord(s->mon_done, s->mon) != hipSuccess)
                     return HBHEAP_E_HIP;
                 mon_busy = true;
+                mon_next_ns = now + kMonitorGapNs;
                 mon_L = L;
                 mon_L_k = L_k;
             }
