@@ -901,8 +901,13 @@ __device__ __forceinline__ bool home_pool_dry(const hbheap_dev_t& h, uint32_t ho
     return hp[0] >= ((const uint32_t*)hp)[2];
 }
 
-__device__ __forceinline__ void* malloc_wave(const hbheap_dev_t& h, uint64_t n, uint32_t home, bool home_dry)
+__device__ __forceinline__ void* malloc_wave(const hbheap_dev_t& h, uint64_t n, uint32_t home_in, bool dry_in)
 {
+    /* the home shard and its hint act for the whole wave: take the first
+     * active lane's (a caller whose lanes disagree would otherwise make the
+     * leader reserve on one queue and its lanes take from another) */
+    const uint32_t home = (uint32_t)__builtin_amdgcn_readfirstlane((int)home_in);
+    const bool home_dry = __builtin_amdgcn_readfirstlane((int)dry_in) != 0;
     const int k = class_of(h, n);
     const uint32_t me = lane();
     uint64_t pending = __ballot(k >= 0);
@@ -994,8 +999,12 @@ __device__ __forceinline__ uint32_t free_wave(const hbheap_dev_t& h, void* p, ui
         if (dbl) { a_or32(h.err, HBHEAP_ERR_DOUBLE_FREE); a_add64(h.stats + HBHEAP_STAT_DOUBLE_FREE, (uint64_t)__popcll(dbl)); }
         if (inv) { a_or32(h.err, HBHEAP_ERR_INVALID_FREE); a_add64(h.stats + HBHEAP_STAT_INVALID_FREE, (uint64_t)__popcll(inv)); }
     }
-    /* aggregated enqueue by (shard, class) */
+    /* aggregated enqueue by (shard, class): one tail and one state add per
+     * group.  Once a group of fewer than 4 lanes shows up (frees scattered
+     * over many queues), the remaining lanes enqueue one entry each, all in
+     * the same instructions, instead of one queue after another. */
     uint64_t pend = __ballot(enq);
+    bool first_group = true;
     while (pend) {
         const uint32_t leader = ctz64(pend);
         const uint32_t kk = bcast(key, leader);
@@ -1004,6 +1013,8 @@ __device__ __forceinline__ uint32_t free_wave(const hbheap_dev_t& h, void* p, ui
             const uint32_t seg = leader & ~(h.width - 1u);
             grp &= ((1ull << h.width) - 1ull) << seg;
         }
+        if (!first_group && __popcll(grp) < 4) break;
+        first_group = false;
         const uint32_t n = (uint32_t)__popcll(grp);
         const Ring R = ring_of(h, kk / h.n_classes, kk % h.n_classes);
         uint32_t t0 = 0;
@@ -1018,6 +1029,14 @@ __device__ __forceinline__ uint32_t free_wave(const hbheap_dev_t& h, void* p, ui
             tl.state += 1;
         }
         pend &= ~grp;
+    }
+    if ((pend >> me) & 1ull) {
+        const Ring R = ring_of(h, key / h.n_classes, key % h.n_classes);
+        const uint32_t t0 = a_add32(R.tail, 1u);
+        tl.headtail += 1;
+        slot_put(h, R, t0, val, tl);
+        a_add64(R.state, 1ull);
+        tl.state += 1;
     }
     tally_flush(h, tl);
     return status;

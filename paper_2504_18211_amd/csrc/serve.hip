@@ -39,6 +39,7 @@ constexpr uint32_t kMaxClasses = 16;
 /* the monitor re-reads the chunk counters at most this often while batches
  * run (each read is one small kernel and an 8-byte copy per class) */
 constexpr uint64_t kMonitorGapNs = 20000;
+
 constexpr uint64_t kUsageBytes = 8 * (1 + kMaxClasses);
 
 struct Slot {
@@ -143,13 +144,14 @@ __global__ void __launch_bounds__(kServeBlock) k_serve_batch(hbheap_dev_t h, con
     const uint64_t i = (uint64_t)blockIdx.x * kServeBlock + threadIdx.x;
     if (i >= n) return;
     const uint32_t me = lane();
-    /* home shard: the request's linear wave index (batches rotate over the
-     * shards); its pool hint is loaded together with the request */
-    const uint64_t req = first_req + i;
-    const uint32_t home = (uint32_t)((req >> 6) % h.n_shards);
+    /* home shard: the wave's index in the launch, offset per batch (the
+     * value must be the same on every lane of the wave); its pool hint is
+     * loaded together with the request */
+    const uint32_t home = (uint32_t)(((first_req >> 6) + (i >> 6)) % h.n_shards);
     const bool dry = home_pool_dry(h, home);
     __asm__ volatile("" ::: "memory");
     const int64_t op = ops[i];
+    const uint64_t req = first_req + i;
     const bool is_alloc = op >= 0;
     uint8_t* p = nullptr;
     uint64_t size = 0;
