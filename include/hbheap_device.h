@@ -730,15 +730,17 @@ __device__ __forceinline__ void clear_bits_grouped(const hbheap_dev_t& h, bool h
 /* Page variant, shard j: requesting lanes of ranks [served, served+need)
  * receive pages; *off is this lane's page. */
 __device__ __forceinline__ void page_serve_shard(const hbheap_dev_t& h, const Group& g, uint32_t j, uint32_t& need,
-                                                 uint32_t& served, uint64_t& off, bool dry, Tally& tl)
+                                                 uint32_t& served, uint64_t& off, bool dry, bool check_first,
+                                                 Tally& tl)
 {
     const Ring R = ring_of(h, j, g.k);
-    /* The first pass reserves without looking first.  On a shard the caller
-     * saw with a dry pool (dry stays dry until a trim) this pass cannot
-     * refill, so it publishes nothing and needs no hold: it only takes
-     * published entries, which keeps waves that scan for out-of-memory from
-     * waiting on it.  Later passes look first and hold the queue. */
-    bool first_pass = true;
+    /* The first pass reserves without looking first (unless check_first).
+     * On a shard the caller saw with a dry pool (dry stays dry until a trim)
+     * that pass cannot refill, so it publishes nothing and needs no hold: it
+     * only takes published entries, which keeps waves that scan for
+     * out-of-memory from waiting on it.  Later passes look first and hold
+     * the queue. */
+    bool first_pass = !check_first;
     while (need > 0) {
         const bool held = !(first_pass && dry);
         if (!first_pass) {
@@ -841,7 +843,8 @@ __device__ __forceinline__ void page_serve_shard(const hbheap_dev_t& h, const Gr
  * without entries, without room and without holds in flight.  Returns this
  * lane's page offset or kNoPage. */
 __device__ __forceinline__ uint64_t alloc_group(const hbheap_dev_t& h, uint32_t k, uint64_t grp, uint64_t* stage,
-                                                uint32_t home, bool home_dry, Tally& tl)
+                                                uint32_t home, bool home_dry, uint32_t served0, bool home_tried,
+                                                Tally& tl)
 {
     const Group g = make_group(h, k, grp);
     const bool chunk = h.variant == HBHEAP_VARIANT_CHUNK;
@@ -850,10 +853,13 @@ __device__ __forceinline__ uint64_t alloc_group(const hbheap_dev_t& h, uint32_t 
         wave_sync_lds();
     }
     uint64_t off = kNoPage;
-    uint32_t need = (uint32_t)__popcll(grp), served = 0;
+    /* ranks below served0 were served already (page variant: the wave's
+     * first pass over all its groups at once, on the home shard; after it,
+     * home_tried makes the home shard look before it reserves again) */
+    uint32_t need = (uint32_t)__popcll(grp) - served0, served = served0;
     const uint32_t S = h.n_shards;
     if (chunk) chunk_serve_shard(h, g, home, need, served, stage, home_dry, tl);
-    else page_serve_shard(h, g, home, need, served, off, home_dry, tl);
+    else page_serve_shard(h, g, home, need, served, off, home_dry && !home_tried, home_tried, tl);
     Backoff wb;
     bool timed_out = false;
     while (need > 0) {
@@ -864,7 +870,7 @@ __device__ __forceinline__ uint64_t alloc_group(const hbheap_dev_t& h, uint32_t 
             const uint32_t j = home + r < S ? home + r : home + r - S;
             const uint32_t before = need;
             if (chunk) chunk_serve_shard(h, g, j, need, served, stage, false, tl);
-            else page_serve_shard(h, g, j, need, served, off, false, tl);
+            else page_serve_shard(h, g, j, need, served, off, false, false, tl);
             if (need < before) continue;
         }
         /* holds in flight, or the shard was drained under us: wait, bounded */
@@ -910,21 +916,81 @@ __device__ __forceinline__ void* malloc_wave(const hbheap_dev_t& h, uint64_t n, 
     const bool home_dry = __builtin_amdgcn_readfirstlane((int)dry_in) != 0;
     const int k = class_of(h, n);
     const uint32_t me = lane();
-    uint64_t pending = __ballot(k >= 0);
     uint64_t* stage = stage_for_wave();
     uint64_t off = kNoPage;
     Tally tl;
-    while (pending) {
-        const uint32_t leader = ctz64(pending);
+    /* groups: lanes of one class (inside aligned segments of `width`
+     * lanes); each lane learns its group's first lane, its rank, the size */
+    uint32_t gl = me, gr = 0, gn = 0, ngroups = 0;
+    uint64_t pend = __ballot(k >= 0);
+    while (pend) {
+        const uint32_t leader = ctz64(pend);
         const uint32_t kk = bcast((uint32_t)k, leader);
-        uint64_t grp = __ballot(k == (int)kk) & pending;
+        uint64_t grp = __ballot(k == (int)kk) & pend;
         if (h.width < 64u) {
             const uint32_t seg = leader & ~(h.width - 1u);
             grp &= ((1ull << h.width) - 1ull) << seg;
         }
-        const uint64_t o = alloc_group(h, kk, grp, stage, home, home_dry, tl);
-        if ((grp >> me) & 1ull) off = o;
-        pending &= ~grp;
+        if ((grp >> me) & 1ull) {
+            gl = leader;
+            gr = rank_in(grp);
+            gn = (uint32_t)__popcll(grp);
+        }
+        pend &= ~grp;
+        ++ngroups;
+    }
+    /* Page variant, several groups: one first pass for all of them at once
+     * on the home shard -- every group's first lane reserves on its own
+     * queue in the same instructions, the lanes take their slots together
+     * and the bits are cleared in one combined step -- instead of one group
+     * after another.  It publishes nothing (no refill); groups left short
+     * continue below, each on its own. */
+    uint32_t done = 0;
+    const bool fast = h.variant == HBHEAP_VARIANT_PAGE && ngroups > 1;
+    if (fast) {
+        const bool lead = k >= 0 && me == gl;
+        Ring R;
+        uint32_t got = 0, h0 = 0;
+        if (k >= 0) R = ring_of(h, home, (uint32_t)k);
+        if (lead) {
+            got = home_dry ? ring_take_published(R, gn, tl) : ring_reserve(R, gn, tl);
+            if (got) {
+                h0 = a_add32(R.head, got);
+                tl.headtail += 1;
+            }
+        }
+        done = perm32(got, gl);
+        h0 = perm32(h0, gl);
+        bool took = false;
+        uint64_t widx = 0, bit = 0, o = 0;
+        if (k >= 0 && gr < done) {
+            const uint32_t shift = 4u + (uint32_t)k;
+            const uint32_t v = slot_take(h, R, h0 + gr, tl);
+            o = (uint64_t)v << 4;
+            if (v != kEmpty && (o >= h.data_bytes || shard_of_chunk(h, o >> h.log2_chunk) != home)) {
+                raise_err(h, HBHEAP_ERR_CORRUPT, HBHEAP_STAT_TIMEOUTS);
+            } else if (v != kEmpty) {
+                const uint64_t c = o >> h.log2_chunk;
+                const uint32_t p = (uint32_t)((o & ((1ull << h.log2_chunk) - 1ull)) >> shift);
+                widx = c * h.words_per_chunk + (p >> 6);
+                bit = 1ull << (p & 63u);
+                took = true;
+            }
+        }
+        clear_bits_grouped(h, took, widx, bit, o, off, tl);
+        if (lead && !home_dry) ring_release(R, 0, tl);
+    }
+    pend = __ballot(k >= 0 && gr >= done);
+    while (pend) {
+        const uint32_t leader = ctz64(pend);
+        const uint32_t kk = bcast((uint32_t)k, leader);
+        const uint32_t l0 = bcast(gl, leader);
+        /* the whole group (served lanes included: ranks stay those of the
+         * group) */
+        uint64_t grp = __ballot(k == (int)kk && gl == l0);
+        const uint64_t o = alloc_group(h, kk, grp, stage, home, home_dry, bcast(done, leader), fast, tl);
+        if (((grp >> me) & 1ull) && o != kNoPage) off = o;
+        pend &= ~grp;
     }
     tally_flush(h, tl);
     return off == kNoPage ? nullptr : (void*)(h.data + off);
