@@ -67,6 +67,7 @@ typedef struct {
     uint8_t lastgot;
     uint8_t dry;               /* page alloc: the pool looked dry at start */
     uint8_t held;              /* page alloc: this pass holds the queue   */
+    uint8_t pass;              /* page alloc: passes made by this op      */
     uint8_t c[M_MAXG];         /* chunk (chunk var.) or page (page var.) per lane */
     int8_t v[M_MAXG];          /* free count read per helper              */
     uint8_t t[M_MAXG];         /* pages this helper serves                */
@@ -555,6 +556,7 @@ static int step(ctx* x, mstate* s, int l)
         /* read the pool before the request (the device loads it beside the
          * request size): a dry pool lets the first pass take published
          * entries without holding the queue, since it cannot refill */
+        L->pass = 0;
         L->dry = (uint8_t)((x->p->dry_hint && s->bump >= N) || mut == MUT_DRY_ALWAYS);
         if (L->dry && x->r->dry_starts < 0xFFFFFFFFu) x->r->dry_starts++;
         L->held = (uint8_t)!L->dry;
@@ -610,6 +612,9 @@ static int step(ctx* x, mstate* s, int l)
         L->exhausted = 0;
         if (L->need == 0) { L->pc = 32; return 1; }
         if (!L->held && mut != MUT_DRY_ALWAYS) { L->exhausted = 1; L->pc = 32; return 1; }
+        /* the wave's first pass made for all its groups at once refills
+         * nothing: what is still needed is asked for again after a look */
+        if (x->p->fast_first && L->pass == 0) { L->exhausted = 1; L->pc = 32; return 1; }
         L->m = (uint8_t)((L->need + P - 1) / P);
         if (s->bump >= N) { L->gm = 0; L->exhausted = 1; L->pc = 32; return 1; }
         {
@@ -686,6 +691,7 @@ static int step(ctx* x, mstate* s, int l)
         s->cnt_pub += (mut == MUT_RELEASE_NO_PUB) ? 0 : L->publish;
         if (mut != MUT_NO_HOLD && L->held) s->H--;
         L->held = 1; /* later passes hold the queue */
+        L->pass = 1;
         L->lo_chunk = M_EMPTY;
         if (L->need > 0 && L->exhausted) { L->pc = 33; return 1; }
         if (L->need > 0) { L->pc = 21; return 1; }
