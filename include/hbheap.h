@@ -35,7 +35,7 @@ typedef struct hbheap_heap* heap_t;
 
 /* Tunables of heap_create_ex.  Zero fields take the defaults. */
 typedef struct heap_config {
-    uint32_t variant;      /* HBHEAP_VARIANT_CHUNK (default) or _PAGE          */
+    uint32_t variant;      /* HBHEAP_VARIANT_CHUNK (default), _PAGE or _VA_PAGE */
     uint32_t width;        /* lanes aggregated per queue operation: power of
                               two in [1, 64], default 64                     */
     uint32_t spin_cap;     /* bounded-wait iterations, default 1 << 18        */
@@ -53,7 +53,9 @@ typedef struct heap_info {
     uint64_t n_chunks;
     uint32_t n_classes;       /* pages 16 B * 2^k, k < n_classes             */
     uint32_t variant;
-    uint64_t ring_entries;    /* capacity of each (shard, class) queue       */
+    uint64_t ring_entries;    /* capacity of each (shard, class) queue; for
+                                 the virtualised array variant, the pages the
+                                 classes of one shard may own together      */
     uint64_t state_bytes;     /* size of the state region (= snapshot size)  */
     uint64_t metadata_bytes;  /* all device memory besides the data region   */
     uint32_t n_shards;        /* shards actually used (chunk runs of a power

@@ -269,9 +269,20 @@ struct Ring {
     uint64_t* state;
     uint32_t* head;
     uint32_t* tail;
-    uint32_t* slots;
+    uint32_t* slots;  /* plain rings: 2^log2q slots, position p at p & mask */
     uint32_t mask;
+    /* virtualised array rings (page variant in segments): the directory of
+     * this queue, the shard's segments and the shard; dir == nullptr for a
+     * plain ring */
+    uint64_t* dir;
+    uint32_t* segs;
+    uint32_t dmask;
+    uint32_t log2g;
+    uint32_t j;
 };
+
+constexpr uint64_t kDirEmpty = ~0ull;
+constexpr uint32_t kStoreBlock = 512; /* state, head, tail, committed pages */
 
 __device__ __forceinline__ uint8_t* class_block(const hbheap_dev_t& h, uint32_t j, uint32_t k)
 {
@@ -285,9 +296,46 @@ __device__ __forceinline__ Ring ring_of(const hbheap_dev_t& h, uint32_t j, uint3
     r.state = (uint64_t*)cb;
     r.head = (uint32_t*)(cb + 128);
     r.tail = (uint32_t*)(cb + 256);
-    r.slots = h.slots + (((uint64_t)j * h.n_classes + k) << h.log2q);
-    r.mask = (1u << h.log2q) - 1u;
+    r.j = j;
+    if (h.variant == HBHEAP_VARIANT_VA_PAGE) {
+        r.slots = nullptr;
+        r.mask = 0;
+        r.dir = h.vdir + (((uint64_t)j * h.n_classes + k) << h.log2_dir);
+        r.dmask = (1u << h.log2_dir) - 1u;
+        r.segs = h.slots + (((uint64_t)j * h.vsegs) << h.log2_seg);
+        r.log2g = h.log2_seg;
+    } else {
+        r.slots = h.slots + (((uint64_t)j * h.n_classes + k) << h.log2q);
+        r.mask = (1u << h.log2q) - 1u;
+        r.dir = nullptr;
+        r.segs = nullptr;
+        r.dmask = 0;
+        r.log2g = 0;
+    }
     return r;
+}
+/* The segment store of shard j (virtualised array variant): a plain ring
+ * of free segment ids. */
+__device__ __forceinline__ Ring store_of(const hbheap_dev_t& h, uint32_t j)
+{
+    uint8_t* sb = h.vstore + (uint64_t)j * kStoreBlock;
+    Ring r;
+    r.state = (uint64_t*)sb;
+    r.head = (uint32_t*)(sb + 128);
+    r.tail = (uint32_t*)(sb + 256);
+    r.slots = h.vstore_slots + ((uint64_t)j << h.log2_store);
+    r.mask = (1u << h.log2_store) - 1u;
+    r.dir = nullptr;
+    r.segs = nullptr;
+    r.dmask = 0;
+    r.log2g = 0;
+    r.j = j;
+    return r;
+}
+/* Pages the classes of shard j own together (virtualised array variant). */
+__device__ __forceinline__ uint64_t* committed_of(const hbheap_dev_t& h, uint32_t j)
+{
+    return (uint64_t*)(h.vstore + (uint64_t)j * kStoreBlock + 384);
 }
 __device__ __forceinline__ uint64_t* owned_of(const hbheap_dev_t& h, uint32_t j, uint32_t k)
 {
@@ -331,11 +379,127 @@ __device__ __forceinline__ void ring_release(const Ring& r, uint32_t publish, Ta
     t.state += 1;
 }
 
+__device__ __forceinline__ uint32_t plain_take(const hbheap_dev_t& h, uint32_t* s, Tally& t);
+__device__ __forceinline__ bool plain_put(const hbheap_dev_t& h, uint32_t* s, uint32_t v, Tally& t);
+
+/* Per lane, segment store of shard j: take a free segment id (wait, bounded,
+ * while none is published); kEmpty on timeout. */
+__device__ __forceinline__ uint32_t store_take(const hbheap_dev_t& h, uint32_t j, Tally& t)
+{
+    const Ring S = store_of(h, j);
+    Backoff b;
+    for (;;) {
+        const uint64_t old = a_add64(S.state, (uint64_t)0 - 1ull);
+        t.state += 1;
+        if (state_count(old) > 0) break;
+        a_add64(S.state, 1ull);
+        if (!b.wait(h)) {
+            raise_err(h, HBHEAP_ERR_TIMEOUT, HBHEAP_STAT_TIMEOUTS);
+            return kEmpty;
+        }
+    }
+    const uint32_t pos = a_add32(S.head, 1u);
+    t.headtail += 1;
+    return plain_take(h, S.slots + (pos & S.mask), t);
+}
+/* Per lane: return segment id seg to the store of shard j. */
+__device__ __forceinline__ void store_put(const hbheap_dev_t& h, uint32_t j, uint32_t seg, Tally& t)
+{
+    const Ring S = store_of(h, j);
+    const uint32_t pos = a_add32(S.tail, 1u);
+    t.headtail += 1;
+    plain_put(h, S.slots + (pos & S.mask), seg, t);
+    a_add64(S.state, 1ull);
+    t.state += 1;
+}
+
+/* Per lane, virtualised array ring: the slot of position pos and its
+ * segment.  The segment of position p is number s = p >> log2g; directory
+ * entry s mod 2^log2_dir holds (s << 32 | id) while it is in use.  The
+ * producer of a segment's first position installs it (a segment from the
+ * store, all slots empty) once the entry is empty; everyone else waits for
+ * the entry to show segment s.  nullptr on timeout. */
+__device__ __forceinline__ uint32_t* va_slot(const hbheap_dev_t& h, const Ring& r, uint32_t pos, bool producer,
+                                             uint32_t* seg_out, Tally& t)
+{
+    const uint32_t s = pos >> r.log2g;
+    const uint32_t off = pos & ((1u << r.log2g) - 1u);
+    uint64_t* e = r.dir + (s & r.dmask);
+    Backoff b;
+    for (;;) {
+        const uint64_t d = a_load64(e);
+        if (d != kDirEmpty && (uint32_t)(d >> 32) == s) {
+            *seg_out = (uint32_t)d;
+            return r.segs + ((uint64_t)(uint32_t)d << r.log2g) + off;
+        }
+        if (producer && off == 0 && d == kDirEmpty) {
+            const uint32_t seg = store_take(h, r.j, t);
+            if (seg == kEmpty) return nullptr;
+            uint64_t expect = kDirEmpty;
+            if (__hip_atomic_compare_exchange_strong(e, &expect, ((uint64_t)s << 32) | seg, __ATOMIC_RELAXED,
+                                                     __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+                t.spread += 1;
+                *seg_out = seg;
+                return r.segs + ((uint64_t)seg << r.log2g);
+            }
+            store_put(h, r.j, seg, t); /* not reached: one installer per segment */
+            continue;
+        }
+        if (!b.wait(h)) {
+            raise_err(h, HBHEAP_ERR_TIMEOUT, HBHEAP_STAT_TIMEOUTS);
+            return nullptr;
+        }
+    }
+}
+
 /* Per lane: take the entry of ring position pos (wait while its producer is
- * late).  kEmpty on timeout. */
+ * late).  kEmpty on timeout.  Virtualised array rings: *seg receives the
+ * position's segment id, and the caller counts the slot consumed with
+ * va_count_taken() once the lanes of the wave have taken theirs. */
+__device__ __forceinline__ uint32_t slot_take(const hbheap_dev_t& h, const Ring& r, uint32_t pos, uint32_t* seg,
+                                              Tally& t)
+{
+    if (r.dir) {
+        uint32_t* s = va_slot(h, r, pos, false, seg, t);
+        return s ? plain_take(h, s, t) : kEmpty;
+    }
+    return plain_take(h, r.slots + (pos & r.mask), t);
+}
 __device__ __forceinline__ uint32_t slot_take(const hbheap_dev_t& h, const Ring& r, uint32_t pos, Tally& t)
 {
-    uint32_t* s = r.slots + (pos & r.mask);
+    uint32_t seg = 0;
+    return slot_take(h, r, pos, &seg, t);
+}
+
+/* Virtualised array rings, wave-wide: the lanes with `took` consumed ring
+ * position pos of segment seg of ring r.  Runs of adjacent lanes on one
+ * segment add their number to its consumed count with one atomic; the run
+ * completing the segment empties its directory entry and returns it to the
+ * store (every slot of it was emptied by its consumer before that consumer
+ * was counted). */
+__device__ __forceinline__ void va_count_taken(const hbheap_dev_t& h, const Ring& r, bool took, uint32_t pos,
+                                               uint32_t seg, Tally& t)
+{
+    const uint32_t me = lane();
+    const Run run = run_combine(took, (uint64_t)r.j * h.vsegs + seg, 1ull << me, 64u);
+    if (took && me == run.tail) {
+        const uint32_t n = (uint32_t)__popcll(run.incl);
+        uint32_t* tk = h.vtaken + (uint64_t)r.j * h.vsegs + seg;
+        const uint32_t c = a_add32(tk, n) + n;
+        t.spread += 1;
+        if (c == (1u << r.log2g)) {
+            __hip_atomic_store(tk, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(r.dir + ((pos >> r.log2g) & r.dmask), kDirEmpty, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+            fence_release();
+            store_put(h, r.j, seg, t);
+        }
+    }
+}
+
+/* Per lane: exchange the entry out of slot s (wait while it is empty). */
+__device__ __forceinline__ uint32_t plain_take(const hbheap_dev_t& h, uint32_t* s, Tally& t)
+{
     Backoff b;
     for (;;) {
         if (a_load32(s) != kEmpty) {
@@ -354,7 +518,17 @@ __device__ __forceinline__ uint32_t slot_take(const hbheap_dev_t& h, const Ring&
  * the entry of the previous lap). */
 __device__ __forceinline__ bool slot_put(const hbheap_dev_t& h, const Ring& r, uint32_t pos, uint32_t v, Tally& t)
 {
-    uint32_t* s = r.slots + (pos & r.mask);
+    if (r.dir) {
+        uint32_t seg = 0;
+        uint32_t* s = va_slot(h, r, pos, true, &seg, t);
+        return s ? plain_put(h, s, v, t) : false;
+    }
+    return plain_put(h, r.slots + (pos & r.mask), v, t);
+}
+
+/* Per lane: compare-and-swap v into slot s (wait while it is still full). */
+__device__ __forceinline__ bool plain_put(const hbheap_dev_t& h, uint32_t* s, uint32_t v, Tally& t)
+{
     Backoff b;
     for (;;) {
         if (a_load32(s) == kEmpty) {
@@ -511,6 +685,24 @@ __device__ __forceinline__ Group make_group(const hbheap_dev_t& h, uint32_t k, u
 __device__ __forceinline__ uint32_t owned_reserve(const hbheap_dev_t& h, uint32_t j, uint32_t k, uint32_t lppc, uint32_t m,
                                                   Tally& tl)
 {
+    if (h.variant == HBHEAP_VARIANT_VA_PAGE) {
+        /* the classes of a shard share one page budget: the store's segments
+         * less a few per queue (positions span at most the pages a queue's
+         * class owns, plus partial segments at both ends) */
+        uint64_t* cm = committed_of(h, j);
+        uint64_t c = a_load64(cm);
+        for (;;) {
+            const uint64_t room = h.vbudget > c ? (h.vbudget - c) >> lppc : 0ull;
+            if (room == 0) return 0;
+            const uint32_t allow = room < m ? (uint32_t)room : m;
+            tl.pool += 1;
+            if (__hip_atomic_compare_exchange_strong(cm, &c, c + ((uint64_t)allow << lppc), __ATOMIC_RELAXED,
+                                                     __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+                a_add64(owned_of(h, j, k), allow);
+                return allow;
+            }
+        }
+    }
     uint64_t* owned = owned_of(h, j, k);
     const uint64_t maxc = page_max_chunks(h, lppc);
     uint64_t o = a_load64(owned);
@@ -528,10 +720,17 @@ __device__ __forceinline__ uint32_t owned_reserve(const hbheap_dev_t& h, uint32_
  * counter read before the state word.)  A wave skips a shard that shows
  * neither instead of taking a hold on it, so waves that find nothing do not
  * keep the shard's hold count busy. */
+/* Page variants: may class k of shard j take another chunk? */
+__device__ __forceinline__ bool class_has_room(const hbheap_dev_t& h, uint32_t j, uint32_t k, uint32_t lppc)
+{
+    if (h.variant == HBHEAP_VARIANT_PAGE) return a_load64(owned_of(h, j, k)) < page_max_chunks(h, lppc);
+    if (h.variant == HBHEAP_VARIANT_VA_PAGE) return a_load64(committed_of(h, j)) + (1ull << lppc) <= h.vbudget;
+    return true;
+}
 __device__ __forceinline__ bool shard_has_something(const hbheap_dev_t& h, uint32_t j, uint32_t k, uint32_t lppc)
 {
     bool grow = !pool_empty(h, j);
-    if (grow && h.variant == HBHEAP_VARIANT_PAGE) grow = a_load64(owned_of(h, j, k)) < page_max_chunks(h, lppc);
+    if (grow) grow = class_has_room(h, j, k, lppc);
     return grow || state_count(a_load64(ring_of(h, j, k).state)) > 0;
 }
 
@@ -553,8 +752,7 @@ __device__ __forceinline__ uint32_t scan_shards(const hbheap_dev_t& h, const Gro
         if (r < S) {
             const uint32_t j = home + r < S ? home + r : home + r - S;
             bool grow = !pool_empty(h, j);
-            if (grow && h.variant == HBHEAP_VARIANT_PAGE)
-                grow = a_load64(owned_of(h, j, g.k)) < page_max_chunks(h, g.lppc);
+            if (grow) grow = class_has_room(h, j, g.k, g.lppc);
             const uint64_t st = a_load64(ring_of(h, j, g.k).state);
             hold = (st >> 32) != 0;
             avail = state_count(st) > 0 || grow;
@@ -763,8 +961,12 @@ __device__ __forceinline__ void page_serve_shard(const hbheap_dev_t& h, const Gr
          * one atomicAnd per bitmask word shared by the takers */
         bool took_page = false;
         uint64_t widx = 0, bit = 0, o = 0;
+        uint32_t vseg = 0;
+        bool took_slot = false;
+        const uint32_t mypos = h0 + (g.qrank - served);
         if (g.req && g.qrank >= served && g.qrank < served + got) {
-            const uint32_t v = slot_take(h, R, h0 + (g.qrank - served), tl);
+            const uint32_t v = slot_take(h, R, mypos, &vseg, tl);
+            took_slot = v != kEmpty;
             o = (uint64_t)v << 4;
             if (v != kEmpty && (o >= h.data_bytes || shard_of_chunk(h, o >> h.log2_chunk) != j)) {
                 raise_err(h, HBHEAP_ERR_CORRUPT, HBHEAP_STAT_TIMEOUTS);
@@ -776,6 +978,7 @@ __device__ __forceinline__ void page_serve_shard(const hbheap_dev_t& h, const Gr
                 took_page = true;
             }
         }
+        if (R.dir) va_count_taken(h, R, took_slot, mypos, vseg, tl);
         clear_bits_grouped(h, took_page, widx, bit, o, off, tl);
         need -= got;
         served += got;
@@ -793,6 +996,8 @@ __device__ __forceinline__ void page_serve_shard(const hbheap_dev_t& h, const Gr
                     if (gm < allow) {
                         /* the pool ran dry: give back what was not taken */
                         a_add64(owned_of(h, j, g.k), (uint64_t)0 - (uint64_t)(allow - gm));
+                        if (h.variant == HBHEAP_VARIANT_VA_PAGE)
+                            a_add64(committed_of(h, j), (uint64_t)0 - ((uint64_t)(allow - gm) << g.lppc));
                         tl.pool += 1;
                     }
                 }
@@ -946,7 +1151,7 @@ __device__ __forceinline__ void* malloc_wave(const hbheap_dev_t& h, uint64_t n, 
      * after another.  It publishes nothing (no refill); groups left short
      * continue below, each on its own. */
     uint32_t done = 0;
-    const bool fast = h.variant == HBHEAP_VARIANT_PAGE && ngroups > 1;
+    const bool fast = h.variant != HBHEAP_VARIANT_CHUNK && ngroups > 1;
     if (fast) {
         const bool lead = k >= 0 && me == gl;
         Ring R;
@@ -961,11 +1166,13 @@ __device__ __forceinline__ void* malloc_wave(const hbheap_dev_t& h, uint64_t n, 
         }
         done = perm32(got, gl);
         h0 = perm32(h0, gl);
-        bool took = false;
+        bool took = false, took_slot = false;
         uint64_t widx = 0, bit = 0, o = 0;
+        uint32_t vseg = 0;
         if (k >= 0 && gr < done) {
             const uint32_t shift = 4u + (uint32_t)k;
-            const uint32_t v = slot_take(h, R, h0 + gr, tl);
+            const uint32_t v = slot_take(h, R, h0 + gr, &vseg, tl);
+            took_slot = v != kEmpty;
             o = (uint64_t)v << 4;
             if (v != kEmpty && (o >= h.data_bytes || shard_of_chunk(h, o >> h.log2_chunk) != home)) {
                 raise_err(h, HBHEAP_ERR_CORRUPT, HBHEAP_STAT_TIMEOUTS);
@@ -977,6 +1184,7 @@ __device__ __forceinline__ void* malloc_wave(const hbheap_dev_t& h, uint64_t n, 
                 took = true;
             }
         }
+        if (h.variant == HBHEAP_VARIANT_VA_PAGE) va_count_taken(h, R, took_slot, h0 + gr, vseg, tl);
         clear_bits_grouped(h, took, widx, bit, o, off, tl);
         if (lead && !home_dry) ring_release(R, 0, tl);
     }

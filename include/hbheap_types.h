@@ -19,9 +19,13 @@ extern "C" {
 #endif
 
 /* Queue variants (Results): "chunk" queues list chunks that have free
- * pages; "page" queues list free pages. */
-#define HBHEAP_VARIANT_CHUNK 0u
-#define HBHEAP_VARIANT_PAGE  1u
+ * pages; "page" queues list free pages; "virtualised array page" queues
+ * list free pages in storage taken on demand, segment by segment, from a
+ * store the class queues of a shard share ("Virtualised array and list
+ * allocators"). */
+#define HBHEAP_VARIANT_CHUNK   0u
+#define HBHEAP_VARIANT_PAGE    1u
+#define HBHEAP_VARIANT_VA_PAGE 2u
 
 /* Return codes of every host entry point. */
 #define HBHEAP_OK          0
@@ -64,7 +68,7 @@ extern "C" {
  */
 typedef struct hbheap_dev {
     uint8_t*  data;            /* data region: n_chunks * 2^log2_chunk bytes  */
-    uint8_t*  state;           /* state region (snapshot layout, version 1)  */
+    uint8_t*  state;           /* state region (snapshot layout, version 3)  */
     uint64_t* pool;            /* n_shards pool blocks of 128 bytes: u64 bump,
                                   u32 size, u32 first index into pool_ids    */
     uint8_t*  classes;         /* n_shards * n_classes blocks of 512 bytes   */
@@ -89,6 +93,22 @@ typedef struct hbheap_dev {
     uint32_t  n_shards;        /* shards; shard j owns chunks
                                   [j << log2_span, (j+1) << log2_span)       */
     uint32_t  log2_span;
+    /* virtualised array page variant (all zero / NULL otherwise): the slot
+     * region holds, per shard, vsegs segments of 2^log2_seg slots; a class
+     * queue finds the segment of ring position p in its directory entry
+     * (p >> log2_seg) mod 2^log2_dir, a u64 (segment number << 32 | segment
+     * id), all ones when empty; free segment ids wait in the shard's store,
+     * a ring of 2^log2_store u32 with its own state/head/tail block (512 B;
+     * u64 pages the shard's classes own @384). */
+    uint64_t* vdir;            /* n_shards * n_classes * 2^log2_dir entries   */
+    uint32_t* vtaken;          /* per segment: slots consumed so far          */
+    uint8_t*  vstore;          /* n_shards store blocks of 512 bytes          */
+    uint32_t* vstore_slots;    /* n_shards rings of 2^log2_store u32          */
+    uint32_t  log2_seg;
+    uint32_t  log2_dir;
+    uint32_t  log2_store;
+    uint32_t  vsegs;           /* segments per shard                         */
+    uint64_t  vbudget;         /* pages the classes of one shard may own     */
 } hbheap_dev_t;
 
 /* Count refills, chunk grabs and atomics by target in the statistics

@@ -29,7 +29,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liboracle.so")
 SOURCES = ["hbheap_oracle.c", "hbheap_model.c"]
 
-VARIANT_CHUNK, VARIANT_PAGE = 0, 1
+VARIANT_CHUNK, VARIANT_PAGE, VARIANT_VA_PAGE = 0, 1, 2
 POLICY_LOWEST, POLICY_FIFO = 0, 1
 FREE_OK, FREE_DOUBLE, FREE_INVALID, FREE_NULL = 0, 1, 2, 3
 MAX_CLASSES = 16
@@ -75,7 +75,9 @@ class SnapReport(C.Structure):
         ("bad_class_byte", C.c_uint64), ("bad_free_chunk", C.c_uint64), ("bad_stray_bits", C.c_uint64),
         ("bad_count", C.c_uint64), ("bad_pool", C.c_uint64), ("bad_ring_ctl", C.c_uint64),
         ("bad_ring_entry", C.c_uint64), ("bad_ring_missing", C.c_uint64), ("bad_ring_dup", C.c_uint64),
-        ("bad_conservation", C.c_uint64), ("bad_owned", C.c_uint64), ("free_chunks", C.c_uint64),
+        ("bad_conservation", C.c_uint64), ("bad_owned", C.c_uint64),
+        ("bad_vdir", C.c_uint64), ("bad_vtaken", C.c_uint64), ("bad_vstore", C.c_uint64),
+        ("bad_committed", C.c_uint64), ("free_chunks", C.c_uint64),
         ("live", C.c_uint64 * MAX_CLASSES), ("chunks", C.c_uint64 * MAX_CLASSES),
         ("free_pages", C.c_uint64 * MAX_CLASSES),
     ]
@@ -119,6 +121,9 @@ def lib():
             "orc_pattern_fill": (None, [u32, u32, vp, u64]),
             "orc_pattern_sum": (u32, [u32, u32, u64]),
             "orc_classes": (None, [vp, u64, u64, vp]),
+            "orc_va_log2_seg": (u32, [u64, u64, u32]),
+            "orc_va_segments": (u64, [u64, u64, u32]),
+            "orc_va_budget": (u64, [u64, u64, u32]),
             "orc_pattern_sums": (None, [u32, vp, vp, u64, vp]),
             "orc_check_blocks": (C.c_int, [u64, u64, vp, vp, u64, C.POINTER(BlocksReport)]),
             "orc_check_snapshot": (C.c_int, [vp, u64, C.POINTER(SnapReport)]),
@@ -235,6 +240,18 @@ def shard_geometry(n_chunks: int, requested: int = 0) -> tuple[int, int]:
 
 def page_ring_entries(nbytes: int, chunk_bytes: int, shards: int = 1) -> int:
     return int(lib().orc_page_ring_entries(nbytes, chunk_bytes, shards))
+
+
+def va_log2_seg(nbytes: int, chunk_bytes: int, shards: int = 1) -> int:
+    return int(lib().orc_va_log2_seg(nbytes, chunk_bytes, shards))
+
+
+def va_segments(nbytes: int, chunk_bytes: int, shards: int = 1) -> int:
+    return int(lib().orc_va_segments(nbytes, chunk_bytes, shards))
+
+
+def va_budget(nbytes: int, chunk_bytes: int, shards: int = 1) -> int:
+    return int(lib().orc_va_budget(nbytes, chunk_bytes, shards))
 
 
 def page_max_chunks(nbytes: int, chunk_bytes: int, k: int, shards: int = 1) -> int:

@@ -104,6 +104,35 @@ uint64_t orc_page_max_chunks(uint64_t bytes, uint64_t chunk_bytes, uint32_t k, u
     return orc_page_ring_entries(bytes, chunk_bytes, shards) / orc_pages_per_chunk(chunk_bytes, k);
 }
 
+/* Virtualised array page variant ("Virtualised array and list allocators":
+ * queue storage taken on demand).  The page variant's per-shard entry
+ * budget (K queues of Q entries) becomes one store of segments of
+ * 2^g entries, g = log2(Q) - 3 kept within [4, 10], shared by the shard's
+ * queues.  A queue whose class owns P pages spans at most P positions,
+ * i.e. at most P / 2^g + 2 segments, plus one being handed back: the
+ * shard's classes may own (M - 3K) * 2^g pages together, M = K*Q / 2^g. */
+uint32_t orc_va_log2_seg(uint64_t bytes, uint64_t chunk_bytes, uint32_t shards)
+{
+    uint64_t q = orc_page_ring_entries(bytes, chunk_bytes, shards);
+    uint32_t lq = 0;
+    while ((1ull << (lq + 1)) <= q) ++lq;
+    int g = (int)lq - 3;
+    if (g < 4) g = 4;
+    if (g > 10) g = 10;
+    return (uint32_t)g;
+}
+uint64_t orc_va_segments(uint64_t bytes, uint64_t chunk_bytes, uint32_t shards)
+{
+    return (orc_num_classes(chunk_bytes) * orc_page_ring_entries(bytes, chunk_bytes, shards)) >>
+           orc_va_log2_seg(bytes, chunk_bytes, shards);
+}
+uint64_t orc_va_budget(uint64_t bytes, uint64_t chunk_bytes, uint32_t shards)
+{
+    const uint64_t m = orc_va_segments(bytes, chunk_bytes, shards);
+    const uint64_t k3 = 3ull * orc_num_classes(chunk_bytes);
+    return m > k3 ? (m - k3) << orc_va_log2_seg(bytes, chunk_bytes, shards) : 0;
+}
+
 /* ------------------------------------------------------------------ */
 /* small containers                                                    */
 /* ------------------------------------------------------------------ */
@@ -213,6 +242,7 @@ struct orc_heap {
     uint32_t* cnt;        /* free pages in each owned chunk                  */
     uint64_t* bits;       /* N*W words, bit set = page free                  */
     uint64_t  maxc[ORC_MAX_CLASSES];  /* chunks a class may own per shard    */
+    uint64_t  va_budget;              /* va page: pages a shard's classes own */
     uint64_t* owned;      /* S*K: chunks owned per (shard, class)            */
     orc_acct  acct;
     /* LOWEST policy */
@@ -238,7 +268,7 @@ static uint64_t shard_end(const orc_heap* h, uint32_t j)
 orc_heap* orc_create_ex(uint64_t bytes, uint64_t chunk_bytes, int variant, int policy, uint32_t shards)
 {
     if (!orc_geometry_ok(bytes, chunk_bytes)) return NULL;
-    if (variant != ORC_VARIANT_CHUNK && variant != ORC_VARIANT_PAGE) return NULL;
+    if (variant != ORC_VARIANT_CHUNK && variant != ORC_VARIANT_PAGE && variant != ORC_VARIANT_VA_PAGE) return NULL;
     if (policy != ORC_POLICY_LOWEST && policy != ORC_POLICY_FIFO) return NULL;
     if (shards > 64 || (shards & (shards - 1))) return NULL;
     orc_heap* h = (orc_heap*)calloc(1, sizeof(orc_heap));
@@ -255,6 +285,10 @@ orc_heap* orc_create_ex(uint64_t bytes, uint64_t chunk_bytes, int variant, int p
     h->owned = (uint64_t*)calloc((uint64_t)h->S * h->K, 8);
     for (uint32_t k = 0; k < h->K; ++k)
         h->maxc[k] = variant == ORC_VARIANT_PAGE ? orc_page_max_chunks(bytes, chunk_bytes, k, h->S) : h->N;
+    if (variant == ORC_VARIANT_VA_PAGE) {
+        h->va_budget = orc_va_budget(bytes, chunk_bytes, h->S);
+        if (h->va_budget == 0) { free(h->cls); free(h->cnt); free(h->bits); free(h->owned); free(h); return NULL; }
+    }
     h->acct.n_classes = h->K;
     h->acct.n_chunks = h->N;
     h->acct.free_chunks = h->N;
@@ -327,7 +361,15 @@ static void claim_fresh(orc_heap* h, uint64_t c, uint32_t k)
     h->acct.live[k]++;
 }
 
-static int can_grow(const orc_heap* h, uint32_t j, uint32_t k) { return h->owned[(uint64_t)j * h->K + k] < h->maxc[k]; }
+static int can_grow(const orc_heap* h, uint32_t j, uint32_t k)
+{
+    if (h->variant == ORC_VARIANT_VA_PAGE) {
+        uint64_t pages = 0;
+        for (uint32_t kk = 0; kk < h->K; ++kk) pages += h->owned[(uint64_t)j * h->K + kk] * ppc_of(h, kk);
+        return pages + ppc_of(h, k) <= h->va_budget;
+    }
+    return h->owned[(uint64_t)j * h->K + k] < h->maxc[k];
+}
 
 static int64_t alloc_lowest(orc_heap* h, uint32_t k)
 {
@@ -599,6 +641,18 @@ int orc_check_blocks(uint64_t data_bytes, uint64_t chunk_bytes, const uint64_t* 
 /* ring (j, k) at slot index (j*K + k) << log2 ring cap; page-variant  */
 /* slots hold the page's byte offset / 16; a page-variant class may    */
 /* own at most (ring entries / pages per chunk) chunks of one shard.   */
+/* virtualised array page variant (variant 2), header continued:       */
+/* 112 u32 log2 seg g  116 u32 log2 dir  120 u32 log2 store            */
+/* 124 u32 segments M per shard  128 u64 page budget per shard         */
+/* 136 u64 off dirs  144 u64 off taken  152 u64 off stores             */
+/* 160 u64 off store slots.  The slot region holds, per shard, M       */
+/* segments of 2^g slots (shard j's segment m at slot index            */
+/* (j*M + m) << g).  Queue (j, k) finds position p in the segment      */
+/* named by its directory entry (p >> g) mod 2^dir, u64 at index       */
+/* ((j*K + k) << dir) + that: (p >> g) << 32 | m, all ones if empty;   */
+/* taken u32[S*M] counts each segment's consumed slots; store j: a     */
+/* 512 B block (u64 state, u32 head +128, u32 tail +256, u64 pages     */
+/* the shard's classes own +384) and a ring of 2^store u32 free ids.   */
 /* ------------------------------------------------------------------ */
 
 #define SNAP_MAGIC 0x48424850u
@@ -611,11 +665,15 @@ typedef struct {
     uint64_t data_bytes, N;
     uint32_t log2C, K, variant, W, log2q, S, log2_span;
     const uint8_t *pool, *classes, *cls, *cnt, *bits, *pool_ids, *slots;
+    /* virtualised array */
+    uint32_t g, ldir, lstore, M;
+    uint64_t budget;
+    const uint8_t *vdir, *vtaken, *vstore, *vslots;
 } snapview;
 
 static int snap_open(const uint8_t* s, uint64_t len, snapview* v)
 {
-    if (len < 256 || rd32(s) != SNAP_MAGIC || rd32(s + 4) != 2) return 0;
+    if (len < 256 || rd32(s) != SNAP_MAGIC || rd32(s + 4) != 3) return 0;
     v->data_bytes = rd64(s + 8);
     v->N = rd32(s + 16); v->log2C = rd32(s + 20); v->K = rd32(s + 24);
     v->variant = rd32(s + 28); v->W = rd32(s + 32); v->log2q = rd32(s + 36);
@@ -629,7 +687,37 @@ static int snap_open(const uint8_t* s, uint64_t len, snapview* v)
     if (o_sl + (((uint64_t)v->S * v->K) << v->log2q) * 4 > total) return 0;
     v->pool = s + o_pool; v->classes = s + o_cl; v->cls = s + o_cls; v->cnt = s + o_cnt;
     v->bits = s + o_bits; v->pool_ids = s + o_pid; v->slots = s + o_sl;
+    if (v->variant > 2) return 0;
+    if (v->variant == 2) {
+        v->g = rd32(s + 112); v->ldir = rd32(s + 116); v->lstore = rd32(s + 120); v->M = rd32(s + 124);
+        v->budget = rd64(s + 128);
+        uint64_t o_dir = rd64(s + 136), o_tk = rd64(s + 144), o_st = rd64(s + 152), o_ss = rd64(s + 160);
+        if (v->g < 4 || v->g > 10 || v->ldir > 24 || v->lstore > 24 || v->M == 0 ||
+            ((uint64_t)v->M << v->g) > ((uint64_t)v->K << v->log2q) || (1ull << v->ldir) < (uint64_t)v->M + 3 ||
+            (1ull << v->lstore) < v->M)
+            return 0;
+        if (o_dir + (((uint64_t)v->S * v->K) << v->ldir) * 8 > total || o_tk + (uint64_t)v->S * v->M * 4 > total ||
+            o_st + (uint64_t)v->S * 512 > total || o_ss + ((uint64_t)v->S << v->lstore) * 4 > total)
+            return 0;
+        v->vdir = s + o_dir; v->vtaken = s + o_tk; v->vstore = s + o_st; v->vslots = s + o_ss;
+    }
     return 1;
+}
+
+/* Entry of queue (j, k) at ring position pos, or SLOT_EMPTY when the
+ * position's storage cannot be found (virtualised array: counted as a bad
+ * directory by the caller's own checks). */
+static uint32_t sv_entry(const snapview* v, uint32_t j, uint32_t k, uint32_t pos)
+{
+    const uint64_t ring = (uint64_t)j * v->K + k;
+    if (v->variant != 2) {
+        const uint64_t Q = 1ull << v->log2q;
+        return rd32(v->slots + ((ring << v->log2q) + (pos & (uint32_t)(Q - 1))) * 4);
+    }
+    const uint32_t sg = pos >> v->g;
+    const uint64_t e = rd64(v->vdir + ((ring << v->ldir) + (sg & ((1u << v->ldir) - 1u))) * 8);
+    if (e == ~0ull || (uint32_t)(e >> 32) != sg || (uint32_t)e >= v->M) return SLOT_EMPTY;
+    return rd32(v->slots + ((((uint64_t)j * v->M + (uint32_t)e) << v->g) + (pos & ((1u << v->g) - 1u))) * 4);
 }
 
 static uint64_t sv_word(const snapview* v, uint64_t c, uint32_t w) { return rd64(v->bits + (c * v->W + w) * 8); }
@@ -639,6 +727,92 @@ static uint64_t popc_chunk(const snapview* v, uint64_t c)
     uint64_t t = 0;
     for (uint32_t w = 0; w < v->W; ++w) t += (uint64_t)__builtin_popcountll(sv_word(v, c, w));
     return t;
+}
+
+/* Virtualised array storage at quiescence, shard by shard:
+ *  - queue (j, k) with positions [head, tail) uses exactly the segments
+ *    s = head >> g, ..., while s << g < tail (a segment is handed back when
+ *    all its slots are consumed, installed when its first one is produced);
+ *    each names a distinct segment id < M in directory entry s mod 2^dir,
+ *    every other entry is empty;
+ *  - a used segment's consumed count is its positions below head, a free
+ *    one's zero; every slot that holds no position in [head, tail) is empty;
+ *  - the store holds exactly the ids no queue uses, once each, with no hold;
+ *  - the pages the shard's classes own equal its committed count, within
+ *    the budget. */
+static void check_va(const snapview* v, const uint64_t* chunks_sk, orc_snap_report* rep)
+{
+    const uint64_t G = 1ull << v->g, D = 1ull << v->ldir, QS = 1ull << v->lstore;
+    uint8_t* used = (uint8_t*)malloc(v->M);
+    uint8_t* mark = (uint8_t*)malloc(((uint64_t)v->M << v->g) ? ((uint64_t)v->M << v->g) : 1);
+    uint32_t* cons = (uint32_t*)malloc((uint64_t)v->M * 4);
+    for (uint32_t j = 0; j < v->S; ++j) {
+        memset(used, 0, v->M);
+        memset(mark, 0, (uint64_t)v->M << v->g);
+        memset(cons, 0, (uint64_t)v->M * 4);
+        uint64_t pages = 0;
+        for (uint32_t k = 0; k < v->K; ++k) {
+            const uint64_t ring = (uint64_t)j * v->K + k;
+            const uint8_t* cb = v->classes + ring * 512;
+            const uint32_t head = rd32(cb + 128), tail = rd32(cb + 256);
+            const uint64_t H = head, T = H + (uint32_t)(tail - head);
+            pages += chunks_sk[ring] * ((1ull << v->log2C) >> (4 + k));
+            uint8_t* want = (uint8_t*)calloc(D, 1);
+            const uint64_t smask = (v->g < 32) ? ((1ull << (32 - v->g)) - 1) : 0;
+            for (uint64_t sg = H >> v->g; (sg << v->g) < T; ++sg) {
+                const uint64_t di = sg & (D - 1);
+                if (want[di]) { rep->bad_vdir++; continue; } /* span beyond the directory */
+                want[di] = 1;
+                const uint64_t e = rd64(v->vdir + ((ring << v->ldir) + di) * 8);
+                if (e == ~0ull || (uint32_t)(e >> 32) != (uint32_t)(sg & smask) || (uint32_t)e >= v->M ||
+                    used[(uint32_t)e]) {
+                    rep->bad_vdir++;
+                    continue;
+                }
+                const uint32_t m = (uint32_t)e;
+                used[m] = 1;
+                const uint64_t s0 = sg << v->g;
+                cons[m] = (uint32_t)(H > s0 ? (H < s0 + G ? H - s0 : G) : 0);
+                for (uint64_t p = s0 > H ? s0 : H; p < s0 + G && p < T; ++p) mark[((uint64_t)m << v->g) + (p - s0)] = 1;
+            }
+            for (uint64_t di = 0; di < D; ++di)
+                if (!want[di] && rd64(v->vdir + ((ring << v->ldir) + di) * 8) != ~0ull) rep->bad_vdir++;
+            free(want);
+        }
+        for (uint32_t m = 0; m < v->M; ++m) {
+            if (rd32(v->vtaken + ((uint64_t)j * v->M + m) * 4) != cons[m]) rep->bad_vtaken++;
+            for (uint64_t o = 0; o < G; ++o) {
+                const uint64_t si = ((uint64_t)m << v->g) + o;
+                if (!mark[si] && rd32(v->slots + (((uint64_t)j * v->M << v->g) + si) * 4) != SLOT_EMPTY)
+                    rep->bad_ring_entry++;
+            }
+        }
+        const uint8_t* sb = v->vstore + (uint64_t)j * 512;
+        const uint64_t st = rd64(sb);
+        const uint32_t sh = rd32(sb + 128), stl = rd32(sb + 256);
+        const uint32_t n = stl - sh;
+        if ((uint32_t)(st >> 32) != 0 || (int64_t)(uint32_t)st - (int64_t)0x80000000u != (int64_t)n || n > QS) {
+            rep->bad_vstore++;
+        } else {
+            const uint8_t* ss = v->vslots + ((uint64_t)j << v->lstore) * 4;
+            uint64_t in_store = 0;
+            for (uint32_t i = 0; i < QS; ++i) {
+                const uint32_t id = rd32(ss + (uint64_t)((sh + i) & (uint32_t)(QS - 1)) * 4);
+                if (i >= n) { if (id != SLOT_EMPTY) rep->bad_vstore++; continue; }
+                if (id >= v->M || used[id]) { rep->bad_vstore++; continue; }
+                used[id] = 2;
+                in_store++;
+            }
+            for (uint32_t m = 0; m < v->M; ++m)
+                if (!used[m]) rep->bad_vstore++; /* a segment neither in use nor in the store */
+            (void)in_store;
+        }
+        const uint64_t committed = rd64(sb + 384);
+        if (committed != pages || committed > v->budget) rep->bad_committed++;
+    }
+    free(used);
+    free(mark);
+    free(cons);
 }
 
 int orc_check_snapshot(const uint8_t* snap, uint64_t len, orc_snap_report* rep)
@@ -712,18 +886,21 @@ int orc_check_snapshot(const uint8_t* snap, uint64_t len, orc_snap_report* rep)
             uint32_t H = (uint32_t)(state >> 32);
             int64_t Cnt = (int64_t)(uint32_t)state - (int64_t)0x80000000u;
             uint32_t used = tail - head;
-            if (H != 0 || Cnt != (int64_t)used || used > Q) { rep->bad_ring_ctl++; continue; }
-            if (v.variant == 1 && owned != chunks_sk[ring]) rep->bad_owned++;
+            const uint64_t cap = v.variant == 2 ? ((uint64_t)v.M << v.g) : Q;
+            if (H != 0 || Cnt != (int64_t)used || used > cap) { rep->bad_ring_ctl++; continue; }
+            if (v.variant != 0 && owned != chunks_sk[ring]) rep->bad_owned++;
             if (v.variant == 1 && chunks_sk[ring] > (Q >> (v.log2C - 4 - k))) rep->bad_owned++;
-            const uint8_t* sl = v.slots + (ring << v.log2q) * 4;
-            for (uint64_t i = used; i < Q; ++i) {
-                uint32_t e = rd32(sl + ((uint64_t)((head + (uint32_t)i) & (uint32_t)(Q - 1))) * 4);
-                if (e != SLOT_EMPTY) rep->bad_ring_entry++;
+            if (v.variant != 2) {
+                const uint8_t* sl = v.slots + (ring << v.log2q) * 4;
+                for (uint64_t i = used; i < Q; ++i) {
+                    uint32_t e = rd32(sl + ((uint64_t)((head + (uint32_t)i) & (uint32_t)(Q - 1))) * 4);
+                    if (e != SLOT_EMPTY) rep->bad_ring_entry++;
+                }
             }
             if (v.variant == 0) {
                 for (uint64_t c = lo; c < hi; ++c) seen[c] = 0;
                 for (uint32_t i = 0; i < used; ++i) {
-                    uint32_t c = rd32(sl + ((uint64_t)((head + i) & (uint32_t)(Q - 1))) * 4);
+                    uint32_t c = sv_entry(&v, j, k, head + i);
                     if (c < lo || c >= hi || v.cls[c] != k || rd32(v.cnt + (uint64_t)c * 4) == 0) { rep->bad_ring_entry++; continue; }
                     if (seen[c]) { rep->bad_ring_dup++; continue; }
                     seen[c] = 1;
@@ -736,7 +913,7 @@ int orc_check_snapshot(const uint8_t* snap, uint64_t len, orc_snap_report* rep)
                 uint64_t npages = (hi - lo) * ppc;
                 uint8_t* pseen = (uint8_t*)calloc(npages ? npages : 1, 1);
                 for (uint32_t i = 0; i < used; ++i) {
-                    uint64_t off = (uint64_t)rd32(sl + ((uint64_t)((head + i) & (uint32_t)(Q - 1))) * 4) * 16;
+                    uint64_t off = (uint64_t)sv_entry(&v, j, k, head + i) * 16;
                     uint64_t c = off >> v.log2C;
                     uint64_t in = off & (C - 1);
                     if (off >= v.data_bytes || c < lo || c >= hi || v.cls[c] != k || in % s) { rep->bad_ring_entry++; continue; }
@@ -756,12 +933,14 @@ int orc_check_snapshot(const uint8_t* snap, uint64_t len, orc_snap_report* rep)
             }
         }
     }
+    if (v.variant == 2) check_va(&v, chunks_sk, rep);
     free(seen);
     free(chunks_sk);
     free(free_s);
     uint64_t bad = rep->bad_class_byte + rep->bad_free_chunk + rep->bad_stray_bits + rep->bad_count + rep->bad_pool +
                    rep->bad_ring_ctl + rep->bad_ring_entry + rep->bad_ring_missing + rep->bad_ring_dup +
-                   rep->bad_conservation + rep->bad_owned;
+                   rep->bad_conservation + rep->bad_owned + rep->bad_vdir + rep->bad_vtaken + rep->bad_vstore +
+                   rep->bad_committed;
     return bad ? 1 : 0;
 }
 

@@ -38,7 +38,7 @@ extern "C" {
 
 #define ORC_MAX_CLASSES 16
 
-enum { ORC_VARIANT_CHUNK = 0, ORC_VARIANT_PAGE = 1 };
+enum { ORC_VARIANT_CHUNK = 0, ORC_VARIANT_PAGE = 1, ORC_VARIANT_VA_PAGE = 2 };
 /* LOWEST: canonical legal outcome (lowest chunk id, then lowest page).
  * FIFO:   the order a single device thread observes (queue order). */
 enum { ORC_POLICY_LOWEST = 0, ORC_POLICY_FIFO = 1 };
@@ -54,6 +54,11 @@ void     orc_shard_geometry(uint64_t n_chunks, uint32_t requested, uint32_t* sha
 uint64_t orc_page_ring_entries(uint64_t bytes, uint64_t chunk_bytes, uint32_t shards);
 uint64_t orc_page_max_chunks(uint64_t bytes, uint64_t chunk_bytes, uint32_t k, uint32_t shards);
 int      orc_geometry_ok(uint64_t bytes, uint64_t chunk_bytes);
+/* virtualised array page variant: segment size (log2 entries), segments and
+ * page budget per shard */
+uint32_t orc_va_log2_seg(uint64_t bytes, uint64_t chunk_bytes, uint32_t shards);
+uint64_t orc_va_segments(uint64_t bytes, uint64_t chunk_bytes, uint32_t shards);
+uint64_t orc_va_budget(uint64_t bytes, uint64_t chunk_bytes, uint32_t shards);
 
 /* ---- sequential allocator ---- */
 typedef struct orc_heap orc_heap;
@@ -113,11 +118,12 @@ typedef struct {
     uint64_t bad_class_byte, bad_free_chunk, bad_stray_bits, bad_count;
     uint64_t bad_pool, bad_ring_ctl, bad_ring_entry, bad_ring_missing, bad_ring_dup;
     uint64_t bad_conservation, bad_owned;
+    uint64_t bad_vdir, bad_vtaken, bad_vstore, bad_committed; /* virtualised array */
     uint64_t free_chunks;
     uint64_t live[ORC_MAX_CLASSES], chunks[ORC_MAX_CLASSES], free_pages[ORC_MAX_CLASSES];
 } orc_snap_report;
 
-/* Quiescent-state consistency of a snapshot (documented layout, version 2). */
+/* Quiescent-state consistency of a snapshot (documented layout, version 3). */
 int orc_check_snapshot(const uint8_t* snap, uint64_t len, orc_snap_report* rep);
 
 /* Blocks against a snapshot: each live block must lie in a chunk of its

@@ -31,7 +31,7 @@ using namespace hbheap::detail;
 namespace {
 
 constexpr uint32_t kMagic = 0x48424850u;
-constexpr uint32_t kVersion = 2;
+constexpr uint32_t kVersion = 3;
 constexpr uint32_t kBatchBlock = 256;
 constexpr uint32_t kTrimBlock = 1024;
 constexpr uint32_t kMaxKeys = 1024; /* trim keys: 64 shards x (13 classes + pool) + none */
@@ -40,6 +40,10 @@ constexpr uint32_t kMaxShards = 64;
 struct Layout {
     uint64_t off_pool, off_cl, off_cls, off_cnt, off_bits, off_pid, off_sl, total;
     uint32_t log2q;
+    /* virtualised array page variant */
+    uint64_t off_vdir = 0, off_vtaken = 0, off_vstore = 0, off_vslots = 0;
+    uint32_t log2_seg = 0, log2_dir = 0, log2_store = 0, vsegs = 0;
+    uint64_t vbudget = 0;
 };
 
 uint64_t al256(uint64_t x) { return (x + 255) & ~255ull; }
@@ -272,7 +276,20 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t* wsum)
 
 /* Pass 3: write pool ids and ring entries in ascending chunk (page) order,
  * for the keys of the shards this block's chunks belong to. */
-__global__ void __launch_bounds__(kTrimBlock) k_trim_write(hbheap_dev_t h, const uint32_t* offsets, uint32_t nblocks)
+/* Virtualised array queues after a trim: queue (j, k) holds its entries at
+ * positions 0 .. totals[j*K+k]-1 in segments numbered from the shard's
+ * first, queue after queue: its first segment id is the number of segments
+ * the shard's lower classes use. */
+__device__ __forceinline__ uint32_t va_first_seg(const hbheap_dev_t& h, const uint32_t* totals, uint32_t j, uint32_t k)
+{
+    uint32_t base = 0;
+    const uint32_t g = 1u << h.log2_seg;
+    for (uint32_t kk = 0; kk < k; ++kk) base += (totals[j * h.n_classes + kk] + g - 1u) >> h.log2_seg;
+    return base;
+}
+
+__global__ void __launch_bounds__(kTrimBlock) k_trim_write(hbheap_dev_t h, const uint32_t* offsets, uint32_t nblocks,
+                                                           const uint32_t* totals)
 {
     __shared__ uint32_t wsum[kTrimBlock / 64];
     const uint64_t c0 = (uint64_t)blockIdx.x * kTrimBlock;
@@ -301,13 +318,22 @@ __global__ void __launch_bounds__(kTrimBlock) k_trim_write(hbheap_dev_t h, const
                 const uint32_t ppc = 1u << (h.log2_chunk - shift);
                 const uint32_t nw = ppc >= 64u ? ppc >> 6 : 1u;
                 uint32_t q = pos;
+                const bool va = h.variant == HBHEAP_VARIANT_VA_PAGE;
+                const uint32_t seg0 = va ? va_first_seg(h, totals, j, kk) : 0u;
                 for (uint32_t wd = 0; wd < nw; ++wd) {
                     uint64_t x = h.bits[c * h.words_per_chunk + wd];
                     while (x) {
                         const uint32_t b = ctz64(x);
                         x &= x - 1ull;
                         const uint64_t off = (c << h.log2_chunk) + ((uint64_t)(wd * 64u + b) << shift);
-                        if (q < Q) h.slots[(uint64_t)key * Q + q] = (uint32_t)(off >> 4);
+                        if (va) {
+                            const uint64_t seg = seg0 + (q >> h.log2_seg);
+                            if (seg < h.vsegs)
+                                h.slots[(((uint64_t)j * h.vsegs + seg) << h.log2_seg) + (q & ((1u << h.log2_seg) - 1u))] =
+                                    (uint32_t)(off >> 4);
+                        } else if (q < Q) {
+                            h.slots[(uint64_t)key * Q + q] = (uint32_t)(off >> 4);
+                        }
                         ++q;
                     }
                 }
@@ -325,12 +351,57 @@ __global__ void k_trim_ctl(hbheap_dev_t h, const uint32_t* totals, const uint32_
         *(uint64_t*)cb = (uint64_t)(totals[i] + kBias);
         *(uint32_t*)(cb + 128) = 0;
         *(uint32_t*)(cb + 256) = totals[i];
-        *(uint64_t*)(cb + 384) = h.variant == HBHEAP_VARIANT_PAGE ? (uint64_t)owned[i] : 0ull;
+        *(uint64_t*)(cb + 384) = h.variant != HBHEAP_VARIANT_CHUNK ? (uint64_t)owned[i] : 0ull;
     }
     for (uint32_t j = threadIdx.x; j < S; j += blockDim.x) {
         uint64_t* pb = h.pool + 16ull * j;
         pb[0] = 0;
         ((uint32_t*)pb)[2] = totals[S * K + j];
+    }
+}
+
+/* Virtualised array queues, all at once (heap creation: totals == nullptr,
+ * every queue empty; trim: queue (j, k) holds totals[j*K+k] entries written
+ * by k_trim_write): directories name the segments in use, every segment's
+ * consumed count is zero, each shard's store holds its unused segment ids
+ * in ascending order, and the shard's committed pages are those its
+ * classes own. */
+__global__ void k_va_rebuild(hbheap_dev_t h, const uint32_t* totals, const uint32_t* owned)
+{
+    const uint32_t S = h.n_shards, K = h.n_classes, M = h.vsegs;
+    const uint64_t D = 1ull << h.log2_dir, QS = 1ull << h.log2_store, g = 1ull << h.log2_seg;
+    const uint64_t n_dir = (uint64_t)S * K * D, n_taken = (uint64_t)S * M, n_store = (uint64_t)S * QS;
+    const uint64_t n = n_dir > n_store ? (n_dir > n_taken ? n_dir : n_taken) : (n_store > n_taken ? n_store : n_taken);
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        if (i < n_dir) {
+            const uint64_t q = i >> h.log2_dir, dd = i & (D - 1);
+            const uint32_t j = (uint32_t)(q / K), k = (uint32_t)(q % K);
+            const uint32_t used = totals ? (uint32_t)((totals[j * K + k] + g - 1) >> h.log2_seg) : 0u;
+            const uint32_t base = totals ? va_first_seg(h, totals, j, k) : 0u;
+            h.vdir[i] = dd < used && base + dd < M ? ((dd << 32) | (uint64_t)(base + (uint32_t)dd)) : kDirEmpty;
+        }
+        if (i < n_taken) h.vtaken[i] = 0;
+        if (i < n_store) {
+            const uint32_t j = (uint32_t)(i >> h.log2_store);
+            const uint32_t p = (uint32_t)(i & (QS - 1));
+            const uint32_t used = totals ? va_first_seg(h, totals, j, K) : 0u;
+            const uint32_t free_n = used < M ? M - used : 0u;
+            h.vstore_slots[i] = p < free_n ? used + p : kEmpty;
+        }
+        if (i < S) {
+            const uint32_t j = (uint32_t)i;
+            const uint32_t used0 = totals ? va_first_seg(h, totals, j, K) : 0u;
+            const uint32_t used = used0 < M ? used0 : M;
+            uint64_t pages = 0;
+            if (owned)
+                for (uint32_t k = 0; k < K; ++k) pages += (uint64_t)owned[j * K + k] << (h.log2_chunk - 4u - k);
+            uint8_t* sb = h.vstore + (uint64_t)j * kStoreBlock;
+            *(uint64_t*)sb = (uint64_t)(M - used) + kBias;
+            *(uint32_t*)(sb + 128) = 0;
+            *(uint32_t*)(sb + 256) = M - used;
+            *(uint64_t*)(sb + 384) = pages;
+        }
     }
 }
 
@@ -514,6 +585,13 @@ int fill_u32(uint32_t* p, uint64_t n, uint32_t v, hipStream_t s)
     return hipGetLastError() == hipSuccess ? HBHEAP_OK : HBHEAP_E_HIP;
 }
 
+int va_rebuild(const hbheap_dev_t& d, const uint32_t* totals, const uint32_t* owned, hipStream_t s)
+{
+    const uint64_t n = (uint64_t)d.n_shards * d.n_classes << d.log2_dir;
+    hipLaunchKernelGGL(k_va_rebuild, dim3(grid_stride(n)), dim3(256), 0, s, d, totals, owned);
+    return hipGetLastError() == hipSuccess ? HBHEAP_OK : HBHEAP_E_HIP;
+}
+
 int fill_u8(uint8_t* p, uint64_t n, uint8_t v, hipStream_t s)
 {
     if (!n) return HBHEAP_OK;
@@ -556,6 +634,22 @@ Layout make_layout(uint64_t N, uint32_t log2C, uint32_t K, uint32_t variant, uin
     L.off_pid = al256(L.off_bits + 8 * N * W);
     L.off_sl = al256(L.off_pid + 4 * N);
     L.total = al256(L.off_sl + 4ull * S * K * (1ull << L.log2q));
+    if (variant == HBHEAP_VARIANT_VA_PAGE) {
+        /* the page variant's slot budget, cut into segments a shard's queues
+         * share: 2^log2_seg slots each (Q/8, kept within 16 .. 1024) */
+        uint32_t lg = L.log2q >= 3 ? L.log2q - 3 : 0;
+        lg = lg < 4 ? 4 : (lg > 10 ? 10 : lg);
+        L.log2_seg = lg;
+        L.vsegs = (uint32_t)(((uint64_t)K << L.log2q) >> lg);
+        L.log2_dir = ceil_log2((uint64_t)L.vsegs + 3);
+        L.log2_store = ceil_log2(L.vsegs);
+        L.vbudget = L.vsegs > 3 * K ? (uint64_t)(L.vsegs - 3 * K) << lg : 0;
+        L.off_vdir = L.total;
+        L.off_vtaken = al256(L.off_vdir + 8ull * S * K * (1ull << L.log2_dir));
+        L.off_vstore = al256(L.off_vtaken + 4ull * S * L.vsegs);
+        L.off_vslots = al256(L.off_vstore + (uint64_t)kStoreBlock * S);
+        L.total = al256(L.off_vslots + 4ull * S * (1ull << L.log2_store));
+    }
     return L;
 }
 
@@ -583,7 +677,7 @@ int heap_create_ex(size_t bytes, size_t chunk_bytes, const heap_config_t* cfg, h
     if (bytes < chunk_bytes) return HBHEAP_E_INVAL;
     heap_config_t c = {};
     if (cfg) c = *cfg;
-    if (c.variant > HBHEAP_VARIANT_PAGE) return HBHEAP_E_INVAL;
+    if (c.variant > HBHEAP_VARIANT_VA_PAGE) return HBHEAP_E_INVAL;
     if (!c.width) c.width = 64;
     if (c.width > 64 || (c.width & (c.width - 1))) return HBHEAP_E_INVAL;
     if (!c.spin_cap) c.spin_cap = 1u << 18;
@@ -592,7 +686,7 @@ int heap_create_ex(size_t bytes, size_t chunk_bytes, const heap_config_t* cfg, h
     if (N >= 0x80000000ull) return HBHEAP_E_INVAL;
     const uint32_t log2C = ilog2(chunk_bytes);
     const uint32_t K = log2C - 3;
-    if (c.variant == HBHEAP_VARIANT_PAGE && N * chunk_bytes > (64ull << 30)) return HBHEAP_E_INVAL;
+    if (c.variant != HBHEAP_VARIANT_CHUNK && N * chunk_bytes > (64ull << 30)) return HBHEAP_E_INVAL;
     if (c.shards > kMaxShards || (c.shards & (c.shards - 1))) return HBHEAP_E_INVAL;
     uint32_t S = 1, log2_span = 0;
     shard_geometry(N, c.shards, &S, &log2_span);
@@ -639,6 +733,18 @@ int heap_create_ex(size_t bytes, size_t chunk_bytes, const heap_config_t* cfg, h
     d.flags = c.flags;
     d.n_shards = S;
     d.log2_span = log2_span;
+    if (c.variant == HBHEAP_VARIANT_VA_PAGE) {
+        if (L.vbudget == 0) { release(h); return HBHEAP_E_INVAL; }
+        d.vdir = (uint64_t*)(st + L.off_vdir);
+        d.vtaken = (uint32_t*)(st + L.off_vtaken);
+        d.vstore = st + L.off_vstore;
+        d.vstore_slots = (uint32_t*)(st + L.off_vslots);
+        d.log2_seg = L.log2_seg;
+        d.log2_dir = L.log2_dir;
+        d.log2_store = L.log2_store;
+        d.vsegs = L.vsegs;
+        d.vbudget = L.vbudget;
+    }
     h->trim_counts = (uint32_t*)(ax + 512);
     h->trim_offsets = (uint32_t*)(ax + 512 + tb);
     h->trim_totals = (uint32_t*)(ax + 512 + 2 * tb);
@@ -668,6 +774,15 @@ int heap_create_ex(size_t bytes, size_t chunk_bytes, const heap_config_t* cfg, h
     put64(hb, 88, L.off_pid);
     put64(hb, 96, L.off_sl);
     put64(hb, 104, L.total);
+    put32(hb, 112, L.log2_seg);
+    put32(hb, 116, L.log2_dir);
+    put32(hb, 120, L.log2_store);
+    put32(hb, 124, L.vsegs);
+    put64(hb, 128, L.vbudget);
+    put64(hb, 136, L.off_vdir);
+    put64(hb, 144, L.off_vtaken);
+    put64(hb, 152, L.off_vstore);
+    put64(hb, 160, L.off_vslots);
     for (uint32_t j = 0; j < S; ++j) {
         const uint64_t first = (uint64_t)j << log2_span;
         const uint64_t size = first + (1ull << log2_span) <= N ? (1ull << log2_span) : N - first;
@@ -687,6 +802,7 @@ int heap_create_ex(size_t bytes, size_t chunk_bytes, const heap_config_t* cfg, h
         if (hipGetLastError() != hipSuccess) rc = HBHEAP_E_HIP;
     }
     if (rc == HBHEAP_OK && hipMemcpyAsync(st, hb, head_bytes, hipMemcpyHostToDevice, s) != hipSuccess) rc = HBHEAP_E_HIP;
+    if (rc == HBHEAP_OK && c.variant == HBHEAP_VARIANT_VA_PAGE) rc = va_rebuild(d, nullptr, nullptr, s);
     if (rc == HBHEAP_OK && hipStreamSynchronize(s) != hipSuccess) rc = HBHEAP_E_HIP;
     free(hb);
     if (rc != HBHEAP_OK) { release(h); return rc; }
@@ -761,7 +877,7 @@ int heap_info(heap_t h, heap_info_t* out)
     out->n_chunks = h->dev.n_chunks;
     out->n_classes = h->dev.n_classes;
     out->variant = h->dev.variant;
-    out->ring_entries = 1ull << h->lay.log2q;
+    out->ring_entries = h->dev.variant == HBHEAP_VARIANT_VA_PAGE ? h->lay.vbudget : 1ull << h->lay.log2q;
     out->n_shards = h->dev.n_shards;
     out->state_bytes = h->lay.total;
     out->metadata_bytes = h->lay.total + h->aux_bytes;
@@ -784,10 +900,11 @@ int heap_trim(heap_t h, hipStream_t stream)
     rc = fill_u32(d.slots, ((uint64_t)d.n_shards * d.n_classes) << d.log2q, kEmpty, stream);
     if (!rc) rc = fill_u32(d.pool_ids, d.n_chunks, kEmpty, stream);
     if (rc) return rc;
-    hipLaunchKernelGGL(k_trim_write, dim3(nb), dim3(kTrimBlock), 0, stream, d, h->trim_offsets, nb);
+    hipLaunchKernelGGL(k_trim_write, dim3(nb), dim3(kTrimBlock), 0, stream, d, h->trim_offsets, nb, h->trim_totals);
     HB_TRY(hipGetLastError());
     hipLaunchKernelGGL(k_trim_ctl, dim3(1), dim3(1024), 0, stream, d, h->trim_totals, h->trim_owned);
     HB_TRY(hipGetLastError());
+    if (d.variant == HBHEAP_VARIANT_VA_PAGE) return va_rebuild(d, h->trim_totals, h->trim_owned, stream);
     return HBHEAP_OK;
 }
 

@@ -14,7 +14,7 @@ import os
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libhbheap.so")
 
-VARIANT_CHUNK, VARIANT_PAGE = 0, 1
+VARIANT_CHUNK, VARIANT_PAGE, VARIANT_VA_PAGE = 0, 1, 2
 OK, E_INVAL, E_NOMEM, E_HIP, E_RANGE, E_UNSUP = 0, -1, -2, -3, -4, -5
 ERR_DOUBLE_FREE, ERR_INVALID_FREE, ERR_TIMEOUT, ERR_CORRUPT = 0x1, 0x2, 0x4, 0x8
 FLAG_STATS, FLAG_VERIFY, FLAG_HOME0 = 0x1, 0x2, 0x4
@@ -77,7 +77,10 @@ class DevHandle(C.Structure):
                [("data_bytes", C.c_uint64)] + \
                [(n, C.c_uint32) for n in ("n_chunks", "log2_chunk", "n_classes", "variant", "words_per_chunk",
                                           "log2q", "width", "spin_cap", "backoff_max", "flags", "n_shards",
-                                          "log2_span")]
+                                          "log2_span")] + \
+               [(n, C.c_void_p) for n in ("vdir", "vtaken", "vstore", "vstore_slots")] + \
+               [(n, C.c_uint32) for n in ("log2_seg", "log2_dir", "log2_store", "vsegs")] + \
+               [("vbudget", C.c_uint64)]
 
 
 _lib = None

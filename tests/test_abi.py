@@ -54,7 +54,7 @@ def test_create_rejects_bad_geometry(L, nbytes, chunk):
 
 def test_create_rejects_bad_config(L):
     out = C.c_void_p(0)
-    for cfg in [hb.HeapConfig(2, 64, 0, 0, 0), hb.HeapConfig(0, 48, 0, 0, 0), hb.HeapConfig(0, 128, 0, 0, 0)]:
+    for cfg in [hb.HeapConfig(3, 64, 0, 0, 0), hb.HeapConfig(0, 48, 0, 0, 0), hb.HeapConfig(0, 128, 0, 0, 0)]:
         assert L.heap_create_ex(1 << 20, 8192, C.byref(cfg), C.byref(out)) == hb.E_INVAL
     # page variant data region above 64 GiB
     assert L.heap_create_ex(65 << 30, 8192, C.byref(hb.HeapConfig(1, 64, 0, 0, 0)), C.byref(out)) == hb.E_INVAL
@@ -75,8 +75,8 @@ def test_null_handle_and_buffers_rejected(L):
 
 
 def test_dev_handle_layout_matches_header():
-    # 11 pointers, one u64, twelve u32
-    assert C.sizeof(hb.DevHandle) == 11 * 8 + 8 + 12 * 4
+    # 11 pointers, one u64, twelve u32; virtualised array: 4 pointers, four u32, one u64
+    assert C.sizeof(hb.DevHandle) == 11 * 8 + 8 + 12 * 4 + 4 * 8 + 4 * 4 + 8
 
 
 def test_growth_rejects_bad_arguments(L):

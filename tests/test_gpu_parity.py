@@ -21,7 +21,7 @@ from tests.hbtest import (check_blocks, check_snapshot, dev_i64, dev_u64, live_o
 pytestmark = pytest.mark.gpu
 
 KiB, MiB, GiB = 1 << 10, 1 << 20, 1 << 30
-VARIANTS = [0, 1]
+VARIANTS = [0, 1, 2]
 
 
 @pytest.fixture(scope="module")
@@ -42,7 +42,12 @@ def _oracle_cap(nbytes, C, variant, k, shards):
     tot = 0
     for j in range(S):
         nj = min(N, (j + 1) << L) - (j << L)
-        cj = nj if variant == 0 else min(nj, O.page_max_chunks(nbytes, C, k, S))
+        if variant == 0:
+            cj = nj
+        elif variant == 1:
+            cj = min(nj, O.page_max_chunks(nbytes, C, k, S))
+        else:
+            cj = min(nj, O.va_budget(nbytes, C, S) // O.pages_per_chunk(C, k))
         tot += cj * O.pages_per_chunk(C, k)
     return tot
 
@@ -146,7 +151,7 @@ def test_sweep_small_exact_capacity(hb, variant, shards):
                 assert live_of(srep)[k] == min(n, cap)
                 if n >= cap:
                     assert srep.free_pages[k] == 0
-                    assert srep.free_chunks == 0 or variant == 1
+                    assert srep.free_chunks == 0 or variant != 0
                 assert O.check_blocks_in_snapshot(snap, sizes, offs) == 0
                 heap.free(ptrs)
                 _, srep = check_snapshot(heap)
@@ -161,7 +166,7 @@ def test_sweep_small_exact_capacity(hb, variant, shards):
 # wave ends up taking from other shards and exactly the capacity succeeds
 # ---------------------------------------------------------------------------
 
-@pytest.mark.parametrize("variant", VARIANTS)
+@pytest.mark.parametrize("variant", [0, 1])  # one-chunk shards leave a virtualised array no page budget
 def test_steal_exact_capacity(hb, variant):
     nbytes, C, n = 64 * 8 * KiB, 8 * KiB, 1 << 14
     with hb.Heap(nbytes, C, variant=variant, shards=64) as heap:
@@ -194,7 +199,8 @@ def test_steal_exact_capacity(hb, variant):
 # freed and reallocated per round
 # ---------------------------------------------------------------------------
 
-@pytest.mark.parametrize("variant,shards,flags", [(0, 1, 0), (0, 0, 0), (1, 1, 0), (1, 0, 0), (1, 0, 2)])
+@pytest.mark.parametrize("variant,shards,flags", [(0, 1, 0), (0, 0, 0), (1, 1, 0), (1, 0, 0), (1, 0, 2), (2, 1, 0),
+                                                  (2, 0, 0), (2, 0, 2)])
 def test_churn_small(hb, variant, shards, flags):
     """flags 2: the page variant verifies every page it takes from a queue."""
     import torch
@@ -436,6 +442,38 @@ def test_paper_sweeps(hb, variant):
                     _, srep = check_snapshot(heap)
                     assert live_of(srep) == ref.accounting()["live"]
                 heap.free(ptrs)
+            heap.trim()
+            assert heap.snapshot() == fresh
+        assert heap.error() == 0
+
+
+# ---------------------------------------------------------------------------
+# virtualised array page variant: the page budget of a shard matches the
+# oracle's closed form, and one class can use all of it (more than the page
+# variant's per-class queue allows)
+# ---------------------------------------------------------------------------
+
+def test_va_budget_and_shared_capacity(hb):
+    nbytes, C = 2 * MiB, 8 * KiB
+    with hb.Heap(nbytes, C, variant=hb.VARIANT_VA_PAGE, shards=1) as heap:
+        assert heap.info.ring_entries == O.va_budget(nbytes, C, 1)
+        fresh = heap.snapshot()
+        n = 1 << 17
+        for size in (16, 4096):
+            say(f"case va-capacity size={size}")
+            sizes = inputs.sizes_fixed(n, size)
+            sd, ptrs = dev_u64(sizes), zeros_i64(n)
+            heap.alloc(sd, ptrs)
+            cap = _oracle_cap(nbytes, C, 2, O.class_of(size, C), 1)
+            rep = check_blocks(heap, sizes, offsets(ptrs, heap.base), allow_null=True)
+            assert rep.n_nonnull == min(n, cap)
+            if size == 16:
+                assert cap > _oracle_cap(nbytes, C, 1, 0, 1)
+            heap.pattern_write(ptrs, sd, 3)
+            assert heap.pattern_check(ptrs, sd, 3) == 0
+            check_snapshot(heap)
+            heap.free(ptrs)
+            check_snapshot(heap)
             heap.trim()
             assert heap.snapshot() == fresh
         assert heap.error() == 0

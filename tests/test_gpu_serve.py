@@ -175,6 +175,13 @@ def test_serve_page_class_capacity_is_not_admitted(hb):
         assert heap.error() == 0
 
 
+def test_serve_refuses_virtualised_array_heap(hb):
+    with hb.Heap(8 * MiB, 8 * KiB, variant=hb.VARIANT_VA_PAGE) as heap:
+        with pytest.raises(hb.HbHeapError) as e:
+            hb.serve_create(heap.h, 2, 64, 1000, 0.95, 1, 1)
+        assert e.value.code == hb.E_INVAL
+
+
 def test_serve_rejects_bad_plans(hb):
     with hb.Heap(8 * MiB, 8 * KiB) as heap:
         s = hb.serve_create(heap.h, 2, 64, 1000, 0.95, 1, 2)

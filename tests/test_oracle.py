@@ -302,10 +302,13 @@ def test_check_blocks_catches_planted_faults():
 # ---------------------------------------------------------------------------
 
 def build_snapshot(N, log2C, variant, log2q, cls, cnt, bits, pool_bumps, pool_ids, rings, owned=None, S=1,
-                   log2_span=None):
-    """Write a version-2 snapshot from plain arrays.  rings[(j, k)] or
+                   log2_span=None, va=None):
+    """Write a version-3 snapshot from plain arrays.  rings[(j, k)] or
     rings[k] (shard 0) = (H, head, entries); pool_bumps: one per shard;
-    pool_ids: the whole id array."""
+    pool_ids: the whole id array.  Virtualised array (variant 2): va =
+    dict(g, ldir, lstore, M, budget, committed per shard); each queue's
+    segments are numbered from the shard's first, queue after queue, the
+    store holds the rest in ascending order."""
     K = log2C - 3
     W = (1 << log2C) // 1024
     Q = 1 << log2q
@@ -324,9 +327,18 @@ def build_snapshot(N, log2C, variant, log2q, cls, cnt, bits, pool_bumps, pool_id
     off_pid = al(off_bits + 8 * N * W)
     off_sl = al(off_pid + 4 * N)
     total = al(off_sl + 4 * S * K * Q)
+    if va:
+        g, ldir, lstore, M = va["g"], va["ldir"], va["lstore"], va["M"]
+        off_vdir = total
+        off_vtk = al(off_vdir + 8 * S * K * (1 << ldir))
+        off_vst = al(off_vtk + 4 * S * M)
+        off_vss = al(off_vst + 512 * S)
+        total = al(off_vss + 4 * S * (1 << lstore))
     b = bytearray(total)
-    struct.pack_into("<IIQIIIIIIIIQQQQQQQQ", b, 0, 0x48424850, 2, N << log2C, N, log2C, K, variant, W, log2q,
+    struct.pack_into("<IIQIIIIIIIIQQQQQQQQ", b, 0, 0x48424850, 3, N << log2C, N, log2C, K, variant, W, log2q,
                      S, log2_span, off_pool, off_cl, off_cls, off_cnt, off_bits, off_pid, off_sl, total)
+    if va:
+        struct.pack_into("<IIIIQQQQQ", b, 112, g, ldir, lstore, M, va["budget"], off_vdir, off_vtk, off_vst, off_vss)
     for j in range(S):
         first = j << log2_span
         size = min(N, (j + 1) << log2_span) - first
@@ -348,10 +360,41 @@ def build_snapshot(N, log2C, variant, log2q, cls, cnt, bits, pool_bumps, pool_id
             struct.pack_into("<I", b, off_cl + 512 * r + 128, head & 0xFFFFFFFF)
             struct.pack_into("<I", b, off_cl + 512 * r + 256, (head + len(ents)) & 0xFFFFFFFF)
             struct.pack_into("<Q", b, off_cl + 512 * r + 384, owned.get((j, k), 0))
+            if va:
+                continue
             for q in range(Q):
                 struct.pack_into("<I", b, off_sl + 4 * (r * Q + q), 0xFFFFFFFF)
             for q, e in enumerate(ents):
                 struct.pack_into("<I", b, off_sl + 4 * (r * Q + ((head + q) % Q)), e)
+    if va:
+        G, D, QS = 1 << g, 1 << ldir, 1 << lstore
+        for i in range(S * M * G):
+            struct.pack_into("<I", b, off_sl + 4 * i, 0xFFFFFFFF)
+        for i in range(S * K * D):
+            struct.pack_into("<Q", b, off_vdir + 8 * i, (1 << 64) - 1)
+        for j in range(S):
+            nxt = 0
+            for k in range(K):
+                r = j * K + k
+                H, head, ents = rings.get((j, k), (0, 0, []))
+                tail = head + len(ents)
+                sg = head >> g
+                while (sg << g) < tail:
+                    m = nxt
+                    nxt += 1
+                    struct.pack_into("<Q", b, off_vdir + 8 * ((r << ldir) + (sg & (D - 1))), ((sg & 0xFFFFFFFF) << 32) | m)
+                    s0 = sg << g
+                    struct.pack_into("<I", b, off_vtk + 4 * (j * M + m), max(0, min(head, s0 + G) - s0))
+                    for p in range(max(s0, head), min(s0 + G, tail)):
+                        struct.pack_into("<I", b, off_sl + 4 * (((j * M + m) << g) + (p - s0)), ents[p - head])
+                    sg += 1
+            free_ids = list(range(nxt, M))
+            struct.pack_into("<QII", b, off_vst + 512 * j, len(free_ids) + 0x80000000, 0, 0)
+            struct.pack_into("<I", b, off_vst + 512 * j + 128, 0)
+            struct.pack_into("<I", b, off_vst + 512 * j + 256, len(free_ids))
+            struct.pack_into("<Q", b, off_vst + 512 * j + 384, va["committed"][j])
+            for i in range(QS):
+                struct.pack_into("<I", b, off_vss + 4 * ((j << lstore) + i), free_ids[i] if i < len(free_ids) else 0xFFFFFFFF)
     return bytes(b)
 
 
@@ -514,3 +557,99 @@ def test_pattern_sum_against_bytes():
 def test_classes_batch_matches_scalar():
     sizes = np.array([0, 1, 15, 16, 17, 32, 33, 4096, 4097, 8192, 8193, 1 << 40], dtype=np.uint64)
     assert O.classes(sizes, 8192).tolist() == [O.class_of(int(s), 8192) for s in sizes]
+
+
+
+# ---------------------------------------------------------------------------
+# virtualised array page variant: budget closed form, capacity, snapshots
+# ---------------------------------------------------------------------------
+
+def test_va_budget_closed_form():
+    """Segments of 2^g entries, g = log2(Q) - 3 within [4, 10]; M = K*Q/2^g
+    per shard; the shard's classes may own (M - 3K) * 2^g pages."""
+    for nbytes, C, S in [(4 << 30, 8192, 64), (8 << 20, 8192, 2), (64 << 20, 16384, 4), (1 << 20, 4096, 1)]:
+        K = O.num_classes(C)
+        Q = O.page_ring_entries(nbytes, C, S)
+        g = min(10, max(4, Q.bit_length() - 1 - 3))
+        M = (K * Q) >> g
+        assert O.va_log2_seg(nbytes, C, S) == g
+        assert O.va_segments(nbytes, C, S) == M
+        assert O.va_budget(nbytes, C, S) == (max(0, M - 3 * K) << g)
+
+
+def test_va_capacity_is_shared_by_the_classes_of_a_shard():
+    """One class alone can use the whole shard budget (the page variant caps
+    each class at Q entries); with two classes the budget is shared."""
+    nbytes, C = 2 << 20, 8192          # 256 chunks, one shard
+    budget = O.va_budget(nbytes, C, 1)
+    Q = O.page_ring_entries(nbytes, C, 1)
+    va = O.OracleHeap(nbytes, C, O.VARIANT_VA_PAGE)
+    pg = O.OracleHeap(nbytes, C, O.VARIANT_PAGE)
+    n16 = 0
+    while va.alloc(16) >= 0:
+        n16 += 1
+    m16 = 0
+    while pg.alloc(16) >= 0:
+        m16 += 1
+    ppc = 512
+    assert n16 == min(256, budget // ppc) * ppc
+    assert m16 == min(256, Q // ppc) * ppc
+    assert n16 > m16
+    # the budget is in pages: a second class gets what the first left
+    nbig = 0
+    while va.alloc(4096) >= 0:
+        nbig += 1
+    used = (n16 // ppc) * ppc
+    assert nbig == min(256 - n16 // ppc, (budget - used) // 2) * 2
+
+
+def _va_state(tamper=None):
+    # one shard, 4 chunks of 4 KiB (K = 9, W = 4): chunk 0 class 6 (1 KiB, 4
+    # pages) with pages 1 and 3 free, chunk 2 class 0 with page 5 free;
+    # segments of 16 entries, 64 segments, directory 128, store 64
+    N, log2C, K = 4, 12, 9
+    cls = [6, 0xFF, 0, 0xFF]
+    cnt = [2, 0, 1, 0]
+    bits = [[0] * 4 for _ in range(N)]
+    bits[0][0] = (1 << 1) | (1 << 3)
+    bits[2][0] = 1 << 5
+    off = lambda c, k, p: ((c << log2C) + p * (16 << k)) >> 4
+    rings = {6: (0, 30, [off(0, 6, 1), off(0, 6, 3)]), 0: (0, 16, [off(2, 0, 5)])}
+    owned = {6: 1, 0: 1}
+    committed = [4 + 256]
+    va = dict(g=4, ldir=7, lstore=6, M=64, budget=(64 - 27) << 4, committed=committed)
+    if tamper:
+        tamper(rings, owned, va)
+    return build_snapshot(N, log2C, 2, 7, cls, cnt, bits, [2], [0, 2, 1, 3], rings, owned=owned, va=va)
+
+
+def test_va_snapshot_clean_and_planted_faults():
+    rep = O.check_snapshot(_va_state())
+    assert rep.ok_header and not rep.violations(), rep.violations()
+    b = bytearray(_va_state())
+    off_vdir, off_vtk, off_vst, off_vss = struct.unpack_from("<QQQQ", b, 136)
+    off_sl = struct.unpack_from("<Q", b, 96)[0]
+    # a directory entry naming the wrong segment number
+    x = bytearray(b)
+    ring6 = 6 << 7
+    e = struct.unpack_from("<Q", x, off_vdir + 8 * (ring6 + (30 >> 4)))[0]
+    struct.pack_into("<Q", x, off_vdir + 8 * (ring6 + (30 >> 4)), e + (1 << 32))
+    assert O.check_snapshot(bytes(x)).bad_vdir > 0
+    # a consumed count off by one
+    x = bytearray(b)
+    v = struct.unpack_from("<I", x, off_vtk)[0]
+    struct.pack_into("<I", x, off_vtk, v + 1)
+    assert O.check_snapshot(bytes(x)).bad_vtaken > 0
+    # the store loses a free segment id
+    x = bytearray(b)
+    n = struct.unpack_from("<I", x, off_vst + 256)[0]
+    struct.pack_into("<I", x, off_vst + 256, n - 1)
+    struct.pack_into("<Q", x, off_vst, (n - 1) + 0x80000000)
+    struct.pack_into("<I", x, off_vss + 4 * (n - 1), 0xFFFFFFFF)
+    assert O.check_snapshot(bytes(x)).bad_vstore > 0
+    # a stray value in a slot no position holds
+    x = bytearray(b)
+    struct.pack_into("<I", x, off_sl + 4 * (63 * 16 + 3), 7)
+    assert O.check_snapshot(bytes(x)).bad_ring_entry > 0
+    # committed pages that do not match the classes' chunks
+    assert O.check_snapshot(_va_state(lambda r, o, v: v.update(committed=[5]))).bad_committed > 0
