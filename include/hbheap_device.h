@@ -175,6 +175,20 @@ __device__ __forceinline__ uint32_t a_load32(uint32_t* p) { return __hip_atomic_
 __device__ __forceinline__ int32_t a_loadi(int32_t* p) { return __hip_atomic_load(p, HBH_A(__ATOMIC_RELAXED)); }
 #undef HBH_A
 
+/* Zero, computed from v by an instruction the compiler cannot see through.
+ * Added to the address of a later load, it makes that load wait for v: the
+ * later load is issued only once the earlier one has returned its value.
+ * With the device-coherent loads above (serviced where device atomics are
+ * performed, never from a stale private cache) the later load then reads
+ * memory no earlier than the earlier one did -- the order an acquire load
+ * would give, without the cache invalidation an acquire also issues. */
+__device__ __forceinline__ uint32_t zero_after(uint32_t v)
+{
+    uint32_t z;
+    __asm__ volatile("v_and_b32 %0, 0, %1" : "=v"(z) : "v"(v));
+    return z;
+}
+
 __device__ __forceinline__ void fence_release() { __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent"); }
 __device__ __forceinline__ void wave_sync_lds()
 {
@@ -473,10 +487,14 @@ __device__ __forceinline__ uint32_t slot_take(const hbheap_dev_t& h, const Ring&
 
 /* Virtualised array rings, wave-wide: the lanes with `took` consumed ring
  * position pos of segment seg of ring r.  Runs of adjacent lanes on one
- * segment add their number to its consumed count with one atomic; the run
- * completing the segment empties its directory entry and returns it to the
- * store (every slot of it was emptied by its consumer before that consumer
- * was counted). */
+ * segment (their positions rise with the lane) add their number to its
+ * consumed count with one atomic.  The run holding the segment's last
+ * position closes it: once the count shows every slot consumed, it empties
+ * the directory entry and returns the segment to the store (each slot was
+ * emptied by its consumer before that consumer was counted).  The closer's
+ * wait is bounded by the other consumers of the segment, which reserved
+ * their positions before it and wait on nothing it holds; so only the
+ * closer needs the count back, and every other add returns nothing. */
 __device__ __forceinline__ void va_count_taken(const hbheap_dev_t& h, const Ring& r, bool took, uint32_t pos,
                                                uint32_t seg, Tally& t)
 {
@@ -484,16 +502,27 @@ __device__ __forceinline__ void va_count_taken(const hbheap_dev_t& h, const Ring
     const Run run = run_combine(took, (uint64_t)r.j * h.vsegs + seg, 1ull << me, 64u);
     if (took && me == run.tail) {
         const uint32_t n = (uint32_t)__popcll(run.incl);
+        const uint32_t G = 1u << r.log2g;
         uint32_t* tk = h.vtaken + (uint64_t)r.j * h.vsegs + seg;
-        const uint32_t c = a_add32(tk, n) + n;
         t.spread += 1;
-        if (c == (1u << r.log2g)) {
-            __hip_atomic_store(tk, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_store(r.dir + ((pos >> r.log2g) & r.dmask), kDirEmpty, __ATOMIC_RELAXED,
-                               __HIP_MEMORY_SCOPE_AGENT);
-            fence_release();
-            store_put(h, r.j, seg, t);
+        if ((pos & (G - 1u)) != G - 1u) {
+            __hip_atomic_fetch_add(tk, n, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            return;
         }
+        uint32_t c = a_add32(tk, n) + n;
+        Backoff b;
+        while (c != G) {
+            if (!b.wait(h)) {
+                raise_err(h, HBHEAP_ERR_TIMEOUT, HBHEAP_STAT_TIMEOUTS);
+                return;
+            }
+            c = a_load32(tk);
+        }
+        __hip_atomic_store(tk, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(r.dir + ((pos >> r.log2g) & r.dmask), kDirEmpty, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+        fence_release();
+        store_put(h, r.j, seg, t);
     }
 }
 
@@ -736,12 +765,13 @@ __device__ __forceinline__ bool shard_has_something(const hbheap_dev_t& h, uint3
 
 /* One look at every shard's queue for the group's class, spread over the
  * active lanes (rank r looks at shards home+r, home+r+nact, ...).  Per
- * shard the pool (and the page-variant owned counter) is read before the
- * state word: a pool once empty stays empty until the next trim, so "pool
- * empty, then no hold and no entry" means the shard had nothing at the
- * moment its state was read.  Returns the rotated rank (from home) of the
- * first shard with published entries or room to grow, or S; *busy tells
- * whether any shard had a hold in flight. */
+ * shard the pool is read before the state word, head and tail: a pool once
+ * empty stays empty until the next trim, so "pool empty, then no hold, no
+ * entry and head = tail" means the shard had nothing for the class at the
+ * moment head was read (no refill in flight, every published entry taken).
+ * Returns the rotated rank (from home) of the first shard with published
+ * entries or room to grow, or S; *busy tells whether any shard had a hold
+ * or a head/tail gap in flight. */
 __device__ __forceinline__ uint32_t scan_shards(const hbheap_dev_t& h, const Group& g, uint32_t home, bool* busy)
 {
     const uint32_t S = h.n_shards;
@@ -751,10 +781,23 @@ __device__ __forceinline__ uint32_t scan_shards(const hbheap_dev_t& h, const Gro
         bool avail = false, hold = false;
         if (r < S) {
             const uint32_t j = home + r < S ? home + r : home + r - S;
-            bool grow = !pool_empty(h, j);
+            /* read in this order (each load's address depends on the value
+             * before it): pool, state word, head, tail.  Head before tail:
+             * both only grow, so an equal pair means that no published entry
+             * was left untaken when head was read; a gap is an operation in
+             * flight (a free publishing, or a taker that over-asked without
+             * a hold and has not yet given the excess back, while the count
+             * can hide entries published meanwhile).  The room counter may
+             * be read in any order: it only shrinks when the pool runs dry. */
+            uint64_t* pb = pool_block(h, j);
+            const uint64_t bump = a_load64(pb);
+            bool grow = bump < ((const uint32_t*)pb)[2];
             if (grow) grow = class_has_room(h, j, g.k, g.lppc);
-            const uint64_t st = a_load64(ring_of(h, j, g.k).state);
-            hold = (st >> 32) != 0;
+            const Ring R = ring_of(h, j, g.k);
+            const uint64_t st = a_load64(R.state + zero_after((uint32_t)bump));
+            const uint32_t hd = a_load32(R.head + zero_after((uint32_t)st));
+            const uint32_t tl_ = a_load32(R.tail + zero_after(hd));
+            hold = (st >> 32) != 0 || hd != tl_;
             avail = state_count(st) > 0 || grow;
         }
         const uint64_t av = __ballot(avail);
@@ -932,21 +975,21 @@ __device__ __forceinline__ void page_serve_shard(const hbheap_dev_t& h, const Gr
                                                  Tally& tl)
 {
     const Ring R = ring_of(h, j, g.k);
-    /* The first pass reserves without looking first (unless check_first).
-     * On a shard the caller saw with a dry pool (dry stays dry until a trim)
-     * that pass cannot refill, so it publishes nothing and needs no hold: it
-     * only takes published entries, which keeps waves that scan for
-     * out-of-memory from waiting on it.  Later passes look first and hold
-     * the queue. */
-    bool first_pass = !check_first;
+    /* The first pass (which looks first only if check_first) takes published
+     * entries without a hold: it never refills, so it has nothing to publish
+     * and a scanning wave need not wait on it (an over-ask it gives back is
+     * covered by the scan's head/tail test instead).  Short of pages, the
+     * next passes look first and hold the queue, so they may refill -- except
+     * on a shard the caller saw with a dry pool (dry stays dry until a trim):
+     * there the caller scans instead. */
+    bool look = check_first, held = false;
     while (need > 0) {
-        const bool held = !(first_pass && dry);
-        if (!first_pass) {
+        if (look) {
             uint32_t some = 0;
             if (g.me == g.leader) some = shard_has_something(h, j, g.k, g.lppc);
             if (!bcast(some, g.leader)) return;
         }
-        first_pass = false;
+        look = true;
         uint32_t got = 0, h0 = 0;
         if (g.me == g.leader) {
             got = held ? ring_reserve(R, need, tl) : ring_take_published(R, need, tl);
@@ -984,7 +1027,7 @@ __device__ __forceinline__ void page_serve_shard(const hbheap_dev_t& h, const Gr
         served += got;
 
         uint32_t publish = 0;
-        bool exhausted = !held;
+        bool exhausted = !held && dry;
         if (need > 0 && held) {
             const uint32_t m = (need + g.ppc - 1u) >> g.lppc;
             uint64_t first = 0;
@@ -1039,6 +1082,7 @@ __device__ __forceinline__ void page_serve_shard(const hbheap_dev_t& h, const Gr
         }
         if (held && g.me == g.leader) ring_release(R, publish, tl);
         if (need > 0 && exhausted) return;
+        held = true;
     }
 }
 
@@ -1158,7 +1202,7 @@ __device__ __forceinline__ void* malloc_wave(const hbheap_dev_t& h, uint64_t n, 
         uint32_t got = 0, h0 = 0;
         if (k >= 0) R = ring_of(h, home, (uint32_t)k);
         if (lead) {
-            got = home_dry ? ring_take_published(R, gn, tl) : ring_reserve(R, gn, tl);
+            got = ring_take_published(R, gn, tl);
             if (got) {
                 h0 = a_add32(R.head, got);
                 tl.headtail += 1;
@@ -1186,7 +1230,6 @@ __device__ __forceinline__ void* malloc_wave(const hbheap_dev_t& h, uint64_t n, 
         }
         if (h.variant == HBHEAP_VARIANT_VA_PAGE) va_count_taken(h, R, took_slot, h0 + gr, vseg, tl);
         clear_bits_grouped(h, took, widx, bit, o, off, tl);
-        if (lead && !home_dry) ring_release(R, 0, tl);
     }
     pend = __ballot(k >= 0 && gr >= done);
     while (pend) {

@@ -154,7 +154,7 @@ class ModelParams(C.Structure):
         ("variant", C.c_int32), ("n_chunks", C.c_int32), ("ppc", C.c_int32), ("maxc", C.c_int32),
         ("n_leaders", C.c_int32), ("n_ops", C.c_int32 * 3), ("ops", (ModelOp * 3) * 3),
         ("prefill", C.c_int32), ("freeze", C.c_int32), ("mutation", C.c_int32), ("dry_hint", C.c_int32),
-        ("fast_first", C.c_int32), ("pad_", C.c_int32), ("max_states", C.c_int64),
+        ("fast_first", C.c_int32), ("first_nohold", C.c_int32), ("max_states", C.c_int64),
     ]
 
 
@@ -173,12 +173,13 @@ class ModelResult(C.Structure):
 
 OP_ALLOC, OP_FREE_OWN, OP_FREE_GIVEN = 1, 2, 3
 MUTATIONS = {"no_hold": 1, "requeue_always": 2, "free_enqueue_always": 3, "no_refund": 4,
-             "release_no_publish": 5, "publish_early": 6, "dry_always": 7}
+             "release_no_publish": 5, "publish_early": 6, "dry_always": 7,
+             "scan_no_positions": 8}
 
 
 def model_run(variant: int, n_chunks: int, ppc: int, leaders: list, prefill: int = 0, maxc: int | None = None,
               freeze: bool = False, mutation: int = 0, max_states: int = 2_000_000, dry_hint: bool = True,
-              fast_first: bool = False) -> dict:
+              fast_first: bool = False, first_nohold: bool = True) -> dict:
     """Explore every interleaving of `leaders` (each a list of (kind, a, b)
     ops) on a heap of n_chunks chunks of ppc pages.  Returns the counters."""
     p = ModelParams()
@@ -193,6 +194,7 @@ def model_run(variant: int, n_chunks: int, ppc: int, leaders: list, prefill: int
     p.prefill, p.freeze, p.mutation, p.max_states = prefill, int(freeze), mutation, max_states
     p.dry_hint = int(dry_hint)
     p.fast_first = int(fast_first)
+    p.first_nohold = int(first_nohold)
     r = ModelResult()
     rc = lib().orc_model_run(C.byref(p), C.byref(r))
     if rc != 0:

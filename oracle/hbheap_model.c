@@ -57,7 +57,8 @@ enum { OP_NONE = ORC_OP_NONE, OP_ALLOC = ORC_OP_ALLOC, OP_FREE_OWN = ORC_OP_FREE
 enum {
     MUT_NONE = 0, MUT_NO_HOLD = 1, MUT_REQUEUE_ALWAYS = 2, MUT_FREE_ENQ_ALWAYS = 3,
     MUT_NO_REFUND = 4, MUT_RELEASE_NO_PUB = 5, MUT_PUBLISH_EARLY = 6,
-    MUT_DRY_ALWAYS = 7 /* page alloc: first pass without a hold even when it refills */
+    MUT_DRY_ALWAYS = 7, /* page alloc: first pass without a hold even when it refills */
+    MUT_SCAN_NO_POS = 8 /* the out-of-memory look ignores a gap between head and tail */
 };
 
 /* ---------------- state ---------------- */
@@ -163,6 +164,23 @@ static int held_by_free(const ctx* x, const mstate* s, uint8_t v)
     return 0;
 }
 
+/* Page variant: page v belongs to an allocation already -- it sits in a
+ * slot whose position the allocation reserved (head moved past it), or the
+ * allocation took it out of its slot and has not yet cleared its bit. */
+static int held_by_alloc(const ctx* x, const mstate* s, uint8_t v)
+{
+    for (int l = 0; l < x->p->n_leaders; ++l) {
+        const leader_t* L = &s->L[l];
+        if (L->pc < 20 || L->pc >= 40) continue;
+        for (int i = 0; i < M_MAXG; ++i)
+            if (L->tok[i] && L->c[i] == v) return 1;
+        if (L->pc == 24)
+            for (int q = L->i; q < L->got; ++q)
+                if (s->slot[(uint8_t)(L->h0 + q) % x->Q] == v) return 1;
+    }
+    return 0;
+}
+
 static void check_tokens(ctx* x, const mstate* s)
 {
     int N = x->N, P = x->P;
@@ -213,6 +231,19 @@ static void check_tokens(ctx* x, const mstate* s)
  * but not yet published.  Entries are interchangeable, so such a request can
  * be ordered before those frees take effect; in runs without concurrent
  * frees this is exactly "nothing of the class is left". */
+/* What the out-of-memory look waits for: a hold (an operation that may
+ * still publish), or a gap between head and tail.  The gap covers takers
+ * that over-asked without a hold and have not yet given the excess back:
+ * while they have not, the count can read zero although a free published
+ * entries meanwhile; those entries still lie between head and tail.  (Head
+ * is read before tail: both only grow, so an equal pair means no published
+ * entry was left untaken at the moment head was read.) */
+static int in_flight(const ctx* x, const mstate* s)
+{
+    if (s->H != 0) return 1;
+    return x->p->mutation != MUT_SCAN_NO_POS && s->head != s->tail;
+}
+
 static void check_oom(ctx* x, const mstate* s)
 {
     int N = x->N, P = x->P;
@@ -230,7 +261,9 @@ static void check_oom(ctx* x, const mstate* s)
             if (s->cnt[c] > 0 && !held_by_free(x, s, (uint8_t)c)) visible++;
         } else {
             for (int pg = 0; pg < P; ++pg)
-                if (((s->bits[c] >> pg) & 1) && !held_by_free(x, s, (uint8_t)(c * P + pg))) visible++;
+                if (((s->bits[c] >> pg) & 1) && !held_by_free(x, s, (uint8_t)(c * P + pg)) &&
+                    !held_by_alloc(x, s, (uint8_t)(c * P + pg)))
+                    visible++;
         }
     }
     if (visible > pending) violation(x, x->p->variant == 0 ? 61 : 62, &x->r->oom_violations);
@@ -542,10 +575,10 @@ static int step(ctx* x, mstate* s, int l)
         finish_op(x, s, l);
         return 1;
     case 16: {
-        /* wait until no hold is in flight or entries were published */
-        if (s->cnt_pub > 0) { L->pc = 1; return 1; }
-        if (s->H != 0) return 0;
-        if (s->bump < N) { L->pc = 1; return 1; }
+        /* look again: entries or room -> another pass; otherwise wait while
+         * anything is in flight, then give up */
+        if (s->cnt_pub > 0 || s->bump < N) { L->pc = 1; return 1; }
+        if (in_flight(x, s)) return 0;
         check_oom(x, s);
         L->failed[L->op] = L->need;
         finish_op(x, s, l);
@@ -557,7 +590,7 @@ static int step(ctx* x, mstate* s, int l)
          * request size): a dry pool lets the first pass take published
          * entries without holding the queue, since it cannot refill */
         L->pass = 0;
-        L->dry = (uint8_t)((x->p->dry_hint && s->bump >= N) || mut == MUT_DRY_ALWAYS);
+        L->dry = (uint8_t)((x->p->dry_hint && s->bump >= N) || x->p->first_nohold || mut == MUT_DRY_ALWAYS);
         if (L->dry && x->r->dry_starts < 0xFFFFFFFFu) x->r->dry_starts++;
         L->held = (uint8_t)!L->dry;
         L->pc = 21;
@@ -698,9 +731,8 @@ static int step(ctx* x, mstate* s, int l)
         finish_op(x, s, l);
         return 1;
     case 33: {
-        if (s->cnt_pub > 0) { L->pc = 21; return 1; }
-        if (s->H != 0) return 0;
-        if (s->bump < N && s->owned < x->p->maxc) { L->pc = 21; return 1; }
+        if (s->cnt_pub > 0 || (s->bump < N && s->owned < x->p->maxc)) { L->pc = 21; return 1; }
+        if (in_flight(x, s)) return 0;
         check_oom(x, s);
         L->failed[L->op] = L->need;
         finish_op(x, s, l);

@@ -156,7 +156,8 @@ typedef struct {
     int32_t dry_hint;          /* page alloc reads the pool first and skips
                                   the hold on a dry pool                  */
     int32_t fast_first;        /* page alloc: the first pass never refills */
-    int32_t pad_;
+    int32_t first_nohold;      /* page alloc: every first pass takes without
+                                  a hold and never refills                */
     int64_t max_states;
 } orc_model_params;
 

@@ -2,7 +2,8 @@
 
 The step-level model (oracle/hbheap_model.c) restates the queue protocol of
 the device allocator one atomic step at a time and explores every schedule
-of two or three wave leaders.  It must find no violation of the token,
+of two or three wave leaders (page variant: every first pass takes without
+a hold, as the device does).  It must find no violation of the token,
 exact-out-of-memory and final-state checks and no deadlock on the clean
 algorithm, and it must find violations for each planted mistake -- which
 shows that the checks can fail.  The freeze analysis must locate blocking
@@ -26,11 +27,17 @@ CONFIGS = {
     "churn": dict(n_chunks=2, ppc=2, leaders=[[(A, 1), (FO, 0), (A, 1)], [(A, 2), (FO, 0)]]),
     "churn3": dict(n_chunks=2, ppc=2, leaders=[[(A, 1), (FO, 0), (A, 1)], [(A, 2), (FO, 0)], [(A, 1)]]),
     "wide_pages": dict(n_chunks=2, ppc=8, leaders=[[(A, 4)], [(A, 4), (FO, 0)], [(A, 3)]]),
+    # a free publishes while another allocation over-asked without a hold
+    "overask_free_own": dict(n_chunks=1, ppc=2, leaders=[[(A, 2), (FO, 0)], [(A, 2)], [(A, 1)]]),
+    "overask_free_given": dict(n_chunks=1, ppc=2, prefill=2, leaders=[[(FG, 0, 2)], [(A, 2)], [(A, 1)]]),
+    "overask_free_one": dict(n_chunks=1, ppc=4, prefill=4, leaders=[[(FG, 0, 1)], [(A, 2)], [(A, 1)]]),
 }
+OVERASK = ("overask_free_own", "overask_free_given", "overask_free_one")
 
 # pcs between a leader's reservation and its release (it holds H), and the
-# slot puts of frees (a tail position reserved but not yet written)
-HOLDING = {0: set(range(2, 16)) | {43}, 1: set(range(22, 33)) | {43}}
+# slot puts and publish of frees (tail positions reserved but not yet
+# published: the out-of-memory look waits on a head/tail gap)
+HOLDING = {0: set(range(2, 16)) | {43, 44}, 1: set(range(22, 33)) | {43, 44}}
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -87,10 +94,11 @@ def test_blocking_points_are_holds_or_reserved_slots(variant, name):
 
 @pytest.mark.parametrize("name", ["oom_one_chunk", "oom_three", "churn", "churn3", "oom_refill_race"])
 def test_dry_pool_first_pass_without_hold(name):
-    """Page variant: an allocation that reads a dry pool first takes published
-    entries without holding the queue.  Those starts happen in these
+    """Page variant, first pass held unless the pool reads dry: an allocation
+    that reads a dry pool first takes published entries without holding the
+    queue.  Those starts happen in these
     configurations, and the checks still hold on every interleaving."""
-    r = O.model_run(1, **CONFIGS[name])
+    r = O.model_run(1, first_nohold=False, **CONFIGS[name])
     assert not r["truncated"]
     assert r["violations"] == 0 and r["deadlocks"] == 0, r
     if name in ("oom_one_chunk", "oom_three", "churn3"):
@@ -117,3 +125,27 @@ def test_first_pass_without_refill(name):
     assert not r["truncated"]
     assert r["violations"] == 0 and r["deadlocks"] == 0, r
     assert r["terminals"] > 0
+
+
+@pytest.mark.parametrize("name", OVERASK)
+def test_overask_hides_a_free_unless_the_look_sees_head_and_tail(name):
+    """Page variant: a first pass that takes without a hold asks for more
+    than is published and gives the excess back a step later.  A free that
+    publishes in between leaves the count at zero or below although its
+    entries are there.  The out-of-memory look waits on a head/tail gap, so
+    the clean algorithm reports no violation; a look that ignores head and
+    tail (planted) returns out-of-memory with those entries free."""
+    r = O.model_run(1, **CONFIGS[name])
+    assert not r["truncated"] and r["violations"] == 0 and r["deadlocks"] == 0, r
+    assert r["null_outcomes"] > 0
+    m = O.model_run(1, mutation=O.MUTATIONS["scan_no_positions"], **CONFIGS[name])
+    assert m["oom_violations"] > 0, m
+
+
+@pytest.mark.parametrize("name", sorted(CONFIGS))
+def test_first_pass_with_hold_when_the_pool_has_chunks(name):
+    """The earlier form of the page-variant first pass (a hold unless the
+    pool read dry) is also clean on every interleaving."""
+    r = O.model_run(1, first_nohold=False, **CONFIGS[name])
+    assert not r["truncated"]
+    assert r["violations"] == 0 and r["deadlocks"] == 0, r
