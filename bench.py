@@ -56,10 +56,11 @@ def parse():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--iters", type=int, default=10, help="alloc-write-check-free iterations per size")
-    ap.add_argument("--variant", choices=["chunk", "page"], default="page")
+    ap.add_argument("--variant", choices=["chunk", "page", "va-page"], default="page")
     ap.add_argument("--width", type=int, default=64)
     ap.add_argument("--shards", type=int, default=0, help="queue shards (0: one per 256 chunks, up to 64)")
     ap.add_argument("--no-other", action="store_true", help="skip the other queue variant")
+    ap.add_argument("--no-va", action="store_true", help="skip the virtualised-array page variant line")
     ap.add_argument("--no-ablation", action="store_true", help="skip the width-1 (no aggregation) ablation")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain device-malloc baseline")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
@@ -126,6 +127,7 @@ def main():
     from paper_2504_18211_amd import inputs
 
     hb.lib()  # fails loudly without the built library
+    VARIANTS = {"chunk": hb.VARIANT_CHUNK, "page": hb.VARIANT_PAGE, "va-page": hb.VARIANT_VA_PAGE}
     if not torch.cuda.is_available():
         log("no GPU visible")
         sys.exit(3)
@@ -197,7 +199,7 @@ def main():
     keys = ("state_ops", "headtail_ops", "pool_ops", "spread_ops")
 
     def run_sweep(variant_name: str, steps: int, warmup: int, count: bool, width: int | None = None) -> dict:
-        variant = hb.VARIANT_CHUNK if variant_name == "chunk" else hb.VARIANT_PAGE
+        variant = VARIANTS[variant_name]
         heap = hb.Heap(w.heap_bytes, w.chunk_bytes, variant=variant, width=args.width if width is None else width,
                        shards=args.shards)
         shards = int(heap.info.n_shards)
@@ -325,7 +327,7 @@ def main():
             busiest = state_atomics / shards / t_sum
             out["roofline"] = {
                 "bound": "atomic",
-                "kernel": "k_alloc_batch<false>",
+                "kernel": f"k_alloc_batch<false, {variant}u>",
                 "achieved": achieved / 1e9,
                 "peak": ceil_spread / 1e9,
                 "unit": "Gatomic/s (device-scope atomics issued; peak = measured per-lane random atomic throughput)",
@@ -345,9 +347,15 @@ def main():
     log(f"{args.variant}: {head['value']/1e9:.2f} G ops/s (iterations 2..10)")
     other = None
     if not args.no_other:
-        other_name = "chunk" if args.variant == "page" else "page"
+        other_name = "chunk" if args.variant != "chunk" else "page"
         other = run_sweep(other_name, 1, 1, count=False)
         log(f"{other_name}: {other['value']/1e9:.2f} G ops/s (iterations 2..10)")
+    # the page variant with its queues in virtualised arrays (one slot budget
+    # per shard, shared by the classes in segments), one step
+    va = None
+    if not args.no_va and args.variant != "va-page":
+        va = run_sweep("va-page", 1, 1, count=False)
+        log(f"va-page: {va['value']/1e9:.2f} G ops/s (iterations 2..10)")
 
     # ablation: the same sweep without wave aggregation (one queue operation
     # per lane), one step
@@ -404,7 +412,7 @@ def main():
     if not args.no_cpu:
         import oracle as O
         O.build(force=False)
-        variant = hb.VARIANT_CHUNK if args.variant == "chunk" else hb.VARIANT_PAGE
+        variant = VARIANTS[args.variant]
         t_cpu, cpu_ops, passes = 0.0, 0, 0
         while t_cpu < args.cpu_seconds and passes < 50:
             h = O.OracleHeap(w.heap_bytes, w.chunk_bytes, variant)
@@ -458,6 +466,7 @@ def main():
                                 "lines_1024": ceil_lines / 1e9, "per_lane_random": ceil_spread / 1e9},
         "per_size": head["per_size"],
         "other_variant": other,
+        "va_variant": va,
         "ablation_width1": ablation,
         "plain": plain,
         "vs_plain": (plain["ours_same_sizes"] / plain["value_full_size_sizes"])
@@ -505,7 +514,7 @@ def bench_paper_sweeps(hb, inputs, torch, args, ev, log):
 
     res = {"workload": "4 GiB heap, 8 KiB chunks; 10 x (alloc -> write -> check -> free) per point",
            "size_sweep_1024_allocs": {}, "thread_sweep_1000B": {}}
-    for vname, variant in (("chunk", hb.VARIANT_CHUNK), ("page", hb.VARIANT_PAGE)):
+    for vname, variant in (("chunk", hb.VARIANT_CHUNK), ("page", hb.VARIANT_PAGE), ("va-page", hb.VARIANT_VA_PAGE)):
         with hb.Heap(w.heap_bytes, w.chunk_bytes, variant=variant) as heap:
             res["size_sweep_1024_allocs"][vname] = {
                 str(s_): point(heap, inputs.PAPER_ALLOCS, s_) for s_ in inputs.SWEEP_SIZES}
@@ -529,7 +538,7 @@ def bench_growth(hb, inputs, torch, args, ev, log):
     KiB = 1024
     d_cal = inputs.growth_doublings(agents, w.seed * 16 + 0xA)   # 0xC0F4A
     d_eval = inputs.growth_doublings(agents, w.seed * 16 + 0xB)  # 0xC0F4B
-    cands = [(c * KiB, v, wd) for c in (8, 16, 32, 64) for v in (0, 1) for wd in (16, 32, 64)]
+    cands = [(c * KiB, v, wd) for c in (8, 16, 32, 64) for v in (0, 1, 2) for wd in (16, 32, 64)]
     t0 = time.perf_counter()
     ms, best = hb.growth_autotune(w.heap_bytes, agents, torch.from_numpy(d_cal).to("cuda"), steps, w.seed, cands,
                                   reps=5)

@@ -109,12 +109,17 @@ __global__ void k_iota_u32(uint32_t* p, uint64_t n)
 #define HBHEAP_ALLOC_ATTR
 #endif
 
-template <bool Counted>
+/* The batch kernels come in one instance per heap variant V (the host
+ * launches the heap's own): with h.variant a constant, every variant test of
+ * the inlined device code folds, and each instance carries only its
+ * variant's code. */
+template <bool Counted, uint32_t V>
 __global__ void __launch_bounds__(kBatchBlock) HBHEAP_ALLOC_ATTR k_alloc_batch(hbheap_dev_t h, const uint64_t* __restrict__ sizes,
                                                              void** __restrict__ ptrs, uint64_t n)
 {
     const uint64_t i = (uint64_t)blockIdx.x * kBatchBlock + threadIdx.x;
     if (i >= n) return;
+    h.variant = V;
     if (Counted) h.flags |= HBHEAP_FLAG_STATS;
     else h.flags &= ~HBHEAP_FLAG_STATS;
     /* home shard: the linear wave index, spread evenly over the shards; its
@@ -126,13 +131,14 @@ __global__ void __launch_bounds__(kBatchBlock) HBHEAP_ALLOC_ATTR k_alloc_batch(h
     ptrs[i] = malloc_wave(h, sizes[i], home, dry);
 }
 
-template <bool Counted>
+template <bool Counted, uint32_t V>
 __global__ void __launch_bounds__(kBatchBlock) k_free_batch(hbheap_dev_t h, const uint64_t* __restrict__ sizes,
                                                             void* const* __restrict__ ptrs, uint64_t n,
                                                             int32_t* __restrict__ status)
 {
     const uint64_t i = (uint64_t)blockIdx.x * kBatchBlock + threadIdx.x;
     if (i >= n) return;
+    h.variant = V;
     if (Counted) h.flags |= HBHEAP_FLAG_STATS;
     else h.flags &= ~HBHEAP_FLAG_STATS;
     const uint32_t st = free_wave(h, ptrs[i], sizes ? sizes[i] : 0, sizes != nullptr);
@@ -666,6 +672,41 @@ void release(hbheap_heap* h)
 
 }  // namespace
 
+namespace {
+template <bool C, uint32_t V>
+void launch_alloc(const hbheap_heap* h, const size_t* sizes, void** ptrs, size_t n, hipStream_t stream)
+{
+    hipLaunchKernelGGL((k_alloc_batch<C, V>), dim3(grid_for(n, kBatchBlock)), dim3(kBatchBlock), 0, stream, h->dev,
+                       (const uint64_t*)sizes, ptrs, (uint64_t)n);
+}
+template <bool C>
+void launch_alloc_v(const hbheap_heap* h, const size_t* sizes, void** ptrs, size_t n, hipStream_t stream)
+{
+    switch (h->dev.variant) {
+    case HBHEAP_VARIANT_CHUNK: launch_alloc<C, HBHEAP_VARIANT_CHUNK>(h, sizes, ptrs, n, stream); break;
+    case HBHEAP_VARIANT_PAGE: launch_alloc<C, HBHEAP_VARIANT_PAGE>(h, sizes, ptrs, n, stream); break;
+    default: launch_alloc<C, HBHEAP_VARIANT_VA_PAGE>(h, sizes, ptrs, n, stream); break;
+    }
+}
+template <bool C, uint32_t V>
+void launch_free(const hbheap_heap* h, const size_t* sizes, void* const* ptrs, size_t n, int32_t* status,
+                 hipStream_t stream)
+{
+    hipLaunchKernelGGL((k_free_batch<C, V>), dim3(grid_for(n, kBatchBlock)), dim3(kBatchBlock), 0, stream, h->dev,
+                       (const uint64_t*)sizes, ptrs, (uint64_t)n, status);
+}
+template <bool C>
+void launch_free_v(const hbheap_heap* h, const size_t* sizes, void* const* ptrs, size_t n, int32_t* status,
+                   hipStream_t stream)
+{
+    switch (h->dev.variant) {
+    case HBHEAP_VARIANT_CHUNK: launch_free<C, HBHEAP_VARIANT_CHUNK>(h, sizes, ptrs, n, status, stream); break;
+    case HBHEAP_VARIANT_PAGE: launch_free<C, HBHEAP_VARIANT_PAGE>(h, sizes, ptrs, n, status, stream); break;
+    default: launch_free<C, HBHEAP_VARIANT_VA_PAGE>(h, sizes, ptrs, n, status, stream); break;
+    }
+}
+}  // namespace
+
 extern "C" {
 
 const char* hbheap_version(void) { return "hbheap 0.1 (gfx950)"; }
@@ -827,12 +868,8 @@ int heap_alloc_batch(heap_t h, const size_t* sizes, void** ptrs, size_t n, hipSt
 {
     if (!h || (n && (!sizes || !ptrs))) return HBHEAP_E_INVAL;
     if (!n) return HBHEAP_OK;
-    if (h->dev.flags & HBHEAP_FLAG_STATS)
-        hipLaunchKernelGGL(k_alloc_batch<true>, dim3(grid_for(n, kBatchBlock)), dim3(kBatchBlock), 0, stream, h->dev,
-                           (const uint64_t*)sizes, ptrs, (uint64_t)n);
-    else
-        hipLaunchKernelGGL(k_alloc_batch<false>, dim3(grid_for(n, kBatchBlock)), dim3(kBatchBlock), 0, stream, h->dev,
-                           (const uint64_t*)sizes, ptrs, (uint64_t)n);
+    if (h->dev.flags & HBHEAP_FLAG_STATS) launch_alloc_v<true>(h, sizes, ptrs, n, stream);
+    else launch_alloc_v<false>(h, sizes, ptrs, n, stream);
     return hipGetLastError() == hipSuccess ? HBHEAP_OK : HBHEAP_E_HIP;
 }
 
@@ -840,12 +877,8 @@ int heap_free_batch_ex(heap_t h, const size_t* sizes, void* const* ptrs, size_t 
 {
     if (!h || (n && !ptrs)) return HBHEAP_E_INVAL;
     if (!n) return HBHEAP_OK;
-    if (h->dev.flags & HBHEAP_FLAG_STATS)
-        hipLaunchKernelGGL(k_free_batch<true>, dim3(grid_for(n, kBatchBlock)), dim3(kBatchBlock), 0, stream, h->dev,
-                           (const uint64_t*)sizes, ptrs, (uint64_t)n, status);
-    else
-        hipLaunchKernelGGL(k_free_batch<false>, dim3(grid_for(n, kBatchBlock)), dim3(kBatchBlock), 0, stream, h->dev,
-                           (const uint64_t*)sizes, ptrs, (uint64_t)n, status);
+    if (h->dev.flags & HBHEAP_FLAG_STATS) launch_free_v<true>(h, sizes, ptrs, n, status, stream);
+    else launch_free_v<false>(h, sizes, ptrs, n, status, stream);
     return hipGetLastError() == hipSuccess ? HBHEAP_OK : HBHEAP_E_HIP;
 }
 
