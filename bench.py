@@ -10,8 +10,11 @@ allocator's figure is the time of the allocations and frees averaged over
 the iterations after the first ("subsequent iterations", Methods): value =
 successful (alloc + free) ops / alloc+free launch time over iterations
 2..10 (HIP events on the launch stream); iterations 1..10 are reported too.
-The whole step's wall time (payload write/check and trims included) is
-ms_per_step, and all ops over it is wall_ops_per_s.
+Each size's ten iterations are queued behind a short device-side wait, so
+every event pair times its launch on the device's timeline rather than the
+host's submission latency.  The whole step's wall time (payload write/check,
+those waits and trims included) is ms_per_step, and all ops over it is
+wall_ops_per_s.
 
 The headline runs the page-queue variant (the faster one on this workload);
 the chunk-queue variant runs the same sweep for one step beside it.
@@ -108,6 +111,28 @@ def recorded_traffic():
     return float(kv["traffic_bytes_per_launch"])
 
 
+_SLEEP_CYCLES_PER_US = None
+
+
+def hold_stream(torch, us: float = 1000.0):
+    """Queue a device-side wait of about `us` microseconds on the current
+    stream, so that the host enqueues the launches that follow before the
+    device reaches them.  Each launch is then timed by its own event pair on
+    the device's timeline without the host's submission latency (the device
+    would otherwise sit idle between an event and the launch it brackets,
+    whenever Python submits more slowly than the kernels run)."""
+    global _SLEEP_CYCLES_PER_US
+    if _SLEEP_CYCLES_PER_US is None:
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda._sleep(1000)
+        e0.record()
+        torch.cuda._sleep(1_000_000)
+        e1.record()
+        torch.cuda.synchronize()
+        _SLEEP_CYCLES_PER_US = 1_000_000 / max(1.0, e0.elapsed_time(e1) * 1e3)
+    torch.cuda._sleep(int(us * _SLEEP_CYCLES_PER_US))
+
+
 def pct(a, q):
     import numpy as np
     return float(np.percentile(np.asarray(a, dtype=float), q)) if len(a) else None
@@ -174,16 +199,19 @@ def main():
     # what an event pair adds around a launch: median over a one-wave kernel
     # doing a single atomic
     def event_overhead_us():
+        """An event pair around a minimal launch, queued behind a device wait
+        as the timed launches are: dispatch plus event packets."""
         buf = torch.zeros(1 << 16, dtype=torch.uint8, device=dev)
-        ts = []
+        hold_stream(torch)
+        es = []
         for _ in range(50):
             e0, e1 = ev(), ev()
             e0.record()
             hb.hb_atomic_probe(1, buf, buf.numel(), 64, 1, 1)
             e1.record()
-            torch.cuda.synchronize()
-            ts.append(e0.elapsed_time(e1) * 1e3)
-        return float(np.median(ts))
+            es.append((e0, e1))
+        torch.cuda.synchronize()
+        return float(np.median([e0.elapsed_time(e1) * 1e3 for e0, e1 in es]))
 
     ev_overhead = event_overhead_us()
     ceil_same = probe(0, 1, 1 << 20, 4)
@@ -206,6 +234,7 @@ def main():
 
         def one_size(s, rec):
             sd = size_dev[s]
+            hold_stream(torch)
             for it in range(args.iters):
                 e = [ev() for _ in range(4)]
                 e[0].record()
@@ -494,6 +523,8 @@ def bench_paper_sweeps(hb, inputs, torch, args, ev, log):
         ptrs = torch.zeros(n, dtype=torch.int64, device="cuda")
         mism = torch.zeros(1, dtype=torch.int64, device="cuda")
         ta, tf = [], []
+        hold_stream(torch)
+        evs = []
         for it in range(10):
             e = [ev() for _ in range(4)]
             e[0].record()
@@ -504,7 +535,9 @@ def bench_paper_sweeps(hb, inputs, torch, args, ev, log):
             e[2].record()
             heap.free(ptrs)
             e[3].record()
-            torch.cuda.synchronize()
+            evs.append(e)
+        torch.cuda.synchronize()
+        for e in evs:
             ta.append(e[0].elapsed_time(e[1]) * 1e3)
             tf.append(e[2].elapsed_time(e[3]) * 1e3)
         heap.trim()

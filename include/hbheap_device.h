@@ -176,12 +176,13 @@ __device__ __forceinline__ int32_t a_loadi(int32_t* p) { return __hip_atomic_loa
 #undef HBH_A
 
 /* Zero, computed from v by an instruction the compiler cannot see through.
- * Added to the address of a later load, it makes that load wait for v: the
- * later load is issued only once the earlier one has returned its value.
- * With the device-coherent loads above (serviced where device atomics are
- * performed, never from a stale private cache) the later load then reads
- * memory no earlier than the earlier one did -- the order an acquire load
- * would give, without the cache invalidation an acquire also issues. */
+ * Added to the address of a later memory operation, it makes that operation
+ * wait for v: it is issued only once the earlier load or atomic has returned
+ * its value, i.e. has been performed.  With the device-coherent accesses
+ * above (serviced where device atomics are performed, never from a stale
+ * private cache) this orders the two as an acquire (after a load) or a
+ * release (before a store) would, without the cache invalidation or
+ * write-back those fences also issue. */
 __device__ __forceinline__ uint32_t zero_after(uint32_t v)
 {
     uint32_t z;
@@ -194,6 +195,18 @@ __device__ __forceinline__ void wave_sync_lds()
 {
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
     __builtin_amdgcn_wave_barrier();
+}
+
+/* Counters the out-of-memory path bumps (requests answered NULL, waits):
+ * kept per home shard, one 128-byte line each after the global counters,
+ * so that the waves of a launch that runs out of memory do not all add to
+ * one word; heap_stats() sums them into HBHEAP_STAT_OOM and
+ * HBHEAP_STAT_OOM_WAITS. */
+constexpr uint32_t kShardStatBase = 32; /* u64 index from h.stats */
+constexpr uint32_t kShardStatStride = 16;
+__device__ __forceinline__ uint64_t* shard_stats(const hbheap_dev_t& h, uint32_t j)
+{
+    return h.stats + kShardStatBase + (uint64_t)kShardStatStride * j;
 }
 
 __device__ __forceinline__ void raise_err(const hbheap_dev_t& h, uint32_t bit, uint32_t stat)
@@ -518,27 +531,38 @@ __device__ __forceinline__ void va_count_taken(const hbheap_dev_t& h, const Ring
             }
             c = a_load32(tk);
         }
-        __hip_atomic_store(tk, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __hip_atomic_store(r.dir + ((pos >> r.log2g) & r.dmask), kDirEmpty, __ATOMIC_RELAXED,
-                           __HIP_MEMORY_SCOPE_AGENT);
-        fence_release();
-        store_put(h, r.j, seg, t);
+        /* reset the count and empty the directory entry, both performed
+         * before the segment can be taken again: exchanges whose returned
+         * values the store's first atomic depends on (no cache-wide
+         * release fence) */
+        const uint32_t was = a_xchg32(tk, 0u);
+        const uint64_t ent = __hip_atomic_exchange(r.dir + ((pos >> r.log2g) & r.dmask), kDirEmpty,
+                                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        store_put(h, r.j + zero_after(was ^ (uint32_t)ent), seg, t);
     }
 }
 
-/* Per lane: exchange the entry out of slot s (wait while it is empty). */
+/* Per lane: exchange the entry out of slot s (wait while it is empty).  The
+ * first attempt exchanges at once (the slot of a published position is
+ * normally full; exchanging an empty slot with the empty mark changes
+ * nothing); only a late producer makes it poll with loads. */
 __device__ __forceinline__ uint32_t plain_take(const hbheap_dev_t& h, uint32_t* s, Tally& t)
 {
+    {
+        const uint32_t v = a_xchg32(s, kEmpty);
+        t.spread += 1;
+        if (v != kEmpty) return v;
+    }
     Backoff b;
     for (;;) {
+        if (!b.wait(h)) {
+            raise_err(h, HBHEAP_ERR_TIMEOUT, HBHEAP_STAT_TIMEOUTS);
+            return kEmpty;
+        }
         if (a_load32(s) != kEmpty) {
             const uint32_t v = a_xchg32(s, kEmpty);
             t.spread += 1;
             if (v != kEmpty) return v;
-        }
-        if (!b.wait(h)) {
-            raise_err(h, HBHEAP_ERR_TIMEOUT, HBHEAP_STAT_TIMEOUTS);
-            return kEmpty;
         }
     }
 }
@@ -555,18 +579,23 @@ __device__ __forceinline__ bool slot_put(const hbheap_dev_t& h, const Ring& r, u
     return plain_put(h, r.slots + (pos & r.mask), v, t);
 }
 
-/* Per lane: compare-and-swap v into slot s (wait while it is still full). */
+/* Per lane: compare-and-swap v into slot s (wait while it is still full).
+ * The first attempt swaps at once (the slot of a reserved position is
+ * normally empty; a failed swap writes nothing); only a late consumer of
+ * the previous lap makes it poll with loads. */
 __device__ __forceinline__ bool plain_put(const hbheap_dev_t& h, uint32_t* s, uint32_t v, Tally& t)
 {
+    t.spread += 1;
+    if (a_cas32(s, kEmpty, v)) return true;
     Backoff b;
     for (;;) {
-        if (a_load32(s) == kEmpty) {
-            t.spread += 1;
-            if (a_cas32(s, kEmpty, v)) return true;
-        }
         if (!b.wait(h)) {
             raise_err(h, HBHEAP_ERR_TIMEOUT, HBHEAP_STAT_TIMEOUTS);
             return false;
+        }
+        if (a_load32(s) == kEmpty) {
+            t.spread += 1;
+            if (a_cas32(s, kEmpty, v)) return true;
         }
     }
 }
@@ -1123,7 +1152,7 @@ __device__ __forceinline__ uint64_t alloc_group(const hbheap_dev_t& h, uint32_t 
             if (need < before) continue;
         }
         /* holds in flight, or the shard was drained under us: wait, bounded */
-        if (g.me == g.leader) a_add64(h.stats + HBHEAP_STAT_OOM_WAITS, 1);
+        if (g.me == g.leader) a_add64(shard_stats(h, home) + 1, 1);
         if (!wb.wait(h)) {
             timed_out = true;
             break;
@@ -1131,7 +1160,7 @@ __device__ __forceinline__ uint64_t alloc_group(const hbheap_dev_t& h, uint32_t 
     }
     if (need > 0 && g.me == g.leader) {
         if (timed_out) raise_err(h, HBHEAP_ERR_TIMEOUT, HBHEAP_STAT_TIMEOUTS);
-        a_add64(h.stats + HBHEAP_STAT_OOM, need);
+        a_add64(shard_stats(h, home), need);
     }
     if (chunk) {
         wave_sync_lds();

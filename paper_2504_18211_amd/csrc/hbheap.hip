@@ -21,6 +21,7 @@
 #include <string.h>
 
 #include <new>
+#include <vector>
 
 #include "hbheap.h"
 #include "hbheap_device.h"
@@ -65,6 +66,7 @@ struct hbheap_heap {
     uint32_t trim_blocks = 0;
     uint32_t owned_words = 0;
     uint64_t aux_bytes = 0;
+    uint64_t shard_stat_bytes = 0;
     uint64_t chunk_bytes = 0;
 };
 
@@ -739,10 +741,12 @@ int heap_create_ex(size_t bytes, size_t chunk_bytes, const heap_config_t* cfg, h
     const Layout& L = h->lay;
     h->trim_blocks = (uint32_t)((N + kTrimBlock - 1) / kTrimBlock);
     const uint32_t nkeys = S * (K + 1) + 1;
-    /* aux: err (256 B) | stats (256 B) | trim counts | offsets | totals | owned */
+    /* aux: err (256 B) | stats (256 B) | per-shard stats (128 B each) |
+     * trim counts | offsets | totals | owned */
     const uint64_t tb = al256((uint64_t)h->trim_blocks * nkeys * 4);
     const uint64_t kb = al256((uint64_t)nkeys * 4);
-    h->aux_bytes = 512 + 2 * tb + 2 * kb;
+    h->shard_stat_bytes = al256(8ull * kShardStatStride * S);
+    h->aux_bytes = 512 + h->shard_stat_bytes + 2 * tb + 2 * kb;
     if (hipMalloc(&h->data, N * chunk_bytes) != hipSuccess) { h->data = nullptr; release(h); return HBHEAP_E_NOMEM; }
     if (hipMalloc(&h->state, L.total) != hipSuccess) { h->state = nullptr; release(h); return HBHEAP_E_NOMEM; }
     if (hipMalloc(&h->aux, h->aux_bytes) != hipSuccess) { h->aux = nullptr; release(h); return HBHEAP_E_NOMEM; }
@@ -786,10 +790,11 @@ int heap_create_ex(size_t bytes, size_t chunk_bytes, const heap_config_t* cfg, h
         d.vsegs = L.vsegs;
         d.vbudget = L.vbudget;
     }
-    h->trim_counts = (uint32_t*)(ax + 512);
-    h->trim_offsets = (uint32_t*)(ax + 512 + tb);
-    h->trim_totals = (uint32_t*)(ax + 512 + 2 * tb);
-    h->trim_owned = (uint32_t*)(ax + 512 + 2 * tb + kb);
+    uint8_t* tw = ax + 512 + h->shard_stat_bytes; /* trim workspace */
+    h->trim_counts = (uint32_t*)tw;
+    h->trim_offsets = (uint32_t*)(tw + tb);
+    h->trim_totals = (uint32_t*)(tw + 2 * tb);
+    h->trim_owned = (uint32_t*)(tw + 2 * tb + kb);
     h->owned_words = S * K;
 
     /* header, pool blocks and class blocks are built on the host */
@@ -974,7 +979,15 @@ int heap_stats(heap_t h, uint64_t* out, size_t count)
     if (!h || !out) return HBHEAP_E_INVAL;
     if (count > HBHEAP_STAT_COUNT) count = HBHEAP_STAT_COUNT;
     HB_TRY(hipDeviceSynchronize());
-    HB_TRY(hipMemcpy(out, h->dev.stats, count * 8, hipMemcpyDeviceToHost));
+    uint64_t all[HBHEAP_STAT_COUNT];
+    HB_TRY(hipMemcpy(all, h->dev.stats, sizeof(all), hipMemcpyDeviceToHost));
+    std::vector<uint64_t> per((uint64_t)kShardStatStride * h->dev.n_shards);
+    HB_TRY(hipMemcpy(per.data(), h->dev.stats + kShardStatBase, per.size() * 8, hipMemcpyDeviceToHost));
+    for (uint32_t j = 0; j < h->dev.n_shards; ++j) {
+        all[HBHEAP_STAT_OOM] += per[(uint64_t)kShardStatStride * j];
+        all[HBHEAP_STAT_OOM_WAITS] += per[(uint64_t)kShardStatStride * j + 1];
+    }
+    memcpy(out, all, count * 8);
     return HBHEAP_OK;
 }
 

@@ -141,12 +141,15 @@ def test_sweep_small_exact_capacity(hb, variant, shards):
                 say(f"case sweep-small variant={variant} shards={shards} size={size} iter={it}")
                 sizes = inputs.sizes_fixed(n, size)
                 sd = dev_u64(sizes)
+                oom0 = heap.stats()["oom"]
                 heap.alloc(sd, ptrs)
                 heap.pattern_write(ptrs, sd, inputs.SEED_SWEEP)
                 assert heap.pattern_check(ptrs, sd, inputs.SEED_SWEEP) == 0
                 offs = offsets(ptrs, heap.base)
                 rep = check_blocks(heap, sizes, offs, allow_null=True)
                 assert rep.n_nonnull == min(n, cap), (rep.n_nonnull, cap)
+                # requests answered NULL are counted (per home shard, summed)
+                assert heap.stats()["oom"] - oom0 == n - min(n, cap)
                 snap, srep = check_snapshot(heap)
                 assert live_of(srep)[k] == min(n, cap)
                 if n >= cap:
