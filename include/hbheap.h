@@ -82,7 +82,10 @@ int heap_destroy(heap_t h);
 /*
  * Batch allocation: thread i of one launch sets ptrs[i] to a block of at
  * least sizes[i] bytes, or NULL when sizes[i] is 0, exceeds chunk_bytes, or
- * neither a page of its class nor an unowned chunk is left.  sizes (u64) and
+ * neither a page of its class nor an unowned chunk is left at some instant
+ * between the start of the launch and the request's answer (all requests of
+ * a launch are issued together; a proof of exhaustion found by one wave of
+ * a workgroup answers the others of the same class).  sizes (u64) and
  * ptrs are device buffers of n entries.  256-thread blocks; the lanes of each
  * wave are aggregated by size class (Porting section: warp votes let several
  * allocations of one warp proceed together).

@@ -702,6 +702,10 @@ __device__ __forceinline__ uint32_t claim_pages(const hbheap_dev_t& h, uint32_t 
 /* LDS staging: 64 page offsets per wave, for up to 16 waves per block. */
 static __shared__ uint64_t hbheap_stage_lds[kMaxWavesPerBlock * 64];
 
+/* Per-workgroup out-of-memory proof states of a class (batch launches). */
+constexpr uint32_t kShareFree = 0, kShareProving = 1, kShareProved = 2;
+constexpr uint32_t kShareSlots = 16; /* >= classes of any chunk size */
+
 __device__ __forceinline__ uint64_t* stage_for_wave()
 {
     const uint32_t lin = threadIdx.x + blockDim.x * (threadIdx.y + blockDim.y * threadIdx.z);
@@ -1122,7 +1126,7 @@ __device__ __forceinline__ void page_serve_shard(const hbheap_dev_t& h, const Gr
  * lane's page offset or kNoPage. */
 __device__ __forceinline__ uint64_t alloc_group(const hbheap_dev_t& h, uint32_t k, uint64_t grp, uint64_t* stage,
                                                 uint32_t home, bool home_dry, uint32_t served0, bool home_tried,
-                                                Tally& tl)
+                                                uint32_t* share, Tally& tl)
 {
     const Group g = make_group(h, k, grp);
     const bool chunk = h.variant == HBHEAP_VARIANT_CHUNK;
@@ -1140,10 +1144,54 @@ __device__ __forceinline__ uint64_t alloc_group(const hbheap_dev_t& h, uint32_t 
     else page_serve_shard(h, g, home, need, served, off, home_dry && !home_tried, home_tried, tl);
     Backoff wb;
     bool timed_out = false;
+    /* share != nullptr (a batch launch, whose requests were all issued when
+     * it began): the waves of one workgroup share out-of-memory proofs of a
+     * class through LDS.  One of them (the prover) scans; its finding that
+     * every shard was exhausted at some instant -- an instant inside the
+     * interval of every request of the launch still unanswered -- answers
+     * its workgroup mates too, who wait for it instead of scanning the same
+     * hot queue words.  A prover that finds entries instead gives up the
+     * claim; a wait that runs out scans on its own. */
+    bool prover = false;
     while (need > 0) {
+        if (share && !prover) {
+            uint32_t* sk = share + k;
+            Backoff pb;
+            bool answered = false;
+            for (;;) {
+                const uint32_t v = __hip_atomic_load(sk, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                if (v == kShareProved) {
+                    answered = true;
+                    break;
+                }
+                if (v == kShareFree) {
+                    uint32_t won = 0;
+                    if (g.me == g.leader) {
+                        uint32_t expect = kShareFree;
+                        won = __hip_atomic_compare_exchange_strong(sk, &expect, kShareProving, __ATOMIC_RELAXED,
+                                                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                    }
+                    if (bcast(won, g.leader)) {
+                        prover = true;
+                        break;
+                    }
+                }
+                if (!pb.wait(h)) break;
+            }
+            if (answered) break;
+        }
         bool busy = false;
         const uint32_t r = scan_shards(h, g, home, &busy);
-        if (r == S && !busy) break; /* every shard empty for this class: out of memory */
+        if (r == S && !busy) { /* every shard empty for this class: out of memory */
+            if (prover && g.me == g.leader)
+                __hip_atomic_store(share + k, kShareProved, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            break;
+        }
+        if (prover && r < S) {
+            if (g.me == g.leader)
+                __hip_atomic_store(share + k, kShareFree, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            prover = false;
+        }
         if (r < S) {
             const uint32_t j = home + r < S ? home + r : home + r - S;
             const uint32_t before = need;
@@ -1158,6 +1206,10 @@ __device__ __forceinline__ uint64_t alloc_group(const hbheap_dev_t& h, uint32_t 
             break;
         }
     }
+    if (prover && need == 0 && g.me == g.leader)
+        __hip_atomic_store(share + k, kShareFree, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    if (prover && timed_out && g.me == g.leader)
+        __hip_atomic_store(share + k, kShareFree, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
     if (need > 0 && g.me == g.leader) {
         if (timed_out) raise_err(h, HBHEAP_ERR_TIMEOUT, HBHEAP_STAT_TIMEOUTS);
         a_add64(shard_stats(h, home), need);
@@ -1185,7 +1237,8 @@ __device__ __forceinline__ bool home_pool_dry(const hbheap_dev_t& h, uint32_t ho
     return hp[0] >= ((const uint32_t*)hp)[2];
 }
 
-__device__ __forceinline__ void* malloc_wave(const hbheap_dev_t& h, uint64_t n, uint32_t home_in, bool dry_in)
+__device__ __forceinline__ void* malloc_wave(const hbheap_dev_t& h, uint64_t n, uint32_t home_in, bool dry_in,
+                                             uint32_t* share = nullptr)
 {
     /* the home shard and its hint act for the whole wave: take the first
      * active lane's (a caller whose lanes disagree would otherwise make the
@@ -1268,7 +1321,7 @@ __device__ __forceinline__ void* malloc_wave(const hbheap_dev_t& h, uint64_t n, 
         /* the whole group (served lanes included: ranks stay those of the
          * group) */
         uint64_t grp = __ballot(k == (int)kk && gl == l0);
-        const uint64_t o = alloc_group(h, kk, grp, stage, home, home_dry, bcast(done, leader), fast, tl);
+        const uint64_t o = alloc_group(h, kk, grp, stage, home, home_dry, bcast(done, leader), fast, share, tl);
         if (((grp >> me) & 1ull) && o != kNoPage) off = o;
         pend &= ~grp;
     }

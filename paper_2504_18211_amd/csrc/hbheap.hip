@@ -119,6 +119,10 @@ template <bool Counted, uint32_t V>
 __global__ void __launch_bounds__(kBatchBlock) HBHEAP_ALLOC_ATTR k_alloc_batch(hbheap_dev_t h, const uint64_t* __restrict__ sizes,
                                                              void** __restrict__ ptrs, uint64_t n)
 {
+    /* out-of-memory proofs shared by the waves of this workgroup */
+    __shared__ uint32_t share[kShareSlots];
+    if (threadIdx.x < kShareSlots) share[threadIdx.x] = kShareFree;
+    __syncthreads();
     const uint64_t i = (uint64_t)blockIdx.x * kBatchBlock + threadIdx.x;
     if (i >= n) return;
     h.variant = V;
@@ -130,7 +134,7 @@ __global__ void __launch_bounds__(kBatchBlock) HBHEAP_ALLOC_ATTR k_alloc_batch(h
     const uint32_t home = (uint32_t)((i >> 6) % h.n_shards);
     const bool dry = home_pool_dry(h, home);
     __asm__ volatile("" ::: "memory");
-    ptrs[i] = malloc_wave(h, sizes[i], home, dry);
+    ptrs[i] = malloc_wave(h, sizes[i], home, dry, share);
 }
 
 template <bool Counted, uint32_t V>
