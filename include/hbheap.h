@@ -35,7 +35,8 @@ typedef struct hbheap_heap* heap_t;
 
 /* Tunables of heap_create_ex.  Zero fields take the defaults. */
 typedef struct heap_config {
-    uint32_t variant;      /* HBHEAP_VARIANT_CHUNK (default), _PAGE or _VA_PAGE */
+    uint32_t variant;      /* HBHEAP_VARIANT_CHUNK (default), _PAGE, _VA_PAGE
+                              or _VA_CHUNK                                   */
     uint32_t width;        /* lanes aggregated per queue operation: power of
                               two in [1, 64], default 64                     */
     uint32_t spin_cap;     /* bounded-wait iterations, default 1 << 18        */
@@ -54,8 +55,11 @@ typedef struct heap_info {
     uint32_t n_classes;       /* pages 16 B * 2^k, k < n_classes             */
     uint32_t variant;
     uint64_t ring_entries;    /* capacity of each (shard, class) queue; for
-                                 the virtualised array variant, the pages the
-                                 classes of one shard may own together      */
+                                 the virtualised array page variant, the
+                                 pages the classes of one shard may own
+                                 together (virtualised array chunk variant:
+                                 the chunks of a shard, which its queues
+                                 always have room for)                      */
     uint64_t state_bytes;     /* size of the state region (= snapshot size)  */
     uint64_t metadata_bytes;  /* all device memory besides the data region   */
     uint32_t n_shards;        /* shards actually used (chunk runs of a power
@@ -67,7 +71,7 @@ typedef struct heap_info {
  * Create a heap of floor(bytes / chunk_bytes) chunks (Introduction: the host
  * preallocates the heap).  Metadata is allocated separately and is not
  * counted in `bytes`.  chunk_bytes: power of two in [4 KiB, 64 KiB]; bytes
- * >= chunk_bytes; page variant: data region at most 64 GiB.  Blocking: the
+ * >= chunk_bytes; page variants: data region at most 64 GiB.  Blocking: the
  * heap is initialised when the call returns.  *out is untouched on error.
  * Errors: HBHEAP_E_INVAL (geometry, config, out == NULL), HBHEAP_E_NOMEM
  * (hipMalloc failed), HBHEAP_E_HIP.

@@ -324,7 +324,7 @@ __device__ __forceinline__ Ring ring_of(const hbheap_dev_t& h, uint32_t j, uint3
     r.head = (uint32_t*)(cb + 128);
     r.tail = (uint32_t*)(cb + 256);
     r.j = j;
-    if (h.variant == HBHEAP_VARIANT_VA_PAGE) {
+    if (HBHEAP_VARIANT_IS_VA(h.variant)) {
         r.slots = nullptr;
         r.mask = 0;
         r.dir = h.vdir + (((uint64_t)j * h.n_classes + k) << h.log2_dir);
@@ -878,10 +878,12 @@ __device__ __forceinline__ void chunk_serve_shard(const hbheap_dev_t& h, const G
 
         /* helpers take one chunk each and read its free count */
         const bool helper = g.arank < got;
-        uint32_t c = kEmpty;
+        uint32_t c = kEmpty, vseg = 0;
         int32_t v = 0;
+        bool took_slot = false;
         if (helper) {
-            c = slot_take(h, R, h0 + g.arank, tl);
+            c = slot_take(h, R, h0 + g.arank, &vseg, tl);
+            took_slot = c != kEmpty;
             if (c != kEmpty && (c >= h.n_chunks || shard_of_chunk(h, c) != j)) {
                 raise_err(h, HBHEAP_ERR_CORRUPT, HBHEAP_STAT_TIMEOUTS);
                 c = kEmpty;
@@ -891,6 +893,7 @@ __device__ __forceinline__ void chunk_serve_shard(const hbheap_dev_t& h, const G
                 if (v <= 0) raise_err(h, HBHEAP_ERR_CORRUPT, HBHEAP_STAT_TIMEOUTS);
             }
         }
+        if (R.dir) va_count_taken(h, R, took_slot, h0 + g.arank, vseg, tl);
         const uint32_t vc = v > 0 ? ((uint32_t)v < need ? (uint32_t)v : need) : 0u;
         uint32_t tot;
         const uint32_t pre = excl_scan<7>(vc, &tot);
@@ -1129,7 +1132,7 @@ __device__ __forceinline__ uint64_t alloc_group(const hbheap_dev_t& h, uint32_t 
                                                 uint32_t* share, Tally& tl)
 {
     const Group g = make_group(h, k, grp);
-    const bool chunk = h.variant == HBHEAP_VARIANT_CHUNK;
+    const bool chunk = HBHEAP_VARIANT_LISTS_CHUNKS(h.variant);
     if (chunk) {
         stage[g.arank] = kNoPage;
         wave_sync_lds();
@@ -1277,7 +1280,7 @@ __device__ __forceinline__ void* malloc_wave(const hbheap_dev_t& h, uint64_t n, 
      * after another.  It publishes nothing (no refill); groups left short
      * continue below, each on its own. */
     uint32_t done = 0;
-    const bool fast = h.variant != HBHEAP_VARIANT_CHUNK && ngroups > 1;
+    const bool fast = !HBHEAP_VARIANT_LISTS_CHUNKS(h.variant) && ngroups > 1;
     if (fast) {
         const bool lead = k >= 0 && me == gl;
         Ring R;
@@ -1373,7 +1376,7 @@ __device__ __forceinline__ uint32_t free_wave(const hbheap_dev_t& h, void* p, ui
         old = a_or64(h.bits + widx, run.incl);
         nnew = (uint32_t)__popcll(run.incl & ~old);
         tl.spread += 1;
-        if (h.variant == HBHEAP_VARIANT_CHUNK && nnew) {
+        if (HBHEAP_VARIANT_LISTS_CHUNKS(h.variant) && nnew) {
             cold = (uint32_t)a_addi(h.chunk_cnt + c, (int32_t)nnew);
             tl.spread += 1;
         }
@@ -1383,7 +1386,7 @@ __device__ __forceinline__ uint32_t free_wave(const hbheap_dev_t& h, void* p, ui
     nnew = perm32(nnew, run.tail);
     if (cand) {
         status = ((run.prior & bit) || (old & bit)) ? kFreeDouble : kFreeOk;
-        if (h.variant == HBHEAP_VARIANT_CHUNK) {
+        if (HBHEAP_VARIANT_LISTS_CHUNKS(h.variant)) {
             /* the chunk's count left zero: the run enqueues it once */
             enq = me == run.tail && nnew > 0 && cold == 0;
             val = (uint32_t)c;

@@ -81,7 +81,7 @@ int growth_launch_shape(growth_t g, uint32_t* blocks, uint32_t* threads);
 
 typedef struct growth_candidate {
     uint64_t chunk_bytes;   /* power of two in [4 KiB, 64 KiB]          */
-    uint32_t variant;       /* HBHEAP_VARIANT_CHUNK or _PAGE            */
+    uint32_t variant;       /* any HBHEAP_VARIANT_*                     */
     uint32_t width;         /* aggregation width: 1, 2, 4 .. 64         */
 } growth_candidate_t;
 

@@ -83,8 +83,8 @@ typedef struct serve_stats {
 /* Create a server over heap h (chunk or page variant: the admission keeps
  * per-class page budgets only for those), with K streams, pinned staging of
  * 16 B per request per slot, and the device table of max_requests
- * addresses.  Blocking.  Errors: HBHEAP_E_INVAL (also for a virtualised
- * array heap), HBHEAP_E_NOMEM, HBHEAP_E_HIP. */
+ * addresses.  Blocking.  Errors: HBHEAP_E_INVAL (also for either
+ * virtualised array heap), HBHEAP_E_NOMEM, HBHEAP_E_HIP. */
 int serve_create(heap_t h, const serve_config_t* cfg, server_t* out);
 
 /* Release the server's streams and buffers (not the heap).  NULL is a no-op. */

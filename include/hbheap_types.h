@@ -19,13 +19,20 @@ extern "C" {
 #endif
 
 /* Queue variants (Results): "chunk" queues list chunks that have free
- * pages; "page" queues list free pages; "virtualised array page" queues
- * list free pages in storage taken on demand, segment by segment, from a
- * store the class queues of a shard share ("Virtualised array and list
+ * pages; "page" queues list free pages; the "virtualised array" variants
+ * keep the same queues in storage taken on demand, segment by segment, from
+ * a store the class queues of a shard share ("Virtualised array and list
  * allocators"). */
-#define HBHEAP_VARIANT_CHUNK   0u
-#define HBHEAP_VARIANT_PAGE    1u
-#define HBHEAP_VARIANT_VA_PAGE 2u
+#define HBHEAP_VARIANT_CHUNK    0u
+#define HBHEAP_VARIANT_PAGE     1u
+#define HBHEAP_VARIANT_VA_PAGE  2u
+#define HBHEAP_VARIANT_VA_CHUNK 3u
+
+/* Queues in segmented storage (the virtualised array variants). */
+#define HBHEAP_VARIANT_IS_VA(v) ((v) == HBHEAP_VARIANT_VA_PAGE || (v) == HBHEAP_VARIANT_VA_CHUNK)
+/* Queues of chunk ids (a chunk is listed while it has free pages), as
+ * opposed to queues of free pages. */
+#define HBHEAP_VARIANT_LISTS_CHUNKS(v) ((v) == HBHEAP_VARIANT_CHUNK || (v) == HBHEAP_VARIANT_VA_CHUNK)
 
 /* Return codes of every host entry point. */
 #define HBHEAP_OK          0

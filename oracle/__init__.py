@@ -29,7 +29,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liboracle.so")
 SOURCES = ["hbheap_oracle.c", "hbheap_model.c"]
 
-VARIANT_CHUNK, VARIANT_PAGE, VARIANT_VA_PAGE = 0, 1, 2
+VARIANT_CHUNK, VARIANT_PAGE, VARIANT_VA_PAGE, VARIANT_VA_CHUNK = 0, 1, 2, 3
 POLICY_LOWEST, POLICY_FIFO = 0, 1
 FREE_OK, FREE_DOUBLE, FREE_INVALID, FREE_NULL = 0, 1, 2, 3
 MAX_CLASSES = 16
@@ -124,6 +124,8 @@ def lib():
             "orc_va_log2_seg": (u32, [u64, u64, u32]),
             "orc_va_segments": (u64, [u64, u64, u32]),
             "orc_va_budget": (u64, [u64, u64, u32]),
+            "orc_va_chunk_log2_seg": (u32, [u64, u64, u32]),
+            "orc_va_chunk_segments": (u64, [u64, u64, u32]),
             "orc_pattern_sums": (None, [u32, vp, vp, u64, vp]),
             "orc_check_blocks": (C.c_int, [u64, u64, vp, vp, u64, C.POINTER(BlocksReport)]),
             "orc_check_snapshot": (C.c_int, [vp, u64, C.POINTER(SnapReport)]),
@@ -254,6 +256,15 @@ def va_segments(nbytes: int, chunk_bytes: int, shards: int = 1) -> int:
 
 def va_budget(nbytes: int, chunk_bytes: int, shards: int = 1) -> int:
     return int(lib().orc_va_budget(nbytes, chunk_bytes, shards))
+
+
+def va_chunk_log2_seg(nbytes: int, chunk_bytes: int, shards: int = 0) -> int:
+    """Virtualised array chunk variant; shards as requested of a heap (0 auto)."""
+    return int(lib().orc_va_chunk_log2_seg(nbytes, chunk_bytes, shards))
+
+
+def va_chunk_segments(nbytes: int, chunk_bytes: int, shards: int = 0) -> int:
+    return int(lib().orc_va_chunk_segments(nbytes, chunk_bytes, shards))
 
 
 def page_max_chunks(nbytes: int, chunk_bytes: int, k: int, shards: int = 1) -> int:

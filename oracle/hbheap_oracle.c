@@ -133,6 +133,28 @@ uint64_t orc_va_budget(uint64_t bytes, uint64_t chunk_bytes, uint32_t shards)
     return m > k3 ? (m - k3) << orc_va_log2_seg(bytes, chunk_bytes, shards) : 0;
 }
 
+/* Virtualised array chunk variant: a chunk is listed in at most one queue,
+ * so the queues of a shard (span = 2^log2_span chunks) hold at most span
+ * entries together.  Segments of 2^g slots, g = log2(span) - 3 kept within
+ * [4, 10]; a queue spans at most ceil(span / 2^g) + 2 segments, plus one on
+ * its way back: M = ceil(span / 2^g) + 3K per shard never runs out. */
+uint32_t orc_va_chunk_log2_seg(uint64_t bytes, uint64_t chunk_bytes, uint32_t shards)
+{
+    uint32_t S = 1, ls = 0;
+    orc_shard_geometry(bytes / chunk_bytes, shards, &S, &ls);
+    int g = (int)ls - 3;
+    if (g < 4) g = 4;
+    if (g > 10) g = 10;
+    return (uint32_t)g;
+}
+uint64_t orc_va_chunk_segments(uint64_t bytes, uint64_t chunk_bytes, uint32_t shards)
+{
+    uint32_t S = 1, ls = 0;
+    orc_shard_geometry(bytes / chunk_bytes, shards, &S, &ls);
+    const uint32_t g = orc_va_chunk_log2_seg(bytes, chunk_bytes, shards);
+    return (((1ull << ls) + (1ull << g) - 1) >> g) + 3ull * orc_num_classes(chunk_bytes);
+}
+
 /* ------------------------------------------------------------------ */
 /* small containers                                                    */
 /* ------------------------------------------------------------------ */
@@ -268,7 +290,9 @@ static uint64_t shard_end(const orc_heap* h, uint32_t j)
 orc_heap* orc_create_ex(uint64_t bytes, uint64_t chunk_bytes, int variant, int policy, uint32_t shards)
 {
     if (!orc_geometry_ok(bytes, chunk_bytes)) return NULL;
-    if (variant != ORC_VARIANT_CHUNK && variant != ORC_VARIANT_PAGE && variant != ORC_VARIANT_VA_PAGE) return NULL;
+    if (variant != ORC_VARIANT_CHUNK && variant != ORC_VARIANT_PAGE && variant != ORC_VARIANT_VA_PAGE &&
+        variant != ORC_VARIANT_VA_CHUNK)
+        return NULL;
     if (policy != ORC_POLICY_LOWEST && policy != ORC_POLICY_FIFO) return NULL;
     if (shards > 64 || (shards & (shards - 1))) return NULL;
     orc_heap* h = (orc_heap*)calloc(1, sizeof(orc_heap));
@@ -361,6 +385,11 @@ static void claim_fresh(orc_heap* h, uint64_t c, uint32_t k)
     h->acct.live[k]++;
 }
 
+/* Queues of chunk ids (the chunk variants; storage does not change the
+ * sequential behaviour) rather than of free pages. */
+static int lists_chunks(int variant) { return variant == ORC_VARIANT_CHUNK || variant == ORC_VARIANT_VA_CHUNK; }
+static int is_va(int variant) { return variant == ORC_VARIANT_VA_PAGE || variant == ORC_VARIANT_VA_CHUNK; }
+
 static int can_grow(const orc_heap* h, uint32_t j, uint32_t k)
 {
     if (h->variant == ORC_VARIANT_VA_PAGE) {
@@ -402,7 +431,7 @@ static int64_t alloc_fifo(orc_heap* h, uint32_t k)
     for (uint32_t j = 0; j < h->S; ++j) {
         fifo* q = &h->q[(uint64_t)j * h->K + k];
         if (q->len) {
-            if (h->variant == ORC_VARIANT_CHUNK) {
+            if (lists_chunks(h->variant)) {
                 uint64_t c = fifo_pop(q);
                 int64_t p = lowest_free_page(h, c);
                 bit_clr(h, c, (uint64_t)p);
@@ -421,7 +450,7 @@ static int64_t alloc_fifo(orc_heap* h, uint32_t k)
         if (!can_grow(h, j, k) || h->pool_next[j] >= h->pool_size[j]) continue;
         uint64_t c = h->pool[shard_first(h, j) + h->pool_next[j]++];
         claim_fresh(h, c, k);
-        if (h->variant == ORC_VARIANT_CHUNK) {
+        if (lists_chunks(h->variant)) {
             if (h->cnt[c] > 0) fifo_push(q, c);
         } else {
             for (uint64_t p = 1; p < ppc_of(h, k); ++p) fifo_push(q, (uint64_t)offset_of(h, c, k, p));
@@ -459,7 +488,7 @@ int orc_free(orc_heap* h, int64_t off)
         if (was == 0) hset_set(&h->avail[k], c);
     } else {
         fifo* q = &h->q[(uint64_t)shard_of(h, c) * h->K + k];
-        if (h->variant == ORC_VARIANT_CHUNK) {
+        if (lists_chunks(h->variant)) {
             if (was == 0) fifo_push(q, c);
         } else {
             fifo_push(q, o);
@@ -499,7 +528,7 @@ void orc_trim(orc_heap* h)
             if (h->cls[c] == FREE_CLASS || h->cnt[c] == 0) continue;
             uint32_t k = h->cls[c];
             fifo* q = &h->q[(uint64_t)shard_of(h, c) * h->K + k];
-            if (h->variant == ORC_VARIANT_CHUNK) {
+            if (lists_chunks(h->variant)) {
                 fifo_push(q, c);
             } else {
                 for (uint64_t p = 0; p < ppc_of(h, k); ++p)
@@ -641,7 +670,7 @@ int orc_check_blocks(uint64_t data_bytes, uint64_t chunk_bytes, const uint64_t* 
 /* ring (j, k) at slot index (j*K + k) << log2 ring cap; page-variant  */
 /* slots hold the page's byte offset / 16; a page-variant class may    */
 /* own at most (ring entries / pages per chunk) chunks of one shard.   */
-/* virtualised array page variant (variant 2), header continued:       */
+/* virtualised array variants (2 pages, 3 chunks), header continued:   */
 /* 112 u32 log2 seg g  116 u32 log2 dir  120 u32 log2 store            */
 /* 124 u32 segments M per shard  128 u64 page budget per shard         */
 /* 136 u64 off dirs  144 u64 off taken  152 u64 off stores             */
@@ -684,18 +713,23 @@ static int snap_open(const uint8_t* s, uint64_t len, snapview* v)
     if (v->W != (1u << v->log2C) / 1024 || v->data_bytes != (v->N << v->log2C)) return 0;
     if (v->S == 0 || v->log2_span > 31 || ((uint64_t)v->S << v->log2_span) < v->N ||
         ((uint64_t)(v->S - 1) << v->log2_span) >= v->N) return 0;
-    if (o_sl + (((uint64_t)v->S * v->K) << v->log2q) * 4 > total) return 0;
     v->pool = s + o_pool; v->classes = s + o_cl; v->cls = s + o_cls; v->cnt = s + o_cnt;
     v->bits = s + o_bits; v->pool_ids = s + o_pid; v->slots = s + o_sl;
-    if (v->variant > 2) return 0;
-    if (v->variant == 2) {
+    if (v->variant > 3) return 0;
+    if (!is_va((int)v->variant) && o_sl + (((uint64_t)v->S * v->K) << v->log2q) * 4 > total) return 0;
+    if (is_va((int)v->variant)) {
         v->g = rd32(s + 112); v->ldir = rd32(s + 116); v->lstore = rd32(s + 120); v->M = rd32(s + 124);
         v->budget = rd64(s + 128);
         uint64_t o_dir = rd64(s + 136), o_tk = rd64(s + 144), o_st = rd64(s + 152), o_ss = rd64(s + 160);
-        if (v->g < 4 || v->g > 10 || v->ldir > 24 || v->lstore > 24 || v->M == 0 ||
-            ((uint64_t)v->M << v->g) > ((uint64_t)v->K << v->log2q) || (1ull << v->ldir) < (uint64_t)v->M + 3 ||
-            (1ull << v->lstore) < v->M)
+        if (v->g < 4 || v->g > 10 || v->ldir > 24 || v->lstore > 24 || v->M == 0 || (1ull << v->lstore) < v->M)
             return 0;
+        if (v->variant == 2 && (((uint64_t)v->M << v->g) > ((uint64_t)v->K << v->log2q) ||
+                                (1ull << v->ldir) < (uint64_t)v->M + 3))
+            return 0;
+        /* chunk queues: a queue spans at most ceil(span / 2^g) + 2 segments */
+        const uint64_t per_queue = ((1ull << v->log2_span) + (1ull << v->g) - 1) >> v->g;
+        if (v->variant == 3 && (v->M != per_queue + 3ull * v->K || (1ull << v->ldir) < per_queue + 3)) return 0;
+        if (o_sl + (((uint64_t)v->S * v->M) << v->g) * 4 > total) return 0;
         if (o_dir + (((uint64_t)v->S * v->K) << v->ldir) * 8 > total || o_tk + (uint64_t)v->S * v->M * 4 > total ||
             o_st + (uint64_t)v->S * 512 > total || o_ss + ((uint64_t)v->S << v->lstore) * 4 > total)
             return 0;
@@ -710,7 +744,7 @@ static int snap_open(const uint8_t* s, uint64_t len, snapview* v)
 static uint32_t sv_entry(const snapview* v, uint32_t j, uint32_t k, uint32_t pos)
 {
     const uint64_t ring = (uint64_t)j * v->K + k;
-    if (v->variant != 2) {
+    if (!is_va((int)v->variant)) {
         const uint64_t Q = 1ull << v->log2q;
         return rd32(v->slots + ((ring << v->log2q) + (pos & (uint32_t)(Q - 1))) * 4);
     }
@@ -738,8 +772,8 @@ static uint64_t popc_chunk(const snapview* v, uint64_t c)
  *  - a used segment's consumed count is its positions below head, a free
  *    one's zero; every slot that holds no position in [head, tail) is empty;
  *  - the store holds exactly the ids no queue uses, once each, with no hold;
- *  - the pages the shard's classes own equal its committed count, within
- *    the budget. */
+ *  - page queues: the pages the shard's classes own equal its committed
+ *    count, within the budget; chunk queues keep that count at zero. */
 static void check_va(const snapview* v, const uint64_t* chunks_sk, orc_snap_report* rep)
 {
     const uint64_t G = 1ull << v->g, D = 1ull << v->ldir, QS = 1ull << v->lstore;
@@ -756,7 +790,7 @@ static void check_va(const snapview* v, const uint64_t* chunks_sk, orc_snap_repo
             const uint8_t* cb = v->classes + ring * 512;
             const uint32_t head = rd32(cb + 128), tail = rd32(cb + 256);
             const uint64_t H = head, T = H + (uint32_t)(tail - head);
-            pages += chunks_sk[ring] * ((1ull << v->log2C) >> (4 + k));
+            if (v->variant == 2) pages += chunks_sk[ring] * ((1ull << v->log2C) >> (4 + k));
             uint8_t* want = (uint8_t*)calloc(D, 1);
             const uint64_t smask = (v->g < 32) ? ((1ull << (32 - v->g)) - 1) : 0;
             for (uint64_t sg = H >> v->g; (sg << v->g) < T; ++sg) {
@@ -808,7 +842,7 @@ static void check_va(const snapview* v, const uint64_t* chunks_sk, orc_snap_repo
             (void)in_store;
         }
         const uint64_t committed = rd64(sb + 384);
-        if (committed != pages || committed > v->budget) rep->bad_committed++;
+        if (committed != pages || (v->variant == 2 && committed > v->budget)) rep->bad_committed++;
     }
     free(used);
     free(mark);
@@ -847,7 +881,7 @@ int orc_check_snapshot(const uint8_t* snap, uint64_t len, orc_snap_report* rep)
             if (x & ~valid) rep->bad_stray_bits++;
         }
         uint64_t f = popc_chunk(&v, c);
-        if (v.variant == 0 && cn != f) rep->bad_count++;
+        if (lists_chunks((int)v.variant) && cn != f) rep->bad_count++;
         rep->chunks[k]++;
         chunks_sk[(uint64_t)j * v.K + k]++;
         rep->free_pages[k] += f;
@@ -886,18 +920,19 @@ int orc_check_snapshot(const uint8_t* snap, uint64_t len, orc_snap_report* rep)
             uint32_t H = (uint32_t)(state >> 32);
             int64_t Cnt = (int64_t)(uint32_t)state - (int64_t)0x80000000u;
             uint32_t used = tail - head;
-            const uint64_t cap = v.variant == 2 ? ((uint64_t)v.M << v.g) : Q;
+            const uint64_t cap = is_va((int)v.variant) ? ((uint64_t)v.M << v.g) : Q;
             if (H != 0 || Cnt != (int64_t)used || used > cap) { rep->bad_ring_ctl++; continue; }
-            if (v.variant != 0 && owned != chunks_sk[ring]) rep->bad_owned++;
+            if (!lists_chunks((int)v.variant) && owned != chunks_sk[ring]) rep->bad_owned++;
+            if (lists_chunks((int)v.variant) && owned != 0) rep->bad_owned++;
             if (v.variant == 1 && chunks_sk[ring] > (Q >> (v.log2C - 4 - k))) rep->bad_owned++;
-            if (v.variant != 2) {
+            if (!is_va((int)v.variant)) {
                 const uint8_t* sl = v.slots + (ring << v.log2q) * 4;
                 for (uint64_t i = used; i < Q; ++i) {
                     uint32_t e = rd32(sl + ((uint64_t)((head + (uint32_t)i) & (uint32_t)(Q - 1))) * 4);
                     if (e != SLOT_EMPTY) rep->bad_ring_entry++;
                 }
             }
-            if (v.variant == 0) {
+            if (lists_chunks((int)v.variant)) {
                 for (uint64_t c = lo; c < hi; ++c) seen[c] = 0;
                 for (uint32_t i = 0; i < used; ++i) {
                     uint32_t c = sv_entry(&v, j, k, head + i);
@@ -933,7 +968,7 @@ int orc_check_snapshot(const uint8_t* snap, uint64_t len, orc_snap_report* rep)
             }
         }
     }
-    if (v.variant == 2) check_va(&v, chunks_sk, rep);
+    if (is_va((int)v.variant)) check_va(&v, chunks_sk, rep);
     free(seen);
     free(chunks_sk);
     free(free_s);

@@ -38,7 +38,7 @@ extern "C" {
 
 #define ORC_MAX_CLASSES 16
 
-enum { ORC_VARIANT_CHUNK = 0, ORC_VARIANT_PAGE = 1, ORC_VARIANT_VA_PAGE = 2 };
+enum { ORC_VARIANT_CHUNK = 0, ORC_VARIANT_PAGE = 1, ORC_VARIANT_VA_PAGE = 2, ORC_VARIANT_VA_CHUNK = 3 };
 /* LOWEST: canonical legal outcome (lowest chunk id, then lowest page).
  * FIFO:   the order a single device thread observes (queue order). */
 enum { ORC_POLICY_LOWEST = 0, ORC_POLICY_FIFO = 1 };
@@ -59,6 +59,10 @@ int      orc_geometry_ok(uint64_t bytes, uint64_t chunk_bytes);
 uint32_t orc_va_log2_seg(uint64_t bytes, uint64_t chunk_bytes, uint32_t shards);
 uint64_t orc_va_segments(uint64_t bytes, uint64_t chunk_bytes, uint32_t shards);
 uint64_t orc_va_budget(uint64_t bytes, uint64_t chunk_bytes, uint32_t shards);
+/* Virtualised array chunk variant (shards as requested of orc_create_ex):
+ * log2 of the segment size and the segments per shard. */
+uint32_t orc_va_chunk_log2_seg(uint64_t bytes, uint64_t chunk_bytes, uint32_t shards);
+uint64_t orc_va_chunk_segments(uint64_t bytes, uint64_t chunk_bytes, uint32_t shards);
 
 /* ---- sequential allocator ---- */
 typedef struct orc_heap orc_heap;

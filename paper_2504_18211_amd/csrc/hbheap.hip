@@ -41,7 +41,8 @@ constexpr uint32_t kMaxShards = 64;
 struct Layout {
     uint64_t off_pool, off_cl, off_cls, off_cnt, off_bits, off_pid, off_sl, total;
     uint32_t log2q;
-    /* virtualised array page variant */
+    uint64_t n_slots; /* u32 slots of the ring storage */
+    /* virtualised array variants */
     uint64_t off_vdir = 0, off_vtaken = 0, off_vstore = 0, off_vslots = 0;
     uint32_t log2_seg = 0, log2_dir = 0, log2_store = 0, vsegs = 0;
     uint64_t vbudget = 0;
@@ -192,7 +193,7 @@ __device__ __forceinline__ TrimKey trim_key(const hbheap_dev_t& h, uint64_t c)
         t.weight = 1;
         return t;
     }
-    if (h.variant == HBHEAP_VARIANT_CHUNK) {
+    if (HBHEAP_VARIANT_LISTS_CHUNKS(h.variant)) {
         const bool listed = h.chunk_cnt[c] > 0;
         t.key = listed ? j * h.n_classes + k : h.n_shards * (h.n_classes + 1);
         t.weight = listed ? 1u : 0u;
@@ -325,6 +326,11 @@ __global__ void __launch_bounds__(kTrimBlock) k_trim_write(hbheap_dev_t h, const
                 if (idx < h.n_chunks) h.pool_ids[idx] = (uint32_t)c;
             } else if (h.variant == HBHEAP_VARIANT_CHUNK) {
                 if (pos < Q) h.slots[(uint64_t)key * Q + pos] = (uint32_t)c;
+            } else if (h.variant == HBHEAP_VARIANT_VA_CHUNK) {
+                const uint64_t seg = va_first_seg(h, totals, j, kk) + (pos >> h.log2_seg);
+                if (seg < h.vsegs)
+                    h.slots[(((uint64_t)j * h.vsegs + seg) << h.log2_seg) + (pos & ((1u << h.log2_seg) - 1u))] =
+                        (uint32_t)c;
             } else {
                 const uint32_t shift = 4u + kk;
                 const uint32_t ppc = 1u << (h.log2_chunk - shift);
@@ -363,7 +369,7 @@ __global__ void k_trim_ctl(hbheap_dev_t h, const uint32_t* totals, const uint32_
         *(uint64_t*)cb = (uint64_t)(totals[i] + kBias);
         *(uint32_t*)(cb + 128) = 0;
         *(uint32_t*)(cb + 256) = totals[i];
-        *(uint64_t*)(cb + 384) = h.variant != HBHEAP_VARIANT_CHUNK ? (uint64_t)owned[i] : 0ull;
+        *(uint64_t*)(cb + 384) = !HBHEAP_VARIANT_LISTS_CHUNKS(h.variant) ? (uint64_t)owned[i] : 0ull;
     }
     for (uint32_t j = threadIdx.x; j < S; j += blockDim.x) {
         uint64_t* pb = h.pool + 16ull * j;
@@ -406,7 +412,7 @@ __global__ void k_va_rebuild(hbheap_dev_t h, const uint32_t* totals, const uint3
             const uint32_t used0 = totals ? va_first_seg(h, totals, j, K) : 0u;
             const uint32_t used = used0 < M ? used0 : M;
             uint64_t pages = 0;
-            if (owned)
+            if (owned && h.variant == HBHEAP_VARIANT_VA_PAGE)
                 for (uint32_t k = 0; k < K; ++k) pages += (uint64_t)owned[j * K + k] << (h.log2_chunk - 4u - k);
             uint8_t* sb = h.vstore + (uint64_t)j * kStoreBlock;
             *(uint64_t*)sb = (uint64_t)(M - used) + kBias;
@@ -632,12 +638,39 @@ Layout make_layout(uint64_t N, uint32_t log2C, uint32_t K, uint32_t variant, uin
 {
     Layout L;
     const uint64_t W = (1ull << log2C) / 1024;
-    if (variant == HBHEAP_VARIANT_CHUNK) {
+    if (HBHEAP_VARIANT_LISTS_CHUNKS(variant)) {
         L.log2q = log2_span;
     } else {
         const uint64_t per = bytes / 8 / K / 4 / S;
         L.log2q = per ? ilog2(per) : 0;
     }
+    L.n_slots = ((uint64_t)S * K) << L.log2q;
+    /* virtualised array: a shard's queues share M segments of 2^log2_seg
+     * slots (Q/8, kept within 16 .. 1024).  Page queues: the page variant's
+     * slot budget cut into segments; a queue spans at most the pages its
+     * class owns plus partial segments at both ends and one on its way
+     * back, so the classes may own (M - 3K) segments' worth of pages.  Chunk
+     * queues: a chunk is listed in at most one queue, so the queues of a
+     * shard hold at most span entries together: M = ceil(span / 2^g) + 3K
+     * segments always suffice, and one queue spans at most
+     * ceil(span / 2^g) + 2 of them. */
+    uint32_t lg = L.log2q >= 3 ? L.log2q - 3 : 0;
+    lg = lg < 4 ? 4 : (lg > 10 ? 10 : lg);
+    if (variant == HBHEAP_VARIANT_VA_PAGE) {
+        L.log2_seg = lg;
+        L.vsegs = (uint32_t)(((uint64_t)K << L.log2q) >> lg);
+        L.log2_dir = ceil_log2((uint64_t)L.vsegs + 3);
+        L.log2_store = ceil_log2(L.vsegs);
+        L.vbudget = L.vsegs > 3 * K ? (uint64_t)(L.vsegs - 3 * K) << lg : 0;
+    } else if (variant == HBHEAP_VARIANT_VA_CHUNK) {
+        const uint64_t per_queue = ((1ull << log2_span) + (1ull << lg) - 1) >> lg;
+        L.log2_seg = lg;
+        L.vsegs = (uint32_t)(per_queue + 3ull * K);
+        L.log2_dir = ceil_log2(per_queue + 3);
+        L.log2_store = ceil_log2(L.vsegs);
+        L.vbudget = 0;
+    }
+    if (HBHEAP_VARIANT_IS_VA(variant)) L.n_slots = ((uint64_t)S * L.vsegs) << lg;
     L.off_pool = 256;
     L.off_cl = al256(L.off_pool + 128ull * S);
     L.off_cls = al256(L.off_cl + (uint64_t)kClassBlock * S * K);
@@ -645,17 +678,8 @@ Layout make_layout(uint64_t N, uint32_t log2C, uint32_t K, uint32_t variant, uin
     L.off_bits = al256(L.off_cnt + 4 * N);
     L.off_pid = al256(L.off_bits + 8 * N * W);
     L.off_sl = al256(L.off_pid + 4 * N);
-    L.total = al256(L.off_sl + 4ull * S * K * (1ull << L.log2q));
-    if (variant == HBHEAP_VARIANT_VA_PAGE) {
-        /* the page variant's slot budget, cut into segments a shard's queues
-         * share: 2^log2_seg slots each (Q/8, kept within 16 .. 1024) */
-        uint32_t lg = L.log2q >= 3 ? L.log2q - 3 : 0;
-        lg = lg < 4 ? 4 : (lg > 10 ? 10 : lg);
-        L.log2_seg = lg;
-        L.vsegs = (uint32_t)(((uint64_t)K << L.log2q) >> lg);
-        L.log2_dir = ceil_log2((uint64_t)L.vsegs + 3);
-        L.log2_store = ceil_log2(L.vsegs);
-        L.vbudget = L.vsegs > 3 * K ? (uint64_t)(L.vsegs - 3 * K) << lg : 0;
+    L.total = al256(L.off_sl + 4ull * L.n_slots);
+    if (HBHEAP_VARIANT_IS_VA(variant)) {
         L.off_vdir = L.total;
         L.off_vtaken = al256(L.off_vdir + 8ull * S * K * (1ull << L.log2_dir));
         L.off_vstore = al256(L.off_vtaken + 4ull * S * L.vsegs);
@@ -691,7 +715,8 @@ void launch_alloc_v(const hbheap_heap* h, const size_t* sizes, void** ptrs, size
     switch (h->dev.variant) {
     case HBHEAP_VARIANT_CHUNK: launch_alloc<C, HBHEAP_VARIANT_CHUNK>(h, sizes, ptrs, n, stream); break;
     case HBHEAP_VARIANT_PAGE: launch_alloc<C, HBHEAP_VARIANT_PAGE>(h, sizes, ptrs, n, stream); break;
-    default: launch_alloc<C, HBHEAP_VARIANT_VA_PAGE>(h, sizes, ptrs, n, stream); break;
+    case HBHEAP_VARIANT_VA_PAGE: launch_alloc<C, HBHEAP_VARIANT_VA_PAGE>(h, sizes, ptrs, n, stream); break;
+    default: launch_alloc<C, HBHEAP_VARIANT_VA_CHUNK>(h, sizes, ptrs, n, stream); break;
     }
 }
 template <bool C, uint32_t V>
@@ -708,7 +733,8 @@ void launch_free_v(const hbheap_heap* h, const size_t* sizes, void* const* ptrs,
     switch (h->dev.variant) {
     case HBHEAP_VARIANT_CHUNK: launch_free<C, HBHEAP_VARIANT_CHUNK>(h, sizes, ptrs, n, status, stream); break;
     case HBHEAP_VARIANT_PAGE: launch_free<C, HBHEAP_VARIANT_PAGE>(h, sizes, ptrs, n, status, stream); break;
-    default: launch_free<C, HBHEAP_VARIANT_VA_PAGE>(h, sizes, ptrs, n, status, stream); break;
+    case HBHEAP_VARIANT_VA_PAGE: launch_free<C, HBHEAP_VARIANT_VA_PAGE>(h, sizes, ptrs, n, status, stream); break;
+    default: launch_free<C, HBHEAP_VARIANT_VA_CHUNK>(h, sizes, ptrs, n, status, stream); break;
     }
 }
 }  // namespace
@@ -724,7 +750,7 @@ int heap_create_ex(size_t bytes, size_t chunk_bytes, const heap_config_t* cfg, h
     if (bytes < chunk_bytes) return HBHEAP_E_INVAL;
     heap_config_t c = {};
     if (cfg) c = *cfg;
-    if (c.variant > HBHEAP_VARIANT_VA_PAGE) return HBHEAP_E_INVAL;
+    if (c.variant > HBHEAP_VARIANT_VA_CHUNK) return HBHEAP_E_INVAL;
     if (!c.width) c.width = 64;
     if (c.width > 64 || (c.width & (c.width - 1))) return HBHEAP_E_INVAL;
     if (!c.spin_cap) c.spin_cap = 1u << 18;
@@ -733,7 +759,7 @@ int heap_create_ex(size_t bytes, size_t chunk_bytes, const heap_config_t* cfg, h
     if (N >= 0x80000000ull) return HBHEAP_E_INVAL;
     const uint32_t log2C = ilog2(chunk_bytes);
     const uint32_t K = log2C - 3;
-    if (c.variant != HBHEAP_VARIANT_CHUNK && N * chunk_bytes > (64ull << 30)) return HBHEAP_E_INVAL;
+    if (!HBHEAP_VARIANT_LISTS_CHUNKS(c.variant) && N * chunk_bytes > (64ull << 30)) return HBHEAP_E_INVAL;
     if (c.shards > kMaxShards || (c.shards & (c.shards - 1))) return HBHEAP_E_INVAL;
     uint32_t S = 1, log2_span = 0;
     shard_geometry(N, c.shards, &S, &log2_span);
@@ -782,8 +808,8 @@ int heap_create_ex(size_t bytes, size_t chunk_bytes, const heap_config_t* cfg, h
     d.flags = c.flags;
     d.n_shards = S;
     d.log2_span = log2_span;
-    if (c.variant == HBHEAP_VARIANT_VA_PAGE) {
-        if (L.vbudget == 0) { release(h); return HBHEAP_E_INVAL; }
+    if (HBHEAP_VARIANT_IS_VA(c.variant)) {
+        if (c.variant == HBHEAP_VARIANT_VA_PAGE && L.vbudget == 0) { release(h); return HBHEAP_E_INVAL; }
         d.vdir = (uint64_t*)(st + L.off_vdir);
         d.vtaken = (uint32_t*)(st + L.off_vtaken);
         d.vstore = st + L.off_vstore;
@@ -845,14 +871,14 @@ int heap_create_ex(size_t bytes, size_t chunk_bytes, const heap_config_t* cfg, h
     int rc = HBHEAP_OK;
     hipStream_t s = nullptr;
     if (fill_u32((uint32_t*)st, L.total / 4, 0u, s) || fill_u8(st + L.off_cls, N, (uint8_t)kFreeClass, s) ||
-        fill_u32(d.slots, ((uint64_t)S * K) << L.log2q, kEmpty, s) || fill_u32((uint32_t*)ax, h->aux_bytes / 4, 0u, s))
+        fill_u32(d.slots, L.n_slots, kEmpty, s) || fill_u32((uint32_t*)ax, h->aux_bytes / 4, 0u, s))
         rc = HBHEAP_E_HIP;
     if (rc == HBHEAP_OK) {
         hipLaunchKernelGGL(k_iota_u32, dim3(grid_stride(N)), dim3(256), 0, s, d.pool_ids, N);
         if (hipGetLastError() != hipSuccess) rc = HBHEAP_E_HIP;
     }
     if (rc == HBHEAP_OK && hipMemcpyAsync(st, hb, head_bytes, hipMemcpyHostToDevice, s) != hipSuccess) rc = HBHEAP_E_HIP;
-    if (rc == HBHEAP_OK && c.variant == HBHEAP_VARIANT_VA_PAGE) rc = va_rebuild(d, nullptr, nullptr, s);
+    if (rc == HBHEAP_OK && HBHEAP_VARIANT_IS_VA(c.variant)) rc = va_rebuild(d, nullptr, nullptr, s);
     if (rc == HBHEAP_OK && hipStreamSynchronize(s) != hipSuccess) rc = HBHEAP_E_HIP;
     free(hb);
     if (rc != HBHEAP_OK) { release(h); return rc; }
@@ -939,14 +965,14 @@ int heap_trim(heap_t h, hipStream_t stream)
     hipLaunchKernelGGL(k_trim_scan, dim3(1), dim3(1024), 0, stream, h->trim_counts, h->trim_offsets, h->trim_totals, nb,
                        nkeys);
     HB_TRY(hipGetLastError());
-    rc = fill_u32(d.slots, ((uint64_t)d.n_shards * d.n_classes) << d.log2q, kEmpty, stream);
+    rc = fill_u32(d.slots, h->lay.n_slots, kEmpty, stream);
     if (!rc) rc = fill_u32(d.pool_ids, d.n_chunks, kEmpty, stream);
     if (rc) return rc;
     hipLaunchKernelGGL(k_trim_write, dim3(nb), dim3(kTrimBlock), 0, stream, d, h->trim_offsets, nb, h->trim_totals);
     HB_TRY(hipGetLastError());
     hipLaunchKernelGGL(k_trim_ctl, dim3(1), dim3(1024), 0, stream, d, h->trim_totals, h->trim_owned);
     HB_TRY(hipGetLastError());
-    if (d.variant == HBHEAP_VARIANT_VA_PAGE) return va_rebuild(d, h->trim_totals, h->trim_owned, stream);
+    if (HBHEAP_VARIANT_IS_VA(d.variant)) return va_rebuild(d, h->trim_totals, h->trim_owned, stream);
     return HBHEAP_OK;
 }
 

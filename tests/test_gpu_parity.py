@@ -21,7 +21,7 @@ from tests.hbtest import (check_blocks, check_snapshot, dev_i64, dev_u64, live_o
 pytestmark = pytest.mark.gpu
 
 KiB, MiB, GiB = 1 << 10, 1 << 20, 1 << 30
-VARIANTS = [0, 1, 2]
+VARIANTS = [0, 1, 2, 3]  # chunk, page, virtualised-array page, virtualised-array chunk
 
 
 @pytest.fixture(scope="module")
@@ -42,7 +42,7 @@ def _oracle_cap(nbytes, C, variant, k, shards):
     tot = 0
     for j in range(S):
         nj = min(N, (j + 1) << L) - (j << L)
-        if variant == 0:
+        if variant in (0, 3):
             cj = nj
         elif variant == 1:
             cj = min(nj, O.page_max_chunks(nbytes, C, k, S))
@@ -154,7 +154,7 @@ def test_sweep_small_exact_capacity(hb, variant, shards):
                 assert live_of(srep)[k] == min(n, cap)
                 if n >= cap:
                     assert srep.free_pages[k] == 0
-                    assert srep.free_chunks == 0 or variant != 0
+                    assert srep.free_chunks == 0 or variant not in (0, 3)
                 assert O.check_blocks_in_snapshot(snap, sizes, offs) == 0
                 heap.free(ptrs)
                 _, srep = check_snapshot(heap)
@@ -169,7 +169,7 @@ def test_sweep_small_exact_capacity(hb, variant, shards):
 # wave ends up taking from other shards and exactly the capacity succeeds
 # ---------------------------------------------------------------------------
 
-@pytest.mark.parametrize("variant", [0, 1])  # one-chunk shards leave a virtualised array no page budget
+@pytest.mark.parametrize("variant", [0, 1, 3])  # one-chunk shards leave the va page variant no page budget
 def test_steal_exact_capacity(hb, variant):
     nbytes, C, n = 64 * 8 * KiB, 8 * KiB, 1 << 14
     with hb.Heap(nbytes, C, variant=variant, shards=64) as heap:
@@ -203,7 +203,7 @@ def test_steal_exact_capacity(hb, variant):
 # ---------------------------------------------------------------------------
 
 @pytest.mark.parametrize("variant,shards,flags", [(0, 1, 0), (0, 0, 0), (1, 1, 0), (1, 0, 0), (1, 0, 2), (2, 1, 0),
-                                                  (2, 0, 0), (2, 0, 2)])
+                                                  (2, 0, 0), (2, 0, 2), (3, 1, 0), (3, 0, 0)])
 def test_churn_small(hb, variant, shards, flags):
     """flags 2: the page variant verifies every page it takes from a queue."""
     import torch

@@ -175,8 +175,9 @@ def test_serve_page_class_capacity_is_not_admitted(hb):
         assert heap.error() == 0
 
 
-def test_serve_refuses_virtualised_array_heap(hb):
-    with hb.Heap(8 * MiB, 8 * KiB, variant=hb.VARIANT_VA_PAGE) as heap:
+@pytest.mark.parametrize("variant", [2, 3])
+def test_serve_refuses_virtualised_array_heap(hb, variant):
+    with hb.Heap(8 * MiB, 8 * KiB, variant=variant) as heap:
         with pytest.raises(hb.HbHeapError) as e:
             hb.serve_create(heap.h, 2, 64, 1000, 0.95, 1, 1)
         assert e.value.code == hb.E_INVAL

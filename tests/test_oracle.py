@@ -305,10 +305,11 @@ def build_snapshot(N, log2C, variant, log2q, cls, cnt, bits, pool_bumps, pool_id
                    log2_span=None, va=None):
     """Write a version-3 snapshot from plain arrays.  rings[(j, k)] or
     rings[k] (shard 0) = (H, head, entries); pool_bumps: one per shard;
-    pool_ids: the whole id array.  Virtualised array (variant 2): va =
-    dict(g, ldir, lstore, M, budget, committed per shard); each queue's
-    segments are numbered from the shard's first, queue after queue, the
-    store holds the rest in ascending order."""
+    pool_ids: the whole id array.  Virtualised array (variants 2 and 3):
+    va = dict(g, ldir, lstore, M, budget, committed per shard); the slot
+    region is the shards' M segments of 2^g slots; each queue's segments are
+    numbered from the shard's first, queue after queue, the store holds the
+    rest in ascending order."""
     K = log2C - 3
     W = (1 << log2C) // 1024
     Q = 1 << log2q
@@ -326,7 +327,8 @@ def build_snapshot(N, log2C, variant, log2q, cls, cnt, bits, pool_bumps, pool_id
     off_bits = al(off_cnt + 4 * N)
     off_pid = al(off_bits + 8 * N * W)
     off_sl = al(off_pid + 4 * N)
-    total = al(off_sl + 4 * S * K * Q)
+    nslots = (S * va["M"]) << va["g"] if va else S * K * Q
+    total = al(off_sl + 4 * nslots)
     if va:
         g, ldir, lstore, M = va["g"], va["ldir"], va["lstore"], va["M"]
         off_vdir = total
@@ -653,3 +655,109 @@ def test_va_snapshot_clean_and_planted_faults():
     assert O.check_snapshot(bytes(x)).bad_ring_entry > 0
     # committed pages that do not match the classes' chunks
     assert O.check_snapshot(_va_state(lambda r, o, v: v.update(committed=[5]))).bad_committed > 0
+
+
+# ---------------------------------------------------------------------------
+# virtualised array chunk variant: segment count, sequential behaviour,
+# snapshots
+# ---------------------------------------------------------------------------
+
+def _max_segments_touched(span, G, K):
+    """Brute force: the most segments K queues of chunk ids can touch at
+    once when they hold at most span entries together (a chunk is listed in
+    at most one queue), over every split of the entries and every start
+    offset of each queue inside its first segment."""
+    f = [0] * (span + 1)   # most segments one queue of e entries touches
+    for e in range(1, span + 1):
+        f[e] = max(-(-(h + e) // G) - h // G for h in range(G))
+    best = [0] * (span + 1)   # best[t]: most segments with t entries so far
+    for _ in range(K):
+        nxt = best[:]
+        for t in range(span + 1):
+            for e in range(1, span - t + 1):
+                nxt[t + e] = max(nxt[t + e], best[t] + f[e])
+        best = nxt
+    return max(best)
+
+
+def test_va_chunk_segments_closed_form():
+    """M = ceil(span / 2^g) + 3K segments per shard, g = log2(span) - 3 in
+    [4, 10]: the queues' storage (brute-forced above) plus one segment per
+    queue on its way back to the store always fits."""
+    for span, G, K in [(4, 16, 9), (40, 16, 3), (64, 16, 2), (33, 16, 4), (100, 32, 3)]:
+        M = -(-span // G) + 3 * K
+        assert _max_segments_touched(span, G, K) + K <= M, (span, G, K)
+    for nbytes, C, shards in [(4 << 30, 8192, 0), (8 << 20, 8192, 1), (64 << 20, 16384, 4), (1 << 20, 4096, 0),
+                              (64 * 8192, 8192, 64)]:
+        N = nbytes // C
+        S, L = O.shard_geometry(N, shards)
+        g = min(10, max(4, L - 3))
+        K = O.num_classes(C)
+        assert O.va_chunk_log2_seg(nbytes, C, shards) == g
+        assert O.va_chunk_segments(nbytes, C, shards) == -(-(1 << L) // (1 << g)) + 3 * K
+
+
+@pytest.mark.parametrize("policy", [0, 1])
+def test_va_chunk_allocator_behaves_as_the_chunk_variant(policy):
+    """Storage in segments changes nothing a request sees: the same request
+    stream gets the same offsets and NULLs as the chunk variant."""
+    rng = np.random.default_rng(5)
+    nbytes, C = 8 << 20, 8192
+    a = O.OracleHeap(nbytes, C, O.VARIANT_CHUNK, policy=policy)
+    b = O.OracleHeap(nbytes, C, O.VARIANT_VA_CHUNK, policy=policy)
+    live = []
+    for _ in range(6):
+        sizes = inputs.sizes_log_uniform(3000, 4, 8192, int(rng.integers(1 << 30)))
+        oa, ob = a.alloc_batch(sizes), b.alloc_batch(sizes)
+        assert np.array_equal(oa, ob)
+        live += [o for o in oa if o >= 0]
+        rng.shuffle(live)
+        half, live = live[: len(live) // 2], live[len(live) // 2:]
+        fa = a.free_batch(np.array(half, dtype=np.int64))
+        fb = b.free_batch(np.array(half, dtype=np.int64))
+        assert np.array_equal(fa, fb)
+    assert a.accounting() == b.accounting()
+
+
+def _va_chunk_state(tamper=None):
+    # one shard, 4 chunks of 4 KiB (K = 9, W = 4): chunk 0 class 6 with pages
+    # 1 and 3 free (count 2), chunk 2 class 0 with page 5 free (count 1);
+    # span 4 -> segments of 16 entries, M = 1 + 27, directory 4, store 32
+    N, log2C, K = 4, 12, 9
+    cls = [6, 0xFF, 0, 0xFF]
+    cnt = [2, 0, 1, 0]
+    bits = [[0] * 4 for _ in range(N)]
+    bits[0][0] = (1 << 1) | (1 << 3)
+    bits[2][0] = 1 << 5
+    rings = {6: (0, 30, [0]), 0: (0, 15, [2])}
+    va = dict(g=4, ldir=2, lstore=5, M=28, budget=0, committed=[0])
+    if tamper:
+        tamper(rings, cnt, va)
+    return build_snapshot(N, log2C, 3, 2, cls, cnt, bits, [2], [0, 2, 1, 3], rings, va=va)
+
+
+def test_va_chunk_snapshot_clean_and_planted_faults():
+    rep = O.check_snapshot(_va_chunk_state())
+    assert rep.ok_header and not rep.violations(), rep.violations()
+    b = bytearray(_va_chunk_state())
+    off_vdir, off_vtk, off_vst, off_vss = struct.unpack_from("<QQQQ", b, 136)
+    # the class-6 queue (ring 6) at position 30: directory entry 30 >> 4 = 1
+    x = bytearray(b)
+    e = struct.unpack_from("<Q", x, off_vdir + 8 * ((6 << 2) + 1))[0]
+    struct.pack_into("<Q", x, off_vdir + 8 * ((6 << 2) + 1), e ^ 1)
+    assert O.check_snapshot(bytes(x)).violations()
+    # a listed chunk whose count disagrees with its free bits
+    assert O.check_snapshot(_va_chunk_state(lambda r, c, v: c.__setitem__(0, 3))).bad_count > 0
+    # a chunk with free pages missing from its queue
+    assert O.check_snapshot(_va_chunk_state(lambda r, c, v: r.update({0: (0, 15, [])}))).bad_ring_missing > 0
+    # chunk queues keep the committed-page counter at zero
+    assert O.check_snapshot(_va_chunk_state(lambda r, c, v: v.update(committed=[4]))).bad_committed > 0
+    # the store loses a free segment id
+    x = bytearray(b)
+    n = struct.unpack_from("<I", x, off_vst + 256)[0]
+    struct.pack_into("<I", x, off_vst + 256, n - 1)
+    struct.pack_into("<Q", x, off_vst, (n - 1) + 0x80000000)
+    struct.pack_into("<I", x, off_vss + 4 * (n - 1), 0xFFFFFFFF)
+    assert O.check_snapshot(bytes(x)).bad_vstore > 0
+    # a header whose segment count is not the closed form
+    assert not O.check_snapshot(_va_chunk_state(lambda r, c, v: v.update(M=27))).ok_header
