@@ -59,11 +59,11 @@ def parse():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--iters", type=int, default=10, help="alloc-write-check-free iterations per size")
-    ap.add_argument("--variant", choices=["chunk", "page", "va-page"], default="page")
+    ap.add_argument("--variant", choices=["chunk", "page", "va-page", "va-chunk"], default="page")
     ap.add_argument("--width", type=int, default=64)
     ap.add_argument("--shards", type=int, default=0, help="queue shards (0: one per 256 chunks, up to 64)")
     ap.add_argument("--no-other", action="store_true", help="skip the other queue variant")
-    ap.add_argument("--no-va", action="store_true", help="skip the virtualised-array page variant line")
+    ap.add_argument("--no-va", action="store_true", help="skip the virtualised-array variant lines")
     ap.add_argument("--no-ablation", action="store_true", help="skip the width-1 (no aggregation) ablation")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain device-malloc baseline")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
@@ -152,7 +152,8 @@ def main():
     from paper_2504_18211_amd import inputs
 
     hb.lib()  # fails loudly without the built library
-    VARIANTS = {"chunk": hb.VARIANT_CHUNK, "page": hb.VARIANT_PAGE, "va-page": hb.VARIANT_VA_PAGE}
+    VARIANTS = {"chunk": hb.VARIANT_CHUNK, "page": hb.VARIANT_PAGE, "va-page": hb.VARIANT_VA_PAGE,
+                "va-chunk": hb.VARIANT_VA_CHUNK}
     if not torch.cuda.is_available():
         log("no GPU visible")
         sys.exit(3)
@@ -381,10 +382,13 @@ def main():
         log(f"{other_name}: {other['value']/1e9:.2f} G ops/s (iterations 2..10)")
     # the page variant with its queues in virtualised arrays (one slot budget
     # per shard, shared by the classes in segments), one step
-    va = None
+    va = va_chunk = None
     if not args.no_va and args.variant != "va-page":
         va = run_sweep("va-page", 1, 1, count=False)
         log(f"va-page: {va['value']/1e9:.2f} G ops/s (iterations 2..10)")
+    if not args.no_va and args.variant != "va-chunk":
+        va_chunk = run_sweep("va-chunk", 1, 1, count=False)
+        log(f"va-chunk: {va_chunk['value']/1e9:.2f} G ops/s (iterations 2..10)")
 
     # ablation: the same sweep without wave aggregation (one queue operation
     # per lane), one step
@@ -496,6 +500,7 @@ def main():
         "per_size": head["per_size"],
         "other_variant": other,
         "va_variant": va,
+        "va_chunk_variant": va_chunk,
         "ablation_width1": ablation,
         "plain": plain,
         "vs_plain": (plain["ours_same_sizes"] / plain["value_full_size_sizes"])
@@ -547,7 +552,8 @@ def bench_paper_sweeps(hb, inputs, torch, args, ev, log):
 
     res = {"workload": "4 GiB heap, 8 KiB chunks; 10 x (alloc -> write -> check -> free) per point",
            "size_sweep_1024_allocs": {}, "thread_sweep_1000B": {}}
-    for vname, variant in (("chunk", hb.VARIANT_CHUNK), ("page", hb.VARIANT_PAGE), ("va-page", hb.VARIANT_VA_PAGE)):
+    for vname, variant in (("chunk", hb.VARIANT_CHUNK), ("page", hb.VARIANT_PAGE), ("va-page", hb.VARIANT_VA_PAGE),
+                           ("va-chunk", hb.VARIANT_VA_CHUNK)):
         with hb.Heap(w.heap_bytes, w.chunk_bytes, variant=variant) as heap:
             res["size_sweep_1024_allocs"][vname] = {
                 str(s_): point(heap, inputs.PAPER_ALLOCS, s_) for s_ in inputs.SWEEP_SIZES}
@@ -571,7 +577,7 @@ def bench_growth(hb, inputs, torch, args, ev, log):
     KiB = 1024
     d_cal = inputs.growth_doublings(agents, w.seed * 16 + 0xA)   # 0xC0F4A
     d_eval = inputs.growth_doublings(agents, w.seed * 16 + 0xB)  # 0xC0F4B
-    cands = [(c * KiB, v, wd) for c in (8, 16, 32, 64) for v in (0, 1, 2) for wd in (16, 32, 64)]
+    cands = [(c * KiB, v, wd) for c in (8, 16, 32, 64) for v in (0, 1, 2, 3) for wd in (16, 32, 64)]
     t0 = time.perf_counter()
     ms, best = hb.growth_autotune(w.heap_bytes, agents, torch.from_numpy(d_cal).to("cuda"), steps, w.seed, cands,
                                   reps=5)
@@ -631,9 +637,9 @@ def bench_growth(hb, inputs, torch, args, ev, log):
         "final_live_bytes": fb,
         "persistent_lanes": lanes,
         "autotune": {
-            "best": {"chunk_bytes": cands[best][0], "variant": "chunk" if cands[best][1] == 0 else "page",
+            "best": {"chunk_bytes": cands[best][0], "variant": ("chunk", "page", "va-page", "va-chunk")[cands[best][1]],
                      "width": cands[best][2]},
-            "calibration_ms": {f"{c // KiB}K/{'page' if v else 'chunk'}/w{wd}": round(t, 4)
+            "calibration_ms": {f"{c // KiB}K/{('chunk', 'page', 'va-page', 'va-chunk')[v]}/w{wd}": round(t, 4)
                                for (c, v, wd), t in zip(cands, ms)},
             "default": {"chunk_bytes": default[0], "variant": "page", "width": default[2]},
             "default_graph_ms": g_def,
