@@ -298,14 +298,20 @@ struct Ring {
     uint32_t* tail;
     uint32_t* slots;  /* plain rings: 2^log2q slots, position p at p & mask */
     uint32_t mask;
-    /* virtualised array rings (page variant in segments): the directory of
-     * this queue, the shard's segments and the shard; dir == nullptr for a
-     * plain ring */
+    /* segmented rings: the shard's segments (nullptr for a plain ring) and
+     * the shard; a virtualised array ring's directory (dmask), or a
+     * virtualised list ring's front and back words, the shard's segment
+     * tags and links, and the queue's index in the shard */
     uint64_t* dir;
     uint32_t* segs;
     uint32_t dmask;
     uint32_t log2g;
     uint32_t j;
+    uint64_t* front;
+    uint64_t* back;
+    uint64_t* vtag;
+    uint64_t* vnext;
+    uint32_t k;
 };
 
 constexpr uint64_t kDirEmpty = ~0ull;
@@ -324,13 +330,24 @@ __device__ __forceinline__ Ring ring_of(const hbheap_dev_t& h, uint32_t j, uint3
     r.head = (uint32_t*)(cb + 128);
     r.tail = (uint32_t*)(cb + 256);
     r.j = j;
-    if (HBHEAP_VARIANT_IS_VA(h.variant)) {
+    r.k = k;
+    r.front = r.back = r.vtag = r.vnext = nullptr;
+    if (HBHEAP_VARIANT_SEGMENTED(h.variant)) {
         r.slots = nullptr;
         r.mask = 0;
-        r.dir = h.vdir + (((uint64_t)j * h.n_classes + k) << h.log2_dir);
-        r.dmask = (1u << h.log2_dir) - 1u;
         r.segs = h.slots + (((uint64_t)j * h.vsegs) << h.log2_seg);
         r.log2g = h.log2_seg;
+        if (HBHEAP_VARIANT_IS_VA(h.variant)) {
+            r.dir = h.vdir + (((uint64_t)j * h.n_classes + k) << h.log2_dir);
+            r.dmask = (1u << h.log2_dir) - 1u;
+        } else {
+            r.dir = nullptr;
+            r.dmask = 0;
+            r.front = (uint64_t*)(cb + 392);
+            r.back = (uint64_t*)(cb + 400);
+            r.vtag = h.vdir + (uint64_t)j * h.vsegs;
+            r.vnext = h.vdir + (uint64_t)h.n_shards * h.vsegs + (uint64_t)j * h.vsegs;
+        }
     } else {
         r.slots = h.slots + (((uint64_t)j * h.n_classes + k) << h.log2q);
         r.mask = (1u << h.log2q) - 1u;
@@ -357,9 +374,11 @@ __device__ __forceinline__ Ring store_of(const hbheap_dev_t& h, uint32_t j)
     r.dmask = 0;
     r.log2g = 0;
     r.j = j;
+    r.k = 0;
+    r.front = r.back = r.vtag = r.vnext = nullptr;
     return r;
 }
-/* Pages the classes of shard j own together (virtualised array variant). */
+/* Pages the classes of shard j own together (segmented page variants). */
 __device__ __forceinline__ uint64_t* committed_of(const hbheap_dev_t& h, uint32_t j)
 {
     return (uint64_t*)(h.vstore + (uint64_t)j * kStoreBlock + 384);
@@ -479,15 +498,143 @@ __device__ __forceinline__ uint32_t* va_slot(const hbheap_dev_t& h, const Ring& 
     }
 }
 
+constexpr uint64_t kNoLink = ~0ull;
+
+__device__ __forceinline__ uint64_t a_xchg64(uint64_t* p, uint64_t v)
+{
+    return __hip_atomic_exchange(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+/* Virtualised list ring, at most once per wave and more as needed: unlink
+ * fully consumed segments from the front and return them to the store.  A
+ * front segment goes once every slot of it is consumed and a successor is
+ * linked (the back stays, for the next producer links from it); the
+ * compare-and-swap on the front word picks one retirer.  Whoever completes
+ * one of those conditions -- the closer that saw the last count, the
+ * installer that linked a successor, the retirer of the segment before --
+ * runs this loop after it, with reads that follow its own update (each
+ * update returns before the reads that depend on it are issued), so the
+ * last of them sees all conditions true. */
+__device__ __forceinline__ void vl_retire(const hbheap_dev_t& h, const Ring& r, uint32_t after, Tally& t)
+{
+    const uint32_t G = 1u << r.log2g;
+    uint32_t* taken = h.vtaken + (uint64_t)r.j * h.vsegs;
+    bool more = true;
+    for (uint32_t guard = 0; more && guard <= h.vsegs; ++guard) {
+        more = false;
+        const uint64_t f = a_load64(r.front + zero_after(after));
+        const uint32_t fm = (uint32_t)f;
+        const bool fm_ok = fm < h.vsegs;
+        const uint32_t c = fm_ok ? a_load32(taken + fm + zero_after((uint32_t)f)) : 0u;
+        const uint64_t nx = fm_ok && c == G ? a_load64(r.vnext + fm + zero_after(c)) : kNoLink;
+        if (!fm_ok || (nx != kNoLink && (uint32_t)nx >= h.vsegs)) raise_err(h, HBHEAP_ERR_CORRUPT, HBHEAP_STAT_TIMEOUTS);
+        if (fm_ok && c == G && nx != kNoLink && (uint32_t)nx < h.vsegs) {
+            uint64_t expect = f;
+            const bool won = __hip_atomic_compare_exchange_strong(
+                r.front + zero_after((uint32_t)nx), &expect, (((f >> 32) + 1ull) << 32) | (uint32_t)nx,
+                __ATOMIC_RELAXED, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            after = (uint32_t)expect;
+            if (won) {
+                t.spread += 1;
+                /* this retirer owns the segment: reset its count and link,
+                 * both performed before the store hands it out again */
+                const uint32_t was = a_xchg32(taken + fm, 0u);
+                const uint64_t lk = a_xchg64(r.vnext + fm, kNoLink);
+                store_put(h, r.j + zero_after(was ^ (uint32_t)lk), fm, t);
+                after = was;
+            }
+            more = true;
+        }
+    }
+}
+
+/* Per lane, virtualised list ring: the slot of position pos and its
+ * segment (number s = pos >> log2g).  A producer first reads the back: the
+ * back's own segment, or -- for the producer of a segment's first position,
+ * once the back is segment s-1 -- a new segment from the store, tagged
+ * (queue, s), linked after the back, which then moves to it.  Everyone else
+ * walks from the front along the links; a link is trusted only if the
+ * segment it was read from still carries the tag the walk expects after the
+ * read (a segment retired and handed out again carries another tag, since a
+ * queue's segment numbers only grow).  nullptr on timeout. */
+__device__ __forceinline__ uint32_t* vl_slot(const hbheap_dev_t& h, const Ring& r, uint32_t pos, bool producer,
+                                             uint32_t* seg_out, Tally& t)
+{
+    const uint32_t s = pos >> r.log2g;
+    const uint32_t off = pos & ((1u << r.log2g) - 1u);
+    const uint64_t qtag = (uint64_t)r.k << 32;
+    Backoff b;
+    for (;;) {
+        bool walk = true;
+        if (producer) {
+            const uint64_t bk = a_load64(r.back);
+            const uint32_t bs = (uint32_t)(bk >> 32), bm = (uint32_t)bk;
+            if (bm >= h.vsegs) {
+                raise_err(h, HBHEAP_ERR_CORRUPT, HBHEAP_STAT_TIMEOUTS);
+                return nullptr;
+            }
+            if (bs == s) {
+                *seg_out = bm;
+                return r.segs + ((uint64_t)bm << r.log2g) + off;
+            }
+            if (off == 0 && bs + 1u == s) {
+                const uint32_t m = store_take(h, r.j, t);
+                if (m == kEmpty) return nullptr;
+                if (m >= h.vsegs) {
+                    raise_err(h, HBHEAP_ERR_CORRUPT, HBHEAP_STAT_TIMEOUTS);
+                    return nullptr;
+                }
+                const uint64_t w1 = a_xchg64(r.vtag + m, qtag | s);
+                const uint64_t w2 = a_xchg64(r.vnext + m + zero_after((uint32_t)w1), kNoLink);
+                const uint64_t w3 = a_xchg64(r.vnext + bm + zero_after((uint32_t)w2), m);
+                uint64_t expect = bk;
+                const bool moved = __hip_atomic_compare_exchange_strong(
+                    r.back + zero_after((uint32_t)w3), &expect, ((uint64_t)s << 32) | m, __ATOMIC_RELAXED,
+                    __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                t.spread += 4;
+                if (!moved || w3 != kNoLink) raise_err(h, HBHEAP_ERR_CORRUPT, HBHEAP_STAT_TIMEOUTS);
+                vl_retire(h, r, (uint32_t)expect, t);
+                *seg_out = m;
+                return r.segs + ((uint64_t)m << r.log2g);
+            }
+            walk = (int32_t)(bs - s) > 0; /* a late producer of an older segment */
+        }
+        if (walk) {
+            const uint64_t f = a_load64(r.front);
+            uint32_t cs = (uint32_t)(f >> 32), cm = (uint32_t)f;
+            bool ok = (int32_t)(s - cs) >= 0 && cm < h.vsegs;
+            while (ok && cs != s) {
+                const uint64_t nx = a_load64(r.vnext + cm);
+                const uint64_t tg = a_load64(r.vtag + cm + zero_after((uint32_t)nx));
+                if (tg != (qtag | cs) || nx == kNoLink || (uint32_t)nx >= h.vsegs) {
+                    ok = false;
+                    break;
+                }
+                cm = (uint32_t)nx;
+                ++cs;
+            }
+            if (ok) {
+                *seg_out = cm;
+                return r.segs + ((uint64_t)cm << r.log2g) + off;
+            }
+        }
+        if (!b.wait(h)) {
+            raise_err(h, HBHEAP_ERR_TIMEOUT, HBHEAP_STAT_TIMEOUTS);
+            return nullptr;
+        }
+    }
+}
+
 /* Per lane: take the entry of ring position pos (wait while its producer is
- * late).  kEmpty on timeout.  Virtualised array rings: *seg receives the
- * position's segment id, and the caller counts the slot consumed with
- * va_count_taken() once the lanes of the wave have taken theirs. */
+ * late).  kEmpty on timeout.  Segmented rings: *seg receives the position's
+ * segment id, and the caller counts the slot consumed with
+ * seg_count_taken() once the lanes of the wave have taken theirs. */
 __device__ __forceinline__ uint32_t slot_take(const hbheap_dev_t& h, const Ring& r, uint32_t pos, uint32_t* seg,
                                               Tally& t)
 {
-    if (r.dir) {
-        uint32_t* s = va_slot(h, r, pos, false, seg, t);
+    if (r.segs) {
+        uint32_t* s = HBHEAP_VARIANT_IS_VL(h.variant) ? vl_slot(h, r, pos, false, seg, t)
+                                                      : va_slot(h, r, pos, false, seg, t);
         return s ? plain_take(h, s, t) : kEmpty;
     }
     return plain_take(h, r.slots + (pos & r.mask), t);
@@ -498,18 +645,19 @@ __device__ __forceinline__ uint32_t slot_take(const hbheap_dev_t& h, const Ring&
     return slot_take(h, r, pos, &seg, t);
 }
 
-/* Virtualised array rings, wave-wide: the lanes with `took` consumed ring
- * position pos of segment seg of ring r.  Runs of adjacent lanes on one
- * segment (their positions rise with the lane) add their number to its
- * consumed count with one atomic.  The run holding the segment's last
- * position closes it: once the count shows every slot consumed, it empties
- * the directory entry and returns the segment to the store (each slot was
- * emptied by its consumer before that consumer was counted).  The closer's
- * wait is bounded by the other consumers of the segment, which reserved
- * their positions before it and wait on nothing it holds; so only the
- * closer needs the count back, and every other add returns nothing. */
-__device__ __forceinline__ void va_count_taken(const hbheap_dev_t& h, const Ring& r, bool took, uint32_t pos,
-                                               uint32_t seg, Tally& t)
+/* Segmented rings, wave-wide: the lanes with `took` consumed ring position
+ * pos of segment seg of ring r.  Runs of adjacent lanes on one segment
+ * (their positions rise with the lane) add their number to its consumed
+ * count with one atomic.  The run holding the segment's last position
+ * closes it once the count shows every slot consumed (each slot was emptied
+ * by its consumer before that consumer was counted): a virtualised array
+ * ring empties the directory entry and returns the segment to the store; a
+ * virtualised list ring unlinks fully consumed segments from its front.
+ * The closer's wait is bounded by the other consumers of the segment, which
+ * reserved their positions before it and wait on nothing it holds; so only
+ * the closer needs the count back, and every other add returns nothing. */
+__device__ __forceinline__ void seg_count_taken(const hbheap_dev_t& h, const Ring& r, bool took, uint32_t pos,
+                                                uint32_t seg, Tally& t)
 {
     const uint32_t me = lane();
     const Run run = run_combine(took, (uint64_t)r.j * h.vsegs + seg, 1ull << me, 64u);
@@ -530,6 +678,17 @@ __device__ __forceinline__ void va_count_taken(const hbheap_dev_t& h, const Ring
                 return;
             }
             c = a_load32(tk);
+            if (HBHEAP_VARIANT_IS_VL(h.variant) && c != G) {
+                /* a list segment may already be retired by someone else's
+                 * loop once its count was full: the retirer moved the front
+                 * past it before resetting the count this load saw */
+                const uint64_t f = a_load64(r.front + zero_after(c));
+                if ((int32_t)((uint32_t)(f >> 32) - (pos >> r.log2g)) > 0) return;
+            }
+        }
+        if (HBHEAP_VARIANT_IS_VL(h.variant)) {
+            vl_retire(h, r, c, t);
+            return;
         }
         /* reset the count and empty the directory entry, both performed
          * before the segment can be taken again: exchanges whose returned
@@ -571,9 +730,10 @@ __device__ __forceinline__ uint32_t plain_take(const hbheap_dev_t& h, uint32_t* 
  * the entry of the previous lap). */
 __device__ __forceinline__ bool slot_put(const hbheap_dev_t& h, const Ring& r, uint32_t pos, uint32_t v, Tally& t)
 {
-    if (r.dir) {
+    if (r.segs) {
         uint32_t seg = 0;
-        uint32_t* s = va_slot(h, r, pos, true, &seg, t);
+        uint32_t* s = HBHEAP_VARIANT_IS_VL(h.variant) ? vl_slot(h, r, pos, true, &seg, t)
+                                                      : va_slot(h, r, pos, true, &seg, t);
         return s ? plain_put(h, s, v, t) : false;
     }
     return plain_put(h, r.slots + (pos & r.mask), v, t);
@@ -747,7 +907,7 @@ __device__ __forceinline__ Group make_group(const hbheap_dev_t& h, uint32_t k, u
 __device__ __forceinline__ uint32_t owned_reserve(const hbheap_dev_t& h, uint32_t j, uint32_t k, uint32_t lppc, uint32_t m,
                                                   Tally& tl)
 {
-    if (h.variant == HBHEAP_VARIANT_VA_PAGE) {
+    if (HBHEAP_VARIANT_SHARED_PAGES(h.variant)) {
         /* the classes of a shard share one page budget: the store's segments
          * less a few per queue (positions span at most the pages a queue's
          * class owns, plus partial segments at both ends) */
@@ -786,7 +946,8 @@ __device__ __forceinline__ uint32_t owned_reserve(const hbheap_dev_t& h, uint32_
 __device__ __forceinline__ bool class_has_room(const hbheap_dev_t& h, uint32_t j, uint32_t k, uint32_t lppc)
 {
     if (h.variant == HBHEAP_VARIANT_PAGE) return a_load64(owned_of(h, j, k)) < page_max_chunks(h, lppc);
-    if (h.variant == HBHEAP_VARIANT_VA_PAGE) return a_load64(committed_of(h, j)) + (1ull << lppc) <= h.vbudget;
+    if (HBHEAP_VARIANT_SHARED_PAGES(h.variant))
+        return a_load64(committed_of(h, j)) + (1ull << lppc) <= h.vbudget;
     return true;
 }
 __device__ __forceinline__ bool shard_has_something(const hbheap_dev_t& h, uint32_t j, uint32_t k, uint32_t lppc)
@@ -893,7 +1054,7 @@ __device__ __forceinline__ void chunk_serve_shard(const hbheap_dev_t& h, const G
                 if (v <= 0) raise_err(h, HBHEAP_ERR_CORRUPT, HBHEAP_STAT_TIMEOUTS);
             }
         }
-        if (R.dir) va_count_taken(h, R, took_slot, h0 + g.arank, vseg, tl);
+        if (R.segs) seg_count_taken(h, R, took_slot, h0 + g.arank, vseg, tl);
         const uint32_t vc = v > 0 ? ((uint32_t)v < need ? (uint32_t)v : need) : 0u;
         uint32_t tot;
         const uint32_t pre = excl_scan<7>(vc, &tot);
@@ -1057,7 +1218,7 @@ __device__ __forceinline__ void page_serve_shard(const hbheap_dev_t& h, const Gr
                 took_page = true;
             }
         }
-        if (R.dir) va_count_taken(h, R, took_slot, mypos, vseg, tl);
+        if (R.segs) seg_count_taken(h, R, took_slot, mypos, vseg, tl);
         clear_bits_grouped(h, took_page, widx, bit, o, off, tl);
         need -= got;
         served += got;
@@ -1075,7 +1236,7 @@ __device__ __forceinline__ void page_serve_shard(const hbheap_dev_t& h, const Gr
                     if (gm < allow) {
                         /* the pool ran dry: give back what was not taken */
                         a_add64(owned_of(h, j, g.k), (uint64_t)0 - (uint64_t)(allow - gm));
-                        if (h.variant == HBHEAP_VARIANT_VA_PAGE)
+                        if (HBHEAP_VARIANT_SHARED_PAGES(h.variant))
                             a_add64(committed_of(h, j), (uint64_t)0 - ((uint64_t)(allow - gm) << g.lppc));
                         tl.pool += 1;
                     }
@@ -1313,7 +1474,7 @@ __device__ __forceinline__ void* malloc_wave(const hbheap_dev_t& h, uint64_t n, 
                 took = true;
             }
         }
-        if (h.variant == HBHEAP_VARIANT_VA_PAGE) va_count_taken(h, R, took_slot, h0 + gr, vseg, tl);
+        if (HBHEAP_VARIANT_SEGMENTED(h.variant)) seg_count_taken(h, R, took_slot, h0 + gr, vseg, tl);
         clear_bits_grouped(h, took, widx, bit, o, off, tl);
     }
     pend = __ballot(k >= 0 && gr >= done);

@@ -27,12 +27,21 @@ extern "C" {
 #define HBHEAP_VARIANT_PAGE     1u
 #define HBHEAP_VARIANT_VA_PAGE  2u
 #define HBHEAP_VARIANT_VA_CHUNK 3u
+#define HBHEAP_VARIANT_VL_PAGE  4u
+#define HBHEAP_VARIANT_VL_CHUNK 5u
 
-/* Queues in segmented storage (the virtualised array variants). */
+/* Virtualised array variants: a queue finds its segments in a directory. */
 #define HBHEAP_VARIANT_IS_VA(v) ((v) == HBHEAP_VARIANT_VA_PAGE || (v) == HBHEAP_VARIANT_VA_CHUNK)
+/* Virtualised list variants: a queue's segments form a linked list. */
+#define HBHEAP_VARIANT_IS_VL(v) ((v) == HBHEAP_VARIANT_VL_PAGE || (v) == HBHEAP_VARIANT_VL_CHUNK)
+/* Queues in segmented storage drawn from a per-shard store. */
+#define HBHEAP_VARIANT_SEGMENTED(v) (HBHEAP_VARIANT_IS_VA(v) || HBHEAP_VARIANT_IS_VL(v))
 /* Queues of chunk ids (a chunk is listed while it has free pages), as
  * opposed to queues of free pages. */
-#define HBHEAP_VARIANT_LISTS_CHUNKS(v) ((v) == HBHEAP_VARIANT_CHUNK || (v) == HBHEAP_VARIANT_VA_CHUNK)
+#define HBHEAP_VARIANT_LISTS_CHUNKS(v) \
+    ((v) == HBHEAP_VARIANT_CHUNK || (v) == HBHEAP_VARIANT_VA_CHUNK || (v) == HBHEAP_VARIANT_VL_CHUNK)
+/* Page queues in segmented storage: a shard's classes share one page budget. */
+#define HBHEAP_VARIANT_SHARED_PAGES(v) ((v) == HBHEAP_VARIANT_VA_PAGE || (v) == HBHEAP_VARIANT_VL_PAGE)
 
 /* Return codes of every host entry point. */
 #define HBHEAP_OK          0
@@ -100,14 +109,18 @@ typedef struct hbheap_dev {
     uint32_t  n_shards;        /* shards; shard j owns chunks
                                   [j << log2_span, (j+1) << log2_span)       */
     uint32_t  log2_span;
-    /* virtualised array page variant (all zero / NULL otherwise): the slot
-     * region holds, per shard, vsegs segments of 2^log2_seg slots; a class
-     * queue finds the segment of ring position p in its directory entry
-     * (p >> log2_seg) mod 2^log2_dir, a u64 (segment number << 32 | segment
-     * id), all ones when empty; free segment ids wait in the shard's store,
-     * a ring of 2^log2_store u32 with its own state/head/tail block (512 B;
-     * u64 pages the shard's classes own @384). */
-    uint64_t* vdir;            /* n_shards * n_classes * 2^log2_dir entries   */
+    /* segmented variants (all zero / NULL otherwise): the slot region
+     * holds, per shard, vsegs segments of 2^log2_seg slots; free segment ids
+     * wait in the shard's store, a ring of 2^log2_store u32 with its own
+     * state/head/tail block (512 B; u64 pages the shard's classes own @384).
+     * Virtualised array: a class queue finds the segment of ring position p
+     * in its directory entry (p >> log2_seg) mod 2^log2_dir, a u64 (segment
+     * number << 32 | segment id), all ones when empty.  Virtualised list:
+     * vdir holds, per segment, a u64 tag (queue index << 32 | segment
+     * number) and then, for all segments, a u64 link to the next segment id
+     * (all ones for none); each queue's class block keeps front and back
+     * words (segment number << 32 | id) at +392 and +400. */
+    uint64_t* vdir;            /* directories, or tags then links            */
     uint32_t* vtaken;          /* per segment: slots consumed so far          */
     uint8_t*  vstore;          /* n_shards store blocks of 512 bytes          */
     uint32_t* vstore_slots;    /* n_shards rings of 2^log2_store u32          */

@@ -290,9 +290,7 @@ static uint64_t shard_end(const orc_heap* h, uint32_t j)
 orc_heap* orc_create_ex(uint64_t bytes, uint64_t chunk_bytes, int variant, int policy, uint32_t shards)
 {
     if (!orc_geometry_ok(bytes, chunk_bytes)) return NULL;
-    if (variant != ORC_VARIANT_CHUNK && variant != ORC_VARIANT_PAGE && variant != ORC_VARIANT_VA_PAGE &&
-        variant != ORC_VARIANT_VA_CHUNK)
-        return NULL;
+    if (variant < ORC_VARIANT_CHUNK || variant > ORC_VARIANT_VL_CHUNK) return NULL;
     if (policy != ORC_POLICY_LOWEST && policy != ORC_POLICY_FIFO) return NULL;
     if (shards > 64 || (shards & (shards - 1))) return NULL;
     orc_heap* h = (orc_heap*)calloc(1, sizeof(orc_heap));
@@ -309,7 +307,7 @@ orc_heap* orc_create_ex(uint64_t bytes, uint64_t chunk_bytes, int variant, int p
     h->owned = (uint64_t*)calloc((uint64_t)h->S * h->K, 8);
     for (uint32_t k = 0; k < h->K; ++k)
         h->maxc[k] = variant == ORC_VARIANT_PAGE ? orc_page_max_chunks(bytes, chunk_bytes, k, h->S) : h->N;
-    if (variant == ORC_VARIANT_VA_PAGE) {
+    if (variant == ORC_VARIANT_VA_PAGE || variant == ORC_VARIANT_VL_PAGE) {
         h->va_budget = orc_va_budget(bytes, chunk_bytes, h->S);
         if (h->va_budget == 0) { free(h->cls); free(h->cnt); free(h->bits); free(h->owned); free(h); return NULL; }
     }
@@ -387,12 +385,18 @@ static void claim_fresh(orc_heap* h, uint64_t c, uint32_t k)
 
 /* Queues of chunk ids (the chunk variants; storage does not change the
  * sequential behaviour) rather than of free pages. */
-static int lists_chunks(int variant) { return variant == ORC_VARIANT_CHUNK || variant == ORC_VARIANT_VA_CHUNK; }
+static int lists_chunks(int variant)
+{
+    return variant == ORC_VARIANT_CHUNK || variant == ORC_VARIANT_VA_CHUNK || variant == ORC_VARIANT_VL_CHUNK;
+}
 static int is_va(int variant) { return variant == ORC_VARIANT_VA_PAGE || variant == ORC_VARIANT_VA_CHUNK; }
+static int is_vl(int variant) { return variant == ORC_VARIANT_VL_PAGE || variant == ORC_VARIANT_VL_CHUNK; }
+static int segmented(int variant) { return is_va(variant) || is_vl(variant); }
+static int shared_pages(int variant) { return variant == ORC_VARIANT_VA_PAGE || variant == ORC_VARIANT_VL_PAGE; }
 
 static int can_grow(const orc_heap* h, uint32_t j, uint32_t k)
 {
-    if (h->variant == ORC_VARIANT_VA_PAGE) {
+    if (shared_pages(h->variant)) {
         uint64_t pages = 0;
         for (uint32_t kk = 0; kk < h->K; ++kk) pages += h->owned[(uint64_t)j * h->K + kk] * ppc_of(h, kk);
         return pages + ppc_of(h, k) <= h->va_budget;
@@ -715,22 +719,24 @@ static int snap_open(const uint8_t* s, uint64_t len, snapview* v)
         ((uint64_t)(v->S - 1) << v->log2_span) >= v->N) return 0;
     v->pool = s + o_pool; v->classes = s + o_cl; v->cls = s + o_cls; v->cnt = s + o_cnt;
     v->bits = s + o_bits; v->pool_ids = s + o_pid; v->slots = s + o_sl;
-    if (v->variant > 3) return 0;
-    if (!is_va((int)v->variant) && o_sl + (((uint64_t)v->S * v->K) << v->log2q) * 4 > total) return 0;
-    if (is_va((int)v->variant)) {
+    if (v->variant > 5) return 0;
+    const int var = (int)v->variant;
+    if (!segmented(var) && o_sl + (((uint64_t)v->S * v->K) << v->log2q) * 4 > total) return 0;
+    if (segmented(var)) {
         v->g = rd32(s + 112); v->ldir = rd32(s + 116); v->lstore = rd32(s + 120); v->M = rd32(s + 124);
         v->budget = rd64(s + 128);
         uint64_t o_dir = rd64(s + 136), o_tk = rd64(s + 144), o_st = rd64(s + 152), o_ss = rd64(s + 160);
         if (v->g < 4 || v->g > 10 || v->ldir > 24 || v->lstore > 24 || v->M == 0 || (1ull << v->lstore) < v->M)
             return 0;
-        if (v->variant == 2 && (((uint64_t)v->M << v->g) > ((uint64_t)v->K << v->log2q) ||
-                                (1ull << v->ldir) < (uint64_t)v->M + 3))
-            return 0;
+        if (shared_pages(var) && ((uint64_t)v->M << v->g) > ((uint64_t)v->K << v->log2q)) return 0;
         /* chunk queues: a queue spans at most ceil(span / 2^g) + 2 segments */
         const uint64_t per_queue = ((1ull << v->log2_span) + (1ull << v->g) - 1) >> v->g;
-        if (v->variant == 3 && (v->M != per_queue + 3ull * v->K || (1ull << v->ldir) < per_queue + 3)) return 0;
+        if (lists_chunks(var) && v->M != per_queue + 3ull * v->K) return 0;
+        if (is_va(var) && (1ull << v->ldir) < (shared_pages(var) ? (uint64_t)v->M + 3 : per_queue + 3)) return 0;
+        if (is_vl(var) && v->ldir != 0) return 0;
         if (o_sl + (((uint64_t)v->S * v->M) << v->g) * 4 > total) return 0;
-        if (o_dir + (((uint64_t)v->S * v->K) << v->ldir) * 8 > total || o_tk + (uint64_t)v->S * v->M * 4 > total ||
+        const uint64_t dir_words = is_vl(var) ? 2ull * v->S * v->M : ((uint64_t)v->S * v->K) << v->ldir;
+        if (o_dir + dir_words * 8 > total || o_tk + (uint64_t)v->S * v->M * 4 > total ||
             o_st + (uint64_t)v->S * 512 > total || o_ss + ((uint64_t)v->S << v->lstore) * 4 > total)
             return 0;
         v->vdir = s + o_dir; v->vtaken = s + o_tk; v->vstore = s + o_st; v->vslots = s + o_ss;
@@ -738,12 +744,41 @@ static int snap_open(const uint8_t* s, uint64_t len, snapview* v)
     return 1;
 }
 
+/* Virtualised list: tag and link of segment m of shard j, and the segment
+ * holding number sg of queue (j, k), found by walking from the queue's
+ * front (UINT32_MAX when the walk breaks: wrong tag, missing link). */
+static uint64_t vl_tag(const snapview* v, uint32_t j, uint32_t m) { return rd64(v->vdir + ((uint64_t)j * v->M + m) * 8); }
+static uint64_t vl_link(const snapview* v, uint32_t j, uint32_t m)
+{
+    return rd64(v->vdir + ((uint64_t)v->S * v->M + (uint64_t)j * v->M + m) * 8);
+}
+static uint32_t vl_find(const snapview* v, uint32_t j, uint32_t k, uint32_t sg)
+{
+    const uint8_t* cb = v->classes + ((uint64_t)j * v->K + k) * 512;
+    const uint64_t f = rd64(cb + 392);
+    uint32_t cs = (uint32_t)(f >> 32), cm = (uint32_t)f;
+    for (uint32_t guard = 0; guard <= v->M; ++guard) {
+        if (cm >= v->M || vl_tag(v, j, cm) != (((uint64_t)k << 32) | cs)) return UINT32_MAX;
+        if (cs == sg) return cm;
+        const uint64_t nx = vl_link(v, j, cm);
+        if (nx == ~0ull) return UINT32_MAX;
+        cm = (uint32_t)nx;
+        ++cs;
+    }
+    return UINT32_MAX;
+}
+
 /* Entry of queue (j, k) at ring position pos, or SLOT_EMPTY when the
- * position's storage cannot be found (virtualised array: counted as a bad
- * directory by the caller's own checks). */
+ * position's storage cannot be found (segmented variants: counted as a bad
+ * directory or list by the caller's own checks). */
 static uint32_t sv_entry(const snapview* v, uint32_t j, uint32_t k, uint32_t pos)
 {
     const uint64_t ring = (uint64_t)j * v->K + k;
+    if (is_vl((int)v->variant)) {
+        const uint32_t m = vl_find(v, j, k, pos >> v->g);
+        if (m == UINT32_MAX) return SLOT_EMPTY;
+        return rd32(v->slots + ((((uint64_t)j * v->M + m) << v->g) + (pos & ((1u << v->g) - 1u))) * 4);
+    }
     if (!is_va((int)v->variant)) {
         const uint64_t Q = 1ull << v->log2q;
         return rd32(v->slots + ((ring << v->log2q) + (pos & (uint32_t)(Q - 1))) * 4);
@@ -849,6 +884,97 @@ static void check_va(const snapview* v, const uint64_t* chunks_sk, orc_snap_repo
     free(cons);
 }
 
+/* Virtualised list storage at quiescence, shard by shard:
+ *  - queue (j, k) is the chain of segments from its front word to its back
+ *    word: consecutive numbers, each tagged (k, number), linked one to the
+ *    next, the back with no link; every segment sits in at most one chain;
+ *  - the front is the segment of head, or -- head on a segment boundary --
+ *    the fully consumed segment before it when that is also the back (a
+ *    back stays linked for the next producer); the back is the segment of
+ *    the last position written (the front for a queue never written);
+ *  - the front's consumed count is its positions below head, every other
+ *    chained segment's and every free segment's zero; every slot that holds
+ *    no position in [head, tail) is empty;
+ *  - the store holds exactly the ids no chain uses, once each, with no hold;
+ *  - page queues: the pages the shard's classes own equal its committed
+ *    count, within the budget; chunk queues keep that count at zero. */
+static void check_vl(const snapview* v, const uint64_t* chunks_sk, orc_snap_report* rep)
+{
+    const uint64_t G = 1ull << v->g, QS = 1ull << v->lstore;
+    uint8_t* used = (uint8_t*)malloc(v->M);
+    uint8_t* mark = (uint8_t*)malloc(((uint64_t)v->M << v->g) ? ((uint64_t)v->M << v->g) : 1);
+    uint32_t* cons = (uint32_t*)malloc((uint64_t)v->M * 4);
+    for (uint32_t j = 0; j < v->S; ++j) {
+        memset(used, 0, v->M);
+        memset(mark, 0, (uint64_t)v->M << v->g);
+        memset(cons, 0, (uint64_t)v->M * 4);
+        uint64_t pages = 0;
+        for (uint32_t k = 0; k < v->K; ++k) {
+            const uint64_t ring = (uint64_t)j * v->K + k;
+            const uint8_t* cb = v->classes + ring * 512;
+            const uint32_t head = rd32(cb + 128), tail = rd32(cb + 256);
+            const uint64_t H = head, T = H + (uint32_t)(tail - head);
+            if (v->variant == ORC_VARIANT_VL_PAGE) pages += chunks_sk[ring] * ((1ull << v->log2C) >> (4 + k));
+            const uint64_t f = rd64(cb + 392), b = rd64(cb + 400);
+            const uint32_t fs = (uint32_t)(f >> 32), bs = (uint32_t)(b >> 32), bm = (uint32_t)b;
+            const uint32_t hs = (uint32_t)(H >> v->g);
+            const int front_ok = fs == hs || (fs + 1 == hs && (H & (G - 1)) == 0 && fs == bs);
+            const uint64_t last = T > 0 ? (T - 1) >> v->g : fs;
+            const int back_ok = bs == (last > fs ? last : fs);
+            if (!front_ok || !back_ok) rep->bad_vdir++;
+            /* walk the chain */
+            uint32_t cs = fs, cm = (uint32_t)f;
+            int ok = 0;
+            for (uint32_t guard = 0; guard <= v->M; ++guard) {
+                if (cm >= v->M || used[cm] || vl_tag(v, j, cm) != (((uint64_t)k << 32) | cs)) break;
+                used[cm] = 1;
+                const uint64_t s0 = (uint64_t)cs << v->g;
+                cons[cm] = cs == fs ? (uint32_t)(H > s0 ? (H < s0 + G ? H - s0 : G) : 0) : 0;
+                for (uint64_t p = s0 > H ? s0 : H; p < s0 + G && p < T; ++p) mark[((uint64_t)cm << v->g) + (p - s0)] = 1;
+                const uint64_t nx = vl_link(v, j, cm);
+                if (cs == bs) {
+                    ok = cm == bm && nx == ~0ull;
+                    break;
+                }
+                if (nx == ~0ull) break;
+                cm = (uint32_t)nx;
+                ++cs;
+            }
+            if (!ok) rep->bad_vdir++;
+        }
+        for (uint32_t m = 0; m < v->M; ++m) {
+            if (rd32(v->vtaken + ((uint64_t)j * v->M + m) * 4) != cons[m]) rep->bad_vtaken++;
+            for (uint64_t o = 0; o < G; ++o) {
+                const uint64_t si = ((uint64_t)m << v->g) + o;
+                if (!mark[si] && rd32(v->slots + (((uint64_t)j * v->M << v->g) + si) * 4) != SLOT_EMPTY)
+                    rep->bad_ring_entry++;
+            }
+        }
+        const uint8_t* sb = v->vstore + (uint64_t)j * 512;
+        const uint64_t st = rd64(sb);
+        const uint32_t sh = rd32(sb + 128), stl = rd32(sb + 256);
+        const uint32_t n = stl - sh;
+        if ((uint32_t)(st >> 32) != 0 || (int64_t)(uint32_t)st - (int64_t)0x80000000u != (int64_t)n || n > QS) {
+            rep->bad_vstore++;
+        } else {
+            const uint8_t* ss = v->vslots + ((uint64_t)j << v->lstore) * 4;
+            for (uint32_t i = 0; i < QS; ++i) {
+                const uint32_t id = rd32(ss + (uint64_t)((sh + i) & (uint32_t)(QS - 1)) * 4);
+                if (i >= n) { if (id != SLOT_EMPTY) rep->bad_vstore++; continue; }
+                if (id >= v->M || used[id]) { rep->bad_vstore++; continue; }
+                used[id] = 2;
+            }
+            for (uint32_t m = 0; m < v->M; ++m)
+                if (!used[m]) rep->bad_vstore++; /* a segment neither in a chain nor in the store */
+        }
+        const uint64_t committed = rd64(sb + 384);
+        if (committed != pages || (v->variant == ORC_VARIANT_VL_PAGE && committed > v->budget)) rep->bad_committed++;
+    }
+    free(used);
+    free(mark);
+    free(cons);
+}
+
 int orc_check_snapshot(const uint8_t* snap, uint64_t len, orc_snap_report* rep)
 {
     memset(rep, 0, sizeof(*rep));
@@ -920,12 +1046,12 @@ int orc_check_snapshot(const uint8_t* snap, uint64_t len, orc_snap_report* rep)
             uint32_t H = (uint32_t)(state >> 32);
             int64_t Cnt = (int64_t)(uint32_t)state - (int64_t)0x80000000u;
             uint32_t used = tail - head;
-            const uint64_t cap = is_va((int)v.variant) ? ((uint64_t)v.M << v.g) : Q;
+            const uint64_t cap = segmented((int)v.variant) ? ((uint64_t)v.M << v.g) : Q;
             if (H != 0 || Cnt != (int64_t)used || used > cap) { rep->bad_ring_ctl++; continue; }
             if (!lists_chunks((int)v.variant) && owned != chunks_sk[ring]) rep->bad_owned++;
             if (lists_chunks((int)v.variant) && owned != 0) rep->bad_owned++;
             if (v.variant == 1 && chunks_sk[ring] > (Q >> (v.log2C - 4 - k))) rep->bad_owned++;
-            if (!is_va((int)v.variant)) {
+            if (!segmented((int)v.variant)) {
                 const uint8_t* sl = v.slots + (ring << v.log2q) * 4;
                 for (uint64_t i = used; i < Q; ++i) {
                     uint32_t e = rd32(sl + ((uint64_t)((head + (uint32_t)i) & (uint32_t)(Q - 1))) * 4);
@@ -969,6 +1095,7 @@ int orc_check_snapshot(const uint8_t* snap, uint64_t len, orc_snap_report* rep)
         }
     }
     if (is_va((int)v.variant)) check_va(&v, chunks_sk, rep);
+    if (is_vl((int)v.variant)) check_vl(&v, chunks_sk, rep);
     free(seen);
     free(chunks_sk);
     free(free_s);

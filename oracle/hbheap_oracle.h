@@ -38,7 +38,10 @@ extern "C" {
 
 #define ORC_MAX_CLASSES 16
 
-enum { ORC_VARIANT_CHUNK = 0, ORC_VARIANT_PAGE = 1, ORC_VARIANT_VA_PAGE = 2, ORC_VARIANT_VA_CHUNK = 3 };
+enum {
+    ORC_VARIANT_CHUNK = 0, ORC_VARIANT_PAGE = 1, ORC_VARIANT_VA_PAGE = 2, ORC_VARIANT_VA_CHUNK = 3,
+    ORC_VARIANT_VL_PAGE = 4, ORC_VARIANT_VL_CHUNK = 5
+};
 /* LOWEST: canonical legal outcome (lowest chunk id, then lowest page).
  * FIFO:   the order a single device thread observes (queue order). */
 enum { ORC_POLICY_LOWEST = 0, ORC_POLICY_FIFO = 1 };

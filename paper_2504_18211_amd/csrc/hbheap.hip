@@ -289,15 +289,20 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t* wsum)
 
 /* Pass 3: write pool ids and ring entries in ascending chunk (page) order,
  * for the keys of the shards this block's chunks belong to. */
-/* Virtualised array queues after a trim: queue (j, k) holds its entries at
- * positions 0 .. totals[j*K+k]-1 in segments numbered from the shard's
- * first, queue after queue: its first segment id is the number of segments
- * the shard's lower classes use. */
+/* Segmented queues after a trim (totals == nullptr: at creation, all
+ * empty): queue (j, k) holds its entries at positions 0 .. totals[j*K+k]-1
+ * in segments numbered from the shard's first, queue after queue.  A
+ * virtualised list queue always keeps one segment, even when empty. */
+__device__ __forceinline__ uint32_t seg_used(const hbheap_dev_t& h, const uint32_t* totals, uint32_t j, uint32_t k)
+{
+    const uint32_t g = 1u << h.log2_seg;
+    const uint32_t n = totals ? (totals[j * h.n_classes + k] + g - 1u) >> h.log2_seg : 0u;
+    return HBHEAP_VARIANT_IS_VL(h.variant) && n == 0 ? 1u : n;
+}
 __device__ __forceinline__ uint32_t va_first_seg(const hbheap_dev_t& h, const uint32_t* totals, uint32_t j, uint32_t k)
 {
     uint32_t base = 0;
-    const uint32_t g = 1u << h.log2_seg;
-    for (uint32_t kk = 0; kk < k; ++kk) base += (totals[j * h.n_classes + kk] + g - 1u) >> h.log2_seg;
+    for (uint32_t kk = 0; kk < k; ++kk) base += seg_used(h, totals, j, kk);
     return base;
 }
 
@@ -326,7 +331,7 @@ __global__ void __launch_bounds__(kTrimBlock) k_trim_write(hbheap_dev_t h, const
                 if (idx < h.n_chunks) h.pool_ids[idx] = (uint32_t)c;
             } else if (h.variant == HBHEAP_VARIANT_CHUNK) {
                 if (pos < Q) h.slots[(uint64_t)key * Q + pos] = (uint32_t)c;
-            } else if (h.variant == HBHEAP_VARIANT_VA_CHUNK) {
+            } else if (HBHEAP_VARIANT_SEGMENTED(h.variant) && HBHEAP_VARIANT_LISTS_CHUNKS(h.variant)) {
                 const uint64_t seg = va_first_seg(h, totals, j, kk) + (pos >> h.log2_seg);
                 if (seg < h.vsegs)
                     h.slots[(((uint64_t)j * h.vsegs + seg) << h.log2_seg) + (pos & ((1u << h.log2_seg) - 1u))] =
@@ -336,7 +341,7 @@ __global__ void __launch_bounds__(kTrimBlock) k_trim_write(hbheap_dev_t h, const
                 const uint32_t ppc = 1u << (h.log2_chunk - shift);
                 const uint32_t nw = ppc >= 64u ? ppc >> 6 : 1u;
                 uint32_t q = pos;
-                const bool va = h.variant == HBHEAP_VARIANT_VA_PAGE;
+                const bool va = HBHEAP_VARIANT_SEGMENTED(h.variant);
                 const uint32_t seg0 = va ? va_first_seg(h, totals, j, kk) : 0u;
                 for (uint32_t wd = 0; wd < nw; ++wd) {
                     uint64_t x = h.bits[c * h.words_per_chunk + wd];
@@ -387,32 +392,60 @@ __global__ void k_trim_ctl(hbheap_dev_t h, const uint32_t* totals, const uint32_
 __global__ void k_va_rebuild(hbheap_dev_t h, const uint32_t* totals, const uint32_t* owned)
 {
     const uint32_t S = h.n_shards, K = h.n_classes, M = h.vsegs;
-    const uint64_t D = 1ull << h.log2_dir, QS = 1ull << h.log2_store, g = 1ull << h.log2_seg;
-    const uint64_t n_dir = (uint64_t)S * K * D, n_taken = (uint64_t)S * M, n_store = (uint64_t)S * QS;
+    const uint64_t D = 1ull << h.log2_dir, QS = 1ull << h.log2_store;
+    const bool vl = HBHEAP_VARIANT_IS_VL(h.variant);
+    const uint64_t n_dir = vl ? (uint64_t)S * M : (uint64_t)S * K * D, n_taken = (uint64_t)S * M,
+                   n_store = (uint64_t)S * QS;
     const uint64_t n = n_dir > n_store ? (n_dir > n_taken ? n_dir : n_taken) : (n_store > n_taken ? n_store : n_taken);
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
-        if (i < n_dir) {
+        if (i < n_dir && !vl) {
             const uint64_t q = i >> h.log2_dir, dd = i & (D - 1);
             const uint32_t j = (uint32_t)(q / K), k = (uint32_t)(q % K);
-            const uint32_t used = totals ? (uint32_t)((totals[j * K + k] + g - 1) >> h.log2_seg) : 0u;
-            const uint32_t base = totals ? va_first_seg(h, totals, j, k) : 0u;
+            const uint32_t used = seg_used(h, totals, j, k);
+            const uint32_t base = va_first_seg(h, totals, j, k);
             h.vdir[i] = dd < used && base + dd < M ? ((dd << 32) | (uint64_t)(base + (uint32_t)dd)) : kDirEmpty;
+        }
+        if (i < n_dir && vl) {
+            /* segment m of shard j: tag (queue << 32 | number) and link to
+             * the next segment of its queue, or no tag and no link */
+            const uint32_t j = (uint32_t)(i / M), m = (uint32_t)(i % M);
+            uint64_t tag = ~0ull, next = kNoLink;
+            uint32_t base = 0;
+            for (uint32_t k = 0; k < K; ++k) {
+                const uint32_t used = seg_used(h, totals, j, k);
+                if (m < base + used) {
+                    tag = ((uint64_t)k << 32) | (m - base);
+                    next = m + 1u < base + used ? (uint64_t)(m + 1u) : kNoLink;
+                    break;
+                }
+                base += used;
+            }
+            h.vdir[i] = tag;
+            h.vdir[(uint64_t)S * M + i] = next;
+        }
+        if (vl && i < (uint64_t)S * K) {
+            /* queue front and back: its first and last segment */
+            const uint32_t j = (uint32_t)(i / K), k = (uint32_t)(i % K);
+            const uint32_t used = seg_used(h, totals, j, k), base = va_first_seg(h, totals, j, k);
+            uint8_t* cb = h.classes + i * kClassBlock;
+            *(uint64_t*)(cb + 392) = (uint64_t)base;
+            *(uint64_t*)(cb + 400) = ((uint64_t)(used - 1u) << 32) | (uint64_t)(base + used - 1u);
         }
         if (i < n_taken) h.vtaken[i] = 0;
         if (i < n_store) {
             const uint32_t j = (uint32_t)(i >> h.log2_store);
             const uint32_t p = (uint32_t)(i & (QS - 1));
-            const uint32_t used = totals ? va_first_seg(h, totals, j, K) : 0u;
+            const uint32_t used = va_first_seg(h, totals, j, K);
             const uint32_t free_n = used < M ? M - used : 0u;
             h.vstore_slots[i] = p < free_n ? used + p : kEmpty;
         }
         if (i < S) {
             const uint32_t j = (uint32_t)i;
-            const uint32_t used0 = totals ? va_first_seg(h, totals, j, K) : 0u;
+            const uint32_t used0 = va_first_seg(h, totals, j, K);
             const uint32_t used = used0 < M ? used0 : M;
             uint64_t pages = 0;
-            if (owned && h.variant == HBHEAP_VARIANT_VA_PAGE)
+            if (owned && HBHEAP_VARIANT_SHARED_PAGES(h.variant))
                 for (uint32_t k = 0; k < K; ++k) pages += (uint64_t)owned[j * K + k] << (h.log2_chunk - 4u - k);
             uint8_t* sb = h.vstore + (uint64_t)j * kStoreBlock;
             *(uint64_t*)sb = (uint64_t)(M - used) + kBias;
@@ -656,13 +689,13 @@ Layout make_layout(uint64_t N, uint32_t log2C, uint32_t K, uint32_t variant, uin
      * ceil(span / 2^g) + 2 of them. */
     uint32_t lg = L.log2q >= 3 ? L.log2q - 3 : 0;
     lg = lg < 4 ? 4 : (lg > 10 ? 10 : lg);
-    if (variant == HBHEAP_VARIANT_VA_PAGE) {
+    if (HBHEAP_VARIANT_SHARED_PAGES(variant)) {
         L.log2_seg = lg;
         L.vsegs = (uint32_t)(((uint64_t)K << L.log2q) >> lg);
         L.log2_dir = ceil_log2((uint64_t)L.vsegs + 3);
         L.log2_store = ceil_log2(L.vsegs);
         L.vbudget = L.vsegs > 3 * K ? (uint64_t)(L.vsegs - 3 * K) << lg : 0;
-    } else if (variant == HBHEAP_VARIANT_VA_CHUNK) {
+    } else if (HBHEAP_VARIANT_SEGMENTED(variant)) {
         const uint64_t per_queue = ((1ull << log2_span) + (1ull << lg) - 1) >> lg;
         L.log2_seg = lg;
         L.vsegs = (uint32_t)(per_queue + 3ull * K);
@@ -670,7 +703,10 @@ Layout make_layout(uint64_t N, uint32_t log2C, uint32_t K, uint32_t variant, uin
         L.log2_store = ceil_log2(L.vsegs);
         L.vbudget = 0;
     }
-    if (HBHEAP_VARIANT_IS_VA(variant)) L.n_slots = ((uint64_t)S * L.vsegs) << lg;
+    /* virtualised list: no directory (its section holds the segments' tags
+     * and links instead) */
+    if (HBHEAP_VARIANT_IS_VL(variant)) L.log2_dir = 0;
+    if (HBHEAP_VARIANT_SEGMENTED(variant)) L.n_slots = ((uint64_t)S * L.vsegs) << lg;
     L.off_pool = 256;
     L.off_cl = al256(L.off_pool + 128ull * S);
     L.off_cls = al256(L.off_cl + (uint64_t)kClassBlock * S * K);
@@ -679,9 +715,10 @@ Layout make_layout(uint64_t N, uint32_t log2C, uint32_t K, uint32_t variant, uin
     L.off_pid = al256(L.off_bits + 8 * N * W);
     L.off_sl = al256(L.off_pid + 4 * N);
     L.total = al256(L.off_sl + 4ull * L.n_slots);
-    if (HBHEAP_VARIANT_IS_VA(variant)) {
+    if (HBHEAP_VARIANT_SEGMENTED(variant)) {
         L.off_vdir = L.total;
-        L.off_vtaken = al256(L.off_vdir + 8ull * S * K * (1ull << L.log2_dir));
+        const uint64_t dir_words = HBHEAP_VARIANT_IS_VL(variant) ? 2ull * S * L.vsegs : (uint64_t)S * K << L.log2_dir;
+        L.off_vtaken = al256(L.off_vdir + 8ull * dir_words);
         L.off_vstore = al256(L.off_vtaken + 4ull * S * L.vsegs);
         L.off_vslots = al256(L.off_vstore + (uint64_t)kStoreBlock * S);
         L.total = al256(L.off_vslots + 4ull * S * (1ull << L.log2_store));
@@ -716,7 +753,9 @@ void launch_alloc_v(const hbheap_heap* h, const size_t* sizes, void** ptrs, size
     case HBHEAP_VARIANT_CHUNK: launch_alloc<C, HBHEAP_VARIANT_CHUNK>(h, sizes, ptrs, n, stream); break;
     case HBHEAP_VARIANT_PAGE: launch_alloc<C, HBHEAP_VARIANT_PAGE>(h, sizes, ptrs, n, stream); break;
     case HBHEAP_VARIANT_VA_PAGE: launch_alloc<C, HBHEAP_VARIANT_VA_PAGE>(h, sizes, ptrs, n, stream); break;
-    default: launch_alloc<C, HBHEAP_VARIANT_VA_CHUNK>(h, sizes, ptrs, n, stream); break;
+    case HBHEAP_VARIANT_VA_CHUNK: launch_alloc<C, HBHEAP_VARIANT_VA_CHUNK>(h, sizes, ptrs, n, stream); break;
+    case HBHEAP_VARIANT_VL_PAGE: launch_alloc<C, HBHEAP_VARIANT_VL_PAGE>(h, sizes, ptrs, n, stream); break;
+    default: launch_alloc<C, HBHEAP_VARIANT_VL_CHUNK>(h, sizes, ptrs, n, stream); break;
     }
 }
 template <bool C, uint32_t V>
@@ -734,7 +773,9 @@ void launch_free_v(const hbheap_heap* h, const size_t* sizes, void* const* ptrs,
     case HBHEAP_VARIANT_CHUNK: launch_free<C, HBHEAP_VARIANT_CHUNK>(h, sizes, ptrs, n, status, stream); break;
     case HBHEAP_VARIANT_PAGE: launch_free<C, HBHEAP_VARIANT_PAGE>(h, sizes, ptrs, n, status, stream); break;
     case HBHEAP_VARIANT_VA_PAGE: launch_free<C, HBHEAP_VARIANT_VA_PAGE>(h, sizes, ptrs, n, status, stream); break;
-    default: launch_free<C, HBHEAP_VARIANT_VA_CHUNK>(h, sizes, ptrs, n, status, stream); break;
+    case HBHEAP_VARIANT_VA_CHUNK: launch_free<C, HBHEAP_VARIANT_VA_CHUNK>(h, sizes, ptrs, n, status, stream); break;
+    case HBHEAP_VARIANT_VL_PAGE: launch_free<C, HBHEAP_VARIANT_VL_PAGE>(h, sizes, ptrs, n, status, stream); break;
+    default: launch_free<C, HBHEAP_VARIANT_VL_CHUNK>(h, sizes, ptrs, n, status, stream); break;
     }
 }
 }  // namespace
@@ -750,7 +791,7 @@ int heap_create_ex(size_t bytes, size_t chunk_bytes, const heap_config_t* cfg, h
     if (bytes < chunk_bytes) return HBHEAP_E_INVAL;
     heap_config_t c = {};
     if (cfg) c = *cfg;
-    if (c.variant > HBHEAP_VARIANT_VA_CHUNK) return HBHEAP_E_INVAL;
+    if (c.variant > HBHEAP_VARIANT_VL_CHUNK) return HBHEAP_E_INVAL;
     if (!c.width) c.width = 64;
     if (c.width > 64 || (c.width & (c.width - 1))) return HBHEAP_E_INVAL;
     if (!c.spin_cap) c.spin_cap = 1u << 18;
@@ -808,8 +849,8 @@ int heap_create_ex(size_t bytes, size_t chunk_bytes, const heap_config_t* cfg, h
     d.flags = c.flags;
     d.n_shards = S;
     d.log2_span = log2_span;
-    if (HBHEAP_VARIANT_IS_VA(c.variant)) {
-        if (c.variant == HBHEAP_VARIANT_VA_PAGE && L.vbudget == 0) { release(h); return HBHEAP_E_INVAL; }
+    if (HBHEAP_VARIANT_SEGMENTED(c.variant)) {
+        if (HBHEAP_VARIANT_SHARED_PAGES(c.variant) && L.vbudget == 0) { release(h); return HBHEAP_E_INVAL; }
         d.vdir = (uint64_t*)(st + L.off_vdir);
         d.vtaken = (uint32_t*)(st + L.off_vtaken);
         d.vstore = st + L.off_vstore;
@@ -878,7 +919,7 @@ int heap_create_ex(size_t bytes, size_t chunk_bytes, const heap_config_t* cfg, h
         if (hipGetLastError() != hipSuccess) rc = HBHEAP_E_HIP;
     }
     if (rc == HBHEAP_OK && hipMemcpyAsync(st, hb, head_bytes, hipMemcpyHostToDevice, s) != hipSuccess) rc = HBHEAP_E_HIP;
-    if (rc == HBHEAP_OK && HBHEAP_VARIANT_IS_VA(c.variant)) rc = va_rebuild(d, nullptr, nullptr, s);
+    if (rc == HBHEAP_OK && HBHEAP_VARIANT_SEGMENTED(c.variant)) rc = va_rebuild(d, nullptr, nullptr, s);
     if (rc == HBHEAP_OK && hipStreamSynchronize(s) != hipSuccess) rc = HBHEAP_E_HIP;
     free(hb);
     if (rc != HBHEAP_OK) { release(h); return rc; }
@@ -945,7 +986,7 @@ int heap_info(heap_t h, heap_info_t* out)
     out->n_chunks = h->dev.n_chunks;
     out->n_classes = h->dev.n_classes;
     out->variant = h->dev.variant;
-    out->ring_entries = h->dev.variant == HBHEAP_VARIANT_VA_PAGE ? h->lay.vbudget : 1ull << h->lay.log2q;
+    out->ring_entries = HBHEAP_VARIANT_SHARED_PAGES(h->dev.variant) ? h->lay.vbudget : 1ull << h->lay.log2q;
     out->n_shards = h->dev.n_shards;
     out->state_bytes = h->lay.total;
     out->metadata_bytes = h->lay.total + h->aux_bytes;
@@ -972,7 +1013,7 @@ int heap_trim(heap_t h, hipStream_t stream)
     HB_TRY(hipGetLastError());
     hipLaunchKernelGGL(k_trim_ctl, dim3(1), dim3(1024), 0, stream, d, h->trim_totals, h->trim_owned);
     HB_TRY(hipGetLastError());
-    if (HBHEAP_VARIANT_IS_VA(d.variant)) return va_rebuild(d, h->trim_totals, h->trim_owned, stream);
+    if (HBHEAP_VARIANT_SEGMENTED(d.variant)) return va_rebuild(d, h->trim_totals, h->trim_owned, stream);
     return HBHEAP_OK;
 }
 

@@ -297,7 +297,7 @@ int serve_create(heap_t h, const serve_config_t* cfg, server_t* out)
     s->heap = h;
     s->cfg = c;
     if (heap_device_handle(h, &s->dev) != HBHEAP_OK || heap_info(h, &s->info) != HBHEAP_OK ||
-        HBHEAP_VARIANT_IS_VA(s->info.variant)) {
+        HBHEAP_VARIANT_SEGMENTED(s->info.variant)) {
         delete s;
         return HBHEAP_E_INVAL;
     }

@@ -54,7 +54,7 @@ def test_create_rejects_bad_geometry(L, nbytes, chunk):
 
 def test_create_rejects_bad_config(L):
     out = C.c_void_p(0)
-    for cfg in [hb.HeapConfig(4, 64, 0, 0, 0), hb.HeapConfig(0, 48, 0, 0, 0), hb.HeapConfig(0, 128, 0, 0, 0)]:
+    for cfg in [hb.HeapConfig(6, 64, 0, 0, 0), hb.HeapConfig(0, 48, 0, 0, 0), hb.HeapConfig(0, 128, 0, 0, 0)]:
         assert L.heap_create_ex(1 << 20, 8192, C.byref(cfg), C.byref(out)) == hb.E_INVAL
     # page variant data region above 64 GiB
     assert L.heap_create_ex(65 << 30, 8192, C.byref(hb.HeapConfig(1, 64, 0, 0, 0)), C.byref(out)) == hb.E_INVAL

@@ -86,7 +86,8 @@ def check_state(hb, heap, gr, ref, seed, sample):
 
 @pytest.mark.parametrize("variant,width,chunk", [(0, 64, 8 * KiB), (1, 64, 8 * KiB), (0, 16, 16 * KiB),
                                                  (1, 1, 64 * KiB), (2, 64, 8 * KiB), (2, 32, 32 * KiB),
-                                                 (3, 64, 8 * KiB), (3, 16, 32 * KiB)])
+                                                 (3, 64, 8 * KiB), (3, 16, 32 * KiB), (4, 64, 8 * KiB),
+                                                 (4, 32, 32 * KiB), (5, 64, 8 * KiB), (5, 16, 32 * KiB)])
 def test_growth_steps_match_oracle(hb, variant, width, chunk):
     import torch
     nbytes, agents, steps, seed = 96 * MiB, 5000, 9, 0x51
@@ -141,7 +142,7 @@ def test_growth_graph_replays_match_eager(hb, variant):
         assert heap.error() == 0
 
 
-@pytest.mark.parametrize("variant", [0, 1, 2, 3])
+@pytest.mark.parametrize("variant", [0, 1, 2, 3, 4, 5])
 def test_growth_full_size(hb, variant):
     """2^18 agents on a 4 GiB heap, nine steps (16 B .. 4 KiB), checked after
     every step, then one graph replay checked again."""

@@ -21,7 +21,8 @@ from tests.hbtest import (check_blocks, check_snapshot, dev_i64, dev_u64, live_o
 pytestmark = pytest.mark.gpu
 
 KiB, MiB, GiB = 1 << 10, 1 << 20, 1 << 30
-VARIANTS = [0, 1, 2, 3]  # chunk, page, virtualised-array page, virtualised-array chunk
+# chunk, page, virtualised-array page and chunk, virtualised-list page and chunk
+VARIANTS = [0, 1, 2, 3, 4, 5]
 
 
 @pytest.fixture(scope="module")
@@ -42,7 +43,7 @@ def _oracle_cap(nbytes, C, variant, k, shards):
     tot = 0
     for j in range(S):
         nj = min(N, (j + 1) << L) - (j << L)
-        if variant in (0, 3):
+        if variant in (0, 3, 5):
             cj = nj
         elif variant == 1:
             cj = min(nj, O.page_max_chunks(nbytes, C, k, S))
@@ -154,7 +155,7 @@ def test_sweep_small_exact_capacity(hb, variant, shards):
                 assert live_of(srep)[k] == min(n, cap)
                 if n >= cap:
                     assert srep.free_pages[k] == 0
-                    assert srep.free_chunks == 0 or variant not in (0, 3)
+                    assert srep.free_chunks == 0 or variant not in (0, 3, 5)
                 assert O.check_blocks_in_snapshot(snap, sizes, offs) == 0
                 heap.free(ptrs)
                 _, srep = check_snapshot(heap)
@@ -169,7 +170,7 @@ def test_sweep_small_exact_capacity(hb, variant, shards):
 # wave ends up taking from other shards and exactly the capacity succeeds
 # ---------------------------------------------------------------------------
 
-@pytest.mark.parametrize("variant", [0, 1, 3])  # one-chunk shards leave the va page variant no page budget
+@pytest.mark.parametrize("variant", [0, 1, 3, 5])  # one-chunk shards leave segmented page variants no budget
 def test_steal_exact_capacity(hb, variant):
     nbytes, C, n = 64 * 8 * KiB, 8 * KiB, 1 << 14
     with hb.Heap(nbytes, C, variant=variant, shards=64) as heap:
@@ -203,7 +204,8 @@ def test_steal_exact_capacity(hb, variant):
 # ---------------------------------------------------------------------------
 
 @pytest.mark.parametrize("variant,shards,flags", [(0, 1, 0), (0, 0, 0), (1, 1, 0), (1, 0, 0), (1, 0, 2), (2, 1, 0),
-                                                  (2, 0, 0), (2, 0, 2), (3, 1, 0), (3, 0, 0)])
+                                                  (2, 0, 0), (2, 0, 2), (3, 1, 0), (3, 0, 0), (4, 1, 0), (4, 0, 0),
+                                                  (4, 0, 2), (5, 1, 0), (5, 0, 0)])
 def test_churn_small(hb, variant, shards, flags):
     """flags 2: the page variant verifies every page it takes from a queue."""
     import torch
@@ -456,9 +458,10 @@ def test_paper_sweeps(hb, variant):
 # variant's per-class queue allows)
 # ---------------------------------------------------------------------------
 
-def test_va_budget_and_shared_capacity(hb):
+@pytest.mark.parametrize("variant", [2, 4])
+def test_va_budget_and_shared_capacity(hb, variant):
     nbytes, C = 2 * MiB, 8 * KiB
-    with hb.Heap(nbytes, C, variant=hb.VARIANT_VA_PAGE, shards=1) as heap:
+    with hb.Heap(nbytes, C, variant=variant, shards=1) as heap:
         assert heap.info.ring_entries == O.va_budget(nbytes, C, 1)
         fresh = heap.snapshot()
         n = 1 << 17
@@ -467,7 +470,7 @@ def test_va_budget_and_shared_capacity(hb):
             sizes = inputs.sizes_fixed(n, size)
             sd, ptrs = dev_u64(sizes), zeros_i64(n)
             heap.alloc(sd, ptrs)
-            cap = _oracle_cap(nbytes, C, 2, O.class_of(size, C), 1)
+            cap = _oracle_cap(nbytes, C, variant, O.class_of(size, C), 1)
             rep = check_blocks(heap, sizes, offsets(ptrs, heap.base), allow_null=True)
             assert rep.n_nonnull == min(n, cap)
             if size == 16:

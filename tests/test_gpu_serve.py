@@ -175,7 +175,7 @@ def test_serve_page_class_capacity_is_not_admitted(hb):
         assert heap.error() == 0
 
 
-@pytest.mark.parametrize("variant", [2, 3])
+@pytest.mark.parametrize("variant", [2, 3, 4, 5])
 def test_serve_refuses_virtualised_array_heap(hb, variant):
     with hb.Heap(8 * MiB, 8 * KiB, variant=variant) as heap:
         with pytest.raises(hb.HbHeapError) as e:

@@ -329,10 +329,11 @@ def build_snapshot(N, log2C, variant, log2q, cls, cnt, bits, pool_bumps, pool_id
     off_sl = al(off_pid + 4 * N)
     nslots = (S * va["M"]) << va["g"] if va else S * K * Q
     total = al(off_sl + 4 * nslots)
+    vl = bool(va and va.get("vl"))
     if va:
         g, ldir, lstore, M = va["g"], va["ldir"], va["lstore"], va["M"]
         off_vdir = total
-        off_vtk = al(off_vdir + 8 * S * K * (1 << ldir))
+        off_vtk = al(off_vdir + 8 * (2 * S * M if vl else S * K * (1 << ldir)))
         off_vst = al(off_vtk + 4 * S * M)
         off_vss = al(off_vst + 512 * S)
         total = al(off_vss + 4 * S * (1 << lstore))
@@ -372,7 +373,7 @@ def build_snapshot(N, log2C, variant, log2q, cls, cnt, bits, pool_bumps, pool_id
         G, D, QS = 1 << g, 1 << ldir, 1 << lstore
         for i in range(S * M * G):
             struct.pack_into("<I", b, off_sl + 4 * i, 0xFFFFFFFF)
-        for i in range(S * K * D):
+        for i in range(2 * S * M if vl else S * K * D):
             struct.pack_into("<Q", b, off_vdir + 8 * i, (1 << 64) - 1)
         for j in range(S):
             nxt = 0
@@ -381,6 +382,23 @@ def build_snapshot(N, log2C, variant, log2q, cls, cnt, bits, pool_bumps, pool_id
                 H, head, ents = rings.get((j, k), (0, 0, []))
                 tail = head + len(ents)
                 sg = head >> g
+                if vl:
+                    # a chain from the front (head's segment) to the back (the
+                    # last written position's, the front if none)
+                    last = max(sg, (tail - 1) >> g) if tail > 0 else sg
+                    ids = list(range(nxt, nxt + last - sg + 1))
+                    nxt += len(ids)
+                    for i, m in enumerate(ids):
+                        sn = sg + i
+                        struct.pack_into("<Q", b, off_vdir + 8 * (j * M + m), (k << 32) | sn)
+                        struct.pack_into("<Q", b, off_vdir + 8 * (S * M + j * M + m),
+                                         ids[i + 1] if i + 1 < len(ids) else (1 << 64) - 1)
+                        s0 = sn << g
+                        struct.pack_into("<I", b, off_vtk + 4 * (j * M + m), max(0, min(head, s0 + G) - s0) if i == 0 else 0)
+                        for p_ in range(max(s0, head), min(s0 + G, tail)):
+                            struct.pack_into("<I", b, off_sl + 4 * (((j * M + m) << g) + (p_ - s0)), ents[p_ - head])
+                    struct.pack_into("<QQ", b, off_cl + 512 * r + 392, (sg << 32) | ids[0], (last << 32) | ids[-1])
+                    continue
                 while (sg << g) < tail:
                     m = nxt
                     nxt += 1
@@ -761,3 +779,96 @@ def test_va_chunk_snapshot_clean_and_planted_faults():
     assert O.check_snapshot(bytes(x)).bad_vstore > 0
     # a header whose segment count is not the closed form
     assert not O.check_snapshot(_va_chunk_state(lambda r, c, v: v.update(M=27))).ok_header
+
+
+# ---------------------------------------------------------------------------
+# virtualised list variants: sequential behaviour, snapshots
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("pair", [(O.VARIANT_VL_PAGE, O.VARIANT_VA_PAGE), (O.VARIANT_VL_CHUNK, O.VARIANT_CHUNK)])
+def test_vl_allocator_behaves_as_its_array_counterpart(pair):
+    """A list of segments instead of a directory changes nothing a request
+    sees: vl-page answers as va-page (same shared page budget), vl-chunk as
+    the chunk variant."""
+    rng = np.random.default_rng(9)
+    nbytes, C = 2 << 20, 8192
+    a, b = O.OracleHeap(nbytes, C, pair[0]), O.OracleHeap(nbytes, C, pair[1])
+    live = []
+    for _ in range(6):
+        sizes = inputs.sizes_log_uniform(1500, 4, 8192, int(rng.integers(1 << 30)))
+        oa, ob = a.alloc_batch(sizes), b.alloc_batch(sizes)
+        assert np.array_equal(oa, ob)
+        live += [o for o in oa if o >= 0]
+        rng.shuffle(live)
+        half, live = live[: len(live) // 2], live[len(live) // 2:]
+        assert np.array_equal(a.free_batch(np.array(half, dtype=np.int64)), b.free_batch(np.array(half, dtype=np.int64)))
+    assert a.accounting() == b.accounting()
+
+
+def _vl_state(variant, tamper=None):
+    # one shard, 4 chunks of 4 KiB (K = 9, W = 4): chunk 0 class 6 with pages
+    # 1 and 3 free, chunk 2 class 0 with page 5 free.  Page queues: the two
+    # free pages of class 6 from position 30 (a chain of segments 1 and 2,
+    # 16 entries each), one page of class 0 at position 15; chunk queues:
+    # chunk 0 at position 31, chunk 2 at position 16 (head on a boundary)
+    N, log2C, K = 4, 12, 9
+    cls = [6, 0xFF, 0, 0xFF]
+    cnt = [2, 0, 1, 0]
+    bits = [[0] * 4 for _ in range(N)]
+    bits[0][0] = (1 << 1) | (1 << 3)
+    bits[2][0] = 1 << 5
+    off = lambda c, k, p: ((c << log2C) + p * (16 << k)) >> 4
+    if variant == O.VARIANT_VL_PAGE:
+        rings = {6: (0, 31, [off(0, 6, 1), off(0, 6, 3)]), 0: (0, 15, [off(2, 0, 5)])}
+        owned = {6: 1, 0: 1}
+        va = dict(vl=True, g=4, ldir=0, lstore=6, M=64, budget=(64 - 27) << 4, committed=[4 + 256])
+        log2q = 7
+    else:
+        rings = {6: (0, 31, [0]), 0: (0, 16, [2])}
+        owned = {}
+        va = dict(vl=True, g=4, ldir=0, lstore=5, M=28, budget=0, committed=[0])
+        log2q = 2
+    if tamper:
+        tamper(rings, owned, va)
+    return build_snapshot(N, log2C, variant, log2q, cls, cnt, bits, [2], [0, 2, 1, 3], rings, owned=owned, va=va)
+
+
+@pytest.mark.parametrize("variant", [4, 5])
+def test_vl_snapshot_clean_and_planted_faults(variant):
+    rep = O.check_snapshot(_vl_state(variant))
+    assert rep.ok_header and not rep.violations(), rep.violations()
+    b = bytearray(_vl_state(variant))
+    off_vdir, off_vtk, off_vst, off_vss = struct.unpack_from("<QQQQ", b, 136)
+    off_cl = struct.unpack_from("<Q", b, 56)[0]
+    M = struct.unpack_from("<I", b, 124)[0]
+    # a broken link: the class-6 queue's first segment loses its successor
+    # (page variant: its chain spans segments 1 and 2)
+    x = bytearray(b)
+    f = struct.unpack_from("<Q", x, off_cl + 512 * 6 + 392)[0]
+    m0 = f & 0xFFFFFFFF
+    struct.pack_into("<Q", x, off_vdir + 8 * (M + m0), (1 << 64) - 1)
+    if variant == 4:
+        assert O.check_snapshot(bytes(x)).bad_vdir > 0
+    # a tag naming another queue
+    x = bytearray(b)
+    t = struct.unpack_from("<Q", x, off_vdir + 8 * m0)[0]
+    struct.pack_into("<Q", x, off_vdir + 8 * m0, t + (1 << 32))
+    assert O.check_snapshot(bytes(x)).bad_vdir > 0
+    # a front word ahead of head
+    x = bytearray(b)
+    struct.pack_into("<Q", x, off_cl + 512 * 6 + 392, f + (1 << 32))
+    assert O.check_snapshot(bytes(x)).violations()
+    # a consumed count off by one
+    x = bytearray(b)
+    v = struct.unpack_from("<I", x, off_vtk + 4 * m0)[0]
+    struct.pack_into("<I", x, off_vtk + 4 * m0, v + 1)
+    assert O.check_snapshot(bytes(x)).bad_vtaken > 0
+    # the store loses a free segment id
+    x = bytearray(b)
+    n = struct.unpack_from("<I", x, off_vst + 256)[0]
+    struct.pack_into("<I", x, off_vst + 256, n - 1)
+    struct.pack_into("<Q", x, off_vst, (n - 1) + 0x80000000)
+    struct.pack_into("<I", x, off_vss + 4 * (n - 1), 0xFFFFFFFF)
+    assert O.check_snapshot(bytes(x)).bad_vstore > 0
+    # committed pages that do not match the classes' chunks
+    assert O.check_snapshot(_vl_state(variant, lambda r, o, v: v.update(committed=[5]))).bad_committed > 0
