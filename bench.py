@@ -59,11 +59,12 @@ def parse():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--iters", type=int, default=10, help="alloc-write-check-free iterations per size")
-    ap.add_argument("--variant", choices=["chunk", "page", "va-page", "va-chunk"], default="page")
+    ap.add_argument("--variant", choices=["chunk", "page", "va-page", "va-chunk", "vl-page", "vl-chunk"],
+                    default="page")
     ap.add_argument("--width", type=int, default=64)
     ap.add_argument("--shards", type=int, default=0, help="queue shards (0: one per 256 chunks, up to 64)")
     ap.add_argument("--no-other", action="store_true", help="skip the other queue variant")
-    ap.add_argument("--no-va", action="store_true", help="skip the virtualised-array variant lines")
+    ap.add_argument("--no-va", action="store_true", help="skip the virtualised-array and -list variant lines")
     ap.add_argument("--no-ablation", action="store_true", help="skip the width-1 (no aggregation) ablation")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain device-malloc baseline")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
@@ -133,6 +134,9 @@ def hold_stream(torch, us: float = 1000.0):
     torch.cuda._sleep(int(us * _SLEEP_CYCLES_PER_US))
 
 
+VNAMES = ("chunk", "page", "va-page", "va-chunk", "vl-page", "vl-chunk")
+
+
 def pct(a, q):
     import numpy as np
     return float(np.percentile(np.asarray(a, dtype=float), q)) if len(a) else None
@@ -153,7 +157,7 @@ def main():
 
     hb.lib()  # fails loudly without the built library
     VARIANTS = {"chunk": hb.VARIANT_CHUNK, "page": hb.VARIANT_PAGE, "va-page": hb.VARIANT_VA_PAGE,
-                "va-chunk": hb.VARIANT_VA_CHUNK}
+                "va-chunk": hb.VARIANT_VA_CHUNK, "vl-page": hb.VARIANT_VL_PAGE, "vl-chunk": hb.VARIANT_VL_CHUNK}
     if not torch.cuda.is_available():
         log("no GPU visible")
         sys.exit(3)
@@ -382,13 +386,17 @@ def main():
         log(f"{other_name}: {other['value']/1e9:.2f} G ops/s (iterations 2..10)")
     # the page variant with its queues in virtualised arrays (one slot budget
     # per shard, shared by the classes in segments), one step
-    va = va_chunk = None
-    if not args.no_va and args.variant != "va-page":
-        va = run_sweep("va-page", 1, 1, count=False)
-        log(f"va-page: {va['value']/1e9:.2f} G ops/s (iterations 2..10)")
-    if not args.no_va and args.variant != "va-chunk":
-        va_chunk = run_sweep("va-chunk", 1, 1, count=False)
-        log(f"va-chunk: {va_chunk['value']/1e9:.2f} G ops/s (iterations 2..10)")
+    # the paper's virtualised variants: queues in segments drawn from a
+    # per-shard store, found through a directory (va) or a linked list (vl);
+    # one step each
+    virt = {}
+    if not args.no_va:
+        for name in ("va-page", "va-chunk", "vl-page", "vl-chunk"):
+            if name == args.variant:
+                continue
+            virt[name] = run_sweep(name, 1, 1, count=False)
+            log(f"{name}: {virt[name]['value']/1e9:.2f} G ops/s (iterations 2..10)")
+    va, va_chunk = virt.get("va-page"), virt.get("va-chunk")
 
     # ablation: the same sweep without wave aggregation (one queue operation
     # per lane), one step
@@ -501,6 +509,8 @@ def main():
         "other_variant": other,
         "va_variant": va,
         "va_chunk_variant": va_chunk,
+        "vl_variant": virt.get("vl-page"),
+        "vl_chunk_variant": virt.get("vl-chunk"),
         "ablation_width1": ablation,
         "plain": plain,
         "vs_plain": (plain["ours_same_sizes"] / plain["value_full_size_sizes"])
@@ -553,7 +563,8 @@ def bench_paper_sweeps(hb, inputs, torch, args, ev, log):
     res = {"workload": "4 GiB heap, 8 KiB chunks; 10 x (alloc -> write -> check -> free) per point",
            "size_sweep_1024_allocs": {}, "thread_sweep_1000B": {}}
     for vname, variant in (("chunk", hb.VARIANT_CHUNK), ("page", hb.VARIANT_PAGE), ("va-page", hb.VARIANT_VA_PAGE),
-                           ("va-chunk", hb.VARIANT_VA_CHUNK)):
+                           ("va-chunk", hb.VARIANT_VA_CHUNK), ("vl-page", hb.VARIANT_VL_PAGE),
+                           ("vl-chunk", hb.VARIANT_VL_CHUNK)):
         with hb.Heap(w.heap_bytes, w.chunk_bytes, variant=variant) as heap:
             res["size_sweep_1024_allocs"][vname] = {
                 str(s_): point(heap, inputs.PAPER_ALLOCS, s_) for s_ in inputs.SWEEP_SIZES}
@@ -577,7 +588,7 @@ def bench_growth(hb, inputs, torch, args, ev, log):
     KiB = 1024
     d_cal = inputs.growth_doublings(agents, w.seed * 16 + 0xA)   # 0xC0F4A
     d_eval = inputs.growth_doublings(agents, w.seed * 16 + 0xB)  # 0xC0F4B
-    cands = [(c * KiB, v, wd) for c in (8, 16, 32, 64) for v in (0, 1, 2, 3) for wd in (16, 32, 64)]
+    cands = [(c * KiB, v, wd) for c in (8, 16, 32, 64) for v in (0, 1, 2, 3, 4, 5) for wd in (16, 32, 64)]
     t0 = time.perf_counter()
     ms, best = hb.growth_autotune(w.heap_bytes, agents, torch.from_numpy(d_cal).to("cuda"), steps, w.seed, cands,
                                   reps=5)
@@ -637,9 +648,9 @@ def bench_growth(hb, inputs, torch, args, ev, log):
         "final_live_bytes": fb,
         "persistent_lanes": lanes,
         "autotune": {
-            "best": {"chunk_bytes": cands[best][0], "variant": ("chunk", "page", "va-page", "va-chunk")[cands[best][1]],
+            "best": {"chunk_bytes": cands[best][0], "variant": VNAMES[cands[best][1]],
                      "width": cands[best][2]},
-            "calibration_ms": {f"{c // KiB}K/{('chunk', 'page', 'va-page', 'va-chunk')[v]}/w{wd}": round(t, 4)
+            "calibration_ms": {f"{c // KiB}K/{VNAMES[v]}/w{wd}": round(t, 4)
                                for (c, v, wd), t in zip(cands, ms)},
             "default": {"chunk_bytes": default[0], "variant": "page", "width": default[2]},
             "default_graph_ms": g_def,
