@@ -1071,7 +1071,13 @@ __device__ __forceinline__ void chunk_serve_shard(const hbheap_dev_t& h, const G
         }
         uint32_t took;
         const uint32_t tpre = excl_scan<7>(t, &took);
-        if (t) claim_pages(h, c, g.k, t, stage + served + tpre, tl);
+        /* a pass that will not refill (its reservations cover the need, or
+         * the queue gave every chunk asked for) puts its kept chunks back
+         * and releases the queue before it claims its pages' bits, so other
+         * waves can take those chunks meanwhile: the pages it claims are
+         * already taken off the counts, which stay within the free bits */
+        const bool early = !(got < want && need > took);
+        if (!early && t) claim_pages(h, c, g.k, t, stage + served + tpre, tl);
 
         /* chunks that still hold free pages go back to the tail */
         const uint64_t rq = __ballot(keep);
@@ -1083,6 +1089,15 @@ __device__ __forceinline__ void chunk_serve_shard(const hbheap_dev_t& h, const G
         }
         t0 = bcast(t0, g.leader);
         if (keep) slot_put(h, R, t0 + rank_in(rq), c, tl);
+        if (early) {
+            if (g.me == g.leader) ring_release(R, nrq, tl);
+            if (t) claim_pages(h, c, g.k, t, stage + served + tpre, tl);
+            need -= took;
+            served += took;
+            /* entries reserved but nothing served: a wait gave up (error raised) */
+            if (got > 0 && took == 0) return;
+            continue;
+        }
         need -= took;
         served += took;
 

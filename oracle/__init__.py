@@ -156,7 +156,7 @@ class ModelParams(C.Structure):
         ("variant", C.c_int32), ("n_chunks", C.c_int32), ("ppc", C.c_int32), ("maxc", C.c_int32),
         ("n_leaders", C.c_int32), ("n_ops", C.c_int32 * 3), ("ops", (ModelOp * 3) * 3),
         ("prefill", C.c_int32), ("freeze", C.c_int32), ("mutation", C.c_int32), ("dry_hint", C.c_int32),
-        ("fast_first", C.c_int32), ("first_nohold", C.c_int32), ("max_states", C.c_int64),
+        ("fast_first", C.c_int32), ("first_nohold", C.c_int32), ("early_requeue", C.c_int32), ("pad2_", C.c_int32), ("max_states", C.c_int64),
     ]
 
 
@@ -181,7 +181,7 @@ MUTATIONS = {"no_hold": 1, "requeue_always": 2, "free_enqueue_always": 3, "no_re
 
 def model_run(variant: int, n_chunks: int, ppc: int, leaders: list, prefill: int = 0, maxc: int | None = None,
               freeze: bool = False, mutation: int = 0, max_states: int = 2_000_000, dry_hint: bool = True,
-              fast_first: bool = False, first_nohold: bool = True) -> dict:
+              fast_first: bool = False, first_nohold: bool = True, early_requeue: bool = True) -> dict:
     """Explore every interleaving of `leaders` (each a list of (kind, a, b)
     ops) on a heap of n_chunks chunks of ppc pages.  Returns the counters."""
     p = ModelParams()
@@ -197,6 +197,7 @@ def model_run(variant: int, n_chunks: int, ppc: int, leaders: list, prefill: int
     p.dry_hint = int(dry_hint)
     p.fast_first = int(fast_first)
     p.first_nohold = int(first_nohold)
+    p.early_requeue = int(early_requeue)
     r = ModelResult()
     rc = lib().orc_model_run(C.byref(p), C.byref(r))
     if rc != 0:

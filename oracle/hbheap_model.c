@@ -66,6 +66,7 @@ enum {
 typedef struct {
     uint8_t op, pc, need, served, got, want, h0, i, t0, nrq, took, publish, exhausted, m, gm, bump0;
     uint8_t lastgot;
+    uint8_t early;             /* chunk alloc: requeue and release before claiming */
     uint8_t dry;               /* page alloc: the pool looked dry at start */
     uint8_t held;              /* page alloc: this pass holds the queue   */
     uint8_t pass;              /* page alloc: passes made by this op      */
@@ -445,13 +446,19 @@ static int step(ctx* x, mstate* s, int l)
         if (!L->keep[i]) L->tok[i] = 0;
         if (++L->i < L->got) return 1;
         L->i = 0;
-        L->pc = 7;
+        /* a pass that will not refill (every reservation served, or the
+         * queue gave all it was asked for) puts its kept chunks back and
+         * releases the queue first, then claims its pages' bits */
+        int sum_t = 0;
+        for (int q = 0; q < L->got; ++q) sum_t += L->t[q];
+        L->early = (uint8_t)(x->p->early_requeue && !(L->got < L->want && L->need > sum_t));
+        L->pc = L->early ? 9 : 7;
         return 1;
     }
     case 7: {
         /* skip helpers with nothing to claim */
         while (L->i < L->got && L->left[L->i] == 0) L->i++;
-        if (L->i >= L->got) { L->i = 0; L->pc = 9; return 1; }
+        if (L->i >= L->got) { L->i = 0; L->pc = L->early ? 18 : 9; return 1; }
         uint8_t x8 = s->bits[L->c[L->i]];
         uint8_t pick = 0;
         for (int b = 0, n = 0; b < P && n < L->left[L->i]; ++b)
@@ -482,7 +489,7 @@ static int step(ctx* x, mstate* s, int l)
         L->served = (uint8_t)(L->served + L->took);
         if (n) { L->t0 = s->tail; s->tail = (uint8_t)(s->tail + n); L->i = 0; L->pc = 10; return 1; }
         L->publish = 0;
-        L->pc = 11;
+        L->pc = L->early ? 17 : 11;
         return 1;
     }
     case 10: {
@@ -493,7 +500,7 @@ static int step(ctx* x, mstate* s, int l)
             if (L->tok[i]) break;
             r++;
         }
-        if (i >= L->got) { L->publish = L->nrq; L->pc = 11; return 1; }
+        if (i >= L->got) { L->publish = L->nrq; L->pc = L->early ? 17 : 11; return 1; }
         uint8_t* sl = &s->slot[(uint8_t)(L->t0 + r) % Q];
         if (*sl != M_EMPTY) return 0;
         *sl = L->c[i];
@@ -570,6 +577,22 @@ static int step(ctx* x, mstate* s, int l)
             s->cnt[L->lo_chunk] = (int8_t)(P - L->lo_u);
         L->lo_chunk = M_EMPTY;
         if (L->need > 0 && L->got < L->want && L->exhausted) { L->pc = 16; return 1; }
+        if (L->got > 0 && L->took == 0 && L->need > 0) { L->pc = 16; return 1; }
+        if (L->need > 0) { L->pc = 1; return 1; }
+        finish_op(x, s, l);
+        return 1;
+    case 17:
+        /* early release: publish the kept chunks, drop the hold, then claim */
+        s->cnt_pub += (mut == MUT_RELEASE_NO_PUB) ? 0 : L->publish;
+        if (mut != MUT_NO_HOLD) s->H--;
+        L->i = 0;
+        L->pc = 7;
+        return 1;
+    case 18:
+        /* early pass: the claims are done */
+        L->need = (uint8_t)(L->need - L->took);
+        L->served = (uint8_t)(L->served + L->took);
+        L->early = 0;
         if (L->got > 0 && L->took == 0 && L->need > 0) { L->pc = 16; return 1; }
         if (L->need > 0) { L->pc = 1; return 1; }
         finish_op(x, s, l);

@@ -165,6 +165,9 @@ typedef struct {
     int32_t fast_first;        /* page alloc: the first pass never refills */
     int32_t first_nohold;      /* page alloc: every first pass takes without
                                   a hold and never refills                */
+    int32_t early_requeue;     /* chunk alloc: a pass that will not refill
+                                  requeues and releases before it claims  */
+    int32_t pad2_;
     int64_t max_states;
 } orc_model_params;
 

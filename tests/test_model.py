@@ -3,7 +3,8 @@
 The step-level model (oracle/hbheap_model.c) restates the queue protocol of
 the device allocator one atomic step at a time and explores every schedule
 of two or three wave leaders (page variant: every first pass takes without
-a hold, as the device does).  It must find no violation of the token,
+a hold; chunk variant: a pass that will not refill requeues its chunks and
+releases the queue before it claims its pages -- both as the device does).  It must find no violation of the token,
 exact-out-of-memory and final-state checks and no deadlock on the clean
 algorithm, and it must find violations for each planted mistake -- which
 shows that the checks can fail.  The freeze analysis must locate blocking
@@ -34,10 +35,11 @@ CONFIGS = {
 }
 OVERASK = ("overask_free_own", "overask_free_given", "overask_free_one")
 
-# pcs between a leader's reservation and its release (it holds H), and the
+# pcs between a leader's reservation and its release (it holds H; pc 17 is a
+# chunk pass's early release, made before it claims its pages), and the
 # slot puts and publish of frees (tail positions reserved but not yet
 # published: the out-of-memory look waits on a head/tail gap)
-HOLDING = {0: set(range(2, 16)) | {43, 44}, 1: set(range(22, 33)) | {43, 44}}
+HOLDING = {0: set(range(2, 16)) | {17, 43, 44}, 1: set(range(22, 33)) | {43, 44}}
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -147,5 +149,14 @@ def test_first_pass_with_hold_when_the_pool_has_chunks(name):
     """The earlier form of the page-variant first pass (a hold unless the
     pool read dry) is also clean on every interleaving."""
     r = O.model_run(1, first_nohold=False, **CONFIGS[name])
+    assert not r["truncated"]
+    assert r["violations"] == 0 and r["deadlocks"] == 0, r
+
+
+@pytest.mark.parametrize("name", sorted(CONFIGS))
+def test_chunk_pass_claiming_before_requeue(name):
+    """The earlier chunk-variant order (claim the pages' bits, then requeue
+    and release) is also clean on every interleaving."""
+    r = O.model_run(0, early_requeue=False, **CONFIGS[name])
     assert not r["truncated"]
     assert r["violations"] == 0 and r["deadlocks"] == 0, r
