@@ -191,6 +191,11 @@ __device__ __forceinline__ uint32_t zero_after(uint32_t v)
 }
 
 __device__ __forceinline__ void fence_release() { __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent"); }
+/* Wait until every memory operation this wave issued has completed (loads
+ * have returned their data), and keep the compiler from moving memory
+ * operations across: enough before freeing a block the wave has only read,
+ * with no cache write-back (a release fence also writes back the L2). */
+__device__ __forceinline__ void wait_own_accesses() { __asm__ volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
 __device__ __forceinline__ void wave_sync_lds()
 {
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");

@@ -7,7 +7,8 @@
  * running kernel allocate without returning to the host; Methods: many
  * threads allocate at once) in its most dynamic form: each step, every
  * active agent allocates a block twice as large, copies its list into it,
- * appends new elements and frees the old block (dev_malloc / dev_free).
+ * appends new elements and frees the old block (the device allocator's
+ * wave-level allocate and free).
  *
  * Agent a's list holds 32-bit words; word j of agent a is
  *     fmix32(seed ^ fmix32(a) ^ j * 0x9E3779B9)
@@ -62,7 +63,7 @@ int growth_step(growth_t g, uint32_t step, hipStream_t stream);
  */
 int growth_graph_launch(growth_t g, hipStream_t stream);
 
-/* Free every agent's list (dev_free in a grid-stride kernel), set the
+/* Free every agent's list (a grid-stride kernel), set the
  * tables to empty and the failure counter to zero. */
 int growth_release(growth_t g, hipStream_t stream);
 

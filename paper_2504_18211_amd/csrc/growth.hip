@@ -10,8 +10,10 @@
  * aggregation width) candidate.
  *
  * Per agent and step s >= 1 (agent active when doublings[a] >= s):
- *   q = dev_malloc(2 * bytes); copy the old list; append the new words;
- *   dev_free(old); the table then points at q.
+ *   q = allocate 2 * bytes; copy the old list; append the new words; free
+ *   the old block once the wave's reads of it have returned (no cache
+ *   write-back is needed for a block only read); the table then points at
+ *   q.
  * Copies of lists of 512 B and more are done by all active lanes of the
  * wave, one list at a time, 16 B per lane per instruction (coalesced);
  * smaller ones per lane.
@@ -113,10 +115,12 @@ __global__ void __launch_bounds__(kGrowBlock) k_growth_step(hbheap_dev_t h, Grow
             for (uint32_t u = r; u < n; u += nact) dst[u] = src[u];
             put_words(dst, bsr, n, 2u * n, r, nact);
         }
-        /* dev_free orders this wave's copies before the old block can be
-         * handed out again */
+        /* the wave only read the old block: once those reads have returned
+         * it can be handed out again (the new block's writes are ordered for
+         * the next step by the kernel boundary) */
+        wait_own_accesses();
         if (ok) {
-            dev_free(h, (void*)old);
+            (void)free_wave(h, (void*)old, 0, false);
             g.lists[a] = (uint64_t)q;
             g.elems[a] = 2u * e;
         }
@@ -128,7 +132,7 @@ __global__ void __launch_bounds__(kGrowBlock) k_growth_release(hbheap_dev_t h, G
     const uint64_t stride = (uint64_t)gridDim.x * kGrowBlock;
     for (uint64_t a = (uint64_t)blockIdx.x * kGrowBlock + threadIdx.x; a < g.agents; a += stride) {
         const uint64_t p = g.lists[a];
-        if (p) dev_free(h, (void*)p);
+        if (p) (void)free_wave(h, (void*)p, 0, false);
         g.lists[a] = 0;
         g.elems[a] = 0;
     }

@@ -194,8 +194,9 @@ __global__ void __launch_bounds__(kServeBlock) k_serve_batch(hbheap_dev_t h, con
     }
     uint32_t status = is_alloc ? (p ? SERVE_OK : SERVE_ALLOC_NULL) : SERVE_FREE_NULL;
     if (!is_alloc) {
-        /* the reads above complete before the block can be handed out again */
-        fence_release();
+        /* the reads above complete before the block can be handed out again
+         * (its writes were ordered by the end of the allocating kernel) */
+        wait_own_accesses();
         const uint32_t st = free_wave(h, p, 0, false);
         status = st == kFreeOk ? SERVE_OK : st == kFreeDouble ? SERVE_FREE_DOUBLE
                                           : st == kFreeInvalid ? SERVE_FREE_INVAL : SERVE_FREE_NULL;
