@@ -131,10 +131,14 @@ int heap_info(heap_t h, heap_info_t* out);
 int heap_trim(heap_t h, hipStream_t stream);
 
 /*
- * Copy the state region (layout version 1, documented in the design doc and in
- * the header of the snapshot itself) into host memory `dst` of `cap` bytes.
- * Synchronises `stream`.  *len receives the size (also when cap is too
- * small, which returns HBHEAP_E_RANGE).  dst may be NULL to query the size.
+ * Copy the state region into host memory `dst` of `cap` bytes.  Layout
+ * version 3: a 256-byte header (magic 0x48424850, version, geometry, the
+ * variant, and the byte offset of every section: pools, class blocks, class
+ * bytes, free counts, bitmask words, pool ids, queue slots, and for the
+ * segmented variants the directories or segment tags and links, consumed
+ * counts and segment stores), then the sections.  Synchronises `stream`.
+ * *len receives the size (also when cap is too small, which returns
+ * HBHEAP_E_RANGE).  dst may be NULL to query the size.
  */
 int heap_snapshot(heap_t h, void* dst, size_t cap, size_t* len, hipStream_t stream);
 
