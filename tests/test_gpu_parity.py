@@ -483,3 +483,39 @@ def test_va_budget_and_shared_capacity(hb, variant):
             heap.trim()
             assert heap.snapshot() == fresh
         assert heap.error() == 0
+
+
+def test_exhausted_class_beside_a_served_one(hb):
+    """Page variant, one launch: every wave asks for 16 B pages far beyond
+    that class's cap and for a few 4 KiB pages that fit.  Waves of a
+    workgroup share out-of-memory proofs per class: the 16 B requests get
+    exactly the cap, every 4 KiB request is served, and the NULLs counted
+    equal the 16 B requests over the cap."""
+    nbytes, C = 64 * MiB, 8 * KiB
+    n = 1 << 18
+    sizes = np.where(np.arange(n) % 32 == 31, 4096, 16).astype(np.uint64)
+    cap16 = _oracle_cap(nbytes, C, 1, 0, 0)
+    n16, n4k = int((sizes == 16).sum()), int((sizes == 4096).sum())
+    ref = O.OracleHeap(nbytes, C, 1)
+    roffs = ref.alloc_batch(sizes)
+    assert int(((roffs >= 0) & (sizes == 16)).sum()) == cap16 < n16
+    assert int(((roffs >= 0) & (sizes == 4096)).sum()) == n4k
+    with hb.Heap(nbytes, C, variant=hb.VARIANT_PAGE) as heap:
+        for it in range(2):
+            say(f"case mixed-exhaustion iter={it}")
+            sd, ptrs = dev_u64(sizes), zeros_i64(n)
+            oom0 = heap.stats()["oom"]
+            heap.alloc(sd, ptrs)
+            offs = offsets(ptrs, heap.base)
+            rep = check_blocks(heap, sizes, offs, allow_null=True)
+            assert rep.n_nonnull == cap16 + n4k
+            assert int(((offs >= 0) & (sizes == 4096)).sum()) == n4k
+            assert int(((offs >= 0) & (sizes == 16)).sum()) == cap16
+            assert heap.stats()["oom"] - oom0 == n16 - cap16
+            heap.pattern_write(ptrs, sd, 11)
+            assert heap.pattern_check(ptrs, sd, 11) == 0
+            _, srep = check_snapshot(heap)
+            assert live_of(srep)[0] == cap16 and live_of(srep)[8] == n4k
+            heap.free(ptrs)
+        heap.trim()
+        assert heap.error() == 0
