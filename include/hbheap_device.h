@@ -91,6 +91,12 @@ __device__ __forceinline__ uint64_t bcast64(uint64_t v, uint32_t l)
     return ((uint64_t)bcast((uint32_t)(v >> 32), l) << 32) | bcast((uint32_t)v, l);
 }
 __device__ __forceinline__ uint32_t ctz64(uint64_t m) { return (uint32_t)__builtin_ctzll(m); }
+/* The lane of rank r among the set lanes of m (r < popcount(m)). */
+__device__ __forceinline__ uint32_t lane_of_rank(uint64_t m, uint32_t r)
+{
+    for (uint32_t i = 0; i < r; ++i) m &= m - 1ull;
+    return ctz64(m);
+}
 
 /* Exclusive prefix sum over the active lanes, in lane order, of values below
  * 2^BITS, built from one ballot per bit: inactive lanes count as zero. */
@@ -165,6 +171,7 @@ __device__ __forceinline__ int32_t a_addi(int32_t* p, int32_t v) { return __hip_
 __device__ __forceinline__ uint64_t a_or64(uint64_t* p, uint64_t v) { return __hip_atomic_fetch_or(p, v, HBH_A(__ATOMIC_RELAXED)); }
 __device__ __forceinline__ uint64_t a_and64(uint64_t* p, uint64_t v) { return __hip_atomic_fetch_and(p, v, HBH_A(__ATOMIC_RELAXED)); }
 __device__ __forceinline__ uint32_t a_or32(uint32_t* p, uint32_t v) { return __hip_atomic_fetch_or(p, v, HBH_A(__ATOMIC_RELAXED)); }
+__device__ __forceinline__ uint32_t a_and32(uint32_t* p, uint32_t v) { return __hip_atomic_fetch_and(p, v, HBH_A(__ATOMIC_RELAXED)); }
 __device__ __forceinline__ uint32_t a_xchg32(uint32_t* p, uint32_t v) { return __hip_atomic_exchange(p, v, HBH_A(__ATOMIC_RELAXED)); }
 __device__ __forceinline__ bool a_cas32(uint32_t* p, uint32_t expect, uint32_t v)
 {
@@ -770,11 +777,143 @@ __device__ __forceinline__ bool plain_put(const hbheap_dev_t& h, uint32_t* s, ui
 /* Pool block of shard j (128 B): u64 bump, u32 size, u32 first pool index. */
 __device__ __forceinline__ uint64_t* pool_block(const hbheap_dev_t& h, uint32_t j) { return h.pool + 16ull * j; }
 
+/* ---------------- eager retirement (chunk variant) ----------------
+ *
+ * A chunk's free-page count shares one u64 with a token saying where the
+ * chunk is listed, so that a chunk whose pages are all free can leave its
+ * class at once, while allocators may be about to take it from its queue.
+ * The rules, each transition one atomic on that word:
+ * - a chunk with free pages has one token: listed (class, queue position)
+ *   or held (an allocator took it from its queue); a chunk with no free
+ *   page, or an unowned one, has none;
+ * - only the token's owner changes the token; frees only add to the count;
+ * - a free that finds no token and a zero count owns the chunk from then
+ *   on and lists it (or retires it if the free made it whole);
+ * - a free that makes the count whole while the chunk is listed retires it
+ *   with a compare-and-swap against that listing; if an allocator took it
+ *   meanwhile, the allocator finds it whole when it puts it back and
+ *   retires it then;
+ * - an allocator that takes an entry from a queue checks it against the
+ *   token: an entry whose chunk was retired since (or listed elsewhere)
+ *   is stale and is dropped.
+ * A retired chunk gets zero bits and the unowned class byte, then goes to
+ * the tail of its shard's pool ring, from which refills take chunks. */
+constexpr uint32_t kTokNone = 0xFFFFFFFFu, kTokHeld = 0xFFFFFFFEu;
+
+__device__ __forceinline__ bool eager(const hbheap_dev_t& h)
+{
+    return h.variant == HBHEAP_VARIANT_CHUNK && (h.flags & HBHEAP_FLAG_EAGER) != 0;
+}
+__host__ __device__ __forceinline__ uint32_t tok_listed(uint32_t k, uint32_t pos) { return (k << 28) | (pos & 0x0FFFFFFFu); }
+__host__ __device__ __forceinline__ uint64_t ct_word(uint32_t tok, uint32_t cnt) { return ((uint64_t)tok << 32) | cnt; }
+__device__ __forceinline__ bool a_cas64(uint64_t* p, uint64_t& expect, uint64_t v)
+{
+    return __hip_atomic_compare_exchange_strong(p, &expect, v, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                                __HIP_MEMORY_SCOPE_AGENT);
+}
+
+/* The pool ring of shard j (eager retirement): state, head and tail in the
+ * shard's pool block, slots in its run of pool ids. */
+__device__ __forceinline__ Ring pool_ring(const hbheap_dev_t& h, uint32_t j)
+{
+    uint64_t* pb = pool_block(h, j);
+    Ring r;
+    r.state = pb;
+    r.head = (uint32_t*)pb + 4;
+    r.tail = (uint32_t*)pb + 5;
+    r.slots = h.pool_ids + ((uint64_t)j << h.log2_span);
+    r.mask = (1u << h.log2_span) - 1u;
+    r.dir = nullptr;
+    r.segs = nullptr;
+    r.dmask = 0;
+    r.log2g = 0;
+    r.j = j;
+    r.k = 0;
+    r.front = r.back = r.vtag = r.vnext = nullptr;
+    return r;
+}
+
+/* Read a word by an atomic that changes nothing: its value is the one at
+ * the point where device atomics are performed, never an older copy a load
+ * could still find in this XCD's cache.  Used where a decision rests on
+ * seeing another wave's last atomic on the word.  The zero OR-ed in comes
+ * from zero_after, so the compiler cannot turn the atomic back into a load. */
+__device__ __forceinline__ uint64_t a_read64(uint64_t* p)
+{
+    return __hip_atomic_fetch_or(p, (uint64_t)zero_after(lane()), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint32_t a_read32(uint32_t* p)
+{
+    return __hip_atomic_fetch_or(p, zero_after(lane()), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+/* The class byte of chunk c (eager retirement changes it while kernels
+ * run, on any XCD). */
+__device__ __forceinline__ uint32_t class_coherent(const hbheap_dev_t& h, uint64_t c)
+{
+    const uint32_t w = a_read32((uint32_t*)(h.chunk_class + (c & ~3ull)));
+    return (w >> ((uint32_t)(c & 3u) * 8u)) & 0xFFu;
+}
+
+/* Per lane: chunk c, all of whose pages are free and which no token names
+ * any more, goes back to its shard's pool.  Its bits and class byte are
+ * reset by atomics, and the put that publishes it depends on their returned
+ * values, so any class that takes it finds them reset. */
+__device__ __forceinline__ void retire_chunk(const hbheap_dev_t& h, uint32_t c, Tally& t)
+{
+    uint64_t* words = h.bits + (uint64_t)c * h.words_per_chunk;
+    uint64_t acc = 0;
+    for (uint32_t w = 0; w < h.words_per_chunk; ++w) acc ^= a_xchg64(words + w, 0ull);
+    const uint32_t sh = (c & 3u) * 8u;
+    acc ^= a_or32((uint32_t*)(h.chunk_class + (c & ~3u)), 0xFFu << sh);
+    t.spread += h.words_per_chunk + 1u;
+    const Ring P = pool_ring(h, shard_of_chunk(h, c));
+    const uint32_t pos = a_add32(P.tail, 1u) + zero_after((uint32_t)acc ^ (uint32_t)(acc >> 32));
+    plain_put(h, P.slots + (pos & P.mask), c, t);
+    a_add64(P.state, 1ull);
+    t.pool += 2;
+    if (h.flags & HBHEAP_FLAG_STATS) a_add64(h.stats + HBHEAP_STAT_RETIRED, 1);
+}
+
+/* Per lane, by the owner of chunk c's token (a free that found none, or
+ * the allocator holding it): list the chunk at position pos of its class
+ * queue, or retire it if its pages are all free by now.  The caller then
+ * fills the slot either way (a retired chunk's entry is stale). */
+__device__ __forceinline__ void list_or_retire(const hbheap_dev_t& h, uint32_t c, uint32_t k, uint32_t ppc, uint32_t pos,
+                                               Tally& t)
+{
+    uint64_t* w = h.chunk_ct + c;
+    uint64_t v = a_load64(w);
+    for (;;) {
+        const uint32_t n = (uint32_t)v;
+        t.spread += 1;
+        if (n >= ppc) {
+            if (a_cas64(w, v, ct_word(kTokNone, 0))) {
+                retire_chunk(h, c, t);
+                return;
+            }
+        } else if (a_cas64(w, v, ct_word(tok_listed(k, pos), n))) {
+            return;
+        }
+        /* a concurrent free raised the count: look again */
+    }
+}
+
+
 /* Leader only: take up to m unowned chunks of shard j; *first receives the
  * index in pool_ids of the first one, the return value how many. */
 __device__ __forceinline__ uint32_t pool_take(const hbheap_dev_t& h, uint32_t j, uint32_t m, uint64_t* first, Tally& t)
 {
     uint64_t* pb = pool_block(h, j);
+    if (h.variant == HBHEAP_VARIANT_CHUNK && (h.flags & HBHEAP_FLAG_EAGER)) {
+        /* pool ring: *first is the ring position of the first entry taken;
+         * the lanes take the entries themselves (pool_entry) */
+        if (state_count(a_load64(pb)) <= 0) return 0;
+        const uint32_t got = ring_take_published(pool_ring(h, j), m, t);
+        if (got) *first = a_add32((uint32_t*)pb + 4, got);
+        t.pool += 1;
+        return got;
+    }
     const uint32_t size = ((const uint32_t*)pb)[2];
     const uint32_t start = ((const uint32_t*)pb)[3];
     if (a_load64(pb) >= size) return 0; /* exhausted: no need to move the bump */
@@ -787,6 +926,7 @@ __device__ __forceinline__ uint32_t pool_take(const hbheap_dev_t& h, uint32_t j,
 __device__ __forceinline__ bool pool_empty(const hbheap_dev_t& h, uint32_t j)
 {
     uint64_t* pb = pool_block(h, j);
+    if (h.variant == HBHEAP_VARIANT_CHUNK && (h.flags & HBHEAP_FLAG_EAGER)) return state_count(a_load64(pb)) <= 0;
     return a_load64(pb) >= ((const uint32_t*)pb)[2];
 }
 
@@ -990,7 +1130,7 @@ __device__ __forceinline__ uint32_t scan_shards(const hbheap_dev_t& h, const Gro
              * be read in any order: it only shrinks when the pool runs dry. */
             uint64_t* pb = pool_block(h, j);
             const uint64_t bump = a_load64(pb);
-            bool grow = bump < ((const uint32_t*)pb)[2];
+            bool grow = eager(h) ? state_count(bump) > 0 : bump < ((const uint32_t*)pb)[2];
             if (grow) grow = class_has_room(h, j, g.k, g.lppc);
             const Ring R = ring_of(h, j, g.k);
             const uint64_t st = a_load64(R.state + zero_after((uint32_t)bump));
@@ -1017,6 +1157,7 @@ __device__ __forceinline__ void chunk_serve_shard(const hbheap_dev_t& h, const G
                                                   uint32_t& served, uint64_t* stage, bool look_first, Tally& tl)
 {
     const Ring R = ring_of(h, j, g.k);
+    const bool ev = eager(h);
     /* look before reserving, except on a first pass the caller vouches for
      * (a home shard whose pool still had chunks, or a shard a scan just found
      * something in): there an empty queue costs only a hold taken and given
@@ -1046,7 +1187,7 @@ __device__ __forceinline__ void chunk_serve_shard(const hbheap_dev_t& h, const G
         const bool helper = g.arank < got;
         uint32_t c = kEmpty, vseg = 0;
         int32_t v = 0;
-        bool took_slot = false;
+        bool took_slot = false, stale = false;
         if (helper) {
             c = slot_take(h, R, h0 + g.arank, &vseg, tl);
             took_slot = c != kEmpty;
@@ -1054,11 +1195,37 @@ __device__ __forceinline__ void chunk_serve_shard(const hbheap_dev_t& h, const G
                 raise_err(h, HBHEAP_ERR_CORRUPT, HBHEAP_STAT_TIMEOUTS);
                 c = kEmpty;
             }
-            if (c != kEmpty) {
+            if (c != kEmpty && ev) {
+                /* take the chunk's token from its listing; an entry the token
+                 * does not name is stale: dropped.  A listing is matched by
+                 * its class and its position modulo the ring capacity: a
+                 * slow taker of position p - Q and the taker of p take from
+                 * the same slot and may get each other's entries, which
+                 * leaves each entry in the slot its position maps to.  Only
+                 * one taker can win the token, whichever copy it came by. */
+                uint64_t* w = h.chunk_ct + c;
+                uint64_t x = a_read64(w);
+                const uint32_t mine = tok_listed(g.k, h0 + g.arank);
+                for (;;) {
+                    const uint32_t tk = (uint32_t)(x >> 32);
+                    if (tk >= kTokHeld || (tk >> 28) != g.k || ((tk ^ mine) & R.mask) != 0) {
+                        stale = true;
+                        break;
+                    }
+                    tl.spread += 1;
+                    if (a_cas64(w, x, ct_word(kTokHeld, (uint32_t)x))) {
+                        v = (int32_t)(uint32_t)x;
+                        break;
+                    }
+                }
+                if (!stale && v <= 0) raise_err(h, HBHEAP_ERR_CORRUPT, HBHEAP_STAT_TIMEOUTS);
+            } else if (c != kEmpty) {
                 v = a_loadi(h.chunk_cnt + c);
                 if (v <= 0) raise_err(h, HBHEAP_ERR_CORRUPT, HBHEAP_STAT_TIMEOUTS);
             }
         }
+        /* stale entries dropped: progress even if nothing was served */
+        const bool dropped = ev && __ballot(stale) != 0;
         if (R.segs) seg_count_taken(h, R, took_slot, h0 + g.arank, vseg, tl);
         const uint32_t vc = v > 0 ? ((uint32_t)v < need ? (uint32_t)v : need) : 0u;
         uint32_t tot;
@@ -1067,7 +1234,11 @@ __device__ __forceinline__ void chunk_serve_shard(const hbheap_dev_t& h, const G
 
         bool keep = false;
         if (vc > 0) {
-            if (t) {
+            if (t && ev) {
+                /* the count never drops below t while the token is held */
+                keep = (uint32_t)a_add64(h.chunk_ct + c, (uint64_t)0 - t) > t;
+                tl.spread += 1;
+            } else if (t) {
                 keep = a_addi(h.chunk_cnt + c, -(int32_t)t) - (int32_t)t > 0;
                 tl.spread += 1;
             } else {
@@ -1093,14 +1264,33 @@ __device__ __forceinline__ void chunk_serve_shard(const hbheap_dev_t& h, const G
             tl.headtail += 1;
         }
         t0 = bcast(t0, g.leader);
-        if (keep) slot_put(h, R, t0 + rank_in(rq), c, tl);
+        if (keep) {
+            const uint32_t pos = t0 + rank_in(rq);
+            if (ev) list_or_retire(h, c, g.k, g.ppc, pos, tl);
+            slot_put(h, R, pos, c, tl);
+        }
+        if (ev && vc > 0 && !keep) {
+            /* every free page taken: give the token up -- unless frees came
+             * in while it was held, which left it to this lane to list the
+             * chunk again (or retire it) */
+            uint64_t x = ct_word(kTokHeld, 0);
+            tl.spread += 1;
+            if (!a_cas64(h.chunk_ct + c, x, ct_word(kTokNone, 0))) {
+                const uint32_t pos = a_add32(R.tail, 1u);
+                tl.headtail += 1;
+                list_or_retire(h, c, g.k, g.ppc, pos, tl);
+                slot_put(h, R, pos, c, tl);
+                a_add64(R.state, 1ull);
+                tl.state += 1;
+            }
+        }
         if (early) {
             if (g.me == g.leader) ring_release(R, nrq, tl);
             if (t) claim_pages(h, c, g.k, t, stage + served + tpre, tl);
             need -= took;
             served += took;
             /* entries reserved but nothing served: a wait gave up (error raised) */
-            if (got > 0 && took == 0) return;
+            if (got > 0 && took == 0 && !dropped) return;
             continue;
         }
         need -= took;
@@ -1120,10 +1310,34 @@ __device__ __forceinline__ void chunk_serve_shard(const hbheap_dev_t& h, const G
             gm = bcast(gm, g.leader);
             first = bcast64(first, g.leader);
             exhausted = gm < m;
-            if (g.arank < gm) h.chunk_class[h.pool_ids[first + g.arank]] = (uint8_t)g.k;
+            /* the chunk of rank q among those taken: a pool id (bump pool),
+             * or what lane q took from the pool ring */
+            uint32_t mine = kEmpty;
+            if (ev) {
+                const Ring P = pool_ring(h, j);
+                if (g.arank < gm) mine = plain_take(h, P.slots + (((uint32_t)first + g.arank) & P.mask), tl);
+                if (__ballot(g.arank < gm && mine == kEmpty)) { /* a wait gave up (error raised) */
+                    gm = 0;
+                    exhausted = true;
+                }
+                if (g.arank < gm) {
+                    const uint32_t sh = (mine & 3u) * 8u;
+                    a_and32((uint32_t*)(h.chunk_class + (mine & ~3u)), ~(0xFFu << sh) | (g.k << sh));
+                    tl.spread += 1;
+                }
+                wait_own_accesses();
+            } else if (g.arank < gm) {
+                h.chunk_class[h.pool_ids[first + g.arank]] = (uint8_t)g.k;
+            }
             const uint32_t cap = gm << g.lppc;
             const uint32_t r = cap < need ? cap : need;
-            if (g.arank < r) {
+            if (ev && gm) {
+                const uint32_t q = (g.arank >> g.lppc) < gm ? (g.arank >> g.lppc) : gm - 1u;
+                const uint32_t ci = perm32(mine, lane_of_rank(g.act, q));
+                if (g.arank < r)
+                    stage[served + g.arank] =
+                        ((uint64_t)ci << h.log2_chunk) + ((uint64_t)(g.arank & (g.ppc - 1u)) << g.shift);
+            } else if (g.arank < r) {
                 const uint32_t ci = h.pool_ids[first + (g.arank >> g.lppc)];
                 stage[served + g.arank] = ((uint64_t)ci << h.log2_chunk) + ((uint64_t)(g.arank & (g.ppc - 1u)) << g.shift);
             }
@@ -1131,15 +1345,21 @@ __device__ __forceinline__ void chunk_serve_shard(const hbheap_dev_t& h, const G
                 /* last chunk keeps pages [u, ppc): set their bits, publish it */
                 const uint32_t last = gm - 1u;
                 const uint32_t u = need - (last << g.lppc);
-                const uint32_t cl = h.pool_ids[first + last];
+                const uint32_t cl = ev ? perm32(mine, lane_of_rank(g.act, last)) : h.pool_ids[first + last];
                 const uint32_t nw = g.ppc >= 64u ? g.ppc >> 6 : 1u;
                 for (uint32_t w = g.arank; w < nw; w += g.nact)
                     h.bits[(uint64_t)cl * h.words_per_chunk + w] = free_mask_word(w, u, g.ppc);
-                if (g.me == g.leader) h.chunk_cnt[cl] = (int32_t)(g.ppc - u);
+                if (g.me == g.leader && !ev) h.chunk_cnt[cl] = (int32_t)(g.ppc - u);
                 fence_release();
                 if (g.me == g.leader) {
-                    const uint32_t pos = a_add32(R.tail, 1u);
+                    uint32_t pos = a_add32(R.tail, 1u);
                     tl.headtail += 1;
+                    if (ev) {
+                        /* listed at pos, with pages [u, ppc) free */
+                        const uint64_t was = a_xchg64(h.chunk_ct + cl, ct_word(tok_listed(g.k, pos), g.ppc - u));
+                        tl.spread += 1;
+                        pos += zero_after((uint32_t)was);
+                    }
                     slot_put(h, R, pos, cl, tl);
                 }
                 publish += 1u;
@@ -1150,7 +1370,7 @@ __device__ __forceinline__ void chunk_serve_shard(const hbheap_dev_t& h, const G
         if (g.me == g.leader) ring_release(R, publish, tl);
         if (need > 0 && got < want && exhausted) return;
         /* entries reserved but nothing served: a wait gave up (error raised) */
-        if (got > 0 && took == 0) return;
+        if (got > 0 && took == 0 && !dropped) return;
     }
 }
 
@@ -1418,6 +1638,7 @@ __device__ __forceinline__ uint64_t alloc_group(const hbheap_dev_t& h, uint32_t 
 __device__ __forceinline__ bool home_pool_dry(const hbheap_dev_t& h, uint32_t home)
 {
     const uint64_t* hp = pool_block(h, home);
+    if (eager(h)) return state_count(hp[0]) <= 0;
     return hp[0] >= ((const uint32_t*)hp)[2];
 }
 
@@ -1529,7 +1750,7 @@ __device__ __forceinline__ uint32_t free_wave(const hbheap_dev_t& h, void* p, ui
         o = (uint64_t)((uint8_t*)p - h.data);
         if ((uint8_t*)p >= h.data && o < h.data_bytes) {
             c = o >> h.log2_chunk;
-            k = h.chunk_class[c];
+            k = eager(h) ? class_coherent(h, c) : h.chunk_class[c];
             const uint32_t shift = 4u + k;
             bool ok = k < h.n_classes && (o & ((1ull << shift) - 1ull)) == 0;
             if (ok && check_size) ok = class_of(h, size_hint) == (int)k;
@@ -1557,7 +1778,27 @@ __device__ __forceinline__ uint32_t free_wave(const hbheap_dev_t& h, void* p, ui
         old = a_or64(h.bits + widx, run.incl);
         nnew = (uint32_t)__popcll(run.incl & ~old);
         tl.spread += 1;
-        if (HBHEAP_VARIANT_LISTS_CHUNKS(h.variant) && nnew) {
+        if (eager(h) && nnew) {
+            /* count and token in one word: a free that finds neither a token
+             * nor a free page owns the chunk (it lists it below, cold = 0);
+             * one that makes a listed chunk whole retires it, unless an
+             * allocator takes it first */
+            const uint32_t ppc = 1u << (h.log2_chunk - 4u - k);
+            const uint64_t ow = a_add64(h.chunk_ct + c, nnew);
+            const uint32_t otok = (uint32_t)(ow >> 32), n = (uint32_t)ow + nnew;
+            tl.spread += 1;
+            if (otok == kTokNone && (uint32_t)ow == 0) {
+                if (n >= ppc) {
+                    uint64_t x = ct_word(kTokNone, n);
+                    if (a_cas64(h.chunk_ct + c, x, ct_word(kTokNone, 0))) retire_chunk(h, (uint32_t)c, tl);
+                } else {
+                    cold = 0;
+                }
+            } else if (otok < kTokHeld && n >= ppc) {
+                uint64_t x = ct_word(otok, n);
+                if (a_cas64(h.chunk_ct + c, x, ct_word(kTokNone, 0))) retire_chunk(h, (uint32_t)c, tl);
+            }
+        } else if (HBHEAP_VARIANT_LISTS_CHUNKS(h.variant) && nnew) {
             cold = (uint32_t)a_addi(h.chunk_cnt + c, (int32_t)nnew);
             tl.spread += 1;
         }
@@ -1606,7 +1847,11 @@ __device__ __forceinline__ uint32_t free_wave(const hbheap_dev_t& h, void* p, ui
             tl.headtail += 1;
         }
         t0 = bcast(t0, leader);
-        if ((grp >> me) & 1ull) slot_put(h, R, t0 + rank_in(grp), val, tl);
+        if ((grp >> me) & 1ull) {
+            const uint32_t pos = t0 + rank_in(grp);
+            if (eager(h)) list_or_retire(h, val, k, 1u << (h.log2_chunk - 4u - k), pos, tl);
+            slot_put(h, R, pos, val, tl);
+        }
         if (me == leader) {
             a_add64(R.state, (uint64_t)n);
             tl.state += 1;
@@ -1617,6 +1862,7 @@ __device__ __forceinline__ uint32_t free_wave(const hbheap_dev_t& h, void* p, ui
         const Ring R = ring_of(h, key / h.n_classes, key % h.n_classes);
         const uint32_t t0 = a_add32(R.tail, 1u);
         tl.headtail += 1;
+        if (eager(h)) list_or_retire(h, val, k, 1u << (h.log2_chunk - 4u - k), t0, tl);
         slot_put(h, R, t0, val, tl);
         a_add64(R.state, 1ull);
         tl.state += 1;

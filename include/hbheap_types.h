@@ -75,6 +75,7 @@ extern "C" {
 #define HBHEAP_STAT_HEADTAIL_OPS  9
 #define HBHEAP_STAT_POOL_OPS      10
 #define HBHEAP_STAT_SPREAD_OPS    11
+#define HBHEAP_STAT_RETIRED       12  /* chunks retired eagerly (FLAG_STATS)     */
 #define HBHEAP_STAT_COUNT         16
 
 /*
@@ -129,6 +130,14 @@ typedef struct hbheap_dev {
     uint32_t  log2_store;
     uint32_t  vsegs;           /* segments per shard                         */
     uint64_t  vbudget;         /* pages the classes of one shard may own     */
+    /* eager retirement (chunk variant created with HBHEAP_FLAG_EAGER; NULL
+     * otherwise): per chunk a u64, free pages in the low half and, in the
+     * high half, where the chunk is listed: (class << 28 | queue position
+     * mod 2^28), held by an allocator (0xFFFFFFFE) or nowhere (0xFFFFFFFF).
+     * Each shard's pool is then a ring: u64 state (free chunks + 2^31) at
+     * +0, u32 head at +16, u32 tail at +20 of its pool block, and slots
+     * pool_ids[(j << log2_span) + (position mod 2^log2_span)]. */
+    uint64_t* chunk_ct;
 } hbheap_dev_t;
 
 /* Count refills, chunk grabs and atomics by target in the statistics
@@ -143,6 +152,10 @@ typedef struct hbheap_dev {
 /* Every wave starts at shard 0 instead of a shard of its XCD (used by the
  * single-lane replay, whose outcome is then deterministic). */
 #define HBHEAP_FLAG_HOME0 0x4u
+/* Chunk variant, fixed at creation (heap_create_ex): a chunk whose pages
+ * are all free again leaves its class at once and returns to its shard's
+ * pool, where any class can take it, instead of waiting for a trim. */
+#define HBHEAP_FLAG_EAGER 0x8u
 
 #ifdef __cplusplus
 }

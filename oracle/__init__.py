@@ -80,6 +80,7 @@ class SnapReport(C.Structure):
         ("bad_committed", C.c_uint64), ("free_chunks", C.c_uint64),
         ("live", C.c_uint64 * MAX_CLASSES), ("chunks", C.c_uint64 * MAX_CLASSES),
         ("free_pages", C.c_uint64 * MAX_CLASSES),
+        ("stale_entries", C.c_uint64), ("eager", C.c_uint32), ("pad", C.c_uint32),
     ]
 
     def violations(self) -> dict:
@@ -108,6 +109,7 @@ def lib():
             "orc_create": (vp, [u64, u64, C.c_int, C.c_int]),
             "orc_create_ex": (vp, [u64, u64, C.c_int, C.c_int, u32]),
             "orc_shards": (u32, [vp]),
+            "orc_set_eager": (C.c_int, [vp]),
             "orc_destroy": (None, [vp]),
             "orc_alloc": (i64, [vp, u64]),
             "orc_free": (C.c_int, [vp, i64]),
@@ -281,10 +283,14 @@ class OracleHeap:
     """Sequential allocator; offsets from the data base, -1 for NULL."""
 
     def __init__(self, nbytes: int, chunk_bytes: int, variant: int = VARIANT_CHUNK, policy: int = POLICY_LOWEST,
-                 shards: int = 1):
+                 shards: int = 1, eager: bool = False):
         self.h = lib().orc_create_ex(nbytes, chunk_bytes, variant, policy, shards)
         if not self.h:
             raise ValueError("invalid oracle geometry")
+        if eager and lib().orc_set_eager(self.h) != 0:
+            lib().orc_destroy(self.h)
+            self.h = None
+            raise ValueError("eager retirement needs the chunk variant")
         self.nbytes, self.chunk_bytes = nbytes, chunk_bytes
         self.n_chunks = nbytes // chunk_bytes
         self.variant, self.policy = variant, policy

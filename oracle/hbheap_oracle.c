@@ -249,6 +249,15 @@ static uint64_t fifo_pop(fifo* q)
     return v;
 }
 static void fifo_clear(fifo* q) { q->head = q->len = 0; }
+/* Drop the first occurrence of v, keeping the order of the rest. */
+static void fifo_remove(fifo* q, uint64_t v)
+{
+    uint64_t i = 0;
+    while (i < q->len && q->a[(q->head + i) % q->cap] != v) ++i;
+    if (i == q->len) return;
+    for (; i + 1 < q->len; ++i) q->a[(q->head + i) % q->cap] = q->a[(q->head + i + 1) % q->cap];
+    q->len--;
+}
 
 /* ------------------------------------------------------------------ */
 /* heap state                                                          */
@@ -276,6 +285,11 @@ struct orc_heap {
     uint64_t* pool_size;
     uint64_t* pool_next;
     fifo* q;
+    /* eager retirement (chunk variant): a chunk whose pages are all free
+     * leaves its class at once; FIFO policy: each shard's pool is then a
+     * queue, retired chunks joining it at the back */
+    int eager;
+    fifo* pq;
 };
 
 static uint64_t ppc_of(const orc_heap* h, uint32_t k) { return h->C >> (4 + k); }
@@ -348,7 +362,25 @@ void orc_destroy(orc_heap* h)
         for (uint64_t i = 0; i < (uint64_t)h->S * h->K; ++i) fifo_free(&h->q[i]);
         free(h->q);
     }
+    if (h->pq) {
+        for (uint32_t j = 0; j < h->S; ++j) fifo_free(&h->pq[j]);
+        free(h->pq);
+    }
     free(h->cls); free(h->cnt); free(h->bits); free(h->owned); free(h);
+}
+
+int orc_set_eager(orc_heap* h)
+{
+    if (h->variant != ORC_VARIANT_CHUNK || h->eager || h->acct.n_alloc_ok || h->acct.n_alloc_null) return -1;
+    h->eager = 1;
+    if (h->policy == ORC_POLICY_FIFO) {
+        h->pq = (fifo*)calloc(h->S, sizeof(fifo));
+        for (uint32_t j = 0; j < h->S; ++j) {
+            fifo_init(&h->pq[j]);
+            for (uint64_t c = shard_first(h, j); c < shard_end(h, j); ++c) fifo_push(&h->pq[j], c);
+        }
+    }
+    return 0;
 }
 
 static int bit_get(const orc_heap* h, uint64_t c, uint64_t p) { return (int)((h->bits[c * h->W + (p >> 6)] >> (p & 63)) & 1); }
@@ -451,8 +483,14 @@ static int64_t alloc_fifo(orc_heap* h, uint32_t k)
                 return (int64_t)off;
             }
         }
-        if (!can_grow(h, j, k) || h->pool_next[j] >= h->pool_size[j]) continue;
-        uint64_t c = h->pool[shard_first(h, j) + h->pool_next[j]++];
+        uint64_t c;
+        if (h->pq) {
+            if (!can_grow(h, j, k) || !h->pq[j].len) continue;
+            c = fifo_pop(&h->pq[j]);
+        } else {
+            if (!can_grow(h, j, k) || h->pool_next[j] >= h->pool_size[j]) continue;
+            c = h->pool[shard_first(h, j) + h->pool_next[j]++];
+        }
         claim_fresh(h, c, k);
         if (lists_chunks(h->variant)) {
             if (h->cnt[c] > 0) fifo_push(q, c);
@@ -473,6 +511,20 @@ int64_t orc_alloc(orc_heap* h, uint64_t n)
     return r;
 }
 
+/* Chunk c of class k, all of whose pages are free, becomes unowned (no
+ * bits, no count); the caller moves it between the structures of its
+ * policy. */
+static void unown(orc_heap* h, uint64_t c, uint32_t k)
+{
+    for (uint32_t w = 0; w < h->W; ++w) h->bits[c * h->W + w] = 0;
+    h->cnt[c] = 0;
+    h->cls[c] = FREE_CLASS;
+    h->owned[(uint64_t)shard_of(h, c) * h->K + k]--;
+    h->acct.chunks[k]--;
+    h->acct.free_pages[k] -= ppc_of(h, k);
+    h->acct.free_chunks++;
+}
+
 int orc_free(orc_heap* h, int64_t off)
 {
     if (off < 0) return ORC_FREE_NULL;
@@ -488,6 +540,19 @@ int orc_free(orc_heap* h, int64_t off)
     bit_set(h, c, p);
     uint32_t was = h->cnt[c]++;
     h->acct.free_pages[k]++; h->acct.live[k]--; h->acct.n_free_ok++;
+    if (h->eager && h->cnt[c] == ppc_of(h, k)) {
+        /* eager retirement: the chunk leaves its class (and its queue, if
+         * it was listed) and joins its shard's pool */
+        unown(h, c, k);
+        if (h->policy == ORC_POLICY_LOWEST) {
+            hset_clear(&h->avail[k], c);
+            hset_set(&h->free_set, c);
+        } else {
+            if (was > 0) fifo_remove(&h->q[(uint64_t)shard_of(h, c) * h->K + k], c);
+            fifo_push(&h->pq[shard_of(h, c)], c);
+        }
+        return ORC_FREE_OK;
+    }
     if (h->policy == ORC_POLICY_LOWEST) {
         if (was == 0) hset_set(&h->avail[k], c);
     } else {
@@ -509,13 +574,7 @@ void orc_trim(orc_heap* h)
         if (h->cls[c] == FREE_CLASS) continue;
         uint32_t k = h->cls[c];
         if (h->cnt[c] != ppc_of(h, k)) continue;
-        for (uint32_t w = 0; w < h->W; ++w) h->bits[c * h->W + w] = 0;
-        h->cnt[c] = 0;
-        h->cls[c] = FREE_CLASS;
-        h->owned[(uint64_t)shard_of(h, c) * h->K + k]--;
-        h->acct.chunks[k]--;
-        h->acct.free_pages[k] -= ppc_of(h, k);
-        h->acct.free_chunks++;
+        unown(h, c, k);
         if (h->policy == ORC_POLICY_LOWEST) {
             hset_clear(&h->avail[k], c);
             hset_set(&h->free_set, c);
@@ -524,8 +583,12 @@ void orc_trim(orc_heap* h)
     if (h->policy == ORC_POLICY_FIFO) {
         for (uint32_t j = 0; j < h->S; ++j) {
             h->pool_size[j] = 0; h->pool_next[j] = 0;
-            for (uint64_t c = shard_first(h, j); c < shard_end(h, j); ++c)
-                if (h->cls[c] == FREE_CLASS) h->pool[shard_first(h, j) + h->pool_size[j]++] = (uint32_t)c;
+            if (h->pq) fifo_clear(&h->pq[j]);
+            for (uint64_t c = shard_first(h, j); c < shard_end(h, j); ++c) {
+                if (h->cls[c] != FREE_CLASS) continue;
+                h->pool[shard_first(h, j) + h->pool_size[j]++] = (uint32_t)c;
+                if (h->pq) fifo_push(&h->pq[j], c);
+            }
         }
         for (uint64_t i = 0; i < (uint64_t)h->S * h->K; ++i) fifo_clear(&h->q[i]);
         for (uint64_t c = 0; c < h->N; ++c) {
@@ -702,6 +765,9 @@ typedef struct {
     uint32_t g, ldir, lstore, M;
     uint64_t budget;
     const uint8_t *vdir, *vtaken, *vstore, *vslots;
+    /* eager retirement */
+    uint32_t eager;
+    const uint8_t* ct;
 } snapview;
 
 static int snap_open(const uint8_t* s, uint64_t len, snapview* v)
@@ -741,8 +807,26 @@ static int snap_open(const uint8_t* s, uint64_t len, snapview* v)
             return 0;
         v->vdir = s + o_dir; v->vtaken = s + o_tk; v->vstore = s + o_st; v->vslots = s + o_ss;
     }
+    v->eager = rd32(s + 168);
+    v->ct = NULL;
+    if (v->eager > 1) return 0;
+    if (v->eager) {
+        uint64_t o_ct = rd64(s + 176);
+        if (var != 0 || v->log2q != v->log2_span + 1 || v->log2q > 28) return 0;
+        if (o_ct + 8 * v->N > total || o_pid + 4 * ((uint64_t)v->S << v->log2_span) > o_sl) return 0;
+        v->ct = s + o_ct;
+    }
     return 1;
 }
+
+/* Eager retirement: free pages and token of chunk c. */
+#define TOK_NONE 0xFFFFFFFFu
+#define TOK_HELD 0xFFFFFFFEu
+static uint32_t sv_count(const snapview* v, uint64_t c)
+{
+    return v->ct ? (uint32_t)rd64(v->ct + c * 8) : rd32(v->cnt + c * 4);
+}
+static uint32_t sv_token(const snapview* v, uint64_t c) { return (uint32_t)(rd64(v->ct + c * 8) >> 32); }
 
 /* Virtualised list: tag and link of segment m of shard j, and the segment
  * holding number sg of queue (j, k), found by walking from the queue's
@@ -988,14 +1072,16 @@ int orc_check_snapshot(const uint8_t* snap, uint64_t len, orc_snap_report* rep)
     uint64_t* free_s = (uint64_t*)calloc(v.S, 8);
 
     /* per chunk: class byte, stray bits beyond the class's pages, counts */
+    rep->eager = v.eager;
     for (uint64_t c = 0; c < v.N; ++c) {
         uint8_t k = v.cls[c];
-        uint32_t cn = rd32(v.cnt + c * 4);
+        uint32_t cn = sv_count(&v, c);
         uint32_t j = (uint32_t)(c >> v.log2_span);
         if (k == 0xFF) {
             rep->free_chunks++;
             free_s[j]++;
             if (cn != 0 || popc_chunk(&v, c) != 0) rep->bad_free_chunk++;
+            if (v.eager && (rd32(v.cnt + c * 4) != 0 || sv_token(&v, c) != TOK_NONE)) rep->bad_free_chunk++;
             continue;
         }
         if (k >= v.K) { rep->bad_class_byte++; continue; }
@@ -1008,6 +1094,15 @@ int orc_check_snapshot(const uint8_t* snap, uint64_t len, orc_snap_report* rep)
         }
         uint64_t f = popc_chunk(&v, c);
         if (lists_chunks((int)v.variant) && cn != f) rep->bad_count++;
+        if (v.eager) {
+            /* at quiescence: no owned chunk is whole (it would have been
+             * retired), none is held, and one without free pages has no
+             * token (the listed ones are checked with the rings) */
+            uint32_t tk = sv_token(&v, c);
+            if (cn >= ppc || tk == TOK_HELD || (cn == 0 && tk != TOK_NONE) || (cn > 0 && tk == TOK_NONE) ||
+                rd32(v.cnt + c * 4) != 0)
+                rep->bad_count++;
+        }
         rep->chunks[k]++;
         chunks_sk[(uint64_t)j * v.K + k]++;
         rep->free_pages[k] += f;
@@ -1022,6 +1117,25 @@ int orc_check_snapshot(const uint8_t* snap, uint64_t len, orc_snap_report* rep)
         uint64_t lo = (uint64_t)j << v.log2_span, hi = lo + (1ull << v.log2_span);
         if (hi > v.N) hi = v.N;
         if (first != lo || psize > hi - lo) { rep->bad_pool++; continue; }
+        if (v.eager) {
+            /* pool ring: entries at positions [head, tail) (slot = position
+             * mod 2^span) are exactly the shard's unowned chunks; no hold;
+             * every other slot empty */
+            const uint64_t span = 1ull << v.log2_span;
+            uint32_t head = rd32(pb + 16), tail = rd32(pb + 20), used = tail - head;
+            int64_t cnt = (int64_t)(uint32_t)bump - (int64_t)0x80000000u;
+            if ((bump >> 32) != 0 || cnt != (int64_t)used || used > span || used != free_s[j]) { rep->bad_pool++; continue; }
+            for (uint64_t i = 0; i < span; ++i) {
+                uint32_t e = rd32(v.pool_ids + (first + ((head + i) & (span - 1))) * 4);
+                if (i >= used) {
+                    if (e != SLOT_EMPTY) rep->bad_pool++;
+                    continue;
+                }
+                if (e < lo || e >= hi || v.cls[e] != 0xFF || seen[e]) { rep->bad_pool++; continue; }
+                seen[e] = 1;
+            }
+            continue;
+        }
         uint64_t start = bump < psize ? bump : psize;
         for (uint64_t i = start; i < psize; ++i) {
             uint32_t c = rd32(v.pool_ids + (first + i) * 4);
@@ -1062,12 +1176,19 @@ int orc_check_snapshot(const uint8_t* snap, uint64_t len, orc_snap_report* rep)
                 for (uint64_t c = lo; c < hi; ++c) seen[c] = 0;
                 for (uint32_t i = 0; i < used; ++i) {
                     uint32_t c = sv_entry(&v, j, k, head + i);
-                    if (c < lo || c >= hi || v.cls[c] != k || rd32(v.cnt + (uint64_t)c * 4) == 0) { rep->bad_ring_entry++; continue; }
+                    if (v.eager && c >= lo && c < hi &&
+                        sv_token(&v, c) != ((k << 28) | ((head + i) & 0x0FFFFFFFu))) {
+                        /* eager retirement: an entry whose chunk's token names
+                         * another listing is stale (dropped when taken) */
+                        rep->stale_entries++;
+                        continue;
+                    }
+                    if (c < lo || c >= hi || v.cls[c] != k || sv_count(&v, c) == 0) { rep->bad_ring_entry++; continue; }
                     if (seen[c]) { rep->bad_ring_dup++; continue; }
                     seen[c] = 1;
                 }
                 for (uint64_t c = lo; c < hi; ++c)
-                    if (v.cls[c] == k && rd32(v.cnt + c * 4) > 0 && !seen[c]) rep->bad_ring_missing++;
+                    if (v.cls[c] == k && sv_count(&v, c) > 0 && !seen[c]) rep->bad_ring_missing++;
             } else {
                 /* page variant: entries are exactly the free pages of class k in shard j */
                 uint64_t s = 16ull << k, ppc = C >> (4 + k);

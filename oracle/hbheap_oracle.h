@@ -84,6 +84,11 @@ typedef struct {
 /* shards: power of two <= 64, 0 for one per 256 chunks (up to 64) */
 orc_heap* orc_create_ex(uint64_t bytes, uint64_t chunk_bytes, int variant, int policy, uint32_t shards);
 orc_heap* orc_create(uint64_t bytes, uint64_t chunk_bytes, int variant, int policy); /* one shard */
+/* Eager retirement (chunk variant, before any request): a chunk whose pages
+ * are all free again returns to its shard's pool at once instead of at the
+ * next trim (LOWEST: the unowned set; FIFO: the back of the shard's pool
+ * queue).  Returns 0, or -1 for another variant or a heap already used. */
+int orc_set_eager(orc_heap* h);
 uint32_t  orc_shards(const orc_heap* h);
 void      orc_destroy(orc_heap* h);
 int64_t   orc_alloc(orc_heap* h, uint64_t n);
@@ -128,6 +133,8 @@ typedef struct {
     uint64_t bad_vdir, bad_vtaken, bad_vstore, bad_committed; /* virtualised array */
     uint64_t free_chunks;
     uint64_t live[ORC_MAX_CLASSES], chunks[ORC_MAX_CLASSES], free_pages[ORC_MAX_CLASSES];
+    uint64_t stale_entries;       /* eager retirement: queue entries no token names */
+    uint32_t eager, pad;
 } orc_snap_report;
 
 /* Quiescent-state consistency of a snapshot (documented layout, version 3). */

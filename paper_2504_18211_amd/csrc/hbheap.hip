@@ -46,6 +46,10 @@ struct Layout {
     uint64_t off_vdir = 0, off_vtaken = 0, off_vstore = 0, off_vslots = 0;
     uint32_t log2_seg = 0, log2_dir = 0, log2_store = 0, vsegs = 0;
     uint64_t vbudget = 0;
+    /* eager retirement: count and token words, and pool ids padded to
+     * S << log2_span (one ring of 2^log2_span slots per shard) */
+    uint64_t off_ct = 0;
+    uint64_t n_pid = 0;
 };
 
 uint64_t al256(uint64_t x) { return (x + 255) & ~255ull; }
@@ -81,6 +85,11 @@ struct hbheap_heap {
 /* ======================================================================= */
 
 __global__ void k_fill_u32(uint32_t* p, uint64_t n, uint32_t v)
+{
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+__global__ void k_fill_u64(uint64_t* p, uint64_t n, uint64_t v)
 {
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
         p[i] = v;
@@ -194,7 +203,7 @@ __device__ __forceinline__ TrimKey trim_key(const hbheap_dev_t& h, uint64_t c)
         return t;
     }
     if (HBHEAP_VARIANT_LISTS_CHUNKS(h.variant)) {
-        const bool listed = h.chunk_cnt[c] > 0;
+        const bool listed = eager(h) ? (uint32_t)h.chunk_ct[c] > 0 : h.chunk_cnt[c] > 0;
         t.key = listed ? j * h.n_classes + k : h.n_shards * (h.n_classes + 1);
         t.weight = listed ? 1u : 0u;
     } else {
@@ -231,6 +240,7 @@ __global__ void __launch_bounds__(kTrimBlock) k_trim_count(hbheap_dev_t h, uint3
             if (f == ppc) {
                 for (uint32_t w = 0; w < h.words_per_chunk; ++w) h.bits[c * h.words_per_chunk + w] = 0;
                 h.chunk_cnt[c] = 0;
+                if (eager(h)) h.chunk_ct[c] = ct_word(kTokNone, 0);
                 h.chunk_class[c] = (uint8_t)kFreeClass;
             } else {
                 atomicAdd(&own[shard_of_chunk(h, c) * h.n_classes + k], 1u);
@@ -331,6 +341,7 @@ __global__ void __launch_bounds__(kTrimBlock) k_trim_write(hbheap_dev_t h, const
                 if (idx < h.n_chunks) h.pool_ids[idx] = (uint32_t)c;
             } else if (h.variant == HBHEAP_VARIANT_CHUNK) {
                 if (pos < Q) h.slots[(uint64_t)key * Q + pos] = (uint32_t)c;
+                if (eager(h)) h.chunk_ct[c] = ct_word(tok_listed(kk, pos), (uint32_t)h.chunk_ct[c]);
             } else if (HBHEAP_VARIANT_SEGMENTED(h.variant) && HBHEAP_VARIANT_LISTS_CHUNKS(h.variant)) {
                 const uint64_t seg = va_first_seg(h, totals, j, kk) + (pos >> h.log2_seg);
                 if (seg < h.vsegs)
@@ -363,6 +374,9 @@ __global__ void __launch_bounds__(kTrimBlock) k_trim_write(hbheap_dev_t h, const
             }
         }
     }
+    /* eager retirement: an owned chunk with no free page has no token */
+    if (eager(h) && c < h.n_chunks && t.weight == 0 && h.chunk_class[c] != kFreeClass)
+        h.chunk_ct[c] = ct_word(kTokNone, 0);
 }
 
 /* Pass 4: queue control words and pool counters. */
@@ -378,8 +392,14 @@ __global__ void k_trim_ctl(hbheap_dev_t h, const uint32_t* totals, const uint32_
     }
     for (uint32_t j = threadIdx.x; j < S; j += blockDim.x) {
         uint64_t* pb = h.pool + 16ull * j;
-        pb[0] = 0;
-        ((uint32_t*)pb)[2] = totals[S * K + j];
+        if (eager(h)) { /* pool ring: the free chunks at positions 0 .. n-1 */
+            pb[0] = (uint64_t)totals[S * K + j] + kBias;
+            ((uint32_t*)pb)[4] = 0;
+            ((uint32_t*)pb)[5] = totals[S * K + j];
+        } else {
+            pb[0] = 0;
+            ((uint32_t*)pb)[2] = totals[S * K + j];
+        }
     }
 }
 
@@ -667,12 +687,13 @@ void shard_geometry(uint64_t N, uint32_t requested, uint32_t* S, uint32_t* log2_
 }
 
 Layout make_layout(uint64_t N, uint32_t log2C, uint32_t K, uint32_t variant, uint64_t bytes, uint32_t S,
-                   uint32_t log2_span)
+                   uint32_t log2_span, bool eager_retire)
 {
     Layout L;
     const uint64_t W = (1ull << log2C) / 1024;
     if (HBHEAP_VARIANT_LISTS_CHUNKS(variant)) {
-        L.log2q = log2_span;
+        /* eager retirement: room for stale entries besides the listed chunks */
+        L.log2q = log2_span + (eager_retire ? 1u : 0u);
     } else {
         const uint64_t per = bytes / 8 / K / 4 / S;
         L.log2q = per ? ilog2(per) : 0;
@@ -713,8 +734,13 @@ Layout make_layout(uint64_t N, uint32_t log2C, uint32_t K, uint32_t variant, uin
     L.off_cnt = al256(L.off_cls + N);
     L.off_bits = al256(L.off_cnt + 4 * N);
     L.off_pid = al256(L.off_bits + 8 * N * W);
-    L.off_sl = al256(L.off_pid + 4 * N);
+    L.n_pid = eager_retire ? (uint64_t)S << log2_span : N;
+    L.off_sl = al256(L.off_pid + 4 * L.n_pid);
     L.total = al256(L.off_sl + 4ull * L.n_slots);
+    if (eager_retire) {
+        L.off_ct = L.total;
+        L.total = al256(L.off_ct + 8 * N);
+    }
     if (HBHEAP_VARIANT_SEGMENTED(variant)) {
         L.off_vdir = L.total;
         const uint64_t dir_words = HBHEAP_VARIANT_IS_VL(variant) ? 2ull * S * L.vsegs : (uint64_t)S * K << L.log2_dir;
@@ -804,11 +830,15 @@ int heap_create_ex(size_t bytes, size_t chunk_bytes, const heap_config_t* cfg, h
     if (c.shards > kMaxShards || (c.shards & (c.shards - 1))) return HBHEAP_E_INVAL;
     uint32_t S = 1, log2_span = 0;
     shard_geometry(N, c.shards, &S, &log2_span);
+    /* eager retirement: chunk variant only; queue positions must stay
+     * distinct modulo 2^28 within a queue's capacity */
+    const bool eager_retire = (c.flags & HBHEAP_FLAG_EAGER) != 0;
+    if (eager_retire && (c.variant != HBHEAP_VARIANT_CHUNK || log2_span + 1 > 28)) return HBHEAP_E_INVAL;
 
     hbheap_heap* h = new (std::nothrow) hbheap_heap();
     if (!h) return HBHEAP_E_NOMEM;
     h->chunk_bytes = chunk_bytes;
-    h->lay = make_layout(N, log2C, K, c.variant, bytes, S, log2_span);
+    h->lay = make_layout(N, log2C, K, c.variant, bytes, S, log2_span, eager_retire);
     const Layout& L = h->lay;
     h->trim_blocks = (uint32_t)((N + kTrimBlock - 1) / kTrimBlock);
     const uint32_t nkeys = S * (K + 1) + 1;
@@ -834,6 +864,7 @@ int heap_create_ex(size_t bytes, size_t chunk_bytes, const heap_config_t* cfg, h
     d.bits = (uint64_t*)(st + L.off_bits);
     d.pool_ids = (uint32_t*)(st + L.off_pid);
     d.slots = (uint32_t*)(st + L.off_sl);
+    d.chunk_ct = eager_retire ? (uint64_t*)(st + L.off_ct) : nullptr;
     d.err = (uint32_t*)ax;
     d.stats = (uint64_t*)(ax + 256);
     d.data_bytes = N * chunk_bytes;
@@ -900,12 +931,17 @@ int heap_create_ex(size_t bytes, size_t chunk_bytes, const heap_config_t* cfg, h
     put64(hb, 144, L.off_vtaken);
     put64(hb, 152, L.off_vstore);
     put64(hb, 160, L.off_vslots);
+    put32(hb, 168, eager_retire ? 1u : 0u);
+    put64(hb, 176, L.off_ct);
     for (uint32_t j = 0; j < S; ++j) {
         const uint64_t first = (uint64_t)j << log2_span;
         const uint64_t size = first + (1ull << log2_span) <= N ? (1ull << log2_span) : N - first;
-        put64(hb, L.off_pool + 128ull * j, 0);
+        /* bump pool: u64 bump; eager retirement: u64 ring state (its
+         * chunks published), u32 head at +16 and tail at +20 */
+        put64(hb, L.off_pool + 128ull * j, eager_retire ? size + kBias : 0);
         put32(hb, L.off_pool + 128ull * j + 8, (uint32_t)size);
         put32(hb, L.off_pool + 128ull * j + 12, (uint32_t)first);
+        if (eager_retire) put32(hb, L.off_pool + 128ull * j + 20, (uint32_t)size);
     }
     for (uint64_t i = 0; i < (uint64_t)S * K; ++i) put64(hb, L.off_cl + i * kClassBlock, kBias);
 
@@ -917,6 +953,16 @@ int heap_create_ex(size_t bytes, size_t chunk_bytes, const heap_config_t* cfg, h
     if (rc == HBHEAP_OK) {
         hipLaunchKernelGGL(k_iota_u32, dim3(grid_stride(N)), dim3(256), 0, s, d.pool_ids, N);
         if (hipGetLastError() != hipSuccess) rc = HBHEAP_E_HIP;
+    }
+    if (rc == HBHEAP_OK && eager_retire) {
+        /* the last shard's ring slots past its chunks, and every chunk's
+         * count/token word: empty, no token */
+        rc = fill_u32(d.pool_ids + N, L.n_pid - N, kEmpty, s);
+        if (rc == HBHEAP_OK) {
+            hipLaunchKernelGGL(k_fill_u64, dim3(grid_stride(N)), dim3(256), 0, s, d.chunk_ct, N,
+                               ct_word(kTokNone, 0));
+            if (hipGetLastError() != hipSuccess) rc = HBHEAP_E_HIP;
+        }
     }
     if (rc == HBHEAP_OK && hipMemcpyAsync(st, hb, head_bytes, hipMemcpyHostToDevice, s) != hipSuccess) rc = HBHEAP_E_HIP;
     if (rc == HBHEAP_OK && HBHEAP_VARIANT_SEGMENTED(c.variant)) rc = va_rebuild(d, nullptr, nullptr, s);
@@ -966,7 +1012,8 @@ int heap_free_batch(heap_t h, const size_t* sizes, void* const* ptrs, size_t n, 
 int heap_set_flags(heap_t h, uint32_t flags)
 {
     if (!h) return HBHEAP_E_INVAL;
-    h->dev.flags = flags;
+    /* eager retirement is fixed at creation */
+    h->dev.flags = (flags & ~HBHEAP_FLAG_EAGER) | (h->dev.flags & HBHEAP_FLAG_EAGER);
     return HBHEAP_OK;
 }
 
@@ -1007,7 +1054,7 @@ int heap_trim(heap_t h, hipStream_t stream)
                        nkeys);
     HB_TRY(hipGetLastError());
     rc = fill_u32(d.slots, h->lay.n_slots, kEmpty, stream);
-    if (!rc) rc = fill_u32(d.pool_ids, d.n_chunks, kEmpty, stream);
+    if (!rc) rc = fill_u32(d.pool_ids, h->lay.n_pid, kEmpty, stream);
     if (rc) return rc;
     hipLaunchKernelGGL(k_trim_write, dim3(nb), dim3(kTrimBlock), 0, stream, d, h->trim_offsets, nb, h->trim_totals);
     HB_TRY(hipGetLastError());

@@ -75,7 +75,8 @@ namespace {
 /* ---------------- device ---------------- */
 
 /* out[0]: chunks taken from the pools (per shard, its chunks minus the
- * pool's remaining ones, size - min(bump, size)); out[1 + k], page variant:
+ * pool's remaining ones: size - min(bump, size), or with eager retirement
+ * the chunks its pool ring holds); out[1 + k], page variant:
  * chunks owned by class k over all shards (0 in the chunk variant).  One
  * wave. */
 __global__ void k_usage(hbheap_dev_t h, uint64_t* out)
@@ -88,7 +89,9 @@ __global__ void k_usage(hbheap_dev_t h, uint64_t* out)
         const uint32_t size = ((const uint32_t*)pb)[2];
         const uint64_t lo = (uint64_t)s << h.log2_span;
         const uint64_t hi = std::min<uint64_t>((uint64_t)h.n_chunks, ((uint64_t)s + 1) << h.log2_span);
-        const uint64_t left = size - std::min<uint64_t>(bump, size);
+        /* eager retirement: the pool ring's published chunks */
+        const uint64_t left = eager(h) ? (uint64_t)std::max<int32_t>(state_count(bump), 0)
+                                       : size - std::min<uint64_t>(bump, size);
         used += (hi - lo) - left;
     }
     for (uint32_t o = 32; o; o >>= 1) used += __shfl_xor(used, o);

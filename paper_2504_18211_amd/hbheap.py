@@ -17,9 +17,9 @@ LIB_PATH = os.path.join(HERE, "libhbheap.so")
 VARIANT_CHUNK, VARIANT_PAGE, VARIANT_VA_PAGE, VARIANT_VA_CHUNK, VARIANT_VL_PAGE, VARIANT_VL_CHUNK = 0, 1, 2, 3, 4, 5
 OK, E_INVAL, E_NOMEM, E_HIP, E_RANGE, E_UNSUP = 0, -1, -2, -3, -4, -5
 ERR_DOUBLE_FREE, ERR_INVALID_FREE, ERR_TIMEOUT, ERR_CORRUPT = 0x1, 0x2, 0x4, 0x8
-FLAG_STATS, FLAG_VERIFY, FLAG_HOME0 = 0x1, 0x2, 0x4
+FLAG_STATS, FLAG_VERIFY, FLAG_HOME0, FLAG_EAGER = 0x1, 0x2, 0x4, 0x8
 STAT_NAMES = ["chunk_grabs", "refills", "oom", "oom_waits", "double_free", "invalid_free", "timeouts", "reserved7",
-              "state_ops", "headtail_ops", "pool_ops", "spread_ops", "reserved12", "reserved13", "reserved14",
+              "state_ops", "headtail_ops", "pool_ops", "spread_ops", "retired", "reserved13", "reserved14",
               "reserved15"]
 FREE_OK, FREE_DOUBLE, FREE_INVALID, FREE_NULL = 0, 1, 2, 3
 
@@ -80,7 +80,7 @@ class DevHandle(C.Structure):
                                           "log2_span")] + \
                [(n, C.c_void_p) for n in ("vdir", "vtaken", "vstore", "vstore_slots")] + \
                [(n, C.c_uint32) for n in ("log2_seg", "log2_dir", "log2_store", "vsegs")] + \
-               [("vbudget", C.c_uint64)]
+               [("vbudget", C.c_uint64), ("chunk_ct", C.c_void_p)]
 
 
 _lib = None
