@@ -65,6 +65,7 @@ def parse():
     ap.add_argument("--shards", type=int, default=0, help="queue shards (0: one per 256 chunks, up to 64)")
     ap.add_argument("--no-other", action="store_true", help="skip the other queue variant")
     ap.add_argument("--no-va", action="store_true", help="skip the virtualised-array and -list variant lines")
+    ap.add_argument("--no-eager", action="store_true", help="skip the eager chunk retirement line")
     ap.add_argument("--no-ablation", action="store_true", help="skip the width-1 (no aggregation) ablation")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain device-malloc baseline")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
@@ -157,7 +158,10 @@ def main():
 
     hb.lib()  # fails loudly without the built library
     VARIANTS = {"chunk": hb.VARIANT_CHUNK, "page": hb.VARIANT_PAGE, "va-page": hb.VARIANT_VA_PAGE,
-                "va-chunk": hb.VARIANT_VA_CHUNK, "vl-page": hb.VARIANT_VL_PAGE, "vl-chunk": hb.VARIANT_VL_CHUNK}
+                "va-chunk": hb.VARIANT_VA_CHUNK, "vl-page": hb.VARIANT_VL_PAGE, "vl-chunk": hb.VARIANT_VL_CHUNK,
+                "chunk-eager": hb.VARIANT_CHUNK}
+    # creation flags per line: eager chunk retirement is fixed at creation
+    CREATE_FLAGS = {"chunk-eager": hb.FLAG_EAGER}
     if not torch.cuda.is_available():
         log("no GPU visible")
         sys.exit(3)
@@ -234,7 +238,7 @@ def main():
     def run_sweep(variant_name: str, steps: int, warmup: int, count: bool, width: int | None = None) -> dict:
         variant = VARIANTS[variant_name]
         heap = hb.Heap(w.heap_bytes, w.chunk_bytes, variant=variant, width=args.width if width is None else width,
-                       shards=args.shards)
+                       shards=args.shards, flags=CREATE_FLAGS.get(variant_name, 0))
         shards = int(heap.info.n_shards)
 
         def one_size(s, rec):
@@ -398,6 +402,41 @@ def main():
             log(f"{name}: {virt[name]['value']/1e9:.2f} G ops/s (iterations 2..10)")
     va, va_chunk = virt.get("va-page"), virt.get("va-chunk")
 
+    # eager chunk retirement (chunk variant: a chunk whose pages are all free
+    # returns to its shard's pool at once): the same sweep, one step -- every
+    # free launch retires the chunks it empties and the next allocation
+    # takes them back from the pool rings; then a change of class with no
+    # trim, lazy against eager
+    eager = None
+    if not args.no_eager:
+        eager = run_sweep("chunk-eager", 1, 1, count=False)
+        log(f"chunk-eager: {eager['value']/1e9:.2f} G ops/s (iterations 2..10)")
+        eager["class_change"] = {}
+        for name, fl in (("lazy", 0), ("eager", hb.FLAG_EAGER)):
+            heap = hb.Heap(w.heap_bytes, w.chunk_bytes, variant=hb.VARIANT_CHUNK, shards=args.shards, flags=fl)
+            rec = {}
+            for phase, s in (("fill_4KiB", 4096), ("refill_16B", 16)):
+                hold_stream(torch)
+                e = [ev() for _ in range(4)]
+                e[0].record()
+                heap.alloc(size_dev[s], ptrs)
+                e[1].record()
+                ok = int((ptrs != 0).sum().item())
+                e[2].record()
+                heap.free(ptrs)
+                e[3].record()
+                torch.cuda.synchronize()
+                rec[phase] = {"ok": ok, "alloc_us": e[0].elapsed_time(e[1]) * 1e3,
+                              "free_us": e[2].elapsed_time(e[3]) * 1e3}
+            err = heap.error()
+            heap.close()
+            if err:
+                log(f"HEAP ERROR WORD {err:#x}")
+                sys.exit(5)
+            eager["class_change"][name] = rec
+            log(f"class change {name}: 4 KiB ok {rec['fill_4KiB']['ok']}, then 16 B ok {rec['refill_16B']['ok']} "
+                f"(no trim)")
+
     # ablation: the same sweep without wave aggregation (one queue operation
     # per lane), one step
     ablation = None
@@ -511,6 +550,7 @@ def main():
         "va_chunk_variant": va_chunk,
         "vl_variant": virt.get("vl-page"),
         "vl_chunk_variant": virt.get("vl-chunk"),
+        "eager_chunk_variant": eager,
         "ablation_width1": ablation,
         "plain": plain,
         "vs_plain": (plain["ours_same_sizes"] / plain["value_full_size_sizes"])

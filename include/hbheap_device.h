@@ -847,49 +847,108 @@ __device__ __forceinline__ uint32_t a_read32(uint32_t* p)
     return __hip_atomic_fetch_or(p, zero_after(lane()), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-/* The class byte of chunk c (eager retirement changes it while kernels
- * run, on any XCD). */
-__device__ __forceinline__ uint32_t class_coherent(const hbheap_dev_t& h, uint64_t c)
+/* Wave-wide: the class byte of chunk c for the lanes with `have` (eager
+ * retirement changes class bytes while kernels run, on any XCD, so they are
+ * read coherently).  Adjacent lanes asking for the same 4-byte word form a
+ * run; the first lane of each run reads the word, the others take it from
+ * that lane, so frees of neighbouring pages do not all hit one word. */
+__device__ __forceinline__ uint32_t class_coherent(const hbheap_dev_t& h, bool have, uint64_t c)
 {
-    const uint32_t w = a_read32((uint32_t*)(h.chunk_class + (c & ~3ull)));
+    const uint32_t me = lane();
+    const uint64_t act = exec_mask();
+    const uint32_t key = have ? (uint32_t)(c >> 2) : 0xFFFFFFFFu;
+    const uint32_t prev = perm32(key, me ? me - 1u : 0u);
+    const bool prev_act = me && ((act >> (me - 1u)) & 1ull);
+    const bool first = have && (!prev_act || prev != key);
+    uint32_t w = 0;
+    if (first) w = a_read32((uint32_t*)(h.chunk_class + (c & ~3ull)));
+    const uint64_t heads = __ballot(first);
+    const uint64_t upto = me == 63u ? ~0ull : ((2ull << me) - 1ull);
+    const uint64_t mine = heads & upto;
+    w = perm32(w, have && mine ? 63u - (uint32_t)__builtin_clzll(mine) : me);
     return (w >> ((uint32_t)(c & 3u) * 8u)) & 0xFFu;
 }
 
-/* Per lane: chunk c, all of whose pages are free and which no token names
- * any more, goes back to its shard's pool.  Its bits and class byte are
- * reset by atomics, and the put that publishes it depends on their returned
- * values, so any class that takes it finds them reset. */
-__device__ __forceinline__ void retire_chunk(const hbheap_dev_t& h, uint32_t c, Tally& t)
+/* Per lane: reset chunk c of class k, all of whose pages are free and
+ * which no token names any more -- its bitmask words (those class k uses;
+ * the others are always zero) and its class byte -- by atomics.  Returns a
+ * value the put that publishes the chunk must depend on, so that any class
+ * that takes it finds it reset. */
+__device__ __forceinline__ uint32_t retire_reset(const hbheap_dev_t& h, uint32_t c, uint32_t k, Tally& t)
 {
+    const uint32_t ppc = 1u << (h.log2_chunk - 4u - k);
+    const uint32_t nw = ppc >= 64u ? ppc >> 6 : 1u;
     uint64_t* words = h.bits + (uint64_t)c * h.words_per_chunk;
     uint64_t acc = 0;
-    for (uint32_t w = 0; w < h.words_per_chunk; ++w) acc ^= a_xchg64(words + w, 0ull);
+    for (uint32_t w = 0; w < nw; ++w) acc ^= a_xchg64(words + w, 0ull);
     const uint32_t sh = (c & 3u) * 8u;
-    acc ^= a_or32((uint32_t*)(h.chunk_class + (c & ~3u)), 0xFFu << sh);
-    t.spread += h.words_per_chunk + 1u;
+    t.spread += nw + 1u;
+    return (uint32_t)acc ^ (uint32_t)(acc >> 32) ^ a_or32((uint32_t*)(h.chunk_class + (c & ~3u)), 0xFFu << sh);
+}
+
+/* Per lane: retire chunk c of class k -- reset it, then put it at the tail
+ * of its shard's pool ring and publish it. */
+__device__ __forceinline__ void retire_chunk(const hbheap_dev_t& h, uint32_t c, uint32_t k, Tally& t)
+{
+    const uint32_t dep = retire_reset(h, c, k, t);
     const Ring P = pool_ring(h, shard_of_chunk(h, c));
-    const uint32_t pos = a_add32(P.tail, 1u) + zero_after((uint32_t)acc ^ (uint32_t)(acc >> 32));
+    const uint32_t pos = a_add32(P.tail, 1u) + zero_after(dep);
     plain_put(h, P.slots + (pos & P.mask), c, t);
     a_add64(P.state, 1ull);
     t.pool += 2;
     if (h.flags & HBHEAP_FLAG_STATS) a_add64(h.stats + HBHEAP_STAT_RETIRED, 1);
 }
 
+/* Wave-wide (every active lane calls it): the lanes with `want` retire
+ * their chunk c of class k.  Chunks of one shard go to its pool ring with
+ * one tail add and one publish for the group. */
+__device__ __forceinline__ void retire_wave(const hbheap_dev_t& h, bool want, uint32_t c, uint32_t k, Tally& t)
+{
+    uint64_t pend = __ballot(want);
+    if (!pend) return;
+    uint32_t dep = 0;
+    if (want) dep = retire_reset(h, c, k, t);
+    const uint32_t me = lane();
+    const uint32_t j = want ? shard_of_chunk(h, c) : 0u;
+    while (pend) {
+        const uint32_t leader = ctz64(pend);
+        const uint32_t jj = bcast(j, leader);
+        const uint64_t grp = __ballot(want && j == jj) & pend;
+        const uint32_t n = (uint32_t)__popcll(grp);
+        const Ring P = pool_ring(h, jj);
+        uint32_t t0 = 0;
+        if (me == leader) {
+            t0 = a_add32(P.tail, n);
+            t.pool += 1;
+        }
+        t0 = bcast(t0, leader);
+        if ((grp >> me) & 1ull) plain_put(h, P.slots + ((t0 + rank_in(grp) + zero_after(dep)) & P.mask), c, t);
+        if (me == leader) {
+            a_add64(P.state, (uint64_t)n);
+            t.pool += 1;
+            if (h.flags & HBHEAP_FLAG_STATS) a_add64(h.stats + HBHEAP_STAT_RETIRED, n);
+        }
+        pend &= ~grp;
+    }
+}
+
 /* Per lane, by the owner of chunk c's token (a free that found none, or
- * the allocator holding it): list the chunk at position pos of its class
- * queue, or retire it if its pages are all free by now.  The caller then
- * fills the slot either way (a retired chunk's entry is stale). */
+ * the allocator holding it, which also takes `take` pages off the count
+ * here): list the chunk at position pos of its class queue, or retire it if
+ * its pages are all free by now.  The caller then fills the slot either way
+ * (a retired chunk's entry is stale).  The first value tried is a plain
+ * load; a failed compare-and-swap returns the word's current value. */
 __device__ __forceinline__ void list_or_retire(const hbheap_dev_t& h, uint32_t c, uint32_t k, uint32_t ppc, uint32_t pos,
-                                               Tally& t)
+                                               uint32_t take, Tally& t)
 {
     uint64_t* w = h.chunk_ct + c;
     uint64_t v = a_load64(w);
     for (;;) {
-        const uint32_t n = (uint32_t)v;
+        const uint32_t n = (uint32_t)v - take;
         t.spread += 1;
         if (n >= ppc) {
             if (a_cas64(w, v, ct_word(kTokNone, 0))) {
-                retire_chunk(h, c, t);
+                retire_chunk(h, c, k, t);
                 return;
             }
         } else if (a_cas64(w, v, ct_word(tok_listed(k, pos), n))) {
@@ -1204,11 +1263,18 @@ __device__ __forceinline__ void chunk_serve_shard(const hbheap_dev_t& h, const G
                  * leaves each entry in the slot its position maps to.  Only
                  * one taker can win the token, whichever copy it came by. */
                 uint64_t* w = h.chunk_ct + c;
-                uint64_t x = a_read64(w);
+                uint64_t x = a_load64(w);   /* a guess: an entry is dropped only on a coherent value */
+                bool sure = false;
                 const uint32_t mine = tok_listed(g.k, h0 + g.arank);
                 for (;;) {
                     const uint32_t tk = (uint32_t)(x >> 32);
                     if (tk >= kTokHeld || (tk >> 28) != g.k || ((tk ^ mine) & R.mask) != 0) {
+                        if (!sure) {
+                            x = a_read64(w);
+                            sure = true;
+                            tl.spread += 1;
+                            continue;
+                        }
                         stale = true;
                         break;
                     }
@@ -1217,6 +1283,7 @@ __device__ __forceinline__ void chunk_serve_shard(const hbheap_dev_t& h, const G
                         v = (int32_t)(uint32_t)x;
                         break;
                     }
+                    sure = true;
                 }
                 if (!stale && v <= 0) raise_err(h, HBHEAP_ERR_CORRUPT, HBHEAP_STAT_TIMEOUTS);
             } else if (c != kEmpty) {
@@ -1235,9 +1302,10 @@ __device__ __forceinline__ void chunk_serve_shard(const hbheap_dev_t& h, const G
         bool keep = false;
         if (vc > 0) {
             if (t && ev) {
-                /* the count never drops below t while the token is held */
-                keep = (uint32_t)a_add64(h.chunk_ct + c, (uint64_t)0 - t) > t;
-                tl.spread += 1;
+                /* the count is lowered by t when the token is put back
+                 * (list_or_retire, or the release below): while it is held
+                 * nobody else takes pages from the chunk and frees only add */
+                keep = (uint32_t)v > t;
             } else if (t) {
                 keep = a_addi(h.chunk_cnt + c, -(int32_t)t) - (int32_t)t > 0;
                 tl.spread += 1;
@@ -1266,19 +1334,19 @@ __device__ __forceinline__ void chunk_serve_shard(const hbheap_dev_t& h, const G
         t0 = bcast(t0, g.leader);
         if (keep) {
             const uint32_t pos = t0 + rank_in(rq);
-            if (ev) list_or_retire(h, c, g.k, g.ppc, pos, tl);
+            if (ev) list_or_retire(h, c, g.k, g.ppc, pos, t, tl);
             slot_put(h, R, pos, c, tl);
         }
         if (ev && vc > 0 && !keep) {
             /* every free page taken: give the token up -- unless frees came
              * in while it was held, which left it to this lane to list the
              * chunk again (or retire it) */
-            uint64_t x = ct_word(kTokHeld, 0);
+            uint64_t x = ct_word(kTokHeld, t);
             tl.spread += 1;
             if (!a_cas64(h.chunk_ct + c, x, ct_word(kTokNone, 0))) {
                 const uint32_t pos = a_add32(R.tail, 1u);
                 tl.headtail += 1;
-                list_or_retire(h, c, g.k, g.ppc, pos, tl);
+                list_or_retire(h, c, g.k, g.ppc, pos, t, tl);
                 slot_put(h, R, pos, c, tl);
                 a_add64(R.state, 1ull);
                 tl.state += 1;
@@ -1745,12 +1813,18 @@ __device__ __forceinline__ uint32_t free_wave(const hbheap_dev_t& h, void* p, ui
     Tally tl;
     uint32_t val = 0, key = 0, k = 0;
     uint64_t c = 0, widx = 0, bit = 0, o = 0;
+    bool inr = false;
     if (p != nullptr) {
         status = kFreeInvalid;
         o = (uint64_t)((uint8_t*)p - h.data);
-        if ((uint8_t*)p >= h.data && o < h.data_bytes) {
-            c = o >> h.log2_chunk;
-            k = eager(h) ? class_coherent(h, c) : h.chunk_class[c];
+        inr = (uint8_t*)p >= h.data && o < h.data_bytes;
+        if (inr) c = o >> h.log2_chunk;
+    }
+    uint32_t kc = 0;
+    if (eager(h)) kc = class_coherent(h, inr, c);
+    if (p != nullptr) {
+        if (inr) {
+            k = eager(h) ? kc : h.chunk_class[c];
             const uint32_t shift = 4u + k;
             bool ok = k < h.n_classes && (o & ((1ull << shift) - 1ull)) == 0;
             if (ok && check_size) ok = class_of(h, size_hint) == (int)k;
@@ -1774,6 +1848,7 @@ __device__ __forceinline__ uint32_t free_wave(const hbheap_dev_t& h, void* p, ui
     const Run run = run_combine(cand, widx, bit, h.width < 64u ? h.width : 64u);
     uint64_t old = 0;
     uint32_t cold = 1, nnew = 0;
+    bool retire = false;
     if (cand && me == run.tail) {
         old = a_or64(h.bits + widx, run.incl);
         nnew = (uint32_t)__popcll(run.incl & ~old);
@@ -1790,19 +1865,20 @@ __device__ __forceinline__ uint32_t free_wave(const hbheap_dev_t& h, void* p, ui
             if (otok == kTokNone && (uint32_t)ow == 0) {
                 if (n >= ppc) {
                     uint64_t x = ct_word(kTokNone, n);
-                    if (a_cas64(h.chunk_ct + c, x, ct_word(kTokNone, 0))) retire_chunk(h, (uint32_t)c, tl);
+                    retire = a_cas64(h.chunk_ct + c, x, ct_word(kTokNone, 0));
                 } else {
                     cold = 0;
                 }
             } else if (otok < kTokHeld && n >= ppc) {
                 uint64_t x = ct_word(otok, n);
-                if (a_cas64(h.chunk_ct + c, x, ct_word(kTokNone, 0))) retire_chunk(h, (uint32_t)c, tl);
+                retire = a_cas64(h.chunk_ct + c, x, ct_word(kTokNone, 0));
             }
         } else if (HBHEAP_VARIANT_LISTS_CHUNKS(h.variant) && nnew) {
             cold = (uint32_t)a_addi(h.chunk_cnt + c, (int32_t)nnew);
             tl.spread += 1;
         }
     }
+    if (eager(h)) retire_wave(h, retire, (uint32_t)c, k, tl);
     old = perm64(old, run.tail);
     cold = perm32(cold, run.tail);
     nnew = perm32(nnew, run.tail);
@@ -1849,7 +1925,7 @@ __device__ __forceinline__ uint32_t free_wave(const hbheap_dev_t& h, void* p, ui
         t0 = bcast(t0, leader);
         if ((grp >> me) & 1ull) {
             const uint32_t pos = t0 + rank_in(grp);
-            if (eager(h)) list_or_retire(h, val, k, 1u << (h.log2_chunk - 4u - k), pos, tl);
+            if (eager(h)) list_or_retire(h, val, k, 1u << (h.log2_chunk - 4u - k), pos, 0u, tl);
             slot_put(h, R, pos, val, tl);
         }
         if (me == leader) {
@@ -1862,7 +1938,7 @@ __device__ __forceinline__ uint32_t free_wave(const hbheap_dev_t& h, void* p, ui
         const Ring R = ring_of(h, key / h.n_classes, key % h.n_classes);
         const uint32_t t0 = a_add32(R.tail, 1u);
         tl.headtail += 1;
-        if (eager(h)) list_or_retire(h, val, k, 1u << (h.log2_chunk - 4u - k), t0, tl);
+        if (eager(h)) list_or_retire(h, val, k, 1u << (h.log2_chunk - 4u - k), t0, 0u, tl);
         slot_put(h, R, t0, val, tl);
         a_add64(R.state, 1ull);
         tl.state += 1;

@@ -66,11 +66,11 @@ def live_requests(ops):
     return np.nonzero((ops >= 0) & ~freed)[0]
 
 
-def run_both(hb, nbytes, chunk, variant, plan, seed, slots, rate, admit=0.95, checks=True):
+def run_both(hb, nbytes, chunk, variant, plan, seed, slots, rate, admit=0.95, checks=True, flags=0):
     import torch
     out = {}
     for mode in ("mix", "alone"):
-        with hb.Heap(nbytes, chunk, variant=variant) as heap:
+        with hb.Heap(nbytes, chunk, variant=variant, flags=flags) as heap:
             s = hb.serve_create(heap.h, slots, int(np.diff(plan.first).max()), len(plan.ops), admit, seed,
                                 plan.free_lag)
             try:
@@ -119,6 +119,23 @@ def test_serve_alone_equals_mix_equals_oracle(hb, variant):
     assert (out["mix"]["latency_ns"] > 0).all()
 
 
+def phase_change_plan(N, lag=2):
+    """2 KiB blocks filling 45 % of N chunks, all freed, then 8 KiB blocks
+    needing 45 % again."""
+    n_small = int(0.45 * N) * 4             # 2 KiB pages, 4 per chunk
+    per = 512
+    small = [np.full(min(per, n_small - i), 2 * KiB, dtype=np.int64) for i in range(0, n_small, per)]
+    R0 = sum(len(x) for x in small)
+    frees = np.arange(R0, dtype=np.int64)
+    free_batches = [-frees[i:i + per] - 1 for i in range(0, R0, per)]
+    n_big = int(0.45 * N)
+    big = [np.full(min(256, n_big - i), 8 * KiB, dtype=np.int64) for i in range(0, n_big, 256)]
+    batches = small + [np.zeros(0, dtype=np.int64)] * lag + free_batches + big
+    first = np.zeros(len(batches) + 1, dtype=np.uint64)
+    first[1:] = np.cumsum([len(x) for x in batches])
+    return inputs.ServePlan(first, np.concatenate(batches), len(small), lag), len(batches)
+
+
 @pytest.mark.parametrize("variant", [0, 1])
 def test_serve_admission_trims_between_phases(hb, variant):
     """2 KiB blocks fill 45 % of the chunks and are all freed; 8 KiB blocks
@@ -146,6 +163,19 @@ def test_serve_admission_trims_between_phases(hb, variant):
     compare(out, oracle_serve(nbytes, chunk, variant, first, ops, seed))
     for mode in ("mix", "alone"):
         assert out[mode]["stats"]["trims"] >= 1, mode
+
+
+def test_serve_eager_retirement_needs_no_trim(hb):
+    """The same phase change on a chunk heap with eager retirement: the
+    freed chunks are back in the pools as soon as their frees complete, so
+    the admission never needs a trim; results equal the oracle's."""
+    nbytes, chunk, seed = 16 * MiB, 8 * KiB, 0x78
+    plan, nb = phase_change_plan(nbytes // chunk)
+    say(f"case serve-eager batches={nb}")
+    out = run_both(hb, nbytes, chunk, 0, plan, seed, slots=4, rate=50000.0, admit=0.6, flags=hb.FLAG_EAGER)
+    compare(out, oracle_serve(nbytes, chunk, 0, plan.first, plan.ops, seed))
+    for mode in ("mix", "alone"):
+        assert out[mode]["stats"]["trims"] == 0, mode
 
 
 def test_serve_page_class_capacity_is_not_admitted(hb):
