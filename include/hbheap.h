@@ -41,7 +41,8 @@ typedef struct heap_config {
                               two in [1, 64], default 64                     */
     uint32_t spin_cap;     /* bounded-wait iterations, default 1 << 18        */
     uint32_t backoff_max;  /* longest backoff in s_sleep(1) units, default 64 */
-    uint32_t flags;        /* HBHEAP_FLAG_*                                   */
+    uint32_t flags;        /* HBHEAP_FLAG_*; HBHEAP_FLAG_EAGER (chunk variant
+                              only) is fixed for the heap's lifetime         */
     uint32_t shards;       /* queue shards: power of two <= 64; 0 = about one
                               per 256 chunks, at most 64                     */
 } heap_config_t;
@@ -73,6 +74,12 @@ typedef struct heap_info {
  * counted in `bytes`.  chunk_bytes: power of two in [4 KiB, 64 KiB]; bytes
  * >= chunk_bytes; page variants: data region at most 64 GiB.  Blocking: the
  * heap is initialised when the call returns.  *out is untouched on error.
+ * cfg->flags with HBHEAP_FLAG_EAGER (chunk variant only; at most 2^27 chunks
+ * per shard): a chunk whose pages are all free again leaves its class at
+ * once and goes back to its shard's pool -- the paper leaves open when a
+ * chunk changes class; the default keeps it with its class until
+ * heap_trim.  Out of memory stays exact for launches without frees (no
+ * chunk retires during them).
  * Errors: HBHEAP_E_INVAL (geometry, config, out == NULL), HBHEAP_E_NOMEM
  * (hipMalloc failed), HBHEAP_E_HIP.
  */
@@ -111,7 +118,8 @@ int heap_free_batch_ex(heap_t h, const size_t* sizes, void* const* ptrs, size_t 
                        hipStream_t stream);
 
 /* Replace the HBHEAP_FLAG_* bits used by launches issued after this call
- * (and by handles obtained after it). */
+ * (and by handles obtained after it).  HBHEAP_FLAG_EAGER is kept as the
+ * heap was created, whatever `flags` says. */
 int heap_set_flags(heap_t h, uint32_t flags);
 
 /* Device handle for user kernels calling dev_malloc/dev_free
@@ -126,7 +134,9 @@ int heap_info(heap_t h, heap_info_t* out);
  * chunks whose pages are all free return to the pool, and the pool and the
  * class queues are rewritten in ascending order with head = 0.  After every
  * block is freed, trim makes the state region byte-identical to a fresh
- * heap's.
+ * heap's.  With eager retirement (HBHEAP_FLAG_EAGER) no owned chunk is ever
+ * whole at quiescence; trim then only compacts the queues (dropping their
+ * stale entries) and the pool rings.
  */
 int heap_trim(heap_t h, hipStream_t stream);
 
@@ -136,7 +146,11 @@ int heap_trim(heap_t h, hipStream_t stream);
  * variant, and the byte offset of every section: pools, class blocks, class
  * bytes, free counts, bitmask words, pool ids, queue slots, and for the
  * segmented variants the directories or segment tags and links, consumed
- * counts and segment stores), then the sections.  Synchronises `stream`.
+ * counts and segment stores), then the sections.  Eager retirement: header
+ * u32 at 168 is 1 and u64 at 176 the offset of the per-chunk count/token
+ * words (hbheap_types.h, chunk_ct); pools are rings (state, head, tail) over
+ * pool ids padded to S << log2_span; queues have twice the slots (room for
+ * stale entries); the u32 free counts stay zero.  Synchronises `stream`.
  * *len receives the size (also when cap is too small, which returns
  * HBHEAP_E_RANGE).  dst may be NULL to query the size.
  */
