@@ -806,6 +806,17 @@ __device__ __forceinline__ bool eager(const hbheap_dev_t& h)
 }
 __host__ __device__ __forceinline__ uint32_t tok_listed(uint32_t k, uint32_t pos) { return (k << 28) | (pos & 0x0FFFFFFFu); }
 __host__ __device__ __forceinline__ uint64_t ct_word(uint32_t tok, uint32_t cnt) { return ((uint64_t)tok << 32) | cnt; }
+/* The count half holds the free pages in bits 0..15 and, in bit 16 + k,
+ * whether the chunk has a stale entry in the queue of class k.  A
+ * retirement that leaves a stale entry in queue k needs bit k clear and sets
+ * it; the taker that drops the entry clears it.  So queue k holds at most one
+ * live and one stale entry per chunk of its shard, and its 2 * span slots
+ * never overflow.  (A whole chunk whose bit is still set stays listed until
+ * an allocation takes it.) */
+constexpr uint32_t kCountMask = 0xFFFFu;
+__host__ __device__ __forceinline__ uint32_t stale_bit(uint32_t k) { return 1u << (16u + k); }
+__device__ __forceinline__ uint32_t ct_count(uint64_t w) { return (uint32_t)w & kCountMask; }
+__device__ __forceinline__ uint32_t ct_stale(uint64_t w) { return (uint32_t)w & ~kCountMask; }
 __device__ __forceinline__ bool a_cas64(uint64_t* p, uint64_t& expect, uint64_t v)
 {
     return __hip_atomic_compare_exchange_strong(p, &expect, v, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
@@ -944,17 +955,20 @@ __device__ __forceinline__ void list_or_retire(const hbheap_dev_t& h, uint32_t c
     uint64_t* w = h.chunk_ct + c;
     uint64_t v = a_load64(w);
     for (;;) {
-        const uint32_t n = (uint32_t)v - take;
+        const uint32_t n = ct_count(v) - take;
         t.spread += 1;
-        if (n >= ppc) {
-            if (a_cas64(w, v, ct_word(kTokNone, 0))) {
+        /* retiring leaves the entry the caller puts stale: only without one
+         * outstanding in this queue (else the whole chunk stays listed) */
+        if (n >= ppc && !(ct_stale(v) & stale_bit(k))) {
+            if (a_cas64(w, v, ct_word(kTokNone, ct_stale(v) | stale_bit(k)))) {
                 retire_chunk(h, c, k, t);
                 return;
             }
-        } else if (a_cas64(w, v, ct_word(tok_listed(k, pos), n))) {
+        } else if (a_cas64(w, v, ct_word(tok_listed(k, pos), n | ct_stale(v)))) {
             return;
         }
-        /* a concurrent free raised the count: look again */
+        /* a concurrent free raised the count, or a stale entry was dropped:
+         * look again */
     }
 }
 
@@ -1276,11 +1290,14 @@ __device__ __forceinline__ void chunk_serve_shard(const hbheap_dev_t& h, const G
                             continue;
                         }
                         stale = true;
+                        /* the chunk's stale entry in this queue is gone */
+                        __hip_atomic_fetch_and(w, ~(uint64_t)stale_bit(g.k), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        tl.spread += 1;
                         break;
                     }
                     tl.spread += 1;
                     if (a_cas64(w, x, ct_word(kTokHeld, (uint32_t)x))) {
-                        v = (int32_t)(uint32_t)x;
+                        v = (int32_t)ct_count(x);
                         break;
                     }
                     sure = true;
@@ -1341,9 +1358,13 @@ __device__ __forceinline__ void chunk_serve_shard(const hbheap_dev_t& h, const G
             /* every free page taken: give the token up -- unless frees came
              * in while it was held, which left it to this lane to list the
              * chunk again (or retire it) */
-            uint64_t x = ct_word(kTokHeld, t);
+            uint64_t x = a_load64(h.chunk_ct + c);
+            bool released = false;
             tl.spread += 1;
-            if (!a_cas64(h.chunk_ct + c, x, ct_word(kTokNone, 0))) {
+            /* held, and no page freed meanwhile: give it up (keep the stale flag) */
+            while (ct_count(x) == t && (uint32_t)(x >> 32) == kTokHeld)
+                if ((released = a_cas64(h.chunk_ct + c, x, ct_word(kTokNone, ct_stale(x))))) break;
+            if (!released) {
                 const uint32_t pos = a_add32(R.tail, 1u);
                 tl.headtail += 1;
                 list_or_retire(h, c, g.k, g.ppc, pos, t, tl);
@@ -1424,7 +1445,11 @@ __device__ __forceinline__ void chunk_serve_shard(const hbheap_dev_t& h, const G
                     tl.headtail += 1;
                     if (ev) {
                         /* listed at pos, with pages [u, ppc) free */
-                        const uint64_t was = a_xchg64(h.chunk_ct + cl, ct_word(tok_listed(g.k, pos), g.ppc - u));
+                        /* keep the stale flag, which a taker dropping an entry
+                         * of this chunk may clear meanwhile */
+                        uint64_t was = a_load64(h.chunk_ct + cl);
+                        while (!a_cas64(h.chunk_ct + cl, was, ct_word(tok_listed(g.k, pos), (g.ppc - u) | ct_stale(was))))
+                            tl.spread += 1;
                         tl.spread += 1;
                         pos += zero_after((uint32_t)was);
                     }
@@ -1860,18 +1885,21 @@ __device__ __forceinline__ uint32_t free_wave(const hbheap_dev_t& h, void* p, ui
              * allocator takes it first */
             const uint32_t ppc = 1u << (h.log2_chunk - 4u - k);
             const uint64_t ow = a_add64(h.chunk_ct + c, nnew);
-            const uint32_t otok = (uint32_t)(ow >> 32), n = (uint32_t)ow + nnew;
+            const uint32_t otok = (uint32_t)(ow >> 32), n = ct_count(ow) + nnew, st = ct_stale(ow);
             tl.spread += 1;
-            if (otok == kTokNone && (uint32_t)ow == 0) {
+            if (otok == kTokNone && ct_count(ow) == 0) {
                 if (n >= ppc) {
-                    uint64_t x = ct_word(kTokNone, n);
-                    retire = a_cas64(h.chunk_ct + c, x, ct_word(kTokNone, 0));
+                    /* whole at once, never listed: no stale entry left */
+                    uint64_t x = ct_word(kTokNone, n | st);
+                    retire = a_cas64(h.chunk_ct + c, x, ct_word(kTokNone, st));
                 } else {
                     cold = 0;
                 }
-            } else if (otok < kTokHeld && n >= ppc) {
-                uint64_t x = ct_word(otok, n);
-                retire = a_cas64(h.chunk_ct + c, x, ct_word(kTokNone, 0));
+            } else if (otok < kTokHeld && n >= ppc && !(st & stale_bit(k))) {
+                /* its entry becomes stale: only without one outstanding in
+                 * its queue */
+                uint64_t x = ct_word(otok, n | st);
+                retire = a_cas64(h.chunk_ct + c, x, ct_word(kTokNone, st | stale_bit(k)));
             }
         } else if (HBHEAP_VARIANT_LISTS_CHUNKS(h.variant) && nnew) {
             cold = (uint32_t)a_addi(h.chunk_cnt + c, (int32_t)nnew);

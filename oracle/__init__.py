@@ -81,6 +81,7 @@ class SnapReport(C.Structure):
         ("live", C.c_uint64 * MAX_CLASSES), ("chunks", C.c_uint64 * MAX_CLASSES),
         ("free_pages", C.c_uint64 * MAX_CLASSES),
         ("stale_entries", C.c_uint64), ("eager", C.c_uint32), ("pad", C.c_uint32),
+        ("whole_owned", C.c_uint64),
     ]
 
     def violations(self) -> dict:
@@ -178,7 +179,7 @@ class ModelResult(C.Structure):
 OP_ALLOC, OP_FREE_OWN, OP_FREE_GIVEN = 1, 2, 3
 MUTATIONS = {"no_hold": 1, "requeue_always": 2, "free_enqueue_always": 3, "no_refund": 4,
              "release_no_publish": 5, "publish_early": 6, "dry_always": 7,
-             "scan_no_positions": 8}
+             "scan_no_positions": 8, "eager_exact_position": 9, "eager_no_stale_bit": 11}
 
 
 def model_run(variant: int, n_chunks: int, ppc: int, leaders: list, prefill: int = 0, maxc: int | None = None,

@@ -58,8 +58,12 @@ enum {
     MUT_NONE = 0, MUT_NO_HOLD = 1, MUT_REQUEUE_ALWAYS = 2, MUT_FREE_ENQ_ALWAYS = 3,
     MUT_NO_REFUND = 4, MUT_RELEASE_NO_PUB = 5, MUT_PUBLISH_EARLY = 6,
     MUT_DRY_ALWAYS = 7, /* page alloc: first pass without a hold even when it refills */
-    MUT_SCAN_NO_POS = 8 /* the out-of-memory look ignores a gap between head and tail */
+    MUT_SCAN_NO_POS = 8, /* the out-of-memory look ignores a gap between head and tail */
+    MUT_EAGER_EXACT_POS = 9, /* eager: a taker accepts only its exact position (no lap swaps) */
+    MUT_EAGER_NO_STALE_FLAG = 11 /* eager: retire leaving a stale entry even with one outstanding */
 };
+#define TOK_NONE 0xFF
+#define TOK_HELD 0xFE
 
 /* ---------------- state ---------------- */
 
@@ -86,6 +90,15 @@ typedef struct {
     uint8_t granted[M_MAXOPS][M_MAXG]; /* pages granted by alloc ops      */
     uint8_t ngranted[M_MAXOPS];
     uint8_t failed[M_MAXOPS];  /* requests that got NULL                   */
+    /* eager retirement */
+    uint8_t dropped;           /* a stale entry was dropped this pass      */
+    uint8_t lpos[M_MAXG];      /* queue position a lane lists its chunk at */
+    uint8_t ppend[M_MAXG];     /* lane has an entry still to put           */
+    uint8_t xtok[M_MAXG], xn[M_MAXG], xst[M_MAXG]; /* free: the retire CAS's expected word */
+    uint8_t rq[M_MAXG];        /* chunk a lane retires (M_EMPTY: none)     */
+    uint8_t nret, rpos, ret_pc;
+    uint8_t pgot, ph0;         /* refill from the pool ring                */
+    uint8_t pch[M_MAXG];       /* chunks taken from the pool ring          */
 } leader_t;
 
 typedef struct {
@@ -97,12 +110,19 @@ typedef struct {
     uint8_t bits[M_MAXN];
     uint8_t given[M_MAXL][M_MAXG]; /* pages handed to leaders by prefill  */
     uint8_t ngiven[M_MAXL];
+    /* eager retirement: per chunk token (TOK_NONE, TOK_HELD or the queue
+     * position it is listed at); the pool ring of unowned chunks */
+    uint8_t tok[M_MAXN];
+    uint8_t stale[M_MAXN];     /* the chunk has a stale entry in the queue */
+    uint8_t pslot[M_MAXN];
+    uint8_t phead, ptail;
+    int8_t pcnt;
     leader_t L[M_MAXL];
 } mstate;
 
 typedef struct {
     const model_params* p;
-    int Q, N, P;
+    int Q, N, P, PQ;
     model_result* r;
     /* visited set: open addressing over stored states */
     mstate* tab;
@@ -270,8 +290,128 @@ static void check_oom(ctx* x, const mstate* s)
     if (visible > pending) violation(x, x->p->variant == 0 ? 61 : 62, &x->r->oom_violations);
 }
 
+
+/* ---------------- eager retirement (variant 2) invariants ---------------- */
+
+/* Is leader l in the middle of a free (its current op frees pages)? */
+static int in_free(const ctx* x, const mstate* s, int l)
+{
+    const leader_t* L = &s->L[l];
+    if (L->pc == 0 || L->pc == 99 || L->op >= x->p->n_ops[l]) return 0;
+    return x->p->ops[l][L->op].kind != OP_ALLOC;
+}
+
+/* Every reachable state: free count (less what holders will take off it)
+ * within the free bits; an unowned chunk
+ * has no bits, count or token; a held token is held by exactly one
+ * allocator lane; a chunk with free pages has a token unless a free that
+ * owns it is still listing it or a retirement of it is under way; a whole
+ * owned chunk is whole only while a free or an allocator is about to
+ * retire it. */
+static void check_tokens_eager(ctx* x, const mstate* s)
+{
+    for (int c = 0; c < x->N; ++c) {
+        /* a holder takes its pages off the count only when it puts the
+         * token back, possibly after clearing their bits */
+        int pending = 0;
+        for (int l = 0; l < x->p->n_leaders; ++l) {
+            const leader_t* L = &s->L[l];
+            if (L->pc < 100 || L->pc >= 140) continue;
+            for (int i = 0; i < M_MAXG; ++i)
+                if (L->tok[i] && L->c[i] == c) pending += L->t[i];
+        }
+        if (s->cnt[c] < 0 || s->cnt[c] - pending > popc8(s->bits[c])) { violation(x, 80 + c, &x->r->token_violations); return; }
+        if (!s->own[c] && (s->cnt[c] || s->bits[c] || s->tok[c] != TOK_NONE)) {
+            violation(x, 84 + c, &x->r->token_violations);
+            return;
+        }
+        int holders = 0, listing = 0;
+        for (int l = 0; l < x->p->n_leaders; ++l) {
+            const leader_t* L = &s->L[l];
+            for (int i = 0; i < M_MAXG; ++i) {
+                if (L->pc >= 100 && L->pc < 140 && L->tok[i] && L->c[i] == c) holders++;
+                if (in_free(x, s, l) && L->c[i] == c && (L->fpend[i] || L->enq[i] == 2)) listing++;
+            }
+        }
+        if ((s->tok[c] == TOK_HELD) != (holders == 1) || holders > 1) { violation(x, 88 + c, &x->r->token_violations); return; }
+        if (s->own[c] && s->cnt[c] > 0 && s->tok[c] == TOK_NONE && !listing) {
+            violation(x, 92 + c, &x->r->token_violations);
+            return;
+        }
+    }
+}
+
+/* A give-up (no hold in flight, no published entry, pool ring empty) with
+ * no free under way: no owned chunk may still have a free page. */
+static void check_oom_eager(ctx* x, const mstate* s)
+{
+    if (s->pcnt > 0) { violation(x, 63, &x->r->oom_violations); return; }
+    for (int l = 0; l < x->p->n_leaders; ++l)
+        if (in_free(x, s, l)) return;
+    for (int c = 0; c < x->N; ++c)
+        if (s->own[c] && s->cnt[c] > 0) { violation(x, 64, &x->r->oom_violations); return; }
+}
+
+/* Final state: the queue and the pool ring are consistent; every owned
+ * chunk has count = free bits; one with free pages is
+ * listed at a position in [head, tail) whose slot holds it; one without has
+ * no token; the pool ring holds exactly the unowned chunks. */
+static void check_final_eager(ctx* x, const mstate* s)
+{
+    const int N = x->N, Q = x->Q, PQ = x->PQ;
+    uint8_t used = (uint8_t)(s->tail - s->head);
+    if (s->H != 0 || s->cnt_pub != used || used > Q) { violation(x, 100, &x->r->final_violations); return; }
+    for (int i = 0; i < Q; ++i) {
+        int in = i < used;
+        uint8_t e = s->slot[(uint8_t)(s->head + i) % Q];
+        if (in != (e != M_EMPTY)) { violation(x, 101, &x->r->final_violations); return; }
+    }
+    uint8_t pused = (uint8_t)(s->ptail - s->phead);
+    if (s->pcnt != pused || pused > PQ) { violation(x, 102, &x->r->final_violations); return; }
+    int inpool[M_MAXN] = {0};
+    for (int i = 0; i < PQ; ++i) {
+        uint8_t e = s->pslot[(uint8_t)(s->phead + i) % PQ];
+        if ((i < pused) != (e != M_EMPTY)) { violation(x, 103, &x->r->final_violations); return; }
+        if (i < pused) {
+            if (e >= N || s->own[e] || inpool[e]) { violation(x, 104, &x->r->final_violations); return; }
+            inpool[e] = 1;
+        }
+    }
+    /* at most one stale entry per chunk, and the flag says whether it has one */
+    for (int c = 0; c < N; ++c) {
+        int nst = 0;
+        for (int i = 0; i < used; ++i) {
+            uint8_t p = (uint8_t)(s->head + i);
+            if (s->slot[p % Q] == c && !(s->own[c] && s->cnt[c] > 0 && s->tok[c] == p)) nst++;
+        }
+        if (nst > 1 || s->stale[c] != (nst == 1)) { violation(x, 109, &x->r->final_violations); return; }
+    }
+    for (int c = 0; c < N; ++c) {
+        if (!s->own[c]) {
+            if (!inpool[c]) { violation(x, 105, &x->r->final_violations); return; }
+            continue;
+        }
+        /* a whole chunk may stay listed (a stale entry of its queue blocked
+         * its retirement) */
+        if (s->cnt[c] != popc8(s->bits[c])) { violation(x, 106, &x->r->final_violations); return; }
+        if (s->cnt[c] == 0) {
+            if (s->tok[c] != TOK_NONE) { violation(x, 107, &x->r->final_violations); return; }
+            continue;
+        }
+        uint8_t p = s->tok[c];
+        if (p >= TOK_HELD || (uint8_t)(p - s->head) >= used || s->slot[p % Q] != c) {
+            violation(x, 108, &x->r->final_violations);
+            return;
+        }
+    }
+}
+
 static void check_final(ctx* x, const mstate* s)
 {
+    if (x->p->variant == 2) {
+        check_final_eager(x, s);
+        if (x->r->final_violations) return;
+    }
     int N = x->N, P = x->P, Q = x->Q;
     uint8_t used = (uint8_t)(s->tail - s->head);
     if (s->H != 0 || s->cnt_pub != used || used > Q) { violation(x, 70, &x->r->final_violations); return; }
@@ -307,11 +447,12 @@ static void check_final(ctx* x, const mstate* s)
     int freeb = 0, owned = 0;
     for (int c = 0; c < N; ++c) {
         if (s->own[c]) { owned++; freeb += popc8(s->bits[c]); }
-        if (x->p->variant == 0 && s->cnt[c] != popc8(s->bits[c])) { violation(x, 77, &x->r->final_violations); return; }
+        if (x->p->variant != 1 && s->cnt[c] != popc8(s->bits[c])) { violation(x, 77, &x->r->final_violations); return; }
     }
-    if (owned != (s->bump < N ? s->bump : N)) { violation(x, 78, &x->r->final_violations); return; }
+    if (x->p->variant != 2 && owned != (s->bump < N ? s->bump : N)) { violation(x, 78, &x->r->final_violations); return; }
     if (owned * P - freeb != live) { violation(x, 79, &x->r->final_violations); return; }
-    check_tokens(x, s);
+    if (x->p->variant == 2) check_tokens_eager(x, s);
+    else check_tokens(x, s);
 }
 
 /* ---------------- transitions ---------------- */
@@ -346,12 +487,15 @@ static void start_op(ctx* x, mstate* s, int l)
     L->lo_chunk = M_EMPTY;
     L->lo_tok = 0;
     L->i = 0;
+    memset(L->rq, M_EMPTY, sizeof(L->rq));
+    memset(L->ppend, 0, sizeof(L->ppend));
+    L->nret = 0;
     if (o->kind == OP_ALLOC) {
         L->need = (uint8_t)o->a;
         L->served = 0;
         L->ngranted[L->op] = (uint8_t)o->a;
         memset(L->granted[L->op], M_EMPTY, M_MAXG);
-        L->pc = x->p->variant == 0 ? 1 : 20;
+        L->pc = x->p->variant == 0 ? 1 : (x->p->variant == 2 ? 100 : 20);
     } else {
         /* the pages to free, one per lane */
         int n = 0;
@@ -763,7 +907,7 @@ static int step(ctx* x, mstate* s, int l)
     }
     /* ---------------- free (both variants) ---------------- */
     case 40: {
-        if (L->i >= L->need) { L->i = 0; L->pc = x->p->variant == 0 ? 41 : 42; return 1; }
+        if (L->i >= L->need) { L->i = 0; L->pc = x->p->variant == 0 ? 41 : (x->p->variant == 2 ? 141 : 42); return 1; }
         uint8_t pg = L->c[L->i];
         if (pg == M_EMPTY) { L->i++; return 1; } /* NULL: nothing to free */
         uint8_t bit = (uint8_t)(1u << (pg % P));
@@ -823,6 +967,408 @@ static int step(ctx* x, mstate* s, int l)
         L->fpub = 0;
         finish_op(x, s, l);
         return 1;
+    /* ---------------- eager retirement (variant 2): alloc ----------------
+     * 100 reserve  101 refund  102 head  103 take slot(i)  104 claim token(i)
+     * 105 tail for kept  106 put token back / retire(i)  107 put slot(i)
+     * 108 release token(i)  109 tail(i)  110 put token back(i)  131 put slot(i)
+     * 132 publish(i)  111 early release  112 pick bits(i)  113 clear bits(i)
+     * 118 early pass done  115 refill?  116 pool reserve  117 pool refund
+     * 119 pool head  120 take pool slot(i)  121 refill init  122 tail
+     * 125 token of the leftover  126 put slot  123 release  124 oom decide */
+    case 100: {
+        L->want = (uint8_t)want_chunks(x, L);
+        int c_old = s->cnt_pub;
+        s->cnt_pub -= L->want;
+        s->H++;
+        int got = c_old <= 0 ? 0 : (c_old < L->want ? c_old : L->want);
+        L->got = (uint8_t)got;
+        L->took = 0;
+        L->dropped = 0;
+        L->publish = 0;
+        L->nrq = 0;
+        L->pc = got < L->want ? 101 : 102;
+        return 1;
+    }
+    case 101:
+        s->cnt_pub += L->want - L->got;
+        L->pc = 102;
+        return 1;
+    case 102:
+        if (L->got) { L->h0 = s->head; s->head = (uint8_t)(s->head + L->got); L->i = 0; L->pc = 103; }
+        else { L->early = 0; L->pc = 115; }
+        return 1;
+    case 103: {
+        uint8_t* sl = &s->slot[(uint8_t)(L->h0 + L->i) % Q];
+        if (*sl == M_EMPTY) return 0;
+        L->c[L->i] = *sl;
+        *sl = M_EMPTY;
+        L->pc = 104;
+        return 1;
+    }
+    case 104: {
+        /* the token, if it names this position modulo Q, becomes held */
+        int i = L->i;
+        uint8_t c = L->c[i], tk = s->tok[c], pos = (uint8_t)(L->h0 + i);
+        int match = tk < TOK_HELD && (mut == MUT_EAGER_EXACT_POS ? tk == pos : (tk % Q) == (pos % Q));
+        if (match) { s->tok[c] = TOK_HELD; L->v[i] = s->cnt[c]; L->tok[i] = 1; }
+        else { L->v[i] = 0; L->tok[i] = 0; L->dropped = 1; s->stale[c] = 0; }
+        if (++L->i < L->got) { L->pc = 103; return 1; }
+        int pre = 0, sum_t = 0;
+        for (int q = 0; q < L->got; ++q) {
+            int vc = L->v[q] > 0 ? (L->v[q] < L->need ? L->v[q] : L->need) : 0;
+            int t = pre < L->need ? ((L->need - pre) < vc ? (L->need - pre) : vc) : 0;
+            L->t[q] = (uint8_t)t;
+            L->left[q] = (uint8_t)t;
+            L->keep[q] = (uint8_t)(L->v[q] > 0 && (t == 0 || L->v[q] > t));
+            pre += vc;
+            sum_t += t;
+        }
+        L->early = (uint8_t)!(L->got < L->want && L->need > sum_t);
+        L->i = 0;
+        L->pc = L->early ? 105 : 112;
+        return 1;
+    }
+    case 105: {
+        int n = 0;
+        for (int q = 0; q < L->got; ++q)
+            if (L->keep[q]) L->lpos[q] = (uint8_t)(s->tail + n++);
+        L->nrq = (uint8_t)n;
+        s->tail = (uint8_t)(s->tail + n);
+        L->i = 0;
+        L->pc = 106;
+        return 1;
+    }
+    case 106: {
+        int q = L->i;
+        while (q < L->got && !(L->keep[q] && L->tok[q])) q++;
+        if (q >= L->got) { L->i = 0; L->pc = 108; return 1; }
+        uint8_t c = L->c[q];
+        int n = s->cnt[c] - L->t[q];
+        L->tok[q] = 0;
+        L->ppend[q] = 1;
+        L->i = (uint8_t)q;
+        if (n >= P && (!s->stale[c] || mut == MUT_EAGER_NO_STALE_FLAG)) {
+            s->tok[c] = TOK_NONE; s->cnt[c] = 0; s->stale[c] = 1;
+            L->rq[q] = c; L->ret_pc = 107; L->pc = 160;
+        } else {
+            s->tok[c] = L->lpos[q]; s->cnt[c] = (int8_t)n;
+            L->pc = 107;
+        }
+        return 1;
+    }
+    case 107: {
+        uint8_t* sl = &s->slot[L->lpos[L->i] % Q];
+        if (*sl != M_EMPTY) return 0;
+        *sl = L->c[L->i];
+        L->ppend[L->i] = 0;
+        L->i++;
+        L->pc = 106;
+        return 1;
+    }
+    case 108: {
+        int q = L->i;
+        while (q < L->got && !(!L->keep[q] && L->tok[q])) q++;
+        if (q >= L->got) { L->pc = 111; return 1; }
+        uint8_t c = L->c[q];
+        if (s->tok[c] == TOK_HELD && s->cnt[c] == L->t[q]) {
+            s->cnt[c] = 0; s->tok[c] = TOK_NONE;
+            L->tok[q] = 0;
+            L->i = (uint8_t)(q + 1);
+            return 1;
+        }
+        L->i = (uint8_t)q;  /* frees came in while it was held: list it after all */
+        L->pc = 109;
+        return 1;
+    }
+    case 109:
+        L->lpos[L->i] = s->tail;
+        s->tail = (uint8_t)(s->tail + 1);
+        L->pc = 110;
+        return 1;
+    case 110: {
+        int q = L->i;
+        uint8_t c = L->c[q];
+        int n = s->cnt[c] - L->t[q];
+        L->tok[q] = 0;
+        L->ppend[q] = 1;
+        if (n >= P && (!s->stale[c] || mut == MUT_EAGER_NO_STALE_FLAG)) {
+            s->tok[c] = TOK_NONE; s->cnt[c] = 0; s->stale[c] = 1;
+            L->rq[q] = c; L->ret_pc = 131; L->pc = 160;
+        } else {
+            s->tok[c] = L->lpos[q]; s->cnt[c] = (int8_t)n;
+            L->pc = 131;
+        }
+        return 1;
+    }
+    case 131: {
+        uint8_t* sl = &s->slot[L->lpos[L->i] % Q];
+        if (*sl != M_EMPTY) return 0;
+        *sl = L->c[L->i];
+        L->ppend[L->i] = 0;
+        L->pc = 132;
+        return 1;
+    }
+    case 132:
+        s->cnt_pub += 1;
+        L->i++;
+        L->pc = 108;
+        return 1;
+    case 111:
+        if (L->early) {
+            s->cnt_pub += L->nrq;
+            s->H--;
+            L->i = 0;
+            L->pc = 112;
+        } else {
+            L->pc = 115;
+        }
+        return 1;
+    case 112: {
+        while (L->i < L->got && L->left[L->i] == 0) L->i++;
+        if (L->i >= L->got) { L->i = 0; L->pc = L->early ? 118 : 105; return 1; }
+        uint8_t x8 = s->bits[L->c[L->i]];
+        uint8_t pick = 0;
+        for (int b = 0, n = 0; b < P && n < L->left[L->i]; ++b)
+            if ((x8 >> b) & 1) { pick |= (uint8_t)(1u << b); n++; }
+        if (!pick) return 0;
+        L->pick = pick;
+        L->pc = 113;
+        return 1;
+    }
+    case 113: {
+        uint8_t* w = &s->bits[L->c[L->i]];
+        uint8_t won = *w & L->pick;
+        *w = (uint8_t)(*w & ~L->pick);
+        for (int b = 0; b < P; ++b)
+            if ((won >> b) & 1) {
+                L->granted[L->op][L->served + L->took] = (uint8_t)(L->c[L->i] * P + b);
+                L->took++;
+                L->left[L->i]--;
+            }
+        L->pc = 112;
+        return 1;
+    }
+    case 118:
+        L->need = (uint8_t)(L->need - L->took);
+        L->served = (uint8_t)(L->served + L->took);
+        L->early = 0;
+        if (L->got > 0 && L->took == 0 && !L->dropped && L->need > 0) { L->pc = 124; return 1; }
+        if (L->need > 0) { L->pc = 100; return 1; }
+        finish_op(x, s, l);
+        return 1;
+    case 115:
+        L->need = (uint8_t)(L->need - L->took);
+        L->served = (uint8_t)(L->served + L->took);
+        L->publish = L->nrq;
+        L->exhausted = 0;
+        if (L->got < L->want && L->need > 0) {
+            L->m = (uint8_t)((L->need + P - 1) / P);
+            L->pc = 116;
+        } else {
+            L->pc = 123;
+        }
+        return 1;
+    case 116: {
+        int c_old = s->pcnt;
+        if (c_old <= 0) { L->gm = 0; L->exhausted = 1; L->pc = 123; return 1; }
+        s->pcnt = (int8_t)(s->pcnt - L->m);
+        L->gm = (uint8_t)(c_old < L->m ? c_old : L->m);
+        L->exhausted = (uint8_t)(L->gm < L->m);
+        L->pc = L->gm < L->m ? 117 : 119;
+        return 1;
+    }
+    case 117:
+        s->pcnt = (int8_t)(s->pcnt + L->m - L->gm);
+        L->pc = 119;
+        return 1;
+    case 119:
+        L->ph0 = s->phead;
+        s->phead = (uint8_t)(s->phead + L->gm);
+        L->i = 0;
+        L->pc = 120;
+        return 1;
+    case 120: {
+        if (L->i >= L->gm) { L->pc = 121; return 1; }
+        uint8_t* sl = &s->pslot[(uint8_t)(L->ph0 + L->i) % x->PQ];
+        if (*sl == M_EMPTY) return 0;
+        L->pch[L->i] = *sl;
+        *sl = M_EMPTY;
+        L->i++;
+        return 1;
+    }
+    case 121: {
+        int gm = L->gm, cap = gm * P;
+        int r = cap < L->need ? cap : L->need;
+        for (int j = 0; j < gm; ++j) s->own[L->pch[j]] = 1;
+        for (int q = 0; q < r; ++q)
+            L->granted[L->op][L->served + q] = (uint8_t)(L->pch[q / P] * P + q % P);
+        if (cap > L->need) {
+            uint8_t last = L->pch[gm - 1];
+            int u = L->need - (gm - 1) * P;
+            L->lo_chunk = last;
+            L->lo_u = (uint8_t)u;
+            s->bits[last] = (uint8_t)(full_mask(P) & ~((1u << u) - 1u));
+            L->lo_tok = 1;
+            L->pc = 122;
+        } else {
+            L->pc = 123;
+        }
+        L->need = (uint8_t)(L->need - r);
+        L->served = (uint8_t)(L->served + r);
+        return 1;
+    }
+    case 122:
+        L->t0 = s->tail;
+        s->tail = (uint8_t)(s->tail + 1);
+        L->pc = 125;
+        return 1;
+    case 125:
+        s->tok[L->lo_chunk] = L->t0;
+        s->cnt[L->lo_chunk] = (int8_t)(P - L->lo_u);
+        L->pc = 126;
+        return 1;
+    case 126: {
+        uint8_t* sl = &s->slot[L->t0 % Q];
+        if (*sl != M_EMPTY) return 0;
+        *sl = L->lo_chunk;
+        L->lo_tok = 0;
+        L->publish = (uint8_t)(L->publish + 1);
+        L->pc = 123;
+        return 1;
+    }
+    case 123:
+        s->cnt_pub += L->publish;
+        s->H--;
+        L->lo_chunk = M_EMPTY;
+        if (L->need > 0 && L->got < L->want && L->exhausted) { L->pc = 124; return 1; }
+        if (L->got > 0 && L->took == 0 && !L->dropped && L->need > 0) { L->pc = 124; return 1; }
+        if (L->need > 0) { L->pc = 100; return 1; }
+        finish_op(x, s, l);
+        return 1;
+    case 124:
+        if (s->cnt_pub > 0 || s->pcnt > 0) { L->pc = 100; return 1; }
+        if (in_flight(x, s)) return 0;
+        check_oom_eager(x, s);
+        L->failed[L->op] = L->need;
+        finish_op(x, s, l);
+        return 1;
+    /* ---------------- eager retirement (variant 2): free ----------------
+     * 40 set bit(i)  141 count add(i)  142 retire CAS(i)  143 tail for owners
+     * 144 list or retire(i)  145 put slot(i)  146 publish */
+    case 141: {
+        if (L->i >= L->need) { L->i = 0; L->pc = 142; return 1; }
+        uint8_t pg = L->c[L->i];
+        L->enq[L->i] = 0;
+        if (pg != M_EMPTY) {
+            uint8_t c = (uint8_t)(pg / P);
+            int old = s->cnt[c], n = old + 1;
+            uint8_t otok = s->tok[c];
+            s->cnt[c] = (int8_t)n;
+            L->c[L->i] = c;
+            L->xst[L->i] = s->stale[c];
+            if (otok == TOK_NONE && old == 0) {
+                if (n >= P) { L->enq[L->i] = 2; L->xtok[L->i] = TOK_NONE; L->xn[L->i] = (uint8_t)n; }
+                else { L->enq[L->i] = 1; L->fpend[L->i] = 1; }
+            } else if (otok < TOK_HELD && n >= P && (!s->stale[c] || mut == MUT_EAGER_NO_STALE_FLAG)) {
+                L->enq[L->i] = 2; L->xtok[L->i] = otok; L->xn[L->i] = (uint8_t)n;
+            }
+        }
+        L->i++;
+        return 1;
+    }
+    case 142: {
+        int q = L->i;
+        while (q < L->need && L->enq[q] != 2) q++;
+        if (q >= L->need) {
+            L->i = 0;
+            int n = 0;
+            for (int j = 0; j < L->need; ++j) n += L->rq[j] != M_EMPTY;
+            if (n) { L->ret_pc = 143; L->pc = 160; } else { L->pc = 143; }
+            return 1;
+        }
+        uint8_t c = L->c[q];
+        if (s->tok[c] == L->xtok[q] && s->cnt[c] == L->xn[q] && (s->stale[c] == L->xst[q] || mut == MUT_EAGER_NO_STALE_FLAG)) {
+            /* retiring a listed chunk leaves its entry stale */
+            if (L->xtok[q] != TOK_NONE) s->stale[c] = 1;
+            s->tok[c] = TOK_NONE; s->cnt[c] = 0; L->rq[q] = c;
+        }
+        L->enq[q] = 0;
+        L->i = (uint8_t)(q + 1);
+        return 1;
+    }
+    case 143: {
+        int n = 0;
+        for (int q = 0; q < L->need; ++q)
+            if (L->enq[q] == 1) L->lpos[q] = (uint8_t)(s->tail + n++);
+        L->nrq = (uint8_t)n;
+        if (!n) { finish_op(x, s, l); return 1; }
+        s->tail = (uint8_t)(s->tail + n);
+        L->i = 0;
+        L->pc = 144;
+        return 1;
+    }
+    case 144: {
+        int q = L->i;
+        while (q < L->need && !(L->enq[q] == 1 && L->fpend[q])) q++;
+        if (q >= L->need) { L->pc = 146; return 1; }
+        uint8_t c = L->c[q];
+        L->i = (uint8_t)q;
+        if (s->cnt[c] >= P && (!s->stale[c] || mut == MUT_EAGER_NO_STALE_FLAG)) {
+            s->tok[c] = TOK_NONE; s->cnt[c] = 0; s->stale[c] = 1;
+            L->rq[q] = c; L->ret_pc = 145; L->pc = 160;
+        } else {
+            s->tok[c] = L->lpos[q];
+            L->pc = 145;
+        }
+        return 1;
+    }
+    case 145: {
+        uint8_t* sl = &s->slot[L->lpos[L->i] % Q];
+        if (*sl != M_EMPTY) return 0;
+        *sl = L->c[L->i];
+        L->fpend[L->i] = 0;
+        L->fpub |= (uint8_t)(1u << L->i);
+        L->i++;
+        L->pc = 144;
+        return 1;
+    }
+    case 146:
+        s->cnt_pub += L->nrq;
+        L->fpub = 0;
+        finish_op(x, s, l);
+        return 1;
+    /* ---------------- eager retirement: the chunks in rq[] go to the pool
+     * 160 reset (bits, class)  161 pool tail  162 put pool slot(i)  163 publish */
+    case 160: {
+        int n = 0;
+        for (int q = 0; q < M_MAXG; ++q)
+            if (L->rq[q] != M_EMPTY) { s->bits[L->rq[q]] = 0; s->own[L->rq[q]] = 0; n++; }
+        L->nret = (uint8_t)n;
+        L->pc = n ? 161 : L->ret_pc;
+        return 1;
+    }
+    case 161:
+        L->rpos = s->ptail;
+        s->ptail = (uint8_t)(s->ptail + L->nret);
+        L->pgot = 0;
+        L->pc = 162;
+        return 1;
+    case 162: {
+        int q = 0;
+        while (q < M_MAXG && L->rq[q] == M_EMPTY) q++;
+        if (q >= M_MAXG) { L->pc = 163; return 1; }
+        uint8_t* sl = &s->pslot[(uint8_t)(L->rpos + L->pgot) % x->PQ];
+        if (*sl != M_EMPTY) return 0;
+        *sl = L->rq[q];
+        L->rq[q] = M_EMPTY;
+        L->pgot++;
+        return 1;
+    }
+    case 163:
+        s->pcnt = (int8_t)(s->pcnt + L->nret);
+        L->nret = 0;
+        L->pc = L->ret_pc;
+        return 1;
     default:
         return 0;
     }
@@ -864,7 +1410,7 @@ static void explore(ctx* x, const mstate* init)
             mstate t = s;
             if (!step(x, &t, l)) continue;
             moved = 1;
-            if (x->frozen < 0) check_tokens(x, &t);
+            if (x->frozen < 0) { if (x->p->variant == 2) check_tokens_eager(x, &t); else check_tokens(x, &t); }
             int v = visit(x, &t);
             if (v < 0) { x->r->truncated = 1; continue; }
             if (v == 1) push(&st, &t);
@@ -906,6 +1452,12 @@ static int build_init(ctx* x, mstate* s)
     memset(s, 0, sizeof(*s));
     memset(s->slot, M_EMPTY, sizeof(s->slot));
     memset(s->given, M_EMPTY, sizeof(s->given));
+    /* eager retirement: no tokens; the pool ring holds every chunk */
+    memset(s->tok, TOK_NONE, sizeof(s->tok));
+    memset(s->pslot, M_EMPTY, sizeof(s->pslot));
+    for (int c = 0; c < x->N; ++c) s->pslot[c] = (uint8_t)c;
+    s->ptail = (uint8_t)x->N;
+    s->pcnt = (int8_t)x->N;
     for (int l = 0; l < M_MAXL; ++l) s->L[l].pc = 0;
     int pages[M_MAXN * M_MAXP];
     int np = 0;
@@ -960,10 +1512,14 @@ int orc_model_run(const orc_model_params* p, orc_model_result* r)
     x.r = r;
     x.N = p->n_chunks;
     x.P = p->ppc;
-    int entries = p->variant == 0 ? p->n_chunks : p->n_chunks * p->ppc;
+    /* eager retirement: twice the chunks, room for stale entries */
+    int entries = p->variant == 0 ? p->n_chunks : (p->variant == 2 ? 2 * p->n_chunks : p->n_chunks * p->ppc);
     x.Q = 1;
     while (x.Q < entries) x.Q *= 2;
     if (x.Q > M_MAXQ) return -1;
+    x.PQ = 1;
+    while (x.PQ < p->n_chunks) x.PQ *= 2;
+    if (p->variant < 0 || p->variant > 2) return -1;
     x.frozen = -1;
     mstate init;
     if (!build_init(&x, &init)) return -2;

@@ -822,9 +822,15 @@ static int snap_open(const uint8_t* s, uint64_t len, snapview* v)
 /* Eager retirement: free pages and token of chunk c. */
 #define TOK_NONE 0xFFFFFFFFu
 #define TOK_HELD 0xFFFFFFFEu
+/* Eager retirement: the count half holds the free pages in bits 0..15 and,
+ * in bit 16 + k, whether the chunk has a stale entry in the queue of class k. */
 static uint32_t sv_count(const snapview* v, uint64_t c)
 {
-    return v->ct ? (uint32_t)rd64(v->ct + c * 8) : rd32(v->cnt + c * 4);
+    return v->ct ? ((uint32_t)rd64(v->ct + c * 8) & 0xFFFFu) : rd32(v->cnt + c * 4);
+}
+static int sv_stale_flag(const snapview* v, uint64_t c, uint32_t k)
+{
+    return ((uint32_t)rd64(v->ct + c * 8) >> (16 + k)) & 1u;
 }
 static uint32_t sv_token(const snapview* v, uint64_t c) { return (uint32_t)(rd64(v->ct + c * 8) >> 32); }
 
@@ -1099,9 +1105,9 @@ int orc_check_snapshot(const uint8_t* snap, uint64_t len, orc_snap_report* rep)
              * retired), none is held, and one without free pages has no
              * token (the listed ones are checked with the rings) */
             uint32_t tk = sv_token(&v, c);
-            if (cn >= ppc || tk == TOK_HELD || (cn == 0 && tk != TOK_NONE) || (cn > 0 && tk == TOK_NONE) ||
-                rd32(v.cnt + c * 4) != 0)
+            if (tk == TOK_HELD || (cn == 0 && tk != TOK_NONE) || (cn > 0 && tk == TOK_NONE) || rd32(v.cnt + c * 4) != 0)
                 rep->bad_count++;
+            if (cn >= ppc) rep->whole_owned++;
         }
         rep->chunks[k]++;
         chunks_sk[(uint64_t)j * v.K + k]++;
@@ -1148,7 +1154,8 @@ int orc_check_snapshot(const uint8_t* snap, uint64_t len, orc_snap_report* rep)
     for (uint32_t k = 0; k < v.K; ++k) sum += rep->chunks[k];
     if (sum != v.N) rep->bad_conservation++;
 
-    /* rings */
+    /* rings (eager retirement: stale entries counted per chunk) */
+    uint8_t* nstale = (uint8_t*)calloc(v.N ? v.N * v.K : 1, 1);
     for (uint32_t j = 0; j < v.S; ++j) {
         uint64_t lo = (uint64_t)j << v.log2_span, hi = lo + (1ull << v.log2_span);
         if (hi > v.N) hi = v.N;
@@ -1181,6 +1188,7 @@ int orc_check_snapshot(const uint8_t* snap, uint64_t len, orc_snap_report* rep)
                         /* eager retirement: an entry whose chunk's token names
                          * another listing is stale (dropped when taken) */
                         rep->stale_entries++;
+                        if (nstale[(uint64_t)c * v.K + k] < 255) nstale[(uint64_t)c * v.K + k]++;
                         continue;
                     }
                     if (c < lo || c >= hi || v.cls[c] != k || sv_count(&v, c) == 0) { rep->bad_ring_entry++; continue; }
@@ -1215,6 +1223,18 @@ int orc_check_snapshot(const uint8_t* snap, uint64_t len, orc_snap_report* rep)
             }
         }
     }
+    /* eager retirement: at most one stale entry per chunk in each queue,
+     * and the chunk's bit for that class says whether it has one */
+    if (v.eager)
+        for (uint64_t c = 0; c < v.N; ++c) {
+            if ((uint32_t)rd64(v.ct + c * 8) >> (16 + v.K)) rep->bad_count++;
+            for (uint32_t k = 0; k < v.K; ++k) {
+                uint8_t n = nstale[c * v.K + k];
+                if (n > 1) rep->bad_ring_dup++;
+                else if (sv_stale_flag(&v, c, k) != (n == 1)) rep->bad_count++;
+            }
+        }
+    free(nstale);
     if (is_va((int)v.variant)) check_va(&v, chunks_sk, rep);
     if (is_vl((int)v.variant)) check_vl(&v, chunks_sk, rep);
     free(seen);

@@ -135,6 +135,8 @@ typedef struct {
     uint64_t live[ORC_MAX_CLASSES], chunks[ORC_MAX_CLASSES], free_pages[ORC_MAX_CLASSES];
     uint64_t stale_entries;       /* eager retirement: queue entries no token names */
     uint32_t eager, pad;
+    uint64_t whole_owned;         /* eager retirement: owned chunks with every page free
+                                     (kept while a stale entry of theirs blocked it) */
 } orc_snap_report;
 
 /* Quiescent-state consistency of a snapshot (documented layout, version 3). */

@@ -203,7 +203,7 @@ __device__ __forceinline__ TrimKey trim_key(const hbheap_dev_t& h, uint64_t c)
         return t;
     }
     if (HBHEAP_VARIANT_LISTS_CHUNKS(h.variant)) {
-        const bool listed = eager(h) ? (uint32_t)h.chunk_ct[c] > 0 : h.chunk_cnt[c] > 0;
+        const bool listed = eager(h) ? ct_count(h.chunk_ct[c]) > 0 : h.chunk_cnt[c] > 0;
         t.key = listed ? j * h.n_classes + k : h.n_shards * (h.n_classes + 1);
         t.weight = listed ? 1u : 0u;
     } else {
@@ -341,7 +341,7 @@ __global__ void __launch_bounds__(kTrimBlock) k_trim_write(hbheap_dev_t h, const
                 if (idx < h.n_chunks) h.pool_ids[idx] = (uint32_t)c;
             } else if (h.variant == HBHEAP_VARIANT_CHUNK) {
                 if (pos < Q) h.slots[(uint64_t)key * Q + pos] = (uint32_t)c;
-                if (eager(h)) h.chunk_ct[c] = ct_word(tok_listed(kk, pos), (uint32_t)h.chunk_ct[c]);
+                if (eager(h)) h.chunk_ct[c] = ct_word(tok_listed(kk, pos), ct_count(h.chunk_ct[c]));
             } else if (HBHEAP_VARIANT_SEGMENTED(h.variant) && HBHEAP_VARIANT_LISTS_CHUNKS(h.variant)) {
                 const uint64_t seg = va_first_seg(h, totals, j, kk) + (pos >> h.log2_seg);
                 if (seg < h.vsegs)
@@ -374,8 +374,9 @@ __global__ void __launch_bounds__(kTrimBlock) k_trim_write(hbheap_dev_t h, const
             }
         }
     }
-    /* eager retirement: an owned chunk with no free page has no token */
-    if (eager(h) && c < h.n_chunks && t.weight == 0 && h.chunk_class[c] != kFreeClass)
+    /* eager retirement: an owned chunk with no free page has no token; the
+     * queues were rewritten without stale entries, so no flag stays set */
+    if (eager(h) && c < h.n_chunks && (h.chunk_class[c] == kFreeClass || t.weight == 0))
         h.chunk_ct[c] = ct_word(kTokNone, 0);
 }
 

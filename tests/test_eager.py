@@ -133,6 +133,9 @@ def test_eager_mode_is_for_the_chunk_variant_of_a_fresh_heap():
 # ---------------------------------------------------------------------------
 
 TOK_NONE, TOK_HELD = 0xFFFFFFFF, 0xFFFFFFFE
+def STALE(k):
+    """Count-word bit: the chunk has a stale entry in the queue of class k."""
+    return 1 << (16 + k)
 
 
 def tok(k, pos):
@@ -196,9 +199,10 @@ def eager_state():
     """8 chunks of 4 KiB (K = 9; class 7 = 2 KiB pages, 2 per chunk; class
     0 = 16 B, 256 per chunk).  Chunk 0: class 7, page 1 free, listed at
     position 5 of its queue (head 4: position 4 holds a stale entry of
-    chunk 6).  Chunk 1: class 7, both pages live (no token).  Chunk 2: class
-    0, 255 pages free, listed at position 0.  Chunks 3..7 unowned; the pool
-    ring holds them from head 9 in the order 5, 6, 3, 4, 7."""
+    chunk 6, whose count word carries the stale bit of class 7).  Chunk 1: class 7,
+    both pages live (no token).  Chunk 2: class 0, 255 pages free, listed at
+    position 0.  Chunks 3..7 unowned; the pool ring holds them from head 9
+    in the order 5, 6, 3, 4, 7."""
     N, log2C = 8, 12
     full = (1 << 64) - 1
     cls = [7, 7, 0] + [0xFF] * 5
@@ -206,6 +210,7 @@ def eager_state():
     bits[0][0] = 0b10
     bits[2] = [full - 1, full, full, full]
     ct = [(tok(7, 5), 1), (TOK_NONE, 0), (tok(0, 0), 255)] + [(TOK_NONE, 0)] * 5
+    ct[6] = (TOK_NONE, STALE(7))
     pool = (9, [5, 6, 3, 4, 7])
     rings = {7: (4, [6, 0]), 0: (0, [2])}
     return N, log2C, cls, bits, ct, pool, rings
@@ -233,11 +238,15 @@ def _planted(mut):
 
 
 def test_eager_checker_finds_planted_mistakes():
-    # a whole chunk still owned (a retirement missed)
-    def whole(cls, bits, ct, rings):
-        bits[0][0] = 0b11
-        ct[0] = (tok(7, 5), 2)
-    assert "bad_count" in _planted(whole)
+    # a whole chunk still listed is legal (a stale entry of its queue can
+    # block its retirement), and reported
+    N, log2C, cls, bits, ct, pool, rings = eager_state()
+    bits = [list(x) for x in bits]
+    bits[0][0] = 0b11
+    ct = list(ct)
+    ct[0] = (tok(7, 5), 2)
+    rep = check(N, log2C, cls, bits, ct, pool, rings)
+    assert rep.violations() == {} and rep.whole_owned == 1
     # a chunk with free pages whose token names no entry
     def moved(cls, bits, ct, rings):
         ct[0] = (tok(7, 6), 1)
@@ -259,6 +268,32 @@ def test_eager_checker_finds_planted_mistakes():
     def miscount(cls, bits, ct, rings):
         ct[2] = (tok(0, 0), 254)
     assert "bad_count" in _planted(miscount)
+    # a stale entry without the flag, or the flag without a stale entry
+    def noflag(cls, bits, ct, rings):
+        ct[6] = (TOK_NONE, 0)
+    assert "bad_count" in _planted(noflag)
+    def flagonly(cls, bits, ct, rings):
+        ct[3] = (TOK_NONE, STALE(2))
+    assert "bad_count" in _planted(flagonly)
+    # the bit of another queue than the one holding the stale entry
+    def otherqueue(cls, bits, ct, rings):
+        ct[6] = (TOK_NONE, STALE(0))
+    assert "bad_count" in _planted(otherqueue)
+    # a bit beyond the classes
+    def beyond(cls, bits, ct, rings):
+        ct[6] = (TOK_NONE, STALE(7) | STALE(9))
+    assert "bad_count" in _planted(beyond)
+    # two stale entries of one chunk (the queue could overflow)
+    def twostale(cls, bits, ct, rings):
+        rings[7] = (3, [6, 6, 0])
+        ct[0] = (tok(7, 5), 1)
+    assert "bad_ring_dup" in _planted(twostale)
+    # the flag does not count as free pages
+    def flagged_live(cls, bits, ct, rings):
+        ct[2] = (tok(0, 0), 255 | STALE(0))
+        rings[0] = (0, [2])
+    v = _planted(flagged_live)
+    assert "bad_count" in v  # chunk 2 has no stale entry
     # the token names the entry but the chunk belongs to another class
     def wrongclass(cls, bits, ct, rings):
         rings[0] = (0, [0])

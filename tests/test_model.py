@@ -35,6 +35,20 @@ CONFIGS = {
 }
 OVERASK = ("overask_free_own", "overask_free_given", "overask_free_one")
 
+# eager retirement (variant 2 of the model: chunk queues whose chunks return
+# to a pool ring as soon as every page is free; each entry names a listing
+# through the chunk's token, stale entries are dropped).  churn3 exceeds the
+# state budget there; two configurations are added: one where a chunk is
+# retired while listed, reused and listed again before its stale entries are
+# taken (the queue would overflow without the per-queue stale bit), and one
+# where retired chunks come back to the same class in turn.
+EAGER_CONFIGS = {k: v for k, v in CONFIGS.items() if k != "churn3"}
+EAGER_CONFIGS["eager_relist_before_drop"] = dict(n_chunks=1, ppc=2,
+                                                 leaders=[[(A, 1)], [(A, 1), (FO, 0)], [(A, 1), (FO, 0), (FO, 0)]])
+EAGER_CONFIGS["eager_reuse_same_class"] = dict(n_chunks=1, ppc=3, leaders=[[(A, 1), (FO, 0)], [(A, 2)], [(A, 1), (FO, 0)]])
+EAGER_CONFIGS["eager_two_chunks_churn"] = dict(n_chunks=2, ppc=2,
+                                               leaders=[[(A, 2), (FO, 0), (A, 1)], [(A, 2), (FO, 0)], [(A, 1)]])
+
 # pcs between a leader's reservation and its release (it holds H; pc 17 is a
 # chunk pass's early release, made before it claims its pages), and the
 # slot puts and publish of frees (tail positions reserved but not yet
@@ -160,3 +174,28 @@ def test_chunk_pass_claiming_before_requeue(name):
     r = O.model_run(0, early_requeue=False, **CONFIGS[name])
     assert not r["truncated"]
     assert r["violations"] == 0 and r["deadlocks"] == 0, r
+
+
+@pytest.mark.parametrize("name", sorted(EAGER_CONFIGS))
+def test_eager_retirement_has_no_violation(name):
+    """Token, exact out-of-memory (launches without frees), final-state
+    checks (queue and pool ring consistent, every chunk with free pages
+    listed at a position whose slot holds it, at most one stale entry per
+    chunk and its bit set exactly then) and no deadlock."""
+    r = O.model_run(2, max_states=3_000_000, **EAGER_CONFIGS[name])
+    assert not r["truncated"], r
+    assert r["terminals"] > 0
+    assert r["violations"] == 0 and r["deadlocks"] == 0, r
+
+
+def test_eager_exact_oom_outcomes_are_reached():
+    assert O.model_run(2, **EAGER_CONFIGS["oom_three"])["null_outcomes"] > 0
+    assert O.model_run(2, **EAGER_CONFIGS["three_allocs"])["null_outcomes"] == 0
+
+
+def test_eager_stale_bit_is_needed():
+    """Without the per-queue stale bit a chunk retired while listed, reused
+    and listed again before its stale entries are taken fills the queue: a
+    producer then waits on a slot nobody will empty."""
+    r = O.model_run(2, mutation=O.MUTATIONS["eager_no_stale_bit"], **EAGER_CONFIGS["eager_relist_before_drop"])
+    assert r["deadlocks"] > 0, r
