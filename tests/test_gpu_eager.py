@@ -71,20 +71,22 @@ def test_eager_single_lane_replay_matches_fifo_oracle(hb, seed, shards):
         assert heap.error() == 0
 
 
-@pytest.mark.parametrize("sa,sb", [(16, 8 * KiB), (8 * KiB, 16), (4 * KiB, 512), (100, 100)])
+@pytest.mark.parametrize("sa,sb,C", [(16, 8 * KiB, 8 * KiB), (8 * KiB, 16, 8 * KiB), (4 * KiB, 512, 8 * KiB),
+                                     (100, 100, 8 * KiB), (16, 64 * KiB, 64 * KiB), (2 * KiB, 16, 4 * KiB)])
 @pytest.mark.parametrize("shards", [1, 0])
-def test_eager_class_change_without_trim(hb, sa, sb, shards):
-    """16 MiB heap (2048 chunks).  Class a fills it (exactly N * C / s_a
-    succeed), every block is freed, and class b then gets exactly
-    N * C / s_b -- no trim in between; each chunk was retired exactly once."""
-    nbytes, C = 16 * MiB, 8 * KiB
+def test_eager_class_change_without_trim(hb, sa, sb, C, shards):
+    """16 MiB heap (2048 chunks of 8 KiB; 256 of 64 KiB, 4096 pages of 16 B
+    each; 4096 of 4 KiB).  Class a fills it (exactly N * C / s_a succeed),
+    every block is freed, and class b then gets exactly N * C / s_b -- no
+    trim in between; each chunk was retired exactly once."""
+    nbytes = 16 * MiB
     N = nbytes // C
     with hb.Heap(nbytes, C, shards=shards, flags=hb.FLAG_EAGER | hb.FLAG_STATS) as heap:
         fresh = heap.snapshot()
         for rnd, s in enumerate((sa, sb)):
             cap = N * (C // O.page_bytes(O.class_of(s, C)))
             n = cap + 4096
-            say(f"case eager-class-change sa={sa} sb={sb} shards={shards} phase={rnd} n={n}")
+            say(f"case eager-class-change sa={sa} sb={sb} C={C} shards={shards} phase={rnd} n={n}")
             sizes = np.full(n, s, dtype=np.uint64)
             sd, ptrs = dev_u64(sizes), zeros_i64(n)
             oom0 = heap.stats()["oom"]
@@ -115,8 +117,9 @@ def test_eager_class_change_without_trim(hb, sa, sb, shards):
         assert heap.error() == 0
 
 
-@pytest.mark.parametrize("shards", [1, 0])
-def test_eager_churn_rounds(hb, shards):
+@pytest.mark.parametrize("shards,chunk,width", [(1, 8 * KiB, 64), (0, 8 * KiB, 64), (0, 64 * KiB, 64),
+                                                (0, 4 * KiB, 16), (1, 16 * KiB, 1)])
+def test_eager_churn_rounds(hb, shards, chunk, width):
     """256 MiB heap, 2^16 requests of log-uniform sizes in [4 B, 8 KiB] (about
     98 MB of pages live, mean class about 1490 B); each
     round frees a random half and allocates the freed slots with fresh sizes.
@@ -125,19 +128,19 @@ def test_eager_churn_rounds(hb, shards):
     the oracle's.  At the end every block is freed: every chunk is back in
     the pools without a trim."""
     import torch
-    nbytes, C, n, rounds, seed = 256 * MiB, 8 * KiB, 1 << 16, 6, 0xE3
+    nbytes, C, n, rounds, seed = 256 * MiB, chunk, 1 << 16, 6, 0xE3
     N = nbytes // C
     ref = O.OracleHeap(nbytes, C, 0, O.POLICY_LOWEST, 1, eager=True)
-    with hb.Heap(nbytes, C, shards=shards, flags=hb.FLAG_EAGER) as heap:
+    with hb.Heap(nbytes, C, shards=shards, flags=hb.FLAG_EAGER, width=width) as heap:
         fresh = heap.snapshot()
-        sizes = inputs.sizes_log_uniform(n, 4, 8 * KiB, seed)
+        sizes = inputs.sizes_log_uniform(n, 4, min(C, 8 * KiB), seed)
         sd, ptrs = dev_u64(sizes), zeros_i64(n)
         heap.alloc(sd, ptrs)
         roffs = ref.alloc_batch(sizes)
         assert (roffs >= 0).all()
         rng = np.random.default_rng(seed)
         for r in range(rounds):
-            say(f"case eager-churn shards={shards} round={r}")
+            say(f"case eager-churn shards={shards} chunk={chunk} width={width} round={r}")
             offs = offsets(ptrs, heap.base)
             check_blocks(heap, sizes, offs)
             heap.pattern_write(ptrs, sd, seed + r)
@@ -154,7 +157,7 @@ def test_eager_churn_rounds(hb, shards):
             assert (ref.free_batch(roffs[idx]) == O.FREE_OK).all()
             _, rep = check_snapshot(heap)
             assert live_of(rep) == ref.accounting()["live"]
-            new = inputs.sizes_log_uniform(len(idx), 4, 8 * KiB, seed + 100 + r)
+            new = inputs.sizes_log_uniform(len(idx), 4, min(C, 8 * KiB), seed + 100 + r)
             sizes[idx] = new
             nd, nptr = dev_u64(new), zeros_i64(len(idx))
             heap.alloc(nd, nptr)
@@ -166,7 +169,11 @@ def test_eager_churn_rounds(hb, shards):
         heap.free(ptrs, status=st)
         assert (st.cpu().numpy() == hb.FREE_OK).all()
         _, rep = check_snapshot(heap)
-        assert rep.free_chunks == N
+        # every chunk is back in the pools, except a whole one whose queue
+        # still held a stale entry of it when it became whole (kept listed)
+        assert sum(live_of(rep)) == 0
+        assert rep.free_chunks + rep.whole_owned == N
+        say(f"  chunks kept whole and listed: {rep.whole_owned}")
         heap.trim()
         assert heap.snapshot() == fresh
         assert heap.error() == 0
