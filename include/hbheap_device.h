@@ -1436,10 +1436,23 @@ __device__ __forceinline__ void chunk_serve_shard(const hbheap_dev_t& h, const G
                 const uint32_t u = need - (last << g.lppc);
                 const uint32_t cl = ev ? perm32(mine, lane_of_rank(g.act, last)) : h.pool_ids[first + last];
                 const uint32_t nw = g.ppc >= 64u ? g.ppc >> 6 : 1u;
-                for (uint32_t w = g.arank; w < nw; w += g.nact)
-                    h.bits[(uint64_t)cl * h.words_per_chunk + w] = free_mask_word(w, u, g.ppc);
-                if (g.me == g.leader && !ev) h.chunk_cnt[cl] = (int32_t)(g.ppc - u);
-                fence_release();
+                if (ev) {
+                    /* eager retirement: every other write of the refill is an
+                     * atomic; the bit words are exchanged too, and the wave
+                     * waits for them instead of writing back the L2 */
+                    uint64_t acc = 0;
+                    for (uint32_t w = g.arank; w < nw; w += g.nact)
+                        acc ^= a_xchg64(h.bits + (uint64_t)cl * h.words_per_chunk + w, free_mask_word(w, u, g.ppc));
+                    /* returning exchanges, waited for: performed before the
+                     * chunk is listed */
+                    __asm__ volatile("" ::"v"((uint32_t)acc), "v"((uint32_t)(acc >> 32)) : "memory");
+                    wait_own_accesses();
+                } else {
+                    for (uint32_t w = g.arank; w < nw; w += g.nact)
+                        h.bits[(uint64_t)cl * h.words_per_chunk + w] = free_mask_word(w, u, g.ppc);
+                    if (g.me == g.leader) h.chunk_cnt[cl] = (int32_t)(g.ppc - u);
+                    fence_release();
+                }
                 if (g.me == g.leader) {
                     uint32_t pos = a_add32(R.tail, 1u);
                     tl.headtail += 1;
