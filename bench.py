@@ -628,7 +628,9 @@ def bench_growth(hb, inputs, torch, args, ev, log):
     KiB = 1024
     d_cal = inputs.growth_doublings(agents, w.seed * 16 + 0xA)   # 0xC0F4A
     d_eval = inputs.growth_doublings(agents, w.seed * 16 + 0xB)  # 0xC0F4B
-    cands = [(c * KiB, v, wd) for c in (8, 16, 32, 64) for v in (0, 1, 2, 3, 4, 5) for wd in (16, 32, 64)]
+    cands = [(c * KiB, v, wd, 0) for c in (8, 16, 32, 64) for v in (0, 1, 2, 3, 4, 5) for wd in (16, 32, 64)]
+    # the chunk variant with eager retirement
+    cands += [(c * KiB, hb.VARIANT_CHUNK, wd, hb.FLAG_EAGER) for c in (8, 16, 32, 64) for wd in (16, 32, 64)]
     t0 = time.perf_counter()
     ms, best = hb.growth_autotune(w.heap_bytes, agents, torch.from_numpy(d_cal).to("cuda"), steps, w.seed, cands,
                                   reps=5)
@@ -636,15 +638,19 @@ def bench_growth(hb, inputs, torch, args, ev, log):
     if best < 0:
         log("growth autotuner: no candidate ran")
         return {"error": "no candidate ran"}
-    default = (8 * KiB, 1, 64)
+    default = (8 * KiB, 1, 64, 0)
+
+    def cname(cfg):
+        c, v, wd, fl = cfg
+        return f"{c // KiB}K/{VNAMES[v]}{'-eager' if fl else ''}/w{wd}"
 
     def measure(cfg, d):
-        chunk, variant, width = cfg
-        with hb.Heap(w.heap_bytes, chunk, variant=variant, width=width) as heap:
+        chunk, variant, width, flags = cfg
+        with hb.Heap(w.heap_bytes, chunk, variant=variant, width=width, flags=flags) as heap:
             with hb.Growth(heap, torch.from_numpy(d).to("cuda"), steps, w.seed) as gr:
                 gr.run_graph()
                 gr.release()
-                graph_t, eager_t = [], []
+                graph_t, step_t = [], []
                 for _ in range(args.growth_reps):
                     e0, e1 = ev(), ev()
                     e0.record()
@@ -663,11 +669,11 @@ def bench_growth(hb, inputs, torch, args, ev, log):
                     e1.record()
                     gr.release()
                     torch.cuda.synchronize()
-                    eager_t.append(e0.elapsed_time(e1))
+                    step_t.append(e0.elapsed_time(e1))
                 final_bytes = int(nbytes.sum().item())
                 blocks, threads = gr.shape()
             assert heap.error() == 0
-        return float(np.median(graph_t)), float(np.median(eager_t)), final_bytes, blocks * threads
+        return float(np.median(graph_t)), float(np.median(step_t)), final_bytes, blocks * threads
 
     # per replay: step 0 allocates for every agent; each doubling allocates,
     # copies the old list and frees it
@@ -681,7 +687,7 @@ def bench_growth(hb, inputs, torch, args, ev, log):
         "workload": f"{agents} agents, 4 GiB heap, {steps} steps (16 B -> 4 KiB doubling reallocs), "
                     "doublings min(8, Geom(0.3)), calibration and evaluation schedules seeded apart",
         "graph_ms": g_best,
-        "eager_ms": e_best,
+        "step_by_step_ms": e_best,
         "realloc_ops": reallocs,
         "alloc_free_ops_per_s": (reallocs + doublings) / (g_best * 1e-3),
         "payload_gb_per_s": (copied + written) / (g_best * 1e-3) / 1e9,
@@ -689,16 +695,15 @@ def bench_growth(hb, inputs, torch, args, ev, log):
         "persistent_lanes": lanes,
         "autotune": {
             "best": {"chunk_bytes": cands[best][0], "variant": VNAMES[cands[best][1]],
-                     "width": cands[best][2]},
-            "calibration_ms": {f"{c // KiB}K/{VNAMES[v]}/w{wd}": round(t, 4)
-                               for (c, v, wd), t in zip(cands, ms)},
+                     "width": cands[best][2], "eager_retirement": bool(cands[best][3])},
+            "calibration_ms": {cname(cf): round(t, 4) for cf, t in zip(cands, ms)},
             "default": {"chunk_bytes": default[0], "variant": "page", "width": default[2]},
             "default_graph_ms": g_def,
             "margin_vs_default": g_def / g_best,
             "seconds": tune_s,
         },
     }
-    log(f"growth: graph {g_best:.3f} ms (eager {e_best:.3f} ms), {res['alloc_free_ops_per_s']/1e9:.2f} G ops/s, "
+    log(f"growth: graph {g_best:.3f} ms (step by step {e_best:.3f} ms), {res['alloc_free_ops_per_s']/1e9:.2f} G ops/s, "
         f"autotune best {res['autotune']['best']} margin {g_def / g_best:.3f}")
     return res
 

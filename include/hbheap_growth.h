@@ -84,6 +84,9 @@ typedef struct growth_candidate {
     uint64_t chunk_bytes;   /* power of two in [4 KiB, 64 KiB]          */
     uint32_t variant;       /* any HBHEAP_VARIANT_*                     */
     uint32_t width;         /* aggregation width: 1, 2, 4 .. 64         */
+    uint32_t flags;         /* creation flags: 0, or HBHEAP_FLAG_EAGER
+                               with the chunk variant                   */
+    uint32_t reserved;      /* 0                                        */
 } growth_candidate_t;
 
 /*

@@ -319,6 +319,7 @@ int growth_autotune(size_t heap_bytes, uint32_t agents, const int32_t* doublings
         memset(&cfg, 0, sizeof(cfg));
         cfg.variant = cand[i].variant;
         cfg.width = cand[i].width;
+        cfg.flags = cand[i].flags & HBHEAP_FLAG_EAGER;
         heap_t h = nullptr;
         if (heap_create_ex(heap_bytes, cand[i].chunk_bytes, &cfg, &h) != HBHEAP_OK) continue;
         growth_t g = nullptr;

@@ -54,7 +54,8 @@ class HeapInfo(C.Structure):
 
 
 class GrowthCandidate(C.Structure):
-    _fields_ = [("chunk_bytes", C.c_uint64), ("variant", C.c_uint32), ("width", C.c_uint32)]
+    _fields_ = [("chunk_bytes", C.c_uint64), ("variant", C.c_uint32), ("width", C.c_uint32), ("flags", C.c_uint32),
+                ("reserved", C.c_uint32)]
 
 
 class ServeConfig(C.Structure):
@@ -372,10 +373,11 @@ def growth_launch_shape(g: int) -> tuple[int, int]:
 
 
 def growth_autotune(heap_bytes: int, agents: int, doublings, steps: int, seed: int, candidates, reps: int):
-    """candidates: list of (chunk_bytes, variant, width).  Returns (median ms
-    per candidate, negative where it could not run; index of the best)."""
+    """candidates: list of (chunk_bytes, variant, width[, flags]).  Returns
+    (median ms per candidate, negative where it could not run; index of the
+    best)."""
     n = len(candidates)
-    arr = (GrowthCandidate * n)(*[GrowthCandidate(c, v, w) for c, v, w in candidates])
+    arr = (GrowthCandidate * n)(*[GrowthCandidate(*(tuple(c) + (0,))[:4], 0) for c in candidates])
     ms = (C.c_float * n)()
     best = C.c_int32()
     _check("growth_autotune", lib().growth_autotune(heap_bytes, agents, _addr(doublings), steps, seed & 0xFFFFFFFF,

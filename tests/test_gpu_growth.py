@@ -175,12 +175,14 @@ def test_growth_autotune_small(hb):
     agents, steps = 4000, 9
     d = torch.from_numpy(inputs.growth_doublings(agents, inputs.SEED_GROWTH)).to("cuda")
     cands = [(c, v, w) for c in (8 * KiB, 32 * KiB) for v in (0, 1) for w in (16, 64)]
+    cands.append((8 * KiB, 0, 64, hb.FLAG_EAGER))  # eager chunk retirement
+    cands.append((8 * KiB, 1, 64, hb.FLAG_EAGER))  # eager with the page variant: not run
     cands.append((2 * KiB, 0, 64))  # invalid chunk size: must be reported as not run
     say("case growth-autotune")
     ms, best = hb.growth_autotune(64 * MiB, agents, d, steps, 3, cands, reps=3)
-    assert ms[-1] < 0
+    assert ms[-1] < 0 and ms[-2] < 0 and ms[-3] > 0
     ran = [i for i, t in enumerate(ms) if t > 0]
-    assert len(ran) == len(cands) - 1
+    assert len(ran) == len(cands) - 2
     assert best == min(ran, key=lambda i: ms[i])
 
 
