@@ -208,3 +208,92 @@ def test_eager_growth_in_one_kernel(hb):
         heap.trim()
         assert heap.snapshot() == fresh
         assert heap.error() == 0
+
+
+def test_eager_sweep_full_size(hb):
+    """The measured sweep at full size -- 4 GiB heap, 8 KiB chunks, 2^20
+    threads, 16 B .. 8 KiB -- on a chunk heap with eager retirement and no
+    trim between sizes.  Each size gets exactly min(2^20, N * C / s)
+    (8 KiB: half the requests fail): the chunks the previous size freed are
+    back in the pools.  After every free launch no page is live and every
+    chunk is in a pool (or kept whole behind a stale entry)."""
+    w = inputs.SWEEP
+    n, C = w.threads, w.chunk_bytes
+    with hb.Heap(w.heap_bytes, C, flags=hb.FLAG_EAGER) as heap:
+        N = heap.info.n_chunks
+        fresh = heap.snapshot()
+        ptrs = zeros_i64(n)
+        for size in inputs.SWEEP_SIZES:
+            k = O.class_of(size, C)
+            cap = N * (C // O.page_bytes(k))
+            sizes = inputs.sizes_fixed(n, size)
+            sd = dev_u64(sizes)
+            for it in range(2):
+                say(f"case eager-sweep-full size={size} iteration={it}")
+                heap.alloc(sd, ptrs)
+                heap.pattern_write(ptrs, sd, w.seed)
+                assert heap.pattern_check(ptrs, sd, w.seed) == 0
+                offs = offsets(ptrs, heap.base)
+                rep = check_blocks(heap, sizes, offs, allow_null=True)
+                assert rep.n_nonnull == min(n, cap), (size, it, rep.n_nonnull, cap)
+                if it == 0:
+                    _, srep = check_snapshot(heap)
+                    assert live_of(srep)[k] == min(n, cap)
+                heap.free(ptrs)
+            _, srep = check_snapshot(heap)
+            assert sum(live_of(srep)) == 0
+            assert srep.free_chunks + srep.whole_owned == N, (size, srep.free_chunks, srep.whole_owned)
+        heap.trim()
+        assert heap.snapshot() == fresh
+        assert heap.error() == 0
+
+
+def test_eager_churn_full_size(hb):
+    """8 GiB heap, 2^21 requests of log-uniform sizes in [4 B, 8 KiB]; six
+    rounds each free a random half and reallocate it with fresh sizes.  Every
+    round: blocks valid and disjoint, patterns intact, snapshot consistent,
+    live counts equal to the oracle's (eager mode)."""
+    import torch
+    w = inputs.CHURN
+    n, seed, rounds = w.threads, w.seed, 6
+    sizes = inputs.sizes_log_uniform(n, 4, 8 * KiB, seed)
+    ref = O.OracleHeap(w.heap_bytes, w.chunk_bytes, 0, O.POLICY_LOWEST, 1, eager=True)
+    roffs = ref.alloc_batch(sizes)
+    assert (roffs >= 0).all()
+    with hb.Heap(w.heap_bytes, w.chunk_bytes, flags=hb.FLAG_EAGER) as heap:
+        N = heap.info.n_chunks
+        fresh = heap.snapshot()
+        sd, ptrs = dev_u64(sizes), zeros_i64(n)
+        heap.alloc(sd, ptrs)
+        rng = np.random.default_rng(seed)
+        for r in range(rounds):
+            say(f"case eager-churn-full round={r}")
+            offs = offsets(ptrs, heap.base)
+            check_blocks(heap, sizes, offs)
+            heap.pattern_write(ptrs, sd, seed + r)
+            assert heap.pattern_check(ptrs, sd, seed + r) == 0
+            snap, rep = check_snapshot(heap)
+            assert live_of(rep) == ref.accounting()["live"]
+            idx = np.sort(rng.choice(n, n // 2, replace=False))
+            ix = torch.from_numpy(idx).to("cuda")
+            st = torch.zeros(len(idx), dtype=torch.int32, device="cuda")
+            heap.free(ptrs[ix].contiguous(), status=st)
+            assert (st.cpu().numpy() == hb.FREE_OK).all()
+            assert (ref.free_batch(roffs[idx]) == O.FREE_OK).all()
+            new = inputs.sizes_log_uniform(len(idx), 4, 8 * KiB, seed + 1000 + r)
+            sizes[idx] = new
+            nptr = zeros_i64(len(idx))
+            heap.alloc(dev_u64(new), nptr)
+            ptrs[ix] = nptr
+            sd = dev_u64(sizes)
+            roffs[idx] = ref.alloc_batch(new)
+            assert (roffs >= 0).all()
+        st = torch.zeros(n, dtype=torch.int32, device="cuda")
+        heap.free(ptrs, status=st)
+        assert (st.cpu().numpy() == hb.FREE_OK).all()
+        _, rep = check_snapshot(heap)
+        assert sum(live_of(rep)) == 0 and rep.free_chunks + rep.whole_owned == N
+        say(f"  chunks kept whole and listed: {rep.whole_owned}")
+        heap.trim()
+        assert heap.snapshot() == fresh
+        assert heap.error() == 0
