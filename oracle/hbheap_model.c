@@ -15,7 +15,13 @@
  *     the per-class owned-chunk counter and cap;
  *   - "leaders": one per wave, each running a list of aggregated operations
  *     (allocate g pages, free its own pages, free pages handed to it), one
- *     atomic memory step at a time; lanes of one leader act in lane order.
+ *     atomic memory step at a time; lanes of one leader act in lane order;
+ *   - variant 2, eager retirement of the chunk variant: per chunk a token
+ *     (the queue position it is listed at, held, or none) changed together
+ *     with its free count, a stale bit per chunk, queue entries taken by
+ *     position modulo Q and dropped when no token names them, chunks whose
+ *     pages are all free retired to a pool ring (a grouped tail add, puts
+ *     and one publish), and refills taken from that ring.
  * Waits are transitions that are disabled until their condition holds, so a
  * deadlock is a state with unfinished leaders and no enabled transition.
  *
@@ -31,7 +37,10 @@
  *     be ordered before it); with no concurrent frees: nothing is left.
  * Checked in every final state: no hold in flight, count = tail - head,
  * every slot outside [head, tail) empty, every token back in the ring,
- * granted pages distinct and marked allocated, pages conserved.
+ * granted pages distinct and marked allocated, pages conserved.  Variant 2
+ * adds: the pool ring holds exactly the unowned chunks; a chunk with free
+ * pages is listed at a position in [head, tail) whose slot holds it; at most
+ * one stale entry per chunk, and its stale bit set exactly then.
  * Freeze mode stops one leader forever after each of its steps and records
  * where the others can no longer finish (the algorithm's blocking points).
  * Mutations plant known mistakes so the tests can show each check fires.
