@@ -131,9 +131,11 @@ typedef struct hbheap_dev {
     uint32_t  vsegs;           /* segments per shard                         */
     uint64_t  vbudget;         /* pages the classes of one shard may own     */
     /* eager retirement (chunk variant created with HBHEAP_FLAG_EAGER; NULL
-     * otherwise): per chunk a u64, free pages in the low half and, in the
-     * high half, where the chunk is listed: (class << 28 | queue position
-     * mod 2^28), held by an allocator (0xFFFFFFFE) or nowhere (0xFFFFFFFF).
+     * otherwise): per chunk a u64.  Low half: free pages in bits 0..15, and
+     * in bit 16 + k whether the chunk has a stale entry in the queue of
+     * class k.  High half: where the chunk is listed: (class << 28 | queue
+     * position mod 2^28), held by an allocator (0xFFFFFFFE) or nowhere
+     * (0xFFFFFFFF).
      * Each shard's pool is then a ring: u64 state (free chunks + 2^31) at
      * +0, u32 head at +16, u32 tail at +20 of its pool block, and slots
      * pool_ids[(j << log2_span) + (position mod 2^log2_span)]. */
