@@ -297,3 +297,47 @@ def test_eager_churn_full_size(hb):
         heap.trim()
         assert heap.snapshot() == fresh
         assert heap.error() == 0
+
+
+def test_eager_free_after_retirement_is_invalid(hb):
+    """A block freed twice, the first free having made its chunk whole (so
+    the chunk retired): the second free finds an unowned chunk and is
+    reported invalid (status 2, the sticky invalid-free bit), and changes
+    nothing -- the snapshot stays consistent and the chunk stays in its
+    pool.  A free into a chunk reused by another class at an offset that is
+    not a page of that class is invalid too."""
+    import torch
+    C = 8 * KiB
+    with hb.Heap(1 * MiB, C, shards=1, flags=hb.FLAG_EAGER) as heap:
+        N = heap.info.n_chunks
+        sd, ptrs = dev_u64(np.full(4, 2 * KiB, dtype=np.uint64)), zeros_i64(4)
+        heap.alloc(sd, ptrs)                 # one chunk, its four 2 KiB pages
+        st = torch.zeros(4, dtype=torch.int32, device="cuda")
+        heap.free(ptrs, status=st)
+        assert (st.cpu().numpy() == hb.FREE_OK).all()
+        _, rep = check_snapshot(heap)
+        assert rep.free_chunks == N
+        say("case eager-free-after-retirement")
+        heap.free(ptrs, status=st)
+        assert (st.cpu().numpy() == hb.FREE_INVALID).all()
+        assert heap.error() & hb.ERR_INVALID_FREE
+        _, rep = check_snapshot(heap)
+        assert rep.free_chunks == N and sum(live_of(rep)) == 0
+        hb.heap_clear_error(heap.h)
+        # the chunk comes back as 3 KiB-class (4 KiB pages) blocks; an old
+        # 2 KiB-page pointer at an odd page offset is not a page of it
+        p4 = zeros_i64(N * 2)
+        heap.alloc(dev_u64(np.full(N * 2, 4 * KiB, dtype=np.uint64)), p4)
+        offs4 = offsets(p4, heap.base)
+        assert (offs4 >= 0).all()
+        old = offsets(ptrs, heap.base)
+        odd = ptrs[torch.from_numpy(np.nonzero(old % (4 * KiB) != 0)[0]).to("cuda")].contiguous()
+        st2 = torch.zeros(len(odd), dtype=torch.int32, device="cuda")
+        heap.free(odd, status=st2)
+        assert (st2.cpu().numpy() == hb.FREE_INVALID).all()
+        _, rep = check_snapshot(heap)
+        assert sum(live_of(rep)) == N * 2
+        heap.free(p4)
+        hb.heap_clear_error(heap.h)
+        _, rep = check_snapshot(heap)
+        assert rep.free_chunks == N
