@@ -169,11 +169,13 @@ class ModelResult(C.Structure):
         ("token_violations", C.c_int64), ("oom_violations", C.c_int64), ("final_violations", C.c_int64),
         ("grant_violations", C.c_int64), ("blocked_freezes", C.c_int64), ("null_outcomes", C.c_int64),
         ("truncated", C.c_int32), ("first_violation", C.c_int32), ("blocking_pcs", C.c_uint32),
-        ("dry_starts", C.c_uint32),
+        ("dry_starts", C.c_uint32), ("blocking_set", C.c_uint64 * 4),
     ]
 
     def as_dict(self) -> dict:
-        return {f: int(getattr(self, f)) for f, _ in self._fields_ if f != "pad"}
+        d = {f: int(getattr(self, f)) for f, _ in self._fields_ if f not in ("pad", "blocking_set")}
+        d["blocking_set"] = {64 * q + b for q in range(4) for b in range(64) if (self.blocking_set[q] >> b) & 1}
+        return d
 
 
 OP_ALLOC, OP_FREE_OWN, OP_FREE_GIVEN = 1, 2, 3

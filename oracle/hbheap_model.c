@@ -1439,6 +1439,7 @@ static void explore(ctx* x, const mstate* init)
             } else {
                 x->r->blocked_freezes++;
                 x->r->blocking_pcs |= 1u << (s.L[x->frozen].pc % 32);
+                x->r->blocking_set[s.L[x->frozen].pc >> 6] |= 1ull << (s.L[x->frozen].pc & 63);
             }
         }
     }
@@ -1564,6 +1565,7 @@ int orc_model_run(const orc_model_params* p, orc_model_result* r)
             }
             saved.blocked_freezes += fr.blocked_freezes;
             saved.blocking_pcs |= fr.blocking_pcs;
+            for (int q = 0; q < 4; ++q) saved.blocking_set[q] |= fr.blocking_set[q];
             free(y.tab);
             free(y.used);
             free(roots);

@@ -187,8 +187,9 @@ typedef struct {
     int64_t null_outcomes;     /* final states where some request got NULL */
     int32_t truncated;
     int32_t first_violation;
-    uint32_t blocking_pcs;     /* bit mask of the frozen leader's pcs      */
+    uint32_t blocking_pcs;     /* bit mask of the frozen leader's pcs mod 32 */
     uint32_t dry_starts;       /* page allocs that started on a dry pool   */
+    uint64_t blocking_set[4];  /* the same pcs, all 256 of them, exactly    */
 } orc_model_result;
 
 /* 0 on success, negative for bad parameters. */

@@ -199,3 +199,27 @@ def test_eager_stale_bit_is_needed():
     producer then waits on a slot nobody will empty."""
     r = O.model_run(2, mutation=O.MUTATIONS["eager_no_stale_bit"], **EAGER_CONFIGS["eager_relist_before_drop"])
     assert r["deadlocks"] > 0, r
+
+
+# eager retirement: a leader holds the queue from its reservation (pc 100)
+# to its release (111 on an early pass, 123 after a refill), also while it
+# relists a chunk late (131, 132); a free has queue positions reserved from
+# 143 to its publish (146); a retirement (160..163) runs inside one of those
+# or reserves a pool-ring position itself
+HOLDING_EAGER = set(range(101, 112)) | (set(range(115, 127)) - {124}) | {131, 132} | set(range(143, 147)) \
+    | set(range(160, 164))
+
+
+def test_eager_freeze_blocks_only_where_the_queue_is_held():
+    """A leader stopped forever keeps the others from finishing only while
+    it holds the queue or a reserved queue or pool position -- never while
+    it claims pages after an early release, looks for out of memory, or adds
+    to a chunk's count in a free."""
+    seen = set()
+    for name in ("churn", "eager_relist_before_drop", "overask_free_own", "oom_three", "free_vs_alloc"):
+        r = O.model_run(2, freeze=True, max_states=1_000_000, **EAGER_CONFIGS[name])
+        assert r["violations"] == 0, (name, r)
+        seen |= r["blocking_set"]
+    assert seen <= HOLDING_EAGER, sorted(seen - HOLDING_EAGER)
+    assert not seen & {100, 112, 113, 118, 124, 141, 142}
+    assert {101, 119, 144, 162} <= seen  # each kind of hold is reached
