@@ -315,3 +315,68 @@ def test_eager_checker_pool_ring():
     # the lazy count array must stay zero in eager mode
     v = check(N, log2C, cls, bits, ct, pool, rings, cnt32={0: 1}).violations()
     assert "bad_count" in v
+
+
+class _BruteEager:
+    """Eager retirement written out from its definition, in plain Python:
+    chunks of C bytes, each unowned or owned by one class with a set of free
+    pages; an allocation takes the lowest free page of the lowest chunk of
+    its class that has one, else page 0 of the lowest unowned chunk; a free
+    that leaves every page of its chunk free makes the chunk unowned."""
+
+    def __init__(self, n_chunks, C):
+        self.C, self.N = C, n_chunks
+        self.cls = [None] * n_chunks
+        self.free = [set() for _ in range(n_chunks)]
+
+    def alloc(self, n):
+        if n == 0 or n > self.C:
+            return -1
+        s = 16
+        while s < n:
+            s *= 2
+        ppc = self.C // s
+        for c in range(self.N):
+            if self.cls[c] == s and self.free[c]:
+                p = min(self.free[c])
+                self.free[c].remove(p)
+                return c * self.C + p * s
+        for c in range(self.N):
+            if self.cls[c] is None:
+                self.cls[c] = s
+                self.free[c] = set(range(1, ppc))
+                return c * self.C
+        return -1
+
+    def free_(self, off):
+        c, s = off // self.C, self.cls[off // self.C]
+        self.free[c].add((off % self.C) // s)
+        if len(self.free[c]) == self.C // s:
+            self.cls[c], self.free[c] = None, set()
+
+
+@pytest.mark.parametrize("C,seed", [(4 * KiB, 11), (8 * KiB, 12), (4 * KiB, 13)])
+def test_eager_oracle_equals_brute_force(C, seed):
+    """The oracle's eager mode (one shard, lowest-first) against the
+    definition above, operation by operation, on random sequences that fill
+    and drain a 12-chunk heap.  Catches: a retirement at the wrong count, a
+    retired chunk not reusable by another class, the wrong chunk or page
+    chosen after a retirement."""
+    rng = np.random.default_rng(seed)
+    N = 12
+    o = O.OracleHeap(N * C, C, O.VARIANT_CHUNK, O.POLICY_LOWEST, 1, eager=True)
+    b = _BruteEager(N, C)
+    live = []
+    for step in range(4000):
+        if live and rng.random() < (0.3 if step % 800 < 400 else 0.7):
+            off = live.pop(int(rng.integers(len(live))))
+            assert o.free(off) == O.FREE_OK
+            b.free_(off)
+        else:
+            n = int(rng.choice([1, 16, 17, 100, 512, 1000, C // 4, C // 2 + 1, C]))
+            a, e = o.alloc(n), b.alloc(n)
+            assert a == e, (step, n, a, e)
+            if a >= 0:
+                live.append(a)
+    acct = o.accounting()
+    assert acct["free_chunks"] == sum(c is None for c in b.cls)
