@@ -440,6 +440,48 @@ def main():
             eager["class_change"][name] = rec
             log(f"class change {name}: 4 KiB ok {rec['fill_4KiB']['ok']}, then 16 B ok {rec['refill_16B']['ok']} "
                 f"(no trim)")
+        # fragmentation under a shifting mix: the churn heap (8 GiB, 2^21
+        # blocks, log-uniform 4 B .. 8 KiB); each round frees a random half
+        # and reallocates it with sizes alternating between small (4 .. 256 B)
+        # and large (1 .. 8 KiB); chunks in use after each round (exact: the
+        # pools' counters at quiescence), lazy against eager
+        wc = inputs.CHURN
+        nc = wc.threads
+        eager["shifting_churn"] = {"workload": f"{wc.heap_bytes >> 30} GiB heap, {nc} blocks, rounds of half freed "
+                                               "and reallocated, sizes alternating 4..256 B / 1..8 KiB",
+                                   "n_chunks": wc.heap_bytes // wc.chunk_bytes}
+        for name, fl in (("lazy", 0), ("eager", hb.FLAG_EAGER)):
+            heap = hb.Heap(wc.heap_bytes, wc.chunk_bytes, variant=hb.VARIANT_CHUNK, shards=args.shards, flags=fl)
+            szh = inputs.sizes_log_uniform(nc, 4, 8 * 1024, wc.seed)
+            sz = torch.from_numpy(szh.view(np.int64)).to(dev)
+            pp = torch.zeros(nc, dtype=torch.int64, device=dev)
+            heap.alloc(sz, pp)
+            gen = torch.Generator(device=dev)
+            gen.manual_seed(wc.seed)
+            traj, nulls, live = [], [], []
+            for r in range(10):
+                idx = torch.randperm(nc, device=dev, generator=gen)[: nc // 2]
+                heap.free(pp[idx].contiguous())
+                lo, hi = (4, 256) if r % 2 == 0 else (1024, 8 * 1024)
+                nsz = torch.from_numpy(inputs.sizes_log_uniform(nc // 2, lo, hi, wc.seed + 1 + r).view(np.int64)).to(dev)
+                sz[idx] = nsz
+                npp = torch.zeros(nc // 2, dtype=torch.int64, device=dev)
+                heap.alloc(nsz, npp)
+                pp[idx] = npp
+                ok = pp != 0
+                cls_bytes = torch.clamp(sz, min=16)
+                cls_bytes = torch.pow(2, torch.ceil(torch.log2(cls_bytes.double()))).long()
+                live.append(int((cls_bytes * ok).sum().item()))
+                nulls.append(int((npp == 0).sum().item()))
+                traj.append(hb.heap_chunks_in_use(heap.h))
+            err = heap.error()
+            heap.close()
+            if err:
+                log(f"HEAP ERROR WORD {err:#x}")
+                sys.exit(5)
+            eager["shifting_churn"][name] = {"chunks_in_use": traj, "failed_requests": nulls, "live_page_bytes": live}
+            log(f"shifting churn {name}: chunks in use {traj[-1]} of {wc.heap_bytes // wc.chunk_bytes}, "
+                f"failed requests {sum(nulls)}")
 
     # ablation: the same sweep without wave aggregation (one queue operation
     # per lane), one step
