@@ -2,14 +2,22 @@
 HBHEAP_FLAG_EAGER): a chunk whose pages are all free again returns to its
 shard's pool at once, while kernels run, instead of at the next trim.
 
-Checked against the oracle's eager mode: a single device lane matches the
-FIFO oracle address for address; a heap filled with one class, emptied and
-refilled with another (no trim) holds exactly the closed-form capacity of
-the second, with every chunk retired exactly once; churn rounds keep the
-eager invariants (no whole chunk left owned, every stale queue entry
-unnamed by any token) and the oracle's live counts; allocations and frees
-inside one kernel (the growth line) keep every list intact; after a trim
-the state equals a fresh heap's byte for byte.
+Checked against the oracle's eager mode:
+
+- a single device lane matches the FIFO oracle address for address;
+- a heap filled with one class, emptied and refilled with another (no
+  trim) holds exactly the closed-form capacity of the second, with every
+  chunk retired exactly once (4, 8 and 64 KiB chunks);
+- churn rounds keep the eager invariants (tokens, stale entries and their
+  per-queue bits) and the oracle's live counts, across chunk sizes and
+  aggregation widths;
+- allocations and frees inside one kernel (the growth line) keep every
+  list intact;
+- frees into a retired or reused chunk are reported invalid and change
+  nothing;
+- at full size: the 4 GiB sweep with no trims gets each size's capacity,
+  the 8 GiB churn matches the oracle's live counts;
+- after a trim the state equals a fresh heap's byte for byte.
 """
 import numpy as np
 import pytest
