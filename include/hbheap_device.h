@@ -35,7 +35,11 @@
  *     the chunk (it is in the queue exactly while its count is positive).
  *   - Unowned chunks sit in a pool array consumed by a 64-bit bump counter,
  *     so "pool empty" is exact and never undone during a kernel; chunks come
- *     back to the pool only through heap_trim() at quiescence.
+ *     back to the pool only through heap_trim() at quiescence.  With eager
+ *     retirement (HBHEAP_FLAG_EAGER, chunk variant) the pool is a ring per
+ *     shard instead, and a free that makes a chunk whole puts it back at
+ *     once; only frees can do that, so "pool empty" still holds for the rest
+ *     of a launch that frees nothing.
  *   - The heap is split into shards, each owning a run of consecutive chunks
  *     with its own pool and its own class queues; a wave starts at its home
  *     shard (spread by wave index); when it runs dry the wave looks at every
@@ -48,7 +52,9 @@
  *     sets HBHEAP_ERR_TIMEOUT and the request returns NULL.
  *   - Metadata atomics are agent-scope and relaxed; ordering comes from
  *     issuing a dependent atomic only after the previous one returned, plus
- *     one release fence before a refill publishes freshly written bitmasks.
+ *     one release fence before a refill publishes freshly written bitmasks
+ *     (with eager retirement those writes are returning atomics the wave
+ *     waits for, and no fence is needed).
  *
  * dev_free() starts with an agent-scope release fence so the caller's
  * writes to the block complete before the block can be handed out again.
