@@ -1184,7 +1184,9 @@ __device__ __forceinline__ bool shard_has_something(const hbheap_dev_t& h, uint3
 /* One look at every shard's queue for the group's class, spread over the
  * active lanes (rank r looks at shards home+r, home+r+nact, ...).  Per
  * shard the pool is read before the state word, head and tail: a pool once
- * empty stays empty until the next trim, so "pool empty, then no hold, no
+ * empty stays empty until the next trim (with eager retirement, until a free
+ * retires a chunk into it, so within a launch that frees nothing it stays
+ * empty as well), so "pool empty, then no hold, no
  * entry and head = tail" means the shard had nothing for the class at the
  * moment head was read (no refill in flight, every published entry taken).
  * Returns the rotated rank (from home) of the first shard with published
@@ -1745,8 +1747,12 @@ __device__ __forceinline__ uint64_t alloc_group(const hbheap_dev_t& h, uint32_t 
  * operation of its leader. */
 /* Whether the home shard's pool has run dry.  A plain load: the bump only
  * grows until a (quiescent) trim, so a stale value can only make the pool
- * look less consumed, never dry when it is not.  Callers that load their
- * request sizes issue this first, so that both loads are in flight together. */
+ * look less consumed, never dry when it is not.  With eager retirement the
+ * ring's count also rises as frees retire chunks, so a stale reading can say
+ * dry when it is not; that only makes the chunk path look at the queue before
+ * reserving, and the scan over shards reads every count afresh.  Callers that
+ * load their request sizes issue this first, so that both loads are in flight
+ * together. */
 __device__ __forceinline__ bool home_pool_dry(const hbheap_dev_t& h, uint32_t home)
 {
     const uint64_t* hp = pool_block(h, home);
