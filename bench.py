@@ -9,24 +9,29 @@ Methods), then a quiescent trim before the next size.  As in the paper, the
 allocator's figure is the time of the allocations and frees averaged over
 the iterations after the first ("subsequent iterations", Methods): value =
 successful (alloc + free) ops / alloc+free launch time over iterations
-2..10 (HIP events on the launch stream); iterations 1..10 are reported too.
-Each size's ten iterations are queued behind a short device-side wait, so
-every event pair times its launch on the device's timeline rather than the
-host's submission latency.  The whole step's wall time (payload write/check,
-those waits and trims included) is ms_per_step, and all ops over it is
-wall_ops_per_s.
+2..10 (HIP events on the launch stream); iterations 1..10 are reported too,
+and the first iteration of each size (served by refills of a freshly
+trimmed heap) on its own.  Each size's ten iterations are queued behind a
+short device-side wait, so every event pair times its launch on the
+device's timeline rather than the host's submission latency.  The whole
+step's wall time (payload write/check, those waits and trims included) is
+ms_per_step, and all ops over it is wall_ops_per_s.
 
 The headline runs the page-queue variant (the faster one on this workload);
-the chunk-queue variant runs the same sweep for one step beside it.
+the other queue variants run the same sweep for one step beside it.
 
 Also measured in the same process:
-  * the device atomic ceilings (same address, 64 and 1024 lines, per-lane
-    random addresses);
+  * device ceilings: atomics on one address, on 64 and 1024 lines, on
+    per-lane random words, lane-contiguous exchanges, a chain of dependent
+    round trips, and an HBM copy;
   * a counting pass with the heap's statistics flag, giving the exact
-    atomics issued per launch by target; the roofline compares all atomics
-    of the allocation launch per second with the measured device atomic
-    throughput, and the busiest queue word with the same-address ceiling;
-  * the plain baseline: the runtime's own per-thread device malloc/free;
+    atomics issued per launch by target;
+  * the roofline of the allocation kernel: HBM bytes (algorithmic, per
+    launch) against 8 TB/s, its atomics priced at the ceiling whose address
+    pattern matches each kind, and the latency floor of its chain of
+    dependent round trips; which of the three binds;
+  * the plain baseline: the runtime's own per-thread device malloc/free in
+    the same driver loop;
   * the CPU baseline: the sequential oracle on a bounded sample, one core.
 
 roofline.traffic is the HBM bytes per allocation launch (FETCH_SIZE and
@@ -34,8 +39,12 @@ WRITE_SIZE counters, scaled by the same counters' reading for a copy of known
 size) recorded in the counter summary under profiles/; it is null once the
 kernel sources differ from the digest stored there.
 
-Prints one JSON line.  Only --gpus 1 is supported.  `--copy-probe BYTES`
-only runs the HBM copy kernel (to calibrate traffic counters).
+Output: the last stdout line is one compact JSON object (a few KB) with the
+headline and a summary of every other line; the full record (per size, per
+variant, per load point) goes to --detail PATH, or to stderr as one line
+starting with "detail " when no path is given.  Only --gpus 1 is supported.
+`--copy-probe BYTES` only runs the HBM copy kernel (to calibrate traffic
+counters).
 """
 from __future__ import annotations
 
@@ -48,12 +57,24 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
+METRIC = "device malloc+free ops/sec (2^20 threads, 16B-8KiB) vs plain; p99 batch latency"
+HBM_PEAK_GBPS = 8000.0  # MI355X HBM3E, published
+# Algorithmic HBM bytes of one allocation launch of the batch interface: per
+# request the 8 B size read and the 8 B pointer write; per page served from
+# a queue, its 4 B slot read and then reset to the empty mark.
+ALG_IO_BYTES = 16
+ALG_SERVED_BYTES = 8
+# Dependent device round trips per wave on the page variant's fast path
+# (queues already stocked): the request size (with the pool hint beside it),
+# the class state word, the head word, the slot.
+FAST_PATH_ROUND_TRIPS = 4
+
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def parse():
+def parse(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
@@ -63,11 +84,13 @@ def parse():
                     default="page")
     ap.add_argument("--width", type=int, default=64)
     ap.add_argument("--shards", type=int, default=0, help="queue shards (0: one per 256 chunks, up to 64)")
+    ap.add_argument("--detail", type=str, default="", help="write the full JSON record here (else to stderr)")
     ap.add_argument("--no-other", action="store_true", help="skip the other queue variant")
     ap.add_argument("--no-va", action="store_true", help="skip the virtualised-array and -list variant lines")
     ap.add_argument("--no-eager", action="store_true", help="skip the eager chunk retirement line")
     ap.add_argument("--no-ablation", action="store_true", help="skip the width-1 (no aggregation) ablation")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain device-malloc baseline")
+    ap.add_argument("--plain-iters", type=int, default=10, help="driver-loop iterations of the plain baseline")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--sizes", type=str, default="", help="comma list overriding the 16..8192 sweep")
@@ -78,7 +101,7 @@ def parse():
     ap.add_argument("--growth-reps", type=int, default=20)
     ap.add_argument("--serve-batches", type=int, default=10000, help="mixed batches per load point")
     ap.add_argument("--serve-slots", type=int, default=4)
-    return ap.parse_args()
+    return ap.parse_args(argv)
 
 
 # sources that make up the allocation kernel; the traffic recorded with the
@@ -111,6 +134,122 @@ def recorded_traffic():
     if kv.get("kernel_source_sha256") != kernel_digest() or "traffic_bytes_per_launch" not in kv:
         return None
     return float(kv["traffic_bytes_per_launch"])
+
+
+def alloc_roofline(launches, ceilings, chain_us, traffic):
+    """Roofline of the allocation kernel from its launches (per launch: the
+    requests n, the successful ones ok, the event-timed seconds t, the
+    counting pass's atomics by target for that launch's iteration kind).
+
+    Three bounds, each as the fraction of the launch time it would need:
+      * HBM: algorithmic bytes per launch (16 B per request, plus 8 B per
+        served page) against 8 TB/s;
+      * atomics: every atomic priced at the measured ceiling whose address
+        pattern matches it -- state, head/tail and pool words (one line per
+        shard and class) at the 64-line rate, ring slots (a wave on
+        consecutive words) at the lane-contiguous exchange rate, bitmask
+        and count words at the per-lane random rate;
+      * latency: the measured time of a kernel of the same number of waves
+        that runs the fast path's dependent round trips and nothing else.
+    The contract fields (bound/achieved/peak/unit/frac) report HBM; which of
+    the three is nearest its ceiling is `binding`."""
+    t_sum = sum(x["t"] for x in launches)
+    nl = len(launches)
+    alg_bytes = sum(ALG_IO_BYTES * x["n"] + ALG_SERVED_BYTES * x["ok"] for x in launches)
+    achieved = alg_bytes / t_sum / 1e9
+    price = {"state_ops": ceilings["lines_64"], "headtail_ops": ceilings["lines_64"],
+             "pool_ops": ceilings["lines_64"], "slot_ops": ceilings["xchg_contiguous"],
+             "spread_ops": ceilings["per_lane_random"]}
+    t_atomic = 0.0
+    per_kind = {k: 0 for k in price}
+    for x in launches:
+        for k, r in price.items():
+            c = x["atomics"].get(k, 0)
+            per_kind[k] += c
+            t_atomic += c / r
+    avg = t_sum / nl
+    frac_hbm = achieved / HBM_PEAK_GBPS
+    frac_atomic = t_atomic / t_sum
+    frac_latency = chain_us * 1e-6 / avg
+    binding = max((("hbm", frac_hbm), ("atomic", frac_atomic), ("latency", frac_latency)), key=lambda kv: kv[1])[0]
+    return {
+        "bound": "hbm",
+        "achieved": achieved,
+        "peak": HBM_PEAK_GBPS,
+        "unit": "GB/s",
+        "frac": frac_hbm,
+        "traffic": traffic,
+        "binding": binding,
+        "algorithmic_bytes_per_launch": alg_bytes / nl,
+        "avg_launch_us": avg * 1e6,
+        "launches": nl,
+        "atomic": {"frac": frac_atomic,
+                   "per_launch": {k: v / nl for k, v in per_kind.items()},
+                   "ceilings_g_per_s": {k: r / 1e9 for k, r in price.items()}},
+        "latency": {"frac": frac_latency, "floor_us": chain_us, "round_trips": FAST_PATH_ROUND_TRIPS},
+    }
+
+
+def compact(d: dict) -> dict:
+    """The one-line summary printed last on stdout (the driver keeps only the
+    tail of the output): the headline, its roofline and baselines, and one
+    figure per other line.  The full record is d itself."""
+    def r(x, nd=4):
+        if x is None:
+            return None
+        return float(f"{x:.{nd}g}")
+
+    head = d["headline"]
+    rl = head.get("roofline") or {}
+    out = {k: d[k] for k in ("metric", "value", "unit", "n_gpus", "steps", "warmup", "ms_per_step",
+                             "higher_is_better", "scaling", "vs_baseline", "dtype", "data", "config")}
+    out["value_all_iterations"] = head["value_all_iterations"]
+    out["first_iteration_ops_per_s"] = head.get("value_first_iteration")
+    out["wall_ops_per_s"] = head["wall_ops_per_s"]
+    out["batch_latency_us"] = {k: r(v) for k, v in head["batch_latency_us"].items()}
+    if rl:
+        out["roofline"] = {
+            "bound": rl["bound"], "achieved": r(rl["achieved"]), "peak": rl["peak"], "unit": rl["unit"],
+            "frac": r(rl["frac"]), "traffic": rl["traffic"], "kernel": rl.get("kernel"),
+            "binding": rl["binding"], "avg_launch_us": r(rl["avg_launch_us"]),
+            "algorithmic_bytes_per_launch": r(rl["algorithmic_bytes_per_launch"]),
+            "atomic_frac": r(rl["atomic"]["frac"]), "latency_frac": r(rl["latency"]["frac"]),
+            "latency_floor_us": r(rl["latency"]["floor_us"]),
+        }
+    cpu = d.get("cpu_baseline")
+    out["cpu_baseline"] = ({k: cpu[k] for k in ("value", "unit", "cores", "kind", "sample")} if cpu else None)
+    plain = d.get("plain")
+    out["vs_plain"] = r(d.get("vs_plain"))
+    if plain:
+        out["plain"] = {"value": r(plain.get("value")), "ours_same_sizes": r(plain.get("ours_same_sizes")),
+                        "iterations": plain.get("iterations"), "threads": plain.get("threads"),
+                        "null_requests": plain.get("null_requests"), "mismatches": plain.get("mismatches")}
+    variants = {}
+    for name, key in (("chunk", "other_variant"), ("va-page", "va_variant"), ("va-chunk", "va_chunk_variant"),
+                      ("vl-page", "vl_variant"), ("vl-chunk", "vl_chunk_variant"),
+                      ("chunk-eager", "eager_chunk_variant")):
+        v = d.get(key)
+        if v:
+            variants[v.get("variant", name) if key != "eager_chunk_variant" else name] = r(v["value"])
+    ab = d.get("ablation_width1")
+    if ab:
+        variants["width1"] = r(ab["value"])
+    out["variants_ops_per_s"] = variants
+    sv = d.get("serving")
+    if sv and "points" in sv:
+        out["serving"] = {"capacity_batches_per_s": r(sv["capacity_batches_per_s"]),
+                          "capacity_ops_per_s": r(sv["points"]["capacity"]["served_ops_per_s"])}
+        for f in ("0.25", "0.5", "0.9"):
+            p = sv["points"].get(f"load_{f}")
+            if p:
+                out["serving"][f"load_{f}"] = {"p50_us": r(p["latency_us"]["p50"]), "p99_us": r(p["latency_us"]["p99"]),
+                                               "failed": p["failed_requests"]}
+    g = d.get("growth")
+    if g and "graph_ms" in g:
+        out["growth"] = {"graph_ms": r(g["graph_ms"]), "alloc_free_ops_per_s": r(g["alloc_free_ops_per_s"]),
+                         "pick": g["autotune"]["best"], "margin_vs_default": r(g["autotune"]["margin_vs_default"])}
+    out["detail"] = d.get("detail_path")
+    return out
 
 
 _SLEEP_CYCLES_PER_US = None
@@ -190,20 +329,25 @@ def main():
     n = w.threads
     sizes_list = [int(x) for x in args.sizes.split(",")] if args.sizes else list(inputs.SWEEP_SIZES)
 
-    # ---------------- atomic ceilings ----------------
-    def probe(pattern, lines, threads, iters):
-        buf = torch.zeros(64 << 20, dtype=torch.uint8, device=dev)
+    # ---------------- device ceilings ----------------
+    probe_buf = torch.zeros(64 << 20, dtype=torch.uint8, device=dev)
+
+    def probe_time(pattern, lines, threads, iters, reps=3):
         best = None
-        for _ in range(3):
+        for _ in range(reps):
             e0, e1 = ev(), ev()
+            hold_stream(torch, 200.0)
             e0.record()
-            hb.hb_atomic_probe(pattern, buf, buf.numel(), threads, lines, iters)
+            hb.hb_atomic_probe(pattern, probe_buf, probe_buf.numel(), threads, lines, iters)
             e1.record()
             torch.cuda.synchronize()
             t = e0.elapsed_time(e1) / 1e3
             best = t if best is None else min(best, t)
-        n_at = threads * iters if pattern in (2, 4, 5, 6, 7) else threads // 64 * iters
-        return n_at / best
+        return best
+
+    def probe(pattern, lines, threads, iters):
+        n_at = threads * iters if pattern in (2, 4, 5, 6, 7, 8) else threads // 64 * iters
+        return n_at / probe_time(pattern, lines, threads, iters)
 
     # what an event pair adds around a launch: median over a one-wave kernel
     # doing a single atomic
@@ -223,17 +367,37 @@ def main():
         return float(np.median([e0.elapsed_time(e1) * 1e3 for e0, e1 in es]))
 
     ev_overhead = event_overhead_us()
-    ceil_same = probe(0, 1, 1 << 20, 4)
-    ceil_64 = probe(1, 64, 1 << 20, 4)
-    ceil_lines = probe(1, 1024, 1 << 20, 4)
-    ceil_spread = probe(2, 1, 1 << 20, 4)
-    log(f"atomic ceilings: same-address {ceil_same/1e9:.3f} G/s, 64 lines {ceil_64/1e9:.2f} G/s, "
-        f"1024 lines {ceil_lines/1e9:.2f} G/s, per-lane random {ceil_spread/1e9:.2f} G/s")
+    ceilings = {
+        "same_address": probe(0, 1, 1 << 20, 4),
+        "lines_64": probe(1, 64, 1 << 20, 4),
+        "lines_1024": probe(1, 1024, 1 << 20, 4),
+        "per_lane_random": probe(2, 1, 1 << 20, 4),
+        "xchg_contiguous": probe(5, 1, 1 << 20, 4),
+    }
+    # latency floor: 2^20 lanes in 256-lane blocks (the allocation kernel's
+    # launch shape), each running the fast path's dependent round trips
+    chain_us = probe_time(8, 1, n, FAST_PATH_ROUND_TRIPS, reps=5) * 1e6
+    chain1_us = probe_time(8, 1, n, 1, reps=5) * 1e6
+    a = torch.ones(1 << 30, dtype=torch.uint8, device=dev)
+    b = torch.empty_like(a)
+    tc = []
+    for _ in range(3):
+        e0, e1 = ev(), ev()
+        e0.record()
+        hb.hb_stream_copy(b, a, a.numel())
+        e1.record()
+        torch.cuda.synchronize()
+        tc.append(e0.elapsed_time(e1) / 1e3)
+    copy_gbps = 2 * a.numel() / min(tc) / 1e9
+    del a, b
+    log("ceilings: " + ", ".join(f"{k} {v/1e9:.2f} G/s" for k, v in ceilings.items()) +
+        f"; chain of {FAST_PATH_ROUND_TRIPS} round trips {chain_us:.1f} us (1: {chain1_us:.1f} us); "
+        f"copy {copy_gbps:.0f} GB/s")
 
     size_dev = {s: torch.from_numpy(inputs.sizes_fixed(n, s).view(np.int64)).to(dev) for s in sizes_list}
     ptrs = torch.zeros(n, dtype=torch.int64, device=dev)
     mism = torch.zeros(1, dtype=torch.int64, device=dev)
-    keys = ("state_ops", "headtail_ops", "pool_ops", "spread_ops")
+    keys = ("state_ops", "headtail_ops", "pool_ops", "spread_ops", "slot_ops")
 
     def run_sweep(variant_name: str, steps: int, warmup: int, count: bool, width: int | None = None) -> dict:
         variant = VARIANTS[variant_name]
@@ -304,8 +468,9 @@ def main():
             log(f"HEAP ERROR WORD {err:#x}")
             sys.exit(5)
 
-        per_size = {s: {"alloc_us": [], "free_us": [], "ok": 0} for s in sizes_list}
-        sub_ops = sub_t = all_ops = all_t = 0.0
+        per_size = {s: {"alloc_us": [], "free_us": [], "first_alloc_us": [], "first_free_us": [], "ok": 0}
+                    for s in sizes_list}
+        sub_ops = sub_t = all_ops = all_t = first_ops = first_t = 0.0
         t_alloc_sub, t_free_sub = [], []
         for s, it, e, ok in recs:
             ta = e[0].elapsed_time(e[1]) / 1e3
@@ -320,12 +485,18 @@ def main():
                 t_free_sub.append(tf)
                 per_size[s]["alloc_us"].append(ta * 1e6)
                 per_size[s]["free_us"].append(tf * 1e6)
+            else:
+                first_ops += 2 * okv
+                first_t += ta + tf
+                per_size[s]["first_alloc_us"].append(ta * 1e6)
+                per_size[s]["first_free_us"].append(tf * 1e6)
             per_size[s]["ok"] = okv
         out = {
             "variant": variant_name,
             "shards": shards,
             "value": sub_ops / sub_t,
             "value_all_iterations": all_ops / all_t,
+            "value_first_iteration": first_ops / first_t if first_t else None,
             "ms_per_step": wall / steps * 1e3,
             "wall_ops_per_s": all_ops / wall,
             "batch_latency_us": {
@@ -337,6 +508,8 @@ def main():
                     "ok": v["ok"],
                     "alloc_us": round(float(np.mean(v["alloc_us"])), 1),
                     "free_us": round(float(np.mean(v["free_us"])), 1),
+                    "first_alloc_us": round(float(np.mean(v["first_alloc_us"])), 1),
+                    "first_free_us": round(float(np.mean(v["first_free_us"])), 1),
                     "ops_per_s": round(2 * v["ok"] / ((np.mean(v["alloc_us"]) + np.mean(v["free_us"])) * 1e-6), 0),
                 }
                 for s, v in per_size.items()
@@ -347,42 +520,31 @@ def main():
                 out["per_size"][str(s)]["atomics_per_op_subsequent"] = {
                     ph: {k: round(c / max(1, per_size[s]["ok"]), 4) for k, c in counts[s]["subsequent"][ph].items()}
                     for ph in ("alloc", "free")}
-            # roofline of the dominant kernel, k_alloc_batch: all atomics it
-            # issues (counted in the counting pass) per launch over the average
-            # time of every non-counting allocation launch of this sweep
-            # (warmup + timed: the population a kernel trace averages over),
-            # against the measured device atomic throughput; the busiest queue
-            # word (a class state word, spread over the shards) against the
-            # same-address ceiling
-            alloc_t, atomics, state_atomics = [], 0, 0
+            # roofline of the dominant kernel, k_alloc_batch, over every
+            # non-counting allocation launch of this sweep (warmup + timed:
+            # the population a kernel trace averages over)
+            launches = []
             for s, it, e, ok in warm + recs:
-                alloc_t.append(e[0].elapsed_time(e[1]) / 1e3)
-                cnt = counts[s]["first" if it == 0 else "subsequent"]["alloc"]
-                atomics += sum(cnt.values())
-                state_atomics += cnt["state_ops"]
-            t_sum = sum(alloc_t)
-            achieved = atomics / t_sum
+                launches.append({"n": n, "ok": int(ok.item()), "t": e[0].elapsed_time(e[1]) / 1e3,
+                                 "atomics": counts[s]["first" if it == 0 else "subsequent"]["alloc"]})
+            rl = alloc_roofline(launches, ceilings, chain_us, recorded_traffic())
+            rl["kernel"] = f"k_alloc_batch<false, {variant}u>"
+            rl["event_overhead_us"] = ev_overhead
+            state_atomics = sum(x["atomics"]["state_ops"] for x in launches)
+            t_sum = sum(x["t"] for x in launches)
             busiest = state_atomics / shards / t_sum
-            out["roofline"] = {
-                "bound": "atomic",
-                "kernel": f"k_alloc_batch<false, {variant}u>",
-                "achieved": achieved / 1e9,
-                "peak": ceil_spread / 1e9,
-                "unit": "Gatomic/s (device-scope atomics issued; peak = measured per-lane random atomic throughput)",
-                "frac": achieved / ceil_spread,
-                "traffic": recorded_traffic(),
-                "avg_launch_us": float(np.mean(alloc_t)) * 1e6,
-                "event_overhead_us": ev_overhead,
-                "launches": len(alloc_t),
-                "atomics_per_launch": atomics / len(alloc_t),
-                "busiest_word": {"achieved": busiest / 1e9, "peak": ceil_same / 1e9, "frac": busiest / ceil_same,
-                                 "state_word_atomics_per_launch": state_atomics / len(alloc_t), "shards": shards},
-                "alloc_share_of_alloc_free_time": sum(t_alloc_sub) / (sum(t_alloc_sub) + sum(t_free_sub)),
-            }
+            rl["busiest_word"] = {"achieved_g_per_s": busiest / 1e9, "peak_g_per_s": ceilings["same_address"] / 1e9,
+                                  "frac": busiest / ceilings["same_address"], "shards": shards}
+            rl["alloc_share_of_alloc_free_time"] = sum(t_alloc_sub) / (sum(t_alloc_sub) + sum(t_free_sub))
+            out["roofline"] = rl
         return out
 
     head = run_sweep(args.variant, args.steps, args.warmup, count=True)
-    log(f"{args.variant}: {head['value']/1e9:.2f} G ops/s (iterations 2..10)")
+    log(f"{args.variant}: {head['value']/1e9:.2f} G ops/s (iterations 2..10), first iterations "
+        f"{(head['value_first_iteration'] or 0)/1e9:.2f} G ops/s; roofline: HBM frac {head['roofline']['frac']:.3f}, "
+        f"atomic frac {head['roofline']['atomic']['frac']:.3f}, latency frac {head['roofline']['latency']['frac']:.3f} "
+        f"(binding: {head['roofline']['binding']})")
+
     other = None
     if not args.no_other:
         other_name = "chunk" if args.variant != "chunk" else "page"
@@ -413,8 +575,9 @@ def main():
         # its own roofline (atomics counted in its counting pass); the
         # recorded HBM traffic belongs to the headline's page instance
         eager["roofline"]["traffic"] = None
-        log(f"chunk-eager: {eager['value']/1e9:.2f} G ops/s (iterations 2..10), roofline frac "
-            f"{eager['roofline']['frac']:.3f} ({eager['roofline']['atomics_per_launch']:.0f} atomics per launch)")
+        log(f"chunk-eager: {eager['value']/1e9:.2f} G ops/s (iterations 2..10), roofline: HBM frac "
+            f"{eager['roofline']['frac']:.3f}, atomic frac {eager['roofline']['atomic']['frac']:.3f}, latency frac "
+            f"{eager['roofline']['latency']['frac']:.3f}")
         eager["class_change"] = {}
         for name, fl in (("lazy", 0), ("eager", hb.FLAG_EAGER)):
             heap = hb.Heap(w.heap_bytes, w.chunk_bytes, variant=hb.VARIANT_CHUNK, shards=args.shards, flags=fl)
@@ -494,43 +657,58 @@ def main():
                     "aggregation_speedup": head["value"] / a["value"]}
         log(f"width 1 ablation: {a['value']/1e9:.2f} G ops/s")
 
+
     # ---------------- plain baseline: runtime device malloc/free ----------------
+    # the same driver loop as ours (alloc -> write -> check -> free, ten
+    # iterations per size, 2^20 threads at every size); requests the runtime
+    # cannot serve come back NULL and are counted, never shrunk away
     plain = None
     if not args.no_plain:
-        plain = {"sizes": {}}
-        rc = hb.hb_plain_set_heap(6 << 30)
-        plain["heap_limit_rc"] = rc
+        plain = {"sizes": {}, "threads": n, "iterations": args.plain_iters}
+        plain["heap_limit_rc"] = hb.hb_plain_set_heap(6 << 30)
+        plain["heap_limit_bytes"] = 6 << 30
         p_ptrs = torch.zeros(n, dtype=torch.int64, device=dev)
-        tot_ops, tot_t = 0, 0.0
+        p_mism = torch.zeros(1, dtype=torch.int64, device=dev)
+        tot_ops = tot_t = 0.0
+        nulls = 0
         for s in sizes_list:
-            nn = n if s <= 1024 else (1 << 16)
-            sd = size_dev[s][:nn]
-            pp = p_ptrs[:nn]
-            e = [ev() for _ in range(4)]
-            e[0].record()
-            hb.hb_plain_alloc(sd, pp)
-            e[1].record()
-            ok = int((pp != 0).sum().item())
-            e[2].record()
-            hb.hb_plain_free(pp)
-            e[3].record()
-            torch.cuda.synchronize()
-            t = (e[0].elapsed_time(e[1]) + e[2].elapsed_time(e[3])) / 1e3
-            plain["sizes"][str(s)] = {"threads": nn, "ok": ok, "ops_per_s": round(2 * ok / t, 0),
-                                      "alloc_us": round(e[0].elapsed_time(e[1]) * 1e3, 1),
-                                      "free_us": round(e[2].elapsed_time(e[3]) * 1e3, 1)}
-            if nn == n:
-                tot_ops += 2 * ok
-                tot_t += t
-            log(f"plain size={s} threads={nn} ok={ok} {2*ok/t/1e6:.2f} M ops/s")
-        plain["value_full_size_sizes"] = tot_ops / tot_t if tot_t else None
-        # ours over the same sizes (those the plain kernel ran at 2^20 threads)
+            sd = size_dev[s]
+            ta, tf, oks = [], [], []
+            for it in range(args.plain_iters):
+                e = [ev() for _ in range(4)]
+                e[0].record()
+                hb.hb_plain_alloc(sd, p_ptrs)
+                e[1].record()
+                hb.hb_plain_pattern(p_ptrs, sd, w.seed)
+                hb.hb_plain_pattern(p_ptrs, sd, w.seed, p_mism)
+                ok = int((p_ptrs != 0).sum().item())
+                e[2].record()
+                hb.hb_plain_free(p_ptrs)
+                e[3].record()
+                torch.cuda.synchronize()
+                ta.append(e[0].elapsed_time(e[1]) / 1e3)
+                tf.append(e[2].elapsed_time(e[3]) / 1e3)
+                oks.append(ok)
+                log(f"plain size={s} iteration {it + 1}: ok {ok} of {n}, alloc {ta[-1]*1e3:.1f} ms, "
+                    f"free {tf[-1]*1e3:.1f} ms")
+            sub = slice(1, None) if len(ta) > 1 else slice(0, None)
+            t_sub = sum(ta[sub]) + sum(tf[sub])
+            ops_sub = 2 * sum(oks[sub])
+            nulls += sum(n - x for x in oks)
+            plain["sizes"][str(s)] = {"ok_per_iteration": oks, "alloc_us": [round(x * 1e6, 1) for x in ta],
+                                      "free_us": [round(x * 1e6, 1) for x in tf],
+                                      "ops_per_s_subsequent": ops_sub / t_sub if t_sub else None}
+            tot_ops += ops_sub
+            tot_t += t_sub
+        plain["null_requests"] = nulls
+        plain["mismatches"] = int(p_mism.item())
+        plain["value"] = tot_ops / tot_t if tot_t else None
+        # ours over the same sizes and iterations (2..10 of each size)
         o_ops = o_t = 0.0
         for s in sizes_list:
-            if s <= 1024:
-                v = head["per_size"][str(s)]
-                o_ops += 2 * v["ok"]
-                o_t += (v["alloc_us"] + v["free_us"]) * 1e-6
+            v = head["per_size"][str(s)]
+            o_ops += 2 * v["ok"]
+            o_t += (v["alloc_us"] + v["free_us"]) * 1e-6
         plain["ours_same_sizes"] = o_ops / o_t if o_t else None
 
     # ---------------- CPU baseline: the oracle on a bounded sample ----------------
@@ -561,8 +739,8 @@ def main():
     growth = None if args.no_growth else bench_growth(hb, inputs, torch, args, ev, log)
     serve = None if args.no_serve else bench_serve(hb, inputs, torch, args, log)
 
-    out = {
-        "metric": "device malloc+free ops/sec (2^20 threads, 16B-8KiB) vs plain; p99 batch latency",
+    detail = {
+        "metric": METRIC,
         "value": head["value"],
         "unit": "ops/s",
         "n_gpus": 1,
@@ -584,13 +762,11 @@ def main():
             "iterations_per_size": args.iters,
             "sizes": sizes_list,
         },
-        "value_all_iterations": head["value_all_iterations"],
-        "wall_ops_per_s": head["wall_ops_per_s"],
-        "batch_latency_us": head["batch_latency_us"],
-        "roofline": head["roofline"],
-        "atomic_ceilings_gps": {"same_address": ceil_same / 1e9, "lines_64": ceil_64 / 1e9,
-                                "lines_1024": ceil_lines / 1e9, "per_lane_random": ceil_spread / 1e9},
-        "per_size": head["per_size"],
+        "headline": head,
+        "ceilings_g_per_s": {k: v / 1e9 for k, v in ceilings.items()},
+        "latency_chain_us": {str(FAST_PATH_ROUND_TRIPS): chain_us, "1": chain1_us},
+        "copy_gb_per_s": copy_gbps,
+        "event_overhead_us": ev_overhead,
         "other_variant": other,
         "va_variant": va,
         "va_chunk_variant": va_chunk,
@@ -599,14 +775,22 @@ def main():
         "eager_chunk_variant": eager,
         "ablation_width1": ablation,
         "plain": plain,
-        "vs_plain": (plain["ours_same_sizes"] / plain["value_full_size_sizes"])
-        if plain and plain["value_full_size_sizes"] and plain["ours_same_sizes"] else None,
+        "vs_plain": (plain["ours_same_sizes"] / plain["value"])
+        if plain and plain["value"] and plain["ours_same_sizes"] else None,
         "cpu_baseline": cpu,
         "paper_sweeps": paper,
         "growth": growth,
         "serving": serve,
+        "detail_path": args.detail or None,
     }
-    print(json.dumps(out), flush=True)
+    text = json.dumps(detail)
+    if args.detail:
+        os.makedirs(os.path.dirname(os.path.abspath(args.detail)), exist_ok=True)
+        with open(args.detail, "w") as f:
+            f.write(text + "\n")
+    else:
+        print("detail " + text, file=sys.stderr, flush=True)
+    print(json.dumps(compact(detail)), flush=True)
 
 
 def bench_paper_sweeps(hb, inputs, torch, args, ev, log):

@@ -197,9 +197,12 @@ int heap_pattern_check(heap_t h, void* const* ptrs, const size_t* sizes, size_t 
  *   pattern 5: one 32-bit exchange per lane, lanes on consecutive words;
  *   pattern 6: one coherent (device-scope) 32-bit load and store per lane,
  *              lanes on consecutive words;
- *   pattern 7: the same with 64-bit words.
+ *   pattern 7: the same with 64-bit words;
+ *   pattern 8: a chain of 32-bit atomic adds per lane, lanes on consecutive
+ *              words, each add's address depending on the value the lane's
+ *              previous add returned (dependent round trips).
  * `threads` lanes each repeat `iters` times.  Operations issued: patterns 2
- * and 4..7: threads * iters; others: threads / 64 * iters. */
+ * and 4..8: threads * iters; others: threads / 64 * iters. */
 int hb_atomic_probe(int pattern, void* buf, size_t buf_bytes, size_t threads, uint32_t lines, uint32_t iters,
                     hipStream_t stream);
 
@@ -211,6 +214,13 @@ int hb_stream_copy(void* dst, const void* src, size_t bytes, hipStream_t stream)
 int hb_plain_set_heap(size_t bytes);
 int hb_plain_alloc(const size_t* sizes, void** ptrs, size_t n, hipStream_t stream);
 int hb_plain_free(void* const* ptrs, size_t n, hipStream_t stream);
+/* The payload words of heap_pattern_write / heap_pattern_check, for blocks
+ * of the runtime's allocator (ptrs from hb_plain_alloc; device buffers):
+ * writes them when mismatches is NULL, else checks them and adds the number
+ * of mismatching words to *mismatches (a device u64).  NULL blocks are
+ * skipped. */
+int hb_plain_pattern(void* const* ptrs, const size_t* sizes, size_t n, uint32_t seed, unsigned long long* mismatches,
+                     hipStream_t stream);
 
 /* Library version string. */
 const char* hbheap_version(void);

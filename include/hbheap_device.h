@@ -246,25 +246,29 @@ struct Backoff {
 };
 
 /* Atomics issued, by target, when HBHEAP_FLAG_STATS is set: class state
- * words, class head/tail words, the pool counter, and per-lane atomics on
- * slots, bitmasks and chunk counts. */
+ * words, class head/tail words, the pool counter, per-lane atomics on
+ * bitmasks, chunk counts and segment counters (spread), and per-lane
+ * atomics on ring slots (slot: the lanes of a wave take or fill consecutive
+ * positions, so these have their own, lane-contiguous address pattern). */
 struct Tally {
-    uint32_t state = 0, headtail = 0, pool = 0, spread = 0;
+    uint32_t state = 0, headtail = 0, pool = 0, spread = 0, slot = 0;
 };
 
 __device__ __forceinline__ void tally_flush(const hbheap_dev_t& h, const Tally& t)
 {
     if (!(h.flags & HBHEAP_FLAG_STATS)) return;
-    uint32_t s, ht, pl, sp;
+    uint32_t s, ht, pl, sp, sl;
     (void)excl_scan<20>(t.state, &s);
     (void)excl_scan<20>(t.headtail, &ht);
     (void)excl_scan<20>(t.pool, &pl);
     (void)excl_scan<20>(t.spread, &sp);
+    (void)excl_scan<20>(t.slot, &sl);
     if (lane() == ctz64(exec_mask())) {
         if (s) a_add64(h.stats + HBHEAP_STAT_STATE_OPS, s);
         if (ht) a_add64(h.stats + HBHEAP_STAT_HEADTAIL_OPS, ht);
         if (pl) a_add64(h.stats + HBHEAP_STAT_POOL_OPS, pl);
         if (sp) a_add64(h.stats + HBHEAP_STAT_SPREAD_OPS, sp);
+        if (sl) a_add64(h.stats + HBHEAP_STAT_SLOT_OPS, sl);
     }
 }
 
@@ -727,7 +731,7 @@ __device__ __forceinline__ uint32_t plain_take(const hbheap_dev_t& h, uint32_t* 
 {
     {
         const uint32_t v = a_xchg32(s, kEmpty);
-        t.spread += 1;
+        t.slot += 1;
         if (v != kEmpty) return v;
     }
     Backoff b;
@@ -738,7 +742,7 @@ __device__ __forceinline__ uint32_t plain_take(const hbheap_dev_t& h, uint32_t* 
         }
         if (a_load32(s) != kEmpty) {
             const uint32_t v = a_xchg32(s, kEmpty);
-            t.spread += 1;
+            t.slot += 1;
             if (v != kEmpty) return v;
         }
     }
@@ -763,7 +767,7 @@ __device__ __forceinline__ bool slot_put(const hbheap_dev_t& h, const Ring& r, u
  * the previous lap makes it poll with loads. */
 __device__ __forceinline__ bool plain_put(const hbheap_dev_t& h, uint32_t* s, uint32_t v, Tally& t)
 {
-    t.spread += 1;
+    t.slot += 1;
     if (a_cas32(s, kEmpty, v)) return true;
     Backoff b;
     for (;;) {
@@ -772,7 +776,7 @@ __device__ __forceinline__ bool plain_put(const hbheap_dev_t& h, uint32_t* s, ui
             return false;
         }
         if (a_load32(s) == kEmpty) {
-            t.spread += 1;
+            t.slot += 1;
             if (a_cas32(s, kEmpty, v)) return true;
         }
     }

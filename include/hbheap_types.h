@@ -70,12 +70,14 @@ extern "C" {
 #define HBHEAP_STAT_INVALID_FREE  5
 #define HBHEAP_STAT_TIMEOUTS      6
 /* atomics issued, by target (FLAG_STATS): class state words, class head and
- * tail words, the pool counters, per-lane slot/bitmask/count atomics */
+ * tail words, the pool counters, per-lane bitmask/count atomics (spread);
+ * per-lane ring slot atomics are counted apart (SLOT_OPS) */
 #define HBHEAP_STAT_STATE_OPS     8
 #define HBHEAP_STAT_HEADTAIL_OPS  9
 #define HBHEAP_STAT_POOL_OPS      10
 #define HBHEAP_STAT_SPREAD_OPS    11
 #define HBHEAP_STAT_RETIRED       12  /* chunks retired eagerly (FLAG_STATS)     */
+#define HBHEAP_STAT_SLOT_OPS      13  /* per-lane ring slot atomics (FLAG_STATS) */
 #define HBHEAP_STAT_COUNT         16
 
 /*

@@ -717,10 +717,10 @@ int orc_check_blocks(uint64_t data_bytes, uint64_t chunk_bytes, const uint64_t* 
 }
 
 /* ------------------------------------------------------------------ */
-/* invariant checker: snapshot (layout version 2)                      */
+/* invariant checker: snapshot (layout version 3)                      */
 /*                                                                     */
 /* header (256 B, little-endian):                                      */
-/*   0 u32 magic 0x48424850   4 u32 version 2     8 u64 data_bytes     */
+/*   0 u32 magic 0x48424850   4 u32 version 3     8 u64 data_bytes     */
 /*  16 u32 n_chunks          20 u32 log2_chunk   24 u32 n_classes      */
 /*  28 u32 variant           32 u32 words/chunk  36 u32 log2 ring cap  */
 /*  40 u32 shards S          44 u32 log2 span    48 u64 off pools      */

@@ -20,25 +20,43 @@ def hipcc() -> str:
     raise RuntimeError("hipcc not found (ROCm toolchain required to build libhbheap.so)")
 
 
-def command(out: str) -> list[str]:
-    return [
-        hipcc(), f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-shared",
-        # packed fp32 ops off: the allocator has no fp32 arithmetic, and this
-        # keeps the compiler from emitting v_pk_*_f32 anywhere in the library
-        "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-        "-Wall", "-I", os.path.join(ROOT, "include"),
-        "-o", out,
-    ] + [os.path.join(HERE, s) for s in SOURCES]
+FLAGS = [
+    f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",
+    # packed fp32 ops off: the allocator has no fp32 arithmetic, and this
+    # keeps the compiler from emitting v_pk_*_f32 anywhere in the library
+    "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    "-Wall", "-I", os.path.join(ROOT, "include"),
+]
+OBJ_DIR = os.path.join(ROOT, "_build")
 
 
-def build(verbose: bool = False) -> str:
-    tmp = LIB + ".tmp"
-    cmd = command(tmp)
+def compile_command(src: str, obj: str) -> list[str]:
+    return [hipcc()] + FLAGS + ["-c", "-o", obj, os.path.join(HERE, src)]
+
+
+def link_command(objs: list[str], out: str) -> list[str]:
+    return [hipcc(), f"--offload-arch={ARCH}", "-fPIC", "-shared", "-o", out] + objs
+
+
+def _run(cmd: list[str], verbose: bool):
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed ({r.returncode}):\n{r.stderr}")
+
+
+def build(verbose: bool = False) -> str:
+    """Compile every source (in parallel, one hipcc each) and link the shared
+    library; it always recompiles."""
+    from concurrent.futures import ThreadPoolExecutor
+    os.makedirs(OBJ_DIR, exist_ok=True)
+    objs = [os.path.join(OBJ_DIR, os.path.basename(s).replace(".hip", ".o")) for s in SOURCES]
+    with ThreadPoolExecutor(max_workers=len(SOURCES)) as ex:
+        for f in [ex.submit(_run, compile_command(s, o), verbose) for s, o in zip(SOURCES, objs)]:
+            f.result()
+    tmp = LIB + ".tmp"
+    _run(link_command(objs, tmp), verbose)
     os.replace(tmp, LIB)
     return LIB
 

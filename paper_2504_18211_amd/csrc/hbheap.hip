@@ -3,7 +3,7 @@
  * (C ABI in include/hbheap.h, device API in include/hbheap_device.h).
  *
  * Contents:
- *   - heap creation: state-region layout (snapshot version 2) and init;
+ *   - heap creation: state-region layout (snapshot version 3) and init;
  *   - batch alloc / free kernels (one lane per request, 256-lane blocks);
  *   - single-lane replay kernel;
  *   - quiescent trim: retire fully free chunks, rebuild pool and queues in
@@ -623,6 +623,20 @@ __global__ void __launch_bounds__(kBatchBlock) k_atomic_probe(int pattern, uint6
         }
         break;
     }
+    case 8: {
+        /* a chain of dependent round trips: each lane's next 32-bit atomic
+         * add waits for the value of its previous one (its address depends
+         * on it), lanes on consecutive words -- the latency floor of a kernel
+         * whose waves each run `iters` such round trips one after another */
+        uint32_t* w32 = (uint32_t*)buf;
+        const uint64_t words32 = words64 * 2;
+        uint32_t v = 0;
+        for (uint32_t it = 0; it < iters; ++it) {
+            v = a_add32(w32 + (tid + (uint64_t)it * threads) % words32 + zero_after(v), 1u);
+            acc += v;
+        }
+        break;
+    }
     default:
         break;
     }
@@ -1139,10 +1153,22 @@ int heap_pattern_check(heap_t h, void* const* ptrs, const size_t* sizes, size_t 
     return hipGetLastError() == hipSuccess ? HBHEAP_OK : HBHEAP_E_HIP;
 }
 
+int hb_plain_pattern(void* const* ptrs, const size_t* sizes, size_t n, uint32_t seed, unsigned long long* mismatches,
+                     hipStream_t stream)
+{
+    if (n && (!ptrs || !sizes)) return HBHEAP_E_INVAL;
+    if (!n) return HBHEAP_OK;
+    /* blocks of the runtime's allocator may lie anywhere: no region check */
+    hipLaunchKernelGGL(k_pattern, dim3(grid_for(n, kBatchBlock)), dim3(kBatchBlock), 0, stream, ptrs,
+                       (const uint64_t*)sizes, (uint64_t)n, seed, mismatches, mismatches ? 1 : 0,
+                       (const uint8_t*)nullptr, ~0ull);
+    return hipGetLastError() == hipSuccess ? HBHEAP_OK : HBHEAP_E_HIP;
+}
+
 int hb_atomic_probe(int pattern, void* buf, size_t buf_bytes, size_t threads, uint32_t lines, uint32_t iters,
                     hipStream_t stream)
 {
-    if (!buf || buf_bytes < 4096 || pattern < 0 || pattern > 7 || !threads || !iters) return HBHEAP_E_INVAL;
+    if (!buf || buf_bytes < 4096 || pattern < 0 || pattern > 8 || !threads || !iters) return HBHEAP_E_INVAL;
     if (pattern == 1 && (!lines || (uint64_t)lines * 128 > buf_bytes)) return HBHEAP_E_INVAL;
     hipLaunchKernelGGL(k_atomic_probe, dim3(grid_for(threads, kBatchBlock)), dim3(kBatchBlock), 0, stream, pattern,
                        (uint64_t*)buf, (uint64_t)(buf_bytes / 8), lines, iters, (uint64_t)threads);

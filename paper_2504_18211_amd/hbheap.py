@@ -19,7 +19,7 @@ OK, E_INVAL, E_NOMEM, E_HIP, E_RANGE, E_UNSUP = 0, -1, -2, -3, -4, -5
 ERR_DOUBLE_FREE, ERR_INVALID_FREE, ERR_TIMEOUT, ERR_CORRUPT = 0x1, 0x2, 0x4, 0x8
 FLAG_STATS, FLAG_VERIFY, FLAG_HOME0, FLAG_EAGER = 0x1, 0x2, 0x4, 0x8
 STAT_NAMES = ["chunk_grabs", "refills", "oom", "oom_waits", "double_free", "invalid_free", "timeouts", "reserved7",
-              "state_ops", "headtail_ops", "pool_ops", "spread_ops", "retired", "reserved13", "reserved14",
+              "state_ops", "headtail_ops", "pool_ops", "spread_ops", "retired", "slot_ops", "reserved14",
               "reserved15"]
 FREE_OK, FREE_DOUBLE, FREE_INVALID, FREE_NULL = 0, 1, 2, 3
 
@@ -27,7 +27,7 @@ EXPORTS = [
     "heap_create", "heap_create_ex", "heap_destroy", "heap_alloc_batch", "heap_free_batch", "heap_free_batch_ex",
     "heap_device_handle", "heap_set_flags", "heap_info", "heap_trim", "heap_snapshot", "heap_get_error", "heap_clear_error",
     "heap_stats", "heap_replay", "heap_pattern_write", "heap_pattern_check", "hb_atomic_probe", "hb_stream_copy",
-    "hb_plain_set_heap", "hb_plain_alloc", "hb_plain_free", "hbheap_version",
+    "hb_plain_set_heap", "hb_plain_alloc", "hb_plain_free", "hb_plain_pattern", "hbheap_version",
     "growth_create", "growth_destroy", "growth_step", "growth_graph_launch", "growth_release", "growth_export",
     "growth_launch_shape", "growth_autotune",
     "serve_create", "serve_destroy", "serve_run", "serve_export", "heap_chunks_in_use",
@@ -120,6 +120,7 @@ def lib():
         "hb_plain_set_heap": [sz],
         "hb_plain_alloc": [vp, vp, sz, vp],
         "hb_plain_free": [vp, sz, vp],
+        "hb_plain_pattern": [vp, vp, sz, u32, vp, vp],
         "growth_create": [vp, u32, vp, u32, u32, C.POINTER(vp)],
         "growth_destroy": [vp],
         "growth_step": [vp, u32, vp],
@@ -279,6 +280,14 @@ def hb_plain_alloc(sizes, ptrs, n: int | None = None, stream=None):
 def hb_plain_free(ptrs, n: int | None = None, stream=None):
     n = ptrs.numel() if n is None else n
     _check("hb_plain_free", lib().hb_plain_free(_addr(ptrs), n, _stream(stream)))
+
+
+def hb_plain_pattern(ptrs, sizes, seed: int, mismatches=None, n: int | None = None, stream=None):
+    """Write (mismatches None) or check the payload words in blocks of the
+    runtime's allocator."""
+    n = ptrs.numel() if n is None else n
+    _check("hb_plain_pattern", lib().hb_plain_pattern(_addr(ptrs), _addr(sizes), n, seed, _addr(mismatches),
+                                                      _stream(stream)))
 
 
 def hbheap_version() -> str:

@@ -7,6 +7,7 @@ free list), brute force on small inputs (an occupancy map over every byte),
 exact accounting, and the published MurmurHash3 vectors for the payload
 pattern.  Each test names the mistake it would catch.
 """
+import functools
 import os
 import struct
 
@@ -872,3 +873,113 @@ def test_vl_snapshot_clean_and_planted_faults(variant):
     assert O.check_snapshot(bytes(x)).bad_vstore > 0
     # committed pages that do not match the classes' chunks
     assert O.check_snapshot(_vl_state(variant, lambda r, o, v: v.update(committed=[5]))).bad_committed > 0
+
+
+# ---------------------------------------------------------------------------
+# virtualised array page variant: the shared page budget, brute-forced
+# ---------------------------------------------------------------------------
+#
+# A page queue in segments of G slots holds every segment from the one its
+# head is in (slots before the head consumed, the segment not yet closed) to
+# the one of its last entry; a segment whose last slot was consumed is on
+# its way back to the store until its closer returns it.  A class that owns
+# P pages has at most P entries queued.  The budget of a shard's classes
+# must leave enough segments that a producer always finds one in the store
+# (the reading of the paper's virtualised array: queues taking storage on
+# demand), in every state where each queue's entries are contiguous and at
+# most one segment per queue is being handed back.
+
+def _held_segments(h, e, G):
+    """Segments one queue holds, enumerated position by position: the head
+    h slots into its segment, e entries from the head on."""
+    return len({p // G for p in range(h + e)})
+
+
+@functools.lru_cache(maxsize=None)
+def _queue_worst(P, G):
+    """Most segments one queue of a class owning P pages can need: every
+    head offset, every entry count up to P, plus one being handed back."""
+    if P == 0:
+        return 0
+    return max(_held_segments(h, e, G) for h in range(G) for e in range(P + 1)) + 1
+
+
+def _most_segments(ppcs, G, budget):
+    """Most segments the queues of one shard can need at once when its
+    classes (pages per chunk ppcs) own at most `budget` pages together:
+    over every split of the budget into whole chunks per class (group
+    knapsack; each class's worst for a given chunk count from _queue_worst,
+    or for large P or G from its closed form, checked against it below)."""
+    best = [0] * (budget + 1)     # best[b]: most segments with b pages owned so far
+    for ppc in ppcs:
+        items = []
+        last = None
+        for c in range(1, budget // ppc + 1):
+            P = c * ppc
+            w = _queue_worst(P, G) if P <= 2 * G and G <= 16 else (P + 2 * G - 2) // G + 1
+            if w != last:
+                items.append((P, w))
+                last = w
+        nxt = best[:]
+        for b in range(budget + 1):
+            for P, w in items:
+                if P > b:
+                    break
+                if best[b - P] + w > nxt[b]:
+                    nxt[b] = best[b - P] + w
+        best = nxt
+    return max(best)
+
+
+def test_queue_worst_closed_form_matches_the_enumeration():
+    """The shortcut _most_segments takes for P > 2G (head one slot before its
+    segment's end, P entries: ceil((G - 1 + P) / G) segments, plus the one
+    handed back), checked against the enumeration where that is cheap."""
+    for G in (4, 8, 16):
+        for P in range(1, 6 * G):
+            assert _queue_worst(P, G) == (P + 2 * G - 2) // G + 1, (G, P)
+
+
+def test_va_budget_exhaustive_tiny():
+    """Exhaustive over tiny shards: with a reserve of 3K segments (K queues)
+    no split of the owned pages, no head offsets, entry counts or hand-backs
+    need more than the shard's M segments; with a reserve of 2K, states
+    that do exist in most of these shapes, so a budget that kept only 2K
+    back would let a producer find the store empty."""
+    import itertools
+    short = []
+    for K, G, ppcs in [(1, 4, (2,)), (2, 4, (4, 1)), (3, 4, (4, 2, 1)), (2, 8, (2, 1)), (3, 8, (8, 4, 1))]:
+        for M in range(3 * K + 1, 3 * K + 4):
+            worst = {}
+            for reserve in (2, 3):
+                budget = (M - reserve * K) * G
+                most = 0
+                ranges = [range(0, budget // p + 1) for p in ppcs]
+                for chunks in itertools.product(*ranges):
+                    P = [c * p for c, p in zip(chunks, ppcs)]
+                    if sum(P) > budget:
+                        continue
+                    most = max(most, sum(_queue_worst(x, G) for x in P))
+                worst[reserve] = most
+                assert most == _most_segments(ppcs, G, budget), (K, G, ppcs, M, reserve)
+            assert worst[3] <= M, (K, G, ppcs, M, worst)
+            short.append(worst[2] > M)
+    # a 2K reserve falls short wherever a class of few pages per chunk can
+    # leave its queue two slots into a segment (not for every tiny shape)
+    assert sum(short) >= len(short) // 2, short
+
+
+@pytest.mark.parametrize("nbytes,C,S", [(1 << 20, 4096, 1), (1 << 20, 4096, 2), (2 << 20, 8192, 4),
+                                        (4 << 20, 16384, 8), (512 << 10, 4096, 1)])
+def test_va_budget_never_drains_the_store(nbytes, C, S):
+    """The oracle's budget on real geometries (K classes of C / 16 / 2^k
+    pages per chunk, the oracle's G and M): the worst state fits in the
+    shard's M segments; a budget with a 2K reserve instead would not."""
+    K = O.num_classes(C)
+    G = 1 << O.va_log2_seg(nbytes, C, S)
+    M = O.va_segments(nbytes, C, S)
+    ppcs = [C // 16 >> k for k in range(K)]
+    budget = O.va_budget(nbytes, C, S)
+    assert 0 < budget
+    assert _most_segments(ppcs, G, budget) <= M
+    assert _most_segments(ppcs, G, (M - 2 * K) * G) > M
