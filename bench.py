@@ -83,6 +83,7 @@ def parse(argv=None):
     ap.add_argument("--variant", choices=["chunk", "page", "va-page", "va-chunk", "vl-page", "vl-chunk"],
                     default="page")
     ap.add_argument("--width", type=int, default=64)
+    ap.add_argument("--rows", type=int, default=0, help="requests per lane of the batch kernels (0: the library's 4)")
     ap.add_argument("--shards", type=int, default=0, help="queue shards (0: one per 256 chunks, up to 64)")
     ap.add_argument("--detail", type=str, default="", help="write the full JSON record here (else to stderr)")
     ap.add_argument("--no-other", action="store_true", help="skip the other queue variant")
@@ -91,6 +92,9 @@ def parse(argv=None):
     ap.add_argument("--no-ablation", action="store_true", help="skip the width-1 (no aggregation) ablation")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain device-malloc baseline")
     ap.add_argument("--plain-iters", type=int, default=10, help="driver-loop iterations of the plain baseline")
+    ap.add_argument("--plain-sizes", type=str, default="16,32,64,128,256,512,1024,2048",
+                    help="sizes of the plain baseline (at 2^20 threads one iteration takes 44 s at 4 KiB, so the "
+                         "default run stops at 2 KiB)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--sizes", type=str, default="", help="comma list overriding the 16..8192 sweep")
@@ -134,6 +138,14 @@ def recorded_traffic():
     if kv.get("kernel_source_sha256") != kernel_digest() or "traffic_bytes_per_launch" not in kv:
         return None
     return float(kv["traffic_bytes_per_launch"])
+
+
+def head_rows_of(args, variant: int, width: int | None = None) -> int:
+    """Requests per lane of the allocation kernel the library launches for
+    this heap: its rows (4 by default) for the page and virtualised-array
+    page variants at width 16 or more, else one."""
+    width = args.width if width is None else width
+    return (args.rows or 4) if variant in (1, 2) and width >= 16 else 1
 
 
 def alloc_roofline(launches, ceilings, chain_us, traffic):
@@ -205,6 +217,9 @@ def compact(d: dict) -> dict:
                              "higher_is_better", "scaling", "vs_baseline", "dtype", "data", "config")}
     out["value_all_iterations"] = head["value_all_iterations"]
     out["first_iteration_ops_per_s"] = head.get("value_first_iteration")
+    out["alloc_us_by_size"] = {s: {"first": v["first_alloc_us"], "later": v["alloc_us"]}
+                               for s, v in head["per_size"].items()}
+    out["free_us_by_size"] = {s: v["free_us"] for s, v in head["per_size"].items()}
     out["wall_ops_per_s"] = head["wall_ops_per_s"]
     out["batch_latency_us"] = {k: r(v) for k, v in head["batch_latency_us"].items()}
     if rl:
@@ -223,6 +238,7 @@ def compact(d: dict) -> dict:
     if plain:
         out["plain"] = {"value": r(plain.get("value")), "ours_same_sizes": r(plain.get("ours_same_sizes")),
                         "iterations": plain.get("iterations"), "threads": plain.get("threads"),
+                        "sizes": [int(x) for x in plain.get("sizes", {})], "not_run": plain.get("not_run"),
                         "null_requests": plain.get("null_requests"), "mismatches": plain.get("mismatches")}
     variants = {}
     for name, key in (("chunk", "other_variant"), ("va-page", "va_variant"), ("va-chunk", "va_chunk_variant"),
@@ -374,10 +390,12 @@ def main():
         "per_lane_random": probe(2, 1, 1 << 20, 4),
         "xchg_contiguous": probe(5, 1, 1 << 20, 4),
     }
-    # latency floor: 2^20 lanes in 256-lane blocks (the allocation kernel's
-    # launch shape), each running the fast path's dependent round trips
-    chain_us = probe_time(8, 1, n, FAST_PATH_ROUND_TRIPS, reps=5) * 1e6
-    chain1_us = probe_time(8, 1, n, 1, reps=5) * 1e6
+    # latency floor: the allocation kernel's launch shape (one lane per
+    # `rows` requests, 256-lane blocks), each lane running the fast path's
+    # dependent round trips (a lane's rows share every round trip)
+    head_rows = head_rows_of(args, VARIANTS[args.variant])
+    chain_us = probe_time(8, 1, n // head_rows, FAST_PATH_ROUND_TRIPS, reps=5) * 1e6
+    chain1_us = probe_time(8, 1, n // head_rows, 1, reps=5) * 1e6
     a = torch.ones(1 << 30, dtype=torch.uint8, device=dev)
     b = torch.empty_like(a)
     tc = []
@@ -402,7 +420,7 @@ def main():
     def run_sweep(variant_name: str, steps: int, warmup: int, count: bool, width: int | None = None) -> dict:
         variant = VARIANTS[variant_name]
         heap = hb.Heap(w.heap_bytes, w.chunk_bytes, variant=variant, width=args.width if width is None else width,
-                       shards=args.shards, flags=CREATE_FLAGS.get(variant_name, 0))
+                       shards=args.shards, flags=CREATE_FLAGS.get(variant_name, 0), rows=args.rows)
         shards = int(heap.info.n_shards)
 
         def one_size(s, rec):
@@ -528,7 +546,7 @@ def main():
                 launches.append({"n": n, "ok": int(ok.item()), "t": e[0].elapsed_time(e[1]) / 1e3,
                                  "atomics": counts[s]["first" if it == 0 else "subsequent"]["alloc"]})
             rl = alloc_roofline(launches, ceilings, chain_us, recorded_traffic())
-            rl["kernel"] = f"k_alloc_batch<false, {variant}u>"
+            rl["kernel"] = f"k_alloc_batch<false, {variant}u, {head_rows_of(args, variant, width)}u>"
             rl["event_overhead_us"] = ev_overhead
             state_atomics = sum(x["atomics"]["state_ops"] for x in launches)
             t_sum = sum(x["t"] for x in launches)
@@ -661,19 +679,24 @@ def main():
     # ---------------- plain baseline: runtime device malloc/free ----------------
     # the same driver loop as ours (alloc -> write -> check -> free, ten
     # iterations per size, 2^20 threads at every size); requests the runtime
-    # cannot serve come back NULL and are counted, never shrunk away
+    # cannot serve come back NULL and are counted, never shrunk away.  Sizes
+    # above 2 KiB are left out of the default run (its per-thread allocator
+    # needs 44 s per iteration at 4 KiB) and are named as not run.
     plain = None
     if not args.no_plain:
-        plain = {"sizes": {}, "threads": n, "iterations": args.plain_iters}
+        plain_sizes = [s for s in (int(x) for x in args.plain_sizes.split(",")) if s in sizes_list]
+        plain = {"sizes": {}, "threads": n, "iterations": args.plain_iters,
+                 "not_run": [s for s in sizes_list if s not in plain_sizes]}
         plain["heap_limit_rc"] = hb.hb_plain_set_heap(6 << 30)
         plain["heap_limit_bytes"] = 6 << 30
         p_ptrs = torch.zeros(n, dtype=torch.int64, device=dev)
         p_mism = torch.zeros(1, dtype=torch.int64, device=dev)
         tot_ops = tot_t = 0.0
         nulls = 0
-        for s in sizes_list:
+        for s in plain_sizes:
             sd = size_dev[s]
             ta, tf, oks = [], [], []
+            mism0 = int(p_mism.item())
             for it in range(args.plain_iters):
                 e = [ev() for _ in range(4)]
                 e[0].record()
@@ -695,7 +718,8 @@ def main():
             t_sub = sum(ta[sub]) + sum(tf[sub])
             ops_sub = 2 * sum(oks[sub])
             nulls += sum(n - x for x in oks)
-            plain["sizes"][str(s)] = {"ok_per_iteration": oks, "alloc_us": [round(x * 1e6, 1) for x in ta],
+            plain["sizes"][str(s)] = {"ok_per_iteration": oks, "mismatched_words": int(p_mism.item()) - mism0,
+                                      "alloc_us": [round(x * 1e6, 1) for x in ta],
                                       "free_us": [round(x * 1e6, 1) for x in tf],
                                       "ops_per_s_subsequent": ops_sub / t_sub if t_sub else None}
             tot_ops += ops_sub
@@ -705,7 +729,7 @@ def main():
         plain["value"] = tot_ops / tot_t if tot_t else None
         # ours over the same sizes and iterations (2..10 of each size)
         o_ops = o_t = 0.0
-        for s in sizes_list:
+        for s in plain_sizes:
             v = head["per_size"][str(s)]
             o_ops += 2 * v["ok"]
             o_t += (v["alloc_us"] + v["free_us"]) * 1e-6
@@ -760,6 +784,7 @@ def main():
             "aggregation_width": args.width,
             "shards": head["shards"],
             "iterations_per_size": args.iters,
+            "requests_per_lane": args.rows or 4,
             "sizes": sizes_list,
         },
         "headline": head,

@@ -35,8 +35,8 @@ typedef struct hbheap_heap* heap_t;
 
 /* Tunables of heap_create_ex.  Zero fields take the defaults. */
 typedef struct heap_config {
-    uint32_t variant;      /* HBHEAP_VARIANT_CHUNK (default), _PAGE, _VA_PAGE
-                              or _VA_CHUNK                                   */
+    uint32_t variant;      /* HBHEAP_VARIANT_CHUNK (default), _PAGE, _VA_PAGE,
+                              _VA_CHUNK, _VL_PAGE or _VL_CHUNK               */
     uint32_t width;        /* lanes aggregated per queue operation: power of
                               two in [1, 64], default 64                     */
     uint32_t spin_cap;     /* bounded-wait iterations, default 1 << 18        */
@@ -45,6 +45,12 @@ typedef struct heap_config {
                               only) is fixed for the heap's lifetime         */
     uint32_t shards;       /* queue shards: power of two <= 64; 0 = about one
                               per 256 chunks, at most 64                     */
+    uint32_t rows;         /* requests per lane of the batch kernels: 1 or 4,
+                              0 = 4.  With 4, a wave serves 256 requests
+                              and each of its queue operations covers all of
+                              them.  Applies to the page and virtualised-
+                              array page variants at widths of 16 or more;
+                              the others always use 1                        */
 } heap_config_t;
 
 /* Geometry and placement of a heap (heap_info). */
@@ -142,11 +148,12 @@ int heap_trim(heap_t h, hipStream_t stream);
 
 /*
  * Copy the state region into host memory `dst` of `cap` bytes.  Layout
- * version 3: a 256-byte header (magic 0x48424850, version, geometry, the
+ * version 4: a 256-byte header (magic 0x48424850, version, geometry, the
  * variant, and the byte offset of every section: pools, class blocks, class
  * bytes, free counts, bitmask words, pool ids, queue slots, and for the
  * segmented variants the directories or segment tags and links, consumed
- * counts and segment stores), then the sections.  Eager retirement: header
+ * counts and segment stores), then the sections.  Bitmask words are
+ * word-major: word w of chunk c at index w * n_chunks + c.  Eager retirement: header
  * u32 at 168 is 1 and u64 at 176 the offset of the per-chunk count/token
  * words (hbheap_types.h, chunk_ct); pools are rings (state, head, tail) over
  * pool ids padded to S << log2_span; queues have twice the slots (room for

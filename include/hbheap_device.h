@@ -50,11 +50,13 @@
  *     class.
  *   - Every wait is bounded: past spin_cap iterations the wait gives up,
  *     sets HBHEAP_ERR_TIMEOUT and the request returns NULL.
- *   - Metadata atomics are agent-scope and relaxed; ordering comes from
- *     issuing a dependent atomic only after the previous one returned, plus
- *     one release fence before a refill publishes freshly written bitmasks
- *     (with eager retirement those writes are returning atomics the wave
- *     waits for, and no fence is needed).
+ *   - Metadata atomics are agent-scope and relaxed.  Every metadata word
+ *     that other waves read while a kernel runs is written by an atomic
+ *     read-modify-write (performed where the device performs atomics, the
+ *     same place for every XCD) and read by one, or by an agent-scope load;
+ *     ordering comes from issuing a dependent access only after the value
+ *     it depends on has returned (a refill waits for the exchanges that set
+ *     its bits before it publishes pages), never from cache-wide fences.
  *
  * dev_free() starts with an agent-scope release fence so the caller's
  * writes to the block complete before the block can be handed out again.
@@ -183,6 +185,14 @@ __device__ __forceinline__ bool a_cas32(uint32_t* p, uint32_t expect, uint32_t v
 {
     return __hip_atomic_compare_exchange_strong(p, &expect, v, __ATOMIC_RELAXED, HBH_A(__ATOMIC_RELAXED));
 }
+/* Compare-and-swap giving the word's old value (the swap happened iff it
+ * equals expect); unlike a_cas32 nothing branches on the outcome where it is
+ * issued, so several of them can be in flight at once. */
+__device__ __forceinline__ uint32_t a_cas32_old(uint32_t* p, uint32_t expect, uint32_t v)
+{
+    __hip_atomic_compare_exchange_strong(p, &expect, v, __ATOMIC_RELAXED, HBH_A(__ATOMIC_RELAXED));
+    return expect;
+}
 __device__ __forceinline__ uint64_t a_load64(uint64_t* p) { return __hip_atomic_load(p, HBH_A(__ATOMIC_RELAXED)); }
 __device__ __forceinline__ uint32_t a_load32(uint32_t* p) { return __hip_atomic_load(p, HBH_A(__ATOMIC_RELAXED)); }
 __device__ __forceinline__ int32_t a_loadi(int32_t* p) { return __hip_atomic_load(p, HBH_A(__ATOMIC_RELAXED)); }
@@ -191,11 +201,13 @@ __device__ __forceinline__ int32_t a_loadi(int32_t* p) { return __hip_atomic_loa
 /* Zero, computed from v by an instruction the compiler cannot see through.
  * Added to the address of a later memory operation, it makes that operation
  * wait for v: it is issued only once the earlier load or atomic has returned
- * its value, i.e. has been performed.  With the device-coherent accesses
- * above (serviced where device atomics are performed, never from a stale
- * private cache) this orders the two as an acquire (after a load) or a
- * release (before a store) would, without the cache invalidation or
- * write-back those fences also issue. */
+ * its value, i.e. has been performed.  Between the accesses above -- atomic
+ * read-modify-writes, performed at the device's one point of coherence for
+ * the address, and agent-scope loads (global_load sc1), which the compiler
+ * maps with no cache invalidation and which must therefore be served
+ * coherently with those atomics -- this orders the two as an acquire (after
+ * a load) or a release (before a store) would, without the L2 invalidation
+ * or write-back those fences also issue. */
 __device__ __forceinline__ uint32_t zero_after(uint32_t v)
 {
     uint32_t z;
@@ -279,6 +291,16 @@ __device__ __forceinline__ int class_of(const hbheap_dev_t& h, uint64_t n)
     if (n == 0 || n > (1ull << h.log2_chunk)) return -1;
     if (n <= 16) return 0;
     return 64 - __builtin_clzll(n - 1) - 4; /* ceil(log2 n) - 4 */
+}
+
+/* Index of bitmask word w of chunk c.  Words are stored word-major: word 0
+ * of every chunk, then word 1 of every chunk, ...  A class with at most 64
+ * pages per chunk uses word 0 only, so the lanes of a wave that work on
+ * consecutive chunks of it hit neighbouring words -- a few cache lines per
+ * instruction instead of one line per chunk. */
+__host__ __device__ __forceinline__ uint64_t bit_index(const hbheap_dev_t& h, uint64_t c, uint32_t w)
+{
+    return (uint64_t)w * h.n_chunks + c;
 }
 
 /* Shard owning chunk c: shards own consecutive runs of 2^log2_span chunks. */
@@ -670,70 +692,82 @@ __device__ __forceinline__ uint32_t slot_take(const hbheap_dev_t& h, const Ring&
 /* Segmented rings, wave-wide: the lanes with `took` consumed ring position
  * pos of segment seg of ring r.  Runs of adjacent lanes on one segment
  * (their positions rise with the lane) add their number to its consumed
- * count with one atomic.  The run holding the segment's last position
- * closes it once the count shows every slot consumed (each slot was emptied
- * by its consumer before that consumer was counted): a virtualised array
- * ring empties the directory entry and returns the segment to the store; a
- * virtualised list ring unlinks fully consumed segments from its front.
- * The closer's wait is bounded by the other consumers of the segment, which
- * reserved their positions before it and wait on nothing it holds; so only
- * the closer needs the count back, and every other add returns nothing. */
-__device__ __forceinline__ void seg_count_taken(const hbheap_dev_t& h, const Ring& r, bool took, uint32_t pos,
-                                                uint32_t seg, Tally& t)
+ * count with one atomic.  The run holding the segment's last position is the
+ * segment's closer: its last lane gets the count after its add back (every
+ * other lane kEmpty, and every other add returns nothing) and closes the
+ * segment with seg_close. */
+__device__ __forceinline__ uint32_t seg_count_add(const hbheap_dev_t& h, const Ring& r, bool took, uint32_t pos,
+                                                  uint32_t seg, Tally& t)
 {
     const uint32_t me = lane();
     const Run run = run_combine(took, (uint64_t)r.j * h.vsegs + seg, 1ull << me, 64u);
-    if (took && me == run.tail) {
-        const uint32_t n = (uint32_t)__popcll(run.incl);
-        const uint32_t G = 1u << r.log2g;
-        uint32_t* tk = h.vtaken + (uint64_t)r.j * h.vsegs + seg;
-        t.spread += 1;
-        if ((pos & (G - 1u)) != G - 1u) {
-            __hip_atomic_fetch_add(tk, n, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            return;
-        }
-        uint32_t c = a_add32(tk, n) + n;
-        Backoff b;
-        while (c != G) {
-            if (!b.wait(h)) {
-                raise_err(h, HBHEAP_ERR_TIMEOUT, HBHEAP_STAT_TIMEOUTS);
-                return;
-            }
-            c = a_load32(tk);
-            if (HBHEAP_VARIANT_IS_VL(h.variant) && c != G) {
-                /* a list segment may already be retired by someone else's
-                 * loop once its count was full: the retirer moved the front
-                 * past it before resetting the count this load saw */
-                const uint64_t f = a_load64(r.front + zero_after(c));
-                if ((int32_t)((uint32_t)(f >> 32) - (pos >> r.log2g)) > 0) return;
-            }
-        }
-        if (HBHEAP_VARIANT_IS_VL(h.variant)) {
-            vl_retire(h, r, c, t);
-            return;
-        }
-        /* reset the count and empty the directory entry, both performed
-         * before the segment can be taken again: exchanges whose returned
-         * values the store's first atomic depends on (no cache-wide
-         * release fence) */
-        const uint32_t was = a_xchg32(tk, 0u);
-        const uint64_t ent = __hip_atomic_exchange(r.dir + ((pos >> r.log2g) & r.dmask), kDirEmpty,
-                                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        store_put(h, r.j + zero_after(was ^ (uint32_t)ent), seg, t);
+    if (!(took && me == run.tail)) return kEmpty;
+    const uint32_t n = (uint32_t)__popcll(run.incl);
+    const uint32_t G = 1u << r.log2g;
+    uint32_t* tk = h.vtaken + (uint64_t)r.j * h.vsegs + seg;
+    t.spread += 1;
+    if ((pos & (G - 1u)) != G - 1u) {
+        __hip_atomic_fetch_add(tk, n, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        return kEmpty;
     }
+    return a_add32(tk, n) + n;
 }
 
-/* Per lane: exchange the entry out of slot s (wait while it is empty).  The
- * first attempt exchanges at once (the slot of a published position is
- * normally full; exchanging an empty slot with the empty mark changes
- * nothing); only a late producer makes it poll with loads. */
-__device__ __forceinline__ uint32_t plain_take(const hbheap_dev_t& h, uint32_t* s, Tally& t)
+/* Per closer lane (seg_count_add returned c): once the count shows every
+ * slot of the segment consumed (each slot was emptied by its consumer before
+ * that consumer was counted), close it: a virtualised array ring empties the
+ * directory entry and returns the segment to the store; a virtualised list
+ * ring unlinks fully consumed segments from its front.  The wait is bounded
+ * by the segment's other consumers, which reserved their positions before
+ * the closer and count them without waiting on any closer (a wave with
+ * several rows counts all of them before it closes any segment). */
+__device__ __forceinline__ void seg_close(const hbheap_dev_t& h, const Ring& r, uint32_t pos, uint32_t seg, uint32_t c,
+                                          Tally& t)
 {
-    {
-        const uint32_t v = a_xchg32(s, kEmpty);
-        t.slot += 1;
-        if (v != kEmpty) return v;
+    const uint32_t G = 1u << r.log2g;
+    uint32_t* tk = h.vtaken + (uint64_t)r.j * h.vsegs + seg;
+    Backoff b;
+    while (c != G) {
+        if (!b.wait(h)) {
+            raise_err(h, HBHEAP_ERR_TIMEOUT, HBHEAP_STAT_TIMEOUTS);
+            return;
+        }
+        c = a_load32(tk);
+        if (HBHEAP_VARIANT_IS_VL(h.variant) && c != G) {
+            /* a list segment may already be retired by someone else's
+             * loop once its count was full: the retirer moved the front
+             * past it before resetting the count this load saw */
+            const uint64_t f = a_load64(r.front + zero_after(c));
+            if ((int32_t)((uint32_t)(f >> 32) - (pos >> r.log2g)) > 0) return;
+        }
     }
+    if (HBHEAP_VARIANT_IS_VL(h.variant)) {
+        vl_retire(h, r, c, t);
+        return;
+    }
+    /* reset the count and empty the directory entry, both performed
+     * before the segment can be taken again: exchanges whose returned
+     * values the store's first atomic depends on (no cache-wide
+     * release fence) */
+    const uint32_t was = a_xchg32(tk, 0u);
+    const uint64_t ent = __hip_atomic_exchange(r.dir + ((pos >> r.log2g) & r.dmask), kDirEmpty,
+                                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    store_put(h, r.j + zero_after(was ^ (uint32_t)ent), seg, t);
+}
+
+/* Both steps for one row of consumers. */
+__device__ __forceinline__ void seg_count_taken(const hbheap_dev_t& h, const Ring& r, bool took, uint32_t pos,
+                                                uint32_t seg, Tally& t)
+{
+    const uint32_t c = seg_count_add(h, r, took, pos, seg, t);
+    if (c != kEmpty) seg_close(h, r, pos, seg, c, t);
+}
+
+/* Per lane: the waiting part of taking the entry of slot s, after a first
+ * exchange found it empty (its producer is late): poll with loads, exchange
+ * once it shows an entry; kEmpty on timeout. */
+__device__ __forceinline__ uint32_t plain_take_wait(const hbheap_dev_t& h, uint32_t* s, Tally& t)
+{
     Backoff b;
     for (;;) {
         if (!b.wait(h)) {
@@ -746,6 +780,18 @@ __device__ __forceinline__ uint32_t plain_take(const hbheap_dev_t& h, uint32_t* 
             if (v != kEmpty) return v;
         }
     }
+}
+
+/* Per lane: exchange the entry out of slot s (wait while it is empty).  The
+ * first attempt exchanges at once (the slot of a published position is
+ * normally full; exchanging an empty slot with the empty mark changes
+ * nothing); only a late producer makes it poll with loads. */
+__device__ __forceinline__ uint32_t plain_take(const hbheap_dev_t& h, uint32_t* s, Tally& t)
+{
+    const uint32_t v = a_xchg32(s, kEmpty);
+    t.slot += 1;
+    if (v != kEmpty) return v;
+    return plain_take_wait(h, s, t);
 }
 
 /* Per lane: fill ring position pos with v (wait while the slot still holds
@@ -761,14 +807,11 @@ __device__ __forceinline__ bool slot_put(const hbheap_dev_t& h, const Ring& r, u
     return plain_put(h, r.slots + (pos & r.mask), v, t);
 }
 
-/* Per lane: compare-and-swap v into slot s (wait while it is still full).
- * The first attempt swaps at once (the slot of a reserved position is
- * normally empty; a failed swap writes nothing); only a late consumer of
- * the previous lap makes it poll with loads. */
-__device__ __forceinline__ bool plain_put(const hbheap_dev_t& h, uint32_t* s, uint32_t v, Tally& t)
+/* Per lane: the waiting part of filling slot s with v, after a first
+ * compare-and-swap found it still full (its consumer of the previous lap is
+ * late): poll with loads, swap once it shows empty; false on timeout. */
+__device__ __forceinline__ bool plain_put_wait(const hbheap_dev_t& h, uint32_t* s, uint32_t v, Tally& t)
 {
-    t.slot += 1;
-    if (a_cas32(s, kEmpty, v)) return true;
     Backoff b;
     for (;;) {
         if (!b.wait(h)) {
@@ -780,6 +823,24 @@ __device__ __forceinline__ bool plain_put(const hbheap_dev_t& h, uint32_t* s, ui
             if (a_cas32(s, kEmpty, v)) return true;
         }
     }
+}
+
+/* Per lane: compare-and-swap v into slot s (wait while it is still full).
+ * The first attempt swaps at once (the slot of a reserved position is
+ * normally empty; a failed swap writes nothing); only a late consumer of
+ * the previous lap makes it poll with loads. */
+__device__ __forceinline__ bool plain_put(const hbheap_dev_t& h, uint32_t* s, uint32_t v, Tally& t)
+{
+    t.slot += 1;
+    if (a_cas32(s, kEmpty, v)) return true;
+    return plain_put_wait(h, s, v, t);
+}
+
+/* The slot of ring position pos of queue (shard j, class k) in the plain
+ * (unsegmented) ring storage. */
+__device__ __forceinline__ uint32_t* plain_slot(const hbheap_dev_t& h, uint32_t j, uint32_t k, uint32_t pos)
+{
+    return h.slots + (((uint64_t)j * h.n_classes + k) << h.log2q) + (pos & ((1u << h.log2q) - 1u));
 }
 
 /* ---------------- pool (per shard) ---------------- */
@@ -854,11 +915,14 @@ __device__ __forceinline__ Ring pool_ring(const hbheap_dev_t& h, uint32_t j)
     return r;
 }
 
-/* Read a word by an atomic that changes nothing: its value is the one at
- * the point where device atomics are performed, never an older copy a load
- * could still find in this XCD's cache.  Used where a decision rests on
- * seeing another wave's last atomic on the word.  The zero OR-ed in comes
- * from zero_after, so the compiler cannot turn the atomic back into a load. */
+/* Read a word by an atomic that changes nothing.  A read-modify-write reads
+ * the last value in the word's modification order; the memory model promises
+ * that for no load (a relaxed load may return an older value, and only the
+ * hardware's coherent service of agent-scope loads rules that out).  Used on
+ * rare paths where a decision -- dropping a queue entry as stale -- would
+ * lose a chunk if it rested on a value older than another wave's last
+ * atomic on the word.  The zero OR-ed in comes from zero_after, so the
+ * compiler cannot turn the atomic back into a load. */
 __device__ __forceinline__ uint64_t a_read64(uint64_t* p)
 {
     return __hip_atomic_fetch_or(p, (uint64_t)zero_after(lane()), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -899,9 +963,8 @@ __device__ __forceinline__ uint32_t retire_reset(const hbheap_dev_t& h, uint32_t
 {
     const uint32_t ppc = 1u << (h.log2_chunk - 4u - k);
     const uint32_t nw = ppc >= 64u ? ppc >> 6 : 1u;
-    uint64_t* words = h.bits + (uint64_t)c * h.words_per_chunk;
     uint64_t acc = 0;
-    for (uint32_t w = 0; w < nw; ++w) acc ^= a_xchg64(words + w, 0ull);
+    for (uint32_t w = 0; w < nw; ++w) acc ^= a_xchg64(h.bits + bit_index(h, c, w), 0ull);
     const uint32_t sh = (c & 3u) * 8u;
     t.spread += nw + 1u;
     return (uint32_t)acc ^ (uint32_t)(acc >> 32) ^ a_or32((uint32_t*)(h.chunk_class + (c & ~3u)), 0xFFu << sh);
@@ -1059,16 +1122,16 @@ __device__ __forceinline__ uint32_t claim_pages(const hbheap_dev_t& h, uint32_t 
     const uint32_t shift = 4u + k;
     const uint32_t ppc = 1u << (h.log2_chunk - shift);
     const uint32_t nw = ppc >= 64u ? ppc >> 6 : 1u;
-    uint64_t* words = h.bits + (uint64_t)c * h.words_per_chunk;
     const uint64_t base = (uint64_t)c << h.log2_chunk;
     uint32_t got = 0;
     Backoff b;
     while (got < t) {
         for (uint32_t w = 0; w < nw && got < t; ++w) {
-            uint64_t x = a_load64(&words[w]);
+            uint64_t* word = h.bits + bit_index(h, c, w);
+            uint64_t x = a_load64(word);
             while (x && got < t) {
                 const uint64_t pick = lowest_bits(x, t - got);
-                const uint64_t old = a_and64(&words[w], ~pick);
+                const uint64_t old = a_and64(word, ~pick);
                 tl.spread += 1;
                 uint64_t won = old & pick;
                 while (won) {
@@ -1102,16 +1165,37 @@ __device__ __forceinline__ uint64_t* stage_for_wave()
 
 /* ---------------- one class group of one wave ---------------- */
 
-/* Wave-uniform facts about the lanes requesting one class.  The leader is
- * the lowest active lane; helpers are the active lanes by rank. */
+/* The requests one call serves: R per lane ("rows"; request (lane l, row
+ * r)).  Requests of one class (inside aligned segments of `width` lanes)
+ * form a group; gid is a request's group and rank its place in the group,
+ * rows first (row 0's requests in lane order, then row 1's, ...), so that
+ * consecutive ranks sit on consecutive lanes of a row.  k < 0: no request
+ * there (an invalid size, or a row past the end of the batch).  off
+ * receives the page offsets (kNoPage: none). */
+template <uint32_t R>
+struct Rows {
+    int32_t k[R];
+    uint32_t gid[R];
+    uint32_t rank[R];
+    uint64_t off[R];
+};
+
+template <uint32_t R>
+__device__ __forceinline__ bool in_group(const Rows<R>& q, uint32_t id, uint32_t r)
+{
+    return q.k[r] >= 0 && q.gid[r] == id;
+}
+
+/* Wave-uniform facts about one group of requests.  The leader is the lowest
+ * active lane; helpers are the active lanes by rank. */
 struct Group {
     uint64_t act;
-    uint32_t me, leader, nact, arank, qrank;
-    bool req;
+    uint32_t me, leader, nact, arank;
+    uint32_t id;
     uint32_t k, shift, lppc, ppc;
 };
 
-__device__ __forceinline__ Group make_group(const hbheap_dev_t& h, uint32_t k, uint64_t grp)
+__device__ __forceinline__ Group make_group(const hbheap_dev_t& h, uint32_t k, uint32_t id)
 {
     Group g;
     g.act = exec_mask();
@@ -1119,13 +1203,99 @@ __device__ __forceinline__ Group make_group(const hbheap_dev_t& h, uint32_t k, u
     g.leader = ctz64(g.act);
     g.nact = (uint32_t)__popcll(g.act);
     g.arank = rank_in(g.act);
-    g.req = (grp >> g.me) & 1ull;
-    g.qrank = rank_in(grp);
+    g.id = id;
     g.k = k;
     g.shift = 4u + k;
     g.lppc = h.log2_chunk - g.shift;
     g.ppc = 1u << g.lppc;
     return g;
+}
+
+/* The lane that acts for group g in a wave's first pass: the g-th active
+ * lane (there are never more groups than active lanes: with one row each
+ * lane asks once; with several rows all 64 lanes are active and the width
+ * is at least 16, so at most 4 segments x 13 classes). */
+__device__ __forceinline__ uint32_t agent_lane(uint64_t act, uint32_t g)
+{
+    return act == ~0ull ? g : lane_of_rank(act, g);
+}
+
+/* Per lane: give unowned chunk c to class k, by an atomic AND on the word
+ * holding its class byte (0xFF while unowned); the returned value is not
+ * needed, only that the atomic is performed before the chunk's pages are
+ * published (write_free_bits waits for it). */
+__device__ __forceinline__ void set_class(const hbheap_dev_t& h, uint32_t c, uint32_t k, Tally& tl)
+{
+    const uint32_t sh = (c & 3u) * 8u;
+    (void)a_and32((uint32_t*)(h.chunk_class + (c & ~3u)), ~(0xFFu << sh) | (k << sh));
+    tl.spread += 1;
+}
+
+/* Wave-wide (the group's lanes): a refill keeps pages [u, ppc) of chunk cl
+ * for its queue; set their bits by returning exchanges spread over the
+ * lanes, then wait for every access the wave has in flight -- these and the
+ * class words -- so that they are performed before the pages are published.
+ * (Plain stores would need an agent-scope release fence, which writes back
+ * the whole L2 of the XCD.) */
+__device__ __forceinline__ void write_free_bits(const hbheap_dev_t& h, uint32_t cl, uint32_t u, const Group& g, Tally& tl)
+{
+    const uint32_t nw = g.ppc >= 64u ? g.ppc >> 6 : 1u;
+    uint64_t acc = 0;
+    for (uint32_t w = g.arank; w < nw; w += g.nact) {
+        acc ^= a_xchg64(h.bits + bit_index(h, cl, w), free_mask_word(w, u, g.ppc));
+        tl.spread += 1;
+    }
+    __asm__ volatile("" ::"v"((uint32_t)acc), "v"((uint32_t)(acc >> 32)) : "memory");
+    wait_own_accesses();
+}
+
+/* Rows, per lane: the requests with tk[r] take ring position pos[r] of
+ * queue (shard j, class kr[r]); v[r] receives the entry (kEmpty: none, or a
+ * wait that timed out).  Plain rings: every row's exchange is issued before
+ * any is waited for, so a lane's rows cost one round trip.  Segmented
+ * rings: row by row, each row's consumed slots counted once its lanes have
+ * taken theirs, and segments closed only after every row is counted
+ * (wave-wide: every active lane calls this). */
+template <uint32_t R>
+__device__ __forceinline__ void take_rows(const hbheap_dev_t& h, uint32_t j, const uint32_t (&kr)[R],
+                                          const bool (&tk)[R], const uint32_t (&pos)[R], uint32_t (&v)[R],
+                                          Tally& tl)
+{
+    if (!HBHEAP_VARIANT_SEGMENTED(h.variant)) {
+        /* v[r] is left unset where no row takes (and set to kEmpty only after
+         * every exchange is issued), so that no copy of a returned value
+         * stands between two exchanges and makes the wave wait for the
+         * first */
+        uint32_t x[R];
+#pragma unroll
+        for (uint32_t r = 0; r < R; ++r) {
+            if (tk[r]) {
+                x[r] = a_xchg32(plain_slot(h, j, kr[r], pos[r]), kEmpty);
+                tl.slot += 1;
+            }
+        }
+#pragma unroll
+        for (uint32_t r = 0; r < R; ++r) {
+            v[r] = tk[r] ? x[r] : kEmpty;
+            if (tk[r] && v[r] == kEmpty) v[r] = plain_take_wait(h, plain_slot(h, j, kr[r], pos[r]), tl);
+        }
+        return;
+    }
+    /* every row's slots taken and counted before any segment is closed: a
+     * closer waits for the segment's other consumers to count, and those may
+     * be this wave's later rows or another wave that is itself closing a
+     * segment of another queue */
+    uint32_t seg[R], cl[R];
+#pragma unroll
+    for (uint32_t r = 0; r < R; ++r) {
+        const Ring Q = ring_of(h, j, kr[r]);
+        seg[r] = 0;
+        v[r] = tk[r] ? slot_take(h, Q, pos[r], &seg[r], tl) : kEmpty;
+        cl[r] = seg_count_add(h, Q, tk[r] && v[r] != kEmpty, pos[r], seg[r], tl);
+    }
+#pragma unroll
+    for (uint32_t r = 0; r < R; ++r)
+        if (cl[r] != kEmpty) seg_close(h, ring_of(h, j, kr[r]), pos[r], seg[r], cl[r], tl);
 }
 
 /* Page variant: reserve room for up to m more chunks of class k in shard j
@@ -1421,14 +1591,10 @@ __device__ __forceinline__ void chunk_serve_shard(const hbheap_dev_t& h, const G
                     gm = 0;
                     exhausted = true;
                 }
-                if (g.arank < gm) {
-                    const uint32_t sh = (mine & 3u) * 8u;
-                    a_and32((uint32_t*)(h.chunk_class + (mine & ~3u)), ~(0xFFu << sh) | (g.k << sh));
-                    tl.spread += 1;
-                }
+                if (g.arank < gm) set_class(h, mine, g.k, tl);
                 wait_own_accesses();
             } else if (g.arank < gm) {
-                h.chunk_class[h.pool_ids[first + g.arank]] = (uint8_t)g.k;
+                set_class(h, h.pool_ids[first + g.arank], g.k, tl);
             }
             const uint32_t cap = gm << g.lppc;
             const uint32_t r = cap < need ? cap : need;
@@ -1447,24 +1613,15 @@ __device__ __forceinline__ void chunk_serve_shard(const hbheap_dev_t& h, const G
                 const uint32_t last = gm - 1u;
                 const uint32_t u = need - (last << g.lppc);
                 const uint32_t cl = ev ? perm32(mine, lane_of_rank(g.act, last)) : h.pool_ids[first + last];
-                const uint32_t nw = g.ppc >= 64u ? g.ppc >> 6 : 1u;
-                if (ev) {
-                    /* eager retirement: every other write of the refill is an
-                     * atomic; the bit words are exchanged too, and the wave
-                     * waits for them instead of writing back the L2 */
-                    uint64_t acc = 0;
-                    for (uint32_t w = g.arank; w < nw; w += g.nact)
-                        acc ^= a_xchg64(h.bits + (uint64_t)cl * h.words_per_chunk + w, free_mask_word(w, u, g.ppc));
-                    /* returning exchanges, waited for: performed before the
-                     * chunk is listed */
-                    __asm__ volatile("" ::"v"((uint32_t)acc), "v"((uint32_t)(acc >> 32)) : "memory");
-                    wait_own_accesses();
-                } else {
-                    for (uint32_t w = g.arank; w < nw; w += g.nact)
-                        h.bits[(uint64_t)cl * h.words_per_chunk + w] = free_mask_word(w, u, g.ppc);
-                    if (g.me == g.leader) h.chunk_cnt[cl] = (int32_t)(g.ppc - u);
-                    fence_release();
+                /* the free count (lazy retirement; with eager retirement it
+                 * is set with the listing below) and the bit words by
+                 * returning exchanges, waited for: performed before the chunk
+                 * is listed, with no write-back of the L2 */
+                if (!ev && g.me == g.leader) {
+                    (void)a_xchg32((uint32_t*)(h.chunk_cnt + cl), g.ppc - u);
+                    tl.spread += 1;
                 }
+                write_free_bits(h, cl, u, g, tl);
                 if (g.me == g.leader) {
                     uint32_t pos = a_add32(R.tail, 1u);
                     tl.headtail += 1;
@@ -1523,13 +1680,37 @@ __device__ __forceinline__ void clear_bits_grouped(const hbheap_dev_t& h, bool h
     }
 }
 
-/* Page variant, shard j: requesting lanes of ranks [served, served+need)
- * receive pages; *off is this lane's page. */
-__device__ __forceinline__ void page_serve_shard(const hbheap_dev_t& h, const Group& g, uint32_t j, uint32_t& need,
-                                                 uint32_t& served, uint64_t& off, bool dry, bool check_first,
+/* Page variants, wave-wide: a lane that took entry v (kEmpty: none) from a
+ * queue of shard j gets that page (off) and its bit is cleared, one
+ * atomicAnd per run of lanes on one bitmask word. */
+__device__ __forceinline__ void page_took(const hbheap_dev_t& h, uint32_t j, uint32_t shift, uint32_t v, uint64_t& off,
+                                          Tally& tl)
+{
+    bool took = false;
+    uint64_t widx = 0, bit = 0, o = 0;
+    if (v != kEmpty) {
+        o = (uint64_t)v << 4;
+        if (o >= h.data_bytes || shard_of_chunk(h, o >> h.log2_chunk) != j) {
+            raise_err(h, HBHEAP_ERR_CORRUPT, HBHEAP_STAT_TIMEOUTS);
+        } else {
+            const uint64_t c = o >> h.log2_chunk;
+            const uint32_t p = (uint32_t)((o & ((1ull << h.log2_chunk) - 1ull)) >> shift);
+            widx = bit_index(h, c, p >> 6);
+            bit = 1ull << (p & 63u);
+            took = true;
+        }
+    }
+    clear_bits_grouped(h, took, widx, bit, o, off, tl);
+}
+
+/* Page variant, shard j: the group's requests of ranks [served,
+ * served+need) receive pages (q.off). */
+template <uint32_t R>
+__device__ __forceinline__ void page_serve_shard(const hbheap_dev_t& h, const Group& g, Rows<R>& q, uint32_t j,
+                                                 uint32_t& need, uint32_t& served, bool dry, bool check_first,
                                                  Tally& tl)
 {
-    const Ring R = ring_of(h, j, g.k);
+    const Ring Q = ring_of(h, j, g.k);
     /* The first pass (which looks first only if check_first) takes published
      * entries without a hold: it never refills, so it has nothing to publish
      * and a scanning wave need not wait on it (an over-ask it gives back is
@@ -1547,37 +1728,27 @@ __device__ __forceinline__ void page_serve_shard(const hbheap_dev_t& h, const Gr
         look = true;
         uint32_t got = 0, h0 = 0;
         if (g.me == g.leader) {
-            got = held ? ring_reserve(R, need, tl) : ring_take_published(R, need, tl);
+            got = held ? ring_reserve(Q, need, tl) : ring_take_published(Q, need, tl);
             if (got) {
-                h0 = a_add32(R.head, got);
+                h0 = a_add32(Q.head, got);
                 tl.headtail += 1;
             }
         }
         got = bcast(got, g.leader);
         h0 = bcast(h0, g.leader);
-        /* takers read their slots; then the bits of taken pages are cleared,
-         * one atomicAnd per bitmask word shared by the takers */
-        bool took_page = false;
-        uint64_t widx = 0, bit = 0, o = 0;
-        uint32_t vseg = 0;
-        bool took_slot = false;
-        const uint32_t mypos = h0 + (g.qrank - served);
-        if (g.req && g.qrank >= served && g.qrank < served + got) {
-            const uint32_t v = slot_take(h, R, mypos, &vseg, tl);
-            took_slot = v != kEmpty;
-            o = (uint64_t)v << 4;
-            if (v != kEmpty && (o >= h.data_bytes || shard_of_chunk(h, o >> h.log2_chunk) != j)) {
-                raise_err(h, HBHEAP_ERR_CORRUPT, HBHEAP_STAT_TIMEOUTS);
-            } else if (v != kEmpty) {
-                const uint64_t c = o >> h.log2_chunk;
-                const uint32_t p = (uint32_t)((o & ((1ull << h.log2_chunk) - 1ull)) >> g.shift);
-                widx = c * h.words_per_chunk + (p >> 6);
-                bit = 1ull << (p & 63u);
-                took_page = true;
-            }
+        /* takers read their slots (all rows at once); then the bits of taken
+         * pages are cleared, one atomicAnd per run of lanes on one word */
+        bool tk[R];
+        uint32_t pos[R], kr[R], v[R];
+#pragma unroll
+        for (uint32_t r = 0; r < R; ++r) {
+            tk[r] = in_group(q, g.id, r) && q.rank[r] >= served && q.rank[r] < served + got;
+            pos[r] = h0 + (q.rank[r] - served);
+            kr[r] = g.k;
         }
-        if (R.segs) seg_count_taken(h, R, took_slot, mypos, vseg, tl);
-        clear_bits_grouped(h, took_page, widx, bit, o, off, tl);
+        take_rows<R>(h, j, kr, tk, pos, v, tl);
+#pragma unroll
+        for (uint32_t r = 0; r < R; ++r) page_took(h, j, g.shift, v[r], q.off[r], tl);
         need -= got;
         served += got;
 
@@ -1604,66 +1775,99 @@ __device__ __forceinline__ void page_serve_shard(const hbheap_dev_t& h, const Gr
             gm = bcast(gm, g.leader);
             first = bcast64(first, g.leader);
             exhausted = gm < m;
-            if (g.arank < gm) h.chunk_class[h.pool_ids[first + g.arank]] = (uint8_t)g.k;
+            /* the chunks' class bytes, by atomics on their words (an unowned
+             * chunk's byte is 0xFF, so an AND sets it): like every word other
+             * waves read during a kernel, written where device atomics are
+             * performed */
+            for (uint32_t i = g.arank; i < gm; i += g.nact) set_class(h, h.pool_ids[first + i], g.k, tl);
             const uint32_t cap = gm << g.lppc;
-            const uint32_t r = cap < need ? cap : need;
-            if (g.req && g.qrank >= served && g.qrank < served + r) {
-                const uint32_t q = g.qrank - served;
-                const uint32_t ci = h.pool_ids[first + (q >> g.lppc)];
-                off = ((uint64_t)ci << h.log2_chunk) + ((uint64_t)(q & (g.ppc - 1u)) << g.shift);
+            const uint32_t rr = cap < need ? cap : need;
+#pragma unroll
+            for (uint32_t r = 0; r < R; ++r) {
+                if (in_group(q, g.id, r) && q.rank[r] >= served && q.rank[r] < served + rr) {
+                    const uint32_t qq = q.rank[r] - served;
+                    const uint32_t ci = h.pool_ids[first + (qq >> g.lppc)];
+                    q.off[r] = ((uint64_t)ci << h.log2_chunk) + ((uint64_t)(qq & (g.ppc - 1u)) << g.shift);
+                }
             }
             if (cap > need) {
                 const uint32_t last = gm - 1u;
                 const uint32_t u = need - (last << g.lppc);
                 const uint32_t cl = h.pool_ids[first + last];
-                const uint32_t nw = g.ppc >= 64u ? g.ppc >> 6 : 1u;
-                for (uint32_t w = g.arank; w < nw; w += g.nact)
-                    h.bits[(uint64_t)cl * h.words_per_chunk + w] = free_mask_word(w, u, g.ppc);
-                fence_release();
+                /* its free bits by returning exchanges, and the wave waits for
+                 * them (and the class words): performed before any of its pages
+                 * is published, with no write-back of the L2 */
+                write_free_bits(h, cl, u, g, tl);
                 const uint32_t L = g.ppc - u;
                 uint32_t t0 = 0;
                 if (g.me == g.leader) {
-                    t0 = a_add32(R.tail, L);
+                    t0 = a_add32(Q.tail, L);
                     tl.headtail += 1;
                 }
                 t0 = bcast(t0, g.leader);
-                const uint64_t cbase = (uint64_t)cl << h.log2_chunk;
-                for (uint32_t i = g.arank; i < L; i += g.nact)
-                    slot_put(h, R, t0 + i, (uint32_t)((cbase + ((uint64_t)(u + i) << g.shift)) >> 4), tl);
+                const uint64_t cbase = ((uint64_t)cl << h.log2_chunk) >> 4;
+                const uint32_t step = 1u << (g.shift - 4u);
+                if (!Q.segs) {
+                    /* eight compare-and-swaps per lane in flight at a time */
+                    for (uint32_t i0 = g.arank; i0 < L; i0 += 8u * g.nact) {
+                        uint32_t was[8];
+#pragma unroll
+                        for (uint32_t b = 0; b < 8u; ++b) {
+                            const uint32_t i = i0 + b * g.nact;
+                            was[b] = kEmpty;
+                            if (i < L) {
+                                was[b] = a_cas32_old(Q.slots + ((t0 + i) & Q.mask), kEmpty,
+                                                     (uint32_t)cbase + (u + i) * step);
+                                tl.slot += 1;
+                            }
+                        }
+#pragma unroll
+                        for (uint32_t b = 0; b < 8u; ++b) {
+                            const uint32_t i = i0 + b * g.nact;
+                            if (i < L && was[b] != kEmpty)
+                                plain_put_wait(h, Q.slots + ((t0 + i) & Q.mask), (uint32_t)cbase + (u + i) * step, tl);
+                        }
+                    }
+                } else {
+                    for (uint32_t i = g.arank; i < L; i += g.nact)
+                        slot_put(h, Q, t0 + i, (uint32_t)cbase + (u + i) * step, tl);
+                }
                 publish = L;
             }
-            need -= r;
-            served += r;
+            need -= rr;
+            served += rr;
         }
-        if (held && g.me == g.leader) ring_release(R, publish, tl);
+        if (held && g.me == g.leader) ring_release(Q, publish, tl);
         if (need > 0 && exhausted) return;
         held = true;
     }
 }
 
-/* Serve one class group: the home shard first; then, while requests remain,
- * scan every shard at once and serve from the first one (after home) that
- * has entries or room to grow; give up only when a scan finds every shard
- * without entries, without room and without holds in flight.  Returns this
- * lane's page offset or kNoPage. */
-__device__ __forceinline__ uint64_t alloc_group(const hbheap_dev_t& h, uint32_t k, uint64_t grp, uint64_t* stage,
-                                                uint32_t home, bool home_dry, uint32_t served0, bool home_tried,
-                                                uint32_t* share, Tally& tl)
+/* Serve one class group (id, class k, tot requests): the home shard first;
+ * then, while requests remain, scan every shard at once and serve from the
+ * first one (after home) that has entries or room to grow; give up only when
+ * a scan finds every shard without entries, without room and without holds
+ * in flight.  The group's requests receive their page offsets in q.off
+ * (unchanged: kNoPage).  Chunk variants serve one row (R == 1). */
+template <uint32_t R>
+__device__ __forceinline__ void alloc_group(const hbheap_dev_t& h, Rows<R>& q, uint32_t id, uint32_t k, uint32_t tot,
+                                            uint64_t* stage, uint32_t home, bool home_dry, uint32_t served0,
+                                            bool home_tried, uint32_t* share, Tally& tl)
 {
-    const Group g = make_group(h, k, grp);
-    const bool chunk = HBHEAP_VARIANT_LISTS_CHUNKS(h.variant);
+    const Group g = make_group(h, k, id);
+    constexpr bool one_row = R == 1;
+    const bool chunk = one_row && HBHEAP_VARIANT_LISTS_CHUNKS(h.variant);
     if (chunk) {
         stage[g.arank] = kNoPage;
         wave_sync_lds();
     }
-    uint64_t off = kNoPage;
     /* ranks below served0 were served already (page variant: the wave's
      * first pass over all its groups at once, on the home shard; after it,
      * home_tried makes the home shard look before it reserves again) */
-    uint32_t need = (uint32_t)__popcll(grp) - served0, served = served0;
+    uint32_t need = tot - served0, served = served0;
     const uint32_t S = h.n_shards;
     if (chunk) chunk_serve_shard(h, g, home, need, served, stage, home_dry, tl);
-    else page_serve_shard(h, g, home, need, served, off, home_dry && !home_tried, home_tried, tl);
+    else page_serve_shard<R>(h, g, q, home, need, served, home_dry && !home_tried, home_tried, tl);
     Backoff wb;
     bool timed_out = false;
     /* share != nullptr (a batch launch, whose requests were all issued when
@@ -1718,7 +1922,7 @@ __device__ __forceinline__ uint64_t alloc_group(const hbheap_dev_t& h, uint32_t 
             const uint32_t j = home + r < S ? home + r : home + r - S;
             const uint32_t before = need;
             if (chunk) chunk_serve_shard(h, g, j, need, served, stage, false, tl);
-            else page_serve_shard(h, g, j, need, served, off, false, false, tl);
+            else page_serve_shard<R>(h, g, q, j, need, served, false, false, tl);
             if (need < before) continue;
         }
         /* holds in flight, or the shard was drained under us: wait, bounded */
@@ -1738,17 +1942,13 @@ __device__ __forceinline__ uint64_t alloc_group(const hbheap_dev_t& h, uint32_t 
     }
     if (chunk) {
         wave_sync_lds();
-        off = g.req ? stage[g.qrank] : kNoPage;
+        if (in_group(q, id, 0)) q.off[0] = stage[q.rank[0]];
         wave_sync_lds();
     }
-    return g.req ? off : kNoPage;
 }
 
 /* ---------------- wave entry points ---------------- */
 
-/* Every active lane calls this; lanes are grouped by class (restricted to
- * aligned segments of `width` lanes) and each group is served by one queue
- * operation of its leader. */
 /* Whether the home shard's pool has run dry.  A plain load: the bump only
  * grows until a (quiescent) trim, so a stale value can only make the pool
  * look less consumed, never dry when it is not.  With eager retirement the
@@ -1764,96 +1964,143 @@ __device__ __forceinline__ bool home_pool_dry(const hbheap_dev_t& h, uint32_t ho
     return hp[0] >= ((const uint32_t*)hp)[2];
 }
 
-__device__ __forceinline__ void* malloc_wave(const hbheap_dev_t& h, uint64_t n, uint32_t home_in, bool dry_in,
-                                             uint32_t* share = nullptr)
+/* Every active lane calls this with R requests (n[r] bytes where has[r]);
+ * requests are grouped by class (inside aligned segments of `width` lanes)
+ * and each group is served by queue operations of one lane for the whole
+ * group.  q.off receives the page offsets.  With R > 1 every lane of the
+ * wave must be active and the width at least 16 (the batch kernels see to
+ * it); chunk variants, which stage pages in LDS 64 at a time, then serve
+ * row after row. */
+template <uint32_t R>
+__device__ __forceinline__ void malloc_rows(const hbheap_dev_t& h, Rows<R>& q, const uint64_t (&n)[R],
+                                            const bool (&has)[R], uint32_t home_in, bool dry_in,
+                                            uint32_t* share = nullptr)
 {
+    if constexpr (R > 1) {
+        if (HBHEAP_VARIANT_LISTS_CHUNKS(h.variant) || h.width < 16u) {
+#pragma unroll
+            for (uint32_t r = 0; r < R; ++r) {
+                Rows<1> one;
+                const uint64_t n1[1] = {n[r]};
+                const bool h1[1] = {has[r]};
+                malloc_rows<1>(h, one, n1, h1, home_in, dry_in, share);
+                q.k[r] = one.k[0];
+                q.gid[r] = 0;
+                q.rank[r] = 0;
+                q.off[r] = one.off[0];
+            }
+            return;
+        }
+    }
     /* the home shard and its hint act for the whole wave: take the first
      * active lane's (a caller whose lanes disagree would otherwise make the
      * leader reserve on one queue and its lanes take from another) */
     const uint32_t home = (uint32_t)__builtin_amdgcn_readfirstlane((int)home_in);
     const bool home_dry = __builtin_amdgcn_readfirstlane((int)dry_in) != 0;
-    const int k = class_of(h, n);
     const uint32_t me = lane();
+    const uint64_t act = exec_mask();
+    const uint32_t arank = rank_in(act);
     uint64_t* stage = stage_for_wave();
-    uint64_t off = kNoPage;
     Tally tl;
-    /* groups: lanes of one class (inside aligned segments of `width`
-     * lanes); each lane learns its group's first lane, its rank, the size */
-    uint32_t gl = me, gr = 0, gn = 0, ngroups = 0;
-    uint64_t pend = __ballot(k >= 0);
-    while (pend) {
-        const uint32_t leader = ctz64(pend);
-        const uint32_t kk = bcast((uint32_t)k, leader);
-        uint64_t grp = __ballot(k == (int)kk) & pend;
-        if (h.width < 64u) {
-            const uint32_t seg = leader & ~(h.width - 1u);
-            grp &= ((1ull << h.width) - 1ull) << seg;
+    /* groups: requests of one class (inside aligned segments of `width`
+     * lanes), ranked rows first; the g-th active lane keeps group g's class
+     * and size */
+    bool pend[R];
+#pragma unroll
+    for (uint32_t r = 0; r < R; ++r) {
+        q.k[r] = has[r] ? class_of(h, n[r]) : -1;
+        q.gid[r] = 0;
+        q.rank[r] = 0;
+        q.off[r] = kNoPage;
+        pend[r] = q.k[r] >= 0;
+    }
+    uint32_t ngroups = 0, my_k = 0, my_tot = 0;
+    for (;;) {
+        /* the first pending request, rows first */
+        uint32_t kk = 0, first = 0;
+        bool found = false;
+#pragma unroll
+        for (uint32_t r = 0; r < R; ++r) {
+            const uint64_t m = __ballot(pend[r]);
+            if (!found && m) {
+                first = ctz64(m);
+                kk = bcast((uint32_t)q.k[r], first);
+                found = true;
+            }
         }
-        if ((grp >> me) & 1ull) {
-            gl = leader;
-            gr = rank_in(grp);
-            gn = (uint32_t)__popcll(grp);
+        if (!found) break;
+        const bool in_seg = h.width >= 64u || ((me ^ first) & ~(h.width - 1u)) == 0u;
+        uint32_t base = 0;
+#pragma unroll
+        for (uint32_t r = 0; r < R; ++r) {
+            const bool mine = pend[r] && q.k[r] == (int32_t)kk && in_seg;
+            const uint64_t m = __ballot(mine);
+            if (mine) {
+                q.gid[r] = ngroups;
+                q.rank[r] = base + rank_in(m);
+                pend[r] = false;
+            }
+            base += (uint32_t)__popcll(m);
         }
-        pend &= ~grp;
+        if (arank == ngroups) {
+            my_k = kk;
+            my_tot = base;
+        }
         ++ngroups;
     }
-    /* Page variant, several groups: one first pass for all of them at once
-     * on the home shard -- every group's first lane reserves on its own
-     * queue in the same instructions, the lanes take their slots together
-     * and the bits are cleared in one combined step -- instead of one group
-     * after another.  It publishes nothing (no refill); groups left short
-     * continue below, each on its own. */
-    uint32_t done = 0;
-    const bool fast = !HBHEAP_VARIANT_LISTS_CHUNKS(h.variant) && ngroups > 1;
+    /* Page variants, several groups or rows: one first pass for all of them
+     * at once on the home shard -- every group's agent lane reserves on its
+     * own queue in the same instructions, the requests take their slots
+     * together (every row's exchange in flight at once) and the bits are
+     * cleared in one combined step per row -- instead of one group after
+     * another.  It publishes nothing (no refill); groups left short continue
+     * below, each on its own. */
+    const bool fast = !HBHEAP_VARIANT_LISTS_CHUNKS(h.variant) && (ngroups > 1 || R > 1);
+    uint32_t got = 0;
     if (fast) {
-        const bool lead = k >= 0 && me == gl;
-        Ring R;
-        uint32_t got = 0, h0 = 0;
-        if (k >= 0) R = ring_of(h, home, (uint32_t)k);
-        if (lead) {
-            got = ring_take_published(R, gn, tl);
+        uint32_t h0 = 0;
+        if (arank < ngroups) {
+            const Ring Q = ring_of(h, home, my_k);
+            got = ring_take_published(Q, my_tot, tl);
             if (got) {
-                h0 = a_add32(R.head, got);
+                h0 = a_add32(Q.head, got);
                 tl.headtail += 1;
             }
         }
-        done = perm32(got, gl);
-        h0 = perm32(h0, gl);
-        bool took = false, took_slot = false;
-        uint64_t widx = 0, bit = 0, o = 0;
-        uint32_t vseg = 0;
-        if (k >= 0 && gr < done) {
-            const uint32_t shift = 4u + (uint32_t)k;
-            const uint32_t v = slot_take(h, R, h0 + gr, &vseg, tl);
-            took_slot = v != kEmpty;
-            o = (uint64_t)v << 4;
-            if (v != kEmpty && (o >= h.data_bytes || shard_of_chunk(h, o >> h.log2_chunk) != home)) {
-                raise_err(h, HBHEAP_ERR_CORRUPT, HBHEAP_STAT_TIMEOUTS);
-            } else if (v != kEmpty) {
-                const uint64_t c = o >> h.log2_chunk;
-                const uint32_t p = (uint32_t)((o & ((1ull << h.log2_chunk) - 1ull)) >> shift);
-                widx = c * h.words_per_chunk + (p >> 6);
-                bit = 1ull << (p & 63u);
-                took = true;
-            }
+        bool tk[R];
+        uint32_t pos[R], kr[R], v[R];
+#pragma unroll
+        for (uint32_t r = 0; r < R; ++r) {
+            const uint32_t al = agent_lane(act, q.k[r] >= 0 ? q.gid[r] : 0u);
+            const uint32_t gg = perm32(got, al), hh = perm32(h0, al);
+            tk[r] = q.k[r] >= 0 && q.rank[r] < gg;
+            pos[r] = hh + q.rank[r];
+            kr[r] = q.k[r] >= 0 ? (uint32_t)q.k[r] : 0u;
         }
-        if (HBHEAP_VARIANT_SEGMENTED(h.variant)) seg_count_taken(h, R, took_slot, h0 + gr, vseg, tl);
-        clear_bits_grouped(h, took, widx, bit, o, off, tl);
+        take_rows<R>(h, home, kr, tk, pos, v, tl);
+#pragma unroll
+        for (uint32_t r = 0; r < R; ++r) page_took(h, home, 4u + kr[r], v[r], q.off[r], tl);
     }
-    pend = __ballot(k >= 0 && gr >= done);
-    while (pend) {
-        const uint32_t leader = ctz64(pend);
-        const uint32_t kk = bcast((uint32_t)k, leader);
-        const uint32_t l0 = bcast(gl, leader);
-        /* the whole group (served lanes included: ranks stay those of the
-         * group) */
-        uint64_t grp = __ballot(k == (int)kk && gl == l0);
-        const uint64_t o = alloc_group(h, kk, grp, stage, home, home_dry, bcast(done, leader), fast, share, tl);
-        if (((grp >> me) & 1ull) && o != kNoPage) off = o;
-        pend &= ~grp;
+    /* groups left short, one after another */
+    for (uint32_t gi = 0; gi < ngroups; ++gi) {
+        const uint32_t al = agent_lane(act, gi);
+        const uint32_t kk = bcast(my_k, al), tot = bcast(my_tot, al);
+        const uint32_t done = fast ? bcast(got, al) : 0u;
+        if (done >= tot) continue;
+        alloc_group<R>(h, q, gi, kk, tot, stage, home, home_dry, done, fast, share, tl);
     }
     tally_flush(h, tl);
-    return off == kNoPage ? nullptr : (void*)(h.data + off);
+}
+
+/* One request per lane: every active lane calls this. */
+__device__ __forceinline__ void* malloc_wave(const hbheap_dev_t& h, uint64_t n, uint32_t home_in, bool dry_in,
+                                             uint32_t* share = nullptr)
+{
+    Rows<1> q;
+    const uint64_t n1[1] = {n};
+    const bool h1[1] = {true};
+    malloc_rows<1>(h, q, n1, h1, home_in, dry_in, share);
+    return q.off[0] == kNoPage ? nullptr : (void*)(h.data + q.off[0]);
 }
 
 /* Every active lane calls this with its pointer (NULL allowed).  size_hint:
@@ -1884,7 +2131,7 @@ __device__ __forceinline__ uint32_t free_wave(const hbheap_dev_t& h, void* p, ui
             if (ok && check_size) ok = class_of(h, size_hint) == (int)k;
             if (ok) {
                 const uint32_t pg = (uint32_t)((o & ((1ull << h.log2_chunk) - 1ull)) >> shift);
-                widx = c * h.words_per_chunk + (pg >> 6);
+                widx = bit_index(h, c, pg >> 6);
                 bit = 1ull << (pg & 63u);
                 key = shard_of_chunk(h, c) * h.n_classes + k;
                 cand = true;
@@ -2002,6 +2249,236 @@ __device__ __forceinline__ uint32_t free_wave(const hbheap_dev_t& h, void* p, ui
     }
     tally_flush(h, tl);
     return status;
+}
+
+/* Rows, per lane: the requests with pt[r] fill ring position pos[r] of
+ * queue (shard jr[r], class kr[r]) with val[r].  Plain rings: every row's
+ * compare-and-swap is issued before any is waited for; segmented rings: row
+ * by row. */
+template <uint32_t R>
+__device__ __forceinline__ void put_rows(const hbheap_dev_t& h, const uint32_t (&jr)[R], const uint32_t (&kr)[R],
+                                         const bool (&pt)[R], const uint32_t (&pos)[R], const uint32_t (&val)[R],
+                                         Tally& tl)
+{
+    if (!HBHEAP_VARIANT_SEGMENTED(h.variant)) {
+        /* was[r] is read only where the row swapped (see take_rows) */
+        uint32_t was[R];
+#pragma unroll
+        for (uint32_t r = 0; r < R; ++r) {
+            if (pt[r]) {
+                was[r] = a_cas32_old(plain_slot(h, jr[r], kr[r], pos[r]), kEmpty, val[r]);
+                tl.slot += 1;
+            }
+        }
+#pragma unroll
+        for (uint32_t r = 0; r < R; ++r)
+            if (pt[r] && was[r] != kEmpty) plain_put_wait(h, plain_slot(h, jr[r], kr[r], pos[r]), val[r], tl);
+        return;
+    }
+#pragma unroll
+    for (uint32_t r = 0; r < R; ++r)
+        if (pt[r]) slot_put(h, ring_of(h, jr[r], kr[r]), pos[r], val[r], tl);
+}
+
+/* R frees per lane (p[r], NULL allowed), for heaps without eager
+ * retirement and with aggregation width 64 (others go row by row through
+ * free_wave).  The same steps as free_wave, each taken for every row before
+ * the next: runs of lanes on one bitmask word set their bits with one
+ * atomicOr per row (all rows' in flight together), and the entries to
+ * enqueue are grouped by (shard, class) over all rows, one tail add and one
+ * state add per group.  status[r] receives kFree* status. */
+template <uint32_t R>
+__device__ __forceinline__ void free_rows(const hbheap_dev_t& h, void* const (&p)[R], const uint64_t (&size_hint)[R],
+                                          bool check_size, uint32_t (&status)[R])
+{
+    if (R == 1 || eager(h) || h.width < 64u) {
+#pragma unroll
+        for (uint32_t r = 0; r < R; ++r) status[r] = free_wave(h, p[r], size_hint[r], check_size);
+        return;
+    }
+    const uint32_t me = lane();
+    Tally tl;
+    bool cand[R], inr[R], enq[R];
+    uint32_t key[R], k[R], val[R];
+    uint64_t c[R], widx[R], bit[R], o[R];
+#pragma unroll
+    for (uint32_t r = 0; r < R; ++r) {
+        status[r] = kFreeNull;
+        cand[r] = inr[r] = enq[r] = false;
+        key[r] = k[r] = val[r] = 0;
+        c[r] = widx[r] = bit[r] = o[r] = 0;
+        if (p[r] != nullptr) {
+            status[r] = kFreeInvalid;
+            o[r] = (uint64_t)((const uint8_t*)p[r] - h.data);
+            inr[r] = (const uint8_t*)p[r] >= h.data && o[r] < h.data_bytes;
+            if (inr[r]) c[r] = o[r] >> h.log2_chunk;
+        }
+    }
+    uint32_t kc[R];
+#pragma unroll
+    for (uint32_t r = 0; r < R; ++r) kc[r] = inr[r] ? h.chunk_class[c[r]] : 0u;
+#pragma unroll
+    for (uint32_t r = 0; r < R; ++r) {
+        if (!inr[r]) continue;
+        k[r] = kc[r];
+        const uint32_t shift = 4u + k[r];
+        bool ok = k[r] < h.n_classes && (o[r] & ((1ull << shift) - 1ull)) == 0;
+        if (ok && check_size) ok = class_of(h, size_hint[r]) == (int)k[r];
+        if (ok) {
+            const uint32_t pg = (uint32_t)((o[r] & ((1ull << h.log2_chunk) - 1ull)) >> shift);
+            widx[r] = bit_index(h, c[r], pg >> 6);
+            bit[r] = 1ull << (pg & 63u);
+            key[r] = shard_of_chunk(h, c[r]) * h.n_classes + k[r];
+            cand[r] = true;
+        }
+    }
+    /* set the free bits: one atomicOr per run of lanes on one word, every
+     * row's in flight together; chunk variant: then one count add per run */
+    Run run[R];
+    uint64_t old[R];
+    uint32_t cold[R], nnew[R];
+#pragma unroll
+    for (uint32_t r = 0; r < R; ++r) run[r] = run_combine(cand[r], widx[r], bit[r], 64u);
+    /* (returned values are left unset on lanes that issue nothing, and
+     * masked only after every row's atomic is issued, so that the rows'
+     * atomics are in flight together) */
+    bool tail[R];
+#pragma unroll
+    for (uint32_t r = 0; r < R; ++r) {
+        tail[r] = cand[r] && me == run[r].tail;
+        if (tail[r]) {
+            old[r] = a_or64(h.bits + widx[r], run[r].incl);
+            tl.spread += 1;
+        }
+    }
+#pragma unroll
+    for (uint32_t r = 0; r < R; ++r) {
+        old[r] = tail[r] ? old[r] : 0ull;
+        nnew[r] = tail[r] ? (uint32_t)__popcll(run[r].incl & ~old[r]) : 0u;
+        if (HBHEAP_VARIANT_LISTS_CHUNKS(h.variant) && nnew[r]) {
+            cold[r] = (uint32_t)a_addi(h.chunk_cnt + c[r], (int32_t)nnew[r]);
+            tl.spread += 1;
+        }
+    }
+#pragma unroll
+    for (uint32_t r = 0; r < R; ++r) cold[r] = nnew[r] ? cold[r] : 1u;
+    uint32_t ndbl = 0, ninv = 0;
+#pragma unroll
+    for (uint32_t r = 0; r < R; ++r) {
+        old[r] = perm64(old[r], run[r].tail);
+        cold[r] = perm32(cold[r], run[r].tail);
+        nnew[r] = perm32(nnew[r], run[r].tail);
+        if (cand[r]) {
+            status[r] = ((run[r].prior & bit[r]) || (old[r] & bit[r])) ? kFreeDouble : kFreeOk;
+            if (HBHEAP_VARIANT_LISTS_CHUNKS(h.variant)) {
+                /* the chunk's count left zero: the run enqueues it once */
+                enq[r] = me == run[r].tail && nnew[r] > 0 && cold[r] == 0;
+                val[r] = (uint32_t)c[r];
+            } else {
+                enq[r] = status[r] == kFreeOk;
+                val[r] = (uint32_t)(o[r] >> 4);
+            }
+        }
+        ndbl += (uint32_t)__popcll(__ballot(status[r] == kFreeDouble));
+        ninv += (uint32_t)__popcll(__ballot(status[r] == kFreeInvalid));
+    }
+    /* rare paths: one report per wave */
+    if ((ndbl | ninv) && me == ctz64(exec_mask())) {
+        if (ndbl) { a_or32(h.err, HBHEAP_ERR_DOUBLE_FREE); a_add64(h.stats + HBHEAP_STAT_DOUBLE_FREE, ndbl); }
+        if (ninv) { a_or32(h.err, HBHEAP_ERR_INVALID_FREE); a_add64(h.stats + HBHEAP_STAT_INVALID_FREE, ninv); }
+    }
+    /* aggregated enqueue by (shard, class) over all rows: one tail and one
+     * state add per group, ranks rows first.  Once a group of fewer than 4
+     * entries shows up (frees scattered over many queues), the remaining
+     * entries are enqueued one by one, all in the same instructions. */
+    uint32_t jr[R], kr[R];
+#pragma unroll
+    for (uint32_t r = 0; r < R; ++r) {
+        jr[r] = key[r] / h.n_classes;
+        kr[r] = key[r] % h.n_classes;
+    }
+    bool first_group = true;
+    for (;;) {
+        uint32_t kk = 0, leader = 0;
+        bool found = false;
+#pragma unroll
+        for (uint32_t r = 0; r < R; ++r) {
+            const uint64_t m = __ballot(enq[r]);
+            if (!found && m) {
+                leader = ctz64(m);
+                kk = bcast(key[r], leader);
+                found = true;
+            }
+        }
+        if (!found) break;
+        bool mem[R];
+        uint32_t pos[R], nn = 0;
+#pragma unroll
+        for (uint32_t r = 0; r < R; ++r) {
+            mem[r] = enq[r] && key[r] == kk;
+            const uint64_t m = __ballot(mem[r]);
+            pos[r] = nn + rank_in(m);
+            nn += (uint32_t)__popcll(m);
+        }
+        if (!first_group && nn < 4u) break;
+        first_group = false;
+        const Ring Q = ring_of(h, kk / h.n_classes, kk % h.n_classes);
+        uint32_t t0 = 0;
+        if (me == leader) {
+            t0 = a_add32(Q.tail, nn);
+            tl.headtail += 1;
+        }
+        t0 = bcast(t0, leader);
+#pragma unroll
+        for (uint32_t r = 0; r < R; ++r) pos[r] += t0;
+        put_rows<R>(h, jr, kr, mem, pos, val, tl);
+        if (me == leader) {
+            a_add64(Q.state, (uint64_t)nn);
+            tl.state += 1;
+        }
+#pragma unroll
+        for (uint32_t r = 0; r < R; ++r) enq[r] = enq[r] && !mem[r];
+    }
+    /* the rest: one entry per request, each with its own tail and state add */
+    if (HBHEAP_VARIANT_SEGMENTED(h.variant)) {
+        /* row by row: a producer in a segmented ring may wait for whoever
+         * installs its segment, which holds a lower position of the ring.
+         * Positions taken and filled one row at a time keep every such wait
+         * on a position reserved earlier -- this row's or another wave's --
+         * never on a later row of this wave, which would not run before the
+         * wait ends. */
+#pragma unroll
+        for (uint32_t r = 0; r < R; ++r) {
+            if (enq[r]) {
+                const Ring Q = ring_of(h, jr[r], kr[r]);
+                const uint32_t t = a_add32(Q.tail, 1u);
+                tl.headtail += 1;
+                slot_put(h, Q, t, val[r], tl);
+                a_add64(Q.state, 1ull);
+                tl.state += 1;
+            }
+        }
+        tally_flush(h, tl);
+        return;
+    }
+    uint32_t pos[R];
+#pragma unroll
+    for (uint32_t r = 0; r < R; ++r) {
+        pos[r] = 0;
+        if (enq[r]) {
+            pos[r] = a_add32(ring_of(h, jr[r], kr[r]).tail, 1u);
+            tl.headtail += 1;
+        }
+    }
+    put_rows<R>(h, jr, kr, enq, pos, val, tl);
+#pragma unroll
+    for (uint32_t r = 0; r < R; ++r) {
+        if (enq[r]) {
+            a_add64(ring_of(h, jr[r], kr[r]).state, 1ull);
+            tl.state += 1;
+        }
+    }
+    tally_flush(h, tl);
 }
 
 }  // namespace detail

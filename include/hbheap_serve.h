@@ -30,9 +30,10 @@
  * The worst case of a batch is the sum, over every (wave of 64 requests,
  * width segment, class) group of its allocations, of ceil(g / pages per
  * chunk): a group never takes more fresh chunks than that.  Chunks in use
- * are read from the pool counters on a monitor stream while batches run
- * (exact for every batch seen complete before the read was issued; the
- * worst cases of the others are added).  Page variant: the same bound is
+ * are read from the pool counters by the last workgroup of each batch's
+ * kernel and come back with its results (exact for that batch; the worst
+ * cases of the batches in flight at its launch, and of those launched
+ * since, are added).  Page variant: the same bound is
  * kept per class against the class's capacity (per shard, the chunks its
  * queue can hold the pages of), so an admitted allocation never fails.
  * When the bound does not admit the next batch and nothing is in flight,
@@ -74,17 +75,21 @@ typedef struct serve_stats {
     uint64_t batches, requests, allocs, frees;
     uint64_t trims;              /* quiescent trims the admission needed      */
     uint64_t admission_stalls;   /* batches that waited for admission         */
-    uint64_t monitor_reads;      /* chunk-usage reads while batches ran       */
+    uint64_t monitor_reads;      /* chunk-usage reads taken with batch results */
     uint64_t peak_bound;         /* largest chunks-in-use bound admitted      */
     uint64_t final_chunks;       /* chunks in use at the end (exact)          */
     double   wall_s;             /* first arrival .. last completion          */
 } serve_stats_t;
 
-/* Create a server over heap h (chunk or page variant: the admission keeps
- * per-class page budgets only for those), with K streams, pinned staging of
- * 16 B per request per slot, and the device table of max_requests
- * addresses.  Blocking.  Errors: HBHEAP_E_INVAL (also for either
- * virtualised array heap), HBHEAP_E_NOMEM, HBHEAP_E_HIP. */
+/* Create a server over heap h, with K streams, pinned staging of 16 B per
+ * request per slot, and the device table of max_requests addresses.  Chunk
+ * variants (plain, virtualised array, virtualised list) and the page
+ * variant are served; the page variant's admission also keeps per-class page
+ * budgets.  The virtualised page variants are refused: their classes share
+ * one page budget per shard, and a request can fail with chunks left in one
+ * shard and budget left in another, which no bound on chunks in use rules
+ * out.  Blocking.  Errors: HBHEAP_E_INVAL (also for a virtualised page
+ * variant heap), HBHEAP_E_NOMEM, HBHEAP_E_HIP. */
 int serve_create(heap_t h, const serve_config_t* cfg, server_t* out);
 
 /* Release the server's streams and buffers (not the heap).  NULL is a no-op. */

@@ -87,13 +87,15 @@ extern "C" {
  */
 typedef struct hbheap_dev {
     uint8_t*  data;            /* data region: n_chunks * 2^log2_chunk bytes  */
-    uint8_t*  state;           /* state region (snapshot layout, version 3)  */
+    uint8_t*  state;           /* state region (snapshot layout, version 4)  */
     uint64_t* pool;            /* n_shards pool blocks of 128 bytes: u64 bump,
                                   u32 size, u32 first index into pool_ids    */
     uint8_t*  classes;         /* n_shards * n_classes blocks of 512 bytes   */
     uint8_t*  chunk_class;     /* class of each chunk, 0xFF when unowned     */
     int32_t*  chunk_cnt;       /* free pages per chunk (chunk variant)       */
-    uint64_t* bits;            /* words_per_chunk words per chunk, 1 = free  */
+    uint64_t* bits;            /* words_per_chunk words per chunk, 1 = free;
+                                  word-major: word w of chunk c at
+                                  w * n_chunks + c                           */
     uint32_t* pool_ids;        /* ids of unowned chunks, consumed by bump    */
     uint32_t* slots;           /* n_shards * n_classes rings of 2^log2q u32  */
     uint32_t* err;             /* sticky error word                          */

@@ -717,10 +717,10 @@ int orc_check_blocks(uint64_t data_bytes, uint64_t chunk_bytes, const uint64_t* 
 }
 
 /* ------------------------------------------------------------------ */
-/* invariant checker: snapshot (layout version 3)                      */
+/* invariant checker: snapshot (layout version 4)                      */
 /*                                                                     */
 /* header (256 B, little-endian):                                      */
-/*   0 u32 magic 0x48424850   4 u32 version 3     8 u64 data_bytes     */
+/*   0 u32 magic 0x48424850   4 u32 version 4     8 u64 data_bytes     */
 /*  16 u32 n_chunks          20 u32 log2_chunk   24 u32 n_classes      */
 /*  28 u32 variant           32 u32 words/chunk  36 u32 log2 ring cap  */
 /*  40 u32 shards S          44 u32 log2 span    48 u64 off pools      */
@@ -732,7 +732,8 @@ int orc_check_blocks(uint64_t data_bytes, uint64_t chunk_bytes, const uint64_t* 
 /* class block (j, k) at index j*K + k (512 B): u64 state              */
 /*   (H<<32 | C+2^31), u32 head at +128, u32 tail at +256, u64 owned   */
 /*   at +384                                                           */
-/* chunk_class u8[N] (0xFF unowned), chunk_cnt u32[N], bits u64[N*W],  */
+/* chunk_class u8[N] (0xFF unowned), chunk_cnt u32[N], bits u64[W*N]   */
+/* (word-major: word w of chunk c at index w*N + c),                   */
 /* pool_ids u32[N], slots u32[S*K << log2 ring cap] (0xFFFFFFFF empty) */
 /* ring (j, k) at slot index (j*K + k) << log2 ring cap; page-variant  */
 /* slots hold the page's byte offset / 16; a page-variant class may    */
@@ -772,7 +773,7 @@ typedef struct {
 
 static int snap_open(const uint8_t* s, uint64_t len, snapview* v)
 {
-    if (len < 256 || rd32(s) != SNAP_MAGIC || rd32(s + 4) != 3) return 0;
+    if (len < 256 || rd32(s) != SNAP_MAGIC || rd32(s + 4) != 4) return 0;
     v->data_bytes = rd64(s + 8);
     v->N = rd32(s + 16); v->log2C = rd32(s + 20); v->K = rd32(s + 24);
     v->variant = rd32(s + 28); v->W = rd32(s + 32); v->log2q = rd32(s + 36);
@@ -879,7 +880,8 @@ static uint32_t sv_entry(const snapview* v, uint32_t j, uint32_t k, uint32_t pos
     return rd32(v->slots + ((((uint64_t)j * v->M + (uint32_t)e) << v->g) + (pos & ((1u << v->g) - 1u))) * 4);
 }
 
-static uint64_t sv_word(const snapview* v, uint64_t c, uint32_t w) { return rd64(v->bits + (c * v->W + w) * 8); }
+/* bitmask word w of chunk c (word-major) */
+static uint64_t sv_word(const snapview* v, uint64_t c, uint32_t w) { return rd64(v->bits + ((uint64_t)w * v->N + c) * 8); }
 
 static uint64_t popc_chunk(const snapview* v, uint64_t c)
 {

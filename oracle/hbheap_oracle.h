@@ -139,7 +139,7 @@ typedef struct {
                                      (kept while a stale entry of theirs blocked it) */
 } orc_snap_report;
 
-/* Quiescent-state consistency of a snapshot (documented layout, version 3). */
+/* Quiescent-state consistency of a snapshot (documented layout, version 4). */
 int orc_check_snapshot(const uint8_t* snap, uint64_t len, orc_snap_report* rep);
 
 /* Blocks against a snapshot: each live block must lie in a chunk of its

@@ -3,7 +3,7 @@
  * (C ABI in include/hbheap.h, device API in include/hbheap_device.h).
  *
  * Contents:
- *   - heap creation: state-region layout (snapshot version 3) and init;
+ *   - heap creation: state-region layout (snapshot version 4) and init;
  *   - batch alloc / free kernels (one lane per request, 256-lane blocks);
  *   - single-lane replay kernel;
  *   - quiescent trim: retire fully free chunks, rebuild pool and queues in
@@ -32,7 +32,7 @@ using namespace hbheap::detail;
 namespace {
 
 constexpr uint32_t kMagic = 0x48424850u;
-constexpr uint32_t kVersion = 3;
+constexpr uint32_t kVersion = 4;
 constexpr uint32_t kBatchBlock = 256;
 constexpr uint32_t kTrimBlock = 1024;
 constexpr uint32_t kMaxKeys = 1024; /* trim keys: 64 shards x (13 classes + pool) + none */
@@ -73,6 +73,7 @@ struct hbheap_heap {
     uint64_t aux_bytes = 0;
     uint64_t shard_stat_bytes = 0;
     uint64_t chunk_bytes = 0;
+    uint32_t rows = 1; /* requests per lane of the batch kernels (1 or 4) */
 };
 
 #define HB_TRY(expr)                                \
@@ -124,8 +125,11 @@ __global__ void k_iota_u32(uint32_t* p, uint64_t n)
 /* The batch kernels come in one instance per heap variant V (the host
  * launches the heap's own): with h.variant a constant, every variant test of
  * the inlined device code folds, and each instance carries only its
- * variant's code. */
-template <bool Counted, uint32_t V>
+ * variant's code.  R: requests per lane.  Wave w serves requests
+ * [64 R w, 64 R (w + 1)), row r of it on lanes l at 64 R w + 64 r + l, so
+ * that each row's loads and stores are contiguous; every lane of a wave
+ * stays active (rows past n carry no request). */
+template <bool Counted, uint32_t V, uint32_t R>
 __global__ void __launch_bounds__(kBatchBlock) HBHEAP_ALLOC_ATTR k_alloc_batch(hbheap_dev_t h, const uint64_t* __restrict__ sizes,
                                                              void** __restrict__ ptrs, uint64_t n)
 {
@@ -133,32 +137,59 @@ __global__ void __launch_bounds__(kBatchBlock) HBHEAP_ALLOC_ATTR k_alloc_batch(h
     __shared__ uint32_t share[kShareSlots];
     if (threadIdx.x < kShareSlots) share[threadIdx.x] = kShareFree;
     __syncthreads();
-    const uint64_t i = (uint64_t)blockIdx.x * kBatchBlock + threadIdx.x;
-    if (i >= n) return;
+    const uint64_t wave = ((uint64_t)blockIdx.x * kBatchBlock + threadIdx.x) >> 6;
+    const uint64_t base = wave * 64u * R + lane();
+    if (wave * 64u * R >= n) return;
     h.variant = V;
     if (Counted) h.flags |= HBHEAP_FLAG_STATS;
     else h.flags &= ~HBHEAP_FLAG_STATS;
     /* home shard: the linear wave index, spread evenly over the shards; its
-     * pool hint is loaded before the size so that both loads are in flight
+     * pool hint is loaded before the sizes so that the loads are in flight
      * together (the empty asm keeps the compiler from sinking it) */
-    const uint32_t home = (uint32_t)((i >> 6) % h.n_shards);
+    const uint32_t home = (uint32_t)(wave % h.n_shards);
     const bool dry = home_pool_dry(h, home);
     __asm__ volatile("" ::: "memory");
-    ptrs[i] = malloc_wave(h, sizes[i], home, dry, share);
+    uint64_t sz[R];
+    bool has[R];
+#pragma unroll
+    for (uint32_t r = 0; r < R; ++r) {
+        has[r] = base + 64u * r < n;
+        sz[r] = has[r] ? sizes[base + 64u * r] : 0;
+    }
+    Rows<R> q;
+    malloc_rows<R>(h, q, sz, has, home, dry, share);
+#pragma unroll
+    for (uint32_t r = 0; r < R; ++r)
+        if (has[r]) ptrs[base + 64u * r] = q.off[r] == kNoPage ? nullptr : (void*)(h.data + q.off[r]);
 }
 
-template <bool Counted, uint32_t V>
+template <bool Counted, uint32_t V, uint32_t R>
 __global__ void __launch_bounds__(kBatchBlock) k_free_batch(hbheap_dev_t h, const uint64_t* __restrict__ sizes,
                                                             void* const* __restrict__ ptrs, uint64_t n,
                                                             int32_t* __restrict__ status)
 {
-    const uint64_t i = (uint64_t)blockIdx.x * kBatchBlock + threadIdx.x;
-    if (i >= n) return;
+    const uint64_t wave = ((uint64_t)blockIdx.x * kBatchBlock + threadIdx.x) >> 6;
+    const uint64_t base = wave * 64u * R + lane();
+    if (wave * 64u * R >= n) return;
     h.variant = V;
     if (Counted) h.flags |= HBHEAP_FLAG_STATS;
     else h.flags &= ~HBHEAP_FLAG_STATS;
-    const uint32_t st = free_wave(h, ptrs[i], sizes ? sizes[i] : 0, sizes != nullptr);
-    if (status) status[i] = (int32_t)st;
+    void* p[R];
+    uint64_t hint[R];
+    bool has[R];
+#pragma unroll
+    for (uint32_t r = 0; r < R; ++r) {
+        has[r] = base + 64u * r < n;
+        p[r] = has[r] ? ptrs[base + 64u * r] : nullptr;
+        hint[r] = has[r] && sizes ? sizes[base + 64u * r] : 0;
+    }
+    uint32_t st[R];
+    free_rows<R>(h, p, hint, sizes != nullptr, st);
+    if (status) {
+#pragma unroll
+        for (uint32_t r = 0; r < R; ++r)
+            if (has[r]) status[base + 64u * r] = (int32_t)st[r];
+    }
 }
 
 /* One lane runs the op list in order. */
@@ -210,7 +241,7 @@ __device__ __forceinline__ TrimKey trim_key(const hbheap_dev_t& h, uint64_t c)
         uint32_t f = 0;
         const uint32_t ppc = 1u << (h.log2_chunk - 4u - k);
         const uint32_t nw = ppc >= 64u ? ppc >> 6 : 1u;
-        for (uint32_t w = 0; w < nw; ++w) f += (uint32_t)__popcll(h.bits[c * h.words_per_chunk + w]);
+        for (uint32_t w = 0; w < nw; ++w) f += (uint32_t)__popcll(h.bits[bit_index(h, c, w)]);
         t.key = j * h.n_classes + k;
         t.weight = f;
     }
@@ -236,9 +267,9 @@ __global__ void __launch_bounds__(kTrimBlock) k_trim_count(hbheap_dev_t h, uint3
             const uint32_t ppc = 1u << (h.log2_chunk - 4u - k);
             const uint32_t nw = ppc >= 64u ? ppc >> 6 : 1u;
             uint32_t f = 0;
-            for (uint32_t w = 0; w < nw; ++w) f += (uint32_t)__popcll(h.bits[c * h.words_per_chunk + w]);
+            for (uint32_t w = 0; w < nw; ++w) f += (uint32_t)__popcll(h.bits[bit_index(h, c, w)]);
             if (f == ppc) {
-                for (uint32_t w = 0; w < h.words_per_chunk; ++w) h.bits[c * h.words_per_chunk + w] = 0;
+                for (uint32_t w = 0; w < h.words_per_chunk; ++w) h.bits[bit_index(h, c, w)] = 0;
                 h.chunk_cnt[c] = 0;
                 if (eager(h)) h.chunk_ct[c] = ct_word(kTokNone, 0);
                 h.chunk_class[c] = (uint8_t)kFreeClass;
@@ -355,7 +386,7 @@ __global__ void __launch_bounds__(kTrimBlock) k_trim_write(hbheap_dev_t h, const
                 const bool va = HBHEAP_VARIANT_SEGMENTED(h.variant);
                 const uint32_t seg0 = va ? va_first_seg(h, totals, j, kk) : 0u;
                 for (uint32_t wd = 0; wd < nw; ++wd) {
-                    uint64_t x = h.bits[c * h.words_per_chunk + wd];
+                    uint64_t x = h.bits[bit_index(h, c, wd)];
                     while (x) {
                         const uint32_t b = ctz64(x);
                         x &= x - 1ull;
@@ -781,42 +812,66 @@ void release(hbheap_heap* h)
 }  // namespace
 
 namespace {
-template <bool C, uint32_t V>
+/* Batch launches: requests per lane R, one 256-lane block per 4 * 64 * R
+ * requests.  R = the heap's rows for the page and virtualised-array page
+ * variants; 1 for the others (chunk queues stage pages per wave 64 at a
+ * time, and a virtualised list queue's takers walk its links row by row,
+ * where more rows per wave measured slower). */
+template <uint32_t V>
+constexpr bool rows_apply() { return V == HBHEAP_VARIANT_PAGE || V == HBHEAP_VARIANT_VA_PAGE; }
+template <bool C, uint32_t V, uint32_t R>
 void launch_alloc(const hbheap_heap* h, const size_t* sizes, void** ptrs, size_t n, hipStream_t stream)
 {
-    hipLaunchKernelGGL((k_alloc_batch<C, V>), dim3(grid_for(n, kBatchBlock)), dim3(kBatchBlock), 0, stream, h->dev,
-                       (const uint64_t*)sizes, ptrs, (uint64_t)n);
+    hipLaunchKernelGGL((k_alloc_batch<C, V, R>), dim3(grid_for((n + R - 1) / R, kBatchBlock)), dim3(kBatchBlock), 0,
+                       stream, h->dev, (const uint64_t*)sizes, ptrs, (uint64_t)n);
+}
+template <bool C, uint32_t V>
+void launch_alloc_r(const hbheap_heap* h, const size_t* sizes, void** ptrs, size_t n, hipStream_t stream)
+{
+    if constexpr (rows_apply<V>()) {
+        if (h->rows == 4) return launch_alloc<C, V, 4>(h, sizes, ptrs, n, stream);
+    }
+    launch_alloc<C, V, 1>(h, sizes, ptrs, n, stream);
 }
 template <bool C>
 void launch_alloc_v(const hbheap_heap* h, const size_t* sizes, void** ptrs, size_t n, hipStream_t stream)
 {
     switch (h->dev.variant) {
-    case HBHEAP_VARIANT_CHUNK: launch_alloc<C, HBHEAP_VARIANT_CHUNK>(h, sizes, ptrs, n, stream); break;
-    case HBHEAP_VARIANT_PAGE: launch_alloc<C, HBHEAP_VARIANT_PAGE>(h, sizes, ptrs, n, stream); break;
-    case HBHEAP_VARIANT_VA_PAGE: launch_alloc<C, HBHEAP_VARIANT_VA_PAGE>(h, sizes, ptrs, n, stream); break;
-    case HBHEAP_VARIANT_VA_CHUNK: launch_alloc<C, HBHEAP_VARIANT_VA_CHUNK>(h, sizes, ptrs, n, stream); break;
-    case HBHEAP_VARIANT_VL_PAGE: launch_alloc<C, HBHEAP_VARIANT_VL_PAGE>(h, sizes, ptrs, n, stream); break;
-    default: launch_alloc<C, HBHEAP_VARIANT_VL_CHUNK>(h, sizes, ptrs, n, stream); break;
+    case HBHEAP_VARIANT_CHUNK: launch_alloc_r<C, HBHEAP_VARIANT_CHUNK>(h, sizes, ptrs, n, stream); break;
+    case HBHEAP_VARIANT_PAGE: launch_alloc_r<C, HBHEAP_VARIANT_PAGE>(h, sizes, ptrs, n, stream); break;
+    case HBHEAP_VARIANT_VA_PAGE: launch_alloc_r<C, HBHEAP_VARIANT_VA_PAGE>(h, sizes, ptrs, n, stream); break;
+    case HBHEAP_VARIANT_VA_CHUNK: launch_alloc_r<C, HBHEAP_VARIANT_VA_CHUNK>(h, sizes, ptrs, n, stream); break;
+    case HBHEAP_VARIANT_VL_PAGE: launch_alloc_r<C, HBHEAP_VARIANT_VL_PAGE>(h, sizes, ptrs, n, stream); break;
+    default: launch_alloc_r<C, HBHEAP_VARIANT_VL_CHUNK>(h, sizes, ptrs, n, stream); break;
     }
 }
-template <bool C, uint32_t V>
+template <bool C, uint32_t V, uint32_t R>
 void launch_free(const hbheap_heap* h, const size_t* sizes, void* const* ptrs, size_t n, int32_t* status,
                  hipStream_t stream)
 {
-    hipLaunchKernelGGL((k_free_batch<C, V>), dim3(grid_for(n, kBatchBlock)), dim3(kBatchBlock), 0, stream, h->dev,
-                       (const uint64_t*)sizes, ptrs, (uint64_t)n, status);
+    hipLaunchKernelGGL((k_free_batch<C, V, R>), dim3(grid_for((n + R - 1) / R, kBatchBlock)), dim3(kBatchBlock), 0,
+                       stream, h->dev, (const uint64_t*)sizes, ptrs, (uint64_t)n, status);
+}
+template <bool C, uint32_t V>
+void launch_free_r(const hbheap_heap* h, const size_t* sizes, void* const* ptrs, size_t n, int32_t* status,
+                   hipStream_t stream)
+{
+    if constexpr (rows_apply<V>()) {
+        if (h->rows == 4) return launch_free<C, V, 4>(h, sizes, ptrs, n, status, stream);
+    }
+    launch_free<C, V, 1>(h, sizes, ptrs, n, status, stream);
 }
 template <bool C>
 void launch_free_v(const hbheap_heap* h, const size_t* sizes, void* const* ptrs, size_t n, int32_t* status,
                    hipStream_t stream)
 {
     switch (h->dev.variant) {
-    case HBHEAP_VARIANT_CHUNK: launch_free<C, HBHEAP_VARIANT_CHUNK>(h, sizes, ptrs, n, status, stream); break;
-    case HBHEAP_VARIANT_PAGE: launch_free<C, HBHEAP_VARIANT_PAGE>(h, sizes, ptrs, n, status, stream); break;
-    case HBHEAP_VARIANT_VA_PAGE: launch_free<C, HBHEAP_VARIANT_VA_PAGE>(h, sizes, ptrs, n, status, stream); break;
-    case HBHEAP_VARIANT_VA_CHUNK: launch_free<C, HBHEAP_VARIANT_VA_CHUNK>(h, sizes, ptrs, n, status, stream); break;
-    case HBHEAP_VARIANT_VL_PAGE: launch_free<C, HBHEAP_VARIANT_VL_PAGE>(h, sizes, ptrs, n, status, stream); break;
-    default: launch_free<C, HBHEAP_VARIANT_VL_CHUNK>(h, sizes, ptrs, n, status, stream); break;
+    case HBHEAP_VARIANT_CHUNK: launch_free_r<C, HBHEAP_VARIANT_CHUNK>(h, sizes, ptrs, n, status, stream); break;
+    case HBHEAP_VARIANT_PAGE: launch_free_r<C, HBHEAP_VARIANT_PAGE>(h, sizes, ptrs, n, status, stream); break;
+    case HBHEAP_VARIANT_VA_PAGE: launch_free_r<C, HBHEAP_VARIANT_VA_PAGE>(h, sizes, ptrs, n, status, stream); break;
+    case HBHEAP_VARIANT_VA_CHUNK: launch_free_r<C, HBHEAP_VARIANT_VA_CHUNK>(h, sizes, ptrs, n, status, stream); break;
+    case HBHEAP_VARIANT_VL_PAGE: launch_free_r<C, HBHEAP_VARIANT_VL_PAGE>(h, sizes, ptrs, n, status, stream); break;
+    default: launch_free_r<C, HBHEAP_VARIANT_VL_CHUNK>(h, sizes, ptrs, n, status, stream); break;
     }
 }
 }  // namespace
@@ -837,6 +892,7 @@ int heap_create_ex(size_t bytes, size_t chunk_bytes, const heap_config_t* cfg, h
     if (c.width > 64 || (c.width & (c.width - 1))) return HBHEAP_E_INVAL;
     if (!c.spin_cap) c.spin_cap = 1u << 18;
     if (!c.backoff_max) c.backoff_max = 64;
+    if (c.rows != 0 && c.rows != 1 && c.rows != 4) return HBHEAP_E_INVAL;
     const uint64_t N = bytes / chunk_bytes;
     if (N >= 0x80000000ull) return HBHEAP_E_INVAL;
     const uint32_t log2C = ilog2(chunk_bytes);
@@ -853,6 +909,10 @@ int heap_create_ex(size_t bytes, size_t chunk_bytes, const heap_config_t* cfg, h
     hbheap_heap* h = new (std::nothrow) hbheap_heap();
     if (!h) return HBHEAP_E_NOMEM;
     h->chunk_bytes = chunk_bytes;
+    /* several requests per lane need every lane of a wave and at most 4
+     * segments of lanes (so at most 52 groups of a wave) */
+    h->rows = c.rows ? c.rows : 4u;
+    if (c.width < 16) h->rows = 1;
     h->lay = make_layout(N, log2C, K, c.variant, bytes, S, log2_span, eager_retire);
     const Layout& L = h->lay;
     h->trim_blocks = (uint32_t)((N + kTrimBlock - 1) / kTrimBlock);

@@ -36,18 +36,17 @@ constexpr uint64_t kServeCoop = 1024;
 constexpr uint32_t kMaxSlots = 16;
 constexpr uint32_t kMaxBatch = 65536;
 constexpr uint32_t kMaxClasses = 16;
-/* the monitor re-reads the chunk counters at most this often while batches
- * run (each read is one small kernel and an 8-byte copy per class) */
-constexpr uint64_t kMonitorGapNs = 20000;
-
-constexpr uint64_t kUsageBytes = 8 * (1 + kMaxClasses);
+/* chunk-usage words (usage_read): chunks in use, then one per class */
+constexpr uint64_t kUsageWords = 1 + kMaxClasses;
+constexpr uint64_t kUsageBytes = 8 * kUsageWords;
 
 struct Slot {
     hipStream_t st = nullptr;
     hipEvent_t done = nullptr;
     int64_t* ops_d = nullptr;
     uint64_t* aux_d = nullptr;
-    uint64_t* res_d = nullptr;
+    uint64_t* res_d = nullptr;  /* results, then the chunk-usage words */
+    uint32_t* done_d = nullptr; /* workgroups of the running batch finished */
     int64_t* ops_h = nullptr;   /* pinned */
     uint64_t* aux_h = nullptr;  /* pinned */
     uint64_t* res_h = nullptr;  /* pinned */
@@ -74,14 +73,15 @@ namespace {
 
 /* ---------------- device ---------------- */
 
-/* out[0]: chunks taken from the pools (per shard, its chunks minus the
- * pool's remaining ones: size - min(bump, size), or with eager retirement
- * the chunks its pool ring holds); out[1 + k], page variant:
- * chunks owned by class k over all shards (0 in the chunk variant).  One
- * wave. */
-__global__ void k_usage(hbheap_dev_t h, uint64_t* out)
+/* One wave: out[0] = chunks taken from the pools (per shard, its chunks
+ * minus the pool's remaining ones: size - min(bump, size), or with eager
+ * retirement the chunks its pool ring holds); out[1 + k], page variant:
+ * chunks owned by class k over all shards (0 otherwise).  Agent-scope loads
+ * of counters that only grow until a trim (with eager retirement, the pool
+ * rings also shrink the count as chunks retire). */
+__device__ __forceinline__ void usage_read(const hbheap_dev_t& h, uint64_t* out)
 {
-    const uint32_t j = threadIdx.x;
+    const uint32_t j = lane();
     uint64_t used = 0;
     for (uint32_t s = j; s < h.n_shards; s += 64) {
         const uint64_t* pb = h.pool + 16ull * s;
@@ -103,6 +103,8 @@ __global__ void k_usage(hbheap_dev_t h, uint64_t* out)
         out[1 + k] = own;
     }
 }
+
+__global__ void k_usage(hbheap_dev_t h, uint64_t* out) { usage_read(h, out); }
 
 /* 32-bit sum of the words of [0, size) read back, per lane (units u of 16 B
  * with u = first, first + step, ...), tail bytes by the lane with first 0. */
@@ -140,12 +142,9 @@ __device__ __forceinline__ uint32_t wave_sum(uint32_t v, uint32_t leader)
  * kServeCoop bytes and more are written and read by all active lanes of the
  * wave, each lane on the same 16-byte units in both passes (so every lane
  * reads back what it wrote itself). */
-__global__ void __launch_bounds__(kServeBlock) k_serve_batch(hbheap_dev_t h, const int64_t* ops, const uint64_t* aux,
-                                                             uint32_t n, uint64_t first_req, uint64_t* handles,
-                                                             uint64_t* res, uint32_t seed)
+__device__ __forceinline__ void serve_one(const hbheap_dev_t& h, const int64_t* ops, const uint64_t* aux, uint64_t i,
+                                          uint64_t first_req, uint64_t* handles, uint64_t* res, uint32_t seed)
 {
-    const uint64_t i = (uint64_t)blockIdx.x * kServeBlock + threadIdx.x;
-    if (i >= n) return;
     const uint32_t me = lane();
     /* home shard: the wave's index in the launch, offset per batch (the
      * value must be the same on every lane of the wave); its pool hint is
@@ -207,6 +206,33 @@ __global__ void __launch_bounds__(kServeBlock) k_serve_batch(hbheap_dev_t h, con
     res[i] = (uint64_t)sum | ((uint64_t)status << 32) | ((uint64_t)(uint8_t)(int8_t)cls << 40);
 }
 
+/* One batch: lane i serves request i (serve_one).  The batch's last
+ * workgroup to finish then reads the chunk usage into res[n ..): every
+ * workgroup waits for its own memory operations (the pool and owned
+ * counters its refills moved included) before it counts itself done, so the
+ * words are exact for this batch and hold whatever other batches in flight
+ * had done by then.  The usage travels back with the results, in the same
+ * copy; done is left at zero for the slot's next batch. */
+__global__ void __launch_bounds__(kServeBlock) k_serve_batch(hbheap_dev_t h, const int64_t* ops, const uint64_t* aux,
+                                                             uint32_t n, uint64_t first_req, uint64_t* handles,
+                                                             uint64_t* res, uint32_t seed, uint32_t* done)
+{
+    __shared__ uint32_t last;
+    const uint64_t i = (uint64_t)blockIdx.x * kServeBlock + threadIdx.x;
+    if (i < n) serve_one(h, ops, aux, i, first_req, handles, res, seed);
+    wait_own_accesses();
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const uint32_t before = __hip_atomic_fetch_add(done, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        last = before + 1u == gridDim.x;
+    }
+    __syncthreads();
+    if (last && threadIdx.x < 64) {
+        usage_read(h, res + n);
+        if (threadIdx.x == 0) __hip_atomic_store(done, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
 __global__ void k_serve_export(const uint64_t* handles, uint64_t first, uint64_t n, uint64_t* dst)
 {
     const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -238,6 +264,7 @@ void free_slot(Slot& s)
     if (s.ops_d) (void)hipFree(s.ops_d);
     if (s.aux_d) (void)hipFree(s.aux_d);
     if (s.res_d) (void)hipFree(s.res_d);
+    if (s.done_d) (void)hipFree(s.done_d);
     if (s.ops_h) (void)hipHostFree(s.ops_h);
     if (s.aux_h) (void)hipHostFree(s.aux_h);
     if (s.res_h) (void)hipHostFree(s.res_h);
@@ -300,8 +327,12 @@ int serve_create(heap_t h, const serve_config_t* cfg, server_t* out)
     if (!s) return HBHEAP_E_NOMEM;
     s->heap = h;
     s->cfg = c;
+    /* the virtualised page variants are refused: the classes of a shard
+     * share one page budget there, and a request can fail with chunks left
+     * in one shard and budget left in another, which no bound on chunks in
+     * use (nor on the pages committed in total) rules out */
     if (heap_device_handle(h, &s->dev) != HBHEAP_OK || heap_info(h, &s->info) != HBHEAP_OK ||
-        HBHEAP_VARIANT_SEGMENTED(s->info.variant)) {
+        HBHEAP_VARIANT_SHARED_PAGES(s->info.variant)) {
         delete s;
         return HBHEAP_E_INVAL;
     }
@@ -330,12 +361,17 @@ int serve_create(heap_t h, const serve_config_t* cfg, server_t* out)
     for (Slot& sl : s->slots) {
         if (hipStreamCreate(&sl.st) != hipSuccess || hipEventCreateWithFlags(&sl.done, hipEventDisableTiming) != hipSuccess ||
             hipMalloc(&sl.ops_d, 8 * mb) != hipSuccess || hipMalloc(&sl.aux_d, 8 * mb) != hipSuccess ||
-            hipMalloc(&sl.res_d, 8 * mb) != hipSuccess ||
+            hipMalloc(&sl.res_d, 8 * (mb + kUsageWords)) != hipSuccess ||
+            hipMalloc(&sl.done_d, sizeof(uint32_t)) != hipSuccess ||
             hipHostMalloc(&sl.ops_h, 8 * mb, hipHostMallocDefault) != hipSuccess ||
             hipHostMalloc(&sl.aux_h, 8 * mb, hipHostMallocDefault) != hipSuccess ||
-            hipHostMalloc(&sl.res_h, 8 * mb, hipHostMallocDefault) != hipSuccess) {
+            hipHostMalloc(&sl.res_h, 8 * (mb + kUsageWords), hipHostMallocDefault) != hipSuccess) {
             release(s);
             return HBHEAP_E_NOMEM;
+        }
+        if (hipMemset(sl.done_d, 0, sizeof(uint32_t)) != hipSuccess) {
+            release(s);
+            return HBHEAP_E_HIP;
         }
     }
     *out = s;
@@ -446,9 +482,11 @@ int serve_run(server_t s, uint32_t nb, const uint64_t* first, const int64_t* ops
     if (usage_sync(s) != HBHEAP_OK) return HBHEAP_E_HIP;
     set_exact();
 
-    bool mon_busy = false;
-    uint64_t mon_L = 0, mon_out = 0, mon_next_ns = 0;
-    std::vector<uint64_t> mon_L_k(K, 0), mon_out_k(K, 0);
+    /* per batch, fixed at its launch: L with it included, and the worst
+     * cases of the other batches then in flight (not seen complete when its
+     * usage words were read, at its end) */
+    std::vector<uint64_t> at_L(nb, 0), at_out(nb, 0);
+    std::vector<uint64_t> at_L_k((size_t)nb * K, 0), at_out_k((size_t)nb * K, 0);
     std::vector<uint8_t> done(nb, 0);
     uint32_t prefix = 0; /* batches [0, prefix) are complete */
     uint32_t next = 0, inflight = 0;
@@ -464,6 +502,17 @@ int serve_run(server_t s, uint32_t nb, const uint64_t* first, const int64_t* ops
             if (status) status[f + i] = (uint8_t)(r >> 32);
             if (cls) cls[f + i] = (int8_t)(uint8_t)(r >> 40);
         }
+        if (n) {
+            /* the usage words read at the batch's end: a bound from them
+             * (the batches in flight at its launch keep their worst case,
+             * as do those launched since); keep the tighter one */
+            const uint64_t* u = sl.res_h + n;
+            base = std::min(base, (int64_t)u[0] + (int64_t)at_out[b] - (int64_t)at_L[b]);
+            for (uint32_t k = 0; k < K; ++k)
+                base_k[k] = std::min(base_k[k], (int64_t)u[1 + k] + (int64_t)at_out_k[(size_t)b * K + k] -
+                                                    (int64_t)at_L_k[(size_t)b * K + k]);
+            ++st.monitor_reads;
+        }
         if (latency_ns) latency_ns[b] = now - (alone ? launch_ns[b] : arrival_ns[b]);
         done[b] = 1;
         while (prefix < nb && done[prefix]) ++prefix;
@@ -475,8 +524,17 @@ int serve_run(server_t s, uint32_t nb, const uint64_t* first, const int64_t* ops
         sl.batch = b;
         launch_ns[b] = now;
         if (wait_ns) wait_ns[b] = alone ? 0 : now - arrival_ns[b];
+        uint64_t out = 0;
+        for (const Slot& o : s->slots)
+            if (o.batch >= 0 && &o != &sl) {
+                out += worst[o.batch];
+                for (uint32_t k = 0; k < K; ++k) at_out_k[(size_t)b * K + k] += worst_k[(size_t)o.batch * K + k];
+            }
+        at_out[b] = out;
         L += worst[b];
         for (uint32_t k = 0; k < K; ++k) L_k[k] += worst_k[(size_t)b * K + k];
+        at_L[b] = L;
+        for (uint32_t k = 0; k < K; ++k) at_L_k[(size_t)b * K + k] = L_k[k];
         st.peak_bound = std::max<uint64_t>(st.peak_bound, (uint64_t)(base + (int64_t)L));
         ++inflight;
         if (!n) return hipEventRecord(sl.done, sl.st) == hipSuccess ? HBHEAP_OK : HBHEAP_E_HIP;
@@ -486,9 +544,11 @@ int serve_run(server_t s, uint32_t nb, const uint64_t* first, const int64_t* ops
             hipMemcpyAsync(sl.aux_d, sl.aux_h, 8 * n, hipMemcpyHostToDevice, sl.st) != hipSuccess)
             return HBHEAP_E_HIP;
         hipLaunchKernelGGL(k_serve_batch, dim3((uint32_t)((n + kServeBlock - 1) / kServeBlock)), dim3(kServeBlock), 0,
-                           sl.st, s->dev, sl.ops_d, sl.aux_d, (uint32_t)n, f, s->handles, sl.res_d, c.seed);
+                           sl.st, s->dev, sl.ops_d, sl.aux_d, (uint32_t)n, f, s->handles, sl.res_d, c.seed, sl.done_d);
         if (hipGetLastError() != hipSuccess) return HBHEAP_E_HIP;
-        if (hipMemcpyAsync(sl.res_h, sl.res_d, 8 * n, hipMemcpyDeviceToHost, sl.st) != hipSuccess) return HBHEAP_E_HIP;
+        /* results and the usage words after them, in one copy */
+        if (hipMemcpyAsync(sl.res_h, sl.res_d, 8 * (n + 1 + K), hipMemcpyDeviceToHost, sl.st) != hipSuccess)
+            return HBHEAP_E_HIP;
         return hipEventRecord(sl.done, sl.st) == hipSuccess ? HBHEAP_OK : HBHEAP_E_HIP;
     };
     /* quiescent trim and exact recount; the caller made sure nothing runs */
@@ -511,10 +571,9 @@ int serve_run(server_t s, uint32_t nb, const uint64_t* first, const int64_t* ops
             }
             if (launch(sl, b, ns_since(t0)) != HBHEAP_OK) return HBHEAP_E_HIP;
             if (hipEventSynchronize(sl.done) != hipSuccess) return HBHEAP_E_HIP;
+            /* nothing else in flight: the usage words the batch read at its
+             * end make the count exact */
             finish(sl, ns_since(t0));
-            /* nothing in flight: the count is exact after every batch */
-            if (usage_sync(s) != HBHEAP_OK) return HBHEAP_E_HIP;
-            set_exact();
         }
     } else {
         while (next < nb || inflight) {
@@ -529,36 +588,6 @@ int serve_run(server_t s, uint32_t nb, const uint64_t* first, const int64_t* ops
                 } else if (q != hipErrorNotReady) {
                     return HBHEAP_E_HIP;
                 }
-            }
-            if (mon_busy) {
-                const hipError_t q = hipEventQuery(s->mon_done);
-                if (q == hipSuccess) {
-                    /* exact for every batch seen complete before the read was
-                     * issued; the others keep their worst case */
-                    base = (int64_t)s->usage_h[0] + (int64_t)mon_out - (int64_t)mon_L;
-                    for (uint32_t k = 0; k < K; ++k)
-                        base_k[k] = (int64_t)s->usage_h[1 + k] + (int64_t)mon_out_k[k] - (int64_t)mon_L_k[k];
-                    mon_busy = false;
-                    ++st.monitor_reads;
-                } else if (q != hipErrorNotReady) {
-                    return HBHEAP_E_HIP;
-                }
-            }
-            if (!mon_busy && inflight && now >= mon_next_ns) {
-                /* worst cases of the batches not yet seen complete */
-                mon_out = 0;
-                std::fill(mon_out_k.begin(), mon_out_k.end(), 0);
-                for (const Slot& sl : s->slots)
-                    if (sl.batch >= 0) {
-                        mon_out += worst[sl.batch];
-                        for (uint32_t k = 0; k < K; ++k) mon_out_k[k] += worst_k[(size_t)sl.batch * K + k];
-                    }
-                if (usage_issue(s) != HBHEAP_OK || hipEventRecord(s->mon_done, s->mon) != hipSuccess)
-                    return HBHEAP_E_HIP;
-                mon_busy = true;
-                mon_next_ns = now + kMonitorGapNs;
-                mon_L = L;
-                mon_L_k = L_k;
             }
             if (next < nb && now >= arrival_ns[next] && prefix + c.free_lag > next) {
                 const uint32_t b = next;
@@ -577,10 +606,6 @@ int serve_run(server_t s, uint32_t nb, const uint64_t* first, const int64_t* ops
                         if (!inflight) {
                             /* quiescent: first an exact count, then, if that
                              * is not enough, a trim */
-                            if (mon_busy) {
-                                if (hipStreamSynchronize(s->mon) != hipSuccess) return HBHEAP_E_HIP;
-                                mon_busy = false;
-                            }
                             if (usage_sync(s) != HBHEAP_OK) return HBHEAP_E_HIP;
                             set_exact();
                             if (!admissible(b)) {
@@ -594,7 +619,6 @@ int serve_run(server_t s, uint32_t nb, const uint64_t* first, const int64_t* ops
             }
             if (!progress) std::this_thread::yield();
         }
-        if (mon_busy && hipStreamSynchronize(s->mon) != hipSuccess) return HBHEAP_E_HIP;
     }
     st.wall_s = (double)ns_since(t0) * 1e-9;
     if (usage_sync(s) != HBHEAP_OK) return HBHEAP_E_HIP;

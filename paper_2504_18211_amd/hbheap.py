@@ -43,7 +43,7 @@ class HbHeapError(RuntimeError):
 
 class HeapConfig(C.Structure):
     _fields_ = [("variant", C.c_uint32), ("width", C.c_uint32), ("spin_cap", C.c_uint32),
-                ("backoff_max", C.c_uint32), ("flags", C.c_uint32), ("shards", C.c_uint32)]
+                ("backoff_max", C.c_uint32), ("flags", C.c_uint32), ("shards", C.c_uint32), ("rows", C.c_uint32)]
 
 
 class HeapInfo(C.Structure):
@@ -176,8 +176,8 @@ def _stream(stream) -> int | None:
 # ---------------------------------------------------------------------------
 
 def heap_create(nbytes: int, chunk_bytes: int, variant: int = VARIANT_CHUNK, width: int = 64,
-                spin_cap: int = 0, backoff_max: int = 0, flags: int = 0, shards: int = 0) -> int:
-    cfg = HeapConfig(variant, width, spin_cap, backoff_max, flags, shards)
+                spin_cap: int = 0, backoff_max: int = 0, flags: int = 0, shards: int = 0, rows: int = 0) -> int:
+    cfg = HeapConfig(variant, width, spin_cap, backoff_max, flags, shards, rows)
     out = C.c_void_p()
     _check("heap_create_ex", lib().heap_create_ex(nbytes, chunk_bytes, C.byref(cfg), C.byref(out)))
     return out.value
@@ -347,6 +347,7 @@ def heap_chunks_in_use(h: int, stream=None) -> int:
     return v.value
 
 
+
 # ---- growth line (include/hbheap_growth.h) ----
 
 def growth_create(h: int, agents: int, doublings, steps: int, seed: int) -> int:
@@ -402,8 +403,8 @@ class Heap:
     """Owns one heap; methods forward to the C ABI above."""
 
     def __init__(self, nbytes: int, chunk_bytes: int = 8192, variant: int = VARIANT_CHUNK, width: int = 64,
-                 spin_cap: int = 0, backoff_max: int = 0, flags: int = 0, shards: int = 0):
-        self.h = heap_create(nbytes, chunk_bytes, variant, width, spin_cap, backoff_max, flags, shards)
+                 spin_cap: int = 0, backoff_max: int = 0, flags: int = 0, shards: int = 0, rows: int = 0):
+        self.h = heap_create(nbytes, chunk_bytes, variant, width, spin_cap, backoff_max, flags, shards, rows)
         self.info = heap_info(self.h)
         self.base = int(self.info.data)
 

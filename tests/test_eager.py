@@ -166,7 +166,7 @@ def build_eager(N, log2C, cls, bits, ct, pool, rings, log2_span=None, cnt32=None
     off_ct = al(off_sl + 4 * K * Q)
     total = al(off_ct + 8 * N)
     b = bytearray(total)
-    struct.pack_into("<IIQIIIIIIIIQQQQQQQQ", b, 0, 0x48424850, 3, N << log2C, N, log2C, K, 0, W, log2q,
+    struct.pack_into("<IIQIIIIIIIIQQQQQQQQ", b, 0, 0x48424850, 4, N << log2C, N, log2C, K, 0, W, log2q,
                      1, log2_span, off_pool, off_cl, off_cls, off_cnt, off_bits, off_pid, off_sl, total)
     struct.pack_into("<IIQ", b, 168, 1, 0, off_ct)
     phead, pents = pool
@@ -180,7 +180,7 @@ def build_eager(N, log2C, cls, bits, ct, pool, rings, log2_span=None, cnt32=None
     for c in range(N):
         struct.pack_into("<I", b, off_cnt + 4 * c, (cnt32 or {}).get(c, 0))
         for w in range(W):
-            struct.pack_into("<Q", b, off_bits + 8 * (c * W + w), bits[c][w])
+            struct.pack_into("<Q", b, off_bits + 8 * (w * N + c), bits[c][w])
         t, n = ct[c]
         struct.pack_into("<Q", b, off_ct + 8 * c, (t << 32) | n)
     for k in range(K):

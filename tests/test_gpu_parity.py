@@ -129,9 +129,10 @@ def test_single_lane_replay_matches_fifo_oracle(hb, variant, seed, shards):
 
 @pytest.mark.parametrize("variant", VARIANTS)
 @pytest.mark.parametrize("shards", [1, 0])
-def test_sweep_small_exact_capacity(hb, variant, shards):
+@pytest.mark.parametrize("rows", [1, 4])
+def test_sweep_small_exact_capacity(hb, variant, shards, rows):
     nbytes, C, n = 64 * MiB, 8 * KiB, 1 << 16
-    with hb.Heap(nbytes, C, variant=variant, shards=shards) as heap:
+    with hb.Heap(nbytes, C, variant=variant, shards=shards, rows=rows) as heap:
         _same_shards(heap, nbytes, C, shards)
         fresh = heap.snapshot()
         ptrs = zeros_i64(n)
@@ -139,7 +140,7 @@ def test_sweep_small_exact_capacity(hb, variant, shards):
             k = O.class_of(size, C)
             cap = _oracle_cap(nbytes, C, variant, k, shards)
             for it in range(2):
-                say(f"case sweep-small variant={variant} shards={shards} size={size} iter={it}")
+                say(f"case sweep-small variant={variant} shards={shards} rows={rows} size={size} iter={it}")
                 sizes = inputs.sizes_fixed(n, size)
                 sd = dev_u64(sizes)
                 oom0 = heap.stats()["oom"]
@@ -206,20 +207,22 @@ def test_steal_exact_capacity(hb, variant):
 @pytest.mark.parametrize("variant,shards,flags", [(0, 1, 0), (0, 0, 0), (1, 1, 0), (1, 0, 0), (1, 0, 2), (2, 1, 0),
                                                   (2, 0, 0), (2, 0, 2), (3, 1, 0), (3, 0, 0), (4, 1, 0), (4, 0, 0),
                                                   (4, 0, 2), (5, 1, 0), (5, 0, 0)])
-def test_churn_small(hb, variant, shards, flags):
-    """flags 2: the page variant verifies every page it takes from a queue."""
+@pytest.mark.parametrize("rows", [1, 4])
+def test_churn_small(hb, variant, shards, flags, rows):
+    """flags 2: the page variant verifies every page it takes from a queue.
+    rows: requests per lane of the batch kernels."""
     import torch
     nbytes, C, n, rounds = 256 * MiB, 8 * KiB, 1 << 16, 4
     seed = inputs.SEED_CHURN
     sizes = inputs.sizes_log_uniform(n, 4, 8 * KiB, seed)
     ref = O.OracleHeap(nbytes, C, variant)
     ref_offs = ref.alloc_batch(sizes)
-    with hb.Heap(nbytes, C, variant=variant, shards=shards, flags=flags) as heap:
+    with hb.Heap(nbytes, C, variant=variant, shards=shards, flags=flags, rows=rows) as heap:
         fresh = heap.snapshot()
         ptrs = zeros_i64(n)
         heap.alloc(dev_u64(sizes), ptrs)
         for r in range(rounds + 1):
-            say(f"case churn-small variant={variant} shards={shards} flags={flags} round={r}")
+            say(f"case churn-small variant={variant} shards={shards} flags={flags} rows={rows} round={r}")
             if r:
                 idx, new_sizes = inputs.churn_round(n, r, seed)
                 idx_d = torch.from_numpy(idx).to("cuda")
@@ -250,11 +253,12 @@ def test_churn_small(hb, variant, shards, flags):
 # ---------------------------------------------------------------------------
 
 @pytest.mark.parametrize("variant", VARIANTS)
-def test_free_errors(hb, variant):
+@pytest.mark.parametrize("rows", [1, 4])
+def test_free_errors(hb, variant, rows):
     import torch
-    say(f"case free-errors variant={variant}")
+    say(f"case free-errors variant={variant} rows={rows}")
     nbytes, C = 1 * MiB, 8 * KiB
-    with hb.Heap(nbytes, C, variant=variant) as heap:
+    with hb.Heap(nbytes, C, variant=variant, rows=rows) as heap:
         sizes = inputs.sizes_fixed(100, 64)
         ptrs = zeros_i64(100)
         heap.alloc(dev_u64(sizes), ptrs)
@@ -311,13 +315,15 @@ def test_pattern_partial_wave_large_blocks(hb):
 
 @pytest.mark.parametrize("variant", VARIANTS)
 @pytest.mark.parametrize("width", [1, 16, 64])
-def test_width_mixed_batch(hb, variant, width):
-    say(f"case width variant={variant} width={width}")
+@pytest.mark.parametrize("rows", [1, 4])
+def test_width_mixed_batch(hb, variant, width, rows):
+    """rows 4 applies at widths 16 and 64 (a narrower width keeps one row)."""
+    say(f"case width variant={variant} width={width} rows={rows}")
     nbytes, C, n = 64 * MiB, 16 * KiB, 20000  # ragged last wave
     sizes = inputs.sizes_log_uniform(n, 1, 16 * KiB, 77)
     sizes[::97] = 0
     sizes[5::101] = 16 * KiB + 1
-    with hb.Heap(nbytes, C, variant=variant, width=width) as heap:
+    with hb.Heap(nbytes, C, variant=variant, width=width, rows=rows) as heap:
         fresh = heap.snapshot()
         sd, ptrs = dev_u64(sizes), zeros_i64(n)
         heap.alloc(sd, ptrs)
@@ -339,16 +345,18 @@ def test_width_mixed_batch(hb, variant, width):
 # headline workload at full size: 4 GiB heap, 2^20 threads, 16 B .. 8 KiB
 # ---------------------------------------------------------------------------
 
-@pytest.mark.parametrize("variant", VARIANTS)
-def test_sweep_full_size(hb, variant):
+@pytest.mark.parametrize("variant,rows", [(v, 0) for v in VARIANTS] + [(1, 1)])
+def test_sweep_full_size(hb, variant, rows):
+    """rows 0: the library's default (4 requests per lane); rows 1 on the
+    page variant keeps one request per lane covered at full size too."""
     w = inputs.SWEEP
     n = w.threads
-    with hb.Heap(w.heap_bytes, w.chunk_bytes, variant=variant) as heap:
+    with hb.Heap(w.heap_bytes, w.chunk_bytes, variant=variant, rows=rows) as heap:
         _same_shards(heap, w.heap_bytes, w.chunk_bytes, 0)
         fresh = heap.snapshot()
         ptrs = zeros_i64(n)
         for size in inputs.SWEEP_SIZES:
-            say(f"case sweep-full variant={variant} size={size}")
+            say(f"case sweep-full variant={variant} rows={rows} size={size}")
             k = O.class_of(size, w.chunk_bytes)
             cap = _oracle_cap(w.heap_bytes, w.chunk_bytes, variant, k, 0)
             sizes = inputs.sizes_fixed(n, size)

@@ -107,8 +107,9 @@ def compare(out, exp):
             assert r["live"] == live, mode
 
 
-@pytest.mark.parametrize("variant", [0, 1])
+@pytest.mark.parametrize("variant", [0, 1, 3, 5])
 def test_serve_alone_equals_mix_equals_oracle(hb, variant):
+    """Chunk, page, virtualised-array chunk and virtualised-list chunk heaps."""
     nbytes, chunk, seed = 256 * MiB, 8 * KiB, 0x5E
     plan = inputs.serve_plan(300, inputs.SEED_SERVE, warm_requests=60000, mean=512, lo=64, hi=4096)
     say(f"case serve-small variant={variant} warm_batches={plan.warm_batches}")
@@ -116,6 +117,8 @@ def test_serve_alone_equals_mix_equals_oracle(hb, variant):
     compare(out, oracle_serve(nbytes, chunk, variant, plan.first, plan.ops, seed))
     st = out["mix"]["stats"]
     assert st["batches"] == 300 and st["peak_bound"] <= 0.95 * (nbytes // chunk)
+    # the chunk usage came back with every batch's results
+    assert st["monitor_reads"] == int((np.diff(plan.first) > 0).sum())
     assert (out["mix"]["latency_ns"] > 0).all()
 
 
@@ -205,8 +208,10 @@ def test_serve_page_class_capacity_is_not_admitted(hb):
         assert heap.error() == 0
 
 
-@pytest.mark.parametrize("variant", [2, 3, 4, 5])
-def test_serve_refuses_virtualised_array_heap(hb, variant):
+@pytest.mark.parametrize("variant", [2, 4])
+def test_serve_refuses_virtualised_page_heap(hb, variant):
+    """The virtualised page variants share one page budget per shard, which
+    the admission cannot bound: serve_create refuses them."""
     with hb.Heap(8 * MiB, 8 * KiB, variant=variant) as heap:
         with pytest.raises(hb.HbHeapError) as e:
             hb.serve_create(heap.h, 2, 64, 1000, 0.95, 1, 1)
@@ -247,7 +252,7 @@ def test_serve_rejects_bad_plans(hb):
             hb.serve_destroy(s)
 
 
-@pytest.mark.parametrize("variant", [1])
+@pytest.mark.parametrize("variant", [1, 0])
 def test_serve_full_size(hb, variant):
     """16 GiB heap, batches of mean 4096 requests (64 .. 65536), sizes
     log-uniform in [16 B, 8 KiB]: warm-up to about half the heap, then mixed

@@ -304,7 +304,8 @@ def test_check_blocks_catches_planted_faults():
 
 def build_snapshot(N, log2C, variant, log2q, cls, cnt, bits, pool_bumps, pool_ids, rings, owned=None, S=1,
                    log2_span=None, va=None):
-    """Write a version-3 snapshot from plain arrays.  rings[(j, k)] or
+    """Write a version-4 snapshot from plain arrays (bitmask words
+    word-major: word w of chunk c at index w*N + c).  rings[(j, k)] or
     rings[k] (shard 0) = (H, head, entries); pool_bumps: one per shard;
     pool_ids: the whole id array.  Virtualised array (variants 2 and 3):
     va = dict(g, ldir, lstore, M, budget, committed per shard); the slot
@@ -339,7 +340,7 @@ def build_snapshot(N, log2C, variant, log2q, cls, cnt, bits, pool_bumps, pool_id
         off_vss = al(off_vst + 512 * S)
         total = al(off_vss + 4 * S * (1 << lstore))
     b = bytearray(total)
-    struct.pack_into("<IIQIIIIIIIIQQQQQQQQ", b, 0, 0x48424850, 3, N << log2C, N, log2C, K, variant, W, log2q,
+    struct.pack_into("<IIQIIIIIIIIQQQQQQQQ", b, 0, 0x48424850, 4, N << log2C, N, log2C, K, variant, W, log2q,
                      S, log2_span, off_pool, off_cl, off_cls, off_cnt, off_bits, off_pid, off_sl, total)
     if va:
         struct.pack_into("<IIIIQQQQQ", b, 112, g, ldir, lstore, M, va["budget"], off_vdir, off_vtk, off_vst, off_vss)
@@ -353,7 +354,7 @@ def build_snapshot(N, log2C, variant, log2q, cls, cnt, bits, pool_bumps, pool_id
     for c in range(N):
         struct.pack_into("<I", b, off_cnt + 4 * c, cnt[c])
         for w in range(W):
-            struct.pack_into("<Q", b, off_bits + 8 * (c * W + w), bits[c][w])
+            struct.pack_into("<Q", b, off_bits + 8 * (w * N + c), bits[c][w])
     rings = {(key if isinstance(key, tuple) else (0, key)): v for key, v in rings.items()}
     owned = {(key if isinstance(key, tuple) else (0, key)): v for key, v in (owned or {}).items()}
     for j in range(S):
