@@ -27,7 +27,7 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liboracle.so")
-SOURCES = ["hbheap_oracle.c", "hbheap_model.c"]
+SOURCES = ["hbheap_oracle.c", "hbheap_model.c", "hbheap_shards_model.c"]
 
 VARIANT_CHUNK, VARIANT_PAGE, VARIANT_VA_PAGE, VARIANT_VA_CHUNK, VARIANT_VL_PAGE, VARIANT_VL_CHUNK = 0, 1, 2, 3, 4, 5
 POLICY_LOWEST, POLICY_FIFO = 0, 1
@@ -148,6 +148,57 @@ def _model_sigs(L):
         return
     L.orc_model_run.restype = C.c_int
     L.orc_model_run.argtypes = [C.POINTER(ModelParams), C.POINTER(ModelResult)]
+    L.orc_shards_model_run.restype = C.c_int
+    L.orc_shards_model_run.argtypes = [C.POINTER(ShardsParams), C.POINTER(ShardsResult)]
+
+
+class ShardsOp(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("a", C.c_int32), ("b", C.c_int32)]
+
+
+class ShardsParams(C.Structure):
+    _fields_ = [
+        ("n_shards", C.c_int32), ("chunks", C.c_int32), ("ppc", C.c_int32), ("n_leaders", C.c_int32),
+        ("ops", ShardsOp * 3), ("taken", C.c_int32 * 3), ("prealloc", C.c_uint32 * 3),
+        ("mutation", C.c_int32), ("pad_", C.c_int32), ("max_states", C.c_int64),
+    ]
+
+
+class ShardsResult(C.Structure):
+    _fields_ = [
+        ("states", C.c_int64), ("terminals", C.c_int64), ("violations", C.c_int64), ("deadlocks", C.c_int64),
+        ("oom_violations", C.c_int64), ("final_violations", C.c_int64), ("grant_violations", C.c_int64),
+        ("null_outcomes", C.c_int64), ("truncated", C.c_int32), ("first_violation", C.c_int32),
+    ]
+
+    def as_dict(self) -> dict:
+        return {f: int(getattr(self, f)) for f, _ in self._fields_}
+
+
+SOP_ALLOC, SOP_FREE = 1, 2
+SHARDS_MUTATIONS = {"state_before_pool": 1, "ignore_positions": 2, "ignore_holds": 3, "home_only": 4}
+
+
+def shards_model_run(n_shards: int, chunks: int, ppc: int, ops: list, taken=(0, 0, 0), prealloc=(0, 0, 0),
+                     mutation: int = 0, max_states: int = 4_000_000) -> dict:
+    """Explore every interleaving of the leaders' operations (each
+    (SOP_ALLOC, pages, home) or (SOP_FREE, first page, count)) on n_shards
+    shards of `chunks` chunks of `ppc` pages; taken[j] chunks of shard j start
+    owned by the class, with the pages in prealloc[j] allocated and the rest
+    published.  Returns the counters."""
+    p = ShardsParams()
+    p.n_shards, p.chunks, p.ppc, p.n_leaders = n_shards, chunks, ppc, len(ops)
+    for i, (kind, a, b) in enumerate(ops):
+        p.ops[i] = ShardsOp(kind, a, b)
+    for j in range(3):
+        p.taken[j] = taken[j] if j < len(taken) else 0
+        p.prealloc[j] = prealloc[j] if j < len(prealloc) else 0
+    p.mutation, p.max_states = mutation, max_states
+    r = ShardsResult()
+    rc = lib().orc_shards_model_run(C.byref(p), C.byref(r))
+    if rc != 0:
+        raise ValueError(f"bad shards model parameters ({rc})")
+    return r.as_dict()
 
 
 class ModelOp(C.Structure):

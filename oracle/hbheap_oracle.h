@@ -195,6 +195,41 @@ typedef struct {
 /* 0 on success, negative for bad parameters. */
 int orc_model_run(const orc_model_params* p, orc_model_result* r);
 
+/* ---- step-level model of the page variant across shards
+ *      (hbheap_shards_model.c): home passes, the scan of every shard,
+ *      stealing, and the out-of-memory answer ---- */
+#define ORC_SHARDS_MAXL 3
+enum { ORC_SOP_ALLOC = 1, ORC_SOP_FREE = 2 };
+
+/* ALLOC: a = pages wanted (<= ppc), b = home shard; FREE: free the
+ * pre-allocated pages [a, a + b) (page v = (shard * chunks + chunk) * ppc
+ * + page). */
+typedef struct { int32_t kind, a, b; } orc_shards_op;
+
+typedef struct {
+    int32_t n_shards;          /* <= 3                                     */
+    int32_t chunks;            /* chunks per shard, <= 2                   */
+    int32_t ppc;               /* pages per chunk, <= 4                    */
+    int32_t n_leaders;         /* <= 3, one operation each                 */
+    orc_shards_op ops[ORC_SHARDS_MAXL];
+    int32_t taken[3];          /* chunks of shard j owned by the class at the start */
+    uint32_t prealloc[3];      /* of those, pages allocated (bit c*ppc + p); the
+                                  others are free and published in order   */
+    int32_t mutation;          /* planted mistake, 0 for none              */
+    int32_t pad_;
+    int64_t max_states;
+} orc_shards_params;
+
+typedef struct {
+    int64_t states, terminals, violations, deadlocks;
+    int64_t oom_violations, final_violations, grant_violations;
+    int64_t null_outcomes;     /* final states where some request got NULL */
+    int32_t truncated;
+    int32_t first_violation;
+} orc_shards_result;
+
+int orc_shards_model_run(const orc_shards_params* p, orc_shards_result* r);
+
 #ifdef __cplusplus
 }
 #endif
