@@ -122,6 +122,22 @@ int serve_export(server_t s, uint64_t first, uint64_t n, uint64_t* dst, hipStrea
  * counters on `stream` and waited for.  Exact at quiescence. */
 int heap_chunks_in_use(heap_t h, uint64_t* out, hipStream_t stream);
 
+/*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * count as heap_chunks_in_use, with no hipMalloc, hipFree or other
+ * allocating call.  Its staging lives in a fixed device array of the
+ * library (17 u64 per GPU, held until the process ends), not in memory
+ * allocated per call.  out: device buffer of one u64, written in stream
+ * order (asynchronous: nothing is waited for, so the call can be captured
+ * into a graph).  Calls that overlap on one GPU share that array and race:
+ * the caller orders them (one stream, or events).
+ * Errors: HBHEAP_E_INVAL (h or out NULL), HBHEAP_E_RANGE (a heap with more
+ * than 16 classes: never for heaps heap_create makes), HBHEAP_E_UNSUP
+ * (device index beyond 63), HBHEAP_E_HIP.
+ */
+int heap_chunks_in_use_noalloc(heap_t h, uint64_t* out, hipStream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

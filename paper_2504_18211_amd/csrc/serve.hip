@@ -19,6 +19,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <mutex>
 #include <new>
 #include <thread>
 #include <vector>
@@ -298,7 +299,58 @@ int usage_sync(hbheap_server* s)
 
 }  // namespace
 
+/* ---------------- chunks in use without allocating ----------------
+ *
+ * Staging of heap_chunks_in_use_noalloc: what k_usage writes -- the chunks
+ * in use, then the chunks each class owns -- in a fixed array instead of
+ * memory allocated per call.  Each GPU the library runs on holds its own
+ * copy until the process ends; every call on a GPU uses that GPU's copy, so
+ * calls that overlap on one GPU race on it.  Host code never passes the
+ * array's name to a kernel (in host code it is not a device address): it
+ * uses the address hipGetSymbolAddress gave for the current device. */
+constexpr uint32_t kNoAllocWords = kUsageWords;
+static __device__ __align__(256) uint64_t scratch[kNoAllocWords];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+uint64_t* g_scratch[kMaxDevices] = {};
+
+/* Device address of `scratch` on the current device: looked up on the first
+ * call on that device (with it current) and kept. */
+int scratch_on_current_device(uint64_t** out)
+{
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess) return HBHEAP_E_HIP;
+    if (dev < 0 || dev >= kMaxDevices) return HBHEAP_E_UNSUP;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch[dev]) {
+        void* p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return HBHEAP_E_HIP;
+        g_scratch[dev] = (uint64_t*)p;
+    }
+    *out = g_scratch[dev];
+    return HBHEAP_OK;
+}
+}  // namespace
+
 extern "C" {
+
+int heap_chunks_in_use_noalloc(heap_t h, uint64_t* out, hipStream_t stream)
+{
+    if (!h || !out) return HBHEAP_E_INVAL;
+    hbheap_dev_t d;
+    if (heap_device_handle(h, &d) != HBHEAP_OK) return HBHEAP_E_INVAL;
+    if (1u + d.n_classes > kNoAllocWords) return HBHEAP_E_RANGE;
+    uint64_t* sp = nullptr;
+    const int rc = scratch_on_current_device(&sp);
+    if (rc != HBHEAP_OK) return rc;
+    /* k_usage writes every word it reports (the count and one per class of
+     * this heap): nothing needs clearing first */
+    hipLaunchKernelGGL(k_usage, dim3(1), dim3(64), 0, stream, d, sp);
+    if (hipGetLastError() != hipSuccess) return HBHEAP_E_HIP;
+    return hipMemcpyAsync(out, sp, 8, hipMemcpyDeviceToDevice, stream) == hipSuccess ? HBHEAP_OK : HBHEAP_E_HIP;
+}
 
 int heap_chunks_in_use(heap_t h, uint64_t* out, hipStream_t stream)
 {

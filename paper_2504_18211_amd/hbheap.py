@@ -31,6 +31,7 @@ EXPORTS = [
     "growth_create", "growth_destroy", "growth_step", "growth_graph_launch", "growth_release", "growth_export",
     "growth_launch_shape", "growth_autotune",
     "serve_create", "serve_destroy", "serve_run", "serve_export", "heap_chunks_in_use",
+    "heap_chunks_in_use_noalloc",
 ]
 SERVE_OK, SERVE_FREE_DOUBLE, SERVE_FREE_INVAL, SERVE_FREE_NULL, SERVE_ALLOC_NULL = 0, 1, 2, 3, 4
 
@@ -135,6 +136,7 @@ def lib():
         "serve_run": [vp, u32, vp, vp, vp, i32, vp, vp, vp, vp, vp, C.POINTER(ServeStats)],
         "serve_export": [vp, C.c_uint64, C.c_uint64, vp, vp],
         "heap_chunks_in_use": [vp, C.POINTER(C.c_uint64), vp],
+        "heap_chunks_in_use_noalloc": [vp, vp, vp],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -345,6 +347,11 @@ def heap_chunks_in_use(h: int, stream=None) -> int:
     v = C.c_uint64()
     _check("heap_chunks_in_use", lib().heap_chunks_in_use(h, C.byref(v), _stream(stream)))
     return v.value
+
+
+def heap_chunks_in_use_noalloc(h: int, out, stream=None):
+    """out: a device tensor of one int64, written in stream order."""
+    _check("heap_chunks_in_use_noalloc", lib().heap_chunks_in_use_noalloc(h, _addr(out), _stream(stream)))
 
 
 
