@@ -27,7 +27,7 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liboracle.so")
-SOURCES = ["hbheap_oracle.c", "hbheap_model.c", "hbheap_shards_model.c"]
+SOURCES = ["hbheap_oracle.c", "hbheap_model.c", "hbheap_shards_model.c", "hbheap_seg_model.c"]
 
 VARIANT_CHUNK, VARIANT_PAGE, VARIANT_VA_PAGE, VARIANT_VA_CHUNK, VARIANT_VL_PAGE, VARIANT_VL_CHUNK = 0, 1, 2, 3, 4, 5
 POLICY_LOWEST, POLICY_FIFO = 0, 1
@@ -150,6 +150,8 @@ def _model_sigs(L):
     L.orc_model_run.argtypes = [C.POINTER(ModelParams), C.POINTER(ModelResult)]
     L.orc_shards_model_run.restype = C.c_int
     L.orc_shards_model_run.argtypes = [C.POINTER(ShardsParams), C.POINTER(ShardsResult)]
+    L.orc_seg_model_run.restype = C.c_int
+    L.orc_seg_model_run.argtypes = [C.POINTER(SegParams), C.POINTER(SegResult)]
 
 
 class ShardsOp(C.Structure):
@@ -173,6 +175,53 @@ class ShardsResult(C.Structure):
 
     def as_dict(self) -> dict:
         return {f: int(getattr(self, f)) for f, _ in self._fields_}
+
+
+class SegOp(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("queue", C.c_int32), ("value", C.c_int32)]
+
+
+class SegParams(C.Structure):
+    _fields_ = [
+        ("list", C.c_int32), ("n_queues", C.c_int32), ("segments", C.c_int32), ("n_leaders", C.c_int32),
+        ("n_ops", C.c_int32 * 3), ("ops", (SegOp * 6) * 3), ("consume_all", C.c_int32), ("mutation", C.c_int32),
+        ("max_states", C.c_int64),
+    ]
+
+
+class SegResult(C.Structure):
+    _fields_ = [
+        ("states", C.c_int64), ("terminals", C.c_int64), ("violations", C.c_int64), ("deadlocks", C.c_int64),
+        ("value_violations", C.c_int64), ("segment_violations", C.c_int64), ("final_violations", C.c_int64),
+        ("truncated", C.c_int32), ("first_violation", C.c_int32),
+    ]
+
+    def as_dict(self) -> dict:
+        return {f: int(getattr(self, f)) for f, _ in self._fields_}
+
+
+GOP_PUT, GOP_GET = 1, 2
+SEG_MUTATIONS = {"close_early": 1, "install_blind": 2, "keep_count": 3, "retire_uncounted": 4}
+
+
+def seg_model_run(list_form: bool, n_queues: int, segments: int, leaders: list, consume_all: bool = True,
+                  mutation: int = 0, max_states: int = 3_000_000) -> dict:
+    """Explore every interleaving of the leaders' operations (each a list of
+    (GOP_PUT, queue, value) or (GOP_GET, queue)) on virtualised queues of
+    2-slot segments drawn from a store of `segments` ids."""
+    p = SegParams()
+    p.list, p.n_queues, p.segments, p.n_leaders = int(list_form), n_queues, segments, len(leaders)
+    for l, ops in enumerate(leaders):
+        p.n_ops[l] = len(ops)
+        for i, op in enumerate(ops):
+            kind, q, v = (tuple(op) + (0,))[:3]
+            p.ops[l][i] = SegOp(kind, q, v)
+    p.consume_all, p.mutation, p.max_states = int(consume_all), mutation, max_states
+    r = SegResult()
+    rc = lib().orc_seg_model_run(C.byref(p), C.byref(r))
+    if rc != 0:
+        raise ValueError(f"bad segment model parameters ({rc})")
+    return r.as_dict()
 
 
 SOP_ALLOC, SOP_FREE = 1, 2

@@ -230,6 +230,39 @@ typedef struct {
 
 int orc_shards_model_run(const orc_shards_params* p, orc_shards_result* r);
 
+/* ---- step-level model of the virtualised queues (hbheap_seg_model.c):
+ *      segments from a shared store, the array form's directory and the
+ *      list form's links, tags and front retirement ---- */
+#define ORC_SEG_MAXL 3
+#define ORC_SEG_MAXOPS 6
+enum { ORC_GOP_PUT = 1, ORC_GOP_GET = 2 };
+
+/* PUT: enqueue `value` (< 32, distinct over the run) on `queue`; GET:
+ * dequeue one entry of `queue` (waits for a published one). */
+typedef struct { int32_t kind, queue, value; } orc_seg_op;
+
+typedef struct {
+    int32_t list;              /* 0: array form, 1: list form              */
+    int32_t n_queues;          /* <= 2, sharing the store                  */
+    int32_t segments;          /* ids in the store (list: one per queue
+                                  starts in use), 2 .. 4; 2 slots each      */
+    int32_t n_leaders;         /* <= 3                                     */
+    int32_t n_ops[ORC_SEG_MAXL];
+    orc_seg_op ops[ORC_SEG_MAXL][ORC_SEG_MAXOPS];
+    int32_t consume_all;       /* every value put is also taken            */
+    int32_t mutation;          /* planted mistake, 0 for none              */
+    int64_t max_states;
+} orc_seg_params;
+
+typedef struct {
+    int64_t states, terminals, violations, deadlocks;
+    int64_t value_violations, segment_violations, final_violations;
+    int32_t truncated;
+    int32_t first_violation;
+} orc_seg_result;
+
+int orc_seg_model_run(const orc_seg_params* p, orc_seg_result* r);
+
 #ifdef __cplusplus
 }
 #endif
