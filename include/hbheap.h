@@ -168,8 +168,32 @@ int heap_snapshot(heap_t h, void* dst, size_t cap, size_t* len, hipStream_t stre
 int heap_get_error(heap_t h, uint32_t* err);
 int heap_clear_error(heap_t h);
 
-/* Device statistics counters (HBHEAP_STAT_*), blocking read. */
-int heap_stats(heap_t h, uint64_t* out, size_t count);
+/* Device statistics counters, one field per HBHEAP_STAT_* index (field i is
+ * counter i).  The failure and timeout counters are always kept; the refill,
+ * grab, retirement and atomics-by-target counters only on heaps created with
+ * HBHEAP_FLAG_STATS (else they stay 0). */
+typedef struct heap_stats_t {
+    uint64_t chunk_grabs;   /* chunks taken from a pool                          */
+    uint64_t refills;       /* refills of a class queue                          */
+    uint64_t oom;           /* requests answered NULL because the heap was full  */
+    uint64_t oom_waits;     /* exhaustion proofs that had to wait for holds      */
+    uint64_t double_free;   /* frees of a block that was already free            */
+    uint64_t invalid_free;  /* frees of an address that is no block of the heap  */
+    uint64_t timeouts;      /* bounded waits that gave up (HBHEAP_ERR_TIMEOUT)   */
+    uint64_t reserved7;
+    uint64_t state_ops;     /* atomics on class state words                      */
+    uint64_t headtail_ops;  /* atomics on class head and tail words              */
+    uint64_t pool_ops;      /* atomics on pool counters                          */
+    uint64_t spread_ops;    /* per-lane bitmask and chunk-count atomics          */
+    uint64_t retired;       /* chunks retired eagerly                            */
+    uint64_t slot_ops;      /* per-lane ring slot atomics                        */
+    uint64_t reserved14;
+    uint64_t reserved15;
+} heap_stats_t;
+
+/* Read the statistics counters into *out (host memory); blocking (waits for
+ * the device).  Errors: HBHEAP_E_INVAL for a NULL argument, HBHEAP_E_HIP. */
+int heap_stats(heap_t h, heap_stats_t* out);
 
 /*
  * Single-thread replay of an op list on one device lane, in order (the

@@ -1167,10 +1167,13 @@ int heap_clear_error(heap_t h)
     return HBHEAP_OK;
 }
 
-int heap_stats(heap_t h, uint64_t* out, size_t count)
+static_assert(sizeof(heap_stats_t) == HBHEAP_STAT_COUNT * sizeof(uint64_t), "one field per counter");
+static_assert(offsetof(heap_stats_t, slot_ops) == HBHEAP_STAT_SLOT_OPS * sizeof(uint64_t), "field order");
+static_assert(offsetof(heap_stats_t, oom) == HBHEAP_STAT_OOM * sizeof(uint64_t), "field order");
+
+int heap_stats(heap_t h, heap_stats_t* out)
 {
     if (!h || !out) return HBHEAP_E_INVAL;
-    if (count > HBHEAP_STAT_COUNT) count = HBHEAP_STAT_COUNT;
     HB_TRY(hipDeviceSynchronize());
     uint64_t all[HBHEAP_STAT_COUNT];
     HB_TRY(hipMemcpy(all, h->dev.stats, sizeof(all), hipMemcpyDeviceToHost));
@@ -1180,7 +1183,7 @@ int heap_stats(heap_t h, uint64_t* out, size_t count)
         all[HBHEAP_STAT_OOM] += per[(uint64_t)kShardStatStride * j];
         all[HBHEAP_STAT_OOM_WAITS] += per[(uint64_t)kShardStatStride * j + 1];
     }
-    memcpy(out, all, count * 8);
+    memcpy(out, all, sizeof(all));
     return HBHEAP_OK;
 }
 

@@ -112,7 +112,7 @@ def lib():
         "heap_snapshot": [vp, vp, sz, C.POINTER(sz), vp],
         "heap_get_error": [vp, C.POINTER(u32)],
         "heap_clear_error": [vp],
-        "heap_stats": [vp, C.POINTER(C.c_uint64), sz],
+        "heap_stats": [vp, C.POINTER(C.c_uint64)],
         "heap_replay": [vp, i64p, i64p, sz, vp],
         "heap_pattern_write": [vp, vp, vp, sz, u32, vp],
         "heap_pattern_check": [vp, vp, vp, sz, u32, vp, vp],
@@ -239,8 +239,8 @@ def heap_clear_error(h: int):
 
 
 def heap_stats(h: int) -> dict:
-    a = (C.c_uint64 * 16)()
-    _check("heap_stats", lib().heap_stats(h, a, 16))
+    a = (C.c_uint64 * len(STAT_NAMES))()  # heap_stats_t: one u64 field per counter, in order
+    _check("heap_stats", lib().heap_stats(h, a))
     return {name: int(a[i]) for i, name in enumerate(STAT_NAMES)}
 
 
