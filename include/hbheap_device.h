@@ -1298,10 +1298,12 @@ __device__ __forceinline__ void take_rows(const hbheap_dev_t& h, uint32_t j, con
         if (cl[r] != kEmpty) seg_close(h, ring_of(h, j, kr[r]), pos[r], seg[r], cl[r], tl);
 }
 
-/* Page variant: reserve room for up to m more chunks of class k in shard j
- * under the cap, with compare-and-swap so the counter never passes the cap.
- * Returns the number reserved; unused reservations are returned by the
- * caller only when the pool ran dry. */
+/* Page variants: reserve room for up to m more chunks of class k in shard j
+ * under the cap (the page variant: the class's own counter, add and give
+ * back the excess; the shared-budget variants: compare-and-swap, so that the
+ * budget the classes share never reads above the truth).  Returns the
+ * number reserved; unused reservations are returned by the caller only when
+ * the pool ran dry. */
 __device__ __forceinline__ uint32_t owned_reserve(const hbheap_dev_t& h, uint32_t j, uint32_t k, uint32_t lppc, uint32_t m,
                                                   Tally& tl)
 {
@@ -1323,17 +1325,23 @@ __device__ __forceinline__ uint32_t owned_reserve(const hbheap_dev_t& h, uint32_
             }
         }
     }
+    /* One class's own counter: add first, then give back what passed the
+     * cap.  A reader can see the counter above the truth only while some
+     * adder's excess is still out, and that adder saw the counter below the
+     * cap and took all the room left: so a counter read at or above the cap
+     * means no room in truth, and one read below it carries no excess and is
+     * exact.  (A compare-and-swap loop gives the same answers, but with
+     * every refilling wave of a shard on one word it retires one success per
+     * round trip.) */
     uint64_t* owned = owned_of(h, j, k);
     const uint64_t maxc = page_max_chunks(h, lppc);
-    uint64_t o = a_load64(owned);
-    for (;;) {
-        if (o >= maxc) return 0;
-        const uint32_t allow = (maxc - o) < m ? (uint32_t)(maxc - o) : m;
-        tl.pool += 1;
-        if (__hip_atomic_compare_exchange_strong(owned, &o, o + allow, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
-                                                 __HIP_MEMORY_SCOPE_AGENT))
-            return allow;
-    }
+    const uint64_t o = a_add64(owned, m);
+    tl.pool += 1;
+    if (o + m <= maxc) return m;
+    const uint32_t allow = o < maxc ? (uint32_t)(maxc - o) : 0u;
+    a_add64(owned, (uint64_t)0 - (uint64_t)(m - allow));
+    tl.pool += 1;
+    return allow;
 }
 
 /* Does shard j show entries or room to grow for class k?  (Pool and owned
