@@ -162,7 +162,7 @@ class ShardsParams(C.Structure):
     _fields_ = [
         ("n_shards", C.c_int32), ("chunks", C.c_int32), ("ppc", C.c_int32), ("n_leaders", C.c_int32),
         ("ops", ShardsOp * 3), ("taken", C.c_int32 * 3), ("prealloc", C.c_uint32 * 3),
-        ("mutation", C.c_int32), ("pad_", C.c_int32), ("max_states", C.c_int64),
+        ("mutation", C.c_int32), ("room", C.c_int32), ("max_states", C.c_int64),
     ]
 
 
@@ -225,16 +225,18 @@ def seg_model_run(list_form: bool, n_queues: int, segments: int, leaders: list, 
 
 
 SOP_ALLOC, SOP_FREE = 1, 2
-SHARDS_MUTATIONS = {"state_before_pool": 1, "ignore_positions": 2, "ignore_holds": 3, "home_only": 4}
+SHARDS_MUTATIONS = {"state_before_pool": 1, "ignore_positions": 2, "ignore_holds": 3, "home_only": 4,
+                    "room_no_cap": 5, "room_keep_excess": 6, "room_back_all": 7}
 
 
 def shards_model_run(n_shards: int, chunks: int, ppc: int, ops: list, taken=(0, 0, 0), prealloc=(0, 0, 0),
-                     mutation: int = 0, max_states: int = 4_000_000) -> dict:
+                     mutation: int = 0, room: int = 0, max_states: int = 4_000_000) -> dict:
     """Explore every interleaving of the leaders' operations (each
     (SOP_ALLOC, pages, home) or (SOP_FREE, first page, count)) on n_shards
     shards of `chunks` chunks of `ppc` pages; taken[j] chunks of shard j start
     owned by the class, with the pages in prealloc[j] allocated and the rest
-    published.  Returns the counters."""
+    published; room > 0 caps the chunks the class may own per shard.
+    Returns the counters."""
     p = ShardsParams()
     p.n_shards, p.chunks, p.ppc, p.n_leaders = n_shards, chunks, ppc, len(ops)
     for i, (kind, a, b) in enumerate(ops):
@@ -242,7 +244,7 @@ def shards_model_run(n_shards: int, chunks: int, ppc: int, ops: list, taken=(0, 
     for j in range(3):
         p.taken[j] = taken[j] if j < len(taken) else 0
         p.prealloc[j] = prealloc[j] if j < len(prealloc) else 0
-    p.mutation, p.max_states = mutation, max_states
+    p.mutation, p.room, p.max_states = mutation, room, max_states
     r = ShardsResult()
     rc = lib().orc_shards_model_run(C.byref(p), C.byref(r))
     if rc != 0:

@@ -216,7 +216,8 @@ typedef struct {
     uint32_t prealloc[3];      /* of those, pages allocated (bit c*ppc + p); the
                                   others are free and published in order   */
     int32_t mutation;          /* planted mistake, 0 for none              */
-    int32_t pad_;
+    int32_t room;              /* most chunks the class may own per shard
+                                  (a cap on the room counter), 0 for none  */
     int64_t max_states;
 } orc_shards_params;
 

@@ -11,13 +11,20 @@
  * each running one operation:
  *   - allocate g pages from home shard h (the wave's aggregated group):
  *       serve(h): a first pass that takes published entries without a hold
- *       (C -= need, any excess given back), then passes that look (pool, then
- *       state), hold the queue, take, and refill from the shard's own pool
- *       (the refill serves the group and publishes the chunk's other pages:
- *       bits, tail add, one slot per page, then one release that publishes
- *       the count and drops the hold);
+ *       (C -= need, any excess given back), then passes that look (pool,
+ *       room, then state), hold the queue, take, and refill from the shard's
+ *       own pool (the refill takes ceil(need / ppc) chunks, serves the group
+ *       and publishes the last chunk's other pages: bits, tail add, one slot
+ *       per page, then one release that publishes the count and drops the
+ *       hold);
+ *       with a room cap (the most chunks the class may own in a shard), the
+ *       refill first adds the chunks it wants to the shard's room counter,
+ *       gives back at once whatever passed the cap, and gives back again
+ *       what the pool could not supply;
  *       while pages are missing: scan every shard, reading per shard its
- *       pool bump, state word, head and tail in that order; serve the first
+ *       pool bump, room counter, state word, head and tail in that order
+ *       (the room counter's place in it is free: a reading at or above the
+ *       cap stays true until the pool runs dry); serve the first
  *       shard (from home on) that shows entries or chunks; answer NULL only
  *       when the scan finds every shard with an empty pool, no hold, no
  *       published entry and head = tail; otherwise scan again;
@@ -34,7 +41,8 @@
  *     by a free) or is still owed to a free that has not finished; with no
  *     frees running this is "nothing is left";
  *   - in every final state: no hold, C = tail - head on every shard, slots
- *     full exactly on [head, tail), every page exactly once either granted
+ *     full exactly on [head, tail), the room counter equal to the chunks the
+ *     class owns and these within the cap, every page exactly once either granted
  *     (bit clear), or free (bit set) in one slot of its own shard's queue,
  *     or in an unowned chunk (bits clear); granted pages distinct;
  *   - deadlock freedom.
@@ -52,10 +60,16 @@
 #define SM_L 3      /* leaders         */
 #define SM_EMPTY 0xFF
 
-enum { SMUT_NONE = 0, SMUT_STATE_FIRST = 1, SMUT_NO_POSITIONS = 2, SMUT_NO_HOLD_CHECK = 3, SMUT_HOME_ONLY = 4 };
+enum {
+    SMUT_NONE = 0, SMUT_STATE_FIRST = 1, SMUT_NO_POSITIONS = 2, SMUT_NO_HOLD_CHECK = 3, SMUT_HOME_ONLY = 4,
+    SMUT_ROOM_NO_CAP = 5,       /* the refill keeps all it added, past the cap    */
+    SMUT_ROOM_KEEP_EXCESS = 6,  /* what passed the cap is never given back        */
+    SMUT_ROOM_BACK_ALL = 7,     /* the give-back returns the granted part as well */
+};
 
 typedef struct {
     uint8_t bump;           /* chunks taken from the pool                 */
+    uint8_t owned;          /* room counter (with a cap)                  */
     int8_t C;               /* published count                             */
     uint8_t H;              /* holds                                       */
     uint8_t head, tail;     /* positions, monotone modulo 256              */
@@ -68,13 +82,19 @@ enum {
     /* allocation */
     PC_START,       /* read the home pool hint (dry)                       */
     PC_LOOK_POOL,   /* look: pool of shard j                               */
+    PC_LOOK_ROOM,   /* look: room counter of shard j (with a cap)          */
     PC_LOOK_STATE,  /* look: state word of shard j                         */
     PC_RESERVE,     /* take_published (no hold) or reserve with a hold     */
     PC_REFUND,      /* give back what the reservation could not cover      */
     PC_HEAD,        /* head add                                            */
     PC_TAKE,        /* take slot h0 + i                                    */
     PC_CLEAR,       /* clear the bits of the pages taken                   */
-    PC_POOL,        /* refill: take one chunk from the pool                */
+    PC_POOL,        /* refill: take chunks from the pool (with a cap: the
+                       pool look; the take is PC_TAKE_POOL)                */
+    PC_ROOM,        /* refill: add the chunks wanted to the room counter   */
+    PC_ROOM_BACK,   /* refill: give back what passed the cap               */
+    PC_TAKE_POOL,   /* refill: bump the pool by what the room allowed      */
+    PC_ROOM_REFUND, /* refill: give back room the pool could not supply    */
     PC_BITS,        /* refill: set the leftover pages' bits                */
     PC_TAIL,        /* refill: tail add                                    */
     PC_PUT,         /* refill: fill slot t0 + k                            */
@@ -88,6 +108,8 @@ typedef struct {
     uint8_t pc, kind;
     uint8_t home, j, need, got, h0, i, held, look, dry, check_first, served_before;
     uint8_t rc, rserve, L, t0, k, exhausted;   /* refill chunk (global), pages served, leftover */
+    uint8_t m, allow, gm, pb;  /* chunks wanted, allowed by the room, taken; first */
+    uint8_t rd_room;        /* scan: the room counter read below the cap   */
     uint8_t taken[SM_P * 2], ntaken;
     uint8_t granted[SM_P * 2], ngranted, failed;
     uint8_t sr, sph, rd_pool, rd_H, rd_head, avail_r, busy;
@@ -108,7 +130,7 @@ typedef struct {
 typedef struct {
     const orc_shards_params* p;
     orc_shards_result* r;
-    int S, Cn, P, Q;
+    int S, Cn, P, Q, room;
     sstate* tab;
     uint8_t* used;
     uint64_t cap;
@@ -171,7 +193,16 @@ static void check_null(sctx* x, const sstate* s, int me)
     int avail = 0;
     for (int j = 0; j < x->S; ++j) {
         const shard_t* sh = &s->sh[j];
-        if (sh->bump < x->Cn) avail += (x->Cn - sh->bump) * x->P;
+        if (sh->bump < x->Cn) {
+            /* chunks still in the pool, as far as the cap lets the class take
+             * them (the class owns exactly the chunks bumped out of the pool) */
+            int chunks = x->Cn - sh->bump;
+            if (x->room) {
+                const int r = x->room - sh->bump;
+                if (r < chunks) chunks = r > 0 ? r : 0;
+            }
+            avail += chunks * x->P;
+        }
         for (uint8_t pos = sh->head; pos != sh->tail; ++pos) {
             const uint8_t v = sh->slot[pos % x->Q];
             if (v == SM_EMPTY) continue;
@@ -196,6 +227,10 @@ static void check_final(sctx* x, const sstate* s)
     for (int j = 0; j < x->S; ++j) {
         const shard_t* sh = &s->sh[j];
         if (sh->H || sh->C != (int8_t)(uint8_t)(sh->tail - sh->head)) { s_violation(x, 200 + j, &x->r->final_violations); return; }
+        if (x->room && (sh->owned != sh->bump || sh->bump > x->room)) {
+            s_violation(x, 260 + j, &x->r->final_violations);
+            return;
+        }
         for (int q = 0; q < x->Q; ++q) {
             int inside = 0;
             for (uint8_t pos = sh->head; pos != sh->tail; ++pos)
@@ -242,6 +277,32 @@ static void check_final(sctx* x, const sstate* s)
         }
 }
 
+/* The refill took gm chunks from shard L->j's pool, the first at pool
+ * position b: serve the group's pages from them in order, and leave the last
+ * chunk's other pages to publish. */
+static void refill_serve(const sctx* x, sleader_t* L, int b, int gm)
+{
+    const int cap = gm * x->P;
+    const int rr = cap < L->need ? cap : L->need;
+    for (int q = 0; q < rr; ++q) {
+        const int c = L->j * x->Cn + b + q / x->P;
+        L->granted[L->ngranted++] = (uint8_t)(c * x->P + q % x->P);
+    }
+    L->exhausted = gm < L->m;
+    if (cap > L->need) {
+        L->rc = (uint8_t)(L->j * x->Cn + b + gm - 1);
+        L->rserve = (uint8_t)(L->need - (gm - 1) * x->P);
+        L->L = (uint8_t)(x->P - L->rserve);
+        L->k = 0;
+        L->pc = PC_BITS;
+    } else {
+        L->L = 0;
+        L->rc = SM_EMPTY;
+        L->pc = PC_RELEASE;
+    }
+    L->need = (uint8_t)(L->need - rr);
+}
+
 /* leader l takes one step; returns 0 if disabled */
 static int step(sctx* x, sstate* s, int l)
 {
@@ -264,6 +325,10 @@ static int step(sctx* x, sstate* s, int l)
     }
     case PC_LOOK_POOL:
         L->rd_pool = s->sh[L->j].bump >= x->Cn; /* 1: dry */
+        L->pc = x->room && !L->rd_pool ? PC_LOOK_ROOM : PC_LOOK_STATE;
+        return 1;
+    case PC_LOOK_ROOM:
+        if (s->sh[L->j].owned >= x->room) L->rd_pool = 1; /* no room: as good as dry */
         L->pc = PC_LOOK_STATE;
         return 1;
     case PC_LOOK_STATE: {
@@ -319,22 +384,62 @@ static int step(sctx* x, sstate* s, int l)
     }
     case PC_POOL: {
         shard_t* sh = &s->sh[L->j];
-        if (sh->bump < x->Cn) {
-            L->rc = (uint8_t)(L->j * x->Cn + sh->bump);
-            sh->bump++;
-            L->rserve = L->need < x->P ? L->need : (uint8_t)x->P;
-            for (int pg = 0; pg < L->rserve; ++pg) L->granted[L->ngranted++] = (uint8_t)(L->rc * x->P + pg);
-            L->need = (uint8_t)(L->need - L->rserve);
-            L->L = (uint8_t)(x->P - L->rserve);
-            L->k = 0;
-            L->exhausted = 0;
-            L->pc = L->L ? PC_BITS : PC_RELEASE;
-            if (!L->L) L->rc = SM_EMPTY;
-        } else {
+        L->m = (uint8_t)((L->need + x->P - 1) / x->P);
+        if (sh->bump >= x->Cn) { /* dry: nothing reserved, nothing taken */
             L->L = 0;
             L->exhausted = 1;
             L->pc = PC_RELEASE;
+            return 1;
         }
+        if (x->room) { /* the look above; the room and the take are steps of their own */
+            L->pc = PC_ROOM;
+            return 1;
+        }
+        const int b = sh->bump, gm = x->Cn - b < L->m ? x->Cn - b : L->m;
+        sh->bump = (uint8_t)(b + gm);
+        refill_serve(x, L, b, gm);
+        return 1;
+    }
+    case PC_ROOM: {
+        /* add first; what passed the cap goes back in the next step */
+        shard_t* sh = &s->sh[L->j];
+        const int o = sh->owned;
+        sh->owned = (uint8_t)(o + L->m);
+        int allow = o + L->m <= x->room ? L->m : (o < x->room ? x->room - o : 0);
+        if (mut == SMUT_ROOM_NO_CAP) allow = L->m;
+        L->allow = (uint8_t)allow;
+        L->pc = allow < L->m ? PC_ROOM_BACK : PC_TAKE_POOL;
+        return 1;
+    }
+    case PC_ROOM_BACK: {
+        shard_t* sh = &s->sh[L->j];
+        if (mut == SMUT_ROOM_BACK_ALL) sh->owned = (uint8_t)(sh->owned - L->m);
+        else if (mut != SMUT_ROOM_KEEP_EXCESS) sh->owned = (uint8_t)(sh->owned - (L->m - L->allow));
+        if (!L->allow) { /* no room: no take */
+            L->L = 0;
+            L->exhausted = 1;
+            L->pc = PC_RELEASE;
+            return 1;
+        }
+        L->pc = PC_TAKE_POOL;
+        return 1;
+    }
+    case PC_TAKE_POOL: {
+        shard_t* sh = &s->sh[L->j];
+        const int b = sh->bump;
+        const int gm = b >= x->Cn ? 0 : (x->Cn - b < L->allow ? x->Cn - b : L->allow);
+        sh->bump = (uint8_t)(b + gm);
+        L->gm = (uint8_t)gm;
+        L->pb = (uint8_t)b;
+        if (gm < L->allow) { L->pc = PC_ROOM_REFUND; return 1; }
+        refill_serve(x, L, b, gm);
+        return 1;
+    }
+    case PC_ROOM_REFUND: {
+        /* the pool ran dry under the reservation: give back the rest */
+        shard_t* sh = &s->sh[L->j];
+        sh->owned = (uint8_t)(sh->owned - (L->allow - L->gm));
+        refill_serve(x, L, L->pb, L->gm);
         return 1;
     }
     case PC_BITS:
@@ -369,29 +474,33 @@ static int step(sctx* x, sstate* s, int l)
         return 1;
     }
     case PC_SCAN: {
-        /* shard sr positions after home; phases read pool, state, head, tail
-         * (the planted mistake reads the state word before the pool) */
+        /* shard sr positions after home; phases read pool, room counter (with
+         * a cap), state, head, tail (the planted mistake reads the state word
+         * before the pool) */
         const int S = mut == SMUT_HOME_ONLY ? 1 : x->S;
         const int j = (L->home + L->sr) % x->S;
         const shard_t* sh = &s->sh[j];
         int phase = L->sph;
-        if (mut == SMUT_STATE_FIRST && phase <= 1) phase = 1 - phase;
+        if (mut == SMUT_STATE_FIRST && (phase == 0 || phase == 2)) phase = 2 - phase;
         switch (phase) {
         case 0: L->rd_pool = sh->bump >= x->Cn; break;
-        case 1: L->rd_H = sh->H; L->rd_C = sh->C; break;
-        case 2: L->rd_head = sh->head; break;
-        case 3: {
+        case 1: L->rd_room = sh->owned < x->room; break;
+        case 2: L->rd_H = sh->H; L->rd_C = sh->C; break;
+        case 3: L->rd_head = sh->head; break;
+        case 4: {
             const uint8_t tl = sh->tail;
             L->scan_tail[j] = tl;
             L->scanned |= (uint8_t)(1u << j);
             int hold = L->rd_H != 0 && mut != SMUT_NO_HOLD_CHECK;
             if (L->rd_head != tl && mut != SMUT_NO_POSITIONS) hold = 1;
             if (hold) L->busy = 1;
-            if ((L->rd_C > 0 || !L->rd_pool) && L->avail_r == SM_EMPTY) L->avail_r = L->sr;
+            const int grow = !L->rd_pool && (!x->room || L->rd_room);
+            if ((L->rd_C > 0 || grow) && L->avail_r == SM_EMPTY) L->avail_r = L->sr;
             break;
         }
         }
-        if (++L->sph < 4) return 1;
+        if (++L->sph == 1 && !x->room) L->sph = 2; /* no cap: no room read */
+        if (L->sph < 5) return 1;
         L->sph = 0;
         if (++L->sr < S) return 1;
         /* the scan is complete */
@@ -479,7 +588,7 @@ int orc_shards_model_run(const orc_shards_params* p, orc_shards_result* r)
 {
     memset(r, 0, sizeof(*r));
     if (p->n_shards < 1 || p->n_shards > SM_S || p->chunks < 1 || p->chunks > SM_C || p->ppc < 1 || p->ppc > SM_P ||
-        p->n_leaders < 1 || p->n_leaders > SM_L)
+        p->n_leaders < 1 || p->n_leaders > SM_L || p->room < 0 || p->room > SM_C)
         return -1;
     sctx x;
     memset(&x, 0, sizeof(x));
@@ -489,6 +598,7 @@ int orc_shards_model_run(const orc_shards_params* p, orc_shards_result* r)
     x.Cn = p->chunks;
     x.P = p->ppc;
     x.Q = SM_Q;
+    x.room = p->room;
     sstate s0;
     memset(&s0, 0, sizeof(s0));
     /* prefill: shard j's first taken[j] chunks are owned by the class; their
@@ -497,8 +607,9 @@ int orc_shards_model_run(const orc_shards_params* p, orc_shards_result* r)
     for (int j = 0; j < x.S; ++j) {
         shard_t* sh = &s0.sh[j];
         memset(sh->slot, SM_EMPTY, sizeof(sh->slot));
-        if (p->taken[j] > x.Cn) return -2;
+        if (p->taken[j] > x.Cn || (x.room && p->taken[j] > x.room)) return -2;
         sh->bump = (uint8_t)p->taken[j];
+        sh->owned = (uint8_t)p->taken[j];
         for (int c = 0; c < p->taken[j]; ++c)
             for (int pg = 0; pg < x.P; ++pg) {
                 if ((p->prealloc[j] >> (c * x.P + pg)) & 1) continue;
@@ -515,7 +626,7 @@ int orc_shards_model_run(const orc_shards_params* p, orc_shards_result* r)
         const orc_shards_op* op = &p->ops[l];
         L->kind = (uint8_t)op->kind;
         if (op->kind == ORC_SOP_ALLOC) {
-            if (op->a < 1 || op->a > x.P || op->b < 0 || op->b >= x.S) return -4;
+            if (op->a < 1 || op->a > 2 * x.P || op->b < 0 || op->b >= x.S) return -4;
             L->need = (uint8_t)op->a;
             L->home = (uint8_t)op->b;
             L->pc = PC_START;

@@ -44,9 +44,21 @@ CONFIGS = {
                       prealloc=(0b0011, 0b0011)),
     "three_shards": dict(n_shards=3, chunks=1, ppc=2, ops=[(A, 2, 0), (A, 1, 2), (A, 2, 1)], taken=(1, 0, 0),
                          prealloc=(0b11, 0, 0)),
+    # a room cap of one chunk per shard (two in each pool): the refills race
+    # on the room counter; the pages that fit the caps are exactly demanded
+    "room_race": dict(n_shards=2, chunks=2, ppc=2, room=1, ops=[(A, 2, 0), (A, 1, 0), (A, 1, 1)]),
+    # a refill that wants two chunks where one fits: it keeps one, gives the
+    # other back, and finds the rest on the other shard
+    "room_partial": dict(n_shards=2, chunks=2, ppc=2, room=1, ops=[(A, 3, 0), (A, 1, 0)]),
+    # one page more than the caps allow: some request is answered NULL, and
+    # every NULL is exact
+    "room_short": dict(n_shards=2, chunks=2, ppc=2, room=1, ops=[(A, 3, 0), (A, 2, 1)]),
+    # a free races the capped refills (a page short of the demand)
+    "room_free": dict(n_shards=2, chunks=2, ppc=2, room=1, ops=[(A, 2, 1), (F, 0, 1), (A, 2, 0)], taken=(1, 0),
+                      prealloc=(0b11, 0)),
 }
 LARGE = ("steal_refill3", "oom_three")  # about 2 M states each (about 2 GB of visited states)
-SHORT = ("oom_exact", "oom_three", "two_pools", "three_shards")  # fewer pages than requested
+SHORT = ("oom_exact", "oom_three", "two_pools", "three_shards", "room_short", "room_free")  # fewer pages than requested
 
 
 @pytest.mark.parametrize("name", [pytest.param(n, marks=pytest.mark.slow) if n in LARGE else n for n in CONFIGS])
@@ -58,7 +70,8 @@ def test_shards_model_clean(name):
     if name in SHORT:
         # not every request can be served, in every schedule
         assert r["null_outcomes"] == r["terminals"], r
-    elif name in ("steal_refill", "steal_refill3"):
+    elif name in ("steal_refill", "steal_refill3", "room_race", "room_partial"):
+        # exactly as many pages as the pools, caps and frees provide
         assert r["null_outcomes"] == 0, r
 
 
@@ -70,6 +83,31 @@ MUTANT_PINS = [
     ("ignore_holds", "oom_exact"),           # a refill in flight not yet published
     ("home_only", "two_pools"),              # chunks left in another shard's pool
 ]
+
+
+# planted mistakes in the room counter's add-and-give-back, caught by the
+# final state (first_violation 260 + shard: the counter differs from the
+# chunks the class owns, or these pass the cap)
+ROOM_MUTANT_PINS = [
+    ("room_no_cap", "room_race"),        # a refill keeps all it added: a second chunk past the cap
+    ("room_keep_excess", "room_race"),   # the excess stays on the counter
+    ("room_back_all", "room_partial"),   # the give-back returns the granted chunk as well
+]
+
+
+@pytest.mark.parametrize("mutation,name", ROOM_MUTANT_PINS)
+def test_shards_model_catches_room_mistake(mutation, name):
+    r = O.shards_model_run(mutation=O.SHARDS_MUTATIONS[mutation], **CONFIGS[name])
+    assert not r["truncated"]
+    assert r["final_violations"] > 0 and 260 <= r["first_violation"] < 263, r
+
+
+def test_shards_model_keep_excess_is_harmless_to_exactness():
+    """An excess never given back only misstates the counter: every answer
+    stays exact (the adder that passed the cap took all the room left), which
+    is why a reading at or above the cap may be trusted."""
+    r = O.shards_model_run(mutation=O.SHARDS_MUTATIONS["room_keep_excess"], **CONFIGS["room_short"])
+    assert r["oom_violations"] == 0 and r["deadlocks"] == 0 and r["final_violations"] > 0, r
 
 
 @pytest.mark.parametrize("mutation,name", MUTANT_PINS)
@@ -92,6 +130,10 @@ def test_shards_model_rejects_bad_parameters():
     with pytest.raises(ValueError):
         O.shards_model_run(n_shards=4, chunks=1, ppc=2, ops=[(A, 1, 0)])
     with pytest.raises(ValueError):
-        O.shards_model_run(n_shards=2, chunks=1, ppc=2, ops=[(A, 3, 0)])   # more than a chunk
+        O.shards_model_run(n_shards=2, chunks=1, ppc=2, ops=[(A, 5, 0)])   # more than two chunks
+    with pytest.raises(ValueError):
+        O.shards_model_run(n_shards=2, chunks=2, ppc=2, room=3, ops=[(A, 1, 0)])   # cap above the chunks
+    with pytest.raises(ValueError):
+        O.shards_model_run(n_shards=2, chunks=2, ppc=2, room=1, taken=(2, 0), ops=[(A, 1, 0)])   # owns past the cap
     with pytest.raises(ValueError):
         O.shards_model_run(n_shards=2, chunks=1, ppc=2, ops=[(F, 0, 1)])   # page 0 not allocated
