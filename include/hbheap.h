@@ -240,6 +240,18 @@ int hb_atomic_probe(int pattern, void* buf, size_t buf_bytes, size_t threads, ui
 /* HBM stream copy of `bytes` (multiple of 16) from src to dst. */
 int hb_stream_copy(void* dst, const void* src, size_t bytes, hipStream_t stream);
 
+/* Schedule fuzzing, for concurrency tests (the paper throttles allocating
+ * threads with sleeps, Porting section; here sleeps are injected to widen
+ * race windows instead).  Only the test build of the library
+ * (libhbheap_fuzz.so, compiled with HBHEAP_FUZZ=1) has fuzz points: between
+ * the atomic steps of reservations, takes, refills, publications, frees,
+ * scans and segment hand-offs, a wave sleeps at one point in four for up to
+ * most_sleeps - 1 periods of s_sleep 4, drawn from (seed, point, wave,
+ * clock).  seed 0 turns it off.  Applies to every later launch of the
+ * process; synchronises the device first.  The normal build returns
+ * HBHEAP_E_UNSUP and has no fuzz points.  Errors: HBHEAP_E_HIP. */
+int hb_fuzz_set(uint32_t seed, uint32_t most_sleeps);
+
 /* Baseline: the runtime's own per-thread device malloc / free.
  * hb_plain_set_heap sets the device malloc heap limit (call before use). */
 int hb_plain_set_heap(size_t bytes);

@@ -257,6 +257,48 @@ struct Backoff {
     }
 };
 
+/* Schedule fuzzing (a build of the library with HBHEAP_FUZZ=1, for tests):
+ * at each fuzz point of the protocol -- between the atomic steps of a
+ * reservation, a take, a refill, a publication, a free, a scan, a segment
+ * hand-off -- the wave sleeps, one point in four, for a pseudo-random
+ * number of s_sleep periods drawn from (seed, point, wave, clock), which
+ * widens the windows in which other waves act between the steps.  Seed 0
+ * turns it off; the normal build compiles every point to nothing. */
+#ifndef HBHEAP_FUZZ
+#define HBHEAP_FUZZ 0
+#endif
+#if HBHEAP_FUZZ
+/* seed, most sleep periods per point; set by a one-lane kernel of
+ * hb_fuzz_set between launches. */
+__device__ uint32_t hbheap_fuzz_cfg[2];
+/* Chris Wellons' "lowbias32" integer hash (public domain). */
+__device__ __forceinline__ uint32_t fuzz_mix(uint32_t x)
+{
+    x ^= x >> 16;
+    x *= 0x7feb352du;
+    x ^= x >> 15;
+    x *= 0x846ca68bu;
+    x ^= x >> 16;
+    return x;
+}
+#endif
+__device__ __forceinline__ void fuzz_point(uint32_t site)
+{
+#if HBHEAP_FUZZ
+    const uint32_t seed = __builtin_amdgcn_readfirstlane(*(volatile uint32_t*)&hbheap_fuzz_cfg[0]);
+    if (!seed) return;
+    const uint32_t most = __builtin_amdgcn_readfirstlane(*(volatile uint32_t*)&hbheap_fuzz_cfg[1]);
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6));
+    const uint32_t t = __builtin_amdgcn_readfirstlane((uint32_t)clock64());
+    const uint32_t x = fuzz_mix(seed ^ fuzz_mix(site * 0x9E3779B9u ^ wave) ^ (t >> 6));
+    if (x & 3u) return;
+    const uint32_t n = most ? (x >> 2) % most : 0u;
+    for (uint32_t i = 0; i < n; ++i) __builtin_amdgcn_s_sleep(4);
+#else
+    (void)site;
+#endif
+}
+
 /* Atomics issued, by target, when HBHEAP_FLAG_STATS is set: class state
  * words, class head/tail words, the pool counter, per-lane atomics on
  * bitmasks, chunk counts and segment counters (spread), and per-lane
@@ -438,11 +480,13 @@ __device__ __forceinline__ int32_t state_count(uint64_t s) { return (int32_t)((u
  * ring_release(), which also publishes entries written meanwhile. */
 __device__ __forceinline__ uint32_t ring_reserve(const Ring& r, uint32_t n, Tally& t)
 {
+    fuzz_point(1);
     const uint64_t old = a_add64(r.state, kHold - n);
     const int32_t c = state_count(old);
     const uint32_t got = c <= 0 ? 0u : ((uint32_t)c < n ? (uint32_t)c : n);
     t.state += 1;
     if (got < n) {
+        fuzz_point(2);
         a_add64(r.state, (uint64_t)(n - got));
         t.state += 1;
     }
@@ -453,11 +497,13 @@ __device__ __forceinline__ uint32_t ring_reserve(const Ring& r, uint32_t n, Tall
  * a deficit is given back at once. */
 __device__ __forceinline__ uint32_t ring_take_published(const Ring& r, uint32_t n, Tally& t)
 {
+    fuzz_point(3);
     const uint64_t old = a_add64(r.state, (uint64_t)0 - (uint64_t)n);
     const int32_t c = state_count(old);
     const uint32_t got = c <= 0 ? 0u : ((uint32_t)c < n ? (uint32_t)c : n);
     t.state += 1;
     if (got < n) {
+        fuzz_point(4);
         a_add64(r.state, (uint64_t)(n - got));
         t.state += 1;
     }
@@ -465,6 +511,7 @@ __device__ __forceinline__ uint32_t ring_take_published(const Ring& r, uint32_t 
 }
 __device__ __forceinline__ void ring_release(const Ring& r, uint32_t publish, Tally& t)
 {
+    fuzz_point(5);
     a_add64(r.state, (uint64_t)publish - kHold);
     t.state += 1;
 }
@@ -488,6 +535,7 @@ __device__ __forceinline__ uint32_t store_take(const hbheap_dev_t& h, uint32_t j
             return kEmpty;
         }
     }
+    fuzz_point(10);
     const uint32_t pos = a_add32(S.head, 1u);
     t.headtail += 1;
     return plain_take(h, S.slots + (pos & S.mask), t);
@@ -498,7 +546,9 @@ __device__ __forceinline__ void store_put(const hbheap_dev_t& h, uint32_t j, uin
     const Ring S = store_of(h, j);
     const uint32_t pos = a_add32(S.tail, 1u);
     t.headtail += 1;
+    fuzz_point(11);
     plain_put(h, S.slots + (pos & S.mask), seg, t);
+    fuzz_point(12);
     a_add64(S.state, 1ull);
     t.state += 1;
 }
@@ -525,6 +575,7 @@ __device__ __forceinline__ uint32_t* va_slot(const hbheap_dev_t& h, const Ring& 
         if (producer && off == 0 && d == kDirEmpty) {
             const uint32_t seg = store_take(h, r.j, t);
             if (seg == kEmpty) return nullptr;
+            fuzz_point(13);
             uint64_t expect = kDirEmpty;
             if (__hip_atomic_compare_exchange_strong(e, &expect, ((uint64_t)s << 32) | seg, __ATOMIC_RELAXED,
                                                      __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
@@ -573,6 +624,7 @@ __device__ __forceinline__ void vl_retire(const hbheap_dev_t& h, const Ring& r, 
         const uint64_t nx = fm_ok && c == G ? a_load64(r.vnext + fm + zero_after(c)) : kNoLink;
         if (!fm_ok || (nx != kNoLink && (uint32_t)nx >= h.vsegs)) raise_err(h, HBHEAP_ERR_CORRUPT, HBHEAP_STAT_TIMEOUTS);
         if (fm_ok && c == G && nx != kNoLink && (uint32_t)nx < h.vsegs) {
+            fuzz_point(16);
             uint64_t expect = f;
             const bool won = __hip_atomic_compare_exchange_strong(
                 r.front + zero_after((uint32_t)nx), &expect, (((f >> 32) + 1ull) << 32) | (uint32_t)nx,
@@ -582,6 +634,7 @@ __device__ __forceinline__ void vl_retire(const hbheap_dev_t& h, const Ring& r, 
                 t.spread += 1;
                 /* this retirer owns the segment: reset its count and link,
                  * both performed before the store hands it out again */
+                fuzz_point(17);
                 const uint32_t was = a_xchg32(taken + fm, 0u);
                 const uint64_t lk = a_xchg64(r.vnext + fm, kNoLink);
                 store_put(h, r.j + zero_after(was ^ (uint32_t)lk), fm, t);
@@ -628,9 +681,11 @@ __device__ __forceinline__ uint32_t* vl_slot(const hbheap_dev_t& h, const Ring& 
                     raise_err(h, HBHEAP_ERR_CORRUPT, HBHEAP_STAT_TIMEOUTS);
                     return nullptr;
                 }
+                fuzz_point(14);
                 const uint64_t w1 = a_xchg64(r.vtag + m, qtag | s);
                 const uint64_t w2 = a_xchg64(r.vnext + m + zero_after((uint32_t)w1), kNoLink);
                 const uint64_t w3 = a_xchg64(r.vnext + bm + zero_after((uint32_t)w2), m);
+                fuzz_point(15);
                 uint64_t expect = bk;
                 const bool moved = __hip_atomic_compare_exchange_strong(
                     r.back + zero_after((uint32_t)w3), &expect, ((uint64_t)s << 32) | m, __ATOMIC_RELAXED,
@@ -676,6 +731,7 @@ __device__ __forceinline__ uint32_t* vl_slot(const hbheap_dev_t& h, const Ring& 
 __device__ __forceinline__ uint32_t slot_take(const hbheap_dev_t& h, const Ring& r, uint32_t pos, uint32_t* seg,
                                               Tally& t)
 {
+    fuzz_point(20);
     if (r.segs) {
         uint32_t* s = HBHEAP_VARIANT_IS_VL(h.variant) ? vl_slot(h, r, pos, false, seg, t)
                                                       : va_slot(h, r, pos, false, seg, t);
@@ -706,6 +762,7 @@ __device__ __forceinline__ uint32_t seg_count_add(const hbheap_dev_t& h, const R
     const uint32_t G = 1u << r.log2g;
     uint32_t* tk = h.vtaken + (uint64_t)r.j * h.vsegs + seg;
     t.spread += 1;
+    fuzz_point(18);
     if ((pos & (G - 1u)) != G - 1u) {
         __hip_atomic_fetch_add(tk, n, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         return kEmpty;
@@ -749,6 +806,7 @@ __device__ __forceinline__ void seg_close(const hbheap_dev_t& h, const Ring& r, 
      * before the segment can be taken again: exchanges whose returned
      * values the store's first atomic depends on (no cache-wide
      * release fence) */
+    fuzz_point(19);
     const uint32_t was = a_xchg32(tk, 0u);
     const uint64_t ent = __hip_atomic_exchange(r.dir + ((pos >> r.log2g) & r.dmask), kDirEmpty,
                                                __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -798,6 +856,7 @@ __device__ __forceinline__ uint32_t plain_take(const hbheap_dev_t& h, uint32_t* 
  * the entry of the previous lap). */
 __device__ __forceinline__ bool slot_put(const hbheap_dev_t& h, const Ring& r, uint32_t pos, uint32_t v, Tally& t)
 {
+    fuzz_point(21);
     if (r.segs) {
         uint32_t seg = 0;
         uint32_t* s = HBHEAP_VARIANT_IS_VL(h.variant) ? vl_slot(h, r, pos, true, &seg, t)
@@ -991,6 +1050,7 @@ __device__ __forceinline__ void retire_wave(const hbheap_dev_t& h, bool want, ui
     uint64_t pend = __ballot(want);
     if (!pend) return;
     uint32_t dep = 0;
+    fuzz_point(47);
     if (want) dep = retire_reset(h, c, k, t);
     const uint32_t me = lane();
     const uint32_t j = want ? shard_of_chunk(h, c) : 0u;
@@ -1026,6 +1086,7 @@ __device__ __forceinline__ void list_or_retire(const hbheap_dev_t& h, uint32_t c
                                                uint32_t take, Tally& t)
 {
     uint64_t* w = h.chunk_ct + c;
+    fuzz_point(46);
     uint64_t v = a_load64(w);
     for (;;) {
         const uint32_t n = ct_count(v) - take;
@@ -1396,8 +1457,11 @@ __device__ __forceinline__ uint32_t scan_shards(const hbheap_dev_t& h, const Gro
             bool grow = eager(h) ? state_count(bump) > 0 : bump < ((const uint32_t*)pb)[2];
             if (grow) grow = class_has_room(h, j, g.k, g.lppc);
             const Ring R = ring_of(h, j, g.k);
+            fuzz_point(35);
             const uint64_t st = a_load64(R.state + zero_after((uint32_t)bump));
+            fuzz_point(36);
             const uint32_t hd = a_load32(R.head + zero_after((uint32_t)st));
+            fuzz_point(37);
             const uint32_t tl_ = a_load32(R.tail + zero_after(hd));
             hold = (st >> 32) != 0 || hd != tl_;
             avail = state_count(st) > 0 || grow;
@@ -1498,6 +1562,7 @@ __device__ __forceinline__ void chunk_serve_shard(const hbheap_dev_t& h, const G
                 if (v <= 0) raise_err(h, HBHEAP_ERR_CORRUPT, HBHEAP_STAT_TIMEOUTS);
             }
         }
+        fuzz_point(28);
         /* stale entries dropped: progress even if nothing was served */
         const bool dropped = ev && __ballot(stale) != 0;
         if (R.segs) seg_count_taken(h, R, took_slot, h0 + g.arank, vseg, tl);
@@ -1514,6 +1579,7 @@ __device__ __forceinline__ void chunk_serve_shard(const hbheap_dev_t& h, const G
                  * nobody else takes pages from the chunk and frees only add */
                 keep = (uint32_t)v > t;
             } else if (t) {
+                fuzz_point(29);
                 keep = a_addi(h.chunk_cnt + c, -(int32_t)t) - (int32_t)t > 0;
                 tl.spread += 1;
             } else {
@@ -1528,12 +1594,14 @@ __device__ __forceinline__ void chunk_serve_shard(const hbheap_dev_t& h, const G
          * waves can take those chunks meanwhile: the pages it claims are
          * already taken off the counts, which stay within the free bits */
         const bool early = !(got < want && need > took);
+        fuzz_point(30);
         if (!early && t) claim_pages(h, c, g.k, t, stage + served + tpre, tl);
 
         /* chunks that still hold free pages go back to the tail */
         const uint64_t rq = __ballot(keep);
         const uint32_t nrq = (uint32_t)__popcll(rq);
         uint32_t t0 = 0;
+        fuzz_point(31);
         if (nrq && g.me == g.leader) {
             t0 = a_add32(R.tail, nrq);
             tl.headtail += 1;
@@ -1589,6 +1657,7 @@ __device__ __forceinline__ void chunk_serve_shard(const hbheap_dev_t& h, const G
             gm = bcast(gm, g.leader);
             first = bcast64(first, g.leader);
             exhausted = gm < m;
+            fuzz_point(32);
             /* the chunk of rank q among those taken: a pool id (bump pool),
              * or what lane q took from the pool ring */
             uint32_t mine = kEmpty;
@@ -1630,6 +1699,7 @@ __device__ __forceinline__ void chunk_serve_shard(const hbheap_dev_t& h, const G
                     tl.spread += 1;
                 }
                 write_free_bits(h, cl, u, g, tl);
+                fuzz_point(33);
                 if (g.me == g.leader) {
                     uint32_t pos = a_add32(R.tail, 1u);
                     tl.headtail += 1;
@@ -1738,6 +1808,7 @@ __device__ __forceinline__ void page_serve_shard(const hbheap_dev_t& h, const Gr
         if (g.me == g.leader) {
             got = held ? ring_reserve(Q, need, tl) : ring_take_published(Q, need, tl);
             if (got) {
+                fuzz_point(22);
                 h0 = a_add32(Q.head, got);
                 tl.headtail += 1;
             }
@@ -1755,6 +1826,7 @@ __device__ __forceinline__ void page_serve_shard(const hbheap_dev_t& h, const Gr
             kr[r] = g.k;
         }
         take_rows<R>(h, j, kr, tk, pos, v, tl);
+        fuzz_point(23);
 #pragma unroll
         for (uint32_t r = 0; r < R; ++r) page_took(h, j, g.shift, v[r], q.off[r], tl);
         need -= got;
@@ -1769,6 +1841,7 @@ __device__ __forceinline__ void page_serve_shard(const hbheap_dev_t& h, const Gr
             if (g.me == g.leader) {
                 if (!pool_empty(h, j)) {
                     const uint32_t allow = owned_reserve(h, j, g.k, g.lppc, m, tl);
+                    fuzz_point(24);
                     gm = allow ? pool_take(h, j, allow, &first, tl) : 0u;
                     if (gm < allow) {
                         /* the pool ran dry: give back what was not taken */
@@ -1783,6 +1856,7 @@ __device__ __forceinline__ void page_serve_shard(const hbheap_dev_t& h, const Gr
             gm = bcast(gm, g.leader);
             first = bcast64(first, g.leader);
             exhausted = gm < m;
+            fuzz_point(25);
             /* the chunks' class bytes, by atomics on their words (an unowned
              * chunk's byte is 0xFF, so an AND sets it): like every word other
              * waves read during a kernel, written where device atomics are
@@ -1808,6 +1882,7 @@ __device__ __forceinline__ void page_serve_shard(const hbheap_dev_t& h, const Gr
                 write_free_bits(h, cl, u, g, tl);
                 const uint32_t L = g.ppc - u;
                 uint32_t t0 = 0;
+                fuzz_point(26);
                 if (g.me == g.leader) {
                     t0 = a_add32(Q.tail, L);
                     tl.headtail += 1;
@@ -1815,6 +1890,7 @@ __device__ __forceinline__ void page_serve_shard(const hbheap_dev_t& h, const Gr
                 t0 = bcast(t0, g.leader);
                 const uint64_t cbase = ((uint64_t)cl << h.log2_chunk) >> 4;
                 const uint32_t step = 1u << (g.shift - 4u);
+                fuzz_point(27);
                 if (!Q.segs) {
                     /* eight compare-and-swaps per lane in flight at a time */
                     for (uint32_t i0 = g.arank; i0 < L; i0 += 8u * g.nact) {
@@ -2190,6 +2266,7 @@ __device__ __forceinline__ uint32_t free_wave(const hbheap_dev_t& h, void* p, ui
             tl.spread += 1;
         }
     }
+    fuzz_point(38);
     if (eager(h)) retire_wave(h, retire, (uint32_t)c, k, tl);
     old = perm64(old, run.tail);
     cold = perm32(cold, run.tail);
@@ -2230,6 +2307,7 @@ __device__ __forceinline__ uint32_t free_wave(const hbheap_dev_t& h, void* p, ui
         const uint32_t n = (uint32_t)__popcll(grp);
         const Ring R = ring_of(h, kk / h.n_classes, kk % h.n_classes);
         uint32_t t0 = 0;
+        fuzz_point(39);
         if (me == leader) {
             t0 = a_add32(R.tail, n);
             tl.headtail += 1;
@@ -2240,6 +2318,7 @@ __device__ __forceinline__ uint32_t free_wave(const hbheap_dev_t& h, void* p, ui
             if (eager(h)) list_or_retire(h, val, k, 1u << (h.log2_chunk - 4u - k), pos, 0u, tl);
             slot_put(h, R, pos, val, tl);
         }
+        fuzz_point(40);
         if (me == leader) {
             a_add64(R.state, (uint64_t)n);
             tl.state += 1;
@@ -2252,6 +2331,7 @@ __device__ __forceinline__ uint32_t free_wave(const hbheap_dev_t& h, void* p, ui
         tl.headtail += 1;
         if (eager(h)) list_or_retire(h, val, k, 1u << (h.log2_chunk - 4u - k), t0, 0u, tl);
         slot_put(h, R, t0, val, tl);
+        fuzz_point(41);
         a_add64(R.state, 1ull);
         tl.state += 1;
     }
@@ -2370,6 +2450,7 @@ __device__ __forceinline__ void free_rows(const hbheap_dev_t& h, void* const (&p
     }
 #pragma unroll
     for (uint32_t r = 0; r < R; ++r) cold[r] = nnew[r] ? cold[r] : 1u;
+    fuzz_point(42);
     uint32_t ndbl = 0, ninv = 0;
 #pragma unroll
     for (uint32_t r = 0; r < R; ++r) {
@@ -2432,6 +2513,7 @@ __device__ __forceinline__ void free_rows(const hbheap_dev_t& h, void* const (&p
         first_group = false;
         const Ring Q = ring_of(h, kk / h.n_classes, kk % h.n_classes);
         uint32_t t0 = 0;
+        fuzz_point(43);
         if (me == leader) {
             t0 = a_add32(Q.tail, nn);
             tl.headtail += 1;
@@ -2440,6 +2522,7 @@ __device__ __forceinline__ void free_rows(const hbheap_dev_t& h, void* const (&p
 #pragma unroll
         for (uint32_t r = 0; r < R; ++r) pos[r] += t0;
         put_rows<R>(h, jr, kr, mem, pos, val, tl);
+        fuzz_point(44);
         if (me == leader) {
             a_add64(Q.state, (uint64_t)nn);
             tl.state += 1;
@@ -2479,6 +2562,7 @@ __device__ __forceinline__ void free_rows(const hbheap_dev_t& h, void* const (&p
         }
     }
     put_rows<R>(h, jr, kr, enq, pos, val, tl);
+    fuzz_point(45);
 #pragma unroll
     for (uint32_t r = 0; r < R; ++r) {
         if (enq[r]) {

@@ -10,6 +10,9 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libhbheap.so")
 SOURCES = ["csrc/hbheap.hip", "csrc/growth.hip", "csrc/serve.hip", "csrc/plain_baseline.hip"]
+# the test build with schedule fuzzing: the allocator's translation unit only
+FUZZ_LIB = os.path.join(HERE, "libhbheap_fuzz.so")
+FUZZ_SOURCES = ["csrc/hbheap.hip"]
 ARCH = "gfx950"
 
 
@@ -30,8 +33,8 @@ FLAGS = [
 OBJ_DIR = os.path.join(ROOT, "_build")
 
 
-def compile_command(src: str, obj: str) -> list[str]:
-    return [hipcc()] + FLAGS + ["-c", "-o", obj, os.path.join(HERE, src)]
+def compile_command(src: str, obj: str, defines: tuple = ()) -> list[str]:
+    return [hipcc()] + FLAGS + [f"-D{d}" for d in defines] + ["-c", "-o", obj, os.path.join(HERE, src)]
 
 
 def link_command(objs: list[str], out: str) -> list[str]:
@@ -48,16 +51,20 @@ def _run(cmd: list[str], verbose: bool):
 
 def build(verbose: bool = False) -> str:
     """Compile every source (in parallel, one hipcc each) and link the shared
-    library; it always recompiles."""
+    library and its schedule-fuzzing test build; it always recompiles."""
     from concurrent.futures import ThreadPoolExecutor
     os.makedirs(OBJ_DIR, exist_ok=True)
     objs = [os.path.join(OBJ_DIR, os.path.basename(s).replace(".hip", ".o")) for s in SOURCES]
-    with ThreadPoolExecutor(max_workers=len(SOURCES)) as ex:
-        for f in [ex.submit(_run, compile_command(s, o), verbose) for s, o in zip(SOURCES, objs)]:
+    fobjs = [os.path.join(OBJ_DIR, os.path.basename(s).replace(".hip", "_fuzz.o")) for s in FUZZ_SOURCES]
+    jobs = [compile_command(s, o) for s, o in zip(SOURCES, objs)]
+    jobs += [compile_command(s, o, ("HBHEAP_FUZZ=1",)) for s, o in zip(FUZZ_SOURCES, fobjs)]
+    with ThreadPoolExecutor(max_workers=len(jobs)) as ex:
+        for f in [ex.submit(_run, cmd, verbose) for cmd in jobs]:
             f.result()
-    tmp = LIB + ".tmp"
-    _run(link_command(objs, tmp), verbose)
-    os.replace(tmp, LIB)
+    for out, o in ((LIB, objs), (FUZZ_LIB, fobjs)):
+        tmp = out + ".tmp"
+        _run(link_command(o, tmp), verbose)
+        os.replace(tmp, out)
     return LIB
 
 

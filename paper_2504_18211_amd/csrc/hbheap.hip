@@ -17,6 +17,7 @@
 #include <hip/hip_runtime.h>
 
 #include <stdint.h>
+#include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
 
@@ -876,6 +877,17 @@ void launch_free_v(const hbheap_heap* h, const size_t* sizes, void* const* ptrs,
 }
 }  // namespace
 
+#if HBHEAP_FUZZ
+/* Sets the schedule-fuzzing parameters every fuzz point reads. */
+__global__ void k_fuzz_set(uint32_t seed, uint32_t most)
+{
+    if (threadIdx.x == 0) {
+        hbheap::detail::hbheap_fuzz_cfg[0] = seed;
+        hbheap::detail::hbheap_fuzz_cfg[1] = most;
+    }
+}
+#endif
+
 extern "C" {
 
 const char* hbheap_version(void) { return "hbheap 0.1 (gfx950)"; }
@@ -1246,6 +1258,28 @@ int hb_stream_copy(void* dst, const void* src, size_t bytes, hipStream_t stream)
     const uint32_t blocks = 256 * 8;
     hipLaunchKernelGGL(k_copy, dim3(blocks), dim3(256), 0, stream, (uint4*)dst, (const uint4*)src, n);
     return hipGetLastError() == hipSuccess ? HBHEAP_OK : HBHEAP_E_HIP;
+}
+
+int hb_fuzz_set(uint32_t seed, uint32_t most_sleeps)
+{
+#if HBHEAP_FUZZ
+    /* a test-build entry point: a failure names the HIP error on stderr */
+    hipError_t e = hipDeviceSynchronize();
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(k_fuzz_set, dim3(1), dim3(64), 0, 0, seed, most_sleeps);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e != hipSuccess) {
+        fprintf(stderr, "hb_fuzz_set: %s (%d)\n", hipGetErrorString(e), (int)e);
+        return HBHEAP_E_HIP;
+    }
+    return HBHEAP_OK;
+#else
+    (void)seed;
+    (void)most_sleeps;
+    return HBHEAP_E_UNSUP;
+#endif
 }
 
 }  // extern "C"

@@ -13,6 +13,9 @@ import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libhbheap.so")
+# the test build with schedule fuzzing (the allocator only: no growth,
+# serving or plain-baseline entry points); see use_fuzz_library()
+FUZZ_LIB_PATH = os.path.join(HERE, "libhbheap_fuzz.so")
 
 VARIANT_CHUNK, VARIANT_PAGE, VARIANT_VA_PAGE, VARIANT_VA_CHUNK, VARIANT_VL_PAGE, VARIANT_VL_CHUNK = 0, 1, 2, 3, 4, 5
 OK, E_INVAL, E_NOMEM, E_HIP, E_RANGE, E_UNSUP = 0, -1, -2, -3, -4, -5
@@ -31,7 +34,7 @@ EXPORTS = [
     "growth_create", "growth_destroy", "growth_step", "growth_graph_launch", "growth_release", "growth_export",
     "growth_launch_shape", "growth_autotune",
     "serve_create", "serve_destroy", "serve_run", "serve_export", "heap_chunks_in_use",
-    "heap_chunks_in_use_noalloc",
+    "heap_chunks_in_use_noalloc", "hb_fuzz_set",
 ]
 SERVE_OK, SERVE_FREE_DOUBLE, SERVE_FREE_INVAL, SERVE_FREE_NULL, SERVE_ALLOC_NULL = 0, 1, 2, 3, 4
 
@@ -86,6 +89,17 @@ class DevHandle(C.Structure):
 
 
 _lib = None
+_libs = {}
+_path = LIB_PATH
+
+
+def use_fuzz_library(on: bool):
+    """Route every later call through the schedule-fuzzing test build (on)
+    or the normal library (off).  Heaps must be used with the library that
+    created them."""
+    global _lib, _path
+    _path = FUZZ_LIB_PATH if on else LIB_PATH
+    _lib = _libs.get(_path)
 
 
 def lib():
@@ -93,10 +107,10 @@ def lib():
     global _lib
     if _lib is not None:
         return _lib
-    if not os.path.exists(LIB_PATH):
-        raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+    if not os.path.exists(_path):
+        raise RuntimeError(f"{_path} is missing: build it with __graft_entry__.build() "
                            "(hipcc --offload-arch=gfx950); there is no fallback")
-    L = C.CDLL(LIB_PATH)
+    L = C.CDLL(_path)
     vp, sz, u32, i32, i64p = C.c_void_p, C.c_size_t, C.c_uint32, C.c_int, C.c_void_p
     sig = {
         "heap_create": [sz, sz, C.POINTER(vp)],
@@ -137,15 +151,23 @@ def lib():
         "serve_export": [vp, C.c_uint64, C.c_uint64, vp, vp],
         "heap_chunks_in_use": [vp, C.POINTER(C.c_uint64), vp],
         "heap_chunks_in_use_noalloc": [vp, vp, vp],
+        "hb_fuzz_set": [u32, u32],
     }
     for name, args in sig.items():
+        if _path == FUZZ_LIB_PATH and not hasattr(L, name):
+            continue  # an entry point of another translation unit
         f = getattr(L, name)
         f.restype = C.c_int
         f.argtypes = args
     L.hbheap_version.restype = C.c_char_p
     L.hbheap_version.argtypes = []
     _lib = L
+    _libs[_path] = L
     return L
+
+
+def hb_fuzz_set(seed: int, most_sleeps: int = 32):
+    _check("hb_fuzz_set", lib().hb_fuzz_set(seed, most_sleeps))
 
 
 def _check(fn: str, rc: int):

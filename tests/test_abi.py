@@ -107,3 +107,20 @@ def test_serve_rejects_bad_arguments(L):
     assert L.serve_export(None, 0, 1, None, None) == hb.E_INVAL
     v = C.c_uint64()
     assert L.heap_chunks_in_use(None, C.byref(v), None) == hb.E_INVAL
+
+
+def test_normal_build_has_no_fuzz_points(L):
+    """Schedule fuzzing exists only in the test build (libhbheap_fuzz.so):
+    the normal library refuses it, with no GPU call."""
+    assert L.hb_fuzz_set(1, 8) == hb.E_UNSUP
+
+
+def test_fuzz_build_exports_the_allocator():
+    """The test build carries the allocator's entry points and the setter."""
+    import os
+    if not os.path.exists(hb.FUZZ_LIB_PATH):
+        pytest.fail(f"{hb.FUZZ_LIB_PATH} is missing: build it with __graft_entry__.build()")
+    F = C.CDLL(hb.FUZZ_LIB_PATH)
+    for name in ("heap_create_ex", "heap_alloc_batch", "heap_free_batch", "heap_trim", "heap_snapshot",
+                 "heap_pattern_write", "heap_pattern_check", "hb_fuzz_set"):
+        assert hasattr(F, name), name
