@@ -97,6 +97,10 @@ def parse(argv=None):
                          "default run stops at 2 KiB)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-host-malloc", action="store_true",
+                    help="skip the host C library malloc/free context figure")
+    ap.add_argument("--host-malloc-iters", type=int, default=3,
+                    help="rounds per size of the host malloc/free context figure (the first is not counted)")
     ap.add_argument("--sizes", type=str, default="", help="comma list overriding the 16..8192 sweep")
     ap.add_argument("--copy-probe", type=int, default=0, help="only run an HBM copy of this many bytes")
     ap.add_argument("--no-growth", action="store_true", help="skip the growth line (graph replay, autotuner)")
@@ -233,6 +237,10 @@ def compact(d: dict) -> dict:
         }
     cpu = d.get("cpu_baseline")
     out["cpu_baseline"] = ({k: cpu[k] for k in ("value", "unit", "cores", "kind", "sample")} if cpu else None)
+    hm = d.get("host_malloc_context")
+    if hm:
+        out["host_malloc_context"] = {"value": r(hm["value"]), "threads": hm["threads"], "failed": hm["failed"],
+                                      "cpu_model": hm["cpu_model"]}
     plain = d.get("plain")
     out["vs_plain"] = r(d.get("vs_plain"))
     if plain:
@@ -759,6 +767,28 @@ def main():
                          f"between sizes) through the sequential oracle, {t_cpu:.1f} s",
                "cpu_model": _cpu_model(), "host_cores_available": os.cpu_count()}
 
+    # ---------------- context: the host C library's malloc/free, all host threads ----------------
+    host_malloc = None
+    if not args.no_host_malloc:
+        threads = max(1, min(16, os.cpu_count() or 1))
+        iters = max(2, args.host_malloc_iters)
+        secs, failed = hb.hb_host_malloc_sweep(sizes_list, n, iters, threads)
+        later = secs[:, 1:]
+        host_malloc = {
+            "value": 2.0 * n * later.size / float(later.sum()),
+            "unit": "ops/s",
+            "threads": threads,
+            "kind": "host C library malloc/free",
+            "sample": f"{len(sizes_list)} sizes x {iters} rounds of 2^20 malloc then 2^20 free split over "
+                      f"{threads} threads; value over rounds 2..{iters}",
+            "per_size_ops_per_s": {str(sz): 2.0 * n * (iters - 1) / float(later[i].sum())
+                                   for i, sz in enumerate(sizes_list)},
+            "failed": failed,
+            "cpu_model": _cpu_model(),
+            "host_cores_available": os.cpu_count(),
+        }
+        log(f"host malloc/free: {host_malloc['value'] / 1e6:.1f} M ops/s on {threads} threads")
+
     paper = None if args.no_paper_sweeps else bench_paper_sweeps(hb, inputs, torch, args, ev, log)
     growth = None if args.no_growth else bench_growth(hb, inputs, torch, args, ev, log)
     serve = None if args.no_serve else bench_serve(hb, inputs, torch, args, log)
@@ -803,6 +833,7 @@ def main():
         "vs_plain": (plain["ours_same_sizes"] / plain["value"])
         if plain and plain["value"] and plain["ours_same_sizes"] else None,
         "cpu_baseline": cpu,
+        "host_malloc_context": host_malloc,
         "paper_sweeps": paper,
         "growth": growth,
         "serving": serve,

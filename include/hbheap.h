@@ -252,6 +252,17 @@ int hb_stream_copy(void* dst, const void* src, size_t bytes, hipStream_t stream)
  * HBHEAP_E_UNSUP and has no fuzz points.  Errors: HBHEAP_E_HIP. */
 int hb_fuzz_set(uint32_t seed, uint32_t most_sleeps);
 
+/* Context figure (host code, no GPU): the host C library's malloc/free over
+ * the device sweep's request streams.  For each of n_sizes sizes and each
+ * of `iterations` rounds, `threads` host threads split `requests`
+ * allocations of that size, wait for each other, then free them all;
+ * seconds[size * iterations + round] receives the round's wall time (both
+ * phases), *failed the number of NULL answers.  Errors: HBHEAP_E_INVAL
+ * (NULL outputs, zero sizes/iterations/threads, threads > 1024),
+ * HBHEAP_E_NOMEM. */
+int hb_host_malloc_sweep(const uint64_t* sizes, uint32_t n_sizes, uint64_t requests, uint32_t iterations,
+                         uint32_t threads, double* seconds, uint64_t* failed);
+
 /* Baseline: the runtime's own per-thread device malloc / free.
  * hb_plain_set_heap sets the device malloc heap limit (call before use). */
 int hb_plain_set_heap(size_t bytes);

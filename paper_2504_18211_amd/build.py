@@ -9,7 +9,8 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libhbheap.so")
-SOURCES = ["csrc/hbheap.hip", "csrc/growth.hip", "csrc/serve.hip", "csrc/plain_baseline.hip"]
+SOURCES = ["csrc/hbheap.hip", "csrc/growth.hip", "csrc/serve.hip", "csrc/plain_baseline.hip",
+           "csrc/host_malloc_baseline.cpp"]
 # the test build with schedule fuzzing: the allocator's translation unit only
 FUZZ_LIB = os.path.join(HERE, "libhbheap_fuzz.so")
 FUZZ_SOURCES = ["csrc/hbheap.hip"]
@@ -54,7 +55,7 @@ def build(verbose: bool = False) -> str:
     library and its schedule-fuzzing test build; it always recompiles."""
     from concurrent.futures import ThreadPoolExecutor
     os.makedirs(OBJ_DIR, exist_ok=True)
-    objs = [os.path.join(OBJ_DIR, os.path.basename(s).replace(".hip", ".o")) for s in SOURCES]
+    objs = [os.path.join(OBJ_DIR, os.path.splitext(os.path.basename(s))[0] + ".o") for s in SOURCES]
     fobjs = [os.path.join(OBJ_DIR, os.path.basename(s).replace(".hip", "_fuzz.o")) for s in FUZZ_SOURCES]
     jobs = [compile_command(s, o) for s, o in zip(SOURCES, objs)]
     jobs += [compile_command(s, o, ("HBHEAP_FUZZ=1",)) for s, o in zip(FUZZ_SOURCES, fobjs)]

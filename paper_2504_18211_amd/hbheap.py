@@ -34,7 +34,7 @@ EXPORTS = [
     "growth_create", "growth_destroy", "growth_step", "growth_graph_launch", "growth_release", "growth_export",
     "growth_launch_shape", "growth_autotune",
     "serve_create", "serve_destroy", "serve_run", "serve_export", "heap_chunks_in_use",
-    "heap_chunks_in_use_noalloc", "hb_fuzz_set",
+    "heap_chunks_in_use_noalloc", "hb_fuzz_set", "hb_host_malloc_sweep",
 ]
 SERVE_OK, SERVE_FREE_DOUBLE, SERVE_FREE_INVAL, SERVE_FREE_NULL, SERVE_ALLOC_NULL = 0, 1, 2, 3, 4
 
@@ -152,6 +152,7 @@ def lib():
         "heap_chunks_in_use": [vp, C.POINTER(C.c_uint64), vp],
         "heap_chunks_in_use_noalloc": [vp, vp, vp],
         "hb_fuzz_set": [u32, u32],
+        "hb_host_malloc_sweep": [vp, u32, C.c_uint64, u32, u32, vp, C.POINTER(C.c_uint64)],
     }
     for name, args in sig.items():
         if _path == FUZZ_LIB_PATH and not hasattr(L, name):
@@ -164,6 +165,17 @@ def lib():
     _lib = L
     _libs[_path] = L
     return L
+
+
+def hb_host_malloc_sweep(sizes, requests: int, iterations: int, threads: int):
+    """Host malloc/free rounds (no GPU): returns (seconds[n_sizes, iterations], failed)."""
+    import numpy as np
+    sz = np.ascontiguousarray(sizes, dtype=np.uint64)
+    secs = np.zeros((len(sz), iterations), dtype=np.float64)
+    failed = C.c_uint64()
+    _check("hb_host_malloc_sweep", lib().hb_host_malloc_sweep(sz.ctypes.data, len(sz), requests, iterations, threads,
+                                                              secs.ctypes.data, C.byref(failed)))
+    return secs, int(failed.value)
 
 
 def hb_fuzz_set(seed: int, most_sleeps: int = 32):

@@ -124,3 +124,16 @@ def test_fuzz_build_exports_the_allocator():
     for name in ("heap_create_ex", "heap_alloc_batch", "heap_free_batch", "heap_trim", "heap_snapshot",
                  "heap_pattern_write", "heap_pattern_check", "hb_fuzz_set"):
         assert hasattr(F, name), name
+
+
+def test_host_malloc_sweep_runs_on_the_host(L):
+    """The host malloc/free context figure needs no GPU: rounds are timed,
+    nothing fails, and bad arguments are refused."""
+    secs, failed = hb.hb_host_malloc_sweep([16, 4096], 1 << 12, 2, 2)
+    assert secs.shape == (2, 2) and (secs > 0).all() and failed == 0
+    out = (C.c_double * 2)()
+    f = C.c_uint64()
+    sizes = (C.c_uint64 * 1)(16)
+    assert L.hb_host_malloc_sweep(sizes, 1, 16, 2, 0, out, C.byref(f)) == hb.E_INVAL   # no threads
+    assert L.hb_host_malloc_sweep(None, 1, 16, 2, 1, out, C.byref(f)) == hb.E_INVAL
+    assert L.hb_host_malloc_sweep(sizes, 1, 16, 0, 1, out, C.byref(f)) == hb.E_INVAL  # no rounds
