@@ -134,39 +134,57 @@ __device__ __forceinline__ uint64_t perm64(uint64_t v, uint32_t src)
 }
 
 /* Runs of adjacent active lanes (inside aligned segments of `seg` lanes)
- * that apply bits to the same bitmask word `key`.  The bits of a run are
- * OR-ed by a segmented inclusive scan over the lanes (six permute steps,
- * whatever the number of runs); the run's last lane then issues the run's
- * single atomic.  incl: bits of the run's lanes up to this one (the whole
- * run at the tail); prior: bits of the run's lower lanes; tail: the run's
- * last lane. */
+ * that apply bits to the same bitmask word `key` (`bit`: one set bit per
+ * lane).  The run's last lane issues the run's single atomic.  incl: bits of
+ * the run's lanes up to this one (the whole run at the tail); prior: bits of
+ * the run's lower lanes; tail: the run's last lane.  When every run holds
+ * consecutive bits in lane order (pages taken or freed in ring order: the
+ * common case), each lane's bits are the range from its run's first bit to
+ * its own; otherwise they are OR-ed by a segmented inclusive scan over the
+ * lanes (six permute steps, whatever the number of runs). */
 struct Run {
     uint64_t incl;
     uint64_t prior;
     uint32_t tail;
 };
+/* Bits lo..hi (lo <= hi <= 63). */
+__device__ __forceinline__ uint64_t bit_range(uint32_t lo, uint32_t hi)
+{
+    const uint64_t upto = hi == 63u ? ~0ull : ((2ull << hi) - 1ull);
+    return upto & ~((1ull << lo) - 1ull);
+}
 __device__ __forceinline__ Run run_combine(bool have, uint64_t key, uint64_t bit, uint32_t seg)
 {
     const uint32_t me = lane();
+    const uint32_t prev = me ? me - 1u : 0u;
     const uint64_t todo = __ballot(have);
-    const uint64_t pkey = perm64(key, me ? me - 1u : 0u);
-    const bool same = have && (me & (seg - 1u)) != 0u && ((todo >> (me - 1u)) & 1ull) && pkey == key;
+    const uint32_t b = have ? (uint32_t)__builtin_ctzll(bit | (1ull << 63)) : 0u;
+    const uint64_t pkey = perm64(key, prev);
+    const uint32_t pb = perm32(b, prev);
+    const bool same = have && (me & (seg - 1u)) != 0u && ((todo >> prev) & 1ull) && pkey == key;
     const uint64_t same_m = __ballot(same);
     const uint64_t heads = todo & ~same_m;
     const uint64_t tails = todo & ~(same_m >> 1);
     const uint64_t upto = me == 63u ? ~0ull : ((2ull << me) - 1ull);
     const uint32_t start = have ? 63u - (uint32_t)__builtin_clzll(heads & upto) : me;
+    Run r;
+    r.tail = have ? ctz64(tails & ~((1ull << me) - 1ull)) : me;
+    if (__ballot(same && b != pb + 1u) == 0) {
+        /* every run is consecutive bits: lanes start..me hold bits bs..b */
+        const uint32_t bs = perm32(b, start);
+        r.incl = have ? bit_range(bs, b) : 0ull;
+        r.prior = same ? bit_range(bs, b - 1u) : 0ull;
+        return r;
+    }
     uint64_t acc = have ? bit : 0ull;
 #pragma unroll
     for (uint32_t d = 1; d < 64u; d <<= 1) {
         const uint64_t v = perm64(acc, me >= d ? me - d : me);
         if (have && me >= start + d) acc |= v;
     }
-    Run r;
     r.incl = acc;
-    const uint64_t pa = perm64(acc, me ? me - 1u : 0u);
+    const uint64_t pa = perm64(acc, prev);
     r.prior = same ? pa : 0ull;
-    r.tail = have ? ctz64(tails & ~((1ull << me) - 1ull)) : me;
     return r;
 }
 
@@ -2086,6 +2104,55 @@ __device__ __forceinline__ void malloc_rows(const hbheap_dev_t& h, Rows<R>& q, c
     const uint32_t arank = rank_in(act);
     uint64_t* stage = stage_for_wave();
     Tally tl;
+    if constexpr (R > 1) {
+        /* Every request of a full wave in one class (a batch of one size,
+         * aggregated over the whole wave): one group, ranked rows first,
+         * with no grouping loop; lane 0 acts for it.  Its first pass takes
+         * published entries on the home shard without a hold, as below. */
+        if (!HBHEAP_VARIANT_LISTS_CHUNKS(h.variant) && h.width >= 64u && act == ~0ull) {
+            const int32_t k0 = __builtin_amdgcn_readfirstlane(has[0] ? class_of(h, n[0]) : -1);
+            bool same = k0 >= 0;
+#pragma unroll
+            for (uint32_t r = 0; r < R; ++r) same = same && has[r] && class_of(h, n[r]) == k0;
+            if (__ballot(!same) == 0) {
+                constexpr uint32_t tot = 64u * R;
+#pragma unroll
+                for (uint32_t r = 0; r < R; ++r) {
+                    q.k[r] = k0;
+                    q.gid[r] = 0;
+                    q.rank[r] = 64u * r + me;
+                    q.off[r] = kNoPage;
+                }
+                uint32_t got = 0, h0 = 0;
+                if (me == 0) {
+                    const Ring Q = ring_of(h, home, (uint32_t)k0);
+                    got = ring_take_published(Q, tot, tl);
+                    if (got) {
+                        fuzz_point(22);
+                        h0 = a_add32(Q.head, got);
+                        tl.headtail += 1;
+                    }
+                }
+                got = (uint32_t)__builtin_amdgcn_readfirstlane((int)got);
+                h0 = (uint32_t)__builtin_amdgcn_readfirstlane((int)h0);
+                bool tk[R];
+                uint32_t pos[R], kr[R], v[R];
+#pragma unroll
+                for (uint32_t r = 0; r < R; ++r) {
+                    tk[r] = q.rank[r] < got;
+                    pos[r] = h0 + q.rank[r];
+                    kr[r] = (uint32_t)k0;
+                }
+                take_rows<R>(h, home, kr, tk, pos, v, tl);
+                fuzz_point(23);
+#pragma unroll
+                for (uint32_t r = 0; r < R; ++r) page_took(h, home, 4u + (uint32_t)k0, v[r], q.off[r], tl);
+                if (got < tot) alloc_group<R>(h, q, 0, (uint32_t)k0, tot, stage, home, home_dry, got, true, share, tl);
+                tally_flush(h, tl);
+                return;
+            }
+        }
+    }
     /* groups: requests of one class (inside aligned segments of `width`
      * lanes), ranked rows first; the g-th active lane keeps group g's class
      * and size */

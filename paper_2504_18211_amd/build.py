@@ -29,6 +29,10 @@ FLAGS = [
     # packed fp32 ops off: the allocator has no fp32 arithmetic, and this
     # keeps the compiler from emitting v_pk_*_f32 anywhere in the library
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # no wave-level rewriting of atomics: the library issues each queue-word
+    # atomic from one lane already, and the rewrite (a loop over the active
+    # lanes around every such atomic) only adds instructions
+    "-mllvm", "-amdgpu-atomic-optimizer-strategy=None",
     "-Wall", "-I", os.path.join(ROOT, "include"),
 ]
 OBJ_DIR = os.path.join(ROOT, "_build")

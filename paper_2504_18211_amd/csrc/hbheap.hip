@@ -144,18 +144,23 @@ __global__ void __launch_bounds__(kBatchBlock) HBHEAP_ALLOC_ATTR k_alloc_batch(h
     h.variant = V;
     if (Counted) h.flags |= HBHEAP_FLAG_STATS;
     else h.flags &= ~HBHEAP_FLAG_STATS;
-    /* home shard: the linear wave index, spread evenly over the shards; its
-     * pool hint is loaded before the sizes so that the loads are in flight
-     * together (the empty asm keeps the compiler from sinking it) */
-    const uint32_t home = (uint32_t)(wave % h.n_shards);
+    /* home shard: the linear wave index, spread evenly over the shards (a
+     * wave-uniform 32-bit remainder, taken on the scalar unit); its pool hint
+     * is loaded before the sizes so that the loads are in flight together
+     * (the empty asm keeps the compiler from sinking it) */
+    const uint32_t wv = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)wave);
+    const uint32_t home = wv % h.n_shards;
     const bool dry = home_pool_dry(h, home);
     __asm__ volatile("" ::: "memory");
+    /* requests past n load the wave's first size (index wave * 64 R < n, in
+     * bounds) and carry no request: no branch per row */
     uint64_t sz[R];
     bool has[R];
 #pragma unroll
     for (uint32_t r = 0; r < R; ++r) {
         has[r] = base + 64u * r < n;
-        sz[r] = has[r] ? sizes[base + 64u * r] : 0;
+        sz[r] = sizes[has[r] ? base + 64u * r : wave * 64u * R];
+        sz[r] = has[r] ? sz[r] : 0;
     }
     Rows<R> q;
     malloc_rows<R>(h, q, sz, has, home, dry, share);
