@@ -2263,7 +2263,7 @@ __device__ __forceinline__ uint32_t free_wave(const hbheap_dev_t& h, void* p, ui
     uint32_t status = kFreeNull;
     bool enq = false, cand = false;
     Tally tl;
-    uint32_t val = 0, key = 0, k = 0;
+    uint32_t val = 0, key = 0, k = 0, jv = 0;
     uint64_t c = 0, widx = 0, bit = 0, o = 0;
     bool inr = false;
     if (p != nullptr) {
@@ -2284,7 +2284,8 @@ __device__ __forceinline__ uint32_t free_wave(const hbheap_dev_t& h, void* p, ui
                 const uint32_t pg = (uint32_t)((o & ((1ull << h.log2_chunk) - 1ull)) >> shift);
                 widx = bit_index(h, c, pg >> 6);
                 bit = 1ull << (pg & 63u);
-                key = shard_of_chunk(h, c) * h.n_classes + k;
+                jv = shard_of_chunk(h, c);
+                key = jv * h.n_classes + k;
                 cand = true;
             }
         }
@@ -2393,7 +2394,7 @@ __device__ __forceinline__ uint32_t free_wave(const hbheap_dev_t& h, void* p, ui
         pend &= ~grp;
     }
     if ((pend >> me) & 1ull) {
-        const Ring R = ring_of(h, key / h.n_classes, key % h.n_classes);
+        const Ring R = ring_of(h, jv, k);
         const uint32_t t0 = a_add32(R.tail, 1u);
         tl.headtail += 1;
         if (eager(h)) list_or_retire(h, val, k, 1u << (h.log2_chunk - 4u - k), t0, 0u, tl);
@@ -2550,12 +2551,48 @@ __device__ __forceinline__ void free_rows(const hbheap_dev_t& h, void* const (&p
     uint32_t jr[R], kr[R];
 #pragma unroll
     for (uint32_t r = 0; r < R; ++r) {
-        jr[r] = key[r] / h.n_classes;
-        kr[r] = key[r] % h.n_classes;
+        jr[r] = cand[r] ? shard_of_chunk(h, c[r]) : 0u;
+        kr[r] = cand[r] ? k[r] : 0u;
+    }
+    {
+        /* every request of a full wave enqueues into one queue (frees of
+         * one size from one shard): one group, ranked rows first, with no
+         * grouping loop; lane 0 acts for it */
+        const uint32_t k0 = (uint32_t)__builtin_amdgcn_readfirstlane((int)key[0]);
+        bool one = exec_mask() == ~0ull;
+#pragma unroll
+        for (uint32_t r = 0; r < R; ++r) one = one && enq[r] && key[r] == k0;
+        if (__ballot(!one) == 0) {
+            const uint32_t jj = (uint32_t)__builtin_amdgcn_readfirstlane((int)jr[0]);
+            const uint32_t kc = (uint32_t)__builtin_amdgcn_readfirstlane((int)kr[0]);
+            const Ring Q = ring_of(h, jj, kc);
+            uint32_t t0 = 0;
+            fuzz_point(43);
+            if (me == 0) {
+                t0 = a_add32(Q.tail, 64u * R);
+                tl.headtail += 1;
+            }
+            t0 = (uint32_t)__builtin_amdgcn_readfirstlane((int)t0);
+            uint32_t ju[R], ku[R], pos[R];
+#pragma unroll
+            for (uint32_t r = 0; r < R; ++r) {
+                ju[r] = jj;
+                ku[r] = kc;
+                pos[r] = t0 + 64u * r + me;
+            }
+            put_rows<R>(h, ju, ku, enq, pos, val, tl);
+            fuzz_point(44);
+            if (me == 0) {
+                a_add64(Q.state, 64ull * R);
+                tl.state += 1;
+            }
+            tally_flush(h, tl);
+            return;
+        }
     }
     bool first_group = true;
     for (;;) {
-        uint32_t kk = 0, leader = 0;
+        uint32_t kk = 0, leader = 0, jj = 0, kc = 0;
         bool found = false;
 #pragma unroll
         for (uint32_t r = 0; r < R; ++r) {
@@ -2563,6 +2600,8 @@ __device__ __forceinline__ void free_rows(const hbheap_dev_t& h, void* const (&p
             if (!found && m) {
                 leader = ctz64(m);
                 kk = bcast(key[r], leader);
+                jj = bcast(jr[r], leader);
+                kc = bcast(kr[r], leader);
                 found = true;
             }
         }
@@ -2578,7 +2617,7 @@ __device__ __forceinline__ void free_rows(const hbheap_dev_t& h, void* const (&p
         }
         if (!first_group && nn < 4u) break;
         first_group = false;
-        const Ring Q = ring_of(h, kk / h.n_classes, kk % h.n_classes);
+        const Ring Q = ring_of(h, jj, kc);
         uint32_t t0 = 0;
         fuzz_point(43);
         if (me == leader) {
