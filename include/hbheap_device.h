@@ -1377,41 +1377,45 @@ __device__ __forceinline__ void take_rows(const hbheap_dev_t& h, uint32_t j, con
         if (cl[r] != kEmpty) seg_close(h, ring_of(h, j, kr[r]), pos[r], seg[r], cl[r], tl);
 }
 
+/* Shared-budget variants: a shard's committed-pages word holds the pages
+ * its classes own (bits 0..39) and, above them, the number of refills whose
+ * reservation is in flight (added, excess not yet given back). */
+constexpr uint32_t kPendShift = 40;
+constexpr uint64_t kPendOne = 1ull << kPendShift;
+constexpr uint64_t kPagesMask = kPendOne - 1ull;
+
 /* Page variants: reserve room for up to m more chunks of class k in shard j
- * under the cap (the page variant: the class's own counter, add and give
- * back the excess; the shared-budget variants: compare-and-swap, so that the
- * budget the classes share never reads above the truth).  Returns the
- * number reserved; unused reservations are returned by the caller only when
- * the pool ran dry. */
+ * under the cap, by adding first and giving back what passed it.  Returns
+ * the number reserved; unused reservations are returned by the caller only
+ * when the pool ran dry.
+ *  - The page variant keeps one counter per class.  A reader can see it
+ *    above the truth only while some adder's excess is still out, and that
+ *    adder saw the counter below the cap and took all the room left: so a
+ *    reading at or above the cap means no room in truth, and one below it
+ *    carries no excess and is exact.
+ *  - The shared-budget variants keep one page budget for all classes of a
+ *    shard, and an excess of one class could hide a remainder that a class
+ *    with fewer pages per chunk could still use.  So each adder also counts
+ *    itself in flight in the same atomic and leaves with its give-back: a
+ *    reading with nobody in flight is exact, and readers that need the truth
+ *    (the exhaustion scan) treat one with adders in flight as undecided.
+ * (A compare-and-swap loop gives exact answers too, but with every
+ * refilling wave of a shard on one word it retires one success per round
+ * trip.) */
 __device__ __forceinline__ uint32_t owned_reserve(const hbheap_dev_t& h, uint32_t j, uint32_t k, uint32_t lppc, uint32_t m,
                                                   Tally& tl)
 {
     if (HBHEAP_VARIANT_SHARED_PAGES(h.variant)) {
-        /* the classes of a shard share one page budget: the store's segments
-         * less a few per queue (positions span at most the pages a queue's
-         * class owns, plus partial segments at both ends) */
         uint64_t* cm = committed_of(h, j);
-        uint64_t c = a_load64(cm);
-        for (;;) {
-            const uint64_t room = h.vbudget > c ? (h.vbudget - c) >> lppc : 0ull;
-            if (room == 0) return 0;
-            const uint32_t allow = room < m ? (uint32_t)room : m;
-            tl.pool += 1;
-            if (__hip_atomic_compare_exchange_strong(cm, &c, c + ((uint64_t)allow << lppc), __ATOMIC_RELAXED,
-                                                     __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
-                a_add64(owned_of(h, j, k), allow);
-                return allow;
-            }
-        }
+        const uint64_t want = (uint64_t)m << lppc;
+        const uint64_t c = a_add64(cm, want + kPendOne) & kPagesMask;
+        uint32_t allow = m;
+        if (c + want > h.vbudget) allow = c < h.vbudget ? (uint32_t)((h.vbudget - c) >> lppc) : 0u;
+        a_add64(cm, (uint64_t)0 - (want - ((uint64_t)allow << lppc)) - kPendOne);
+        tl.pool += 2;
+        if (allow) a_add64(owned_of(h, j, k), allow);
+        return allow;
     }
-    /* One class's own counter: add first, then give back what passed the
-     * cap.  A reader can see the counter above the truth only while some
-     * adder's excess is still out, and that adder saw the counter below the
-     * cap and took all the room left: so a counter read at or above the cap
-     * means no room in truth, and one read below it carries no excess and is
-     * exact.  (A compare-and-swap loop gives the same answers, but with
-     * every refilling wave of a shard on one word it retires one success per
-     * round trip.) */
     uint64_t* owned = owned_of(h, j, k);
     const uint64_t maxc = page_max_chunks(h, lppc);
     const uint64_t o = a_add64(owned, m);
@@ -1423,17 +1427,25 @@ __device__ __forceinline__ uint32_t owned_reserve(const hbheap_dev_t& h, uint32_
     return allow;
 }
 
-/* Does shard j show entries or room to grow for class k?  (Pool and owned
+/* Page variants: may class k of shard j take another chunk?  0: no (exact at
+ * the read), 1: yes, 2: undecided (shared budget with refills in flight). */
+__device__ __forceinline__ uint32_t class_room(const hbheap_dev_t& h, uint32_t j, uint32_t k, uint32_t lppc)
+{
+    if (h.variant == HBHEAP_VARIANT_PAGE) return a_load64(owned_of(h, j, k)) < page_max_chunks(h, lppc) ? 1u : 0u;
+    if (HBHEAP_VARIANT_SHARED_PAGES(h.variant)) {
+        const uint64_t c = a_load64(committed_of(h, j));
+        if (c >> kPendShift) return 2u;
+        return (c & kPagesMask) + (1ull << lppc) <= h.vbudget ? 1u : 0u;
+    }
+    return 1u;
+}
+/* Does shard j show entries or room to grow for class k?  (Pool and room
  * counter read before the state word.)  A wave skips a shard that shows
  * neither instead of taking a hold on it, so waves that find nothing do not
- * keep the shard's hold count busy. */
-/* Page variants: may class k of shard j take another chunk? */
+ * keep the shard's hold count busy; undecided room counts as room. */
 __device__ __forceinline__ bool class_has_room(const hbheap_dev_t& h, uint32_t j, uint32_t k, uint32_t lppc)
 {
-    if (h.variant == HBHEAP_VARIANT_PAGE) return a_load64(owned_of(h, j, k)) < page_max_chunks(h, lppc);
-    if (HBHEAP_VARIANT_SHARED_PAGES(h.variant))
-        return a_load64(committed_of(h, j)) + (1ull << lppc) <= h.vbudget;
-    return true;
+    return class_room(h, j, k, lppc) != 0u;
 }
 __device__ __forceinline__ bool shard_has_something(const hbheap_dev_t& h, uint32_t j, uint32_t k, uint32_t lppc)
 {
@@ -1469,11 +1481,18 @@ __device__ __forceinline__ uint32_t scan_shards(const hbheap_dev_t& h, const Gro
              * flight (a free publishing, or a taker that over-asked without
              * a hold and has not yet given the excess back, while the count
              * can hide entries published meanwhile).  The room counter may
-             * be read in any order: it only shrinks when the pool runs dry. */
+             * be read in any order: a reading of no room is true when read
+             * and stays true until the pool runs dry (the only give-back of
+             * real room before a trim); an undecided one (refills in flight
+             * on a shared budget) counts as an operation in flight. */
             uint64_t* pb = pool_block(h, j);
             const uint64_t bump = a_load64(pb);
             bool grow = eager(h) ? state_count(bump) > 0 : bump < ((const uint32_t*)pb)[2];
-            if (grow) grow = class_has_room(h, j, g.k, g.lppc);
+            uint32_t room = 1u;
+            if (grow) {
+                room = class_room(h, j, g.k, g.lppc);
+                grow = room == 1u;
+            }
             const Ring R = ring_of(h, j, g.k);
             fuzz_point(35);
             const uint64_t st = a_load64(R.state + zero_after((uint32_t)bump));
@@ -1481,7 +1500,7 @@ __device__ __forceinline__ uint32_t scan_shards(const hbheap_dev_t& h, const Gro
             const uint32_t hd = a_load32(R.head + zero_after((uint32_t)st));
             fuzz_point(37);
             const uint32_t tl_ = a_load32(R.tail + zero_after(hd));
-            hold = (st >> 32) != 0 || hd != tl_;
+            hold = (st >> 32) != 0 || hd != tl_ || room == 2u;
             avail = state_count(st) > 0 || grow;
         }
         const uint64_t av = __ballot(avail);
