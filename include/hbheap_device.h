@@ -1229,17 +1229,24 @@ __device__ __forceinline__ uint32_t claim_pages(const hbheap_dev_t& h, uint32_t 
     return got;
 }
 
-/* LDS staging: 64 page offsets per wave, for up to 16 waves per block. */
+/* LDS staging of the chunk variants' page offsets: 64 per wave for one
+ * request per lane (up to 16 waves per block), 64 R per wave for R requests
+ * per lane (the batch kernels: blocks of at most kRowsBlockWaves waves). */
+constexpr uint32_t kRowsBlockWaves = 4;
 static __shared__ uint64_t hbheap_stage_lds[kMaxWavesPerBlock * 64];
+static __shared__ uint64_t hbheap_stage_lds4[kRowsBlockWaves * 64 * 4];
 
 /* Per-workgroup out-of-memory proof states of a class (batch launches). */
 constexpr uint32_t kShareFree = 0, kShareProving = 1, kShareProved = 2;
 constexpr uint32_t kShareSlots = 16; /* >= classes of any chunk size */
 
+template <uint32_t R = 1>
 __device__ __forceinline__ uint64_t* stage_for_wave()
 {
+    static_assert(R == 1 || R == 4, "rows per lane: 1 or 4");
     const uint32_t lin = threadIdx.x + blockDim.x * (threadIdx.y + blockDim.y * threadIdx.z);
-    return hbheap_stage_lds + (lin >> 6) * 64u;
+    if constexpr (R == 1) return hbheap_stage_lds + (lin >> 6) * 64u;
+    return hbheap_stage_lds4 + (lin >> 6) * 64u * R;
 }
 
 /* ---------------- one class group of one wave ---------------- */
@@ -1517,11 +1524,16 @@ __device__ __forceinline__ uint32_t scan_shards(const hbheap_dev_t& h, const Gro
 /* Chunk variant, shard j: serve up to `need` pages of the group's class,
  * writing their byte offsets to stage[served..).  Returns when need is met
  * or when shard j's queue and pool could not supply more. */
+template <uint32_t RW>
 __device__ __forceinline__ void chunk_serve_shard(const hbheap_dev_t& h, const Group& g, uint32_t j, uint32_t& need,
                                                   uint32_t& served, uint64_t* stage, bool look_first, Tally& tl)
 {
     const Ring R = ring_of(h, j, g.k);
-    const bool ev = eager(h);
+    /* several requests per lane (RW > 1) only without eager retirement (the
+     * library launches those heaps one request per lane) */
+    const bool ev = RW == 1 && eager(h);
+    /* a group's need is at most 64 RW: scans of per-lane page counts */
+    constexpr int kBits = RW == 1 ? 7 : 9;
     /* look before reserving, except on a first pass the caller vouches for
      * (a home shard whose pool still had chunks, or a shard a scan just found
      * something in): there an empty queue costs only a hold taken and given
@@ -1605,7 +1617,7 @@ __device__ __forceinline__ void chunk_serve_shard(const hbheap_dev_t& h, const G
         if (R.segs) seg_count_taken(h, R, took_slot, h0 + g.arank, vseg, tl);
         const uint32_t vc = v > 0 ? ((uint32_t)v < need ? (uint32_t)v : need) : 0u;
         uint32_t tot;
-        const uint32_t pre = excl_scan<7>(vc, &tot);
+        const uint32_t pre = excl_scan<kBits>(vc, &tot);
         const uint32_t t = pre < need ? ((need - pre) < vc ? (need - pre) : vc) : 0u;
 
         bool keep = false;
@@ -1624,7 +1636,7 @@ __device__ __forceinline__ void chunk_serve_shard(const hbheap_dev_t& h, const G
             }
         }
         uint32_t took;
-        const uint32_t tpre = excl_scan<7>(t, &took);
+        const uint32_t tpre = excl_scan<kBits>(t, &took);
         /* a pass that will not refill (its reservations cover the need, or
          * the queue gave every chunk asked for) puts its kept chunks back
          * and releases the queue before it claims its pages' bits, so other
@@ -1707,8 +1719,8 @@ __device__ __forceinline__ void chunk_serve_shard(const hbheap_dev_t& h, const G
                 }
                 if (g.arank < gm) set_class(h, mine, g.k, tl);
                 wait_own_accesses();
-            } else if (g.arank < gm) {
-                set_class(h, h.pool_ids[first + g.arank], g.k, tl);
+            } else {
+                for (uint32_t i = g.arank; i < gm; i += g.nact) set_class(h, h.pool_ids[first + i], g.k, tl);
             }
             const uint32_t cap = gm << g.lppc;
             const uint32_t r = cap < need ? cap : need;
@@ -1718,9 +1730,11 @@ __device__ __forceinline__ void chunk_serve_shard(const hbheap_dev_t& h, const G
                 if (g.arank < r)
                     stage[served + g.arank] =
                         ((uint64_t)ci << h.log2_chunk) + ((uint64_t)(g.arank & (g.ppc - 1u)) << g.shift);
-            } else if (g.arank < r) {
-                const uint32_t ci = h.pool_ids[first + (g.arank >> g.lppc)];
-                stage[served + g.arank] = ((uint64_t)ci << h.log2_chunk) + ((uint64_t)(g.arank & (g.ppc - 1u)) << g.shift);
+            } else {
+                for (uint32_t i = g.arank; i < r; i += g.nact) {
+                    const uint32_t ci = h.pool_ids[first + (i >> g.lppc)];
+                    stage[served + i] = ((uint64_t)ci << h.log2_chunk) + ((uint64_t)(i & (g.ppc - 1u)) << g.shift);
+                }
             }
             if (cap > need) {
                 /* last chunk keeps pages [u, ppc): set their bits, publish it */
@@ -1969,17 +1983,17 @@ __device__ __forceinline__ void page_serve_shard(const hbheap_dev_t& h, const Gr
  * first one (after home) that has entries or room to grow; give up only when
  * a scan finds every shard without entries, without room and without holds
  * in flight.  The group's requests receive their page offsets in q.off
- * (unchanged: kNoPage).  Chunk variants serve one row (R == 1). */
+ * (unchanged: kNoPage).  Chunk variants stage the group's offsets in LDS
+ * (64 R per wave) and hand them out by rank at the end. */
 template <uint32_t R>
 __device__ __forceinline__ void alloc_group(const hbheap_dev_t& h, Rows<R>& q, uint32_t id, uint32_t k, uint32_t tot,
                                             uint64_t* stage, uint32_t home, bool home_dry, uint32_t served0,
                                             bool home_tried, uint32_t* share, Tally& tl)
 {
     const Group g = make_group(h, k, id);
-    constexpr bool one_row = R == 1;
-    const bool chunk = one_row && HBHEAP_VARIANT_LISTS_CHUNKS(h.variant);
+    const bool chunk = HBHEAP_VARIANT_LISTS_CHUNKS(h.variant);
     if (chunk) {
-        stage[g.arank] = kNoPage;
+        for (uint32_t i = g.arank; i < tot; i += g.nact) stage[i] = kNoPage;
         wave_sync_lds();
     }
     /* ranks below served0 were served already (page variant: the wave's
@@ -1987,7 +2001,7 @@ __device__ __forceinline__ void alloc_group(const hbheap_dev_t& h, Rows<R>& q, u
      * home_tried makes the home shard look before it reserves again) */
     uint32_t need = tot - served0, served = served0;
     const uint32_t S = h.n_shards;
-    if (chunk) chunk_serve_shard(h, g, home, need, served, stage, home_dry, tl);
+    if (chunk) chunk_serve_shard<R>(h, g, home, need, served, stage, home_dry, tl);
     else page_serve_shard<R>(h, g, q, home, need, served, home_dry && !home_tried, home_tried, tl);
     Backoff wb;
     bool timed_out = false;
@@ -2042,7 +2056,7 @@ __device__ __forceinline__ void alloc_group(const hbheap_dev_t& h, Rows<R>& q, u
         if (r < S) {
             const uint32_t j = home + r < S ? home + r : home + r - S;
             const uint32_t before = need;
-            if (chunk) chunk_serve_shard(h, g, j, need, served, stage, false, tl);
+            if (chunk) chunk_serve_shard<R>(h, g, j, need, served, stage, false, tl);
             else page_serve_shard<R>(h, g, q, j, need, served, false, false, tl);
             if (need < before) continue;
         }
@@ -2063,7 +2077,9 @@ __device__ __forceinline__ void alloc_group(const hbheap_dev_t& h, Rows<R>& q, u
     }
     if (chunk) {
         wave_sync_lds();
-        if (in_group(q, id, 0)) q.off[0] = stage[q.rank[0]];
+#pragma unroll
+        for (uint32_t r = 0; r < R; ++r)
+            if (in_group(q, id, r)) q.off[r] = stage[q.rank[r]];
         wave_sync_lds();
     }
 }
@@ -2089,16 +2105,16 @@ __device__ __forceinline__ bool home_pool_dry(const hbheap_dev_t& h, uint32_t ho
  * requests are grouped by class (inside aligned segments of `width` lanes)
  * and each group is served by queue operations of one lane for the whole
  * group.  q.off receives the page offsets.  With R > 1 every lane of the
- * wave must be active and the width at least 16 (the batch kernels see to
- * it); chunk variants, which stage pages in LDS 64 at a time, then serve
- * row after row. */
+ * wave must be active, the width at least 16 and the block at most
+ * kRowsBlockWaves waves (the batch kernels see to it); a chunk heap with
+ * eager retirement then serves row after row. */
 template <uint32_t R>
 __device__ __forceinline__ void malloc_rows(const hbheap_dev_t& h, Rows<R>& q, const uint64_t (&n)[R],
                                             const bool (&has)[R], uint32_t home_in, bool dry_in,
                                             uint32_t* share = nullptr)
 {
     if constexpr (R > 1) {
-        if (HBHEAP_VARIANT_LISTS_CHUNKS(h.variant) || h.width < 16u) {
+        if (h.width < 16u || (HBHEAP_VARIANT_LISTS_CHUNKS(h.variant) && eager(h))) {
 #pragma unroll
             for (uint32_t r = 0; r < R; ++r) {
                 Rows<1> one;
@@ -2121,7 +2137,7 @@ __device__ __forceinline__ void malloc_rows(const hbheap_dev_t& h, Rows<R>& q, c
     const uint32_t me = lane();
     const uint64_t act = exec_mask();
     const uint32_t arank = rank_in(act);
-    uint64_t* stage = stage_for_wave();
+    uint64_t* stage = stage_for_wave<R>();
     Tally tl;
     if constexpr (R > 1) {
         /* Every request of a full wave in one class (a batch of one size,

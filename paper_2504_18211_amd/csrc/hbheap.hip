@@ -819,12 +819,13 @@ void release(hbheap_heap* h)
 
 namespace {
 /* Batch launches: requests per lane R, one 256-lane block per 4 * 64 * R
- * requests.  R = the heap's rows for the page and virtualised-array page
- * variants; 1 for the others (chunk queues stage pages per wave 64 at a
- * time, and a virtualised list queue's takers walk its links row by row,
- * where more rows per wave measured slower). */
+ * requests.  R = the heap's rows for every variant but the virtualised-list
+ * page variant, whose takers walk its links row by row (more rows per wave
+ * measured slower there); the heap's rows are 1 for widths below 16 and
+ * for eager retirement. */
+static_assert(kBatchBlock / 64 <= hbheap::detail::kRowsBlockWaves, "LDS staging of the rows kernels");
 template <uint32_t V>
-constexpr bool rows_apply() { return V == HBHEAP_VARIANT_PAGE || V == HBHEAP_VARIANT_VA_PAGE; }
+constexpr bool rows_apply() { return V != HBHEAP_VARIANT_VL_PAGE; }
 template <bool C, uint32_t V, uint32_t R>
 void launch_alloc(const hbheap_heap* h, const size_t* sizes, void** ptrs, size_t n, hipStream_t stream)
 {
@@ -929,7 +930,7 @@ int heap_create_ex(size_t bytes, size_t chunk_bytes, const heap_config_t* cfg, h
     /* several requests per lane need every lane of a wave and at most 4
      * segments of lanes (so at most 52 groups of a wave) */
     h->rows = c.rows ? c.rows : 4u;
-    if (c.width < 16) h->rows = 1;
+    if (c.width < 16 || eager_retire) h->rows = 1;
     h->lay = make_layout(N, log2C, K, c.variant, bytes, S, log2_span, eager_retire);
     const Layout& L = h->lay;
     h->trim_blocks = (uint32_t)((N + kTrimBlock - 1) / kTrimBlock);
