@@ -1521,6 +1521,58 @@ __device__ __forceinline__ uint32_t scan_shards(const hbheap_dev_t& h, const Gro
     return S;
 }
 
+/* Wave-wide (chunk variants, a full wave): the helper of rank i (lane i)
+ * takes t free bits of its chunk c, lowest first, writing the pages' byte
+ * offsets to out[tpre .. tpre + t), as claim_pages does -- but with the
+ * (helper, word) pairs spread over the lanes, so that a helper whose pages
+ * span several bitmask words reads and clears them all in one round trip
+ * each instead of one word after another.  A lane reads its word, takes its
+ * share of the helper's t (the lowest set bits, words in order) with one
+ * atomicAnd and writes what it won; bits a concurrent claimer took first are
+ * looked for again by the helper alone (claim_pages).  Pairs that do not fit
+ * the wave fall back to claim_pages per helper. */
+__device__ __forceinline__ void claim_wave(const hbheap_dev_t& h, const Group& g, uint32_t nh, uint32_t c, uint32_t t,
+                                           uint32_t tpre, uint64_t* out, Tally& tl)
+{
+    const uint32_t nw = g.ppc >= 64u ? g.ppc >> 6 : 1u;
+    if (g.act != ~0ull || nh * nw > 64u) {
+        if (t) claim_pages(h, c, g.k, t, out + tpre, tl);
+        return;
+    }
+    const uint32_t me = g.me;
+    const uint32_t hi = me / nw, w = me % nw;  /* pair (helper hi, word w) */
+    const bool on = hi < nh;
+    const uint32_t ch = perm32(c, hi), th = perm32(t, hi), tph = perm32(tpre, hi);
+    const bool valid = on && th > 0u;
+    uint64_t* word = h.bits + bit_index(h, valid ? ch : 0u, w);
+    uint64_t x = 0;
+    if (valid) x = a_load64(word);
+    const uint32_t pop = valid ? (uint32_t)__popcll(x) : 0u;
+    uint32_t tot;
+    const uint32_t gp = excl_scan<7>(pop, &tot);
+    const uint32_t before = gp - perm32(gp, hi * nw); /* set bits of the helper's lower words */
+    const uint32_t q = valid && th > before ? (th - before < pop ? th - before : pop) : 0u;
+    uint64_t won = 0;
+    if (q) {
+        const uint64_t pick = lowest_bits(x, q);
+        won = a_and64(word, ~pick) & pick;
+        tl.spread += 1;
+    }
+    const uint32_t nwon = (uint32_t)__popcll(won);
+    const uint32_t gw = excl_scan<7>(nwon, &tot);
+    uint32_t idx = tph + (gw - perm32(gw, hi * nw));
+    const uint64_t cbase = (uint64_t)ch << h.log2_chunk;
+    while (won) {
+        const uint32_t b = ctz64(won);
+        won &= won - 1ull;
+        out[idx++] = cbase + ((uint64_t)(w * 64u + b) << g.shift);
+    }
+    /* helper lanes: what their pairs won in all; the rest alone */
+    const uint32_t first = me * nw < 64u ? me * nw : 0u, last = me * nw + nw - 1u < 64u ? me * nw + nw - 1u : 0u;
+    const uint32_t mine = perm32(gw + nwon, last) - perm32(gw, first);
+    if (t && mine < t) claim_pages(h, c, g.k, t - mine, out + tpre + mine, tl);
+}
+
 /* Chunk variant, shard j: serve up to `need` pages of the group's class,
  * writing their byte offsets to stage[served..).  Returns when need is met
  * or when shard j's queue and pool could not supply more. */
@@ -1644,7 +1696,7 @@ __device__ __forceinline__ void chunk_serve_shard(const hbheap_dev_t& h, const G
          * already taken off the counts, which stay within the free bits */
         const bool early = !(got < want && need > took);
         fuzz_point(30);
-        if (!early && t) claim_pages(h, c, g.k, t, stage + served + tpre, tl);
+        if (!early) claim_wave(h, g, got, c, t, tpre, stage + served, tl);
 
         /* chunks that still hold free pages go back to the tail */
         const uint64_t rq = __ballot(keep);
@@ -1682,7 +1734,7 @@ __device__ __forceinline__ void chunk_serve_shard(const hbheap_dev_t& h, const G
         }
         if (early) {
             if (g.me == g.leader) ring_release(R, nrq, tl);
-            if (t) claim_pages(h, c, g.k, t, stage + served + tpre, tl);
+            claim_wave(h, g, got, c, t, tpre, stage + served, tl);
             need -= took;
             served += took;
             /* entries reserved but nothing served: a wait gave up (error raised) */
