@@ -1521,6 +1521,11 @@ __device__ __forceinline__ uint32_t scan_shards(const hbheap_dev_t& h, const Gro
     return S;
 }
 
+template <uint32_t R>
+__device__ __forceinline__ void put_rows(const hbheap_dev_t& h, const uint32_t (&jr)[R], const uint32_t (&kr)[R],
+                                         const bool (&pt)[R], const uint32_t (&pos)[R], const uint32_t (&val)[R],
+                                         Tally& tl);
+
 /* Wave-wide (chunk variants, a full wave): the helper of rank i (lane i)
  * takes t free bits of its chunk c, lowest first, writing the pages' byte
  * offsets to out[tpre .. tpre + t), as claim_pages does -- but with the
@@ -1535,6 +1540,7 @@ __device__ __forceinline__ void claim_wave(const hbheap_dev_t& h, const Group& g
                                            uint32_t tpre, uint64_t* out, Tally& tl)
 {
     const uint32_t nw = g.ppc >= 64u ? g.ppc >> 6 : 1u;
+    if (nh == 0) return;
     if (g.act != ~0ull || nh * nw > 64u) {
         if (t) claim_pages(h, c, g.k, t, out + tpre, tl);
         return;
@@ -1599,7 +1605,10 @@ __device__ __forceinline__ void chunk_serve_shard(const hbheap_dev_t& h, const G
         }
         first_pass = false;
         const uint32_t want0 = (need + g.ppc - 1u) >> g.lppc;
-        const uint32_t want = want0 < g.nact ? want0 : g.nact;
+        /* each lane takes up to K queue entries (K = requests per lane:
+         * entry i * nact + rank of the reservation), all in flight together */
+        constexpr uint32_t K = RW;
+        const uint32_t want = want0 < g.nact * K ? want0 : g.nact * K;
         uint32_t got = 0, h0 = 0;
         if (g.me == g.leader) {
             got = ring_reserve(R, want, tl);
@@ -1611,84 +1620,123 @@ __device__ __forceinline__ void chunk_serve_shard(const hbheap_dev_t& h, const G
         got = bcast(got, g.leader);
         h0 = bcast(h0, g.leader);
 
-        /* helpers take one chunk each and read its free count */
-        const bool helper = g.arank < got;
-        uint32_t c = kEmpty, vseg = 0;
-        int32_t v = 0;
-        bool took_slot = false, stale = false;
-        if (helper) {
-            c = slot_take(h, R, h0 + g.arank, &vseg, tl);
-            took_slot = c != kEmpty;
-            if (c != kEmpty && (c >= h.n_chunks || shard_of_chunk(h, c) != j)) {
+        /* helpers take their chunks (segmented rings: every slot counted
+         * consumed before any segment is closed) and read their free counts */
+        uint32_t c[K], kq[K], qpos[K];
+        bool tk[K];
+        int32_t v[K];
+#pragma unroll
+        for (uint32_t i = 0; i < K; ++i) {
+            tk[i] = i * g.nact + g.arank < got;
+            qpos[i] = h0 + i * g.nact + g.arank;
+            kq[i] = g.k;
+            v[i] = 0;
+        }
+        take_rows<K>(h, j, kq, tk, qpos, c, tl);
+        bool stale = false;
+#pragma unroll
+        for (uint32_t i = 0; i < K; ++i) {
+            if (!tk[i]) c[i] = kEmpty;
+            if (c[i] != kEmpty && (c[i] >= h.n_chunks || shard_of_chunk(h, c[i]) != j)) {
                 raise_err(h, HBHEAP_ERR_CORRUPT, HBHEAP_STAT_TIMEOUTS);
-                c = kEmpty;
+                c[i] = kEmpty;
             }
-            if (c != kEmpty && ev) {
-                /* take the chunk's token from its listing; an entry the token
-                 * does not name is stale: dropped.  A listing is matched by
-                 * its class and its position modulo the ring capacity: a
-                 * slow taker of position p - Q and the taker of p take from
-                 * the same slot and may get each other's entries, which
-                 * leaves each entry in the slot its position maps to.  Only
-                 * one taker can win the token, whichever copy it came by. */
-                uint64_t* w = h.chunk_ct + c;
-                uint64_t x = a_load64(w);   /* a guess: an entry is dropped only on a coherent value */
-                bool sure = false;
-                const uint32_t mine = tok_listed(g.k, h0 + g.arank);
-                for (;;) {
-                    const uint32_t tk = (uint32_t)(x >> 32);
-                    if (tk >= kTokHeld || (tk >> 28) != g.k || ((tk ^ mine) & R.mask) != 0) {
-                        if (!sure) {
-                            x = a_read64(w);
-                            sure = true;
-                            tl.spread += 1;
-                            continue;
-                        }
-                        stale = true;
-                        /* the chunk's stale entry in this queue is gone */
-                        __hip_atomic_fetch_and(w, ~(uint64_t)stale_bit(g.k), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        if (ev && c[0] != kEmpty) {
+            /* take the chunk's token from its listing; an entry the token
+             * does not name is stale: dropped.  A listing is matched by its
+             * class and its position modulo the ring capacity: a slow taker
+             * of position p - Q and the taker of p take from the same slot and
+             * may get each other's entries, which leaves each entry in the
+             * slot its position maps to.  Only one taker can win the token,
+             * whichever copy it came by. */
+            uint64_t* w = h.chunk_ct + c[0];
+            uint64_t x = a_load64(w);   /* a guess: an entry is dropped only on a coherent value */
+            bool sure = false;
+            const uint32_t mine = tok_listed(g.k, h0 + g.arank);
+            for (;;) {
+                const uint32_t tk0 = (uint32_t)(x >> 32);
+                if (tk0 >= kTokHeld || (tk0 >> 28) != g.k || ((tk0 ^ mine) & R.mask) != 0) {
+                    if (!sure) {
+                        x = a_read64(w);
+                        sure = true;
                         tl.spread += 1;
-                        break;
+                        continue;
                     }
+                    stale = true;
+                    /* the chunk's stale entry in this queue is gone */
+                    __hip_atomic_fetch_and(w, ~(uint64_t)stale_bit(g.k), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                     tl.spread += 1;
-                    if (a_cas64(w, x, ct_word(kTokHeld, (uint32_t)x))) {
-                        v = (int32_t)ct_count(x);
-                        break;
-                    }
-                    sure = true;
+                    break;
                 }
-                if (!stale && v <= 0) raise_err(h, HBHEAP_ERR_CORRUPT, HBHEAP_STAT_TIMEOUTS);
-            } else if (c != kEmpty) {
-                v = a_loadi(h.chunk_cnt + c);
-                if (v <= 0) raise_err(h, HBHEAP_ERR_CORRUPT, HBHEAP_STAT_TIMEOUTS);
+                tl.spread += 1;
+                if (a_cas64(w, x, ct_word(kTokHeld, (uint32_t)x))) {
+                    v[0] = (int32_t)ct_count(x);
+                    break;
+                }
+                sure = true;
             }
+            if (!stale && v[0] <= 0) raise_err(h, HBHEAP_ERR_CORRUPT, HBHEAP_STAT_TIMEOUTS);
+        } else if (!ev) {
+#pragma unroll
+            for (uint32_t i = 0; i < K; ++i)
+                if (c[i] != kEmpty) v[i] = a_loadi(h.chunk_cnt + c[i]);
+#pragma unroll
+            for (uint32_t i = 0; i < K; ++i)
+                if (c[i] != kEmpty && v[i] <= 0) raise_err(h, HBHEAP_ERR_CORRUPT, HBHEAP_STAT_TIMEOUTS);
         }
         fuzz_point(28);
         /* stale entries dropped: progress even if nothing was served */
         const bool dropped = ev && __ballot(stale) != 0;
-        if (R.segs) seg_count_taken(h, R, took_slot, h0 + g.arank, vseg, tl);
-        const uint32_t vc = v > 0 ? ((uint32_t)v < need ? (uint32_t)v : need) : 0u;
-        uint32_t tot;
-        const uint32_t pre = excl_scan<kBits>(vc, &tot);
-        const uint32_t t = pre < need ? ((need - pre) < vc ? (need - pre) : vc) : 0u;
-
-        bool keep = false;
-        if (vc > 0) {
-            if (t && ev) {
-                /* the count is lowered by t when the token is put back
-                 * (list_or_retire, or the release below): while it is held
-                 * nobody else takes pages from the chunk and frees only add */
-                keep = (uint32_t)v > t;
-            } else if (t) {
-                fuzz_point(29);
-                keep = a_addi(h.chunk_cnt + c, -(int32_t)t) - (int32_t)t > 0;
-                tl.spread += 1;
-            } else {
-                keep = true;
+        /* pages each chunk gives, in entry order (entry i * nact + rank) */
+        uint32_t t[K], tpre[K], vc[K];
+        bool keep[K];
+        uint32_t base = 0;
+        /* rows of entries in use (wave-uniform): the rest skip their scans */
+        const uint32_t rows = (got + g.nact - 1u) / g.nact;
+#pragma unroll
+        for (uint32_t i = 0; i < K; ++i) {
+            vc[i] = v[i] > 0 ? ((uint32_t)v[i] < need ? (uint32_t)v[i] : need) : 0u;
+            t[i] = 0;
+            if (i < rows) {
+                uint32_t tot;
+                const uint32_t pre = base + excl_scan<kBits>(vc[i], &tot);
+                base += tot;
+                t[i] = pre < need ? ((need - pre) < vc[i] ? (need - pre) : vc[i]) : 0u;
             }
         }
-        uint32_t took;
-        const uint32_t tpre = excl_scan<kBits>(t, &took);
+        int32_t cnt[K];
+#pragma unroll
+        for (uint32_t i = 0; i < K; ++i) {
+            if (!ev && t[i]) {
+                fuzz_point(29);
+                cnt[i] = a_addi(h.chunk_cnt + c[i], -(int32_t)t[i]);
+                tl.spread += 1;
+            }
+        }
+#pragma unroll
+        for (uint32_t i = 0; i < K; ++i) {
+            keep[i] = false;
+            if (vc[i] > 0) {
+                /* eager: the count is lowered by t when the token is put
+                 * back (list_or_retire, or the release below): while it is
+                 * held nobody else takes pages from the chunk and frees only
+                 * add */
+                if (t[i] && ev) keep[i] = (uint32_t)v[i] > t[i];
+                else if (t[i]) keep[i] = cnt[i] - (int32_t)t[i] > 0;
+                else keep[i] = true;
+            }
+        }
+        uint32_t took = 0;
+#pragma unroll
+        for (uint32_t i = 0; i < K; ++i) {
+            tpre[i] = took;
+            if (i < rows) {
+                uint32_t tt;
+                tpre[i] = took + excl_scan<kBits>(t[i], &tt);
+                took += tt;
+            }
+        }
         /* a pass that will not refill (its reservations cover the need, or
          * the queue gave every chunk asked for) puts its kept chunks back
          * and releases the queue before it claims its pages' bits, so other
@@ -1696,11 +1744,26 @@ __device__ __forceinline__ void chunk_serve_shard(const hbheap_dev_t& h, const G
          * already taken off the counts, which stay within the free bits */
         const bool early = !(got < want && need > took);
         fuzz_point(30);
-        if (!early) claim_wave(h, g, got, c, t, tpre, stage + served, tl);
+        if (!early) {
+#pragma unroll
+            for (uint32_t i = 0; i < K; ++i) {
+                const uint32_t nh = got > i * g.nact ? (got - i * g.nact < g.nact ? got - i * g.nact : g.nact) : 0u;
+                claim_wave(h, g, nh, c[i], t[i], tpre[i], stage + served, tl);
+            }
+        }
 
         /* chunks that still hold free pages go back to the tail */
-        const uint64_t rq = __ballot(keep);
-        const uint32_t nrq = (uint32_t)__popcll(rq);
+        uint32_t nrq = 0, rpos[K], jq[K];
+#pragma unroll
+        for (uint32_t i = 0; i < K; ++i) {
+            rpos[i] = 0;
+            jq[i] = j;
+            if (i < rows) {
+                const uint64_t rq = __ballot(keep[i]);
+                rpos[i] = nrq + rank_in(rq);
+                nrq += (uint32_t)__popcll(rq);
+            }
+        }
         uint32_t t0 = 0;
         fuzz_point(31);
         if (nrq && g.me == g.leader) {
@@ -1708,33 +1771,42 @@ __device__ __forceinline__ void chunk_serve_shard(const hbheap_dev_t& h, const G
             tl.headtail += 1;
         }
         t0 = bcast(t0, g.leader);
-        if (keep) {
-            const uint32_t pos = t0 + rank_in(rq);
-            if (ev) list_or_retire(h, c, g.k, g.ppc, pos, t, tl);
-            slot_put(h, R, pos, c, tl);
+#pragma unroll
+        for (uint32_t i = 0; i < K; ++i) rpos[i] += t0;
+        if (ev) {
+            if (keep[0]) {
+                list_or_retire(h, c[0], g.k, g.ppc, rpos[0], t[0], tl);
+                slot_put(h, R, rpos[0], c[0], tl);
+            }
+        } else {
+            put_rows<K>(h, jq, kq, keep, rpos, c, tl);
         }
-        if (ev && vc > 0 && !keep) {
+        if (ev && vc[0] > 0 && !keep[0]) {
             /* every free page taken: give the token up -- unless frees came
              * in while it was held, which left it to this lane to list the
              * chunk again (or retire it) */
-            uint64_t x = a_load64(h.chunk_ct + c);
+            uint64_t x = a_load64(h.chunk_ct + c[0]);
             bool released = false;
             tl.spread += 1;
             /* held, and no page freed meanwhile: give it up (keep the stale flag) */
-            while (ct_count(x) == t && (uint32_t)(x >> 32) == kTokHeld)
-                if ((released = a_cas64(h.chunk_ct + c, x, ct_word(kTokNone, ct_stale(x))))) break;
+            while (ct_count(x) == t[0] && (uint32_t)(x >> 32) == kTokHeld)
+                if ((released = a_cas64(h.chunk_ct + c[0], x, ct_word(kTokNone, ct_stale(x))))) break;
             if (!released) {
                 const uint32_t pos = a_add32(R.tail, 1u);
                 tl.headtail += 1;
-                list_or_retire(h, c, g.k, g.ppc, pos, t, tl);
-                slot_put(h, R, pos, c, tl);
+                list_or_retire(h, c[0], g.k, g.ppc, pos, t[0], tl);
+                slot_put(h, R, pos, c[0], tl);
                 a_add64(R.state, 1ull);
                 tl.state += 1;
             }
         }
         if (early) {
             if (g.me == g.leader) ring_release(R, nrq, tl);
-            claim_wave(h, g, got, c, t, tpre, stage + served, tl);
+#pragma unroll
+            for (uint32_t i = 0; i < K; ++i) {
+                const uint32_t nh = got > i * g.nact ? (got - i * g.nact < g.nact ? got - i * g.nact : g.nact) : 0u;
+                claim_wave(h, g, nh, c[i], t[i], tpre[i], stage + served, tl);
+            }
             need -= took;
             served += took;
             /* entries reserved but nothing served: a wait gave up (error raised) */
