@@ -2225,6 +2225,31 @@ __device__ __forceinline__ bool home_pool_dry(const hbheap_dev_t& h, uint32_t ho
     return hp[0] >= ((const uint32_t*)hp)[2];
 }
 
+template <uint32_t R>
+__device__ __forceinline__ void malloc_rows(const hbheap_dev_t& h, Rows<R>& q, const uint64_t (&n)[R],
+                                            const bool (&has)[R], uint32_t home_in, bool dry_in,
+                                            uint32_t* share = nullptr);
+
+/* Rows served one after another, one request per lane each (row r a
+ * compile-time index, so that q stays in registers). */
+template <uint32_t R, uint32_t r>
+__device__ __forceinline__ void malloc_rows_one_by_one(const hbheap_dev_t& h, Rows<R>& q, const uint64_t (&n)[R],
+                                                       const bool (&has)[R], uint32_t home_in, bool dry_in,
+                                                       uint32_t* share)
+{
+    if constexpr (r < R) {
+        Rows<1> one;
+        const uint64_t n1[1] = {n[r]};
+        const bool h1[1] = {has[r]};
+        malloc_rows<1>(h, one, n1, h1, home_in, dry_in, share);
+        q.k[r] = one.k[0];
+        q.gid[r] = 0;
+        q.rank[r] = 0;
+        q.off[r] = one.off[0];
+        malloc_rows_one_by_one<R, r + 1>(h, q, n, has, home_in, dry_in, share);
+    }
+}
+
 /* Every active lane calls this with R requests (n[r] bytes where has[r]);
  * requests are grouped by class (inside aligned segments of `width` lanes)
  * and each group is served by queue operations of one lane for the whole
@@ -2235,21 +2260,11 @@ __device__ __forceinline__ bool home_pool_dry(const hbheap_dev_t& h, uint32_t ho
 template <uint32_t R>
 __device__ __forceinline__ void malloc_rows(const hbheap_dev_t& h, Rows<R>& q, const uint64_t (&n)[R],
                                             const bool (&has)[R], uint32_t home_in, bool dry_in,
-                                            uint32_t* share = nullptr)
+                                            uint32_t* share)
 {
     if constexpr (R > 1) {
         if (h.width < 16u || (HBHEAP_VARIANT_LISTS_CHUNKS(h.variant) && eager(h))) {
-#pragma unroll
-            for (uint32_t r = 0; r < R; ++r) {
-                Rows<1> one;
-                const uint64_t n1[1] = {n[r]};
-                const bool h1[1] = {has[r]};
-                malloc_rows<1>(h, one, n1, h1, home_in, dry_in, share);
-                q.k[r] = one.k[0];
-                q.gid[r] = 0;
-                q.rank[r] = 0;
-                q.off[r] = one.off[0];
-            }
+            malloc_rows_one_by_one<R, 0>(h, q, n, has, home_in, dry_in, share);
             return;
         }
     }

@@ -120,7 +120,9 @@ __global__ void k_iota_u32(uint32_t* p, uint64_t n)
 #if HBHEAP_ALLOC_WAVES > 0
 #define HBHEAP_ALLOC_ATTR __attribute__((amdgpu_waves_per_eu(HBHEAP_ALLOC_WAVES, 8)))
 #else
-#define HBHEAP_ALLOC_ATTR
+/* 4 requests per lane: 2^20 requests are 4096 waves, 4 per SIMD, so ask for
+ * that occupancy (at most 128 VGPRs) and have every wave resident */
+#define HBHEAP_ALLOC_ATTR __attribute__((amdgpu_waves_per_eu(R == 4 ? 4 : 1, 8)))
 #endif
 
 /* The batch kernels come in one instance per heap variant V (the host
