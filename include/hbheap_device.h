@@ -679,6 +679,12 @@ __device__ __forceinline__ uint32_t* vl_slot(const hbheap_dev_t& h, const Ring& 
     const uint32_t off = pos & ((1u << r.log2g) - 1u);
     const uint64_t qtag = (uint64_t)r.k << 32;
     Backoff b;
+    /* the producer of a segment's first slot takes and tags its segment as
+     * soon as it knows its position, while earlier segments are still being
+     * linked, and waits only to link it: the links of consecutive segments
+     * then follow each other one round trip apart.  An unlinked segment is
+     * reachable by no walk (links lead only to linked segments). */
+    uint32_t prep = kEmpty, pdep = 0;
     for (;;) {
         bool walk = true;
         if (producer) {
@@ -692,29 +698,39 @@ __device__ __forceinline__ uint32_t* vl_slot(const hbheap_dev_t& h, const Ring& 
                 *seg_out = bm;
                 return r.segs + ((uint64_t)bm << r.log2g) + off;
             }
-            if (off == 0 && bs + 1u == s) {
-                const uint32_t m = store_take(h, r.j, t);
-                if (m == kEmpty) return nullptr;
-                if (m >= h.vsegs) {
-                    raise_err(h, HBHEAP_ERR_CORRUPT, HBHEAP_STAT_TIMEOUTS);
-                    return nullptr;
+            if (off == 0 && (int32_t)(s - bs) >= 1) {
+                if (prep == kEmpty) {
+                    const uint32_t m = store_take(h, r.j, t);
+                    if (m == kEmpty) return nullptr;
+                    if (m >= h.vsegs) {
+                        raise_err(h, HBHEAP_ERR_CORRUPT, HBHEAP_STAT_TIMEOUTS);
+                        return nullptr;
+                    }
+                    fuzz_point(14);
+                    const uint64_t w1 = a_xchg64(r.vtag + m, qtag | s);
+                    const uint64_t w2 = a_xchg64(r.vnext + m + zero_after((uint32_t)w1), kNoLink);
+                    prep = m;
+                    pdep = (uint32_t)w2;
+                    t.spread += 2;
                 }
-                fuzz_point(14);
-                const uint64_t w1 = a_xchg64(r.vtag + m, qtag | s);
-                const uint64_t w2 = a_xchg64(r.vnext + m + zero_after((uint32_t)w1), kNoLink);
-                const uint64_t w3 = a_xchg64(r.vnext + bm + zero_after((uint32_t)w2), m);
-                fuzz_point(15);
-                uint64_t expect = bk;
-                const bool moved = __hip_atomic_compare_exchange_strong(
-                    r.back + zero_after((uint32_t)w3), &expect, ((uint64_t)s << 32) | m, __ATOMIC_RELAXED,
-                    __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                t.spread += 4;
-                if (!moved || w3 != kNoLink) raise_err(h, HBHEAP_ERR_CORRUPT, HBHEAP_STAT_TIMEOUTS);
-                vl_retire(h, r, (uint32_t)expect, t);
-                *seg_out = m;
-                return r.segs + ((uint64_t)m << r.log2g);
+                if (bs + 1u == s) {
+                    /* the back is segment s - 1: link after it, move the back */
+                    const uint64_t w3 = a_xchg64(r.vnext + bm + zero_after(pdep), prep);
+                    fuzz_point(15);
+                    uint64_t expect = bk;
+                    const bool moved = __hip_atomic_compare_exchange_strong(
+                        r.back + zero_after((uint32_t)w3), &expect, ((uint64_t)s << 32) | prep, __ATOMIC_RELAXED,
+                        __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    t.spread += 2;
+                    if (!moved || w3 != kNoLink) raise_err(h, HBHEAP_ERR_CORRUPT, HBHEAP_STAT_TIMEOUTS);
+                    vl_retire(h, r, (uint32_t)expect, t);
+                    *seg_out = prep;
+                    return r.segs + ((uint64_t)prep << r.log2g);
+                }
+                walk = false; /* wait for the back to reach segment s - 1 */
+            } else {
+                walk = (int32_t)(bs - s) > 0; /* a late producer of an older segment */
             }
-            walk = (int32_t)(bs - s) > 0; /* a late producer of an older segment */
         }
         if (walk) {
             const uint64_t f = a_load64(r.front);
@@ -737,6 +753,9 @@ __device__ __forceinline__ uint32_t* vl_slot(const hbheap_dev_t& h, const Ring& 
         }
         if (!b.wait(h)) {
             raise_err(h, HBHEAP_ERR_TIMEOUT, HBHEAP_STAT_TIMEOUTS);
+            /* an unlinked segment goes back to the store, after its tag and
+             * link writes */
+            if (prep != kEmpty) store_put(h, r.j + zero_after(pdep), prep, t);
             return nullptr;
         }
     }

@@ -201,7 +201,7 @@ class SegResult(C.Structure):
 
 
 GOP_PUT, GOP_GET = 1, 2
-SEG_MUTATIONS = {"close_early": 1, "install_blind": 2, "keep_count": 3, "retire_uncounted": 4}
+SEG_MUTATIONS = {"close_early": 1, "install_blind": 2, "keep_count": 3, "retire_uncounted": 4, "link_early": 5}
 
 
 def seg_model_run(list_form: bool, n_queues: int, segments: int, leaders: list, consume_all: bool = True,

@@ -15,9 +15,10 @@
  *     the empty entry, everyone else waits for the entry to show s;
  *   - list: the queue keeps a front and a back word (number, id); segment
  *     ids carry a tag (queue, number) and a link to the next segment; the
- *     producer of a segment's first slot, once the back is segment s - 1,
- *     takes a segment from the store, tags it, clears its link, links it
- *     after the back and moves the back to it; consumers walk from the front
+ *     producer of a segment's first slot takes a segment from the store,
+ *     tags it and clears its link as soon as it knows its position (the back
+ *     may still be behind s - 1), then, once the back is segment s - 1,
+ *     links it after the back and moves the back to it; consumers walk from the front
  *     along links, trusting a link only while the segment it was read from
  *     still carries the tag the walk expects.
  * In both, the consumer of a segment's last slot is its closer: once the
@@ -54,7 +55,8 @@
 #define GM_OPS 6      /* operations per leader       */
 #define GM_E 0xFF
 
-enum { GMUT_NONE = 0, GMUT_CLOSE_EARLY = 1, GMUT_INSTALL_BLIND = 2, GMUT_KEEP_COUNT = 3, GMUT_RETIRE_UNCOUNTED = 4 };
+enum { GMUT_NONE = 0, GMUT_CLOSE_EARLY = 1, GMUT_INSTALL_BLIND = 2, GMUT_KEEP_COUNT = 3, GMUT_RETIRE_UNCOUNTED = 4,
+       GMUT_LINK_EARLY = 5 /* list: a prepared segment linked after whatever the back is */ };
 
 typedef struct {
     int8_t C;                  /* published entries                          */
@@ -246,7 +248,18 @@ static int gstep(gctx* x, gstate* s, int l)
             return 0; /* wait for the installer */
         }
         if (Q->back_s == sg) { L->seg = Q->back_m; L->pc = G_P_PUT; return 1; }
-        if (off == 0 && (uint8_t)(Q->back_s + 1) == sg) { L->rf_m = Q->back_m; L->pc = G_P_STORE_RES; return 1; }
+        if (off == 0 && (int8_t)(sg - Q->back_s) >= 1) {
+            /* the producer of a segment's first slot takes and tags its
+             * segment first (even while earlier segments are not linked
+             * yet), then links it once the back is segment sg - 1 */
+            if (L->hand == GM_E) { L->pc = G_P_STORE_RES; return 1; }
+            if ((uint8_t)(Q->back_s + 1) == sg || mut == GMUT_LINK_EARLY) {
+                L->rf_m = Q->back_m;
+                L->pc = G_P_LINK;
+                return 1;
+            }
+            return 0; /* wait for the back */
+        }
         if ((int8_t)(Q->back_s - sg) > 0) {
             /* a late producer of an older segment: walk from the front */
             L->prod = 1;
@@ -292,7 +305,7 @@ static int gstep(gctx* x, gstate* s, int l)
         return 1;
     case G_P_CLEARLINK:
         s->next[L->hand] = GM_E;
-        L->pc = G_P_LINK;
+        L->pc = G_P_LOOK; /* linked once the back is the segment before */
         return 1;
     case G_P_LINK:
         /* link after the back this producer read (only it moves the back

@@ -40,9 +40,15 @@ CONFIGS = {
     # two list queues handing segments to each other through the store
     "cross": dict(n_queues=2, segments=3, leaders=[[(P, 0, 1), (P, 0, 2), (P, 0, 3), (P, 0, 4)], [(G, 0)] * 4,
                                                     [(P, 1, 5), (P, 1, 6), (G, 1), (P, 1, 7), (G, 1), (G, 1)]]),
+    # three producers: the producer of segment 2's first slot can take its
+    # segment while segment 1 is not linked yet (values left in the queue)
+    "ahead": dict(n_queues=1, segments=4, consume_all=False,
+                  leaders=[[(P, 0, 1), (P, 0, 2)], [(P, 0, 3), (P, 0, 4)], [(P, 0, 5)]]),
+    "ahead_get": dict(n_queues=1, segments=4, consume_all=False,
+                      leaders=[[(P, 0, 1), (P, 0, 2), (G, 0)], [(P, 0, 3), (P, 0, 4)], [(P, 0, 5), (G, 0)]]),
 }
 ARRAY = ["one_queue", "two_producers", "two_consumers", "two_queues", "wrap", "reuse", "reuse3"]
-LIST = ["one_queue", "two_producers", "two_consumers", "two_queues", "wrap", "reuse", "cross"]
+LIST = ["one_queue", "two_producers", "two_consumers", "two_queues", "wrap", "reuse", "cross", "ahead", "ahead_get"]
 LARGE = {(True, "reuse")}  # about 1.9 M states
 
 
@@ -76,6 +82,9 @@ MUTANT_PINS = [
     # list retirement that does not check the count: a segment leaves the
     # chain with a slot still to be taken
     (True, "retire_uncounted", "cross", "deadlocks"),
+    # list installer that links its segment, taken ahead, without waiting
+    # for the back to be the segment before: a link is overwritten
+    (True, "link_early", "ahead", "segment_violations"),
 ]
 
 
