@@ -144,13 +144,12 @@ def recorded_traffic():
     return float(kv["traffic_bytes_per_launch"])
 
 
-def head_rows_of(args, variant: int, width: int | None = None, eager: bool = False) -> int:
+def head_rows_of(args, variant: int, width: int | None = None) -> int:
     """Requests per lane of the allocation kernel the library launches for
     this heap: its rows (4 by default) for every variant but the
-    virtualised-list page variant, at width 16 or more and without eager
-    retirement, else one."""
+    virtualised-list page variant, at width 16 or more, else one."""
     width = args.width if width is None else width
-    return (args.rows or 4) if variant != 4 and width >= 16 and not eager else 1
+    return (args.rows or 4) if variant != 4 and width >= 16 else 1
 
 
 def alloc_roofline(launches, ceilings, chain_us, traffic):
@@ -555,8 +554,10 @@ def main():
                 launches.append({"n": n, "ok": int(ok.item()), "t": e[0].elapsed_time(e[1]) / 1e3,
                                  "atomics": counts[s]["first" if it == 0 else "subsequent"]["alloc"]})
             rl = alloc_roofline(launches, ceilings, chain_us, recorded_traffic())
-            eager_line = bool(CREATE_FLAGS.get(variant_name, 0) & hb.FLAG_EAGER)
-            rl["kernel"] = f"k_alloc_batch<false, {variant}u, {head_rows_of(args, variant, width, eager_line)}u>"
+            # the library's kernel instance: the variant's, or 6 for the chunk
+            # variant with eager retirement
+            inst = 6 if CREATE_FLAGS.get(variant_name, 0) & hb.FLAG_EAGER else variant
+            rl["kernel"] = f"k_alloc_batch<false, {inst}u, {head_rows_of(args, variant, width)}u>"
             rl["event_overhead_us"] = ev_overhead
             state_atomics = sum(x["atomics"]["state_ops"] for x in launches)
             t_sum = sum(x["t"] for x in launches)

@@ -48,9 +48,9 @@ typedef struct heap_config {
     uint32_t rows;         /* requests per lane of the batch kernels: 1 or 4,
                               0 = 4.  With 4, a wave serves 256 requests
                               and each of its queue operations covers all of
-                              them.  Applies to the page and virtualised-
-                              array page variants at widths of 16 or more;
-                              the others always use 1                        */
+                              them.  Applies at widths of 16 or more to
+                              every variant but the virtualised-list page
+                              variant, which always uses 1                   */
 } heap_config_t;
 
 /* Geometry and placement of a heap (heap_info). */

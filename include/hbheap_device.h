@@ -1601,16 +1601,19 @@ __device__ __forceinline__ void claim_wave(const hbheap_dev_t& h, const Group& g
 /* Chunk variant, shard j: serve up to `need` pages of the group's class,
  * writing their byte offsets to stage[served..).  Returns when need is met
  * or when shard j's queue and pool could not supply more. */
-template <uint32_t RW>
+template <uint32_t RQ, uint32_t RW>
 __device__ __forceinline__ void chunk_serve_shard(const hbheap_dev_t& h, const Group& g, uint32_t j, uint32_t& need,
                                                   uint32_t& served, uint64_t* stage, bool look_first, Tally& tl)
 {
     const Ring R = ring_of(h, j, g.k);
-    /* several requests per lane (RW > 1) only without eager retirement (the
-     * library launches those heaps one request per lane) */
+    /* RQ requests per lane, RW queue entries per lane and pass.  Several
+     * entries per lane (RW > 1) only without eager retirement: there a lane
+     * takes at most one entry per pass (it takes the entry's token by a
+     * compare-and-swap), whatever its number of requests */
+    static_assert(RW == 1 || RW == RQ, "queue entries per lane: 1 or one per request");
     const bool ev = RW == 1 && eager(h);
-    /* a group's need is at most 64 RW: scans of per-lane page counts */
-    constexpr int kBits = RW == 1 ? 7 : 9;
+    /* a group's need is at most 64 RQ: scans of per-lane page counts */
+    constexpr int kBits = RQ == 1 ? 7 : 9;
     /* look before reserving, except on a first pass the caller vouches for
      * (a home shard whose pool still had chunks, or a shard a scan just found
      * something in): there an empty queue costs only a hold taken and given
@@ -1838,8 +1841,12 @@ __device__ __forceinline__ void chunk_serve_shard(const hbheap_dev_t& h, const G
         uint32_t publish = nrq;
         bool exhausted = false;
         if (got < want && need > 0) {
-            /* refill from the shard's pool while still holding the queue */
-            const uint32_t m = (need + g.ppc - 1u) >> g.lppc;
+            /* refill from the shard's pool while still holding the queue
+             * (eager retirement: at most one chunk per active lane, each lane
+             * taking one from the pool ring; a need beyond that takes further
+             * passes) */
+            uint32_t m = (need + g.ppc - 1u) >> g.lppc;
+            if (ev && m > g.nact) m = g.nact;
             uint64_t first = 0;
             uint32_t gm = 0;
             if (g.me == g.leader) {
@@ -1868,11 +1875,17 @@ __device__ __forceinline__ void chunk_serve_shard(const hbheap_dev_t& h, const G
             const uint32_t cap = gm << g.lppc;
             const uint32_t r = cap < need ? cap : need;
             if (ev && gm) {
-                const uint32_t q = (g.arank >> g.lppc) < gm ? (g.arank >> g.lppc) : gm - 1u;
-                const uint32_t ci = perm32(mine, lane_of_rank(g.act, q));
-                if (g.arank < r)
-                    stage[served + g.arank] =
-                        ((uint64_t)ci << h.log2_chunk) + ((uint64_t)(g.arank & (g.ppc - 1u)) << g.shift);
+                /* page i of the refill (i < r <= 64 RQ) is in chunk i >> lppc,
+                 * which the lane of that rank took: RQ uniform rounds, so the
+                 * lane read from is active */
+#pragma unroll
+                for (uint32_t b = 0; b < RQ; ++b) {
+                    const uint32_t i = g.arank + b * g.nact;
+                    const uint32_t q = (i >> g.lppc) < gm ? (i >> g.lppc) : gm - 1u;
+                    const uint32_t ci = perm32(mine, lane_of_rank(g.act, q));
+                    if (i < r)
+                        stage[served + i] = ((uint64_t)ci << h.log2_chunk) + ((uint64_t)(i & (g.ppc - 1u)) << g.shift);
+                }
             } else {
                 for (uint32_t i = g.arank; i < r; i += g.nact) {
                     const uint32_t ci = h.pool_ids[first + (i >> g.lppc)];
@@ -2129,6 +2142,19 @@ __device__ __forceinline__ void page_serve_shard(const hbheap_dev_t& h, const Gr
  * (unchanged: kNoPage).  Chunk variants stage the group's offsets in LDS
  * (64 R per wave) and hand them out by rank at the end. */
 template <uint32_t R>
+__device__ __forceinline__ void chunk_serve(const hbheap_dev_t& h, const Group& g, uint32_t j, uint32_t& need,
+                                            uint32_t& served, uint64_t* stage, bool look_first, Tally& tl)
+{
+    if constexpr (R > 1) {
+        if (eager(h)) {
+            chunk_serve_shard<R, 1>(h, g, j, need, served, stage, look_first, tl);
+            return;
+        }
+    }
+    chunk_serve_shard<R, R>(h, g, j, need, served, stage, look_first, tl);
+}
+
+template <uint32_t R>
 __device__ __forceinline__ void alloc_group(const hbheap_dev_t& h, Rows<R>& q, uint32_t id, uint32_t k, uint32_t tot,
                                             uint64_t* stage, uint32_t home, bool home_dry, uint32_t served0,
                                             bool home_tried, uint32_t* share, Tally& tl)
@@ -2144,7 +2170,7 @@ __device__ __forceinline__ void alloc_group(const hbheap_dev_t& h, Rows<R>& q, u
      * home_tried makes the home shard look before it reserves again) */
     uint32_t need = tot - served0, served = served0;
     const uint32_t S = h.n_shards;
-    if (chunk) chunk_serve_shard<R>(h, g, home, need, served, stage, home_dry, tl);
+    if (chunk) chunk_serve<R>(h, g, home, need, served, stage, home_dry, tl);
     else page_serve_shard<R>(h, g, q, home, need, served, home_dry && !home_tried, home_tried, tl);
     Backoff wb;
     bool timed_out = false;
@@ -2199,7 +2225,7 @@ __device__ __forceinline__ void alloc_group(const hbheap_dev_t& h, Rows<R>& q, u
         if (r < S) {
             const uint32_t j = home + r < S ? home + r : home + r - S;
             const uint32_t before = need;
-            if (chunk) chunk_serve_shard<R>(h, g, j, need, served, stage, false, tl);
+            if (chunk) chunk_serve<R>(h, g, j, need, served, stage, false, tl);
             else page_serve_shard<R>(h, g, q, j, need, served, false, false, tl);
             if (need < before) continue;
         }
@@ -2273,16 +2299,17 @@ __device__ __forceinline__ void malloc_rows_one_by_one(const hbheap_dev_t& h, Ro
  * requests are grouped by class (inside aligned segments of `width` lanes)
  * and each group is served by queue operations of one lane for the whole
  * group.  q.off receives the page offsets.  With R > 1 every lane of the
- * wave must be active, the width at least 16 and the block at most
- * kRowsBlockWaves waves (the batch kernels see to it); a chunk heap with
- * eager retirement then serves row after row. */
+ * wave must be active and the block at most kRowsBlockWaves waves (the
+ * batch kernels see to it); below width 16 the rows are served one after
+ * another.  A chunk heap with eager retirement serves a group's rows
+ * together, one queue entry per lane and pass. */
 template <uint32_t R>
 __device__ __forceinline__ void malloc_rows(const hbheap_dev_t& h, Rows<R>& q, const uint64_t (&n)[R],
                                             const bool (&has)[R], uint32_t home_in, bool dry_in,
                                             uint32_t* share)
 {
     if constexpr (R > 1) {
-        if (h.width < 16u || (HBHEAP_VARIANT_LISTS_CHUNKS(h.variant) && eager(h))) {
+        if (h.width < 16u) {
             malloc_rows_one_by_one<R, 0>(h, q, n, has, home_in, dry_in, share);
             return;
         }

@@ -128,10 +128,21 @@ __global__ void k_iota_u32(uint32_t* p, uint64_t n)
 /* The batch kernels come in one instance per heap variant V (the host
  * launches the heap's own): with h.variant a constant, every variant test of
  * the inlined device code folds, and each instance carries only its
- * variant's code.  R: requests per lane.  Wave w serves requests
+ * variant's code.  V = kChunkEager is the chunk variant with eager
+ * retirement, an instance of its own for the same reason (and so that the
+ * lazy instance keeps its register budget).  R: requests per lane.  Wave w serves requests
  * [64 R w, 64 R (w + 1)), row r of it on lanes l at 64 R w + 64 r + l, so
  * that each row's loads and stores are contiguous; every lane of a wave
  * stays active (rows past n carry no request). */
+constexpr uint32_t kChunkEager = 6;
+template <uint32_t V>
+__device__ __forceinline__ void batch_variant(hbheap_dev_t& h)
+{
+    h.variant = V == kChunkEager ? (uint32_t)HBHEAP_VARIANT_CHUNK : V;
+    if (V == kChunkEager) h.flags |= HBHEAP_FLAG_EAGER;
+    else h.flags &= ~HBHEAP_FLAG_EAGER;
+}
+
 template <bool Counted, uint32_t V, uint32_t R>
 __global__ void __launch_bounds__(kBatchBlock) HBHEAP_ALLOC_ATTR k_alloc_batch(hbheap_dev_t h, const uint64_t* __restrict__ sizes,
                                                              void** __restrict__ ptrs, uint64_t n)
@@ -143,7 +154,7 @@ __global__ void __launch_bounds__(kBatchBlock) HBHEAP_ALLOC_ATTR k_alloc_batch(h
     const uint64_t wave = ((uint64_t)blockIdx.x * kBatchBlock + threadIdx.x) >> 6;
     const uint64_t base = wave * 64u * R + lane();
     if (wave * 64u * R >= n) return;
-    h.variant = V;
+    batch_variant<V>(h);
     if (Counted) h.flags |= HBHEAP_FLAG_STATS;
     else h.flags &= ~HBHEAP_FLAG_STATS;
     /* home shard: the linear wave index, spread evenly over the shards (a
@@ -179,7 +190,7 @@ __global__ void __launch_bounds__(kBatchBlock) k_free_batch(hbheap_dev_t h, cons
     const uint64_t wave = ((uint64_t)blockIdx.x * kBatchBlock + threadIdx.x) >> 6;
     const uint64_t base = wave * 64u * R + lane();
     if (wave * 64u * R >= n) return;
-    h.variant = V;
+    batch_variant<V>(h);
     if (Counted) h.flags |= HBHEAP_FLAG_STATS;
     else h.flags &= ~HBHEAP_FLAG_STATS;
     void* p[R];
@@ -823,8 +834,7 @@ namespace {
 /* Batch launches: requests per lane R, one 256-lane block per 4 * 64 * R
  * requests.  R = the heap's rows for every variant but the virtualised-list
  * page variant, whose takers walk its links row by row (more rows per wave
- * measured slower there); the heap's rows are 1 for widths below 16 and
- * for eager retirement. */
+ * measured slower there); the heap's rows are 1 for widths below 16. */
 static_assert(kBatchBlock / 64 <= hbheap::detail::kRowsBlockWaves, "LDS staging of the rows kernels");
 template <uint32_t V>
 constexpr bool rows_apply() { return V != HBHEAP_VARIANT_VL_PAGE; }
@@ -846,7 +856,10 @@ template <bool C>
 void launch_alloc_v(const hbheap_heap* h, const size_t* sizes, void** ptrs, size_t n, hipStream_t stream)
 {
     switch (h->dev.variant) {
-    case HBHEAP_VARIANT_CHUNK: launch_alloc_r<C, HBHEAP_VARIANT_CHUNK>(h, sizes, ptrs, n, stream); break;
+    case HBHEAP_VARIANT_CHUNK:
+        if (h->dev.flags & HBHEAP_FLAG_EAGER) launch_alloc_r<C, kChunkEager>(h, sizes, ptrs, n, stream);
+        else launch_alloc_r<C, HBHEAP_VARIANT_CHUNK>(h, sizes, ptrs, n, stream);
+        break;
     case HBHEAP_VARIANT_PAGE: launch_alloc_r<C, HBHEAP_VARIANT_PAGE>(h, sizes, ptrs, n, stream); break;
     case HBHEAP_VARIANT_VA_PAGE: launch_alloc_r<C, HBHEAP_VARIANT_VA_PAGE>(h, sizes, ptrs, n, stream); break;
     case HBHEAP_VARIANT_VA_CHUNK: launch_alloc_r<C, HBHEAP_VARIANT_VA_CHUNK>(h, sizes, ptrs, n, stream); break;
@@ -875,7 +888,10 @@ void launch_free_v(const hbheap_heap* h, const size_t* sizes, void* const* ptrs,
                    hipStream_t stream)
 {
     switch (h->dev.variant) {
-    case HBHEAP_VARIANT_CHUNK: launch_free_r<C, HBHEAP_VARIANT_CHUNK>(h, sizes, ptrs, n, status, stream); break;
+    case HBHEAP_VARIANT_CHUNK:
+        if (h->dev.flags & HBHEAP_FLAG_EAGER) launch_free_r<C, kChunkEager>(h, sizes, ptrs, n, status, stream);
+        else launch_free_r<C, HBHEAP_VARIANT_CHUNK>(h, sizes, ptrs, n, status, stream);
+        break;
     case HBHEAP_VARIANT_PAGE: launch_free_r<C, HBHEAP_VARIANT_PAGE>(h, sizes, ptrs, n, status, stream); break;
     case HBHEAP_VARIANT_VA_PAGE: launch_free_r<C, HBHEAP_VARIANT_VA_PAGE>(h, sizes, ptrs, n, status, stream); break;
     case HBHEAP_VARIANT_VA_CHUNK: launch_free_r<C, HBHEAP_VARIANT_VA_CHUNK>(h, sizes, ptrs, n, status, stream); break;
@@ -932,7 +948,7 @@ int heap_create_ex(size_t bytes, size_t chunk_bytes, const heap_config_t* cfg, h
     /* several requests per lane need every lane of a wave and at most 4
      * segments of lanes (so at most 52 groups of a wave) */
     h->rows = c.rows ? c.rows : 4u;
-    if (c.width < 16 || eager_retire) h->rows = 1;
+    if (c.width < 16) h->rows = 1;
     h->lay = make_layout(N, log2C, K, c.variant, bytes, S, log2_span, eager_retire);
     const Layout& L = h->lay;
     h->trim_blocks = (uint32_t)((N + kTrimBlock - 1) / kTrimBlock);

@@ -82,19 +82,21 @@ def test_eager_single_lane_replay_matches_fifo_oracle(hb, seed, shards):
 @pytest.mark.parametrize("sa,sb,C", [(16, 8 * KiB, 8 * KiB), (8 * KiB, 16, 8 * KiB), (4 * KiB, 512, 8 * KiB),
                                      (100, 100, 8 * KiB), (16, 64 * KiB, 64 * KiB), (2 * KiB, 16, 4 * KiB)])
 @pytest.mark.parametrize("shards", [1, 0])
-def test_eager_class_change_without_trim(hb, sa, sb, C, shards):
+@pytest.mark.parametrize("rows", [1, 4])
+def test_eager_class_change_without_trim(hb, sa, sb, C, shards, rows):
     """16 MiB heap (2048 chunks of 8 KiB; 256 of 64 KiB, 4096 pages of 16 B
     each; 4096 of 4 KiB).  Class a fills it (exactly N * C / s_a succeed),
     every block is freed, and class b then gets exactly N * C / s_b -- no
-    trim in between; each chunk was retired exactly once."""
+    trim in between; each chunk was retired exactly once.  rows: requests
+    per lane of the batch kernels."""
     nbytes = 16 * MiB
     N = nbytes // C
-    with hb.Heap(nbytes, C, shards=shards, flags=hb.FLAG_EAGER | hb.FLAG_STATS) as heap:
+    with hb.Heap(nbytes, C, shards=shards, flags=hb.FLAG_EAGER | hb.FLAG_STATS, rows=rows) as heap:
         fresh = heap.snapshot()
         for rnd, s in enumerate((sa, sb)):
             cap = N * (C // O.page_bytes(O.class_of(s, C)))
             n = cap + 4096
-            say(f"case eager-class-change sa={sa} sb={sb} C={C} shards={shards} phase={rnd} n={n}")
+            say(f"case eager-class-change sa={sa} sb={sb} C={C} shards={shards} rows={rows} phase={rnd} n={n}")
             sizes = np.full(n, s, dtype=np.uint64)
             sd, ptrs = dev_u64(sizes), zeros_i64(n)
             oom0 = heap.stats()["oom"]
@@ -127,19 +129,21 @@ def test_eager_class_change_without_trim(hb, sa, sb, C, shards):
 
 @pytest.mark.parametrize("shards,chunk,width", [(1, 8 * KiB, 64), (0, 8 * KiB, 64), (0, 64 * KiB, 64),
                                                 (0, 4 * KiB, 16), (1, 16 * KiB, 1)])
-def test_eager_churn_rounds(hb, shards, chunk, width):
+@pytest.mark.parametrize("rows", [1, 4])
+def test_eager_churn_rounds(hb, shards, chunk, width, rows):
     """256 MiB heap, 2^16 requests of log-uniform sizes in [4 B, 8 KiB] (about
     98 MB of pages live, mean class about 1490 B); each
     round frees a random half and allocates the freed slots with fresh sizes.
     Every round: blocks valid and non-overlapping, patterns intact, the
     snapshot consistent (eager invariants included), live counts equal to
     the oracle's.  At the end every block is freed: every chunk is back in
-    the pools without a trim."""
+    the pools without a trim.  rows: requests per lane of the batch kernels
+    (4 applies from width 16)."""
     import torch
     nbytes, C, n, rounds, seed = 256 * MiB, chunk, 1 << 16, 6, 0xE3
     N = nbytes // C
     ref = O.OracleHeap(nbytes, C, 0, O.POLICY_LOWEST, 1, eager=True)
-    with hb.Heap(nbytes, C, shards=shards, flags=hb.FLAG_EAGER, width=width) as heap:
+    with hb.Heap(nbytes, C, shards=shards, flags=hb.FLAG_EAGER, width=width, rows=rows) as heap:
         fresh = heap.snapshot()
         sizes = inputs.sizes_log_uniform(n, 4, min(C, 8 * KiB), seed)
         sd, ptrs = dev_u64(sizes), zeros_i64(n)
@@ -148,7 +152,7 @@ def test_eager_churn_rounds(hb, shards, chunk, width):
         assert (roffs >= 0).all()
         rng = np.random.default_rng(seed)
         for r in range(rounds):
-            say(f"case eager-churn shards={shards} chunk={chunk} width={width} round={r}")
+            say(f"case eager-churn shards={shards} chunk={chunk} width={width} rows={rows} round={r}")
             offs = offsets(ptrs, heap.base)
             check_blocks(heap, sizes, offs)
             heap.pattern_write(ptrs, sd, seed + r)

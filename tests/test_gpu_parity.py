@@ -206,16 +206,17 @@ def test_steal_exact_capacity(hb, variant):
 
 @pytest.mark.parametrize("variant,shards,flags", [(0, 1, 0), (0, 0, 0), (1, 1, 0), (1, 0, 0), (1, 0, 2), (2, 1, 0),
                                                   (2, 0, 0), (2, 0, 2), (3, 1, 0), (3, 0, 0), (4, 1, 0), (4, 0, 0),
-                                                  (4, 0, 2), (5, 1, 0), (5, 0, 0)])
+                                                  (4, 0, 2), (5, 1, 0), (5, 0, 0), (0, 1, 8), (0, 0, 8)])
 @pytest.mark.parametrize("rows", [1, 4])
 def test_churn_small(hb, variant, shards, flags, rows):
-    """flags 2: the page variant verifies every page it takes from a queue.
-    rows: requests per lane of the batch kernels."""
+    """flags 2: the page variant verifies every page it takes from a queue;
+    flags 8: the chunk variant with eager retirement.  rows: requests per
+    lane of the batch kernels."""
     import torch
     nbytes, C, n, rounds = 256 * MiB, 8 * KiB, 1 << 16, 4
     seed = inputs.SEED_CHURN
     sizes = inputs.sizes_log_uniform(n, 4, 8 * KiB, seed)
-    ref = O.OracleHeap(nbytes, C, variant)
+    ref = O.OracleHeap(nbytes, C, variant, eager=bool(flags & 8))
     ref_offs = ref.alloc_batch(sizes)
     with hb.Heap(nbytes, C, variant=variant, shards=shards, flags=flags, rows=rows) as heap:
         fresh = heap.snapshot()
