@@ -108,34 +108,39 @@ __device__ __forceinline__ void usage_read(const hbheap_dev_t& h, uint64_t* out)
 __global__ void k_usage(hbheap_dev_t h, uint64_t* out) { usage_read(h, out); }
 
 /* 32-bit sum of the words of [0, size) read back, per lane (units u of 16 B
- * with u = first, first + step, ...), tail bytes by the lane with first 0. */
+ * with u = first, first + step, ...), tail bytes by the lane with first 0.
+ * Eight units per lane are loaded before any is added, so a lane waits once
+ * per eight loads rather than once per load.  The tail (size not a multiple
+ * of 16) is read as its whole 16-byte unit, which lies inside the block's
+ * page (a multiple of 16 bytes), and each word is masked to the bytes below
+ * size: the same sum as adding the bytes one by one, each at its place in
+ * its word. */
 __device__ __forceinline__ uint32_t sum_range(const uint8_t* p, uint64_t size, uint64_t first, uint64_t step)
 {
     const uint64_t nq = size >> 4;
     const uint4* q = (const uint4*)p;
     uint32_t s = 0;
-    for (uint64_t u = first; u < nq; u += step) {
-        const uint4 v = q[u];
-        s += v.x + v.y + v.z + v.w;
+    for (uint64_t u = first; u < nq; u += 8u * step) {
+        uint4 v[8];
+#pragma unroll
+        for (uint32_t b = 0; b < 8u; ++b) {
+            const uint64_t x = u + b * step;
+            v[b] = x < nq ? q[x] : make_uint4(0u, 0u, 0u, 0u);
+        }
+#pragma unroll
+        for (uint32_t b = 0; b < 8u; ++b) s += v[b].x + v[b].y + v[b].z + v[b].w;
     }
-    if (first == 0) {
-        for (uint64_t b = nq << 4; b < size; ++b) s += (uint32_t)p[b] << (8 * (b & 3));
+    const uint32_t nb = (uint32_t)(size & 15u);
+    if (first == 0 && nb) {
+        const uint4 v = q[nq];
+        const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+        for (uint32_t k = 0; k < 4u; ++k) {
+            const uint32_t m = nb >= 4u * k + 4u ? ~0u : nb <= 4u * k ? 0u : (1u << (8u * (nb - 4u * k))) - 1u;
+            s += w[k] & m;
+        }
     }
     return s;
-}
-
-/* Sum of v over the active lanes of the wave (any subset), through the
- * wave's LDS stage word. */
-__device__ __forceinline__ uint32_t wave_sum(uint32_t v, uint32_t leader)
-{
-    uint32_t* acc = (uint32_t*)stage_for_wave();
-    if (lane() == leader) *acc = 0;
-    wave_sync_lds();
-    __hip_atomic_fetch_add(acc, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-    wave_sync_lds();
-    const uint32_t t = *acc;
-    wave_sync_lds();
-    return t;
 }
 
 /* One lane per request.  ops[i] >= 0: allocate, write the words, read them
@@ -188,12 +193,21 @@ __device__ __forceinline__ void serve_one(const hbheap_dev_t& h, const int64_t* 
     uint32_t sum = 0;
     if (size && !coop) sum = sum_range(p, size, 0, 1);
     big = __ballot(coop);
-    while (big) {
-        const uint32_t l = ctz64(big);
-        big &= big - 1ull;
-        const uint32_t part = sum_range((const uint8_t*)bcast64((uint64_t)p, l), bcast64(size, l), r, nact);
-        const uint32_t tot = wave_sum(part, l);
-        if (me == l) sum = tot;
+    if (big) {
+        /* each lane adds its part of every large block to the block owner's
+         * LDS word; one wait for all of them at the end */
+        uint32_t* acc = (uint32_t*)stage_for_wave();
+        acc[me] = 0;
+        wave_sync_lds();
+        while (big) {
+            const uint32_t l = ctz64(big);
+            big &= big - 1ull;
+            const uint32_t part = sum_range((const uint8_t*)bcast64((uint64_t)p, l), bcast64(size, l), r, nact);
+            __hip_atomic_fetch_add(acc + l, part, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        }
+        wave_sync_lds();
+        if (coop) sum = acc[me];
+        wave_sync_lds();
     }
     uint32_t status = is_alloc ? (p ? SERVE_OK : SERVE_ALLOC_NULL) : SERVE_FREE_NULL;
     if (!is_alloc) {
