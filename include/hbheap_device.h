@@ -1598,6 +1598,23 @@ __device__ __forceinline__ void claim_wave(const hbheap_dev_t& h, const Group& g
     if (t && mine < t) claim_pages(h, c, g.k, t - mine, out + tpre + mine, tl);
 }
 
+/* Eager refills, wave-wide: the chunk of refill rank q (< RQ nact), held in
+ * slot q / nact of the lane of rank q mod nact (every lane calls this: the
+ * lanes read from must be active). */
+template <uint32_t RQ>
+__device__ __forceinline__ uint32_t refill_chunk(const Group& g, const uint32_t (&mine)[RQ], uint32_t q)
+{
+    const uint32_t slot = RQ == 1 ? 0u : q / g.nact;
+    const uint32_t src = lane_of_rank(g.act, q - slot * g.nact);
+    uint32_t ci = kEmpty;
+#pragma unroll
+    for (uint32_t b = 0; b < RQ; ++b) {
+        const uint32_t v = perm32(mine[b], src);
+        if (b == slot) ci = v;
+    }
+    return ci;
+}
+
 /* Chunk variant, shard j: serve up to `need` pages of the group's class,
  * writing their byte offsets to stage[served..).  Returns when need is met
  * or when shard j's queue and pool could not supply more. */
@@ -1842,11 +1859,11 @@ __device__ __forceinline__ void chunk_serve_shard(const hbheap_dev_t& h, const G
         bool exhausted = false;
         if (got < want && need > 0) {
             /* refill from the shard's pool while still holding the queue
-             * (eager retirement: at most one chunk per active lane, each lane
-             * taking one from the pool ring; a need beyond that takes further
-             * passes) */
+             * (eager retirement: at most RQ chunks per active lane, each lane
+             * taking its own from the pool ring, all in flight together; a
+             * need beyond that takes further passes) */
             uint32_t m = (need + g.ppc - 1u) >> g.lppc;
-            if (ev && m > g.nact) m = g.nact;
+            if (ev && m > g.nact * RQ) m = g.nact * RQ;
             uint64_t first = 0;
             uint32_t gm = 0;
             if (g.me == g.leader) {
@@ -1858,16 +1875,39 @@ __device__ __forceinline__ void chunk_serve_shard(const hbheap_dev_t& h, const G
             exhausted = gm < m;
             fuzz_point(32);
             /* the chunk of rank q among those taken: a pool id (bump pool),
-             * or what lane q took from the pool ring */
-            uint32_t mine = kEmpty;
+             * or what the lane of rank q mod nact took from the pool ring
+             * into its slot q / nact */
+            uint32_t mine[RQ];
+#pragma unroll
+            for (uint32_t b = 0; b < RQ; ++b) mine[b] = kEmpty;
             if (ev) {
                 const Ring P = pool_ring(h, j);
-                if (g.arank < gm) mine = plain_take(h, P.slots + (((uint32_t)first + g.arank) & P.mask), tl);
-                if (__ballot(g.arank < gm && mine == kEmpty)) { /* a wait gave up (error raised) */
+                uint32_t x[RQ];
+                bool fail = false;
+#pragma unroll
+                for (uint32_t b = 0; b < RQ; ++b) {
+                    const uint32_t q = g.arank + b * g.nact;
+                    if (q < gm) {
+                        x[b] = a_xchg32(P.slots + (((uint32_t)first + q) & P.mask), kEmpty);
+                        tl.slot += 1;
+                    }
+                }
+#pragma unroll
+                for (uint32_t b = 0; b < RQ; ++b) {
+                    const uint32_t q = g.arank + b * g.nact;
+                    if (q < gm) {
+                        mine[b] = x[b] != kEmpty ? x[b]
+                                                 : plain_take_wait(h, P.slots + (((uint32_t)first + q) & P.mask), tl);
+                        fail = fail || mine[b] == kEmpty;
+                    }
+                }
+                if (__ballot(fail)) { /* a wait gave up (error raised) */
                     gm = 0;
                     exhausted = true;
                 }
-                if (g.arank < gm) set_class(h, mine, g.k, tl);
+#pragma unroll
+                for (uint32_t b = 0; b < RQ; ++b)
+                    if (g.arank + b * g.nact < gm) set_class(h, mine[b], g.k, tl);
                 wait_own_accesses();
             } else {
                 for (uint32_t i = g.arank; i < gm; i += g.nact) set_class(h, h.pool_ids[first + i], g.k, tl);
@@ -1875,14 +1915,13 @@ __device__ __forceinline__ void chunk_serve_shard(const hbheap_dev_t& h, const G
             const uint32_t cap = gm << g.lppc;
             const uint32_t r = cap < need ? cap : need;
             if (ev && gm) {
-                /* page i of the refill (i < r <= 64 RQ) is in chunk i >> lppc,
-                 * which the lane of that rank took: RQ uniform rounds, so the
-                 * lane read from is active */
+                /* page i of the refill (i < r <= 64 RQ) is in chunk i >> lppc:
+                 * RQ uniform rounds, so every lane read from is active */
 #pragma unroll
                 for (uint32_t b = 0; b < RQ; ++b) {
                     const uint32_t i = g.arank + b * g.nact;
                     const uint32_t q = (i >> g.lppc) < gm ? (i >> g.lppc) : gm - 1u;
-                    const uint32_t ci = perm32(mine, lane_of_rank(g.act, q));
+                    const uint32_t ci = refill_chunk<RQ>(g, mine, q);
                     if (i < r)
                         stage[served + i] = ((uint64_t)ci << h.log2_chunk) + ((uint64_t)(i & (g.ppc - 1u)) << g.shift);
                 }
@@ -1896,7 +1935,7 @@ __device__ __forceinline__ void chunk_serve_shard(const hbheap_dev_t& h, const G
                 /* last chunk keeps pages [u, ppc): set their bits, publish it */
                 const uint32_t last = gm - 1u;
                 const uint32_t u = need - (last << g.lppc);
-                const uint32_t cl = ev ? perm32(mine, lane_of_rank(g.act, last)) : h.pool_ids[first + last];
+                const uint32_t cl = ev ? refill_chunk<RQ>(g, mine, last) : h.pool_ids[first + last];
                 /* the free count (lazy retirement; with eager retirement it
                  * is set with the listing below) and the bit words by
                  * returning exchanges, waited for: performed before the chunk
