@@ -188,6 +188,32 @@ __device__ __forceinline__ Run run_combine(bool have, uint64_t key, uint64_t bit
     return r;
 }
 
+/* The runs of a full wave whose lanes hold consecutive pages of one class
+ * (lane l has page g0 + l, g = offset >> shift, p its page in its chunk,
+ * ppc pages per chunk): a run ends at a word's last bit, at its chunk's last
+ * page or at lane 63, so each lane knows its run without looking at its
+ * neighbours.  Gives what run_combine gives for such a wave (segments of 64
+ * lanes); false, r untouched, unless every lane has a page, the class is
+ * the same on every lane and the pages are consecutive (wave-uniform). */
+__device__ __forceinline__ bool run_consecutive(bool have, uint64_t o, uint32_t shift, uint32_t ppc, uint32_t p, Run& r)
+{
+    if (exec_mask() != ~0ull || __ballot(!have) != 0ull) return false;
+    const uint32_t me = lane();
+    const uint32_t s0 = (uint32_t)__builtin_amdgcn_readfirstlane((int)shift);
+    const uint64_t g = o >> shift;
+    const uint64_t g0 = bcast64(g, 0);
+    if (__ballot(shift != s0 || g != g0 + me) != 0ull) return false;
+    const uint32_t b = p & 63u;
+    const uint32_t before = me < b ? me : b;
+    uint32_t after = 63u - b;
+    if (63u - me < after) after = 63u - me;
+    if (ppc - 1u - p < after) after = ppc - 1u - p;
+    r.incl = bit_range(b - before, b);
+    r.prior = before ? bit_range(b - before, b - 1u) : 0ull;
+    r.tail = me + after;
+    return true;
+}
+
 /* ---------------- scoped atomics ---------------- */
 
 #define HBH_A(order) order, __HIP_MEMORY_SCOPE_AGENT
@@ -1981,9 +2007,10 @@ __device__ __forceinline__ void chunk_serve_shard(const hbheap_dev_t& h, const G
  * out; without it the clearing atomic returns nothing, so the allocation
  * does not wait for it. */
 __device__ __forceinline__ void clear_bits_grouped(const hbheap_dev_t& h, bool have, uint64_t widx, uint64_t bit,
-                                                   uint64_t o, uint64_t& off, Tally& tl)
+                                                   uint64_t o, uint32_t shift, uint32_t p, uint64_t& off, Tally& tl)
 {
-    const Run r = run_combine(have, widx, bit, 64u);
+    Run r;
+    if (!run_consecutive(have, o, shift, 1u << (h.log2_chunk - shift), p, r)) r = run_combine(have, widx, bit, 64u);
     if (!(h.flags & HBHEAP_FLAG_VERIFY)) {
         if (have && lane() == r.tail) {
             __hip_atomic_fetch_and(h.bits + widx, ~r.incl, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -2012,19 +2039,20 @@ __device__ __forceinline__ void page_took(const hbheap_dev_t& h, uint32_t j, uin
 {
     bool took = false;
     uint64_t widx = 0, bit = 0, o = 0;
+    uint32_t p = 0;
     if (v != kEmpty) {
         o = (uint64_t)v << 4;
         if (o >= h.data_bytes || shard_of_chunk(h, o >> h.log2_chunk) != j) {
             raise_err(h, HBHEAP_ERR_CORRUPT, HBHEAP_STAT_TIMEOUTS);
         } else {
             const uint64_t c = o >> h.log2_chunk;
-            const uint32_t p = (uint32_t)((o & ((1ull << h.log2_chunk) - 1ull)) >> shift);
+            p = (uint32_t)((o & ((1ull << h.log2_chunk) - 1ull)) >> shift);
             widx = bit_index(h, c, p >> 6);
             bit = 1ull << (p & 63u);
             took = true;
         }
     }
-    clear_bits_grouped(h, took, widx, bit, o, off, tl);
+    clear_bits_grouped(h, took, widx, bit, o, shift, p, off, tl);
 }
 
 /* Page variant, shard j: the group's requests of ranks [served,
@@ -2714,13 +2742,13 @@ __device__ __forceinline__ void free_rows(const hbheap_dev_t& h, void* const (&p
     const uint32_t me = lane();
     Tally tl;
     bool cand[R], inr[R], enq[R];
-    uint32_t key[R], k[R], val[R];
+    uint32_t key[R], k[R], val[R], pg[R];
     uint64_t c[R], widx[R], bit[R], o[R];
 #pragma unroll
     for (uint32_t r = 0; r < R; ++r) {
         status[r] = kFreeNull;
         cand[r] = inr[r] = enq[r] = false;
-        key[r] = k[r] = val[r] = 0;
+        key[r] = k[r] = val[r] = pg[r] = 0;
         c[r] = widx[r] = bit[r] = o[r] = 0;
         if (p[r] != nullptr) {
             status[r] = kFreeInvalid;
@@ -2740,9 +2768,9 @@ __device__ __forceinline__ void free_rows(const hbheap_dev_t& h, void* const (&p
         bool ok = k[r] < h.n_classes && (o[r] & ((1ull << shift) - 1ull)) == 0;
         if (ok && check_size) ok = class_of(h, size_hint[r]) == (int)k[r];
         if (ok) {
-            const uint32_t pg = (uint32_t)((o[r] & ((1ull << h.log2_chunk) - 1ull)) >> shift);
-            widx[r] = bit_index(h, c[r], pg >> 6);
-            bit[r] = 1ull << (pg & 63u);
+            pg[r] = (uint32_t)((o[r] & ((1ull << h.log2_chunk) - 1ull)) >> shift);
+            widx[r] = bit_index(h, c[r], pg[r] >> 6);
+            bit[r] = 1ull << (pg[r] & 63u);
             key[r] = shard_of_chunk(h, c[r]) * h.n_classes + k[r];
             cand[r] = true;
         }
@@ -2753,7 +2781,11 @@ __device__ __forceinline__ void free_rows(const hbheap_dev_t& h, void* const (&p
     uint64_t old[R];
     uint32_t cold[R], nnew[R];
 #pragma unroll
-    for (uint32_t r = 0; r < R; ++r) run[r] = run_combine(cand[r], widx[r], bit[r], 64u);
+    for (uint32_t r = 0; r < R; ++r) {
+        const uint32_t shift = cand[r] ? 4u + k[r] : h.log2_chunk;
+        if (!run_consecutive(cand[r], o[r], shift, 1u << (h.log2_chunk - shift), pg[r], run[r]))
+            run[r] = run_combine(cand[r], widx[r], bit[r], 64u);
+    }
     /* (returned values are left unset on lanes that issue nothing, and
      * masked only after every row's atomic is issued, so that the rows'
      * atomics are in flight together) */
