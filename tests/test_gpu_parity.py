@@ -288,6 +288,57 @@ def test_free_errors(hb, variant, rows):
 
 
 # ---------------------------------------------------------------------------
+# rows of consecutive pages: a ragged first batch makes the later rows start
+# inside a bitmask word (and, from 1 KiB pages, cross chunks); the rows take
+# their pages from the queue in order, free them, free them again (every
+# request a double free, nothing changed), and take them back
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("variant", VARIANTS)
+@pytest.mark.parametrize("size", [16, 1024, 8 * KiB])
+def test_consecutive_rows_double_free(hb, variant, size):
+    import torch
+    say(f"case consecutive-rows variant={variant} size={size}")
+    nbytes, C, n0, n = 64 * MiB, 8 * KiB, 37, 1 << 12
+    k = O.class_of(size, C)
+    with hb.Heap(nbytes, C, variant=variant, shards=1, rows=4) as heap:
+        fresh = heap.snapshot()
+        s0, s = inputs.sizes_fixed(n0, size), inputs.sizes_fixed(n, size)
+        p0, p = zeros_i64(n0), zeros_i64(n)
+        heap.alloc(dev_u64(s0), p0)
+        sd = dev_u64(s)
+        heap.alloc(sd, p)
+        check_blocks(heap, s, offsets(p, heap.base))
+        heap.free(p)                      # pages back to the queue in request order
+        heap.alloc(sd, p)                 # rows of consecutive pages taken from the queue
+        offs = offsets(p, heap.base)
+        check_blocks(heap, s, offs)
+        heap.pattern_write(p, sd, 0xC0)
+        assert heap.pattern_check(p, sd, 0xC0) == 0
+        _, rep = check_snapshot(heap)
+        assert live_of(rep)[k] == n0 + n
+        st = torch.zeros(n, dtype=torch.int32, device="cuda")
+        heap.free(p, status=st)
+        assert (st.cpu().numpy() == hb.FREE_OK).all()
+        _, rep = check_snapshot(heap)
+        assert live_of(rep)[k] == n0
+        heap.free(p, status=st)           # the same rows again: every request a double free
+        assert (st.cpu().numpy() == hb.FREE_DOUBLE).all()
+        assert heap.error() & hb.ERR_DOUBLE_FREE
+        assert heap.stats()["double_free"] == n
+        _, rep = check_snapshot(heap)
+        assert live_of(rep)[k] == n0
+        heap.alloc(sd, p)
+        check_blocks(heap, s, offsets(p, heap.base))
+        _, rep = check_snapshot(heap)
+        assert live_of(rep)[k] == n0 + n
+        heap.free(p)
+        heap.free(p0)
+        heap.trim()
+        assert heap.snapshot() == fresh
+
+
+# ---------------------------------------------------------------------------
 # payload harness on a partial last wave: large blocks are written and
 # checked by the active lanes only, and must still be covered completely
 # ---------------------------------------------------------------------------
