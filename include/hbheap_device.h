@@ -1966,15 +1966,19 @@ __device__ __forceinline__ void chunk_serve_shard(const hbheap_dev_t& h, const G
                  * is set with the listing below) and the bit words by
                  * returning exchanges, waited for: performed before the chunk
                  * is listed, with no write-back of the L2 */
-                if (!ev && g.me == g.leader) {
-                    (void)a_xchg32((uint32_t*)(h.chunk_cnt + cl), g.ppc - u);
-                    tl.spread += 1;
+                uint32_t pos = 0;
+                if (g.me == g.leader) {
+                    if (!ev) {
+                        (void)a_xchg32((uint32_t*)(h.chunk_cnt + cl), g.ppc - u);
+                        tl.spread += 1;
+                    }
+                    /* its tail position, reserved in the same round trip */
+                    pos = a_add32(R.tail, 1u);
+                    tl.headtail += 1;
                 }
                 write_free_bits(h, cl, u, g, tl);
                 fuzz_point(33);
                 if (g.me == g.leader) {
-                    uint32_t pos = a_add32(R.tail, 1u);
-                    tl.headtail += 1;
                     if (ev) {
                         /* listed at pos, with pages [u, ppc) free */
                         /* keep the stale flag, which a taker dropping an entry
@@ -2152,8 +2156,9 @@ __device__ __forceinline__ void page_serve_shard(const hbheap_dev_t& h, const Gr
                 const uint32_t cl = h.pool_ids[first + last];
                 /* its free bits by returning exchanges, and the wave waits for
                  * them (and the class words): performed before any of its pages
-                 * is published, with no write-back of the L2 */
-                write_free_bits(h, cl, u, g, tl);
+                 * is published, with no write-back of the L2.  The tail
+                 * positions are reserved in the same round trip (a reserved
+                 * position is taken by nobody before its count is published) */
                 const uint32_t L = g.ppc - u;
                 uint32_t t0 = 0;
                 fuzz_point(26);
@@ -2161,6 +2166,7 @@ __device__ __forceinline__ void page_serve_shard(const hbheap_dev_t& h, const Gr
                     t0 = a_add32(Q.tail, L);
                     tl.headtail += 1;
                 }
+                write_free_bits(h, cl, u, g, tl);
                 t0 = bcast(t0, g.leader);
                 const uint64_t cbase = ((uint64_t)cl << h.log2_chunk) >> 4;
                 const uint32_t step = 1u << (g.shift - 4u);
