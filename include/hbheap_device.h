@@ -2064,7 +2064,7 @@ __device__ __forceinline__ void page_took(const hbheap_dev_t& h, uint32_t j, uin
 template <uint32_t R>
 __device__ __forceinline__ void page_serve_shard(const hbheap_dev_t& h, const Group& g, Rows<R>& q, uint32_t j,
                                                  uint32_t& need, uint32_t& served, bool dry, bool check_first,
-                                                 Tally& tl)
+                                                 Tally& tl, bool hold_first = false)
 {
     const Ring Q = ring_of(h, j, g.k);
     /* The first pass (which looks first only if check_first) takes published
@@ -2073,8 +2073,12 @@ __device__ __forceinline__ void page_serve_shard(const hbheap_dev_t& h, const Gr
      * covered by the scan's head/tail test instead).  Short of pages, the
      * next passes look first and hold the queue, so they may refill -- except
      * on a shard the caller saw with a dry pool (dry stays dry until a trim):
-     * there the caller scans instead. */
-    bool look = check_first, held = false;
+     * there the caller scans instead.  hold_first: the caller has just made
+     * that first pass itself and saw the pool not dry, so the first pass here
+     * holds at once, without a look (a look could only say that the pool has
+     * chunks; should it have run dry meanwhile, the held pass finds it so and
+     * returns, and the caller scans). */
+    bool look = check_first && !hold_first, held = hold_first;
     while (need > 0) {
         if (look) {
             uint32_t some = 0;
@@ -2240,11 +2244,13 @@ __device__ __forceinline__ void alloc_group(const hbheap_dev_t& h, Rows<R>& q, u
     }
     /* ranks below served0 were served already (page variant: the wave's
      * first pass over all its groups at once, on the home shard; after it,
-     * home_tried makes the home shard look before it reserves again) */
+     * home_tried makes the home shard hold at once where its pool was not
+     * dry, and look before it reserves again where it was) */
     uint32_t need = tot - served0, served = served0;
     const uint32_t S = h.n_shards;
     if (chunk) chunk_serve<R>(h, g, home, need, served, stage, home_dry, tl);
-    else page_serve_shard<R>(h, g, q, home, need, served, home_dry && !home_tried, home_tried, tl);
+    else page_serve_shard<R>(h, g, q, home, need, served, home_dry && !home_tried, home_tried, tl,
+                             home_tried && !home_dry);
     Backoff wb;
     bool timed_out = false;
     /* share != nullptr (a batch launch, whose requests were all issued when

@@ -822,8 +822,9 @@ static int step(ctx* x, mstate* s, int l)
         if (L->need == 0) { L->pc = 32; return 1; }
         if (!L->held && mut != MUT_DRY_ALWAYS) { L->exhausted = 1; L->pc = 32; return 1; }
         /* the wave's first pass made for all its groups at once refills
-         * nothing: what is still needed is asked for again after a look */
-        if (x->p->fast_first && L->pass == 0) { L->exhausted = 1; L->pc = 32; return 1; }
+         * nothing: what is still needed is asked for again by a held pass at
+         * once where the pool did not look dry, after a look where it did */
+        if (x->p->fast_first && L->pass == 0) { L->exhausted = L->dry; L->pc = 32; return 1; }
         L->m = (uint8_t)((L->need + P - 1) / P);
         if (s->bump >= N) { L->gm = 0; L->exhausted = 1; L->pc = 32; return 1; }
         {

@@ -136,7 +136,8 @@ def test_hold_skipped_while_refilling_is_caught():
 def test_first_pass_without_refill(name):
     """Page variant, a wave with several class groups: the first pass of all
     groups reserves and takes but never refills; what is missing is asked
-    for again after a look.  No check fails on any interleaving."""
+    for again by a held pass at once where the pool did not look dry, after
+    a look where it did.  No check fails on any interleaving."""
     r = O.model_run(1, fast_first=True, **CONFIGS[name])
     assert not r["truncated"]
     assert r["violations"] == 0 and r["deadlocks"] == 0, r
